@@ -1,0 +1,787 @@
+/*
+ * eco_oracle.c -- CPU oracle for the ecological world step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, sequential, slow on purpose: one loop per
+ * rule, FP64 for the policy, exact integers for the world.  Shares no code with
+ * the GPU library (see eco_oracle.h).
+ *
+ * What it computes, and where the paper states it:
+ *   - The state is factored into map layers and per-agent records (Sec. 3.2).
+ *     Map: occupancy (one agent per cell), one resource layer, a static wall
+ *     mask.  Agent: position, facing, energy, age, identity and parent
+ *     identity (the population function of Sec. 3.1 reads alive + parent uid).
+ *   - Observation (Sec. 3.2 "Sensors"; App. F vision layout): an egocentric
+ *     S x S window drawn with the agent facing the top of the page ("Around"
+ *     layout), 4 channels per cell, then internal/external/compass scalars.
+ *   - Policy (Sec. 3.3): per-agent memoryless MLP with two ReLU hidden layers
+ *     and a linear head; actions drawn from the softmax (temperature 1).
+ *   - Actions (Sec. 3.2 "Actions"): rest, rotate CCW/CW, forward, eat,
+ *     reproduce (and an inert attack slot).  Contested or occupied targets do
+ *     not move; here the lowest slot wins a contested empty cell.
+ *   - Resources (Sec. 3.2 "Resources"): every step costs energy, eating moves a
+ *     resource unit from the cell into the agent, energy slowly regrows on
+ *     empty cells (Bernoulli per cell and step).
+ *   - Reproduction (Sec. 3.2 "Actions", Sec. 3.3): single parent with enough
+ *     energy, child placed directly behind the parent, child receives a fixed
+ *     amount of the parent's energy, child weights = parent weights + Gaussian
+ *     noise on every mutable value.  Initial weights are Gaussian with zero
+ *     biases (Sec. 3.3; here N(0, 1/fan_in)).
+ *
+ * Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC'11), keyed by the world seed, with
+ * counter (entity, step, stream, block).  Gaussians use the Box-Muller
+ * transform (Box & Muller, 1958) with libm log/cos/sin/sqrt in FP64.
+ */
+#include "eco_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* errors                                                                    */
+/* ------------------------------------------------------------------------- */
+static _Thread_local char g_err[256] = "";
+static int fail(const char* msg) { snprintf(g_err, sizeof g_err, "%s", msg); return -1; }
+const char* orc_last_error(void) { return g_err; }
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (SC'11): 10 rounds of two 32x32->64 multiplies; the key is   */
+/* bumped by the Weyl constants between rounds.                               */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Stream tags of the counter's third word. */
+enum { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
+       ST_MUTATE = 5, ST_REGROW = 6 };
+
+static uint32_t draw_x0(const uint32_t key[2], uint32_t a, uint32_t step, uint32_t stream, uint32_t blk) {
+    uint32_t ctr[4] = {a, step, stream, blk}, out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[0];
+}
+
+/* Box-Muller on one Philox block: (x0,x1) -> z0,z1 and (x2,x3) -> z2,z3.
+ * u1 = ((x>>8)+1) 2^-24 lies in (0,1] so log(u1) is finite; u2 = (y>>8) 2^-24. */
+void orc_gauss4(const uint32_t ctr[4], const uint32_t key[2], double z[4]) {
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int pair = 0; pair < 2; ++pair) {
+        double u1 = (double)((x[2 * pair] >> 8) + 1u) * 0x1p-24;
+        double u2 = (double)(x[2 * pair + 1] >> 8) * 0x1p-24;
+        double r = sqrt(-2.0 * log(u1));
+        double th = two_pi * u2;
+        z[2 * pair] = r * cos(th);
+        z[2 * pair + 1] = r * sin(th);
+    }
+}
+
+/* Integer threshold for a Bernoulli(p) draw on a 32-bit uniform: x < floor(p 2^32). */
+static uint64_t bern_threshold(float p) {
+    double t = floor((double)p * 4294967296.0);
+    if (t < 0) t = 0;
+    if (t > 4294967296.0) t = 4294967296.0;
+    return (uint64_t)t;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Number formats                                                            */
+/* ------------------------------------------------------------------------- */
+/* bfloat16 round-to-nearest-even of a finite float: add half an ulp of the
+ * kept part (0x7FFF plus the kept LSB for ties) and truncate. */
+uint16_t orc_bf16_rne(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+static double bf16_value(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* OCP FP8 E4M3FN: sign, 4 exponent bits (bias 7), 3 mantissa bits, no
+ * infinities, 0x7F/0xFF are NaN, largest finite 448. */
+double orc_fp8e4m3_decode(uint8_t q) {
+    int s = q >> 7, e = (q >> 3) & 15, m = q & 7;
+    if (e == 15 && m == 7) return NAN;
+    double v = (e == 0) ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7);
+    return s ? -v : v;
+}
+/* Round to nearest, ties to even code, saturating at 448: a binary search for
+ * the two neighbouring non-negative codes (value is monotone in the code). */
+uint8_t orc_fp8e4m3_rne_sat(float x) {
+    uint8_t sign = (x < 0.0f) ? 0x80 : 0x00;
+    double a = fabs((double)x);
+    if (a >= 448.0) return (uint8_t)(sign | 0x7E);
+    int lo = 0, hi = 0x7E;                 /* decode(lo) <= a < decode(hi) */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (orc_fp8e4m3_decode((uint8_t)mid) <= a) lo = mid; else hi = mid;
+    }
+    double dlo = a - orc_fp8e4m3_decode((uint8_t)lo), dhi = orc_fp8e4m3_decode((uint8_t)hi) - a;
+    int q = (dlo < dhi) ? lo : (dhi < dlo) ? hi : ((lo & 1) ? hi : lo);
+    if (q == 0) return 0;                  /* +0 for tiny values of either sign */
+    return (uint8_t)(sign | q);
+}
+
+/* ------------------------------------------------------------------------- */
+/* World                                                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct { int64_t parent; uint32_t parent_slot; uint32_t step; uint32_t root; } lineage_node;
+
+struct orc_world {
+    orc_desc d;
+    uint32_t W, H, cells, cap, S, R, ns, D, H1, H2, A;
+    uint64_t P;
+    uint32_t key[2];
+    uint64_t step, uid_next;
+    int32_t *pos, *energy, *age;
+    uint8_t *facing, *alive, *action;
+    uint64_t *uid, *puid;
+    int32_t *occ;
+    uint8_t *res, *wall;
+    int materialize;
+    float *master;            /* [cap][P] FP32 master, materialized mode */
+    double *stored;           /* [cap][P] dequantised storage (BF16/FP8), materialized mode */
+    int64_t *node;            /* [cap] lineage node of each live slot */
+    lineage_node *nodes;
+    size_t n_nodes, nodes_cap;
+    double *trait;            /* [cap] squared L2 norm of the FP32 master */
+    orc_stats stats;
+};
+
+uint32_t orc_input_dim(const orc_desc* d) { return 4u * d->window * d->window + d->n_scalars; }
+uint64_t orc_param_count(const orc_desc* d) {
+    uint64_t D = orc_input_dim(d), H1 = d->hidden1, H2 = d->hidden2, A = d->n_actions;
+    return D * H1 + H1 + H1 * H2 + H2 + H2 * A + A;
+}
+
+/* Facing 0..3 = N, E, S, W; y grows downward. */
+static const int DX[4] = {0, 1, 0, -1};
+static const int DY[4] = {-1, 0, 1, 0};
+
+static uint32_t wrap_cell(const orc_world* w, int64_t x, int64_t y) {
+    int64_t xx = ((x % (int64_t)w->W) + (int64_t)w->W) % (int64_t)w->W;
+    int64_t yy = ((y % (int64_t)w->H) + (int64_t)w->H) % (int64_t)w->H;
+    return (uint32_t)(yy * (int64_t)w->W + xx);
+}
+static uint32_t step_cell(const orc_world* w, uint32_t cell, int facing, int sign) {
+    int64_t x = cell % w->W, y = cell / w->W;
+    return wrap_cell(w, x + sign * DX[facing], y + sign * DY[facing]);
+}
+
+/* Layer geometry in the logical parameter vector. */
+typedef struct { uint64_t w_off, b_off; uint32_t rows, cols; } layer_geom;
+static void layers(const orc_world* w, layer_geom L[3]) {
+    uint64_t o = 0;
+    L[0].rows = w->H1; L[0].cols = w->D;  L[0].w_off = o; o += (uint64_t)w->H1 * w->D;  L[0].b_off = o; o += w->H1;
+    L[1].rows = w->H2; L[1].cols = w->H1; L[1].w_off = o; o += (uint64_t)w->H2 * w->H1; L[1].b_off = o; o += w->H2;
+    L[2].rows = w->A;  L[2].cols = w->H2; L[2].w_off = o; o += (uint64_t)w->A * w->H2;  L[2].b_off = o; o += w->A;
+}
+
+/* Initial weights of slot j: N(0, 1/fan_in) weights, zero biases.  The
+ * Gaussian for logical parameter p is output p%4 of block p/4 of stream WINIT. */
+static void init_weights(const orc_world* w, uint32_t j, float* out) {
+    layer_geom L[3];
+    layers(w, L);
+    double z[4];
+    uint64_t cur_blk = UINT64_MAX;
+    for (int l = 0; l < 3; ++l) {
+        double std = sqrt(1.0 / (double)L[l].cols);
+        uint64_t nw = (uint64_t)L[l].rows * L[l].cols;
+        for (uint64_t i = 0; i < nw; ++i) {
+            uint64_t p = L[l].w_off + i;
+            if (p / 4 != cur_blk) {
+                cur_blk = p / 4;
+                uint32_t ctr[4] = {j, 0u, ST_WINIT, (uint32_t)cur_blk};
+                orc_gauss4(ctr, w->key, z);
+            }
+            out[p] = (float)(z[p % 4] * std);
+        }
+        for (uint32_t r = 0; r < L[l].rows; ++r) out[L[l].b_off + r] = 0.0f;
+    }
+}
+
+/* Mutation (Sec. 3.3): child = parent + sigma * z on every parameter, with one
+ * rounding of fma(sigma, z, parent) in FP64 and one rounding to FP32. */
+static void mutate(const orc_world* w, const float* parent, uint32_t parent_slot, uint32_t step, float* child) {
+    double z[4];
+    double sigma = (double)w->d.mutation_sigma;
+    for (uint64_t p = 0; p < w->P; ++p) {
+        if (p % 4 == 0) {
+            uint32_t ctr[4] = {parent_slot, step, ST_MUTATE, (uint32_t)(p / 4)};
+            orc_gauss4(ctr, w->key, z);
+        }
+        child[p] = (float)fma(sigma, z[p % 4], (double)parent[p]);
+    }
+}
+
+/* Storage copy of a master vector, dequantised exactly into doubles. */
+static void quantize(const orc_world* w, const float* master, double* out) {
+    if (w->d.wdtype == ORC_FP32) {
+        for (uint64_t p = 0; p < w->P; ++p) out[p] = (double)master[p];
+        return;
+    }
+    if (w->d.wdtype == ORC_BF16) {           /* weights and biases in BF16 */
+        for (uint64_t p = 0; p < w->P; ++p) out[p] = bf16_value(orc_bf16_rne(master[p]));
+        return;
+    }
+    /* FP8: per output row, scale = amax/448 (1 if the row is zero); q = RNE(w/scale)
+     * saturated; value = q * scale.  Biases stay FP32. */
+    layer_geom L[3];
+    layers(w, L);
+    for (int l = 0; l < 3; ++l) {
+        for (uint32_t r = 0; r < L[l].rows; ++r) {
+            const float* row = master + L[l].w_off + (uint64_t)r * L[l].cols;
+            float amax = 0.0f;
+            for (uint32_t c = 0; c < L[l].cols; ++c) {
+                float a = fabsf(row[c]);
+                if (a > amax) amax = a;
+            }
+            float scale = (amax > 0.0f) ? amax / 448.0f : 1.0f;
+            for (uint32_t c = 0; c < L[l].cols; ++c) {
+                uint8_t q = orc_fp8e4m3_rne_sat(row[c] / scale);
+                out[L[l].w_off + (uint64_t)r * L[l].cols + c] = orc_fp8e4m3_decode(q) * (double)scale;
+            }
+            out[L[l].b_off + r] = (double)master[L[l].b_off + r];
+        }
+    }
+}
+
+static double sqnorm(const float* v, uint64_t n) {
+    double s = 0.0;
+    for (uint64_t i = 0; i < n; ++i) s += (double)v[i] * (double)v[i];
+    return s;
+}
+
+static int64_t new_node(orc_world* w, int64_t parent, uint32_t parent_slot, uint32_t step, uint32_t root) {
+    if (w->n_nodes == w->nodes_cap) {
+        size_t nc = w->nodes_cap ? 2 * w->nodes_cap : 1024;
+        lineage_node* nn = (lineage_node*)realloc(w->nodes, nc * sizeof(lineage_node));
+        if (!nn) return -1;
+        w->nodes = nn;
+        w->nodes_cap = nc;
+    }
+    lineage_node* n = &w->nodes[w->n_nodes];
+    n->parent = parent; n->parent_slot = parent_slot; n->step = step; n->root = root;
+    return (int64_t)w->n_nodes++;
+}
+
+/* Rebuild the FP32 master of a lineage node: initial weights of the root slot,
+ * then every ancestor's mutation in birth order. */
+static void materialize_node(const orc_world* w, int64_t id, float* out) {
+    const lineage_node* n = &w->nodes[id];
+    if (n->parent < 0) { init_weights(w, n->root, out); return; }
+    float* tmp = (float*)malloc(w->P * sizeof(float));
+    materialize_node(w, n->parent, tmp);
+    mutate(w, tmp, n->parent_slot, n->step, out);
+    free(tmp);
+}
+
+/* Give slot s a freshly initialised genome (init and write_state). */
+static int seed_slot(orc_world* w, uint32_t s) {
+    int64_t id = new_node(w, -1, 0, 0, s);
+    if (id < 0) return fail("out of memory");
+    w->node[s] = id;
+    if (!w->materialize) { w->trait[s] = NAN; return 0; }   /* lineage mode: no traits */
+    float* m = w->master + (uint64_t)s * w->P;
+    init_weights(w, s, m);
+    w->trait[s] = sqnorm(m, w->P);
+    if (w->stored) quantize(w, m, w->stored + (uint64_t)s * w->P);
+    return 0;
+}
+
+static void compute_stats_tail(orc_world* w) {
+    orc_stats* st = &w->stats;
+    st->step = w->step;
+    uint64_t pop = 0;
+    int64_t esum = 0;
+    double tsum = 0.0;
+    for (uint32_t s = 0; s < w->cap; ++s)
+        if (w->alive[s]) { ++pop; esum += w->energy[s]; tsum += w->trait[s]; }
+    double mean = pop ? tsum / (double)pop : 0.0, var = 0.0;
+    for (uint32_t s = 0; s < w->cap; ++s)
+        if (w->alive[s]) { double dv = w->trait[s] - mean; var += dv * dv; }
+    st->population = pop;
+    st->energy_total = (double)esum;
+    st->trait_mean = mean;
+    st->trait_var = pop ? var / (double)pop : 0.0;
+    uint64_t rsum = 0;
+    for (uint32_t c = 0; c < w->cells; ++c) rsum += w->res[c];
+    st->resource_total = rsum;
+}
+
+static int validate(const orc_desc* d) {
+    if (!d) return fail("null desc");
+    if (d->width < 1 || d->height < 1) return fail("empty grid");
+    if ((uint64_t)d->width * d->height > (1ull << 31)) return fail("grid too large");
+    if (d->window < 1 || d->window % 2 == 0) return fail("window must be odd");
+    if (d->window > d->width || d->window > d->height) return fail("window larger than the grid");
+    if (d->n_scalars != 4 && d->n_scalars != 8) return fail("n_scalars must be 4 or 8");
+    if (d->n_actions != 5 && d->n_actions != 7) return fail("n_actions must be 5 or 7");
+    if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
+    if (d->capacity < d->n_agents_init) return fail("capacity below the initial population");
+    if ((uint64_t)d->n_agents_init > (uint64_t)d->width * d->height) return fail("more agents than cells");
+    if (d->e_repro <= 0) return fail("e_repro must be positive");
+    if (d->wdtype > ORC_FP8) return fail("unknown weight format");
+    if (!(d->mutation_sigma >= 0.0f)) return fail("negative sigma");
+    if (!(d->resource_density >= 0.0f && d->resource_density <= 1.0f)) return fail("density outside [0,1]");
+    if (!(d->regrow_prob >= 0.0f && d->regrow_prob <= 1.0f)) return fail("regrow outside [0,1]");
+    return 0;
+}
+
+typedef struct { uint32_t key, cell; } cell_key;
+static int cmp_cell_key(const void* a, const void* b) {
+    const cell_key* x = (const cell_key*)a;
+    const cell_key* y = (const cell_key*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->cell < y->cell ? -1 : (x->cell > y->cell);
+}
+
+void orc_destroy(orc_world* w) {
+    if (!w) return;
+    free(w->pos); free(w->energy); free(w->age); free(w->facing); free(w->alive); free(w->action);
+    free(w->uid); free(w->puid); free(w->occ); free(w->res); free(w->wall);
+    free(w->master); free(w->stored); free(w->node); free(w->nodes); free(w->trait);
+    free(w);
+}
+
+orc_world* orc_create(const orc_desc* d, int materialize) {
+    if (validate(d)) return NULL;
+    orc_world* w = (orc_world*)calloc(1, sizeof(orc_world));
+    if (!w) { fail("out of memory"); return NULL; }
+    w->d = *d;
+    w->W = d->width; w->H = d->height; w->cells = d->width * d->height; w->cap = d->capacity;
+    w->S = d->window; w->R = (d->window - 1) / 2; w->ns = d->n_scalars;
+    w->D = orc_input_dim(d); w->H1 = d->hidden1; w->H2 = d->hidden2; w->A = d->n_actions;
+    w->P = orc_param_count(d);
+    w->key[0] = (uint32_t)(d->seed & 0xFFFFFFFFu);
+    w->key[1] = (uint32_t)(d->seed >> 32);
+    w->materialize = materialize;
+    uint32_t cap = w->cap;
+    w->pos = (int32_t*)calloc(cap ? cap : 1, 4);    w->energy = (int32_t*)calloc(cap ? cap : 1, 4);
+    w->age = (int32_t*)calloc(cap ? cap : 1, 4);    w->facing = (uint8_t*)calloc(cap ? cap : 1, 1);
+    w->alive = (uint8_t*)calloc(cap ? cap : 1, 1);  w->action = (uint8_t*)calloc(cap ? cap : 1, 1);
+    w->uid = (uint64_t*)calloc(cap ? cap : 1, 8);   w->puid = (uint64_t*)calloc(cap ? cap : 1, 8);
+    w->node = (int64_t*)calloc(cap ? cap : 1, 8);   w->trait = (double*)calloc(cap ? cap : 1, 8);
+    w->occ = (int32_t*)malloc((size_t)w->cells * 4);
+    w->res = (uint8_t*)calloc(w->cells, 1);
+    w->wall = (uint8_t*)calloc(w->cells, 1);
+    if (materialize) {
+        w->master = (float*)calloc((size_t)cap * w->P + 1, sizeof(float));
+        if (d->wdtype != ORC_FP32) w->stored = (double*)calloc((size_t)cap * w->P + 1, sizeof(double));
+    }
+    if (!w->pos || !w->energy || !w->age || !w->facing || !w->alive || !w->action || !w->uid ||
+        !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall ||
+        (materialize && (!w->master || (d->wdtype != ORC_FP32 && !w->stored)))) {
+        orc_destroy(w);
+        fail("out of memory");
+        return NULL;
+    }
+    for (uint32_t c = 0; c < w->cells; ++c) w->occ[c] = -1;
+
+    /* Placement: the n_agents_init cells with the smallest (Philox key, cell)
+     * pairs, slot j taking the j-th smallest. */
+    cell_key* ck = (cell_key*)malloc((size_t)w->cells * sizeof(cell_key));
+    if (!ck) { orc_destroy(w); fail("out of memory"); return NULL; }
+    for (uint32_t c = 0; c < w->cells; ++c) { ck[c].key = draw_x0(w->key, c, 0, ST_CELLKEY, 0); ck[c].cell = c; }
+    qsort(ck, w->cells, sizeof(cell_key), cmp_cell_key);
+    uint64_t rho = bern_threshold(d->resource_density);
+    for (uint32_t c = 0; c < w->cells; ++c) w->res[c] = ((uint64_t)draw_x0(w->key, c, 0, ST_RESINIT, 0) < rho) ? 1 : 0;
+    for (uint32_t j = 0; j < d->n_agents_init; ++j) {
+        uint32_t cell = ck[j].cell;
+        w->alive[j] = 1;
+        w->pos[j] = (int32_t)cell;
+        w->occ[cell] = (int32_t)j;
+        w->facing[j] = (uint8_t)(draw_x0(w->key, j, 0, ST_FACING, 0) >> 30);
+        w->energy[j] = d->e_init;
+        w->age[j] = 0;
+        w->uid[j] = j;
+        w->puid[j] = UINT64_MAX;
+        if (seed_slot(w, j)) { free(ck); orc_destroy(w); return NULL; }
+    }
+    free(ck);
+    w->uid_next = d->n_agents_init;
+    w->step = 0;
+    memset(&w->stats, 0, sizeof w->stats);
+    compute_stats_tail(w);
+    return w;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Observation and policy                                                    */
+/* ------------------------------------------------------------------------- */
+int orc_observe(const orc_world* w, uint32_t slot, double* x) {
+    if (slot >= w->cap || !w->alive[slot]) return fail("slot not alive");
+    int f = w->facing[slot];
+    int64_t ax = w->pos[slot] % w->W, ay = w->pos[slot] / w->W;
+    int dx = DX[f], dy = DY[f];
+    int rx = -dy, ry = dx;                     /* the agent's right-hand direction */
+    int S = (int)w->S, R = (int)w->R;
+    for (int r = 0; r < S; ++r) {
+        for (int c = 0; c < S; ++c) {
+            int fwd = R - r, right = c - R;   /* window row 0 is the far front */
+            uint32_t cell = wrap_cell(w, ax + fwd * dx + right * rx, ay + fwd * dy + right * ry);
+            int32_t o = w->occ[cell];
+            double* v = x + 4 * (r * S + c);
+            v[0] = (o >= 0) ? 1.0 : 0.0;
+            v[1] = (double)w->res[cell];
+            v[2] = (double)w->wall[cell];
+            if (o >= 0) {
+                int64_t eb = (int64_t)w->energy[o] * 8 / w->d.e_repro;
+                if (eb < 0) eb = 0;
+                if (eb > 7) eb = 7;
+                v[3] = (double)eb;
+            } else {
+                v[3] = 0.0;
+            }
+        }
+    }
+    /* Scalars: internal (energy, age), external (resource here), eligibility,
+     * then the 4-way compass when n_s = 8 (Sec. 3.2 "Sensors"). */
+    double* s = x + 4 * S * S;
+    int32_t E = w->energy[slot];
+    int32_t age = w->age[slot] < 1024 ? w->age[slot] : 1024;
+    s[0] = ldexp((double)E, -8);
+    s[1] = ldexp((double)age, -10);
+    s[2] = (double)w->res[w->pos[slot]];
+    s[3] = (E >= w->d.e_repro) ? 1.0 : 0.0;
+    if (w->ns == 8)
+        for (int k = 0; k < 4; ++k) s[4 + k] = (k == f) ? 1.0 : 0.0;
+    return 0;
+}
+
+/* FP64 forward: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), l = W3 h2 + b3. */
+static void forward(const orc_world* w, const double* theta, const double* x, double* logits) {
+    layer_geom L[3];
+    layers(w, L);
+    double* h1 = (double*)malloc(sizeof(double) * (w->H1 + w->H2));
+    double* h2 = h1 + w->H1;
+    for (uint32_t j = 0; j < w->H1; ++j) {
+        double acc = theta[L[0].b_off + j];
+        for (uint32_t k = 0; k < w->D; ++k) acc += theta[L[0].w_off + (uint64_t)j * w->D + k] * x[k];
+        h1[j] = acc > 0.0 ? acc : 0.0;
+    }
+    for (uint32_t i = 0; i < w->H2; ++i) {
+        double acc = theta[L[1].b_off + i];
+        for (uint32_t j = 0; j < w->H1; ++j) acc += theta[L[1].w_off + (uint64_t)i * w->H1 + j] * h1[j];
+        h2[i] = acc > 0.0 ? acc : 0.0;
+    }
+    for (uint32_t a = 0; a < w->A; ++a) {
+        double acc = theta[L[2].b_off + a];
+        for (uint32_t i = 0; i < w->H2; ++i) acc += theta[L[2].w_off + (uint64_t)a * w->H2 + i] * h2[i];
+        logits[a] = acc;
+    }
+    free(h1);
+}
+
+/* Softmax inverse CDF: m = max l, w_k = exp(l_k - m), C_k = w_0 + ... + w_k,
+ * t = u C_{A-1}; the least k with t < C_k, else the last k with w_k > 0. */
+int orc_sample(const double* l, int A, double u) {
+    double m = l[0];
+    for (int k = 1; k < A; ++k) if (l[k] > m) m = l[k];
+    double wk[8], C[8], acc = 0.0;
+    for (int k = 0; k < A; ++k) { wk[k] = exp(l[k] - m); acc += wk[k]; C[k] = acc; }
+    double t = u * C[A - 1];
+    for (int k = 0; k < A; ++k) if (t < C[k]) return k;
+    for (int k = A - 1; k >= 0; --k) if (wk[k] > 0.0) return k;
+    return A - 1;
+}
+
+/* Weights of live slot s in logical order: storage (which=0) or master (which=1). */
+static int slot_theta(orc_world* w, uint32_t s, int which, double* out) {
+    if (s >= w->cap || !w->alive[s]) return fail("slot not alive");
+    if (w->materialize) {
+        const float* m = w->master + (uint64_t)s * w->P;
+        if (which == 1 || w->d.wdtype == ORC_FP32) {
+            for (uint64_t p = 0; p < w->P; ++p) out[p] = (double)m[p];
+        } else {
+            memcpy(out, w->stored + (uint64_t)s * w->P, w->P * sizeof(double));
+        }
+        return 0;
+    }
+    float* m = (float*)malloc(w->P * sizeof(float));
+    if (!m) return fail("out of memory");
+    materialize_node(w, w->node[s], m);
+    if (which == 1) for (uint64_t p = 0; p < w->P; ++p) out[p] = (double)m[p];
+    else quantize(w, m, out);
+    free(m);
+    return 0;
+}
+
+int orc_read_weights(orc_world* w, uint32_t slot, int which, double* out) {
+    return slot_theta(w, slot, which, out);
+}
+
+int orc_agent_logits(orc_world* w, uint32_t slot, double* out) {
+    if (slot >= w->cap || !w->alive[slot]) return fail("slot not alive");
+    double* theta = (double*)malloc(w->P * sizeof(double));
+    double* x = (double*)malloc(w->D * sizeof(double));
+    if (!theta || !x) { free(theta); free(x); return fail("out of memory"); }
+    int rc = slot_theta(w, slot, 0, theta);
+    if (!rc) rc = orc_observe(w, slot, x);
+    if (!rc) forward(w, theta, x, out);
+    free(theta);
+    free(x);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The step                                                                  */
+/* ------------------------------------------------------------------------- */
+int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* sampled_out) {
+    const uint32_t cap = w->cap, A = w->A;
+    const uint32_t step32 = (uint32_t)w->step;
+    if (!actions && !w->materialize) return fail("sampling needs materialized weights");
+    if (sampled_out && !w->materialize) return fail("sampling needs materialized weights");
+    if (actions)
+        for (uint32_t s = 0; s < cap; ++s)
+            if (w->alive[s] && actions[s] >= A) return fail("action out of range");
+
+    orc_stats* st = &w->stats;
+    memset(st, 0, sizeof *st);
+
+    /* 1. Live agents at the start of the step, ascending slot order. */
+    uint8_t* live = (uint8_t*)malloc(cap ? cap : 1);
+    memcpy(live, w->alive, cap);
+
+    /* 2. Every live agent observes the pre-step state and picks an action. */
+    if (logits_out) for (uint64_t i = 0; i < (uint64_t)cap * A; ++i) logits_out[i] = NAN;
+    if (sampled_out) memset(sampled_out, 255, cap);
+    if (w->materialize) {
+#pragma omp parallel
+        {
+            double* x = (double*)malloc(w->D * sizeof(double));
+            double* theta = (double*)malloc(w->P * sizeof(double));
+            double l[8];
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t si = 0; si < (int64_t)cap; ++si) {
+                uint32_t s = (uint32_t)si;
+                if (!live[s]) continue;
+                slot_theta(w, s, 0, theta);
+                orc_observe(w, s, x);
+                forward(w, theta, x, l);
+                uint32_t x0 = draw_x0(w->key, s, step32, ST_ACTION, 0);
+                double u = (double)(x0 >> 8) * 0x1p-24;
+                int a = orc_sample(l, (int)A, u);
+                if (logits_out) for (uint32_t k = 0; k < A; ++k) logits_out[(uint64_t)s * A + k] = l[k];
+                if (sampled_out) sampled_out[s] = (uint8_t)a;
+                w->action[s] = (uint8_t)a;
+            }
+            free(x);
+            free(theta);
+        }
+    }
+    for (uint32_t s = 0; s < cap; ++s) {
+        if (!live[s]) continue;
+        if (actions) w->action[s] = actions[s];
+        st->action_hist[w->action[s]]++;
+    }
+
+    /* 3. Turns; then every FORWARD mover claims its target if the target was
+     *    empty at the start of the step and is not a wall.  Lowest slot wins. */
+    uint32_t* claim = (uint32_t*)malloc((size_t)w->cells * sizeof(uint32_t));
+    int64_t* tgt = (int64_t*)malloc((size_t)(cap ? cap : 1) * sizeof(int64_t));
+    for (uint32_t c = 0; c < w->cells; ++c) claim[c] = UINT32_MAX;
+    for (uint32_t s = 0; s < cap; ++s) {
+        if (!live[s]) continue;
+        if (w->action[s] == ORC_TURN_L) w->facing[s] = (uint8_t)((w->facing[s] + 3) % 4);
+        if (w->action[s] == ORC_TURN_R) w->facing[s] = (uint8_t)((w->facing[s] + 1) % 4);
+    }
+    for (uint32_t s = 0; s < cap; ++s) {
+        tgt[s] = -1;
+        if (!live[s] || w->action[s] != ORC_FORWARD) continue;
+        uint32_t t = step_cell(w, (uint32_t)w->pos[s], w->facing[s], +1);
+        if (w->occ[t] == -1 && !w->wall[t]) {
+            tgt[s] = t;
+            if (s < claim[t]) claim[t] = s;
+        }
+    }
+    /* 4. Winners move; everyone else stays (no chains: targets were empty). */
+    for (uint32_t s = 0; s < cap; ++s) {
+        if (!live[s] || w->action[s] != ORC_FORWARD) continue;
+        if (tgt[s] >= 0 && claim[tgt[s]] == s) {
+            w->occ[w->pos[s]] = -1;
+            w->occ[tgt[s]] = (int32_t)s;
+            w->pos[s] = (int32_t)tgt[s];
+            st->moves_ok++;
+        } else {
+            st->moves_blocked++;
+        }
+    }
+
+    /* 5. Eat, pay the step cost, die at energy <= 0; survivors age. */
+    for (uint32_t s = 0; s < cap; ++s) {
+        if (!live[s]) continue;
+        uint32_t cell = (uint32_t)w->pos[s];
+        if (w->action[s] == ORC_EAT && w->res[cell] > 0) {
+            w->res[cell] -= 1;
+            w->energy[s] += w->d.e_eat;
+            st->eaten++;
+        }
+        w->energy[s] -= w->d.e_cost;
+        if (w->energy[s] <= 0) {
+            w->alive[s] = 0;
+            w->occ[cell] = -1;
+            st->deaths++;
+        } else {
+            w->age[s] += 1;
+        }
+    }
+
+    /* 6. Births.  Eligible parents target the cell directly behind them; it must
+     *    be empty now and not a wall; lowest slot wins.  Winners in slot order
+     *    take the free slots in ascending order until they run out. */
+    for (uint32_t c = 0; c < w->cells; ++c) claim[c] = UINT32_MAX;
+    for (uint32_t s = 0; s < cap; ++s) {
+        tgt[s] = -1;
+        if (!w->alive[s]) continue;
+        int eligible = w->energy[s] >= w->d.e_repro && (A == 5 || w->action[s] == ORC_REPRODUCE);
+        if (!eligible) continue;
+        uint32_t t = step_cell(w, (uint32_t)w->pos[s], w->facing[s], -1);
+        if (w->occ[t] == -1 && !w->wall[t]) {
+            tgt[s] = t;
+            if (s < claim[t]) claim[t] = s;
+        } else {
+            st->births_blocked_cell++;
+        }
+    }
+    uint32_t* winners = (uint32_t*)malloc((size_t)(cap ? cap : 1) * sizeof(uint32_t));
+    uint32_t* freel = (uint32_t*)malloc((size_t)(cap ? cap : 1) * sizeof(uint32_t));
+    uint32_t n_win = 0, n_free = 0;
+    for (uint32_t s = 0; s < cap; ++s) {
+        if (tgt[s] >= 0) {
+            if (claim[tgt[s]] == s) winners[n_win++] = s;
+            else st->births_blocked_cell++;
+        }
+        if (!w->alive[s]) freel[n_free++] = s;
+    }
+    uint64_t births = 0;
+    for (uint32_t k = 0; k < n_win; ++k) {
+        uint32_t p = winners[k];
+        if (k >= n_free) { st->births_blocked_capacity++; continue; }
+        uint32_t c = freel[k];
+        uint32_t t = (uint32_t)tgt[p];
+        w->energy[p] -= w->d.e_child;
+        w->alive[c] = 1;
+        w->pos[c] = (int32_t)t;
+        w->occ[t] = (int32_t)c;
+        w->facing[c] = w->facing[p];
+        w->energy[c] = w->d.e_child;
+        w->age[c] = 0;
+        w->uid[c] = w->uid_next + k;
+        w->puid[c] = w->uid[p];
+        w->node[c] = new_node(w, w->node[p], p, step32, 0);
+        if (w->materialize) {
+            float* cm = w->master + (uint64_t)c * w->P;
+            mutate(w, w->master + (uint64_t)p * w->P, p, step32, cm);
+            w->trait[c] = sqnorm(cm, w->P);
+            if (w->stored) quantize(w, cm, w->stored + (uint64_t)c * w->P);
+        } else {
+            w->trait[c] = NAN;                   /* lineage mode: weights rebuilt on demand */
+        }
+        births++;
+    }
+    st->births = births;
+    w->uid_next += births;
+    free(winners);
+    free(freel);
+
+    /* 7. Regrowth: an empty cell gets one unit with probability regrow_prob. */
+    uint64_t thr = bern_threshold(w->d.regrow_prob);
+    for (uint32_t c = 0; c < w->cells; ++c) {
+        if (w->res[c] != 0) continue;
+        if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->res[c] = 1; st->regrown++; }
+    }
+
+    /* 8. Advance the clock and record the step's statistics. */
+    w->step += 1;
+    compute_stats_tail(w);
+    free(claim);
+    free(tgt);
+    free(live);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* State access                                                              */
+/* ------------------------------------------------------------------------- */
+size_t orc_state_bytes(const orc_world* w) {
+    return 32 + (size_t)w->cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + (size_t)w->cells * (4 + 1 + 1);
+}
+
+int orc_read_state(const orc_world* w, void* buf, size_t bytes) {
+    if (bytes < orc_state_bytes(w)) return fail("state buffer too small");
+    uint8_t* b = (uint8_t*)buf;
+    size_t cap = w->cap, cells = w->cells;
+    uint32_t hdr32[4] = {w->W, w->H, w->cap, 0};
+    memcpy(b, &w->step, 8); memcpy(b + 8, &w->uid_next, 8); memcpy(b + 16, hdr32, 16);
+    b += 32;
+    memcpy(b, w->uid, cap * 8); b += cap * 8;
+    memcpy(b, w->puid, cap * 8); b += cap * 8;
+    memcpy(b, w->pos, cap * 4); b += cap * 4;
+    memcpy(b, w->energy, cap * 4); b += cap * 4;
+    memcpy(b, w->age, cap * 4); b += cap * 4;
+    memcpy(b, w->occ, cells * 4); b += cells * 4;
+    memcpy(b, w->facing, cap); b += cap;
+    memcpy(b, w->alive, cap); b += cap;
+    memcpy(b, w->action, cap); b += cap;
+    memcpy(b, w->res, cells); b += cells;
+    memcpy(b, w->wall, cells);
+    return 0;
+}
+
+int orc_write_state(orc_world* w, const void* buf, size_t bytes) {
+    if (bytes < orc_state_bytes(w)) return fail("state buffer too small");
+    const uint8_t* b = (const uint8_t*)buf;
+    uint32_t hdr32[4];
+    memcpy(hdr32, b + 16, 16);
+    if (hdr32[0] != w->W || hdr32[1] != w->H || hdr32[2] != w->cap) return fail("state shape mismatch");
+    size_t cap = w->cap, cells = w->cells;
+    uint8_t* was_alive = (uint8_t*)malloc(cap ? cap : 1);
+    memcpy(was_alive, w->alive, cap);
+    memcpy(&w->step, b, 8); memcpy(&w->uid_next, b + 8, 8);
+    b += 32;
+    memcpy(w->uid, b, cap * 8); b += cap * 8;
+    memcpy(w->puid, b, cap * 8); b += cap * 8;
+    memcpy(w->pos, b, cap * 4); b += cap * 4;
+    memcpy(w->energy, b, cap * 4); b += cap * 4;
+    memcpy(w->age, b, cap * 4); b += cap * 4;
+    memcpy(w->occ, b, cells * 4); b += cells * 4;
+    memcpy(w->facing, b, cap); b += cap;
+    memcpy(w->alive, b, cap); b += cap;
+    memcpy(w->action, b, cap); b += cap;
+    memcpy(w->res, b, cells); b += cells;
+    memcpy(w->wall, b, cells);
+    for (uint32_t s = 0; s < w->cap; ++s) {
+        if (w->alive[s] && !was_alive[s] && seed_slot(w, s)) { free(was_alive); return -1; }
+    }
+    free(was_alive);
+    compute_stats_tail(w);
+    return 0;
+}
+
+int orc_stats_get(const orc_world* w, orc_stats* out) {
+    *out = w->stats;
+    return 0;
+}

@@ -1,0 +1,115 @@
+/*
+ * eco_oracle.h -- CPU oracle for the ecological world step (TEST INFRASTRUCTURE).
+ *
+ * This is a plain, slow, sequential implementation of one world step of the
+ * paper's Ecological Game (Sec. 3.1: transition + population function +
+ * observation function; Sec. 3.2: resources, sensors, actions, reproduction;
+ * Sec. 3.3: per-agent MLP policy, softmax sampling, Gaussian mutation), in FP64
+ * for the policy and exact integers for the world.  It shares no code, header,
+ * table or constant with the GPU library; only tests/, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  The product path never calls it.
+ *
+ * Every function follows the step algorithm written out in eco_oracle.c, whose
+ * comments cite the passage of the paper each rule restates.
+ */
+#ifndef ECO_ORACLE_H
+#define ECO_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Weight storage formats the oracle evaluates logits on. */
+enum { ORC_FP32 = 0, ORC_BF16 = 1, ORC_FP8 = 2 };
+
+/* Actions.  A = 5 uses 0..4; A = 7 adds REPRODUCE and ATTACK (inert). */
+enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 4,
+       ORC_REPRODUCE = 5, ORC_ATTACK = 6 };
+
+/* One world's parameters.  Energies are integers in units of 0.1 energy. */
+typedef struct {
+    uint32_t width, height;            /* toroidal grid */
+    uint32_t n_agents_init, capacity;  /* initial live agents, slot capacity */
+    float    resource_density;         /* initial Bernoulli density of resource cells */
+    float    regrow_prob;              /* per-step regrowth probability of an empty cell */
+    float    mutation_sigma;           /* std of the Gaussian mutation noise */
+    uint32_t window;                   /* S, odd */
+    uint32_t n_scalars;                /* 4 or 8 */
+    uint32_t hidden1, hidden2, n_actions;
+    int32_t  e_init, e_cost, e_eat, e_repro, e_child;
+    uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
+    uint64_t seed;
+} orc_desc;
+
+/* Per-step statistics (the measurement interface of App. E). */
+typedef struct {
+    uint64_t step, population, births, deaths, eaten, regrown, moves_ok, moves_blocked,
+             births_blocked_cell, births_blocked_capacity, resource_total, action_hist[8];
+    double   energy_total, trait_mean, trait_var;
+} orc_stats;
+
+typedef struct orc_world orc_world;
+
+/* Sizes derived from a desc: D = 4*S*S + n_s inputs, P parameters. */
+uint32_t orc_input_dim(const orc_desc* d);
+uint64_t orc_param_count(const orc_desc* d);
+
+/* Create a world and run the deterministic init.  materialize != 0 keeps every
+ * live agent's weights in memory (needed to sample actions).  materialize == 0
+ * ("lineage mode", for full-size worlds driven by given actions) keeps only each
+ * agent's lineage (root slot + the (parent slot, step) of every mutation):
+ * weights are rebuilt on demand for sampled agents and the trait statistics are
+ * NaN.  Returns NULL on invalid desc (orc_last_error() says why). */
+orc_world* orc_create(const orc_desc* d, int materialize);
+void       orc_destroy(orc_world* w);
+const char* orc_last_error(void);
+
+/* One step.  actions: NULL = sample from the policy, else one action per slot
+ * (entries of dead slots are ignored).  logits_out: NULL or [capacity][A] (NaN
+ * for slots not live at step start).  sampled_out: NULL or [capacity] (the
+ * policy's own choice; 255 for dead slots; needs materialized weights).
+ * Returns 0, or -1 with orc_last_error(). */
+int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* sampled_out);
+
+/* Logits of live slot `slot` on the current state, FP64 (materialized or lineage). */
+int orc_agent_logits(orc_world* w, uint32_t slot, double* out /* [A] */);
+
+/* The FP64 observation vector x (D values) of live slot `slot`. */
+int orc_observe(const orc_world* w, uint32_t slot, double* out /* [D] */);
+
+/* Weights of live slot `slot` in logical nn.Linear order
+ * (W1[H1][D], b1, W2[H2][H1], b2, W3[A][H2], b3).
+ * which = 0: storage values dequantised exactly (FP32 = master), 1: FP32 master. */
+int orc_read_weights(orc_world* w, uint32_t slot, int which, double* out /* [P] */);
+
+/* State access.  State byte layout (shared by interface contract with the
+ * library's read_state, written independently here):
+ *   u64 step, u64 uid_next, u32 width, u32 height, u32 capacity, u32 reserved  (32 B)
+ *   u64 uid[cap], u64 parent_uid[cap], i32 pos[cap], i32 energy[cap], i32 age[cap],
+ *   i32 occ[cells], u8 facing[cap], u8 alive[cap], u8 action[cap], u8 res[cells],
+ *   u8 wall[cells]
+ * pos = y*width + x. */
+size_t orc_state_bytes(const orc_world* w);
+int    orc_read_state(const orc_world* w, void* buf, size_t bytes);
+/* Overwrite the integer state.  Newly alive slots get fresh initial weights for
+ * that slot index (as at init); trait is recomputed. */
+int    orc_write_state(orc_world* w, const void* buf, size_t bytes);
+
+int orc_stats_get(const orc_world* w, orc_stats* out);
+
+/* Building blocks exposed for the pins. */
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void   orc_gauss4(const uint32_t ctr[4], const uint32_t key[2], double z[4]);
+uint16_t orc_bf16_rne(float x);
+uint8_t  orc_fp8e4m3_rne_sat(float x);
+double   orc_fp8e4m3_decode(uint8_t q);
+/* Inverse-CDF softmax sample of A logits with uniform u in [0,1). */
+int    orc_sample(const double* logits, int A, double u);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

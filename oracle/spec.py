@@ -1,0 +1,309 @@
+"""Pure-Python statement of the world step for tiny worlds (TEST INFRASTRUCTURE).
+
+A second, independently written version of the same rules as eco_oracle.c, in
+plain Python integers and floats, used to cross-check the C oracle on tiny
+worlds and to run the hand-traced cases.  Rules (paper sections):
+
+* Sec. 3.1: an Ecological Game step = observation of each live agent, one
+  action each, a synchronous transition, and the population function (who is
+  alive, who is whose parent).
+* Sec. 3.2: one agent per cell; rotate / forward / eat / reproduce actions;
+  moving into an occupied cell or a contested cell does not happen (here the
+  lowest slot wins a contested empty cell); every step costs energy; eating
+  moves a resource unit into the agent; a child appears directly behind its
+  single parent and receives a fixed amount of energy; death at energy <= 0.
+* Sec. 3.3: per-agent MLP with two ReLU hidden layers and a linear head;
+  softmax sampling; zero-mean Gaussian initial weights with zero biases;
+  children copy the parent's weights plus Gaussian noise.
+
+Random numbers: Philox4x32-10 (Salmon et al., SC'11) computed with Python
+integers; Box-Muller (1958) with the math module.
+"""
+import math
+from fractions import Fraction
+
+M32 = 0xFFFFFFFF
+REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
+HEADINGS = [(0, -1), (1, 0), (0, 1), (-1, 0)]  # N, E, S, W with y pointing down
+
+
+def philox4x32_10(ctr, key):
+    """Ten Philox rounds on a 4-word counter with a 2-word key (SC'11)."""
+    x = list(ctr)
+    k = list(key)
+    for rnd in range(10):
+        if rnd:
+            k = [(k[0] + 0x9E3779B9) & M32, (k[1] + 0xBB67AE85) & M32]
+        a = 0xD2511F53 * x[0]
+        b = 0xCD9E8D57 * x[2]
+        x = [((b >> 32) ^ x[1] ^ k[0]) & M32, b & M32, ((a >> 32) ^ x[3] ^ k[1]) & M32, a & M32]
+    return x
+
+
+def gauss4(ctr, key):
+    x = philox4x32_10(ctr, key)
+    out = []
+    for i in (0, 2):
+        u1 = ((x[i] >> 8) + 1) / 16777216.0
+        u2 = (x[i + 1] >> 8) / 16777216.0
+        r = math.sqrt(-2.0 * math.log(u1))
+        out += [r * math.cos(6.283185307179586 * u2), r * math.sin(6.283185307179586 * u2)]
+    return out
+
+
+def fma(a, b, c):
+    """a*b + c with a single rounding to double (exact rational arithmetic)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def f32(v):
+    """Round a Python float to the nearest IEEE single."""
+    import struct
+    return struct.unpack("<f", struct.pack("<f", v))[0]
+
+
+class SpecWorld:
+    """Tiny-world version of the rules; FP32 weights only (storage == master)."""
+
+    def __init__(self, cfg):
+        self.c = dict(cfg)
+        c = self.c
+        self.W, self.H, self.cap = c["width"], c["height"], c["capacity"]
+        self.S = c["window"]
+        self.A = c["n_actions"]
+        self.key = [c["seed"] & M32, (c["seed"] >> 32) & M32]
+        self.D = 4 * self.S * self.S + c["n_scalars"]
+        self.shapes = [(c["hidden1"], self.D), (c["hidden2"], c["hidden1"]), (self.A, c["hidden2"])]
+        self.P = sum(r * k + r for r, k in self.shapes)
+        self.step_no = 0
+        self.uid_next = c["n_agents_init"]
+        cells = self.W * self.H
+        self.occ = [-1] * cells
+        self.wall = [0] * cells
+        rho = math.floor(f32(c["resource_density"]) * 4294967296.0)  # descriptor fields are float32
+        self.res = [1 if philox4x32_10([i, 0, 2, 0], self.key)[0] < rho else 0 for i in range(cells)]
+        order = sorted(range(cells), key=lambda i: (philox4x32_10([i, 0, 0, 0], self.key)[0], i))
+        self.agents = {}  # slot -> dict
+        for j in range(c["n_agents_init"]):
+            self._spawn(j, order[j], philox4x32_10([j, 0, 1, 0], self.key)[0] >> 30, c["e_init"], j, None)
+            self.agents[j]["theta"] = self._init_theta(j)
+
+    def _spawn(self, slot, cell, facing, energy, uid, puid):
+        self.agents[slot] = {"cell": cell, "facing": facing, "energy": energy, "age": 0,
+                             "uid": uid, "puid": puid, "action": 0}
+        self.occ[cell] = slot
+
+    def _init_theta(self, j):
+        theta = []
+        p = 0
+        for rows, cols in self.shapes:
+            sd = math.sqrt(1.0 / cols)
+            for _ in range(rows * cols):
+                theta.append(f32(gauss4([j, 0, 3, p // 4], self.key)[p % 4] * sd))
+                p += 1
+            theta += [0.0] * rows
+            p += rows
+        return theta
+
+    def _xy(self, cell):
+        return cell % self.W, cell // self.W
+
+    def _cell(self, x, y):
+        return (y % self.H) * self.W + (x % self.W)
+
+    def observe(self, slot):
+        ag = self.agents[slot]
+        ax, ay = self._xy(ag["cell"])
+        fx, fy = HEADINGS[ag["facing"]]
+        rx, ry = -fy, fx
+        R = self.S // 2
+        obs = []
+        for r in range(self.S):
+            for col in range(self.S):
+                ahead, right = R - r, col - R
+                cell = self._cell(ax + ahead * fx + right * rx, ay + ahead * fy + right * ry)
+                o = self.occ[cell]
+                eb = 0
+                if o >= 0:  # energy bin of the occupant, 8 bins up to the reproduction threshold
+                    eb = min(max(self.agents[o]["energy"] * 8 // self.c["e_repro"], 0), 7)
+                obs += [1.0 if o >= 0 else 0.0, float(self.res[cell]), float(self.wall[cell]), float(eb)]
+        e = ag["energy"]
+        obs += [e / 256.0, min(ag["age"], 1024) / 1024.0, float(self.res[ag["cell"]]),
+                1.0 if e >= self.c["e_repro"] else 0.0]
+        if self.c["n_scalars"] == 8:
+            obs += [1.0 if k == ag["facing"] else 0.0 for k in range(4)]
+        return obs
+
+    def logits(self, slot):
+        theta = self.agents[slot]["theta"]
+        h = self.observe(slot)
+        p = 0
+        for li, (rows, cols) in enumerate(self.shapes):
+            W = theta[p:p + rows * cols]
+            b = theta[p + rows * cols:p + rows * cols + rows]
+            p += rows * cols + rows
+            out = [b[i] + sum(W[i * cols + k] * h[k] for k in range(cols)) for i in range(rows)]
+            h = out if li == 2 else [max(v, 0.0) for v in out]
+        return h
+
+    @staticmethod
+    def sample(logits, u):
+        m = max(logits)
+        w = [math.exp(v - m) for v in logits]
+        cum, acc = [], 0.0
+        for v in w:
+            acc += v
+            cum.append(acc)
+        t = u * cum[-1]
+        for k, ck in enumerate(cum):
+            if t < ck:
+                return k
+        return max(k for k in range(len(w)) if w[k] > 0)
+
+    def step(self, actions=None):
+        c = self.c
+        n = self.step_no
+        st = {k: 0 for k in ("births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+                             "births_blocked_cell", "births_blocked_capacity")}
+        st["action_hist"] = [0] * 8
+        live = sorted(self.agents)
+        for s in live:
+            if actions is None:
+                u = (philox4x32_10([s, n, 4, 0], self.key)[0] >> 8) / 16777216.0
+                a = self.sample(self.logits(s), u)
+            else:
+                a = int(actions[s])
+            self.agents[s]["action"] = a
+            st["action_hist"][a] += 1
+        # turns, then claims on the pre-step occupancy
+        for s in live:
+            a = self.agents[s]["action"]
+            if a == TURN_L:
+                self.agents[s]["facing"] = (self.agents[s]["facing"] - 1) % 4
+            elif a == TURN_R:
+                self.agents[s]["facing"] = (self.agents[s]["facing"] + 1) % 4
+        claims = {}
+        for s in live:
+            ag = self.agents[s]
+            if ag["action"] != FORWARD:
+                continue
+            x, y = self._xy(ag["cell"])
+            fx, fy = HEADINGS[ag["facing"]]
+            t = self._cell(x + fx, y + fy)
+            if self.occ[t] == -1 and not self.wall[t]:
+                claims.setdefault(t, []).append(s)
+        winners = {min(v): t for t, v in claims.items()}
+        for s in live:
+            ag = self.agents[s]
+            if ag["action"] != FORWARD:
+                continue
+            if s in winners:
+                self.occ[ag["cell"]] = -1
+                ag["cell"] = winners[s]
+                self.occ[ag["cell"]] = s
+                st["moves_ok"] += 1
+            else:
+                st["moves_blocked"] += 1
+        # eat, cost, death, age
+        for s in live:
+            ag = self.agents[s]
+            if ag["action"] == EAT and self.res[ag["cell"]] > 0:
+                self.res[ag["cell"]] -= 1
+                ag["energy"] += c["e_eat"]
+                st["eaten"] += 1
+            ag["energy"] -= c["e_cost"]
+            if ag["energy"] <= 0:
+                self.occ[ag["cell"]] = -1
+                del self.agents[s]
+                st["deaths"] += 1
+            else:
+                ag["age"] += 1
+        # births
+        claims = {}
+        for s in sorted(self.agents):
+            ag = self.agents[s]
+            if ag["energy"] < c["e_repro"] or (self.A == 7 and ag["action"] != REPRODUCE):
+                continue
+            x, y = self._xy(ag["cell"])
+            fx, fy = HEADINGS[ag["facing"]]
+            t = self._cell(x - fx, y - fy)
+            if self.occ[t] == -1 and not self.wall[t]:
+                claims.setdefault(t, []).append(s)
+            else:
+                st["births_blocked_cell"] += 1
+        won = sorted(min(v) for v in claims.values())
+        st["births_blocked_cell"] += sum(len(v) - 1 for v in claims.values())
+        target_of = {min(v): t for t, v in claims.items()}
+        free = [s for s in range(self.cap) if s not in self.agents]
+        sigma = f32(c["mutation_sigma"])
+        nb = 0
+        for k, p in enumerate(won):
+            if k >= len(free):
+                st["births_blocked_capacity"] += 1
+                continue
+            child = free[k]
+            par = self.agents[p]
+            par["energy"] -= c["e_child"]
+            self._spawn(child, target_of[p], par["facing"], c["e_child"], self.uid_next + k, par["uid"])
+            theta = []
+            for q, v in enumerate(par["theta"]):
+                z = gauss4([p, n, 5, q // 4], self.key)[q % 4]
+                theta.append(f32(fma(sigma, z, v)))
+            self.agents[child]["theta"] = theta
+            nb += 1
+        st["births"] = nb
+        self.uid_next += nb
+        # regrowth
+        thr = math.floor(f32(c["regrow_prob"]) * 4294967296.0)
+        for i in range(self.W * self.H):
+            if self.res[i] == 0 and philox4x32_10([i, n, 6, 0], self.key)[0] < thr:
+                self.res[i] = 1
+                st["regrown"] += 1
+        self.step_no += 1
+        st["population"] = len(self.agents)
+        st["resource_total"] = sum(self.res)
+        st["energy_total"] = float(sum(a["energy"] for a in self.agents.values()))
+        return st
+
+    def state(self):
+        """Same dictionary shape as oracle.unpack_state (dead slots zeroed)."""
+        import numpy as np
+        cap = self.cap
+        out = {"step": self.step_no, "uid_next": self.uid_next,
+               "uid": np.zeros(cap, np.uint64), "parent_uid": np.zeros(cap, np.uint64),
+               "pos": np.zeros(cap, np.int32), "energy": np.zeros(cap, np.int32),
+               "age": np.zeros(cap, np.int32), "facing": np.zeros(cap, np.uint8),
+               "alive": np.zeros(cap, np.uint8), "action": np.zeros(cap, np.uint8),
+               "occ": np.array(self.occ, np.int32), "res": np.array(self.res, np.uint8),
+               "wall": np.array(self.wall, np.uint8)}
+        for s, ag in self.agents.items():
+            out["uid"][s] = ag["uid"]
+            out["parent_uid"][s] = 0xFFFFFFFFFFFFFFFF if ag["puid"] is None else ag["puid"]
+            out["pos"][s] = ag["cell"]
+            out["energy"][s] = ag["energy"]
+            out["age"][s] = ag["age"]
+            out["facing"][s] = ag["facing"]
+            out["alive"][s] = 1
+            out["action"][s] = ag["action"]
+        return out
+
+
+def from_state(cfg, st):
+    """A SpecWorld holding the integer state `st` (same dict layout as
+    oracle.unpack_state); live slots get the initial weights of their index."""
+    w = SpecWorld(dict(cfg, n_agents_init=0))
+    w.step_no = int(st["step"])
+    w.uid_next = int(st["uid_next"])
+    w.occ = [int(v) for v in st["occ"]]
+    w.res = [int(v) for v in st["res"]]
+    w.wall = [int(v) for v in st["wall"]]
+    w.agents = {}
+    for s in range(w.cap):
+        if not st["alive"][s]:
+            continue
+        puid = int(st["parent_uid"][s])
+        w.agents[s] = {"cell": int(st["pos"][s]), "facing": int(st["facing"][s]), "energy": int(st["energy"][s]),
+                       "age": int(st["age"][s]), "uid": int(st["uid"][s]),
+                       "puid": None if puid == 0xFFFFFFFFFFFFFFFF else puid, "action": int(st["action"][s]),
+                       "theta": w._init_theta(s)}
+    return w

@@ -1,0 +1,571 @@
+"""Pins of the CPU oracle against things other than itself (no GPU).
+
+Each test fixes the oracle to an independent reference: a library routine
+(rocRAND's Philox, torch's BF16/FP8 casts, numpy's matmul and rot90), the
+paper's printed parameter table, closed forms, hand-traced steps, statistical
+laws, and a second independently written statement of the rules (oracle/spec.py).
+"""
+import json
+import math
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from oracle import spec
+from paper_2510_18221_amd import workloads as wl
+
+from worldstate import N, E, S, W, empty_state, place, assert_same_state, check_invariants
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND's implementation (a library routine)
+# ---------------------------------------------------------------------------
+_ROCRAND_PROBE = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+struct Eng : rocrand_device::philox4x32_10_engine { uint4 f(uint4 c, uint2 k) { return ten_rounds(c, k); } };
+int main() {
+  Eng e; unsigned c0, c1, c2, c3, k0, k1;
+  while (std::scanf("%u %u %u %u %u %u", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    uint4 r = e.f(uint4{c0, c1, c2, c3}, uint2{k0, k1});
+    std::printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+}
+"""
+
+
+def _rocrand_philox(inputs):
+    inc = "/opt/rocm/include"
+    if not os.path.exists(os.path.join(inc, "rocrand", "rocrand_philox4x32_10.h")):
+        pytest.skip("rocRAND headers not installed")
+    with tempfile.TemporaryDirectory() as td:
+        src, exe = os.path.join(td, "p.cpp"), os.path.join(td, "p")
+        open(src, "w").write(_ROCRAND_PROBE)
+        subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", "-I" + inc, src, "-o", exe], check=True,
+                       capture_output=True)
+        text = "\n".join(" ".join(str(int(v)) for v in row) for row in inputs) + "\n"
+        out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+    return np.array([[int(t) for t in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+
+
+def test_philox_matches_rocrand_and_python_spec():
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, 2**32, size=(400, 6), dtype=np.uint64)
+    rows[:8, :4] = [[0, 0, 0, 0], [1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1],
+                    [2**32 - 1] * 4, [5, 7, 4, 0], [123, 99, 6, 0]]
+    ref = _rocrand_philox(rows)
+    for row, r in zip(rows, ref):
+        ctr, key = [int(v) for v in row[:4]], [int(v) for v in row[4:]]
+        assert list(orc.philox(ctr, key)) == [int(v) for v in r]
+        assert spec.philox4x32_10(ctr, key) == [int(v) for v in r]
+
+
+def test_philox_output_bits_are_uniform():
+    key = [0xDEADBEEF, 0x12345678]
+    words = np.array([orc.philox([i, 3, 4, 0], key) for i in range(4000)], dtype=np.uint64).ravel()
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint64)) & 1).astype(np.float64)
+    p = bits.mean(axis=0)
+    n = words.size
+    assert np.all(np.abs(p - 0.5) < 5 * math.sqrt(0.25 / n))
+
+
+# ---------------------------------------------------------------------------
+# Box-Muller normals: moments and distribution
+# ---------------------------------------------------------------------------
+def test_gauss_moments_and_ks():
+    from scipy import stats
+    key = [42, 0]
+    z = np.array([orc.gauss4([i, 0, 3, i // 7], key) for i in range(20000)]).ravel()
+    n = z.size
+    assert abs(z.mean()) < 4 / math.sqrt(n)
+    assert abs(z.var() - 1) < 4 * math.sqrt(2 / n)
+    assert abs(stats.kurtosis(z, fisher=False) - 3) < 0.1
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # python spec and C oracle agree to within rounding of libm
+    for i in range(50):
+        a = orc.gauss4([i, 1, 5, i], key)
+        b = spec.gauss4([i, 1, 5, i], key)
+        np.testing.assert_allclose(a, b, rtol=1e-14, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Number formats against torch's CPU casts
+# ---------------------------------------------------------------------------
+def test_bf16_rne_matches_torch():
+    import torch
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.standard_normal(5000).astype(np.float32),
+                        (rng.standard_normal(500) * 1e-30).astype(np.float32),
+                        np.array([1.0, -1.0, 0.0, 1.00390625, 1.01171875, 3.0e38], np.float32)])
+    # exact ties: mantissa low half = 0x8000
+    ties = (rng.integers(0, 128, 200).astype(np.uint32) << 16) | 0x3F800000 | 0x8000
+    x = np.concatenate([x, ties.view(np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    got = np.array([orc.bf16_rne(float(v)) for v in x], dtype=np.uint16)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_fp8_decode_and_rne_match_torch():
+    import torch
+    codes = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(codes).view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    got = np.array([orc.fp8_decode(int(q)) for q in codes])
+    finite = ~np.isnan(ref)
+    np.testing.assert_array_equal(got[finite], ref[finite])
+    assert np.all(np.isnan(got[~finite]))
+    rng = np.random.default_rng(2)
+    x = np.concatenate([(rng.standard_normal(4000) * 100).astype(np.float32),
+                        (rng.standard_normal(1000) * 0.01).astype(np.float32),
+                        ref[finite].astype(np.float32),
+                        ((ref[finite][:-1] + ref[finite][1:]) / 2).astype(np.float32)])  # ties
+    x = np.clip(x, -448, 448).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    got = np.array([orc.fp8_decode(orc.fp8_rne_sat(float(v))) for v in x])
+    np.testing.assert_array_equal(got, want)
+    assert orc.fp8_decode(orc.fp8_rne_sat(1e6)) == 448.0
+    assert orc.fp8_decode(orc.fp8_rne_sat(-500.0)) == -448.0
+
+
+# ---------------------------------------------------------------------------
+# Sizes: closed forms and the paper's parameter table
+# ---------------------------------------------------------------------------
+def test_input_dim_and_param_count_closed_forms():
+    for cfg, D, P in [(wl.world_small(), 104, 4581), (wl.world_65k(), 492, 36167), (wl.world_large(), 908, 133767)]:
+        assert orc.input_dim(cfg) == D == 4 * cfg["window"] ** 2 + cfg["n_scalars"]
+        H1, H2, A = cfg["hidden1"], cfg["hidden2"], cfg["n_actions"]
+        assert orc.param_count(cfg) == P == D * H1 + H1 + H1 * H2 + H2 + H2 * A + A
+
+
+def test_paper_parameter_table_reading():
+    """The paper's table fits R = (L-1)(c^2+c) + c^2 + 217c + 1 and RC = R + 5c:
+    L layers means L hidden c x c blocks after the summed sensor encoders, and the
+    compass adds 4 inputs (5c with its share of biases).  This pins the reading
+    '2-layer MLP' = two hidden layers of equal width used for the policy."""
+    tab = json.load(open(os.path.join(HERE, "golden", "network_params.json")))
+    for L, c, rc, r in tab["rows"]:
+        assert r == (L - 1) * (c * c + c) + c * c + 217 * c + 1
+        assert rc == r + 5 * c
+
+
+# ---------------------------------------------------------------------------
+# Observation window: independent construction with numpy roll + rot90
+# ---------------------------------------------------------------------------
+def _window_numpy(st, cfg, slot):
+    Wd, Ht, Sw = cfg["width"], cfg["height"], cfg["window"]
+    R = Sw // 2
+    occ = st["occ"].reshape(Ht, Wd)
+    agent = (occ >= 0).astype(np.float64)
+    res = st["res"].reshape(Ht, Wd).astype(np.float64)
+    wall = st["wall"].reshape(Ht, Wd).astype(np.float64)
+    ebin = np.zeros((Ht, Wd))
+    o = occ[occ >= 0]
+    ebin[occ >= 0] = np.clip(st["energy"][o].astype(np.int64) * 8 // cfg["e_repro"], 0, 7)
+    x, y = st["pos"][slot] % Wd, st["pos"][slot] // Wd
+    rows = (np.arange(y - R, y + R + 1)) % Ht
+    cols = (np.arange(x - R, x + R + 1)) % Wd
+    chans = []
+    for layer in (agent, res, wall, ebin):
+        patch = layer[np.ix_(rows, cols)]           # row 0 = north
+        chans.append(np.rot90(patch, k=int(st["facing"][slot])))  # facing becomes "up"
+    win = np.stack(chans, axis=-1).reshape(-1)
+    e = st["energy"][slot]
+    sc = [e / 256.0, min(st["age"][slot], 1024) / 1024.0, float(st["res"][st["pos"][slot]]),
+          1.0 if e >= cfg["e_repro"] else 0.0]
+    if cfg["n_scalars"] == 8:
+        sc += [1.0 if k == st["facing"][slot] else 0.0 for k in range(4)]
+    return np.concatenate([win, sc])
+
+
+def test_observation_matches_numpy_rot90():
+    cfg = wl.desc(width=23, height=17, n_agents_init=120, capacity=200, window=7, n_scalars=8, seed=3,
+                  resource_density=0.4)
+    w = orc.OracleWorld(cfg)
+    acts = wl.biased_actions(cfg["capacity"], cfg["n_actions"], 3, 0)
+    for step in range(3):
+        st = w.state()
+        for s in np.nonzero(st["alive"])[0][:60]:
+            np.testing.assert_array_equal(w.observe(int(s)), _window_numpy(st, cfg, int(s)))
+        w.step(actions=wl.biased_actions(cfg["capacity"], cfg["n_actions"], 3, step))
+
+
+# ---------------------------------------------------------------------------
+# Policy forward against numpy float64; sampling against searchsorted + chi2
+# ---------------------------------------------------------------------------
+def _forward_numpy(theta, x, D, H1, H2, A):
+    o = 0
+    W1 = theta[o:o + H1 * D].reshape(H1, D); o += H1 * D
+    b1 = theta[o:o + H1]; o += H1
+    W2 = theta[o:o + H2 * H1].reshape(H2, H1); o += H2 * H1
+    b2 = theta[o:o + H2]; o += H2
+    W3 = theta[o:o + A * H2].reshape(A, H2); o += A * H2
+    b3 = theta[o:o + A]
+    h1 = np.maximum(W1 @ x + b1, 0)
+    h2 = np.maximum(W2 @ h1 + b2, 0)
+    return W3 @ h2 + b3
+
+
+@pytest.mark.parametrize("wdtype", [0, 1, 2])
+def test_forward_matches_numpy(wdtype):
+    cfg = wl.desc(width=32, height=32, n_agents_init=40, capacity=64, window=5, n_scalars=8, hidden1=64,
+                  hidden2=64, n_actions=7, wdtype=wdtype, seed=11)
+    w = orc.OracleWorld(cfg)
+    D = orc.input_dim(cfg)
+    for s in range(40):
+        theta = w.weights(s)
+        ref = _forward_numpy(theta, w.observe(s), D, 64, 64, 7)
+        np.testing.assert_allclose(w.agent_logits(s), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_quantised_weights_match_torch_casts():
+    import torch
+    base = wl.desc(width=16, height=16, n_agents_init=4, capacity=8, window=3, hidden1=32, hidden2=32, seed=5)
+    m = orc.OracleWorld(dict(base, wdtype=0)).weights(1, master=True)
+    bf = orc.OracleWorld(dict(base, wdtype=1)).weights(1)
+    ref_bf = torch.from_numpy(m.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(bf, ref_bf)
+    f8w = orc.OracleWorld(dict(base, wdtype=2))
+    q = f8w.weights(1)
+    D = orc.input_dim(base)
+    # rows of W1: scale = amax/448 (FP32), value = fp8(w/scale) * scale
+    W1 = m[:32 * D].reshape(32, D).astype(np.float32)
+    for j in range(32):
+        sc = np.float32(np.abs(W1[j]).max()) / np.float32(448.0)
+        qq = torch.from_numpy((W1[j] / sc).astype(np.float32)).to(torch.float8_e4m3fn).double().numpy()
+        np.testing.assert_array_equal(q[j * D:(j + 1) * D], qq * np.float64(sc))
+    np.testing.assert_array_equal(q[32 * D:32 * D + 32], m[32 * D:32 * D + 32])  # biases stay FP32
+
+
+def test_sample_inverse_cdf_and_frequencies():
+    from scipy import stats
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        l = rng.standard_normal(7) * 3
+        u = rng.random()
+        p = np.exp(l - l.max())
+        c = np.cumsum(p)
+        assert orc.sample(l, u) == int(np.searchsorted(c, u * c[-1], side="right"))
+    l = np.array([0.3, -1.0, 2.0, 0.0, 1.0])
+    p = np.exp(l) / np.exp(l).sum()
+    key = [9, 9]
+    draws = [orc.sample(l, (orc.philox([i, 0, 4, 0], key)[0] >> 8) / 2**24) for i in range(20000)]
+    counts = np.bincount(draws, minlength=5)
+    assert stats.chisquare(counts, p * len(draws)).pvalue > 1e-3
+    assert orc.sample(np.array([0.0, -np.inf, 0.0]), 0.999999) == 2
+
+
+# ---------------------------------------------------------------------------
+# Hand-traced steps on a 4x4 torus (expected values written by hand)
+# ---------------------------------------------------------------------------
+def tiny_cfg(**kw):
+    c = wl.desc(width=4, height=4, n_agents_init=0, capacity=4, window=3, n_scalars=4, hidden1=32, hidden2=32,
+                n_actions=5, resource_density=0.0, regrow_prob=0.0, seed=1)
+    c.update(kw)
+    return c
+
+
+def run_both(cfg, st, actions):
+    """Step the C oracle and the python spec from `st` with `actions`; both must agree."""
+    o = orc.OracleWorld(cfg)
+    o.write_state(st)
+    o.step(actions=np.asarray(actions, np.uint8))
+    sp = spec.from_state(cfg, st)
+    sst = sp.step(actions=actions)
+    ost = o.state()
+    assert_same_state(ost, sp.state(), "oracle vs spec")
+    ostats = o.stats()
+    for k in ("births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked", "births_blocked_cell",
+              "births_blocked_capacity", "population", "resource_total"):
+        assert ostats[k] == sst[k], k
+    return ost, ostats
+
+
+def xy(st, slot, width=4):
+    return int(st["pos"][slot]) % width, int(st["pos"][slot]) // width
+
+
+def test_T1_contested_cell_lowest_slot_wins():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 1, E, 100)
+    place(st, 4, 1, 3, 1, W, 100)
+    out, s = run_both(tiny_cfg(), st, [3, 3, 0, 0])
+    assert xy(out, 0) == (2, 1) and xy(out, 1) == (3, 1)
+    assert s["moves_ok"] == 1 and s["moves_blocked"] == 1
+    assert out["energy"][0] == 99 and out["energy"][1] == 99
+
+
+def test_T2_no_chains():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 0, 0, E, 100)
+    place(st, 4, 1, 1, 0, E, 100)
+    out, s = run_both(tiny_cfg(), st, [3, 3, 0, 0])
+    assert xy(out, 1) == (2, 0) and xy(out, 0) == (0, 0)
+    assert s["moves_ok"] == 1 and s["moves_blocked"] == 1
+
+
+def test_T3_wraparound():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 3, 2, E, 100)
+    out, _ = run_both(tiny_cfg(), st, [3, 0, 0, 0])
+    assert xy(out, 0) == (0, 2)
+
+
+def test_T4_swap_blocks_both():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 1, E, 100)
+    place(st, 4, 1, 2, 1, W, 100)
+    out, s = run_both(tiny_cfg(), st, [3, 3, 0, 0])
+    assert xy(out, 0) == (1, 1) and xy(out, 1) == (2, 1)
+    assert s["moves_blocked"] == 2
+
+
+def test_T5_eat():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 1, N, 100)
+    place(st, 4, 1, 3, 3, N, 100)
+    st["res"][1 * 4 + 1] = 1
+    out, s = run_both(tiny_cfg(), st, [4, 4, 0, 0])
+    assert out["res"][5] == 0 and out["energy"][0] == 109 and out["energy"][1] == 99 and s["eaten"] == 1
+
+
+def test_turns():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 0, 0, N, 100)
+    place(st, 4, 1, 2, 2, N, 100)
+    out, _ = run_both(tiny_cfg(), st, [1, 2, 0, 0])
+    assert out["facing"][0] == W and out["facing"][1] == E
+
+
+def test_T6_death_frees_slot_for_same_step_birth():
+    st = empty_state(4, 4, 2)
+    place(st, 4, 0, 0, 0, N, 1)
+    place(st, 4, 1, 2, 2, N, 300, uid=7)
+    out, s = run_both(tiny_cfg(capacity=2), st, [0, 0])
+    assert s["deaths"] == 1 and s["births"] == 1
+    assert out["alive"][0] == 1 and xy(out, 0) == (2, 3)
+    assert out["energy"][0] == 100 and out["energy"][1] == 300 - 1 - 100
+    assert out["uid"][0] == 100 and out["parent_uid"][0] == 7 and out["uid_next"] == 101
+    assert out["occ"][0] == -1
+
+
+def test_T7_births_take_lowest_free_slots():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 1, N, 201)
+    place(st, 4, 2, 3, 3, E, 210)
+    out, s = run_both(tiny_cfg(), st, [0, 0, 0, 0])
+    assert s["births"] == 2
+    assert xy(out, 1) == (1, 2) and xy(out, 3) == (2, 3)
+    assert out["energy"][0] == 100 and out["energy"][2] == 109
+    assert out["energy"][1] == 100 and out["energy"][3] == 100
+    assert out["uid"][1] == 100 and out["uid"][3] == 101
+    assert out["facing"][1] == N and out["facing"][3] == E and out["age"][1] == 0
+
+
+def test_T8_birth_conflict():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 0, N, 250)
+    place(st, 4, 1, 1, 2, S, 250)
+    out, s = run_both(tiny_cfg(), st, [0, 0, 0, 0])
+    assert s["births"] == 1 and s["births_blocked_cell"] == 1
+    assert xy(out, 2) == (1, 1) and out["parent_uid"][2] == 0
+    assert out["energy"][0] == 149 and out["energy"][1] == 249
+
+
+def test_T9_capacity_blocks_birth():
+    st = empty_state(4, 4, 2)
+    place(st, 4, 0, 1, 1, N, 250)
+    place(st, 4, 1, 3, 3, N, 50)
+    out, s = run_both(tiny_cfg(capacity=2), st, [0, 0])
+    assert s["births"] == 0 and s["births_blocked_capacity"] == 1 and out["energy"][0] == 249
+
+
+def test_reproduce_action_required_with_seven_actions():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 1, 1, N, 250)
+    place(st, 4, 1, 3, 3, N, 250)
+    out, s = run_both(tiny_cfg(n_actions=7), st, [5, 0, 0, 0])
+    assert s["births"] == 1 and out["alive"][2] == 1 and out["parent_uid"][2] == 0
+
+
+def test_T10_regrowth_extremes():
+    st = empty_state(4, 4, 4)
+    place(st, 4, 0, 0, 0, N, 100)
+    st["res"][3] = 1
+    out, s = run_both(tiny_cfg(regrow_prob=1.0), st, [0, 0, 0, 0])
+    assert s["regrown"] == 15 and np.all(out["res"] == 1)
+    out, s = run_both(tiny_cfg(regrow_prob=0.0), st, [0, 0, 0, 0])
+    assert s["regrown"] == 0 and out["res"].sum() == 1
+
+
+def test_T11_window_orientation():
+    cfg = tiny_cfg(width=5, height=5, window=3, capacity=4)
+    for facing, idx in [(E, 4 * (0 * 3 + 1) + 1), (N, 4 * (1 * 3 + 2) + 1), (S, 4 * (1 * 3 + 0) + 1),
+                        (W, 4 * (2 * 3 + 1) + 1)]:
+        st = empty_state(5, 5, 4)
+        place(st, 5, 0, 2, 2, facing, 100)
+        st["res"][2 * 5 + 3] = 1  # resource at (x+1, y)
+        o = orc.OracleWorld(cfg)
+        o.write_state(st)
+        x = o.observe(0)
+        assert x[idx] == 1.0 and x[1:36:4].sum() == 1.0, facing
+        assert x[4 * 4 + 0] == 1.0  # the agent sees itself at the centre
+        assert list(spec.from_state(cfg, st).observe(0)) == list(x)
+
+
+def test_energy_bin_channel():
+    cfg = tiny_cfg(width=5, height=5, window=3)
+    st = empty_state(5, 5, 4)
+    place(st, 5, 0, 2, 2, N, 100)
+    place(st, 5, 1, 2, 1, N, 199)   # ahead: floor(199*8/200) = 7
+    place(st, 5, 2, 3, 2, N, 25)    # right: floor(25*8/200) = 1
+    place(st, 5, 3, 1, 2, N, 500)   # left: clamps at 7
+    o = orc.OracleWorld(cfg)
+    o.write_state(st)
+    x = o.observe(0)
+    assert x[4 * (0 * 3 + 1) + 3] == 7 and x[4 * (1 * 3 + 2) + 3] == 1 and x[4 * (1 * 3 + 0) + 3] == 7
+    assert x[4 * (1 * 3 + 1) + 3] == 4   # itself: 100*8/200
+
+
+# ---------------------------------------------------------------------------
+# N-version: C oracle vs python spec on tiny worlds, policy-sampled actions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_oracle_matches_spec_free_running(seed):
+    cfg = wl.desc(width=12, height=10, n_agents_init=14, capacity=24, window=3, n_scalars=8, hidden1=32,
+                  hidden2=32, n_actions=5, resource_density=0.5, regrow_prob=0.05, e_init=185, seed=seed)
+    o = orc.OracleWorld(cfg)
+    sp = spec.SpecWorld(cfg)
+    assert_same_state(o.state(), sp.state(), "init")
+    for s in range(12):
+        logits, sampled = o.step(want_logits=True, want_sampled=True)
+        live = sorted(sp.agents)
+        spl = {k: sp.logits(k) for k in live}
+        sst = sp.step()
+        for k in live:
+            np.testing.assert_allclose(logits[k], spl[k], rtol=1e-12, atol=1e-12)
+        assert_same_state(o.state(), sp.state(), f"step {s}")
+        assert o.stats()["births"] == sst["births"]
+        for k in sp.agents:
+            np.testing.assert_array_equal(o.weights(k, master=True), np.array(sp.agents[k]["theta"]))
+
+
+# ---------------------------------------------------------------------------
+# Invariants on longer runs with births and deaths
+# ---------------------------------------------------------------------------
+def test_invariants_over_random_run():
+    cfg = wl.desc(width=40, height=30, n_agents_init=200, capacity=320, window=5, resource_density=0.3,
+                  regrow_prob=0.02, e_init=150, seed=4)
+    w = orc.OracleWorld(cfg, materialize=False)
+    st0 = w.state()
+    st0["energy"][:200] = np.random.default_rng(4).integers(1, 260, 200)  # some die, some reproduce
+    w.write_state(st0)
+    prev = w.stats()
+    prev_st = w.state()
+    saw_births = saw_deaths = 0
+    for step in range(40):
+        acts = wl.biased_actions(cfg["capacity"], 5, 4, step)
+        w.step(actions=acts)
+        st, s = w.state(), w.stats()
+        check_invariants(st, 40, 30)
+        assert s["population"] == prev["population"] + s["births"] - s["deaths"]
+        assert s["resource_total"] == prev["resource_total"] - s["eaten"] + s["regrown"]
+        n_pre = prev["population"]
+        assert s["energy_total"] == prev["energy_total"] + cfg["e_eat"] * s["eaten"] - cfg["e_cost"] * n_pre
+        live = st["alive"].astype(bool)
+        uids = st["uid"][live]
+        assert len(np.unique(uids)) == len(uids)
+        assert st["uid_next"] == prev_st["uid_next"] + s["births"]
+        assert sum(s["action_hist"]) == n_pre
+        saw_births += s["births"]
+        saw_deaths += s["deaths"]
+        prev, prev_st = s, st
+    assert saw_births > 0 and saw_deaths > 0
+
+
+def test_mutation_noise_moments_and_lineage():
+    cfg = wl.desc(width=32, height=32, n_agents_init=100, capacity=256, window=3, n_scalars=4, hidden1=32,
+                  hidden2=32, resource_density=1.0, regrow_prob=1.0, e_init=195, mutation_sigma=0.05, seed=8)
+    w = orc.OracleWorld(cfg)
+    lazy = orc.OracleWorld(cfg, materialize=False)
+    acts = np.full(cfg["capacity"], 4, np.uint8)
+    before = w.state()
+    w.step(actions=acts)
+    lazy.step(actions=acts)
+    st = w.state()
+    kids = [s for s in range(cfg["capacity"]) if st["alive"][s] and not before["alive"][s]]
+    assert len(kids) > 20
+    parents_uid = {int(before["uid"][s]): s for s in range(cfg["capacity"]) if before["alive"][s]}
+    zs = []
+    for k in kids:
+        p = parents_uid[int(st["parent_uid"][k])]
+        parent_w = orc.OracleWorld(cfg).weights(p, master=True)  # parents are initial agents
+        child_w = w.weights(k, master=True)
+        zs.append((child_w - parent_w) / cfg["mutation_sigma"])
+        np.testing.assert_array_equal(lazy.weights(k, master=True), child_w)
+    z = np.concatenate(zs)
+    n = z.size
+    assert abs(z.mean()) < 4 / math.sqrt(n)
+    assert abs(z.var() - 1) < 4 * math.sqrt(2 / n) + 1e-3
+    w0 = orc.OracleWorld(dict(cfg, mutation_sigma=0.0))
+    b0 = w0.state()
+    w0.step(actions=acts)
+    s0 = w0.state()
+    for k in [s for s in range(cfg["capacity"]) if s0["alive"][s] and not b0["alive"][s]][:5]:
+        p = {int(b0["uid"][s]): s for s in range(cfg["capacity"]) if b0["alive"][s]}[int(s0["parent_uid"][k])]
+        np.testing.assert_array_equal(w0.weights(k, master=True), orc.OracleWorld(cfg).weights(p, master=True))
+
+
+def test_init_statistics():
+    from scipy import stats
+    cfg = wl.desc(width=128, height=128, n_agents_init=3000, capacity=4000, resource_density=0.1, window=3,
+                  seed=21)
+    w = orc.OracleWorld(cfg, materialize=False)
+    st = w.state()
+    live = np.nonzero(st["alive"])[0]
+    np.testing.assert_array_equal(live, np.arange(3000))
+    assert len(np.unique(st["pos"][live])) == 3000
+    n, p = 128 * 128, 0.1
+    assert abs(st["res"].sum() - n * p) < 5 * math.sqrt(n * p * (1 - p))
+    counts = np.bincount(st["facing"][live], minlength=4)
+    assert stats.chisquare(counts).pvalue > 1e-3
+    # uniform placement: agents per quadrant
+    x, y = st["pos"][live] % 128, st["pos"][live] // 128
+    q = np.bincount((x >= 64) * 2 + (y >= 64), minlength=4)
+    assert stats.chisquare(q).pvalue > 1e-3
+
+
+def test_init_weight_scale():
+    cfg = wl.desc(width=16, height=16, n_agents_init=20, capacity=32, window=5, n_scalars=8, hidden1=64,
+                  hidden2=64, n_actions=7, seed=2)
+    w = orc.OracleWorld(cfg)
+    D = orc.input_dim(cfg)
+    th = np.stack([w.weights(s, master=True) for s in range(20)])
+    o = 0
+    for rows, cols in [(64, D), (64, 64), (7, 64)]:
+        blk = th[:, o:o + rows * cols].ravel()
+        o += rows * cols
+        n = blk.size
+        assert abs(blk.var() * cols - 1) < 5 * math.sqrt(2 / n)
+        assert np.all(th[:, o:o + rows] == 0)  # biases
+        o += rows
+
+
+def test_regrowth_rate():
+    cfg = wl.desc(width=100, height=100, n_agents_init=0, capacity=8, resource_density=0.0, regrow_prob=0.3,
+                  window=3, seed=5)
+    w = orc.OracleWorld(cfg, materialize=False)
+    w.step(actions=np.zeros(8, np.uint8))
+    n, p = 10000, 0.3
+    assert abs(w.stats()["regrown"] - n * p) < 5 * math.sqrt(n * p * (1 - p))
+
+
+def test_invalid_descs_rejected():
+    for bad in [dict(window=4), dict(n_scalars=5), dict(n_actions=6), dict(capacity=10, n_agents_init=20),
+                dict(e_repro=0), dict(wdtype=7), dict(window=99)]:
+        with pytest.raises(ValueError):
+            orc.OracleWorld(wl.desc(**bad))
