@@ -1,0 +1,174 @@
+"""Benchmark of the world step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants]
+
+Workload: the 1024x1024 torus started with 65,536 agents (capacity 131,072),
+11x11x4 window + 8 scalars, per-agent 492->64->64->7 MLP, FP32 weights, with
+the full dynamics (costs, eating, deaths, births with mutation, regrowth).
+One step = one pass of the whole hot path (policy forward, sampling, moves,
+eating, births/deaths, regrowth, compaction/statistics) over all live agents.
+
+value = live agent-steps per second (sum over the timed steps of the agents
+alive at each step's start, divided by the wall time of the timed region,
+inputs resident in HBM).  The roofline object reports the policy kernel
+(the dominant kernel): algorithmic bytes (live agents x per-agent weight and
+state bytes) over its average duration measured with HIP events on the
+library's stream during the timed steps.  Also reported: BF16 and FP8 weight
+storage on the same world, the frozen-population form (exactly 65,536 agents
+every step), the replayed-hipGraph step time, and the CPU oracle on a bounded
+sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, AMD published
+STATE_BYTES_PER_AGENT = 24   # policy kernel's per-agent state traffic: live idx, pos, facing, energy, age, outputs
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True):
+    import torch
+    w = eco.World(cfg)
+    tuned = w.autotune() if autotune else w.get_launch()
+    w.set_flags(eco.RT_USE_GRAPH)
+    w.step(warmup)
+    torch.cuda.synchronize()
+    # timed region: eager launches with HIP events around every kernel (same stream)
+    w.set_flags(eco.RT_TIME_KERNELS)
+    w.kernel_times(reset=True)
+    s0 = w.stats()[0]["step"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = w.kernel_times(reset=True)
+    hist = w.stats_history(0, steps + 1)
+    assert hist[-1]["step"] == s0 + steps
+    agent_steps = sum(h["population"] for h in hist[:-1])  # live at the start of each timed step
+    res = dict(seconds=t1 - t0, steps=steps, agent_steps=agent_steps, kernel_times=kt, launch=tuned,
+               pop_start=hist[0]["population"], pop_end=hist[-1]["population"],
+               births=sum(h["births"] for h in hist[1:]), deaths=sum(h["deaths"] for h in hist[1:]),
+               info=w.info)
+    if graph_compare:
+        w.set_flags(eco.RT_USE_GRAPH)
+        w.step(2)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        w.step(steps)
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = (time.perf_counter() - g0) * 1e3 / steps
+    w.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(r):
+    ms, n = r["kernel_times"]["forward"]
+    avg_ms = ms / max(n, 1)
+    agents_per_launch = r["agent_steps"] / max(n, 1)
+    bytes_per_agent = r["info"]["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT
+    gbs = agents_per_launch * bytes_per_agent / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
+            "bytes_per_agent": bytes_per_agent, "agents_per_launch": round(agents_per_launch, 1)}
+
+
+def cpu_baseline(n_agents=8192, steps=4):
+    """The oracle as it stands, on a bounded sample of the same world shape."""
+    import numpy as np  # noqa: F401
+    from oracle import oracle as orc
+    from paper_2510_18221_amd import workloads as wl
+    cfg = wl.world_65k(seed=0)
+    cfg.update(n_agents_init=n_agents, capacity=2 * n_agents)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    w = orc.OracleWorld(cfg)
+    pops = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pops.append(w.stats()["population"])
+        w.step()
+    dt = time.perf_counter() - t0
+    return {"value": round(sum(pops) / dt, 1), "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"1024x1024 world, 492->64->64->7 FP32 policy, {n_agents} agents (1/8 of the 65,536), "
+                      f"{steps} full steps after init, FP64 policy + sequential world, OpenMP over the policy loop",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a plain 4 GiB device copy (PMC scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: worlds shard across GPUs by design but no multi-GPU path is "
+              "built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_18221_amd import eco
+    from paper_2510_18221_amd import workloads as wl
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    eco.lib()
+
+    log(f"[bench] 65k world FP32: warmup {args.warmup}, timed {args.steps}")
+    main_r = timed_run(eco, wl.world_65k(seed=0), args.steps, args.warmup, autotune=not args.no_autotune)
+    value = main_r["agent_steps"] / main_r["seconds"]
+    ms_per_step = main_r["seconds"] * 1e3 / main_r["steps"]
+    log(f"[bench] fp32: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, launch {main_r['launch']}")
+    out = {
+        "metric": "agent-steps/s at 65,536 agents, FP32 vs BF16 weights; % of HBM peak",
+        "value": round(value, 1), "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, "
+                               "11x11x4 window + 8 scalars, per-agent 492->64->64->7 MLP, FP32 weights, "
+                               "full dynamics", "agents_start": main_r["pop_start"],
+                   "agents_end": main_r["pop_end"], "births": main_r["births"], "deaths": main_r["deaths"],
+                   "launch": main_r["launch"]},
+        "roofline": roofline(main_r),
+        "graph_ms_per_step": round(main_r.get("graph_ms_per_step", 0.0), 4),
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in main_r["kernel_times"].items()},
+    }
+    if not args.no_variants:
+        variants = {}
+        for name, cfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)), ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
+                          ("fp32_frozen", wl.world_65k(seed=0, frozen=True))]:
+            log(f"[bench] variant {name}")
+            r = timed_run(eco, cfg, args.steps, args.warmup, autotune=not args.no_autotune, graph_compare=False)
+            v = r["agent_steps"] / r["seconds"]
+            variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
+                              "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
+                              "launch": r["launch"]}
+            log(f"[bench] {name}: {v / 1e6:.2f} M agent-steps/s")
+        out["variants"] = variants
+    if args.copy_probe:
+        x = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * eco.h -- C ABI of the MI355X (gfx950) world-step library libeco.so.
+ *
+ * The library advances one or more independent ecological worlds by whole
+ * steps on the GPU.  One step is the transition of the paper's Ecological Game
+ * (Sec. 3.1): every live agent observes the pre-step state through an
+ * egocentric window plus scalar sensors (Sec. 3.2 "Sensors"), evaluates its own
+ * MLP policy (Sec. 3.3), samples an action from the softmax, and the world then
+ * applies turns, forward moves (one agent per cell; a contested empty cell goes
+ * to the lowest slot), eating, the per-step energy cost and death, single-parent
+ * births directly behind the parent with Gaussian weight mutation into recycled
+ * slots (Sec. 3.2 "Actions", Sec. 3.3), and resource regrowth (Sec. 3.2
+ * "Resources").  The population function of Sec. 3.1 is exposed as the alive
+ * flags and parent identities of the state.
+ *
+ * Conventions
+ *  - Every call returns eco_status; the library never aborts or exits.
+ *    eco_last_error() returns a thread-local message for the last failure.
+ *  - Device buffers are owned by the eco_world (allocated through the caller's
+ *    eco_allocator when one is given, else hipMalloc) and released by
+ *    eco_world_destroy.  Host buffers passed in stay owned by the caller.
+ *  - All work is enqueued on the stream given at create (NULL = the null
+ *    stream).  eco_world_step is asynchronous; calls that return data to the
+ *    host synchronise that stream first.
+ *  - After a device error the object enters ECO_ESTATE: every call except
+ *    reset/destroy/last_error fails until eco_world_reset succeeds.
+ *  - An eco_world is not thread-safe; use one per host thread.
+ *  - Energies are int32 fixed point in units of 0.1 energy.
+ *  - Logical weight order (read/write_weights): W1[H1][D], b1[H1], W2[H2][H1],
+ *    b2[H2], W3[A][H2], b3[A] (row = output unit).  The device layout is private.
+ */
+#ifndef ECO_H
+#define ECO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eco_world eco_world;
+
+typedef enum {
+    ECO_OK = 0,
+    ECO_EINVAL = -1,   /* bad argument / descriptor / buffer size */
+    ECO_ENOMEM = -2,   /* device allocation failed */
+    ECO_EDEVICE = -3,  /* a HIP call failed; the object is now in ECO_ESTATE */
+    ECO_ESTATE = -4,   /* object unusable after an earlier device error */
+    ECO_ENOTSUP = -5   /* valid but unsupported configuration */
+} eco_status;
+
+/* Storage format of the per-agent weights used by the forward pass.
+ * FP32: the storage is the master copy.  BF16 (round-to-nearest-even) and
+ * FP8 E4M3FN (OCP, per-output-row FP32 scale = row amax / 448, biases FP32)
+ * are re-quantised from an FP32 master copy that mutation updates. */
+typedef enum { ECO_W_FP32 = 0, ECO_W_BF16 = 1, ECO_W_FP8E4M3 = 2 } eco_wdtype;
+
+/* Optional device allocator; alloc returns NULL on failure. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} eco_allocator;
+
+/* One world (POD, copied at create).  Grid is a torus of width x height. */
+typedef struct {
+    uint32_t struct_size;        /* = sizeof(eco_world_desc) */
+    uint32_t width, height;      /* 1 <= side, width*height < 2^31 */
+    uint32_t n_agents_init;      /* agents placed at init (<= capacity, <= cells) */
+    uint32_t capacity;           /* agent slots (births beyond it are blocked) */
+    float resource_density;      /* initial P(cell holds one resource unit) */
+    float regrow_prob;           /* per-step P(empty cell regrows one unit) */
+    float mutation_sigma;        /* std of the child's Gaussian weight noise */
+    uint32_t window;             /* S, odd, S <= width, S <= height */
+    uint32_t n_scalars;          /* 4 (internal+external) or 8 (+compass) */
+    uint32_t hidden1, hidden2;   /* each 32, 64 or 128 */
+    uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack) */
+    int32_t e_init, e_cost, e_eat, e_repro, e_child;  /* units of 0.1 energy; e_repro > 0 */
+    uint32_t wdtype;             /* eco_wdtype; identical for all worlds of one object */
+    uint32_t keep_master;        /* reserved: BF16/FP8 always keep an FP32 master */
+    uint32_t attack_enabled;     /* must be 0 (the attack action is inert) */
+    uint32_t flags;              /* ECO_DESC_* */
+    uint64_t seed;               /* Philox key of this world */
+} eco_world_desc;
+
+/* Statistics of one step of one world (the measurement interface of App. E). */
+typedef struct {
+    uint64_t step;                     /* steps completed */
+    uint64_t population;               /* live agents after the step */
+    uint64_t births, deaths, eaten, regrown;
+    uint64_t moves_ok, moves_blocked;  /* FORWARD actions that did / did not move */
+    uint64_t births_blocked_cell;      /* eligible parents whose cell behind was taken */
+    uint64_t births_blocked_capacity;  /* winners left without a free slot */
+    uint64_t resource_total;           /* resource units on the grid after regrowth */
+    uint64_t action_hist[8];           /* actions taken by the agents live at step start */
+    double energy_total;               /* sum of live energies (units of 0.1; exact) */
+    double trait_mean, trait_var;      /* mean / variance over live agents of |theta_master|^2 */
+} eco_stats;
+
+/* Launch shape of the policy-forward kernel (tuned by eco_world_autotune). */
+typedef struct {
+    uint32_t waves_per_block;   /* 1, 2, 4 or 8 */
+    uint32_t blocks_per_cu;     /* persistent grid = blocks_per_cu * CUs */
+    uint32_t unroll;            /* 16-byte weight loads in flight per lane: 4, 8 or 16 */
+    uint32_t reserved;
+} eco_launch;
+
+/* Static facts about an object (sizes for bandwidth accounting). */
+typedef struct {
+    uint32_t n_worlds, total_slots;
+    uint64_t total_cells;
+    uint32_t input_dim, hidden1, hidden2, n_actions;
+    uint64_t param_count;              /* P */
+    uint64_t weight_bytes_per_agent;   /* bytes one forward pass reads (algorithmic) */
+    uint64_t storage_stride, master_stride;  /* device bytes per slot (0 = no master) */
+    uint64_t device_bytes;             /* total device memory held */
+    uint32_t n_cus;
+    uint32_t wdtype;
+} eco_info;
+
+/* Per-kernel GPU time accumulated while ECO_RT_TIME_KERNELS is set. */
+enum { ECO_K_FORWARD = 0, ECO_K_MOVE = 1, ECO_K_BIRTH_CLAIM = 2, ECO_K_BIRTH_SCAN = 3,
+       ECO_K_BIRTH_COMMIT = 4, ECO_K_REGROW = 5, ECO_K_COMPACT = 6, ECO_K_COUNT = 7 };
+typedef struct {
+    double ms[8];
+    uint64_t launches[8];
+} eco_kernel_times;
+
+/* Runtime flags (eco_world_set_flags). */
+#define ECO_RT_KEEP_LOGITS 1u   /* forward writes FP32 logits for read_logits */
+#define ECO_RT_USE_GRAPH 2u     /* eco_world_step replays a captured hipGraph (default on) */
+#define ECO_RT_TIME_KERNELS 4u  /* eager launches bracketed by hipEvents per kernel */
+
+/* Create n_worlds worlds (all with the same window, n_scalars, hidden sizes,
+ * n_actions and wdtype) and run the deterministic init of Sec. 3.3 / placement.
+ * hip_stream: a hipStream_t or NULL.  alloc: NULL = hipMalloc/hipFree.
+ * Errors: EINVAL (bad desc, with the field named), ENOTSUP (attack, sizes
+ * without a kernel), ENOMEM, EDEVICE. */
+eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void* hip_stream,
+                            const eco_allocator* alloc, eco_world** out);
+void eco_world_destroy(eco_world* w);
+const char* eco_last_error(void);
+
+/* Advance every world by n_steps whole steps (asynchronous). */
+eco_status eco_world_step(eco_world* w, uint32_t n_steps);
+
+/* Re-initialise every world; seeds = NULL keeps each world's seed, else
+ * seeds[n_worlds] replaces them.  Clears ECO_ESTATE on success. */
+eco_status eco_world_reset(eco_world* w, const uint64_t* seeds);
+
+/* Latest step's statistics of worlds 0..min(n_worlds, max_worlds)-1 (synchronises). */
+eco_status eco_world_stats(eco_world* w, eco_stats* out, uint32_t max_worlds);
+/* The last up to max_records steps of one world, oldest first; *n_out = count.
+ * The device ring keeps the most recent 1024 steps. */
+eco_status eco_world_stats_history(eco_world* w, uint32_t world, eco_stats* out,
+                                   uint32_t max_records, uint32_t* n_out);
+
+eco_status eco_world_info(const eco_world* w, eco_info* out);
+eco_status eco_world_set_flags(eco_world* w, uint32_t flags);
+eco_status eco_world_set_launch(eco_world* w, const eco_launch* launch);
+eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
+/* Time every candidate launch shape on the forward pass of the current state
+ * (the forward has no side effect on the world) and keep the fastest.  Every
+ * candidate produces bit-identical actions.  *best may be NULL. */
+eco_status eco_world_autotune(eco_world* w, eco_launch* best);
+eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);
+
+/* ---- parity / test hooks (not on the timed path) ------------------------ */
+
+/* One step with the given actions (host array, one per slot of every world,
+ * worlds concatenated in order; entries of dead slots ignored; values must be
+ * < n_actions for live slots).  The policy still runs, so read_logits and
+ * read_sampled report what the policy would have done. */
+eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions);
+
+/* Integer state of one world, layout (little endian):
+ *   u64 step, u64 uid_next, u32 width, u32 height, u32 capacity, u32 0   (32 B)
+ *   u64 uid[cap], u64 parent_uid[cap], i32 pos[cap], i32 energy[cap], i32 age[cap],
+ *   i32 occ[cells], u8 facing[cap], u8 alive[cap], u8 action[cap], u8 res[cells], u8 wall[cells]
+ * pos = y*width + x; occ = slot or -1; facing 0..3 = N,E,S,W (y grows down);
+ * parent_uid of initial agents = UINT64_MAX.  Fields of dead slots other than
+ * alive are unspecified.  bytes must be >= eco_world_state_bytes(). */
+size_t eco_world_state_bytes(const eco_world* w, uint32_t world);
+eco_status eco_world_read_state(eco_world* w, uint32_t world, void* buf, size_t bytes);
+/* Replace the integer state; slots alive in buf but not before get the
+ * initial weights of their slot index.  Must keep occ consistent with pos. */
+eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, size_t bytes);
+
+/* FP32 logits of the last step's forward, [cap][n_actions]; NaN for slots not
+ * live at that step's start.  Requires ECO_RT_KEEP_LOGITS during that step. */
+eco_status eco_world_read_logits(eco_world* w, uint32_t world, float* out, size_t n_floats);
+/* The policy's sampled action of the last step per slot (255 if not live). */
+eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, size_t n);
+
+/* Weights of one live slot in logical order as doubles: which = 0 the storage
+ * values dequantised exactly, which = 1 the FP32 master. */
+eco_status eco_world_read_weights(eco_world* w, uint32_t world, uint32_t slot, int which,
+                                  double* out, size_t n);
+/* Overwrite one slot's FP32 master (logical order) and re-quantise its storage. */
+eco_status eco_world_write_weights(eco_world* w, uint32_t world, uint32_t slot,
+                                   const float* master, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECO_H */

@@ -1,0 +1,193 @@
+// eco_device.h -- device-side definitions shared by the gfx950 kernels of libeco.
+//
+// Data layout in HBM (all worlds of one object concatenated):
+//   per slot (SoA, global slot = world.slot_off + local slot):
+//     pos i32, energy i32, age i32, tgt i32 (move / birth target cell),
+//     facing u8, flags u8 (bit0 alive, bit1 birth claim made, bit2 birth won),
+//     act u8 (action applied), sampled u8 (policy's choice), act_in u8 (injected),
+//     uid u64, puid u64, trait f64 (|theta_master|^2)
+//   per cell (global cell = world.cell_off + y*W + x):
+//     occ i32 (local slot or -1), claim u32 (lowest claiming global slot), res u8, wall u8
+//   weights: storage[slot][storage_stride bytes] in the blocked layout below,
+//            master[slot][master_stride bytes] FP32 (BF16/FP8 only; FP32 storage is the master)
+//   per world: live list segment live[slot_off ..], birth lists, WorldVar, stats ring.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/eco.h"
+
+namespace eco {
+
+constexpr int kStatsRing = 1024;
+constexpr uint8_t kAlive = 1, kBirthClaim = 2, kBirthWon = 4;
+enum Action : uint8_t { REST = 0, TURN_L = 1, TURN_R = 2, FORWARD = 3, EAT = 4, REPRODUCE = 5, ATTACK = 6 };
+// Philox stream tags (third counter word).
+enum Stream : uint32_t { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
+                         ST_MUTATE = 5, ST_REGROW = 6 };
+
+// Immutable per-world parameters (device table, one entry per world).
+struct WorldParams {
+  uint32_t W, H, cells, cap;
+  uint32_t slot_off, cell_off;
+  uint32_t key0, key1;
+  uint64_t regrow_thr;          // floor(p * 2^32), compared with a 32-bit draw
+  uint64_t density_thr;         // floor(rho * 2^32)
+  int32_t e_init, e_cost, e_eat, e_repro, e_child;
+  float sigma;
+  uint32_t n_init;
+  uint32_t has_walls;
+};
+
+// Mutable per-world scalars.
+struct WorldVar {
+  uint64_t step;
+  uint64_t uid_next;
+  uint32_t n_live;      // live agents (the live list of this step)
+  uint32_t n_births;    // successful births of this step
+  uint32_t n_win;       // birth-claim winners of this step
+  uint32_t pad;
+};
+
+// Counters accumulated by the kernels of one step (u64 atomics), finalised
+// into the eco_stats ring by the compaction kernel.
+struct StepCounters {
+  unsigned long long births, deaths, eaten, regrown, moves_ok, moves_blocked, births_blocked_cell,
+      births_blocked_capacity, resource_total, action_hist[8];
+};
+
+// Weight layouts.  VPL = values per 16-byte block (FP32 4, BF16 8, FP8 16).
+// Master (FP32, and FP32 storage):  L1 [KB1][H1][4] | b1[H1] | L2 [H1/4][H2][4] | b2[H2] |
+//                                   L3 [8][H2] | b3[8]     (rows a >= A of L3/b3 are zero)
+// BF16 storage: L1 [ceil(KB1/2)][H1][8] | b1[H1] | L2 [H1/8][H2][8] | b2[H2] | L3 [8][H2] | b3[8]
+// FP8 storage:  L1 [ceil(KB1/4)][H1][16] | L2 [H1/16][H2][16] | L3 [8][H2] (bytes) |
+//               b1,b2,b3 FP32 | sc1[H1], sc2[H2], sc3[8] FP32 per-row scales
+// KB1 = D/4 (D = 4 S^2 + n_s is a multiple of 4).
+struct Layout {
+  uint32_t D, S, R, ns, H1, H2, A, wdtype;
+  uint32_t P;                   // logical parameters
+  uint32_t KB1;                 // FP32 16-byte blocks per L1 row
+  uint32_t KBv;                 // storage 16-byte blocks per L1 row
+  uint32_t Dpad;                // KBv * VPL (observation buffer length)
+  // logical offsets (nn.Linear order)
+  uint32_t p_w1, p_b1, p_w2, p_b2, p_w3, p_b3;
+  // master unit ranges (a unit = 4 consecutive logical parameters = 16 bytes)
+  uint32_t u_w1, u_b1, u_w2, u_b2, u_w3, u_b3, u_end;
+  // storage byte offsets
+  uint32_t s_w1, s_b1, s_w2, s_b2, s_w3, s_b3, s_sc1, s_sc2, s_sc3;
+  uint64_t sstride;             // storage bytes per slot (multiple of 256)
+  uint64_t mstride;             // master bytes per slot (0 when storage is FP32)
+};
+
+// Pointers of one object's device state.
+struct Dev {
+  const WorldParams* wp;
+  WorldVar* wv;
+  StepCounters* cnt;
+  eco_stats* ring;              // [n_worlds][kStatsRing]
+  int32_t *pos, *energy, *age, *tgt;
+  uint8_t *facing, *flags, *act, *sampled, *act_in;
+  unsigned long long *uid, *puid;
+  double* trait;
+  int32_t* occ;
+  uint32_t* claim;
+  uint8_t *res, *wall;
+  uint8_t* store;               // [total_slots][sstride]
+  uint8_t* master;              // [total_slots][mstride] or == store for FP32
+  int32_t* live;                // [total_slots], per-world segments at slot_off
+  int32_t* bparent;             // [total_slots] birth winners (local slots) by rank
+  int32_t* freel;               // [total_slots] free slots (local) ascending
+  float* logits;                // [total_slots][8] or null
+  unsigned long long* cellkeys; // init scratch: [total_cells] (key << 32 | local cell)
+  unsigned long long* sorted;   // init scratch
+  uint32_t n_worlds;
+  uint32_t total_slots;
+  uint32_t total_cells;
+  uint32_t keep_logits;
+  uint32_t inject;
+  uint32_t dry;                 // forward only: write sampled/logits, leave the world untouched
+};
+
+// Tile of one world's slot or cell range, for per-slot / per-cell kernels.
+struct Tile {
+  uint32_t world, start, count, pad;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, two 32x32->64
+// multiplies per round, key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t draw32(const WorldParams& w, uint32_t a, uint32_t step, uint32_t stream) {
+  return philox10(a, step, stream, 0u, w.key0, w.key1).x;
+}
+
+// Four standard normals from one Philox block by the Box-Muller transform
+// (Box & Muller 1958), evaluated in FP64 so the noise is the correctly
+// rounded transform up to the last bit of log/sin/cos.
+__device__ __forceinline__ void gauss4(const WorldParams& w, uint32_t a, uint32_t step, uint32_t stream,
+                                       uint32_t blk, double z[4]) {
+  const uint4 x = philox10(a, step, stream, blk, w.key0, w.key1);
+  const double two_pi = 6.283185307179586476925286766559;
+  const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const double u1 = (double)((xs[2 * p] >> 8) + 1u) * 0x1p-24;
+    const double u2 = (double)(xs[2 * p + 1] >> 8) * 0x1p-24;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincos(two_pi * u2, &s, &c);
+    z[2 * p] = r * c;
+    z[2 * p + 1] = r * s;
+  }
+}
+
+__device__ __forceinline__ int dir_dx(int f) { return f == 1 ? 1 : (f == 3 ? -1 : 0); }
+__device__ __forceinline__ int dir_dy(int f) { return f == 0 ? -1 : (f == 2 ? 1 : 0); }
+
+// Local cell one step from `cell` along facing f (sign = +1 ahead, -1 behind), torus.
+__device__ __forceinline__ uint32_t neighbour(const WorldParams& w, uint32_t cell, int f, int sign) {
+  int x = (int)(cell % w.W), y = (int)(cell / w.W);
+  x += sign * dir_dx(f);
+  y += sign * dir_dy(f);
+  if (x < 0) x += (int)w.W; else if (x >= (int)w.W) x -= (int)w.W;
+  if (y < 0) y += (int)w.H; else if (y >= (int)w.H) y -= (int)w.H;
+  return (uint32_t)y * w.W + (uint32_t)x;
+}
+
+// Wave-local LDS ordering: keeps the compiler from moving LDS accesses across
+// this point; LDS operations of one wave complete in issue order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Index of the world whose [off[w], off[w+1]) range holds g (off in LDS, n worlds).
+__device__ __forceinline__ uint32_t find_world(const uint32_t* off, uint32_t n, uint32_t g) {
+  uint32_t lo = 0, hi = n;  // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace eco

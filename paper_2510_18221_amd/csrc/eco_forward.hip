@@ -1,0 +1,369 @@
+// eco_forward.hip -- policy step of every live agent (observation, MLP, sample, turn/claim).
+//
+// One wavefront evaluates one agent at a time; each agent's weights are read
+// exactly once per step (no reuse across agents), so the kernel is bound by HBM
+// bandwidth, not by the matrix cores: the product is a batched GEMV with a
+// private matrix per agent (Sec. 3.3 per-agent policies).
+//
+// Per agent:
+//  1. Observation (Sec. 3.2 "Sensors", App. F "Around" layout): the S x S
+//     window around the agent, rotated so the agent faces the top row, four
+//     channels per cell (agent present, resource, wall, occupant energy bin),
+//     then the scalar sensors (energy, age, resource here, reproduction
+//     eligibility, and the 4-way compass when n_s = 8).  Written to LDS.
+//  2. h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), l = W3 h2 + b3 (Sec. 3.3).
+//     The weights of a layer are stored as 16-byte blocks [k-block][row]; lane
+//     l streams block it*64+l, so every load instruction of the wave reads one
+//     contiguous kilobyte, and each lane owns whole output rows (no cross-lane
+//     reduction in layers 1-2).  The input values come from LDS as broadcasts.
+//  3. Softmax sample with a Philox uniform (Sec. 3.3), temperature 1.
+//  4. Turns; a FORWARD mover whose target was empty at step start claims it
+//     with atomicMin on the slot id (lowest slot wins, Sec. 3.2 "Actions").
+#include "eco_device.h"
+
+#ifndef ECO_FWD_WDT
+#error "compile with -DECO_FWD_WDT=0|1|2"
+#endif
+
+namespace eco {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int WDT>
+struct WTraits;
+template <>
+struct WTraits<0> { static constexpr int VPL = 4; };
+template <>
+struct WTraits<1> { static constexpr int VPL = 8; };
+template <>
+struct WTraits<2> { static constexpr int VPL = 16; };
+
+__device__ __forceinline__ float bf16lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// acc += sum over the VPL values of one 16-byte weight block times xs[0..VPL),
+// in ascending value order.
+template <int WDT>
+__device__ __forceinline__ float dot_block(u32x4 w, const float* __restrict__ xs, float acc);
+
+template <>
+__device__ __forceinline__ float dot_block<0>(u32x4 w, const float* __restrict__ xs, float acc) {
+  const float4 x = *reinterpret_cast<const float4*>(xs);
+  acc = __builtin_fmaf(__uint_as_float(w.x), x.x, acc);
+  acc = __builtin_fmaf(__uint_as_float(w.y), x.y, acc);
+  acc = __builtin_fmaf(__uint_as_float(w.z), x.z, acc);
+  acc = __builtin_fmaf(__uint_as_float(w.w), x.w, acc);
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ float dot_block<1>(u32x4 w, const float* __restrict__ xs, float acc) {
+  const float4 a = *reinterpret_cast<const float4*>(xs);
+  const float4 b = *reinterpret_cast<const float4*>(xs + 4);
+  acc = __builtin_fmaf(bf16lo(w.x), a.x, acc);
+  acc = __builtin_fmaf(bf16hi(w.x), a.y, acc);
+  acc = __builtin_fmaf(bf16lo(w.y), a.z, acc);
+  acc = __builtin_fmaf(bf16hi(w.y), a.w, acc);
+  acc = __builtin_fmaf(bf16lo(w.z), b.x, acc);
+  acc = __builtin_fmaf(bf16hi(w.z), b.y, acc);
+  acc = __builtin_fmaf(bf16lo(w.w), b.z, acc);
+  acc = __builtin_fmaf(bf16hi(w.w), b.w, acc);
+  return acc;
+}
+
+// FP8 E4M3 (OCP) pairs decoded by the gfx950 conversion instruction.
+__device__ __forceinline__ float dot_fp8_word(uint32_t w, float4 x, float acc) {
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+  acc = __builtin_fmaf(lo[0], x.x, acc);
+  acc = __builtin_fmaf(lo[1], x.y, acc);
+  acc = __builtin_fmaf(hi[0], x.z, acc);
+  acc = __builtin_fmaf(hi[1], x.w, acc);
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ float dot_block<2>(u32x4 w, const float* __restrict__ xs, float acc) {
+  acc = dot_fp8_word(w.x, *reinterpret_cast<const float4*>(xs), acc);
+  acc = dot_fp8_word(w.y, *reinterpret_cast<const float4*>(xs + 4), acc);
+  acc = dot_fp8_word(w.z, *reinterpret_cast<const float4*>(xs + 8), acc);
+  acc = dot_fp8_word(w.w, *reinterpret_cast<const float4*>(xs + 12), acc);
+  return acc;
+}
+
+// Streams one layer stored as [KB][ROWS] 16-byte blocks.  Lane l reads block
+// it*64 + l; ROWS = 64: row l, k-block it.  ROWS = 32: row l%32, k-block
+// 2it + l/32 (the two half-waves are summed afterwards).  ROWS = 128: row
+// l + 64 (it%2), k-block it/2 (two accumulators).  Accumulation order per
+// row is fixed by (ROWS, KB) only, never by U.
+template <int WDT, int ROWS, int U>
+__device__ __forceinline__ void stream_layer(const u32x4* __restrict__ blk, int KB, const float* __restrict__ xs,
+                                             int lane, float (&acc)[ROWS == 128 ? 2 : 1]) {
+  constexpr int VPL = WTraits<WDT>::VPL;
+  static_assert(U % 2 == 0, "U must be even");
+  const int nblk = KB * ROWS;
+  const int nit = (nblk + 63) >> 6;
+  for (int it0 = 0; it0 < nit; it0 += U) {
+    u32x4 w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = ((it0 + u) << 6) + lane;
+      w[u] = (e < nblk) ? __builtin_nontemporal_load(blk + e) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int it = it0 + u;
+      if (it < nit) {
+        if (ROWS == 64) {
+          acc[0] = dot_block<WDT>(w[u], xs + it * VPL, acc[0]);
+        } else if (ROWS == 32) {
+          const int kb = 2 * it + (lane >> 5);
+          if (kb < KB) acc[0] = dot_block<WDT>(w[u], xs + kb * VPL, acc[0]);
+        } else {
+          acc[u & 1] = dot_block<WDT>(w[u], xs + (it >> 1) * VPL, acc[u & 1]);
+        }
+      }
+    }
+  }
+}
+
+template <int WDT>
+__device__ __forceinline__ float load_bias(const uint8_t* __restrict__ p, int i) {
+  if (WDT == 1) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(p)[i] << 16);
+  return reinterpret_cast<const float*>(p)[i];
+}
+
+// One hidden layer: streamed dot products, half-wave combine, scale, bias, ReLU,
+// result to LDS hs[0..ROWS).
+template <int WDT, int ROWS, int U>
+__device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, uint32_t w_off, uint32_t b_off,
+                                             uint32_t sc_off, int KB, const float* __restrict__ xs,
+                                             float* __restrict__ hs, int lane) {
+  float acc[ROWS == 128 ? 2 : 1];
+#pragma unroll
+  for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) acc[r] = 0.0f;
+  stream_layer<WDT, ROWS, U>(reinterpret_cast<const u32x4*>(wbase + w_off), KB, xs, lane, acc);
+  if (ROWS == 32) acc[0] += __shfl_xor(acc[0], 32);
+#pragma unroll
+  for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) {
+    const int j = (ROWS == 32) ? (lane & 31) : lane + 64 * r;
+    float v = acc[r];
+    if (WDT == 2) v *= reinterpret_cast<const float*>(wbase + sc_off)[j];
+    v += load_bias<WDT>(wbase + b_off, j);
+    v = fmaxf(v, 0.0f);
+    if (ROWS != 32 || lane < 32) hs[j] = v;
+  }
+  wave_sync();
+}
+
+// Output layer [8][H2] values: lane l = 8a + g sums H2/8 products of row a,
+// then a butterfly over g; returns logit a (rows a >= A are zero).
+template <int WDT, int H2>
+__device__ __forceinline__ float output_layer(const uint8_t* __restrict__ wbase, const Layout& L,
+                                              const float* __restrict__ h2, int lane) {
+  constexpr int NV = H2 / 8;
+  const int a = lane >> 3, g = lane & 7;
+  const int first = a * H2 + g * NV;
+  const float* hv = h2 + g * NV;
+  float part = 0.0f;
+  if (WDT == 0) {
+    const float4* w = reinterpret_cast<const float4*>(wbase + L.s_w3) + first / 4;
+#pragma unroll
+    for (int q = 0; q < NV / 4; ++q) {
+      const float4 v = w[q];
+      part = __builtin_fmaf(v.x, hv[4 * q + 0], part);
+      part = __builtin_fmaf(v.y, hv[4 * q + 1], part);
+      part = __builtin_fmaf(v.z, hv[4 * q + 2], part);
+      part = __builtin_fmaf(v.w, hv[4 * q + 3], part);
+    }
+  } else if (WDT == 1) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(wbase + L.s_w3) + first / 2;
+#pragma unroll
+    for (int q = 0; q < NV / 2; ++q) {
+      const uint32_t v = w[q];
+      part = __builtin_fmaf(bf16lo(v), hv[2 * q + 0], part);
+      part = __builtin_fmaf(bf16hi(v), hv[2 * q + 1], part);
+    }
+  } else {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(wbase + L.s_w3 + first);
+#pragma unroll
+    for (int q = 0; q < NV / 4; ++q)
+      part = dot_fp8_word(w[q], make_float4(hv[4 * q], hv[4 * q + 1], hv[4 * q + 2], hv[4 * q + 3]), part);
+  }
+  part += __shfl_xor(part, 1);
+  part += __shfl_xor(part, 2);
+  part += __shfl_xor(part, 4);
+  if (WDT == 2) part *= reinterpret_cast<const float*>(wbase + L.s_sc3)[a];
+  part += load_bias<WDT>(wbase + L.s_b3, a);
+  return part;
+}
+
+// Exclusive prefix of the per-world live counts into off[0..n] (wave 0 of the block).
+__device__ __forceinline__ void world_offsets(const WorldVar* __restrict__ wv, uint32_t n, uint32_t* off) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const uint32_t per = (n + 63) / 64;
+    const uint32_t lo = tid * per, hi = min(lo + per, n);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i) s += wv[i].n_live;
+    uint32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(inc, d);
+      if (tid >= d) inc += v;
+    }
+    uint32_t run = inc - s;
+    for (uint32_t i = lo; i < hi; ++i) {
+      off[i] = run;
+      run += wv[i].n_live;
+    }
+    if (tid == 63) off[n] = inc;
+  }
+  __syncthreads();
+}
+
+template <int WDT, int H, int U>
+__global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
+  constexpr int VPL = WTraits<WDT>::VPL;
+  extern __shared__ __align__(16) float smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  uint32_t* woff = reinterpret_cast<uint32_t*>(smem);
+  const uint32_t woff_words = (d.n_worlds + 1 + 3) & ~3u;
+  float* xs = smem + woff_words + wave * (L.Dpad + 2 * 128);
+  float* h1s = xs + L.Dpad;
+  float* h2s = h1s + 128;
+
+  for (uint32_t i = L.D + lane; i < L.Dpad; i += 64) xs[i] = 0.0f;  // padding stays zero
+  world_offsets(d.wv, d.n_worlds, woff);
+  const uint32_t total = woff[d.n_worlds];
+  const uint32_t n_waves = gridDim.x * wpb;
+  const uint32_t gw = blockIdx.x * wpb + wave;
+  const uint32_t chunk = (total + n_waves - 1) / n_waves;
+  const uint32_t g_lo = gw * chunk, g_hi = min(g_lo + chunk, total);
+  if (g_lo >= g_hi) return;
+
+  const int S = (int)L.S, R = (int)L.R, SS = S * S;
+  uint32_t w = find_world(woff, d.n_worlds, g_lo);
+  for (uint32_t g = g_lo; g < g_hi; ++g) {
+    while (g >= woff[w + 1]) ++w;
+    const WorldParams wp = d.wp[w];
+    const uint32_t step = (uint32_t)d.wv[w].step;
+    const uint32_t local = (uint32_t)d.live[wp.slot_off + (g - woff[w])];
+    const uint32_t slot = wp.slot_off + local;
+
+    // ---- 1. observation into LDS ----
+    const int pos = d.pos[slot];
+    const int f = d.facing[slot];
+    const int E = d.energy[slot];
+    const int age = d.age[slot];
+    const int ax = pos % (int)wp.W, ay = pos / (int)wp.W;
+    const int dx = dir_dx(f), dy = dir_dy(f), rx = -dy, ry = dx;
+    for (int i = lane; i < SS; i += 64) {
+      const int r = i / S, c = i - r * S;
+      const int fw = R - r, rt = c - R;
+      int cx = ax + fw * dx + rt * rx, cy = ay + fw * dy + rt * ry;
+      if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
+      if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
+      const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
+      const int o = d.occ[cell];
+      const float rs = (float)d.res[cell];
+      const float wl = wp.has_walls ? (float)d.wall[cell] : 0.0f;
+      int eb = 0;
+      if (o >= 0) {
+        const long long e8 = (long long)d.energy[wp.slot_off + o] * 8;
+#pragma unroll
+        for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1 : 0;
+      }
+      reinterpret_cast<float4*>(xs)[i] = make_float4(o >= 0 ? 1.0f : 0.0f, rs, wl, (float)eb);
+    }
+    if (lane < (int)L.ns) {
+      float v;
+      if (lane == 0) v = ldexpf((float)E, -8);
+      else if (lane == 1) v = ldexpf((float)min(age, 1024), -10);
+      else if (lane == 2) v = (float)d.res[wp.cell_off + pos];
+      else if (lane == 3) v = (E >= wp.e_repro) ? 1.0f : 0.0f;
+      else v = (lane - 4 == f) ? 1.0f : 0.0f;
+      xs[4 * SS + lane] = v;
+    }
+    wave_sync();
+
+    // ---- 2. the agent's MLP, weights streamed once from HBM ----
+    const uint8_t* wbase = d.store + (uint64_t)slot * L.sstride;
+    hidden_layer<WDT, H, U>(wbase, L.s_w1, L.s_b1, L.s_sc1, (int)L.KBv, xs, h1s, lane);
+    hidden_layer<WDT, H, U>(wbase, L.s_w2, L.s_b2, L.s_sc2, H / VPL, h1s, h2s, lane);
+    const float lg = output_layer<WDT, H>(wbase, L, h2s, lane);
+
+    // ---- 3. softmax inverse-CDF sample ----
+    const int A = (int)L.A;
+    float l[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) l[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lg), 8 * a));
+    float m = l[0];
+#pragma unroll
+    for (int a = 1; a < 8; ++a)
+      if (a < A) m = fmaxf(m, l[a]);
+    float C[8], wk[8], accum = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      wk[a] = (a < A) ? expf(l[a] - m) : 0.0f;
+      accum += wk[a];
+      C[a] = accum;
+    }
+    const uint32_t x0 = draw32(wp, local, step, ST_ACTION);
+    const float u = (float)(x0 >> 8) * 0x1p-24f;
+    const float t = u * C[A - 1];
+    int as = -1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (as < 0 && a < A && t < C[a]) as = a;
+    if (as < 0) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a < A && wk[a] > 0.0f) as = a;
+    }
+
+    // ---- 4. bookkeeping, turn, move claim (lane 0) ----
+    if (d.keep_logits && (lane & 7) == 0) d.logits[(uint64_t)slot * 8 + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
+    if (lane == 0 && d.dry) d.sampled[slot] = (uint8_t)as;
+    if (lane == 0 && !d.dry) {
+      const int a = d.inject ? (int)d.act_in[slot] : as;
+      d.sampled[slot] = (uint8_t)as;
+      d.act[slot] = (uint8_t)a;
+      int tg = -1;
+      if (a == TURN_L) d.facing[slot] = (uint8_t)((f + 3) & 3);
+      else if (a == TURN_R) d.facing[slot] = (uint8_t)((f + 1) & 3);
+      else if (a == FORWARD) {
+        const uint32_t tc = neighbour(wp, (uint32_t)pos, f, +1);
+        const bool walled = wp.has_walls && d.wall[wp.cell_off + tc];
+        if (d.occ[wp.cell_off + tc] == -1 && !walled) {
+          atomicMin(&d.claim[wp.cell_off + tc], slot);
+          tg = (int)tc;
+        }
+      }
+      d.tgt[slot] = tg;
+    }
+  }
+}
+
+}  // namespace eco
+
+// Host-side launcher for this storage type: picks the (H, U) instantiation.
+namespace eco {
+#define ECO_CAT2(a, b) a##b
+#define ECO_CAT(a, b) ECO_CAT2(a, b)
+hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 block, size_t shmem,
+                                                  hipStream_t s, const Dev& d, const Layout& L) {
+#define ECO_CASE(HH, UU)                                                                          \
+  if (H == HH && U == UU) {                                                                       \
+    hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU>), grid, block, shmem, s, d, L);            \
+    return hipGetLastError();                                                                     \
+  }
+  ECO_CASE(32, 4) ECO_CASE(32, 8) ECO_CASE(32, 16)
+  ECO_CASE(64, 4) ECO_CASE(64, 8) ECO_CASE(64, 16)
+  ECO_CASE(128, 4) ECO_CASE(128, 8) ECO_CASE(128, 16)
+#undef ECO_CASE
+  return hipErrorInvalidValue;
+}
+}  // namespace eco

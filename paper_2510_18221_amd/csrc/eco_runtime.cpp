@@ -1,0 +1,1063 @@
+// eco_runtime.cpp -- host side of libeco: the C ABI of include/eco.h.
+//
+// Owns the device buffers of one or more worlds, runs the deterministic init,
+// sequences the step kernels on the caller's stream (eagerly, or as a replayed
+// hipGraph), and implements the parity / checkpoint hooks.  Compiled by hipcc
+// as HIP host code; all step arithmetic lives in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eco_device.h"
+
+namespace eco {
+hipError_t launch_forward_w0(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
+                             const Layout& L);
+hipError_t launch_forward_w1(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
+                             const Layout& L);
+hipError_t launch_forward_w2(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
+                             const Layout& L);
+hipError_t launch_move(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part);
+hipError_t launch_birth_claim(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part,
+                              uint32_t A);
+hipError_t launch_birth_scan(hipStream_t s, const Dev& d);
+hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
+hipError_t launch_regrow(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part);
+hipError_t launch_compact(hipStream_t s, const Dev& d, const uint32_t* part_slot, const uint32_t* part_cell,
+                          const uint32_t* tile_rng, int init, int only_world);
+hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
+hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
+hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
+hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
+hipError_t launch_emit_list(hipStream_t s, const Dev& d, const Layout& L, const uint32_t* list, uint32_t n, int mode,
+                            double std1, double std2, double std3, uint32_t blocks);
+hipError_t sort_keys_temp_bytes(uint32_t n, size_t* bytes);
+hipError_t sort_keys(void* tmp, size_t bytes, const unsigned long long* in, unsigned long long* out, uint32_t n,
+                     hipStream_t s);
+}  // namespace eco
+
+using namespace eco;
+
+namespace {
+
+constexpr uint32_t kSlotTileH = 256;
+constexpr uint32_t kCellTileH = 4096;
+constexpr uint32_t kSlotPartH = 16;
+constexpr uint32_t kCellPartH = 2;
+constexpr uint32_t kMaxWorldsH = 1024;
+enum { EMIT_INIT = 0, EMIT_MUTATE = 1, EMIT_REQUANT = 2 };
+
+thread_local std::string g_err;
+
+eco_status fail(eco_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+uint64_t bern_threshold(float p) {
+  double t = std::floor((double)p * 4294967296.0);
+  if (t < 0) t = 0;
+  if (t > 4294967296.0) t = 4294967296.0;
+  return (uint64_t)t;
+}
+
+}  // namespace
+
+struct eco_world {
+  uint32_t n_worlds = 0;
+  std::vector<eco_world_desc> descs;
+  std::vector<WorldParams> wp;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool has_alloc = false;
+  eco_allocator alloc{};
+  std::vector<std::pair<void*, size_t>> allocations;
+  Dev d{};
+  Layout L{};
+  double std1 = 0, std2 = 0, std3 = 0;
+  uint32_t total_slots = 0, total_cells = 0;
+  std::vector<Tile> slot_tiles_h, cell_tiles_h;
+  std::vector<uint32_t> tile_rng_h;
+  Tile* slot_tiles = nullptr;
+  Tile* cell_tiles = nullptr;
+  uint32_t n_slot_tiles = 0, n_cell_tiles = 0;
+  uint32_t* part_slot = nullptr;
+  uint32_t* part_cell = nullptr;
+  uint32_t* tile_rng = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  uint32_t* emit_list = nullptr;
+  int n_cus = 256;
+  eco_launch launch{4, 4, 8, 0};
+  uint32_t rt_flags = ECO_RT_USE_GRAPH;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool broken = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_used = 0;
+  eco_kernel_times kt{};
+  uint64_t device_bytes = 0;
+};
+
+namespace {
+
+eco_status dev_fail(eco_world* w, hipError_t e, const char* what) {
+  w->broken = true;
+  return fail(ECO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(w, call, what)                       \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return dev_fail(w, e_, what); \
+  } while (0)
+
+void* dalloc(eco_world* w, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (w->has_alloc) {
+    p = w->alloc.alloc(bytes, w->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) {
+    w->allocations.push_back({p, bytes});
+    w->device_bytes += bytes;
+  }
+  return p;
+}
+
+void free_all(eco_world* w) {
+  for (auto& a : w->allocations) {
+    if (w->has_alloc) w->alloc.free(a.first, w->alloc.ctx);
+    else (void)hipFree(a.first);
+  }
+  w->allocations.clear();
+}
+
+eco_status check_desc(const eco_world_desc& d, uint32_t i) {
+  char buf[160];
+  auto bad = [&](eco_status st, const char* field, const char* why) {
+    snprintf(buf, sizeof buf, "world %u: %s %s", i, field, why);
+    return fail(st, buf);
+  };
+  if (d.struct_size != sizeof(eco_world_desc)) return bad(ECO_EINVAL, "struct_size", "!= sizeof(eco_world_desc)");
+  if (d.width < 1 || d.height < 1) return bad(ECO_EINVAL, "width/height", "must be >= 1");
+  if ((uint64_t)d.width * d.height >= (1ull << 31)) return bad(ECO_EINVAL, "width*height", "must be < 2^31");
+  if (d.capacity < 1) return bad(ECO_EINVAL, "capacity", "must be >= 1");
+  if (d.n_agents_init > d.capacity) return bad(ECO_EINVAL, "n_agents_init", "exceeds capacity");
+  if ((uint64_t)d.n_agents_init > (uint64_t)d.width * d.height) return bad(ECO_EINVAL, "n_agents_init", "exceeds cells");
+  if (d.window < 1 || d.window % 2 == 0) return bad(ECO_EINVAL, "window", "must be odd");
+  if (d.window > d.width || d.window > d.height) return bad(ECO_EINVAL, "window", "larger than the grid");
+  if (d.n_scalars != 4 && d.n_scalars != 8) return bad(ECO_EINVAL, "n_scalars", "must be 4 or 8");
+  if (d.n_actions != 5 && d.n_actions != 7) return bad(ECO_EINVAL, "n_actions", "must be 5 or 7");
+  if (d.e_repro <= 0) return bad(ECO_EINVAL, "e_repro", "must be > 0");
+  if (d.wdtype > ECO_W_FP8E4M3) return bad(ECO_EINVAL, "wdtype", "unknown");
+  if (!(d.resource_density >= 0.0f && d.resource_density <= 1.0f)) return bad(ECO_EINVAL, "resource_density", "outside [0,1]");
+  if (!(d.regrow_prob >= 0.0f && d.regrow_prob <= 1.0f)) return bad(ECO_EINVAL, "regrow_prob", "outside [0,1]");
+  if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
+  if (d.attack_enabled) return bad(ECO_ENOTSUP, "attack_enabled", "is not supported");
+  auto okh = [](uint32_t h) { return h == 32 || h == 64 || h == 128; };
+  if (!okh(d.hidden1) || !okh(d.hidden2)) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be 32, 64 or 128");
+  if (d.hidden1 != d.hidden2) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be equal");
+  return ECO_OK;
+}
+
+// Device layout of one agent's parameters (see eco_device.h).
+void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, double& s3) {
+  L = Layout{};
+  L.S = d.window;
+  L.R = (d.window - 1) / 2;
+  L.ns = d.n_scalars;
+  L.D = 4 * d.window * d.window + d.n_scalars;
+  L.H1 = d.hidden1;
+  L.H2 = d.hidden2;
+  L.A = d.n_actions;
+  L.wdtype = d.wdtype;
+  L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A;
+  L.p_w1 = 0;
+  L.p_b1 = L.p_w1 + L.H1 * L.D;
+  L.p_w2 = L.p_b1 + L.H1;
+  L.p_b2 = L.p_w2 + L.H2 * L.H1;
+  L.p_w3 = L.p_b2 + L.H2;
+  L.p_b3 = L.p_w3 + L.A * L.H2;
+  L.KB1 = L.D / 4;
+  L.u_w1 = 0;
+  L.u_b1 = L.KB1 * L.H1;
+  L.u_w2 = L.u_b1 + L.H1 / 4;
+  L.u_b2 = L.u_w2 + (L.H1 / 4) * L.H2;
+  L.u_w3 = L.u_b2 + L.H2 / 4;
+  L.u_b3 = L.u_w3 + 8 * (L.H2 / 4);
+  L.u_end = L.u_b3 + 2;
+  const uint32_t vpl = d.wdtype == ECO_W_FP32 ? 4 : (d.wdtype == ECO_W_BF16 ? 8 : 16);
+  L.KBv = (L.D + vpl - 1) / vpl;
+  L.Dpad = L.KBv * vpl;
+  uint64_t o = 0;
+  auto put = [&](uint32_t& field, uint64_t bytes) {
+    field = (uint32_t)o;
+    o = round_up(o + bytes, 16);
+  };
+  if (d.wdtype == ECO_W_FP32) {
+    put(L.s_w1, (uint64_t)L.KBv * L.H1 * 16);
+    put(L.s_b1, 4ull * L.H1);
+    put(L.s_w2, (uint64_t)(L.H1 / 4) * L.H2 * 16);
+    put(L.s_b2, 4ull * L.H2);
+    put(L.s_w3, 4ull * 8 * L.H2);
+    put(L.s_b3, 4ull * 8);
+  } else if (d.wdtype == ECO_W_BF16) {
+    put(L.s_w1, (uint64_t)L.KBv * L.H1 * 16);
+    put(L.s_b1, 2ull * L.H1);
+    put(L.s_w2, (uint64_t)(L.H1 / 8) * L.H2 * 16);
+    put(L.s_b2, 2ull * L.H2);
+    put(L.s_w3, 2ull * 8 * L.H2);
+    put(L.s_b3, 2ull * 8);
+  } else {
+    put(L.s_w1, (uint64_t)L.KBv * L.H1 * 16);
+    put(L.s_w2, (uint64_t)(L.H1 / 16) * L.H2 * 16);
+    put(L.s_w3, 1ull * 8 * L.H2);
+    put(L.s_b1, 4ull * L.H1);
+    put(L.s_b2, 4ull * L.H2);
+    put(L.s_b3, 4ull * 8);
+    put(L.s_sc1, 4ull * L.H1);
+    put(L.s_sc2, 4ull * L.H2);
+    put(L.s_sc3, 4ull * 8);
+  }
+  L.sstride = round_up(o, 256);
+  L.mstride = (d.wdtype == ECO_W_FP32) ? L.sstride : round_up(16ull * L.u_end, 256);
+  s1 = std::sqrt(1.0 / (double)L.D);
+  s2 = std::sqrt(1.0 / (double)L.H1);
+  s3 = std::sqrt(1.0 / (double)L.H2);
+}
+
+// Bytes one forward pass of one agent reads from its weight block (algorithmic).
+uint64_t weight_bytes(const Layout& L) {
+  const uint64_t nw = (uint64_t)L.H1 * L.D + (uint64_t)L.H2 * L.H1 + (uint64_t)L.A * L.H2;
+  const uint64_t nb = (uint64_t)L.H1 + L.H2 + L.A;
+  if (L.wdtype == ECO_W_FP32) return 4 * (nw + nb);
+  if (L.wdtype == ECO_W_BF16) return 2 * (nw + nb);
+  return nw + 4 * nb + 4 * nb;  // FP8 weights, FP32 biases and row scales
+}
+
+void upload_world_params(eco_world* w) {
+  for (uint32_t i = 0; i < w->n_worlds; ++i) {
+    w->wp[i].key0 = (uint32_t)(w->descs[i].seed & 0xFFFFFFFFu);
+    w->wp[i].key1 = (uint32_t)(w->descs[i].seed >> 32);
+  }
+}
+
+eco_status sync(eco_world* w) {
+  HIPCHK(w, hipStreamSynchronize(w->stream), "hipStreamSynchronize");
+  return ECO_OK;
+}
+
+uint32_t emit_blocks(eco_world* w) { return (uint32_t)std::max(1, w->n_cus * 4); }
+
+// Full deterministic init of every world.
+eco_status run_init(eco_world* w) {
+  hipStream_t s = w->stream;
+  Dev& d = w->d;
+  HIPCHK(w, hipMemcpyAsync((void*)d.wp, w->wp.data(), sizeof(WorldParams) * w->n_worlds, hipMemcpyHostToDevice, s),
+         "upload world params");
+  std::vector<WorldVar> wv(w->n_worlds);
+  for (uint32_t i = 0; i < w->n_worlds; ++i) {
+    wv[i] = WorldVar{};
+    wv[i].uid_next = w->descs[i].n_agents_init;
+  }
+  HIPCHK(w, hipMemcpyAsync(d.wv, wv.data(), sizeof(WorldVar) * w->n_worlds, hipMemcpyHostToDevice, s), "upload vars");
+  HIPCHK(w, hipMemsetAsync(d.flags, 0, w->total_slots, s), "clear flags");
+  HIPCHK(w, hipMemsetAsync(d.ring, 0, sizeof(eco_stats) * kStatsRing * w->n_worlds, s), "clear stats");
+  HIPCHK(w, launch_init_cells(s, d, w->cell_tiles, w->n_cell_tiles), "init cells");
+  for (uint32_t i = 0; i < w->n_worlds; ++i) {
+    const WorldParams& p = w->wp[i];
+    HIPCHK(w, sort_keys(w->sort_tmp, w->sort_tmp_bytes, d.cellkeys + p.cell_off, d.sorted + p.cell_off, p.cells, s),
+           "placement sort");
+  }
+  HIPCHK(w, launch_init_agents(s, d, w->slot_tiles, w->n_slot_tiles), "init agents");
+  std::vector<uint32_t> list;
+  for (uint32_t i = 0; i < w->n_worlds; ++i)
+    for (uint32_t j = 0; j < w->descs[i].n_agents_init; ++j) {
+      list.push_back(i);
+      list.push_back(j);
+    }
+  const uint32_t n = (uint32_t)(list.size() / 2);
+  if (n) {
+    HIPCHK(w, hipMemcpyAsync(w->emit_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, s), "upload list");
+    HIPCHK(w, launch_emit_list(s, d, w->L, w->emit_list, n, EMIT_INIT, w->std1, w->std2, w->std3, emit_blocks(w)),
+           "init weights");
+  }
+  HIPCHK(w, launch_compact(s, d, w->part_slot, w->part_cell, w->tile_rng, 1, -1), "compact");
+  HIPCHK(w, launch_resource_total(s, d, -1), "resource total");
+  eco_status st = sync(w);
+  if (st != ECO_OK) return st;
+  w->broken = false;
+  return ECO_OK;
+}
+
+size_t forward_shmem(const eco_world* w, uint32_t wpb) {
+  const uint32_t woff_words = (w->n_worlds + 1 + 3) & ~3u;
+  return 4ull * (woff_words + (uint64_t)wpb * (w->L.Dpad + 256));
+}
+
+hipError_t launch_forward(eco_world* w, hipStream_t s, const Dev& d, const eco_launch& lc) {
+  const dim3 grid((unsigned)std::max(1u, lc.blocks_per_cu * (uint32_t)w->n_cus));
+  const dim3 block(64 * lc.waves_per_block);
+  const size_t shmem = forward_shmem(w, lc.waves_per_block);
+  if (w->L.wdtype == 0) return launch_forward_w0((int)w->L.H1, (int)lc.unroll, grid, block, shmem, s, d, w->L);
+  if (w->L.wdtype == 1) return launch_forward_w1((int)w->L.H1, (int)lc.unroll, grid, block, shmem, s, d, w->L);
+  return launch_forward_w2((int)w->L.H1, (int)lc.unroll, grid, block, shmem, s, d, w->L);
+}
+
+hipEvent_t take_event(eco_world* w) {
+  if (w->ev_used == w->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    w->ev_pool.push_back(e);
+  }
+  return w->ev_pool[w->ev_used++];
+}
+
+// Enqueue one step's kernels.  timed: bracket each kernel with events.
+eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
+  auto run = [&](int k, auto&& fn) -> hipError_t {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed) {
+      a = take_event(w);
+      b = take_event(w);
+      if (!a || !b) return hipErrorOutOfMemory;
+      hipError_t e = hipEventRecord(a, s);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = fn();
+    if (e != hipSuccess) return e;
+    if (timed) {
+      e = hipEventRecord(b, s);
+      if (e != hipSuccess) return e;
+      w->ev_pending.push_back({k, {a, b}});
+    }
+    return hipSuccess;
+  };
+  if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
+  HIPCHK(w, run(ECO_K_FORWARD, [&] { return launch_forward(w, s, d, w->launch); }), "forward kernel");
+  HIPCHK(w, run(ECO_K_MOVE, [&] { return launch_move(s, d, w->slot_tiles, w->n_slot_tiles, w->part_slot); }),
+         "move kernel");
+  HIPCHK(w, run(ECO_K_BIRTH_CLAIM, [&] {
+           return launch_birth_claim(s, d, w->slot_tiles, w->n_slot_tiles, w->part_slot, w->L.A);
+         }), "birth claim kernel");
+  HIPCHK(w, run(ECO_K_BIRTH_SCAN, [&] { return launch_birth_scan(s, d); }), "birth scan kernel");
+  HIPCHK(w, run(ECO_K_BIRTH_COMMIT, [&] { return launch_birth_commit(s, d, w->L, emit_blocks(w)); }),
+         "birth commit kernel");
+  HIPCHK(w, run(ECO_K_REGROW, [&] { return launch_regrow(s, d, w->cell_tiles, w->n_cell_tiles, w->part_cell); }),
+         "regrow kernel");
+  HIPCHK(w, run(ECO_K_COMPACT, [&] {
+           return launch_compact(s, d, w->part_slot, w->part_cell, w->tile_rng, 0, -1);
+         }), "compact kernel");
+  return ECO_OK;
+}
+
+eco_status drain_events(eco_world* w) {
+  if (w->ev_pending.empty()) return ECO_OK;
+  HIPCHK(w, hipStreamSynchronize(w->stream), "hipStreamSynchronize");
+  for (auto& p : w->ev_pending) {
+    float ms = 0.0f;
+    HIPCHK(w, hipEventElapsedTime(&ms, p.second.first, p.second.second), "hipEventElapsedTime");
+    w->kt.ms[p.first] += ms;
+    w->kt.launches[p.first] += 1;
+  }
+  w->ev_pending.clear();
+  w->ev_used = 0;
+  return ECO_OK;
+}
+
+void drop_graph(eco_world* w) {
+  if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
+  if (w->graph) (void)hipGraphDestroy(w->graph);
+  w->gexec = nullptr;
+  w->graph = nullptr;
+}
+
+eco_status build_graph(eco_world* w) {
+  drop_graph(w);
+  Dev d = w->d;
+  d.inject = 0;
+  d.dry = 0;
+  d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  HIPCHK(w, hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  eco_status st = enqueue_step(w, w->cap_stream, d, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(w->cap_stream, &g);
+  if (st != ECO_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(w, e, "end capture");
+  w->graph = g;
+  HIPCHK(w, hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+  return ECO_OK;
+}
+
+eco_status check_world(const eco_world* w) {
+  if (!w) return fail(ECO_EINVAL, "null world");
+  if (w->broken) return fail(ECO_ESTATE, "world is in error state; call eco_world_reset");
+  return ECO_OK;
+}
+
+// Host copy of the layout's unit mapping (read/write of weights in logical order).
+struct HostUnit {
+  uint32_t p, nvalid, row, kb;
+  int layer;
+};
+HostUnit host_unit(const Layout& L, uint32_t u) {
+  HostUnit r{};
+  if (u < L.u_b1) { r.layer = 0; r.kb = u / L.H1; r.row = u % L.H1; r.p = L.p_w1 + r.row * L.D + 4 * r.kb; r.nvalid = 4; }
+  else if (u < L.u_w2) { r.layer = 3; r.row = 4 * (u - L.u_b1); r.p = L.p_b1 + r.row; r.nvalid = 4; }
+  else if (u < L.u_b2) { uint32_t e = u - L.u_w2; r.layer = 1; r.kb = e / L.H2; r.row = e % L.H2; r.p = L.p_w2 + r.row * L.H1 + 4 * r.kb; r.nvalid = 4; }
+  else if (u < L.u_w3) { r.layer = 4; r.row = 4 * (u - L.u_b2); r.p = L.p_b2 + r.row; r.nvalid = 4; }
+  else if (u < L.u_b3) { uint32_t e = u - L.u_w3, per = L.H2 / 4; r.layer = 2; r.row = e / per; r.kb = e % per; r.p = L.p_w3 + r.row * L.H2 + 4 * r.kb; r.nvalid = r.row < L.A ? 4 : 0; }
+  else { uint32_t e = u - L.u_b3; r.layer = 5; r.row = 4 * e; r.p = L.p_b3 + r.row; r.nvalid = r.row < L.A ? std::min(4u, L.A - r.row) : 0; }
+  return r;
+}
+
+double host_fp8(uint8_t q) {
+  const int e = (q >> 3) & 15, m = q & 7;
+  double v = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
+  return (q & 0x80) ? -v : v;
+}
+
+double host_bf16(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* eco_last_error(void) { return g_err.c_str(); }
+
+eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void* hip_stream,
+                            const eco_allocator* alloc, eco_world** out) {
+  if (!out) return fail(ECO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || n_worlds == 0) return fail(ECO_EINVAL, "no worlds");
+  if (n_worlds > kMaxWorldsH) return fail(ECO_EINVAL, "n_worlds exceeds 1024");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(ECO_EINVAL, "allocator needs alloc and free");
+  for (uint32_t i = 0; i < n_worlds; ++i) {
+    eco_status st = check_desc(descs[i], i);
+    if (st != ECO_OK) return st;
+    const eco_world_desc& a = descs[0];
+    const eco_world_desc& b = descs[i];
+    if (a.window != b.window || a.n_scalars != b.n_scalars || a.hidden1 != b.hidden1 || a.hidden2 != b.hidden2 ||
+        a.n_actions != b.n_actions || a.wdtype != b.wdtype)
+      return fail(ECO_EINVAL, "all worlds of one object need the same window, n_scalars, hidden sizes, "
+                              "n_actions and wdtype");
+  }
+  eco_world* w = new eco_world();
+  w->n_worlds = n_worlds;
+  w->descs.assign(descs, descs + n_worlds);
+  w->stream = (hipStream_t)hip_stream;
+  if (alloc) {
+    w->has_alloc = true;
+    w->alloc = *alloc;
+  }
+  make_layout(descs[0], w->L, w->std1, w->std2, w->std3);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&w->n_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete w;
+    return fail(ECO_EDEVICE, "no HIP device");
+  }
+  // world tables: slot and cell ranges aligned to 64
+  uint64_t so = 0, co = 0;
+  w->wp.resize(n_worlds);
+  uint32_t max_cells = 0;
+  for (uint32_t i = 0; i < n_worlds; ++i) {
+    const eco_world_desc& d = descs[i];
+    WorldParams& p = w->wp[i];
+    p = WorldParams{};
+    p.W = d.width;
+    p.H = d.height;
+    p.cells = d.width * d.height;
+    p.cap = d.capacity;
+    p.slot_off = (uint32_t)so;
+    p.cell_off = (uint32_t)co;
+    p.regrow_thr = bern_threshold(d.regrow_prob);
+    p.density_thr = bern_threshold(d.resource_density);
+    p.e_init = d.e_init;
+    p.e_cost = d.e_cost;
+    p.e_eat = d.e_eat;
+    p.e_repro = d.e_repro;
+    p.e_child = d.e_child;
+    p.sigma = d.mutation_sigma;
+    p.n_init = d.n_agents_init;
+    p.has_walls = 0;
+    w->tile_rng_h.push_back(w->n_slot_tiles);
+    for (uint32_t s = 0; s < p.cap; s += kSlotTileH) {
+      w->slot_tiles_h.push_back(Tile{i, s, std::min(kSlotTileH, p.cap - s), 0});
+      ++w->n_slot_tiles;
+    }
+    w->tile_rng_h.push_back(w->n_slot_tiles);
+    w->tile_rng_h.push_back(w->n_cell_tiles);
+    for (uint32_t c = 0; c < p.cells; c += kCellTileH) {
+      w->cell_tiles_h.push_back(Tile{i, c, std::min(kCellTileH, p.cells - c), 0});
+      ++w->n_cell_tiles;
+    }
+    w->tile_rng_h.push_back(w->n_cell_tiles);
+    so = round_up(so + p.cap, 64);
+    co = round_up(co + p.cells, 64);
+    max_cells = std::max(max_cells, p.cells);
+  }
+  if (so >= (1ull << 31) || co >= (1ull << 31)) {
+    delete w;
+    return fail(ECO_EINVAL, "total slots or cells exceed 2^31");
+  }
+  w->total_slots = (uint32_t)so;
+  w->total_cells = (uint32_t)co;
+  upload_world_params(w);
+
+  // allocations
+  Dev& d = w->d;
+  const uint64_t TS = so, TC = co;
+  bool ok = true;
+  auto A = [&](size_t bytes) -> void* {
+    void* p = ok ? dalloc(w, bytes) : nullptr;
+    if (!p) ok = false;
+    return p;
+  };
+  d.wp = (const WorldParams*)A(sizeof(WorldParams) * n_worlds);
+  d.wv = (WorldVar*)A(sizeof(WorldVar) * n_worlds);
+  d.cnt = (StepCounters*)A(sizeof(StepCounters) * n_worlds);
+  d.ring = (eco_stats*)A(sizeof(eco_stats) * kStatsRing * n_worlds);
+  d.pos = (int32_t*)A(4 * TS);
+  d.energy = (int32_t*)A(4 * TS);
+  d.age = (int32_t*)A(4 * TS);
+  d.tgt = (int32_t*)A(4 * TS);
+  d.facing = (uint8_t*)A(TS);
+  d.flags = (uint8_t*)A(TS);
+  d.act = (uint8_t*)A(TS);
+  d.sampled = (uint8_t*)A(TS);
+  d.act_in = (uint8_t*)A(TS);
+  d.uid = (unsigned long long*)A(8 * TS);
+  d.puid = (unsigned long long*)A(8 * TS);
+  d.trait = (double*)A(8 * TS);
+  d.occ = (int32_t*)A(4 * TC);
+  d.claim = (uint32_t*)A(4 * TC);
+  d.res = (uint8_t*)A(TC);
+  d.wall = (uint8_t*)A(TC);
+  d.live = (int32_t*)A(4 * TS);
+  d.bparent = (int32_t*)A(4 * TS);
+  d.freel = (int32_t*)A(4 * TS);
+  d.logits = (float*)A(4 * 8 * TS);
+  d.cellkeys = (unsigned long long*)A(8 * TC);
+  d.sorted = (unsigned long long*)A(8 * TC);
+  d.store = (uint8_t*)A(w->L.sstride * TS);
+  d.master = (w->L.wdtype == ECO_W_FP32) ? d.store : (uint8_t*)A(w->L.mstride * TS);
+  w->slot_tiles = (Tile*)A(sizeof(Tile) * std::max<size_t>(1, w->slot_tiles_h.size()));
+  w->cell_tiles = (Tile*)A(sizeof(Tile) * std::max<size_t>(1, w->cell_tiles_h.size()));
+  w->part_slot = (uint32_t*)A(4ull * kSlotPartH * std::max(1u, w->n_slot_tiles));
+  w->part_cell = (uint32_t*)A(4ull * kCellPartH * std::max(1u, w->n_cell_tiles));
+  w->tile_rng = (uint32_t*)A(4ull * w->tile_rng_h.size());
+  w->emit_list = (uint32_t*)A(8 * TS);
+  if (ok && sort_keys_temp_bytes(max_cells, &w->sort_tmp_bytes) != hipSuccess) ok = false;
+  if (ok) w->sort_tmp = A(w->sort_tmp_bytes);
+  if (!ok) {
+    free_all(w);
+    delete w;
+    return fail(ECO_ENOMEM, "device allocation failed");
+  }
+  d.n_worlds = n_worlds;
+  d.total_slots = w->total_slots;
+  d.total_cells = w->total_cells;
+  d.keep_logits = 0;
+  d.inject = 0;
+  d.dry = 0;
+  hipStream_t s = w->stream;
+  eco_status st = ECO_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (st == ECO_OK && e != hipSuccess) st = dev_fail(w, e, what);
+  };
+  chk(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking), "create capture stream");
+  chk(hipMemcpyAsync(w->slot_tiles, w->slot_tiles_h.data(), sizeof(Tile) * w->slot_tiles_h.size(),
+                     hipMemcpyHostToDevice, s), "upload tiles");
+  chk(hipMemcpyAsync(w->cell_tiles, w->cell_tiles_h.data(), sizeof(Tile) * w->cell_tiles_h.size(),
+                     hipMemcpyHostToDevice, s), "upload tiles");
+  chk(hipMemcpyAsync(w->tile_rng, w->tile_rng_h.data(), 4 * w->tile_rng_h.size(), hipMemcpyHostToDevice, s),
+      "upload tile ranges");
+  chk(hipMemsetAsync(d.store, 0, w->L.sstride * TS, s), "clear weights");
+  if (d.master != d.store) chk(hipMemsetAsync(d.master, 0, w->L.mstride * TS, s), "clear master");
+  chk(hipMemsetAsync(d.trait, 0, 8 * TS, s), "clear trait");
+  chk(hipMemsetAsync(d.sampled, 0xFF, TS, s), "clear sampled");
+  chk(hipMemsetAsync(d.act_in, 0, TS, s), "clear act_in");
+  chk(hipMemsetAsync(w->part_slot, 0, 4ull * kSlotPartH * std::max(1u, w->n_slot_tiles), s), "clear partials");
+  chk(hipMemsetAsync(w->part_cell, 0, 4ull * kCellPartH * std::max(1u, w->n_cell_tiles), s), "clear partials");
+  chk(hipMemsetAsync(d.cnt, 0, sizeof(StepCounters) * n_worlds, s), "clear counters");
+  if (st == ECO_OK) st = run_init(w);
+  if (st != ECO_OK) {
+    std::string msg = g_err;
+    eco_world_destroy(w);
+    g_err = msg;
+    return st;
+  }
+  *out = w;
+  return ECO_OK;
+}
+
+void eco_world_destroy(eco_world* w) {
+  if (!w) return;
+  (void)hipStreamSynchronize(w->stream);
+  drop_graph(w);
+  for (auto e : w->ev_pool) (void)hipEventDestroy(e);
+  if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
+  free_all(w);
+  delete w;
+}
+
+eco_status eco_world_step(eco_world* w, uint32_t n_steps) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (n_steps == 0) return ECO_OK;
+  const bool timed = (w->rt_flags & ECO_RT_TIME_KERNELS) != 0;
+  const bool graph = (w->rt_flags & ECO_RT_USE_GRAPH) != 0 && !timed;
+  Dev d = w->d;
+  d.inject = 0;
+  d.dry = 0;
+  d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  if (graph) {
+    if (!w->gexec) {
+      st = build_graph(w);
+      if (st != ECO_OK) return st;
+    }
+    for (uint32_t i = 0; i < n_steps; ++i) HIPCHK(w, hipGraphLaunch(w->gexec, w->stream), "graph launch");
+    return ECO_OK;
+  }
+  for (uint32_t i = 0; i < n_steps; ++i) {
+    st = enqueue_step(w, w->stream, d, timed);
+    if (st != ECO_OK) return st;
+  }
+  if (timed) return drain_events(w);
+  return ECO_OK;
+}
+
+eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (!actions) return fail(ECO_EINVAL, "actions is NULL");
+  // validate against the live slots
+  std::vector<uint8_t> flags(w->total_slots), act(w->total_slots, 0);
+  HIPCHK(w, hipMemcpyAsync(flags.data(), w->d.flags, w->total_slots, hipMemcpyDeviceToHost, w->stream), "read flags");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  uint64_t k = 0;
+  for (uint32_t i = 0; i < w->n_worlds; ++i) {
+    const WorldParams& p = w->wp[i];
+    for (uint32_t s = 0; s < p.cap; ++s, ++k) {
+      const uint8_t a = actions[k];
+      if ((flags[p.slot_off + s] & kAlive) && a >= w->L.A) return fail(ECO_EINVAL, "action out of range for a live slot");
+      act[p.slot_off + s] = a;
+    }
+  }
+  HIPCHK(w, hipMemcpyAsync(w->d.act_in, act.data(), w->total_slots, hipMemcpyHostToDevice, w->stream), "upload actions");
+  Dev d = w->d;
+  d.inject = 1;
+  d.dry = 0;
+  d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  st = enqueue_step(w, w->stream, d, false);
+  if (st != ECO_OK) return st;
+  return sync(w);
+}
+
+eco_status eco_world_reset(eco_world* w, const uint64_t* seeds) {
+  if (!w) return fail(ECO_EINVAL, "null world");
+  (void)hipGetLastError();
+  if (seeds)
+    for (uint32_t i = 0; i < w->n_worlds; ++i) w->descs[i].seed = seeds[i];
+  upload_world_params(w);
+  hipStream_t s = w->stream;
+  Dev& d = w->d;
+  w->broken = false;
+  HIPCHK(w, hipMemsetAsync(d.store, 0, w->L.sstride * (uint64_t)w->total_slots, s), "clear weights");
+  if (d.master != d.store) HIPCHK(w, hipMemsetAsync(d.master, 0, w->L.mstride * (uint64_t)w->total_slots, s), "clear master");
+  HIPCHK(w, hipMemsetAsync(d.trait, 0, 8ull * w->total_slots, s), "clear trait");
+  return run_init(w);
+}
+
+eco_status eco_world_stats(eco_world* w, eco_stats* out, uint32_t max_worlds) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (!out) return fail(ECO_EINVAL, "out is NULL");
+  const uint32_t n = std::min(max_worlds, w->n_worlds);
+  std::vector<WorldVar> wv(w->n_worlds);
+  HIPCHK(w, hipMemcpyAsync(wv.data(), w->d.wv, sizeof(WorldVar) * w->n_worlds, hipMemcpyDeviceToHost, w->stream), "read vars");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (uint32_t i = 0; i < n; ++i)
+    HIPCHK(w, hipMemcpyAsync(out + i, w->d.ring + (uint64_t)i * kStatsRing + wv[i].step % kStatsRing, sizeof(eco_stats),
+                             hipMemcpyDeviceToHost, w->stream), "read stats");
+  return sync(w);
+}
+
+eco_status eco_world_stats_history(eco_world* w, uint32_t world, eco_stats* out, uint32_t max_records, uint32_t* n_out) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (!out || !n_out || world >= w->n_worlds) return fail(ECO_EINVAL, "bad arguments");
+  WorldVar v;
+  HIPCHK(w, hipMemcpyAsync(&v, w->d.wv + world, sizeof v, hipMemcpyDeviceToHost, w->stream), "read vars");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  const uint64_t avail = std::min<uint64_t>(v.step + 1, kStatsRing);
+  const uint32_t n = (uint32_t)std::min<uint64_t>(avail, max_records);
+  std::vector<eco_stats> ring(kStatsRing);
+  HIPCHK(w, hipMemcpyAsync(ring.data(), w->d.ring + (uint64_t)world * kStatsRing, sizeof(eco_stats) * kStatsRing,
+                           hipMemcpyDeviceToHost, w->stream), "read ring");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (uint32_t i = 0; i < n; ++i) out[i] = ring[(v.step - (n - 1) + i) % kStatsRing];
+  *n_out = n;
+  return ECO_OK;
+}
+
+eco_status eco_world_info(const eco_world* w, eco_info* out) {
+  if (!w || !out) return fail(ECO_EINVAL, "null argument");
+  eco_info i{};
+  i.n_worlds = w->n_worlds;
+  i.total_slots = w->total_slots;
+  i.total_cells = w->total_cells;
+  i.input_dim = w->L.D;
+  i.hidden1 = w->L.H1;
+  i.hidden2 = w->L.H2;
+  i.n_actions = w->L.A;
+  i.param_count = w->L.P;
+  i.weight_bytes_per_agent = weight_bytes(w->L);
+  i.storage_stride = w->L.sstride;
+  i.master_stride = (w->L.wdtype == ECO_W_FP32) ? 0 : w->L.mstride;
+  i.device_bytes = w->device_bytes;
+  i.n_cus = (uint32_t)w->n_cus;
+  i.wdtype = w->L.wdtype;
+  *out = i;
+  return ECO_OK;
+}
+
+eco_status eco_world_set_flags(eco_world* w, uint32_t flags) {
+  if (!w) return fail(ECO_EINVAL, "null world");
+  if (flags & ~(ECO_RT_KEEP_LOGITS | ECO_RT_USE_GRAPH | ECO_RT_TIME_KERNELS)) return fail(ECO_EINVAL, "unknown flag");
+  if (flags != w->rt_flags) drop_graph(w);
+  w->rt_flags = flags;
+  return ECO_OK;
+}
+
+eco_status eco_world_set_launch(eco_world* w, const eco_launch* lc) {
+  if (!w || !lc) return fail(ECO_EINVAL, "null argument");
+  const uint32_t wpb = lc->waves_per_block, u = lc->unroll;
+  if (!(wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8)) return fail(ECO_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
+  if (!(u == 4 || u == 8 || u == 16)) return fail(ECO_EINVAL, "unroll must be 4, 8 or 16");
+  if (lc->blocks_per_cu < 1 || lc->blocks_per_cu > 64) return fail(ECO_EINVAL, "blocks_per_cu must be in 1..64");
+  if (forward_shmem(w, wpb) > 64 * 1024) return fail(ECO_EINVAL, "launch needs more than 64 KiB of LDS per block");
+  w->launch = *lc;
+  w->launch.reserved = 0;
+  drop_graph(w);
+  return ECO_OK;
+}
+
+eco_status eco_world_get_launch(const eco_world* w, eco_launch* out) {
+  if (!w || !out) return fail(ECO_EINVAL, "null argument");
+  *out = w->launch;
+  return ECO_OK;
+}
+
+eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  Dev d = w->d;
+  d.dry = 1;
+  d.inject = 0;
+  d.keep_logits = 0;
+  hipEvent_t a, b;
+  HIPCHK(w, hipEventCreate(&a), "event");
+  HIPCHK(w, hipEventCreate(&b), "event");
+  eco_launch chosen = w->launch;
+  float best_ms = 1e30f;
+  const uint32_t wpbs[] = {1, 2, 4, 8}, us[] = {4, 8, 16}, bpcs[] = {1, 2, 4, 8, 16};
+  for (uint32_t wpb : wpbs)
+    for (uint32_t u : us)
+      for (uint32_t bpc : bpcs) {
+        if (wpb * bpc > 32 || wpb * bpc < 4) continue;  // 4..32 waves per CU
+        if (forward_shmem(w, wpb) > 64 * 1024 || forward_shmem(w, wpb) * bpc > 160 * 1024) continue;
+        const eco_launch lc{wpb, bpc, u, 0};
+        hipError_t e = launch_forward(w, w->stream, d, lc);  // warm-up
+        if (e != hipSuccess) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); return dev_fail(w, e, "autotune launch"); }
+        HIPCHK(w, hipEventRecord(a, w->stream), "event");
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) (void)launch_forward(w, w->stream, d, lc);
+        HIPCHK(w, hipEventRecord(b, w->stream), "event");
+        HIPCHK(w, hipEventSynchronize(b), "event sync");
+        float ms = 0;
+        HIPCHK(w, hipEventElapsedTime(&ms, a, b), "elapsed");
+        if (ms < best_ms) {
+          best_ms = ms;
+          chosen = lc;
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  w->launch = chosen;
+  drop_graph(w);
+  if (best) *best = chosen;
+  return ECO_OK;
+}
+
+eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset) {
+  if (!w) return fail(ECO_EINVAL, "null world");
+  eco_status st = drain_events(w);
+  if (st != ECO_OK) return st;
+  if (out) *out = w->kt;
+  if (reset) w->kt = eco_kernel_times{};
+  return ECO_OK;
+}
+
+size_t eco_world_state_bytes(const eco_world* w, uint32_t world) {
+  if (!w || world >= w->n_worlds) return 0;
+  const uint64_t cap = w->wp[world].cap, cells = w->wp[world].cells;
+  return 32 + cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + cells * (4 + 1 + 1);
+}
+
+eco_status eco_world_read_state(eco_world* w, uint32_t world, void* buf, size_t bytes) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !buf) return fail(ECO_EINVAL, "bad world or buffer");
+  if (bytes < eco_world_state_bytes(w, world)) return fail(ECO_EINVAL, "state buffer too small");
+  const WorldParams& p = w->wp[world];
+  const size_t cap = p.cap, cells = p.cells;
+  uint8_t* b = (uint8_t*)buf;
+  WorldVar v;
+  std::vector<uint8_t> flags(cap);
+  hipStream_t s = w->stream;
+  HIPCHK(w, hipMemcpyAsync(&v, w->d.wv + world, sizeof v, hipMemcpyDeviceToHost, s), "read vars");
+  uint8_t* q = b + 32;
+  auto cp = [&](const void* src, size_t n) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(q, src, n, hipMemcpyDeviceToHost, s);
+    q += n;
+    return e;
+  };
+  HIPCHK(w, cp(w->d.uid + p.slot_off, cap * 8), "read uid");
+  HIPCHK(w, cp(w->d.puid + p.slot_off, cap * 8), "read puid");
+  HIPCHK(w, cp(w->d.pos + p.slot_off, cap * 4), "read pos");
+  HIPCHK(w, cp(w->d.energy + p.slot_off, cap * 4), "read energy");
+  HIPCHK(w, cp(w->d.age + p.slot_off, cap * 4), "read age");
+  HIPCHK(w, cp(w->d.occ + p.cell_off, cells * 4), "read occ");
+  HIPCHK(w, cp(w->d.facing + p.slot_off, cap), "read facing");
+  uint8_t* alive = q;
+  HIPCHK(w, cp(w->d.flags + p.slot_off, cap), "read flags");
+  HIPCHK(w, cp(w->d.act + p.slot_off, cap), "read action");
+  HIPCHK(w, cp(w->d.res + p.cell_off, cells), "read res");
+  HIPCHK(w, cp(w->d.wall + p.cell_off, cells), "read wall");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (size_t i = 0; i < cap; ++i) alive[i] &= kAlive;
+  const uint32_t hdr[4] = {p.W, p.H, p.cap, 0};
+  std::memcpy(b, &v.step, 8);
+  std::memcpy(b + 8, &v.uid_next, 8);
+  std::memcpy(b + 16, hdr, 16);
+  return ECO_OK;
+}
+
+eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, size_t bytes) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !buf) return fail(ECO_EINVAL, "bad world or buffer");
+  if (bytes < eco_world_state_bytes(w, world)) return fail(ECO_EINVAL, "state buffer too small");
+  const WorldParams& p = w->wp[world];
+  const size_t cap = p.cap, cells = p.cells;
+  const uint8_t* b = (const uint8_t*)buf;
+  uint32_t hdr[4];
+  std::memcpy(hdr, b + 16, 16);
+  if (hdr[0] != p.W || hdr[1] != p.H || hdr[2] != p.cap) return fail(ECO_EINVAL, "state shape mismatch");
+  // consistency: occ and pos describe the same placement
+  const uint8_t* q = b + 32;
+  const int32_t* pos = (const int32_t*)(q + cap * 16);
+  const int32_t* occ = (const int32_t*)(q + cap * 28);
+  const uint8_t* alive_new = q + cap * 28 + cells * 4 + cap;
+  const uint8_t* facing = q + cap * 28 + cells * 4;
+  for (size_t s = 0; s < cap; ++s) {
+    if (alive_new[s] > 1) return fail(ECO_EINVAL, "alive must be 0 or 1");
+    if (!alive_new[s]) continue;
+    if (pos[s] < 0 || (uint32_t)pos[s] >= p.cells || occ[pos[s]] != (int32_t)s) return fail(ECO_EINVAL, "occ/pos mismatch");
+    if (facing[s] > 3) return fail(ECO_EINVAL, "facing must be 0..3");
+  }
+  for (size_t c = 0; c < cells; ++c) {
+    const int32_t o = occ[c];
+    if (o < -1 || o >= (int32_t)cap || (o >= 0 && (!alive_new[o] || pos[o] != (int32_t)c)))
+      return fail(ECO_EINVAL, "occ/pos mismatch");
+  }
+  const uint8_t* wall = q + cap * 28 + cells * 4 + 3 * cap + cells;
+  bool walls = false;
+  for (size_t c = 0; c < cells; ++c) walls |= wall[c] != 0;
+  std::vector<uint8_t> old(cap);
+  hipStream_t s = w->stream;
+  HIPCHK(w, hipMemcpyAsync(old.data(), w->d.flags + p.slot_off, cap, hipMemcpyDeviceToHost, s), "read flags");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  WorldVar v;
+  HIPCHK(w, hipMemcpyAsync(&v, w->d.wv + world, sizeof v, hipMemcpyDeviceToHost, s), "read vars");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  std::memcpy(&v.step, b, 8);
+  std::memcpy(&v.uid_next, b + 8, 8);
+  v.n_births = 0;
+  HIPCHK(w, hipMemcpyAsync(w->d.wv + world, &v, sizeof v, hipMemcpyHostToDevice, s), "write vars");
+  auto cp = [&](void* dst, size_t n) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst, q, n, hipMemcpyHostToDevice, s);
+    q += n;
+    return e;
+  };
+  HIPCHK(w, cp(w->d.uid + p.slot_off, cap * 8), "write uid");
+  HIPCHK(w, cp(w->d.puid + p.slot_off, cap * 8), "write puid");
+  HIPCHK(w, cp(w->d.pos + p.slot_off, cap * 4), "write pos");
+  HIPCHK(w, cp(w->d.energy + p.slot_off, cap * 4), "write energy");
+  HIPCHK(w, cp(w->d.age + p.slot_off, cap * 4), "write age");
+  HIPCHK(w, cp(w->d.occ + p.cell_off, cells * 4), "write occ");
+  HIPCHK(w, cp(w->d.facing + p.slot_off, cap), "write facing");
+  HIPCHK(w, cp(w->d.flags + p.slot_off, cap), "write alive");
+  HIPCHK(w, cp(w->d.act + p.slot_off, cap), "write action");
+  HIPCHK(w, cp(w->d.res + p.cell_off, cells), "write res");
+  HIPCHK(w, cp(w->d.wall + p.cell_off, cells), "write wall");
+  if (walls != (w->wp[world].has_walls != 0)) {
+    w->wp[world].has_walls = walls ? 1u : 0u;
+    HIPCHK(w, hipMemcpyAsync((void*)(w->d.wp + world), &w->wp[world], sizeof(WorldParams), hipMemcpyHostToDevice, s),
+           "write world params");
+  }
+  std::vector<uint32_t> list;
+  for (uint32_t sl = 0; sl < p.cap; ++sl)
+    if (alive_new[sl] && !(old[sl] & kAlive)) {
+      list.push_back(world);
+      list.push_back(sl);
+    }
+  if (!list.empty()) {
+    HIPCHK(w, hipMemcpyAsync(w->emit_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, s), "upload list");
+    HIPCHK(w, launch_emit_list(s, w->d, w->L, w->emit_list, (uint32_t)(list.size() / 2), EMIT_INIT, w->std1, w->std2,
+                               w->std3, emit_blocks(w)), "init weights");
+  }
+  HIPCHK(w, launch_compact(s, w->d, w->part_slot, w->part_cell, w->tile_rng, 1, (int)world), "compact");
+  HIPCHK(w, launch_resource_total(s, w->d, (int)world), "resource total");
+  return sync(w);
+}
+
+eco_status eco_world_read_logits(eco_world* w, uint32_t world, float* out, size_t n_floats) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !out) return fail(ECO_EINVAL, "bad world or buffer");
+  const WorldParams& p = w->wp[world];
+  if (n_floats < (size_t)p.cap * w->L.A) return fail(ECO_EINVAL, "logits buffer too small");
+  std::vector<float> tmp((size_t)p.cap * 8);
+  HIPCHK(w, hipMemcpyAsync(tmp.data(), w->d.logits + (uint64_t)p.slot_off * 8, tmp.size() * 4, hipMemcpyDeviceToHost,
+                           w->stream), "read logits");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (size_t s = 0; s < p.cap; ++s)
+    for (uint32_t a = 0; a < w->L.A; ++a) out[s * w->L.A + a] = tmp[s * 8 + a];
+  return ECO_OK;
+}
+
+eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, size_t n) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !out) return fail(ECO_EINVAL, "bad world or buffer");
+  const WorldParams& p = w->wp[world];
+  if (n < p.cap) return fail(ECO_EINVAL, "buffer too small");
+  HIPCHK(w, hipMemcpyAsync(out, w->d.sampled + p.slot_off, p.cap, hipMemcpyDeviceToHost, w->stream), "read sampled");
+  return sync(w);
+}
+
+eco_status eco_world_read_weights(eco_world* w, uint32_t world, uint32_t slot, int which, double* out, size_t n) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !out) return fail(ECO_EINVAL, "bad world or buffer");
+  const WorldParams& p = w->wp[world];
+  const Layout& L = w->L;
+  if (slot >= p.cap) return fail(ECO_EINVAL, "slot out of range");
+  if (n < L.P) return fail(ECO_EINVAL, "buffer too small");
+  const uint64_t g = (uint64_t)p.slot_off + slot;
+  const bool master = which == 1 || L.wdtype == ECO_W_FP32;
+  std::vector<uint8_t> blk(master ? L.mstride : L.sstride);
+  HIPCHK(w, hipMemcpyAsync(blk.data(), (master ? w->d.master + g * L.mstride : w->d.store + g * L.sstride), blk.size(),
+                           hipMemcpyDeviceToHost, w->stream), "read weights");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (uint32_t u = 0; u < L.u_end; ++u) {
+    const HostUnit hu = host_unit(L, u);
+    for (uint32_t i = 0; i < hu.nvalid; ++i) {
+      double v;
+      if (master) {
+        float f;
+        std::memcpy(&f, blk.data() + 16ull * u + 4 * i, 4);
+        v = f;
+      } else if (L.wdtype == ECO_W_BF16) {
+        uint64_t off;
+        if (hu.layer == 0) off = L.s_w1 + ((uint64_t)(hu.kb >> 1) * L.H1 + hu.row) * 16 + (hu.kb & 1) * 8;
+        else if (hu.layer == 1) off = L.s_w2 + ((uint64_t)(hu.kb >> 1) * L.H2 + hu.row) * 16 + (hu.kb & 1) * 8;
+        else if (hu.layer == 2) off = L.s_w3 + ((uint64_t)hu.row * L.H2 + 4 * hu.kb) * 2;
+        else if (hu.layer == 3) off = L.s_b1 + (uint64_t)hu.row * 2;
+        else if (hu.layer == 4) off = L.s_b2 + (uint64_t)hu.row * 2;
+        else off = L.s_b3 + (uint64_t)hu.row * 2;
+        uint16_t h;
+        std::memcpy(&h, blk.data() + off + 2 * i, 2);
+        v = host_bf16(h);
+      } else {
+        if (hu.layer >= 3) {
+          const uint64_t off = (hu.layer == 3 ? L.s_b1 : (hu.layer == 4 ? L.s_b2 : L.s_b3)) + (uint64_t)hu.row * 4;
+          float f;
+          std::memcpy(&f, blk.data() + off + 4 * i, 4);
+          v = f;
+        } else {
+          uint64_t off, soff;
+          if (hu.layer == 0) { off = L.s_w1 + ((uint64_t)(hu.kb >> 2) * L.H1 + hu.row) * 16 + (hu.kb & 3) * 4; soff = L.s_sc1 + 4ull * hu.row; }
+          else if (hu.layer == 1) { off = L.s_w2 + ((uint64_t)(hu.kb >> 2) * L.H2 + hu.row) * 16 + (hu.kb & 3) * 4; soff = L.s_sc2 + 4ull * hu.row; }
+          else { off = L.s_w3 + (uint64_t)hu.row * L.H2 + 4 * hu.kb; soff = L.s_sc3 + 4ull * hu.row; }
+          float sc;
+          std::memcpy(&sc, blk.data() + soff, 4);
+          v = host_fp8(blk[off + i]) * (double)sc;
+        }
+      }
+      out[hu.p + i] = v;
+    }
+  }
+  return ECO_OK;
+}
+
+eco_status eco_world_write_weights(eco_world* w, uint32_t world, uint32_t slot, const float* master, size_t n) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !master) return fail(ECO_EINVAL, "bad world or buffer");
+  const WorldParams& p = w->wp[world];
+  const Layout& L = w->L;
+  if (slot >= p.cap) return fail(ECO_EINVAL, "slot out of range");
+  if (n < L.P) return fail(ECO_EINVAL, "buffer too small");
+  std::vector<float> blk(L.mstride / 4, 0.0f);
+  for (uint32_t u = 0; u < L.u_end; ++u) {
+    const HostUnit hu = host_unit(L, u);
+    for (uint32_t i = 0; i < hu.nvalid; ++i) blk[4ull * u + i] = master[hu.p + i];
+  }
+  const uint64_t g = (uint64_t)p.slot_off + slot;
+  hipStream_t s = w->stream;
+  HIPCHK(w, hipMemcpyAsync(w->d.master + g * L.mstride, blk.data(), 16ull * L.u_end, hipMemcpyHostToDevice, s),
+         "write master");
+  const uint32_t list[2] = {world, slot};
+  HIPCHK(w, hipMemcpyAsync(w->emit_list, list, 8, hipMemcpyHostToDevice, s), "upload list");
+  HIPCHK(w, launch_emit_list(s, w->d, L, w->emit_list, 1, EMIT_REQUANT, 0, 0, 0, 1), "requantise");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  return ECO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,734 @@
+// eco_step.hip -- world-dynamics kernels of one step, and the init kernels.
+//
+// Step order (the policy kernel in eco_forward.hip runs first and has already
+// applied turns and made the forward-move claims on the pre-step occupancy):
+//   k_move         winners move; EAT; step cost; death at energy <= 0; age
+//                  (Sec. 3.2 "Resources and Agent Health", "Actions")
+//   k_birth_claim  eligible parents claim the empty cell behind them
+//                  (Sec. 3.2 "Actions": child placed directly behind the parent)
+//   k_birth_scan   per world: winners ranked in slot order, free slots listed in
+//                  ascending order (the recycled-slot free list)
+//   k_birth_commit child state + child weights = parent + sigma * N(0,1)
+//                  (Sec. 3.3 mutation) into the recycled slot
+//   k_regrow       each empty cell regrows one unit with probability p
+//                  (Sec. 3.2: energy slowly grows back)
+//   k_compact      per world: live list of the next step and the step's
+//                  statistics (App. E measurement interface)
+// Every contended write is an atomicMin on a claim word; every other write goes
+// to a unique slot or cell, so the integer state is independent of scheduling.
+#include "eco_device.h"
+
+namespace eco {
+
+constexpr int kSlotTile = 256;   // slots per block in per-slot kernels
+constexpr int kCellTile = 4096;  // cells per block in per-cell kernels
+constexpr int kScanThreads = 1024;
+constexpr int kSlotPart = 16;    // u32 counters per slot tile
+constexpr int kCellPart = 2;     // u32 counters per cell tile
+
+// Per-slot-tile counters (index in the partials row).
+enum { PC_HIST = 0, PC_MOVES_OK = 8, PC_MOVES_BLOCKED = 9, PC_EATEN = 10, PC_DEATHS = 11, PC_BB_CELL = 12 };
+
+// ---------------------------------------------------------------------------
+// Small block helpers
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// Deterministic FP64 block sum: fixed butterfly per wave, then waves in order.
+template <int NT>
+__device__ __forceinline__ double block_sum_f64(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// Exclusive scan of one u32 per thread over the block; returns the exclusive
+// prefix, *total gets the block total (all threads).
+template <int NT>
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* red, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) red[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < NT / 64; ++i) {
+      const uint32_t t = red[i];
+      red[i] = run;
+      run += t;
+    }
+    red[NT / 64] = run;
+  }
+  __syncthreads();
+  const uint32_t ex = red[wave] + inc - v;
+  *total = red[NT / 64];
+  __syncthreads();
+  return ex;
+}
+
+// ---------------------------------------------------------------------------
+// Weight emission (init, mutation, re-quantisation) for one agent, one block.
+// A "unit" is 4 consecutive logical parameters = one 16-byte FP32 master block.
+// ---------------------------------------------------------------------------
+struct UnitInfo {
+  uint32_t p;      // logical index of the first parameter
+  uint32_t nvalid; // parameters of the unit that exist (0..4)
+  int layer;       // 0,1,2 weights; 3,4,5 biases of layer 0,1,2
+  uint32_t row;    // output row (weights) / first row (biases)
+  uint32_t kb;     // k-block (weights of layers 0,1) or column quad (layer 2)
+};
+
+__device__ __forceinline__ UnitInfo unit_info(const Layout& L, uint32_t u) {
+  UnitInfo r;
+  if (u < L.u_b1) {                 // W1 [kb][j]
+    r.layer = 0; r.kb = u / L.H1; r.row = u % L.H1;
+    r.p = L.p_w1 + r.row * L.D + 4 * r.kb; r.nvalid = 4;
+  } else if (u < L.u_w2) {          // b1
+    r.layer = 3; r.row = 4 * (u - L.u_b1); r.kb = 0;
+    r.p = L.p_b1 + r.row; r.nvalid = 4;
+  } else if (u < L.u_b2) {          // W2 [kb][i]
+    const uint32_t e = u - L.u_w2;
+    r.layer = 1; r.kb = e / L.H2; r.row = e % L.H2;
+    r.p = L.p_w2 + r.row * L.H1 + 4 * r.kb; r.nvalid = 4;
+  } else if (u < L.u_w3) {          // b2
+    r.layer = 4; r.row = 4 * (u - L.u_b2); r.kb = 0;
+    r.p = L.p_b2 + r.row; r.nvalid = 4;
+  } else if (u < L.u_b3) {          // W3 [a][H2], 4 columns per unit
+    const uint32_t e = u - L.u_w3, per = L.H2 / 4;
+    r.layer = 2; r.row = e / per; r.kb = e % per;
+    r.p = L.p_w3 + r.row * L.H2 + 4 * r.kb; r.nvalid = (r.row < L.A) ? 4 : 0;
+  } else {                          // b3 (8 padded)
+    const uint32_t e = u - L.u_b3;
+    r.layer = 5; r.row = 4 * e; r.kb = 0;
+    r.p = L.p_b3 + r.row;
+    r.nvalid = (r.row < L.A) ? min(4u, L.A - r.row) : 0;
+  }
+  return r;
+}
+
+// Round-to-nearest-even FP32 -> BF16 of a finite value.
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// FP32 -> OCP FP8 E4M3FN, round to nearest even, saturating at 448; values
+// that round to zero give +0.  Works on the magnitude's bit pattern: the
+// E4M3 exponent range is [-6, 8], subnormal step 2^-9.
+__device__ __forceinline__ uint32_t fp8_rne_sat(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (!(a < 448.0f)) return sign | 0x7Eu;
+  uint32_t q;
+  if (a < 0x1p-6f) {
+    // subnormal range: q = RNE(a / 2^-9) in 0..8 (8 = smallest normal, code 0x08)
+    const float t = a * 512.0f;        // exact (power-of-two scale)
+    q = (uint32_t)__builtin_rintf(t);  // round half to even
+  } else {
+    const uint32_t u = __float_as_uint(a);
+    const int e = (int)(u >> 23) - 127;               // -6 .. 8
+    const uint32_t mant = u & 0x7FFFFFu;
+    uint32_t m3 = mant >> 20;                         // top 3 mantissa bits
+    const uint32_t rest = mant & 0xFFFFFu;            // 20 dropped bits
+    const uint32_t half = 0x80000u;
+    if (rest > half || (rest == half && (m3 & 1u))) ++m3;
+    uint32_t ee = (uint32_t)(e + 7);
+    if (m3 == 8) { m3 = 0; ++ee; }
+    q = (ee << 3) | m3;
+    if (q > 0x7Eu) q = 0x7Eu;
+  }
+  if (q == 0) return 0u;
+  return sign | q;
+}
+
+__device__ __forceinline__ float fp8_value(uint32_t q) {
+  const uint32_t e = (q >> 3) & 15u, m = q & 7u;
+  float v = (e == 0) ? (float)m * 0x1p-9f : ldexpf(1.0f + (float)m * 0.125f, (int)e - 7);
+  return (q & 0x80u) ? -v : v;
+}
+
+enum EmitMode { EMIT_INIT = 0, EMIT_MUTATE = 1, EMIT_REQUANT = 2 };
+
+// Writes the FP32 master of global slot `child` and its storage copy, and the
+// trait |theta|^2.  INIT: N(0, 1/fan_in) weights from (rng_slot, step 0,
+// WINIT), zero biases.  MUTATE: parent master + sigma z, z from (rng_slot =
+// parent local slot, step, MUTATE).  REQUANT: master already written.
+template <int WDT>
+__device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp, uint32_t child, int mode,
+                           uint32_t parent, uint32_t rng_slot, uint32_t step, double std1, double std2,
+                           double std3, uint32_t* s_amax, double* s_red) {
+  const int tid = threadIdx.x;
+  float* mc = reinterpret_cast<float*>(d.master + (uint64_t)child * L.mstride);
+  const float* mp = reinterpret_cast<const float*>(d.master + (uint64_t)parent * L.mstride);
+  uint8_t* sc = d.store + (uint64_t)child * L.sstride;
+  const uint32_t nrows = L.H1 + L.H2 + 8;
+  if (WDT == 2) {
+    for (uint32_t i = tid; i < nrows; i += blockDim.x) s_amax[i] = 0u;
+    __syncthreads();
+  }
+  const double sigma = (double)wp.sigma;
+  double tsum = 0.0;
+  for (uint32_t u = tid; u < L.u_end; u += blockDim.x) {
+    const UnitInfo ui = unit_info(L, u);
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (mode == EMIT_REQUANT) {
+      const float4 m4 = reinterpret_cast<const float4*>(mc)[u];
+      v[0] = m4.x; v[1] = m4.y; v[2] = m4.z; v[3] = m4.w;
+    } else if (ui.nvalid > 0) {
+      double z[4];
+      if (mode == EMIT_INIT) {
+        if (ui.layer < 3) {
+          gauss4(wp, rng_slot, 0u, ST_WINIT, ui.p >> 2, z);
+          const double sd = ui.layer == 0 ? std1 : (ui.layer == 1 ? std2 : std3);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (float)(z[i] * sd);
+        }
+      } else {
+        const float4 p4 = reinterpret_cast<const float4*>(mp)[u];
+        const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+        gauss4(wp, rng_slot, step, ST_MUTATE, ui.p >> 2, z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          v[i] = (i < (int)ui.nvalid) ? (float)__builtin_fma(sigma, z[i], (double)pv[i]) : 0.0f;
+      }
+    }
+    if (mode != EMIT_REQUANT) reinterpret_cast<float4*>(mc)[u] = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tsum += (double)v[i] * (double)v[i];
+
+    if (WDT == 1) {
+      const uint32_t lo = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
+      const uint32_t hi = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
+      uint64_t off;
+      if (ui.layer == 0) off = L.s_w1 + ((uint64_t)(ui.kb >> 1) * L.H1 + ui.row) * 16 + (ui.kb & 1) * 8;
+      else if (ui.layer == 1) off = L.s_w2 + ((uint64_t)(ui.kb >> 1) * L.H2 + ui.row) * 16 + (ui.kb & 1) * 8;
+      else if (ui.layer == 2) off = L.s_w3 + ((uint64_t)ui.row * L.H2 + 4 * ui.kb) * 2;
+      else if (ui.layer == 3) off = L.s_b1 + (uint64_t)ui.row * 2;
+      else if (ui.layer == 4) off = L.s_b2 + (uint64_t)ui.row * 2;
+      else off = L.s_b3 + (uint64_t)ui.row * 2;
+      *reinterpret_cast<uint2*>(sc + off) = make_uint2(lo, hi);
+    } else if (WDT == 2) {
+      if (ui.layer < 3) {
+        const uint32_t r = ui.layer == 0 ? ui.row : (ui.layer == 1 ? L.H1 + ui.row : L.H1 + L.H2 + ui.row);
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
+        atomicMax(&s_amax[r], __float_as_uint(mx));
+      } else {
+        const uint64_t off = (ui.layer == 3 ? L.s_b1 : (ui.layer == 4 ? L.s_b2 : L.s_b3)) + (uint64_t)ui.row * 4;
+        *reinterpret_cast<float4*>(sc + off) = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+  }
+  if (WDT == 2) {
+    __syncthreads();
+    // scales, then a second pass over the same units (each thread re-reads its own writes)
+    for (uint32_t r = tid; r < nrows; r += blockDim.x) {
+      const float amax = __uint_as_float(s_amax[r]);
+      const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+      uint64_t off;
+      if (r < L.H1) off = L.s_sc1 + (uint64_t)r * 4;
+      else if (r < L.H1 + L.H2) off = L.s_sc2 + (uint64_t)(r - L.H1) * 4;
+      else off = L.s_sc3 + (uint64_t)(r - L.H1 - L.H2) * 4;
+      *reinterpret_cast<float*>(sc + off) = scale;
+    }
+    for (uint32_t u = tid; u < L.u_end; u += blockDim.x) {
+      const UnitInfo ui = unit_info(L, u);
+      if (ui.layer >= 3) continue;
+      const uint32_t r = ui.layer == 0 ? ui.row : (ui.layer == 1 ? L.H1 + ui.row : L.H1 + L.H2 + ui.row);
+      const float amax = __uint_as_float(s_amax[r]);
+      const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+      const float4 m4 = reinterpret_cast<const float4*>(mc)[u];
+      const uint32_t q = fp8_rne_sat(m4.x / scale) | (fp8_rne_sat(m4.y / scale) << 8) |
+                         (fp8_rne_sat(m4.z / scale) << 16) | (fp8_rne_sat(m4.w / scale) << 24);
+      uint64_t off;
+      if (ui.layer == 0) off = L.s_w1 + ((uint64_t)(ui.kb >> 2) * L.H1 + ui.row) * 16 + (ui.kb & 3) * 4;
+      else if (ui.layer == 1) off = L.s_w2 + ((uint64_t)(ui.kb >> 2) * L.H2 + ui.row) * 16 + (ui.kb & 3) * 4;
+      else off = L.s_w3 + (uint64_t)ui.row * L.H2 + 4 * ui.kb;
+      *reinterpret_cast<uint32_t*>(sc + off) = q;
+    }
+  }
+  const double t = block_sum_f64<256>(tsum, s_red);
+  if (tid == 0) d.trait[child] = t;
+}
+
+// ---------------------------------------------------------------------------
+// Step kernels
+// ---------------------------------------------------------------------------
+// Winners move, then EAT, step cost, death, age; per-tile counters.
+__global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part) {
+  __shared__ uint32_t cnt[kSlotPart];
+  if (threadIdx.x < kSlotPart) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  if (threadIdx.x < tl.count) {
+    const uint32_t local = tl.start + threadIdx.x;
+    const uint32_t slot = wp.slot_off + local;
+    if (d.flags[slot] & kAlive) {
+      const int a = d.act[slot];
+      atomicAdd(&cnt[PC_HIST + a], 1u);
+      int cell = d.pos[slot];
+      if (a == FORWARD) {
+        const int t = d.tgt[slot];
+        if (t >= 0 && d.claim[wp.cell_off + t] == slot) {
+          d.claim[wp.cell_off + t] = 0xFFFFFFFFu;
+          d.occ[wp.cell_off + cell] = -1;
+          d.occ[wp.cell_off + t] = (int)local;
+          cell = t;
+          d.pos[slot] = cell;
+          atomicAdd(&cnt[PC_MOVES_OK], 1u);
+        } else {
+          atomicAdd(&cnt[PC_MOVES_BLOCKED], 1u);
+        }
+      }
+      int E = d.energy[slot];
+      if (a == EAT && d.res[wp.cell_off + cell] > 0) {
+        d.res[wp.cell_off + cell] -= 1;
+        E += wp.e_eat;
+        atomicAdd(&cnt[PC_EATEN], 1u);
+      }
+      E -= wp.e_cost;
+      if (E <= 0) {
+        d.flags[slot] = 0;
+        d.occ[wp.cell_off + cell] = -1;
+        atomicAdd(&cnt[PC_DEATHS], 1u);
+      } else {
+        d.age[slot] += 1;
+      }
+      d.energy[slot] = E;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) part[blockIdx.x * kSlotPart + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Eligible parents claim the empty cell directly behind them.
+__global__ __launch_bounds__(kSlotTile) void k_birth_claim(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part,
+                                                           uint32_t n_actions) {
+  __shared__ uint32_t blocked;
+  if (threadIdx.x == 0) blocked = 0;
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  if (threadIdx.x < tl.count) {
+    const uint32_t local = tl.start + threadIdx.x;
+    const uint32_t slot = wp.slot_off + local;
+    const uint8_t fl = d.flags[slot];
+    if (fl & kAlive) {
+      const bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
+      if (eligible) {
+        const uint32_t t = neighbour(wp, (uint32_t)d.pos[slot], d.facing[slot], -1);
+        const bool walled = wp.has_walls && d.wall[wp.cell_off + t];
+        if (d.occ[wp.cell_off + t] == -1 && !walled) {
+          atomicMin(&d.claim[wp.cell_off + t], slot);
+          d.tgt[slot] = (int)t;
+          d.flags[slot] = fl | kBirthClaim;
+        } else {
+          atomicAdd(&blocked, 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x * kSlotPart + PC_BB_CELL] = blocked;
+}
+
+// Per world (one block): rank the claim winners in slot order and list the
+// free slots in ascending order.  Birth rank k takes free slot k.
+__global__ __launch_bounds__(kScanThreads) void k_birth_scan(Dev d) {
+  __shared__ uint32_t red[kScanThreads / 64 + 1];
+  __shared__ uint32_t tot_claim;
+  const uint32_t w = blockIdx.x;
+  const WorldParams wp = d.wp[w];
+  const uint32_t per = (wp.cap + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, wp.cap);
+  if (threadIdx.x == 0) tot_claim = 0;
+  uint32_t nwin = 0, nfree = 0, nclaim = 0;
+  for (uint32_t s = lo; s < hi; ++s) {
+    uint8_t fl = d.flags[wp.slot_off + s];
+    if (fl & kBirthClaim) {
+      ++nclaim;
+      const int t = d.tgt[wp.slot_off + s];
+      if (d.claim[wp.cell_off + t] == wp.slot_off + s) {
+        fl |= kBirthWon;
+        d.flags[wp.slot_off + s] = fl;
+        ++nwin;
+      }
+    }
+    if (!(fl & kAlive)) ++nfree;
+  }
+  __syncthreads();
+  if (nclaim) atomicAdd(&tot_claim, nclaim);
+  uint32_t W, F;
+  uint32_t off_win = block_exscan<kScanThreads>(nwin, red, &W);
+  uint32_t off_free = block_exscan<kScanThreads>(nfree, red, &F);
+  for (uint32_t s = lo; s < hi; ++s) {
+    const uint8_t fl = d.flags[wp.slot_off + s];
+    if (fl & kBirthClaim) d.claim[wp.cell_off + d.tgt[wp.slot_off + s]] = 0xFFFFFFFFu;
+    if (fl & kBirthWon) d.bparent[wp.slot_off + off_win++] = (int)s;
+    if (!(fl & kAlive)) {
+      if (off_free < W) d.freel[wp.slot_off + off_free] = (int)s;
+      ++off_free;
+    }
+    if (fl & (kBirthClaim | kBirthWon)) d.flags[wp.slot_off + s] = fl & kAlive;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nb = min(W, F);
+    d.wv[w].n_births = nb;
+    d.wv[w].n_win = W;
+    d.cnt[w].births = nb;
+    d.cnt[w].births_blocked_cell = tot_claim - W;
+    d.cnt[w].births_blocked_capacity = W - nb;
+  }
+}
+
+// Prefix of per-world birth counts in LDS (same scheme as the live offsets).
+__device__ __forceinline__ void birth_offsets(const WorldVar* __restrict__ wv, uint32_t n, uint32_t* off) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const uint32_t per = (n + 63) / 64;
+    const uint32_t lo = tid * per, hi = min(lo + per, n);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i) s += wv[i].n_births;
+    uint32_t inc = s;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t v = __shfl_up(inc, dd);
+      if (tid >= dd) inc += v;
+    }
+    uint32_t run = inc - s;
+    for (uint32_t i = lo; i < hi; ++i) {
+      off[i] = run;
+      run += wv[i].n_births;
+    }
+    if (tid == 63) off[n] = inc;
+  }
+  __syncthreads();
+}
+
+constexpr int kMaxWorlds = 1024;
+
+// One block per birth (persistent over all worlds' births).
+template <int WDT>
+__global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
+  __shared__ uint32_t off[kMaxWorlds + 1];
+  __shared__ uint32_t s_amax[128 + 128 + 8];
+  __shared__ double s_red[4];
+  birth_offsets(d.wv, d.n_worlds, off);
+  const uint32_t total = off[d.n_worlds];
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const uint32_t w = find_world(off, d.n_worlds, g);
+    const WorldParams wp = d.wp[w];
+    const uint32_t k = g - off[w];
+    const uint32_t p_local = (uint32_t)d.bparent[wp.slot_off + k];
+    const uint32_t c_local = (uint32_t)d.freel[wp.slot_off + k];
+    const uint32_t pg = wp.slot_off + p_local, cg = wp.slot_off + c_local;
+    const uint32_t step = (uint32_t)d.wv[w].step;
+    if (threadIdx.x == 0) {
+      const int t = d.tgt[pg];
+      d.energy[pg] -= wp.e_child;
+      d.flags[cg] = kAlive;
+      d.pos[cg] = t;
+      d.occ[wp.cell_off + t] = (int)c_local;
+      d.facing[cg] = d.facing[pg];
+      d.energy[cg] = wp.e_child;
+      d.age[cg] = 0;
+      d.uid[cg] = d.wv[w].uid_next + k;
+      d.puid[cg] = d.uid[pg];
+    }
+    emit_agent<WDT>(d, L, wp, cg, EMIT_MUTATE, pg, p_local, step, 0.0, 0.0, 0.0, s_amax, s_red);
+    __syncthreads();
+  }
+}
+
+// Regrowth and the resource total, per cell tile.
+__global__ __launch_bounds__(256) void k_regrow(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part) {
+  __shared__ uint32_t cnt[2];
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  const uint32_t step = (uint32_t)d.wv[tl.world].step;
+  uint32_t grown = 0, total = 0;
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i;
+    uint8_t r = d.res[wp.cell_off + c];
+    if (r == 0 && (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr) {
+      r = 1;
+      d.res[wp.cell_off + c] = 1;
+      ++grown;
+    }
+    total += r;
+  }
+  if (grown) atomicAdd(&cnt[0], grown);
+  atomicAdd(&cnt[1], total);
+  __syncthreads();
+  if (threadIdx.x < 2) part[blockIdx.x * kCellPart + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Per world (one block): live list, statistics record, clock.  init != 0:
+// statistics of the current state without advancing the clock or counters.
+__global__ __launch_bounds__(kScanThreads) void k_compact(Dev d, const uint32_t* __restrict__ part_slot,
+                                                          const uint32_t* __restrict__ part_cell,
+                                                          const uint32_t* __restrict__ tile_rng, int init,
+                                                          int only_world) {
+  __shared__ uint32_t red[kScanThreads / 64 + 1];
+  __shared__ unsigned long long red64[kScanThreads / 64];
+  __shared__ double redf[kScanThreads / 64];
+  __shared__ uint32_t s_cnt[kSlotPart + kCellPart];
+  const uint32_t w = blockIdx.x;
+  if (only_world >= 0 && (int)w != only_world) return;
+  const WorldParams wp = d.wp[w];
+  const uint32_t per = (wp.cap + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, wp.cap);
+  uint32_t n = 0;
+  long long esum = 0;
+  double tsum = 0.0;
+  for (uint32_t s = lo; s < hi; ++s) {
+    const uint32_t g = wp.slot_off + s;
+    if (d.flags[g] & kAlive) {
+      ++n;
+      esum += d.energy[g];
+      tsum += d.trait[g];
+    }
+  }
+  uint32_t N;
+  uint32_t o = block_exscan<kScanThreads>(n, red, &N);
+  for (uint32_t s = lo; s < hi; ++s)
+    if (d.flags[wp.slot_off + s] & kAlive) d.live[wp.slot_off + o++] = (int)s;
+  const unsigned long long E = block_sum_u64<kScanThreads>((unsigned long long)esum, red64);
+  const double T = block_sum_f64<kScanThreads>(tsum, redf);
+  __shared__ double s_mean;
+  if (threadIdx.x == 0) s_mean = N ? T / (double)N : 0.0;
+  __syncthreads();
+  const double mean = s_mean;
+  double vsum = 0.0;
+  for (uint32_t s = lo; s < hi; ++s) {
+    const uint32_t g = wp.slot_off + s;
+    if (d.flags[g] & kAlive) {
+      const double dv = d.trait[g] - mean;
+      vsum += dv * dv;
+    }
+  }
+  const double V = block_sum_f64<kScanThreads>(vsum, redf);
+  // tile counters of this world
+  if (threadIdx.x < kSlotPart + kCellPart) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (!init) {
+    const uint32_t st0 = tile_rng[4 * w], st1 = tile_rng[4 * w + 1];
+    const uint32_t ct0 = tile_rng[4 * w + 2], ct1 = tile_rng[4 * w + 3];
+    for (uint32_t i = threadIdx.x; i < (st1 - st0) * kSlotPart; i += blockDim.x)
+      atomicAdd(&s_cnt[i % kSlotPart], part_slot[st0 * kSlotPart + i]);
+    for (uint32_t i = threadIdx.x; i < (ct1 - ct0) * kCellPart; i += blockDim.x)
+      atomicAdd(&s_cnt[kSlotPart + i % kCellPart], part_cell[ct0 * kCellPart + i]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    WorldVar& v = d.wv[w];
+    eco_stats st = {};
+    if (!init) {
+      v.step += 1;
+      v.uid_next += v.n_births;
+      st.births = d.cnt[w].births;
+      st.births_blocked_cell = d.cnt[w].births_blocked_cell + s_cnt[PC_BB_CELL];
+      st.births_blocked_capacity = d.cnt[w].births_blocked_capacity;
+      st.deaths = s_cnt[PC_DEATHS];
+      st.eaten = s_cnt[PC_EATEN];
+      st.moves_ok = s_cnt[PC_MOVES_OK];
+      st.moves_blocked = s_cnt[PC_MOVES_BLOCKED];
+      for (int a = 0; a < 8; ++a) st.action_hist[a] = s_cnt[PC_HIST + a];
+      st.regrown = s_cnt[kSlotPart + 0];
+      st.resource_total = s_cnt[kSlotPart + 1];
+    } else {
+      // resource total of the current grid (init / state writes)
+      st.resource_total = 0;
+    }
+    v.n_live = N;
+    st.step = v.step;
+    st.population = N;
+    st.energy_total = (double)(long long)E;
+    st.trait_mean = mean;
+    st.trait_var = N ? V / (double)N : 0.0;
+    d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
+  }
+}
+
+// Resource total of each world (init / after state writes): one block per world.
+__global__ __launch_bounds__(kScanThreads) void k_resource_total(Dev d, int only_world) {
+  __shared__ unsigned long long red64[kScanThreads / 64];
+  const uint32_t w = blockIdx.x;
+  if (only_world >= 0 && (int)w != only_world) return;
+  const WorldParams wp = d.wp[w];
+  unsigned long long s = 0;
+  for (uint32_t c = threadIdx.x; c < wp.cells; c += blockDim.x) s += d.res[wp.cell_off + c];
+  const unsigned long long t = block_sum_u64<kScanThreads>(s, red64);
+  if (threadIdx.x == 0) d.ring[(uint64_t)w * kStatsRing + (d.wv[w].step % kStatsRing)].resource_total = t;
+}
+
+// ---------------------------------------------------------------------------
+// Init kernels
+// ---------------------------------------------------------------------------
+// Cell keys (for placement), initial resources, empty occupancy and claims.
+__global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i, g = wp.cell_off + c;
+    const uint32_t key = draw32(wp, c, 0u, ST_CELLKEY);
+    d.cellkeys[g] = ((unsigned long long)key << 32) | c;
+    d.res[g] = ((uint64_t)draw32(wp, c, 0u, ST_RESINIT) < wp.density_thr) ? 1 : 0;
+    d.occ[g] = -1;
+    d.claim[g] = 0xFFFFFFFFu;
+    d.wall[g] = 0;
+  }
+}
+
+// Slot j < n_init takes the j-th smallest (key, cell); all other slots are free.
+__global__ __launch_bounds__(kSlotTile) void k_init_agents(Dev d, const Tile* __restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  if (threadIdx.x >= tl.count) return;
+  const uint32_t j = tl.start + threadIdx.x, g = wp.slot_off + j;
+  d.tgt[g] = -1;
+  d.act[g] = 0;
+  d.sampled[g] = 255;
+  if (j < wp.n_init) {
+    const uint32_t cell = (uint32_t)(d.sorted[wp.cell_off + j] & 0xFFFFFFFFull);
+    d.flags[g] = kAlive;
+    d.pos[g] = (int)cell;
+    d.occ[wp.cell_off + cell] = (int)j;
+    d.facing[g] = (uint8_t)(draw32(wp, j, 0u, ST_FACING) >> 30);
+    d.energy[g] = wp.e_init;
+    d.age[g] = 0;
+    d.uid[g] = j;
+    d.puid[g] = ~0ull;
+  } else {
+    d.flags[g] = 0;
+    d.trait[g] = 0.0;
+  }
+}
+
+// Initial weights of a list of (world, local slot) pairs, one block per entry
+// (persistent).  list == nullptr: every slot j < n_init of every world, with
+// entries enumerated through the per-world init counts.
+template <int WDT>
+__global__ __launch_bounds__(256) void k_emit_list(Dev d, Layout L, const uint32_t* __restrict__ list, uint32_t n,
+                                                   int mode, double std1, double std2, double std3) {
+  __shared__ uint32_t s_amax[128 + 128 + 8];
+  __shared__ double s_red[4];
+  for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint32_t w = list[2 * e], j = list[2 * e + 1];
+    const WorldParams wp = d.wp[w];
+    const uint32_t g = wp.slot_off + j;
+    emit_agent<WDT>(d, L, wp, g, mode, g, j, 0u, std1, std2, std3, s_amax, s_red);
+    __syncthreads();
+  }
+}
+
+// Parity mode: mark every slot "not evaluated" before the policy kernel runs.
+__global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.total_slots) return;
+  d.sampled[i] = 255;
+  if (d.keep_logits) {
+    const float nan = __builtin_nanf("");
+#pragma unroll
+    for (int a = 0; a < 8; ++a) d.logits[(uint64_t)i * 8 + a] = nan;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (used by eco_runtime.cpp)
+// ---------------------------------------------------------------------------
+#define ECO_CHECK_LAUNCH() return hipGetLastError()
+
+hipError_t launch_move(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move, dim3(nt), dim3(kSlotTile), 0, s, d, tiles, part);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_birth_claim(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part,
+                              uint32_t A) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_birth_claim, dim3(nt), dim3(kSlotTile), 0, s, d, tiles, part, A);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_birth_scan(hipStream_t s, const Dev& d) {
+  hipLaunchKernelGGL(k_birth_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks) {
+  if (L.wdtype == 0) hipLaunchKernelGGL(k_birth_commit<0>, dim3(blocks), dim3(256), 0, s, d, L);
+  else if (L.wdtype == 1) hipLaunchKernelGGL(k_birth_commit<1>, dim3(blocks), dim3(256), 0, s, d, L);
+  else hipLaunchKernelGGL(k_birth_commit<2>, dim3(blocks), dim3(256), 0, s, d, L);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_regrow(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_regrow, dim3(nt), dim3(256), 0, s, d, tiles, part);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_compact(hipStream_t s, const Dev& d, const uint32_t* part_slot, const uint32_t* part_cell,
+                          const uint32_t* tile_rng, int init, int only_world) {
+  hipLaunchKernelGGL(k_compact, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, part_slot, part_cell, tile_rng,
+                     init, only_world);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {
+  hipLaunchKernelGGL(k_prestep_fill, dim3((d.total_slots + 255) / 256), dim3(256), 0, s, d);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world) {
+  hipLaunchKernelGGL(k_resource_total, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, only_world);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_cells, dim3(nt), dim3(256), 0, s, d, tiles);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_agents, dim3(nt), dim3(kSlotTile), 0, s, d, tiles);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_emit_list(hipStream_t s, const Dev& d, const Layout& L, const uint32_t* list, uint32_t n, int mode,
+                            double std1, double std2, double std3, uint32_t blocks) {
+  if (n == 0) return hipSuccess;
+  if (L.wdtype == 0)
+    hipLaunchKernelGGL(k_emit_list<0>, dim3(blocks), dim3(256), 0, s, d, L, list, n, mode, std1, std2, std3);
+  else if (L.wdtype == 1)
+    hipLaunchKernelGGL(k_emit_list<1>, dim3(blocks), dim3(256), 0, s, d, L, list, n, mode, std1, std2, std3);
+  else
+    hipLaunchKernelGGL(k_emit_list<2>, dim3(blocks), dim3(256), 0, s, d, L, list, n, mode, std1, std2, std3);
+  ECO_CHECK_LAUNCH();
+}
+
+}  // namespace eco

@@ -1,0 +1,57 @@
+"""Shared helpers of the GPU tests: world pairs (HIP library + oracle) and comparisons."""
+import sys
+
+import numpy as np
+import pytest
+
+from worldstate import assert_same_state
+
+LOGIT_TOL = 1e-5    # normwise relative, FP32 GPU vs FP64 oracle on the same stored weights
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def logit_err(gpu, ref):
+    """Per-agent normwise relative error max|l_gpu - l_ref| / max(max|l_ref|, 1e-30)."""
+    num = np.abs(gpu.astype(np.float64) - ref).max(axis=-1)
+    den = np.maximum(np.abs(ref).max(axis=-1), 1e-30)
+    return num / den
+
+
+def assert_weights_close(gpu, ref, what, ulps=4):
+    """FP32 master / storage values: identical up to a few FP32 ulps (the Box-Muller
+    transform runs on libm on the CPU and on ocml on the GPU; both within an ulp
+    in FP64, which moves the FP32 result by at most one rounding step)."""
+    tol = ulps * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    bad = np.abs(gpu - ref) > tol
+    assert not bad.any(), (what, int(bad.sum()), np.nonzero(bad)[0][:5])
+
+
+def assert_stats_match(g, o, what, check_trait=True):
+    for k in ("step", "population", "births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+              "births_blocked_cell", "births_blocked_capacity", "resource_total", "action_hist"):
+        assert g[k] == o[k], (what, k, g[k], o[k])
+    assert g["energy_total"] == o["energy_total"], (what, "energy_total")
+    if check_trait:
+        for k in ("trait_mean", "trait_var"):
+            assert abs(g[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), (what, k, g[k], o[k])
+
+
+def compare_world(gw, ow, what, world=0, weights_slots=8):
+    gs, os_ = gw.read_state(world), ow.state()
+    assert_same_state(gs, os_, what)
+    live = np.nonzero(os_["alive"])[0]
+    for s in live[:: max(1, len(live) // weights_slots)][:weights_slots]:
+        assert_weights_close(gw.read_weights(int(s), world, master=True), ow.weights(int(s), master=True),
+                             f"{what} master slot {s}")
+        assert_weights_close(gw.read_weights(int(s), world), ow.weights(int(s)), f"{what} storage slot {s}")
+    return gs

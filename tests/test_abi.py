@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every symbol include/eco.h declares (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "eco.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eco_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_boundary():
+    names = declared_functions()
+    for required in ("eco_world_create", "eco_world_step", "eco_world_reset", "eco_world_stats"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2510_18221_amd import eco
+    lib = eco.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(eco.EXPORTS) == sorted(declared_functions())
+
+
+def test_validation_errors_without_device():
+    """Descriptor checks run before any HIP call, so they are testable on the CPU."""
+    from paper_2510_18221_amd import eco
+    from paper_2510_18221_amd import workloads as wl
+    lib = eco.lib()
+    out = ctypes.c_void_p()
+    assert lib.eco_world_create(None, 0, None, None, ctypes.byref(out)) == eco.ECO_EINVAL
+    for bad, status in [(dict(window=4), eco.ECO_EINVAL), (dict(n_scalars=3), eco.ECO_EINVAL),
+                        (dict(hidden1=48, hidden2=48), eco.ECO_ENOTSUP), (dict(attack_enabled=1), eco.ECO_ENOTSUP),
+                        (dict(capacity=10), eco.ECO_EINVAL), (dict(e_repro=0), eco.ECO_EINVAL)]:
+        d = (eco.Desc * 1)(eco.make_desc(wl.desc(**bad)))
+        assert lib.eco_world_create(d, 1, None, None, ctypes.byref(out)) == status, bad
+        assert lib.eco_last_error()
+    d = eco.make_desc(wl.desc())
+    d.struct_size = 4
+    assert lib.eco_world_create((eco.Desc * 1)(d), 1, None, None, ctypes.byref(out)) == eco.ECO_EINVAL
+    assert b"struct_size" in lib.eco_last_error()
+
+
+def test_struct_sizes_match_header():
+    from paper_2510_18221_amd import eco
+    assert ctypes.sizeof(eco.Desc) == 96
+    assert ctypes.sizeof(eco.Stats) == 19 * 8 + 3 * 8

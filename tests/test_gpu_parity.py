@@ -1,0 +1,256 @@
+"""Parity of the HIP world step (libeco.so through its C ABI) with the CPU oracle.
+
+Integer world state must match bit for bit given identical actions; FP32
+logits within 1e-5 normwise relative of the oracle's FP64 logits on the same
+stored weights; weights within a few FP32 ulps.  Actions always come from the
+oracle or from the seeded input generators, never from the GPU.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2510_18221_amd import workloads as wl
+
+from gpu_util import LOGIT_TOL, assert_stats_match, assert_weights_close, compare_world, logit_err, need_gpu, say
+from worldstate import N, E, S, W, assert_same_state, check_invariants, empty_state, place
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eco():
+    need_gpu()
+    from paper_2510_18221_amd import eco as m
+    m.lib()
+    return m
+
+
+def mid_world(seed=0, wdtype=0, **kw):
+    """Several forward tiles and a ragged tail: 96x80 torus, 11x11 window, 64-wide MLP."""
+    d = wl.desc(width=96, height=80, n_agents_init=450, capacity=700, resource_density=0.3, regrow_prob=0.02,
+                mutation_sigma=0.01, window=11, n_scalars=8, hidden1=64, hidden2=64, n_actions=7, wdtype=wdtype,
+                seed=seed, e_init=170)
+    d.update(kw)
+    return d
+
+
+def run_pair(eco, cfg, steps, actions_fn=None, check_logits=True, what="", every=1):
+    """Step GPU and oracle together.  actions_fn(step) -> actions, or None for the
+    oracle's own sampled actions, which are injected into the GPU world."""
+    ow = orc.OracleWorld(cfg)
+    gw = eco.World(cfg)
+    gw.set_flags(eco.RT_KEEP_LOGITS)
+    compare_world(gw, ow, f"{what} init")
+    assert_stats_match(gw.stats()[0], ow.stats(), f"{what} init")
+    worst = 0.0
+    mismatched = 0
+    for t in range(steps):
+        pre_alive = ow.state()["alive"].astype(bool)
+        if actions_fn is None:
+            logits, sampled = ow.step(want_logits=True, want_sampled=True)
+            acts = sampled.copy()
+            acts[~pre_alive] = 0
+        else:
+            acts = actions_fn(t)
+            logits, sampled = ow.step(actions=acts, want_logits=True, want_sampled=True)
+        gw.step_with_actions(acts)
+        if check_logits:
+            gl = gw.read_logits()
+            err = logit_err(gl[pre_alive], logits[pre_alive])
+            worst = max(worst, float(err.max(initial=0.0)))
+            assert np.all(np.isnan(gl[~pre_alive]))
+            gs = gw.read_sampled()
+            mismatched += int((gs[pre_alive] != sampled[pre_alive]).sum())
+        if t % every == 0 or t == steps - 1:
+            compare_world(gw, ow, f"{what} step {t}")
+            assert_stats_match(gw.stats()[0], ow.stats(), f"{what} step {t}")
+    gw.close()
+    say(f"{what}: worst normwise logit error {worst:.3e}, sampled-action mismatches {mismatched}")
+    assert worst <= LOGIT_TOL
+    return worst, mismatched
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_world_100_steps_oracle_actions(eco, seed):
+    """64x64, 256 agents, D=104, 104->32->32->5 FP32, sigma 0.02: 100 steps."""
+    cfg = wl.world_small(seed=seed)
+    _, mism = run_pair(eco, cfg, 100, what=f"small seed {seed}", every=5)
+    assert mism <= 3
+
+
+@pytest.mark.parametrize("wdtype", [0, 1, 2])
+def test_mid_world_births_and_deaths(eco, wdtype):
+    cfg = mid_world(seed=5, wdtype=wdtype)
+    acts = lambda t: wl.biased_actions(cfg["capacity"], 7, 5, t)
+    run_pair(eco, cfg, 25, actions_fn=acts, what=f"mid wdtype {wdtype}", every=4)
+
+
+def test_mid_world_free_running_logits(eco):
+    cfg = mid_world(seed=9, e_init=100)
+    run_pair(eco, cfg, 8, what="mid free-running")
+
+
+def test_capacity_pressure_and_extinction(eco):
+    cfg = mid_world(seed=3, capacity=456, e_init=199, resource_density=1.0)
+    acts = lambda t: wl.biased_actions(cfg["capacity"], 7, 3, t, p_forward=0.1, p_eat=0.6)
+    run_pair(eco, cfg, 6, actions_fn=acts, what="capacity", check_logits=False)
+    cfg = mid_world(seed=3, e_init=2, e_eat=0)
+    run_pair(eco, cfg, 4, actions_fn=lambda t: np.zeros(cfg["capacity"], np.uint8), what="extinction",
+             check_logits=False)
+
+
+def test_multi_world_object(eco):
+    """Worlds of uneven size in one object, each against its own oracle."""
+    cfgs = [mid_world(seed=s, width=w, height=h, n_agents_init=n, capacity=c)
+            for s, (w, h, n, c) in enumerate([(40, 30, 70, 128), (96, 80, 450, 700), (17, 23, 20, 64),
+                                               (60, 60, 200, 320)])]
+    gw = eco.World(cfgs)
+    gw.set_flags(eco.RT_KEEP_LOGITS)
+    ows = [orc.OracleWorld(c) for c in cfgs]
+    for i, ow in enumerate(ows):
+        compare_world(gw, ow, f"world {i} init", world=i)
+    for t in range(12):
+        acts = [wl.biased_actions(c["capacity"], 7, i, t) for i, c in enumerate(cfgs)]
+        outs = [ow.step(actions=a, want_logits=True) for ow, a in zip(ows, acts)]
+        pre = [ow for ow in ows]
+        gw.step_with_actions(np.concatenate(acts))
+        for i, ow in enumerate(ows):
+            compare_world(gw, ow, f"world {i} step {t}", world=i, weights_slots=2)
+            assert_stats_match(gw.stats()[i], ow.stats(), f"world {i} step {t}")
+            gl = gw.read_logits(i)
+            ok = ~np.isnan(gl[:, 0])
+            assert logit_err(gl[ok], outs[i][0][ok]).max(initial=0) <= LOGIT_TOL
+    gw.close()
+
+
+def test_determinism_and_launch_shapes(eco):
+    """Free-running GPU worlds: same seed, any launch shape -> identical state."""
+    cfg = mid_world(seed=4, e_init=150)
+    ref = None
+    for lc in [(4, 4, 8), (1, 16, 4), (8, 2, 16), (2, 8, 8)]:
+        gw = eco.World(cfg)
+        gw.set_launch(*lc)
+        gw.step(30)
+        st = gw.read_state()
+        hist = gw.stats_history(0, 31)
+        gw.close()
+        if ref is None:
+            ref = (st, hist)
+        else:
+            assert_same_state(st, ref[0], f"launch {lc}")
+            assert hist == ref[1]
+
+
+def test_graph_and_eager_paths_agree(eco):
+    cfg = mid_world(seed=6, e_init=150)
+    a = eco.World(cfg)
+    b = eco.World(cfg)
+    b.set_flags(0)  # eager
+    a.step(20)
+    b.step(20)
+    assert_same_state(a.read_state(), b.read_state(), "graph vs eager")
+    assert a.stats() == b.stats()
+    a.close()
+    b.close()
+
+
+def test_resume_from_state_and_weights(eco):
+    cfg = mid_world(seed=7, e_init=150)
+    a = eco.World(cfg)
+    a.step(15)
+    st = a.read_state()
+    live = np.nonzero(st["alive"])[0]
+    masters = {int(s): a.read_weights(int(s), master=True).astype(np.float32) for s in live}
+    b = eco.World(cfg)
+    b.write_state(st)
+    for s, m in masters.items():
+        b.write_weights(s, m)
+    a.step(15)
+    b.step(15)
+    assert_same_state(a.read_state(), b.read_state(), "resume")
+    a.close()
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# Hand-built states on the GPU, against the oracle
+# ---------------------------------------------------------------------------
+def _tiny(**kw):
+    c = wl.desc(width=5, height=5, n_agents_init=0, capacity=4, window=3, n_scalars=4, hidden1=32, hidden2=32,
+                n_actions=5, resource_density=0.0, regrow_prob=0.0, seed=1)
+    c.update(kw)
+    return c
+
+
+@pytest.mark.parametrize("case", ["contest", "chain", "wrap", "swap", "eat", "death_birth", "births", "conflict",
+                                  "capacity", "regrow", "walls"])
+def test_hand_built_cases(eco, case):
+    cfg = _tiny()
+    st = empty_state(5, 5, 4)
+    acts = [0, 0, 0, 0]
+    if case == "contest":
+        place(st, 5, 0, 1, 1, E, 100); place(st, 5, 1, 3, 1, W, 100); acts = [3, 3, 0, 0]
+    elif case == "chain":
+        place(st, 5, 0, 0, 0, E, 100); place(st, 5, 1, 1, 0, E, 100); acts = [3, 3, 0, 0]
+    elif case == "wrap":
+        place(st, 5, 0, 4, 2, E, 100); acts = [3, 0, 0, 0]
+    elif case == "swap":
+        place(st, 5, 0, 1, 1, E, 100); place(st, 5, 1, 2, 1, W, 100); acts = [3, 3, 0, 0]
+    elif case == "eat":
+        place(st, 5, 0, 1, 1, N, 100); place(st, 5, 1, 3, 3, N, 100); st["res"][6] = 1; acts = [4, 4, 0, 0]
+    elif case == "death_birth":
+        cfg = _tiny(capacity=2)
+        st = empty_state(5, 5, 2)
+        place(st, 5, 0, 0, 0, N, 1); place(st, 5, 1, 2, 2, N, 300, uid=7); acts = [0, 0]
+    elif case == "births":
+        place(st, 5, 0, 1, 1, N, 201); place(st, 5, 2, 3, 3, E, 210)
+    elif case == "conflict":
+        place(st, 5, 0, 1, 0, N, 250); place(st, 5, 1, 1, 2, S, 250)
+    elif case == "capacity":
+        cfg = _tiny(capacity=2)
+        st = empty_state(5, 5, 2)
+        place(st, 5, 0, 1, 1, N, 250); place(st, 5, 1, 3, 3, N, 50); acts = [0, 0]
+    elif case == "regrow":
+        cfg = _tiny(regrow_prob=1.0)
+        place(st, 5, 0, 0, 0, N, 100); st["res"][3] = 1
+    elif case == "walls":
+        place(st, 5, 0, 1, 1, E, 100); place(st, 5, 1, 3, 3, N, 250); acts = [3, 0, 0, 0]
+        st["wall"][1 * 5 + 2] = 1; st["wall"][4 * 5 + 3] = 1
+    ow = orc.OracleWorld(cfg)
+    ow.write_state(st)
+    gw = eco.World(cfg)
+    gw.write_state(st)
+    assert_same_state(gw.read_state(), ow.state(), f"{case} written")
+    a = np.array(acts, np.uint8)
+    ow.step(actions=a)
+    gw.step_with_actions(a)
+    assert_same_state(gw.read_state(), ow.state(), case)
+    assert_stats_match(gw.stats()[0], ow.stats(), case)
+    check_invariants(gw.read_state(), 5, 5)
+    gw.close()
+
+
+def test_errors(eco):
+    with pytest.raises(eco.EcoError) as e:
+        eco.World(wl.desc(window=4))
+    assert e.value.status == eco.ECO_EINVAL
+    with pytest.raises(eco.EcoError) as e:
+        eco.World(wl.desc(hidden1=48, hidden2=48))
+    assert e.value.status == eco.ECO_ENOTSUP
+    with pytest.raises(eco.EcoError) as e:
+        eco.World(wl.desc(attack_enabled=1))
+    assert e.value.status == eco.ECO_ENOTSUP
+    with pytest.raises(eco.EcoError):
+        eco.World([wl.desc(), wl.desc(hidden1=64, hidden2=64)])
+    gw = eco.World(wl.world_small())
+    bad = np.full(4096, 9, np.uint8)
+    with pytest.raises(eco.EcoError) as e:
+        gw.step_with_actions(bad)
+    assert e.value.status == eco.ECO_EINVAL
+    st = gw.read_state()
+    st["occ"][:] = -1
+    with pytest.raises(eco.EcoError):
+        gw.write_state(st)
+    gw.step(2)
+    assert gw.stats()[0]["step"] == 2
+    gw.close()
