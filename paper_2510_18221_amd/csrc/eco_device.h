@@ -114,6 +114,23 @@ struct Tile {
   uint32_t world, start, count, pad;
 };
 
+// Per-tile scratch of the multi-block passes (slot tiles of 256 slots, cell
+// tiles of 4096 cells; a world's tiles are contiguous: tile_rng[4w..4w+3] =
+// first/last slot tile, first/last cell tile).
+struct TileScratch {
+  const Tile* slot_tiles;
+  const Tile* cell_tiles;
+  const uint32_t* tile_rng;
+  uint32_t n_slot_tiles, n_cell_tiles;
+  uint32_t* part_slot;   // [slot tiles][16] step counters (actions, moves, meals, deaths, blocked births)
+  uint32_t* part_cell;   // [cell tiles][2] regrown, resource total
+  uint32_t* scan;        // [slot tiles][4] claims, winners, free slots, live slots
+  uint32_t* off;         // [slot tiles][3] world-exclusive offsets: winners, free slots, live slots
+  long long* esum;       // [slot tiles] energy sum of live slots
+  double* tsum;          // [slot tiles] trait sum
+  double* tsq;           // [slot tiles] trait sum of squares
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, two 32x32->64
 // multiplies per round, key bumped by the Weyl constants between rounds.

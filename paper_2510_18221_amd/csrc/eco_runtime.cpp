@@ -22,14 +22,11 @@ hipError_t launch_forward_w1(int H, int U, dim3 grid, dim3 block, size_t shmem, 
                              const Layout& L);
 hipError_t launch_forward_w2(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
-hipError_t launch_move(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part);
-hipError_t launch_birth_claim(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part,
-                              uint32_t A);
-hipError_t launch_birth_scan(hipStream_t s, const Dev& d);
+hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
+hipError_t launch_birth_claim_regrow(hipStream_t s, const Dev& d, const TileScratch& ts, uint32_t A);
+hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
-hipError_t launch_regrow(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part);
-hipError_t launch_compact(hipStream_t s, const Dev& d, const uint32_t* part_slot, const uint32_t* part_cell,
-                          const uint32_t* tile_rng, int init, int only_world);
+hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
@@ -91,6 +88,7 @@ struct eco_world {
   uint32_t* part_slot = nullptr;
   uint32_t* part_cell = nullptr;
   uint32_t* tile_rng = nullptr;
+  TileScratch ts{};
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   uint32_t* emit_list = nullptr;
@@ -293,7 +291,7 @@ eco_status run_init(eco_world* w) {
     HIPCHK(w, launch_emit_list(s, d, w->L, w->emit_list, n, EMIT_INIT, w->std1, w->std2, w->std3, emit_blocks(w)),
            "init weights");
   }
-  HIPCHK(w, launch_compact(s, d, w->part_slot, w->part_cell, w->tile_rng, 1, -1), "compact");
+  HIPCHK(w, launch_compact(s, d, w->ts, 1, -1), "compact");
   HIPCHK(w, launch_resource_total(s, d, -1), "resource total");
   eco_status st = sync(w);
   if (st != ECO_OK) return st;
@@ -346,19 +344,13 @@ eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
   };
   if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
   HIPCHK(w, run(ECO_K_FORWARD, [&] { return launch_forward(w, s, d, w->launch); }), "forward kernel");
-  HIPCHK(w, run(ECO_K_MOVE, [&] { return launch_move(s, d, w->slot_tiles, w->n_slot_tiles, w->part_slot); }),
-         "move kernel");
-  HIPCHK(w, run(ECO_K_BIRTH_CLAIM, [&] {
-           return launch_birth_claim(s, d, w->slot_tiles, w->n_slot_tiles, w->part_slot, w->L.A);
-         }), "birth claim kernel");
-  HIPCHK(w, run(ECO_K_BIRTH_SCAN, [&] { return launch_birth_scan(s, d); }), "birth scan kernel");
+  HIPCHK(w, run(ECO_K_MOVE, [&] { return launch_move(s, d, w->ts); }), "move kernel");
+  HIPCHK(w, run(ECO_K_BIRTH_CLAIM, [&] { return launch_birth_claim_regrow(s, d, w->ts, w->L.A); }),
+         "birth claim / regrowth kernel");
+  HIPCHK(w, run(ECO_K_BIRTH_SCAN, [&] { return launch_birth_rank(s, d, w->ts); }), "birth ranking kernels");
   HIPCHK(w, run(ECO_K_BIRTH_COMMIT, [&] { return launch_birth_commit(s, d, w->L, emit_blocks(w)); }),
          "birth commit kernel");
-  HIPCHK(w, run(ECO_K_REGROW, [&] { return launch_regrow(s, d, w->cell_tiles, w->n_cell_tiles, w->part_cell); }),
-         "regrow kernel");
-  HIPCHK(w, run(ECO_K_COMPACT, [&] {
-           return launch_compact(s, d, w->part_slot, w->part_cell, w->tile_rng, 0, -1);
-         }), "compact kernel");
+  HIPCHK(w, run(ECO_K_COMPACT, [&] { return launch_compact(s, d, w->ts, 0, -1); }), "compaction kernels");
   return ECO_OK;
 }
 
@@ -569,6 +561,22 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   w->part_slot = (uint32_t*)A(4ull * kSlotPartH * std::max(1u, w->n_slot_tiles));
   w->part_cell = (uint32_t*)A(4ull * kCellPartH * std::max(1u, w->n_cell_tiles));
   w->tile_rng = (uint32_t*)A(4ull * w->tile_rng_h.size());
+  {
+    const uint64_t T = std::max(1u, w->n_slot_tiles);
+    TileScratch& ts = w->ts;
+    ts.slot_tiles = w->slot_tiles;
+    ts.cell_tiles = w->cell_tiles;
+    ts.tile_rng = w->tile_rng;
+    ts.n_slot_tiles = w->n_slot_tiles;
+    ts.n_cell_tiles = w->n_cell_tiles;
+    ts.part_slot = w->part_slot;
+    ts.part_cell = w->part_cell;
+    ts.scan = (uint32_t*)A(16 * T);
+    ts.off = (uint32_t*)A(12 * T);
+    ts.esum = (long long*)A(8 * T);
+    ts.tsum = (double*)A(8 * T);
+    ts.tsq = (double*)A(8 * T);
+  }
   w->emit_list = (uint32_t*)A(8 * TS);
   if (ok && sort_keys_temp_bytes(max_cells, &w->sort_tmp_bytes) != hipSuccess) ok = false;
   if (ok) w->sort_tmp = A(w->sort_tmp_bytes);
@@ -948,7 +956,7 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
     HIPCHK(w, launch_emit_list(s, w->d, w->L, w->emit_list, (uint32_t)(list.size() / 2), EMIT_INIT, w->std1, w->std2,
                                w->std3, emit_blocks(w)), "init weights");
   }
-  HIPCHK(w, launch_compact(s, w->d, w->part_slot, w->part_cell, w->tile_rng, 1, (int)world), "compact");
+  HIPCHK(w, launch_compact(s, w->d, w->ts, 1, (int)world), "compact");
   HIPCHK(w, launch_resource_total(s, w->d, (int)world), "resource total");
   return sync(w);
 }

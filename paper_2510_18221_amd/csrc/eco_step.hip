@@ -328,13 +328,12 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
   if (threadIdx.x < 12) part[blockIdx.x * kSlotPart + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Eligible parents claim the empty cell directly behind them.
-__global__ __launch_bounds__(kSlotTile) void k_birth_claim(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part,
-                                                           uint32_t n_actions) {
-  __shared__ uint32_t blocked;
-  if (threadIdx.x == 0) blocked = 0;
-  __syncthreads();
-  const Tile tl = tiles[blockIdx.x];
+// Eligible parents claim the empty cell directly behind them (slot tiles), and
+// in the same launch each cell tile regrows its empty cells (independent work:
+// regrowth reads and writes only the resource layer).
+__device__ __forceinline__ void birth_claim_tile(const Dev& d, const TileScratch& ts, uint32_t tile, uint32_t n_actions,
+                                                 uint32_t* blocked) {
+  const Tile tl = ts.slot_tiles[tile];
   const WorldParams wp = d.wp[tl.world];
   if (threadIdx.x < tl.count) {
     const uint32_t local = tl.start + threadIdx.x;
@@ -350,62 +349,88 @@ __global__ __launch_bounds__(kSlotTile) void k_birth_claim(Dev d, const Tile* __
           d.tgt[slot] = (int)t;
           d.flags[slot] = fl | kBirthClaim;
         } else {
-          atomicAdd(&blocked, 1u);
+          atomicAdd(blocked, 1u);
         }
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x * kSlotPart + PC_BB_CELL] = blocked;
+  if (threadIdx.x == 0) ts.part_slot[tile * kSlotPart + PC_BB_CELL] = *blocked;
 }
 
-// Per world (one block): rank the claim winners in slot order and list the
-// free slots in ascending order.  Birth rank k takes free slot k.
-__global__ __launch_bounds__(kScanThreads) void k_birth_scan(Dev d) {
-  __shared__ uint32_t red[kScanThreads / 64 + 1];
-  __shared__ uint32_t tot_claim;
-  const uint32_t w = blockIdx.x;
-  const WorldParams wp = d.wp[w];
-  const uint32_t per = (wp.cap + kScanThreads - 1) / kScanThreads;
-  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, wp.cap);
-  if (threadIdx.x == 0) tot_claim = 0;
-  uint32_t nwin = 0, nfree = 0, nclaim = 0;
-  for (uint32_t s = lo; s < hi; ++s) {
-    uint8_t fl = d.flags[wp.slot_off + s];
+__device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile, uint32_t* cnt) {
+  const Tile tl = ts.cell_tiles[tile];
+  const WorldParams wp = d.wp[tl.world];
+  const uint32_t step = (uint32_t)d.wv[tl.world].step;
+  uint32_t grown = 0, total = 0;
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i;
+    uint8_t r = d.res[wp.cell_off + c];
+    if (r == 0 && (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr) {
+      r = 1;
+      d.res[wp.cell_off + c] = 1;
+      ++grown;
+    }
+    total += r;
+  }
+  if (grown) atomicAdd(&cnt[0], grown);
+  atomicAdd(&cnt[1], total);
+  __syncthreads();
+  if (threadIdx.x < 2) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_birth_claim_regrow(Dev d, TileScratch ts, uint32_t n_actions) {
+  __shared__ uint32_t cnt[2];
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (blockIdx.x < ts.n_slot_tiles) birth_claim_tile(d, ts, blockIdx.x, n_actions, &cnt[0]);
+  else regrow_tile(d, ts, blockIdx.x - ts.n_slot_tiles, cnt);
+}
+
+// Birth ranking, pass 1 (slot tiles): mark the claim winners; count claims,
+// winners and free slots of the tile.
+__global__ __launch_bounds__(kSlotTile) void k_birth_rank_count(Dev d, TileScratch ts) {
+  __shared__ uint32_t cnt[3];
+  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const Tile tl = ts.slot_tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  if (threadIdx.x < tl.count) {
+    const uint32_t slot = wp.slot_off + tl.start + threadIdx.x;
+    const uint8_t fl = d.flags[slot];
     if (fl & kBirthClaim) {
-      ++nclaim;
-      const int t = d.tgt[wp.slot_off + s];
-      if (d.claim[wp.cell_off + t] == wp.slot_off + s) {
-        fl |= kBirthWon;
-        d.flags[wp.slot_off + s] = fl;
-        ++nwin;
+      atomicAdd(&cnt[0], 1u);
+      if (d.claim[wp.cell_off + d.tgt[slot]] == slot) {
+        d.flags[slot] = fl | kBirthWon;
+        atomicAdd(&cnt[1], 1u);
       }
     }
-    if (!(fl & kAlive)) ++nfree;
+    if (!(fl & kAlive)) atomicAdd(&cnt[2], 1u);
   }
   __syncthreads();
-  if (nclaim) atomicAdd(&tot_claim, nclaim);
-  uint32_t W, F;
-  uint32_t off_win = block_exscan<kScanThreads>(nwin, red, &W);
-  uint32_t off_free = block_exscan<kScanThreads>(nfree, red, &F);
-  for (uint32_t s = lo; s < hi; ++s) {
-    const uint8_t fl = d.flags[wp.slot_off + s];
-    if (fl & kBirthClaim) d.claim[wp.cell_off + d.tgt[wp.slot_off + s]] = 0xFFFFFFFFu;
-    if (fl & kBirthWon) d.bparent[wp.slot_off + off_win++] = (int)s;
-    if (!(fl & kAlive)) {
-      if (off_free < W) d.freel[wp.slot_off + off_free] = (int)s;
-      ++off_free;
-    }
-    if (fl & (kBirthClaim | kBirthWon)) d.flags[wp.slot_off + s] = fl & kAlive;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t nb = min(W, F);
-    d.wv[w].n_births = nb;
-    d.wv[w].n_win = W;
-    d.cnt[w].births = nb;
-    d.cnt[w].births_blocked_cell = tot_claim - W;
-    d.cnt[w].births_blocked_capacity = W - nb;
+  if (threadIdx.x < 3) ts.scan[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Birth ranking, pass 3 (slot tiles): winner k of the world (slot order) is
+// recorded as bparent[k], free slot f (ascending) as freel[f] while f < W.
+// Claims of this step are cleared.
+__global__ __launch_bounds__(kSlotTile) void k_birth_rank_write(Dev d, TileScratch ts) {
+  __shared__ uint32_t red[kSlotTile / 64 + 1];
+  const Tile tl = ts.slot_tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  const uint32_t W = d.wv[tl.world].n_win;
+  const bool in = threadIdx.x < tl.count;
+  const uint32_t local = tl.start + threadIdx.x;
+  const uint32_t slot = wp.slot_off + local;
+  const uint8_t fl = in ? d.flags[slot] : (uint8_t)kAlive;
+  uint32_t tot;
+  const uint32_t rw = ts.off[blockIdx.x * 3 + 0] + block_exscan<kSlotTile>((fl & kBirthWon) ? 1u : 0u, red, &tot);
+  const uint32_t rf = ts.off[blockIdx.x * 3 + 1] + block_exscan<kSlotTile>((fl & kAlive) ? 0u : 1u, red, &tot);
+  if (in) {
+    if (fl & kBirthClaim) d.claim[wp.cell_off + d.tgt[slot]] = 0xFFFFFFFFu;
+    if (fl & kBirthWon) d.bparent[wp.slot_off + rw] = (int)local;
+    if (!(fl & kAlive) && rf < W) d.freel[wp.slot_off + rf] = (int)local;
+    if (fl & (kBirthClaim | kBirthWon)) d.flags[slot] = fl & kAlive;
   }
 }
 
@@ -468,86 +493,118 @@ __global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
   }
 }
 
-// Regrowth and the resource total, per cell tile.
-__global__ __launch_bounds__(256) void k_regrow(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part) {
-  __shared__ uint32_t cnt[2];
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const Tile tl = tiles[blockIdx.x];
+// Compaction, pass 1 (slot tiles): live count, energy sum, trait sums of the tile.
+__global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch ts, int only_world) {
+  __shared__ unsigned long long red64[kSlotTile / 64];
+  __shared__ double redf[kSlotTile / 64];
+  const Tile tl = ts.slot_tiles[blockIdx.x];
+  if (only_world >= 0 && (int)tl.world != only_world) return;
   const WorldParams wp = d.wp[tl.world];
-  const uint32_t step = (uint32_t)d.wv[tl.world].step;
-  uint32_t grown = 0, total = 0;
-  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-    const uint32_t c = tl.start + i;
-    uint8_t r = d.res[wp.cell_off + c];
-    if (r == 0 && (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr) {
-      r = 1;
-      d.res[wp.cell_off + c] = 1;
-      ++grown;
+  bool alive = false;
+  long long e = 0;
+  double t = 0.0;
+  if (threadIdx.x < tl.count) {
+    const uint32_t slot = wp.slot_off + tl.start + threadIdx.x;
+    alive = d.flags[slot] & kAlive;
+    if (alive) {
+      e = d.energy[slot];
+      t = d.trait[slot];
     }
-    total += r;
   }
-  if (grown) atomicAdd(&cnt[0], grown);
-  atomicAdd(&cnt[1], total);
-  __syncthreads();
-  if (threadIdx.x < 2) part[blockIdx.x * kCellPart + threadIdx.x] = cnt[threadIdx.x];
+  const unsigned long long n = block_sum_u64<kSlotTile>(alive ? 1ull : 0ull, red64);
+  const unsigned long long es = block_sum_u64<kSlotTile>((unsigned long long)e, red64);
+  const double s1 = block_sum_f64<kSlotTile>(t, redf);
+  const double s2 = block_sum_f64<kSlotTile>(t * t, redf);
+  if (threadIdx.x == 0) {
+    ts.scan[blockIdx.x * 4 + 3] = (uint32_t)n;
+    ts.esum[blockIdx.x] = (long long)es;
+    ts.tsum[blockIdx.x] = s1;
+    ts.tsq[blockIdx.x] = s2;
+  }
 }
 
-// Per world (one block): live list, statistics record, clock.  init != 0:
-// statistics of the current state without advancing the clock or counters.
-__global__ __launch_bounds__(kScanThreads) void k_compact(Dev d, const uint32_t* __restrict__ part_slot,
-                                                          const uint32_t* __restrict__ part_cell,
-                                                          const uint32_t* __restrict__ tile_rng, int init,
-                                                          int only_world) {
+// Compaction, pass 3 (slot tiles): live slots of the tile at their offsets.
+__global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch ts, int only_world) {
+  __shared__ uint32_t red[kSlotTile / 64 + 1];
+  const Tile tl = ts.slot_tiles[blockIdx.x];
+  if (only_world >= 0 && (int)tl.world != only_world) return;
+  const WorldParams wp = d.wp[tl.world];
+  const bool in = threadIdx.x < tl.count;
+  const uint32_t local = tl.start + threadIdx.x;
+  const bool alive = in && (d.flags[wp.slot_off + local] & kAlive);
+  uint32_t tot;
+  const uint32_t r = ts.off[blockIdx.x * 3 + 2] + block_exscan<kSlotTile>(alive ? 1u : 0u, red, &tot);
+  if (alive) d.live[wp.slot_off + r] = (int)local;
+}
+
+// Pass 2 of both tile scans (one block per world).
+//  mode 0: exclusive tile offsets of birth winners and free slots; birth totals.
+//  mode 1: exclusive tile offsets of live slots; the step's statistics record;
+//          the clock advances unless init != 0 (init / state writes).
+__global__ __launch_bounds__(kScanThreads) void k_world_scan(Dev d, TileScratch ts, int mode, int init, int only_world) {
   __shared__ uint32_t red[kScanThreads / 64 + 1];
   __shared__ unsigned long long red64[kScanThreads / 64];
   __shared__ double redf[kScanThreads / 64];
   __shared__ uint32_t s_cnt[kSlotPart + kCellPart];
   const uint32_t w = blockIdx.x;
   if (only_world >= 0 && (int)w != only_world) return;
-  const WorldParams wp = d.wp[w];
-  const uint32_t per = (wp.cap + kScanThreads - 1) / kScanThreads;
-  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, wp.cap);
-  uint32_t n = 0;
-  long long esum = 0;
-  double tsum = 0.0;
-  for (uint32_t s = lo; s < hi; ++s) {
-    const uint32_t g = wp.slot_off + s;
-    if (d.flags[g] & kAlive) {
-      ++n;
-      esum += d.energy[g];
-      tsum += d.trait[g];
+  const uint32_t t0 = ts.tile_rng[4 * w], t1 = ts.tile_rng[4 * w + 1];
+  const uint32_t nt = t1 - t0;
+  const uint32_t per = (nt + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = t0 + threadIdx.x * per, hi = min(lo + per, t1);
+  if (mode == 0) {
+    uint32_t nc = 0, nw = 0, nf = 0;
+    for (uint32_t t = lo; t < hi; ++t) {
+      nc += ts.scan[t * 4 + 0];
+      nw += ts.scan[t * 4 + 1];
+      nf += ts.scan[t * 4 + 2];
     }
+    uint32_t C, Wn, F;
+    uint32_t ow = block_exscan<kScanThreads>(nw, red, &Wn);
+    uint32_t of = block_exscan<kScanThreads>(nf, red, &F);
+    block_exscan<kScanThreads>(nc, red, &C);
+    for (uint32_t t = lo; t < hi; ++t) {
+      ts.off[t * 3 + 0] = ow;
+      ts.off[t * 3 + 1] = of;
+      ow += ts.scan[t * 4 + 1];
+      of += ts.scan[t * 4 + 2];
+    }
+    if (threadIdx.x == 0) {
+      const uint32_t nb = min(Wn, F);
+      d.wv[w].n_births = nb;
+      d.wv[w].n_win = Wn;
+      d.cnt[w].births = nb;
+      d.cnt[w].births_blocked_cell = C - Wn;
+      d.cnt[w].births_blocked_capacity = Wn - nb;
+    }
+    return;
+  }
+  uint32_t n = 0;
+  long long es = 0;
+  double s1 = 0.0, s2 = 0.0;
+  for (uint32_t t = lo; t < hi; ++t) {
+    n += ts.scan[t * 4 + 3];
+    es += ts.esum[t];
+    s1 += ts.tsum[t];
+    s2 += ts.tsq[t];
   }
   uint32_t N;
   uint32_t o = block_exscan<kScanThreads>(n, red, &N);
-  for (uint32_t s = lo; s < hi; ++s)
-    if (d.flags[wp.slot_off + s] & kAlive) d.live[wp.slot_off + o++] = (int)s;
-  const unsigned long long E = block_sum_u64<kScanThreads>((unsigned long long)esum, red64);
-  const double T = block_sum_f64<kScanThreads>(tsum, redf);
-  __shared__ double s_mean;
-  if (threadIdx.x == 0) s_mean = N ? T / (double)N : 0.0;
-  __syncthreads();
-  const double mean = s_mean;
-  double vsum = 0.0;
-  for (uint32_t s = lo; s < hi; ++s) {
-    const uint32_t g = wp.slot_off + s;
-    if (d.flags[g] & kAlive) {
-      const double dv = d.trait[g] - mean;
-      vsum += dv * dv;
-    }
+  for (uint32_t t = lo; t < hi; ++t) {
+    ts.off[t * 3 + 2] = o;
+    o += ts.scan[t * 4 + 3];
   }
-  const double V = block_sum_f64<kScanThreads>(vsum, redf);
-  // tile counters of this world
+  const unsigned long long E = block_sum_u64<kScanThreads>((unsigned long long)es, red64);
+  const double T1 = block_sum_f64<kScanThreads>(s1, redf);
+  const double T2 = block_sum_f64<kScanThreads>(s2, redf);
   if (threadIdx.x < kSlotPart + kCellPart) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   if (!init) {
-    const uint32_t st0 = tile_rng[4 * w], st1 = tile_rng[4 * w + 1];
-    const uint32_t ct0 = tile_rng[4 * w + 2], ct1 = tile_rng[4 * w + 3];
-    for (uint32_t i = threadIdx.x; i < (st1 - st0) * kSlotPart; i += blockDim.x)
-      atomicAdd(&s_cnt[i % kSlotPart], part_slot[st0 * kSlotPart + i]);
+    const uint32_t ct0 = ts.tile_rng[4 * w + 2], ct1 = ts.tile_rng[4 * w + 3];
+    for (uint32_t i = threadIdx.x; i < nt * kSlotPart; i += blockDim.x)
+      atomicAdd(&s_cnt[i % kSlotPart], ts.part_slot[t0 * kSlotPart + i]);
     for (uint32_t i = threadIdx.x; i < (ct1 - ct0) * kCellPart; i += blockDim.x)
-      atomicAdd(&s_cnt[kSlotPart + i % kCellPart], part_cell[ct0 * kCellPart + i]);
+      atomicAdd(&s_cnt[kSlotPart + i % kCellPart], ts.part_cell[ct0 * kCellPart + i]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -566,16 +623,14 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Dev d, const uint32_t*
       for (int a = 0; a < 8; ++a) st.action_hist[a] = s_cnt[PC_HIST + a];
       st.regrown = s_cnt[kSlotPart + 0];
       st.resource_total = s_cnt[kSlotPart + 1];
-    } else {
-      // resource total of the current grid (init / state writes)
-      st.resource_total = 0;
     }
+    const double mean = N ? T1 / (double)N : 0.0;
     v.n_live = N;
     st.step = v.step;
     st.population = N;
     st.energy_total = (double)(long long)E;
     st.trait_mean = mean;
-    st.trait_var = N ? V / (double)N : 0.0;
+    st.trait_var = N ? fmax(T2 / (double)N - mean * mean, 0.0) : 0.0;
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
 }
@@ -669,19 +724,25 @@ __global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
 // ---------------------------------------------------------------------------
 #define ECO_CHECK_LAUNCH() return hipGetLastError()
 
-hipError_t launch_move(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part) {
-  if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_move, dim3(nt), dim3(kSlotTile), 0, s, d, tiles, part);
+hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts) {
+  if (ts.n_slot_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts.slot_tiles, ts.part_slot);
   ECO_CHECK_LAUNCH();
 }
-hipError_t launch_birth_claim(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part,
-                              uint32_t A) {
-  if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_birth_claim, dim3(nt), dim3(kSlotTile), 0, s, d, tiles, part, A);
+hipError_t launch_birth_claim_regrow(hipStream_t s, const Dev& d, const TileScratch& ts, uint32_t A) {
+  const uint32_t nb = ts.n_slot_tiles + ts.n_cell_tiles;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_birth_claim_regrow, dim3(nb), dim3(256), 0, s, d, ts, A);
   ECO_CHECK_LAUNCH();
 }
-hipError_t launch_birth_scan(hipStream_t s, const Dev& d) {
-  hipLaunchKernelGGL(k_birth_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d);
+hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts) {
+  hipLaunchKernelGGL(k_birth_rank_count, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_world_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, ts, 0, 0, -1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_birth_rank_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks) {
@@ -690,15 +751,14 @@ hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uin
   else hipLaunchKernelGGL(k_birth_commit<2>, dim3(blocks), dim3(256), 0, s, d, L);
   ECO_CHECK_LAUNCH();
 }
-hipError_t launch_regrow(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt, uint32_t* part) {
-  if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_regrow, dim3(nt), dim3(256), 0, s, d, tiles, part);
-  ECO_CHECK_LAUNCH();
-}
-hipError_t launch_compact(hipStream_t s, const Dev& d, const uint32_t* part_slot, const uint32_t* part_cell,
-                          const uint32_t* tile_rng, int init, int only_world) {
-  hipLaunchKernelGGL(k_compact, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, part_slot, part_cell, tile_rng,
-                     init, only_world);
+hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world) {
+  hipLaunchKernelGGL(k_compact_count, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts, only_world);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_world_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, ts, 1, init, only_world);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts, only_world);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {
