@@ -35,9 +35,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True):
+def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True, launch=None):
     import torch
     w = eco.World(cfg)
+    if launch:
+        w.set_launch(*launch)
     tuned = w.autotune() if autotune else w.get_launch()
     w.set_flags(eco.RT_USE_GRAPH)
     w.step(warmup)
@@ -72,14 +74,32 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True):
     return res
 
 
-def roofline(r):
+def profiled_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the policy kernel's source changed since the counters were taken."""
+    from paper_2510_18221_amd import rocprof_summary
+    path = os.path.join(ROOT, "profiles", f"k_forward_{name}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("source_sha256") != rocprof_summary.forward_source_sha():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def roofline(r, profile_name=None):
     ms, n = r["kernel_times"]["forward"]
     avg_ms = ms / max(n, 1)
     agents_per_launch = r["agent_steps"] / max(n, 1)
     bytes_per_agent = r["info"]["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT
     gbs = agents_per_launch * bytes_per_agent / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic(profile_name) if profile_name else None,
             "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_agent": bytes_per_agent, "agents_per_launch": round(agents_per_launch, 1)}
 
@@ -114,6 +134,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 4 GiB device copy (PMC scaling)")
+    ap.add_argument("--launch", default=None, help="fixed policy-kernel launch 'waves_per_block,blocks_per_cu,unroll'")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: worlds shard across GPUs by design but no multi-GPU path is "
@@ -127,7 +148,9 @@ def main():
     eco.lib()
 
     log(f"[bench] 65k world FP32: warmup {args.warmup}, timed {args.steps}")
-    main_r = timed_run(eco, wl.world_65k(seed=0), args.steps, args.warmup, autotune=not args.no_autotune)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    autotune = not args.no_autotune and launch is None
+    main_r = timed_run(eco, wl.world_65k(seed=0), args.steps, args.warmup, autotune=autotune, launch=launch)
     value = main_r["agent_steps"] / main_r["seconds"]
     ms_per_step = main_r["seconds"] * 1e3 / main_r["steps"]
     log(f"[bench] fp32: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, launch {main_r['launch']}")
@@ -141,7 +164,7 @@ def main():
                                "full dynamics", "agents_start": main_r["pop_start"],
                    "agents_end": main_r["pop_end"], "births": main_r["births"], "deaths": main_r["deaths"],
                    "launch": main_r["launch"]},
-        "roofline": roofline(main_r),
+        "roofline": roofline(main_r, "65k_fp32"),
         "graph_ms_per_step": round(main_r.get("graph_ms_per_step", 0.0), 4),
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in main_r["kernel_times"].items()},
     }
@@ -150,7 +173,7 @@ def main():
         for name, cfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)), ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                           ("fp32_frozen", wl.world_65k(seed=0, frozen=True))]:
             log(f"[bench] variant {name}")
-            r = timed_run(eco, cfg, args.steps, args.warmup, autotune=not args.no_autotune, graph_compare=False)
+            r = timed_run(eco, cfg, args.steps, args.warmup, autotune=autotune, graph_compare=False, launch=launch)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
                               "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
