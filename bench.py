@@ -104,24 +104,25 @@ def roofline(r, profile_name=None):
             "bytes_per_agent": bytes_per_agent, "agents_per_launch": round(agents_per_launch, 1)}
 
 
-def cpu_baseline(n_agents=8192, steps=4):
-    """The oracle as it stands, on a bounded sample of the same world shape."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(min_seconds=10.0, max_steps=100):
+    """The oracle as it stands, on a bounded sample of the same workload: the
+    same 65,536-agent world (init not timed), stepped until ~10 s of CPU work."""
     from oracle import oracle as orc
     from paper_2510_18221_amd import workloads as wl
     cfg = wl.world_65k(seed=0)
-    cfg.update(n_agents_init=n_agents, capacity=2 * n_agents)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     w = orc.OracleWorld(cfg)
     pops = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    while len(pops) < max_steps and (time.perf_counter() - t0 < min_seconds or len(pops) < 2):
         pops.append(w.stats()["population"])
         w.step()
     dt = time.perf_counter() - t0
+    w.close()
     return {"value": round(sum(pops) / dt, 1), "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"1024x1024 world, 492->64->64->7 FP32 policy, {n_agents} agents (1/8 of the 65,536), "
-                      f"{steps} full steps after init, FP64 policy + sequential world, OpenMP over the policy loop",
+            "sample": f"the same 1024x1024 world with 65,536 agents, FP32 weights, {len(pops)} full steps "
+                      f"(policy sampled by the oracle) after an untimed init; FP64 policy with OpenMP over "
+                      f"agents, sequential world update",
             "seconds": round(dt, 2)}
 
 

@@ -418,9 +418,22 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
         w->age[j] = 0;
         w->uid[j] = j;
         w->puid[j] = UINT64_MAX;
-        if (seed_slot(w, j)) { free(ck); orc_destroy(w); return NULL; }
+        int64_t id = new_node(w, -1, 0, 0, j);
+        if (id < 0) { free(ck); orc_destroy(w); fail("out of memory"); return NULL; }
+        w->node[j] = id;
+        w->trait[j] = NAN;
     }
     free(ck);
+    /* Initial weights: independent per agent, so the loop runs in parallel. */
+    if (materialize) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t j = 0; j < (int64_t)d->n_agents_init; ++j) {
+            float* m = w->master + (uint64_t)j * w->P;
+            init_weights(w, (uint32_t)j, m);
+            w->trait[j] = sqnorm(m, w->P);
+            if (w->stored) quantize(w, m, w->stored + (uint64_t)j * w->P);
+        }
+    }
     w->uid_next = d->n_agents_init;
     w->step = 0;
     memset(&w->stats, 0, sizeof w->stats);

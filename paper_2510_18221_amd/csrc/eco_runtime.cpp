@@ -791,9 +791,12 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
   d.dry = 1;
   d.inject = 0;
   d.keep_logits = 0;
-  hipEvent_t a, b;
-  HIPCHK(w, hipEventCreate(&a), "event");
-  HIPCHK(w, hipEventCreate(&b), "event");
+  constexpr int kReps = 5;
+  hipEvent_t ev[kReps + 1];
+  for (auto& e : ev) HIPCHK(w, hipEventCreate(&e), "event");
+  auto destroy = [&] {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  };
   eco_launch chosen = w->launch;
   float best_ms = 1e30f;
   const uint32_t wpbs[] = {1, 2, 4, 8}, us[] = {4, 8, 16}, bpcs[] = {1, 2, 4, 8, 16};
@@ -804,21 +807,26 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
         if (forward_shmem(w, wpb) > 64 * 1024 || forward_shmem(w, wpb) * bpc > 160 * 1024) continue;
         const eco_launch lc{wpb, bpc, u, 0};
         hipError_t e = launch_forward(w, w->stream, d, lc);  // warm-up
-        if (e != hipSuccess) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); return dev_fail(w, e, "autotune launch"); }
-        HIPCHK(w, hipEventRecord(a, w->stream), "event");
-        const int reps = 3;
-        for (int r = 0; r < reps; ++r) (void)launch_forward(w, w->stream, d, lc);
-        HIPCHK(w, hipEventRecord(b, w->stream), "event");
-        HIPCHK(w, hipEventSynchronize(b), "event sync");
-        float ms = 0;
-        HIPCHK(w, hipEventElapsedTime(&ms, a, b), "elapsed");
-        if (ms < best_ms) {
-          best_ms = ms;
+        if (e == hipSuccess) e = hipEventRecord(ev[0], w->stream);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+          e = launch_forward(w, w->stream, d, lc);
+          if (e == hipSuccess) e = hipEventRecord(ev[r + 1], w->stream);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+        float t[kReps];
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
+        if (e != hipSuccess) {
+          destroy();
+          return dev_fail(w, e, "autotune");
+        }
+        std::sort(t, t + kReps);
+        const float med = t[kReps / 2];  // median launch time of this shape
+        if (med < best_ms) {
+          best_ms = med;
           chosen = lc;
         }
       }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  destroy();
   w->launch = chosen;
   drop_graph(w);
   if (best) *best = chosen;
