@@ -194,6 +194,8 @@ class World:
         if getattr(self, "_h", None):
             lib().eco_world_destroy(self._h)
             self._h = None
+            if self._allocator is not None:
+                self._allocator.torch.cuda.empty_cache()  # hand large blocks back for the next world
 
     def __del__(self):
         try:

@@ -52,9 +52,12 @@ def world_large(seed=0, wdtype=BF16):
 
 
 def batch_sides(n_worlds=64, seed=12345, lo=128, hi=1024):
-    """Square sides drawn log-uniform in [lo, hi] from a seeded numpy generator."""
+    """Square sides log-uniform in [lo, hi]: one draw per equal-probability
+    stratum (stratified sampling, so the batch total is close to its expected
+    value), in an order shuffled by a seeded numpy generator."""
     rng = np.random.default_rng(seed)
-    u = rng.random(n_worlds)
+    u = (np.arange(n_worlds) + rng.random(n_worlds)) / n_worlds
+    rng.shuffle(u)
     return [int(round(math.exp(math.log(lo) + x * math.log(hi / lo)))) for x in u]
 
 
