@@ -54,13 +54,17 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True, launch
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = w.kernel_times(reset=True)
-    hist = w.stats_history(0, steps + 1)
-    assert hist[-1]["step"] == s0 + steps
-    agent_steps = sum(h["population"] for h in hist[:-1])  # live at the start of each timed step
+    agent_steps = pop_start = pop_end = births = deaths = 0
+    for i in range(w.n_worlds):
+        hist = w.stats_history(i, steps + 1)
+        assert hist[-1]["step"] == s0 + steps
+        agent_steps += sum(h["population"] for h in hist[:-1])  # live at the start of each timed step
+        pop_start += hist[0]["population"]
+        pop_end += hist[-1]["population"]
+        births += sum(h["births"] for h in hist[1:])
+        deaths += sum(h["deaths"] for h in hist[1:])
     res = dict(seconds=t1 - t0, steps=steps, agent_steps=agent_steps, kernel_times=kt, launch=tuned,
-               pop_start=hist[0]["population"], pop_end=hist[-1]["population"],
-               births=sum(h["births"] for h in hist[1:]), deaths=sum(h["deaths"] for h in hist[1:]),
-               info=w.info)
+               pop_start=pop_start, pop_end=pop_end, births=births, deaths=deaths, info=w.info)
     if graph_compare:
         w.set_flags(eco.RT_USE_GRAPH)
         w.step(2)
@@ -72,6 +76,44 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, graph_compare=True, launch
     w.close()
     torch.cuda.empty_cache()
     return res
+
+
+def trajectory(eco, cfg, steps, chunk=1000, out_path=None):
+    """Long free-running run (graph replay): population and policy-kernel bandwidth per chunk."""
+    import torch
+    w = eco.World(cfg)
+    w.autotune()
+    rows = []
+    for c0 in range(0, steps, chunk):
+        n = min(chunk, steps - c0)
+        w.set_flags(eco.RT_USE_GRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w.step(n - 1)
+        w.set_flags(eco.RT_TIME_KERNELS)
+        w.kernel_times(reset=True)
+        w.step(1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = w.kernel_times(reset=True)
+        hist = w.stats_history(0, n + 1)
+        agent_steps = sum(h["population"] for h in hist[:-1])
+        fwd_ms = kt["forward"][0]
+        pop_last_start = hist[-2]["population"]
+        gbs = pop_last_start * (w.info["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT) / (fwd_ms * 1e-3) / 1e9
+        row = {"step": hist[-1]["step"], "population": hist[-1]["population"],
+               "births": sum(h["births"] for h in hist[1:]), "deaths": sum(h["deaths"] for h in hist[1:]),
+               "agent_steps_per_s": round(agent_steps / dt, 1), "ms_per_step": round(dt * 1e3 / n, 4),
+               "forward_GBps_last_step": round(gbs, 1),
+               "pop_min": min(h["population"] for h in hist), "pop_max": max(h["population"] for h in hist)}
+        rows.append(row)
+        log(f"[trajectory] {row}")
+    w.close()
+    torch.cuda.empty_cache()
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(rows, f, indent=1)
+    return rows
 
 
 def profiled_traffic(name):
@@ -126,16 +168,37 @@ def cpu_baseline(min_seconds=10.0, max_steps=100):
             "seconds": round(dt, 2)}
 
 
+WORKLOADS = {
+    "65k": ("single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, 11x11x4 window + 8 "
+            "scalars, per-agent 492->64->64->7 MLP, FP32 weights, full dynamics", "f32"),
+    "batch": ("64 independent worlds in one object (one graph per step), sides log-uniform in [128, 1024], 6.25% "
+              "occupancy (984,579 agents), capacity 1.125x, 492->64->64->7 BF16 weights + FP32 master", "bf16"),
+    "large": ("single world 2048x2048, capacity 262,144 starting half full, density 0.03, regrowth 0.005, "
+              "15x15x4 window + 8 scalars, 908->128->128->7 BF16 weights + FP32 master", "bf16"),
+}
+
+
+def workload_cfg(wl, name):
+    if name == "65k":
+        return wl.world_65k(seed=0)
+    if name == "batch":
+        return wl.world_batch(64)
+    return wl.world_large(seed=0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="65k")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 4 GiB device copy (PMC scaling)")
     ap.add_argument("--launch", default=None, help="fixed policy-kernel launch 'waves_per_block,blocks_per_cu,unroll'")
+    ap.add_argument("--trajectory", type=int, default=0, help="instead: free-run this many steps, report per 1000")
+    ap.add_argument("--trajectory-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: worlds shard across GPUs by design but no multi-GPU path is "
@@ -148,33 +211,39 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     eco.lib()
 
-    log(f"[bench] 65k world FP32: warmup {args.warmup}, timed {args.steps}")
+    cfg = workload_cfg(wl, args.workload)
+    if args.trajectory:
+        rows = trajectory(eco, cfg, args.trajectory, out_path=args.trajectory_out)
+        print(json.dumps({"workload": args.workload, "trajectory": rows}), flush=True)
+        return
+
+    log(f"[bench] {args.workload}: warmup {args.warmup}, timed {args.steps}")
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     autotune = not args.no_autotune and launch is None
-    main_r = timed_run(eco, wl.world_65k(seed=0), args.steps, args.warmup, autotune=autotune, launch=launch)
+    main_r = timed_run(eco, cfg, args.steps, args.warmup, autotune=autotune, launch=launch)
     value = main_r["agent_steps"] / main_r["seconds"]
     ms_per_step = main_r["seconds"] * 1e3 / main_r["steps"]
-    log(f"[bench] fp32: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, launch {main_r['launch']}")
+    log(f"[bench] {args.workload}: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, "
+        f"launch {main_r['launch']}")
+    desc, dtype = WORKLOADS[args.workload]
     out = {
         "metric": "agent-steps/s at 65,536 agents, FP32 vs BF16 weights; % of HBM peak",
         "value": round(value, 1), "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, "
-                               "11x11x4 window + 8 scalars, per-agent 492->64->64->7 MLP, FP32 weights, "
-                               "full dynamics", "agents_start": main_r["pop_start"],
-                   "agents_end": main_r["pop_end"], "births": main_r["births"], "deaths": main_r["deaths"],
-                   "launch": main_r["launch"]},
-        "roofline": roofline(main_r, "65k_fp32"),
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": desc, "agents_start": main_r["pop_start"], "agents_end": main_r["pop_end"],
+                   "births": main_r["births"], "deaths": main_r["deaths"], "launch": main_r["launch"]},
+        "roofline": roofline(main_r, "65k_fp32" if args.workload == "65k" else None),
         "graph_ms_per_step": round(main_r.get("graph_ms_per_step", 0.0), 4),
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in main_r["kernel_times"].items()},
     }
-    if not args.no_variants:
+    if args.workload == "65k" and not args.no_variants:
         variants = {}
-        for name, cfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)), ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
-                          ("fp32_frozen", wl.world_65k(seed=0, frozen=True))]:
+        for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
+                           ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
+                           ("fp32_frozen", wl.world_65k(seed=0, frozen=True))]:
             log(f"[bench] variant {name}")
-            r = timed_run(eco, cfg, args.steps, args.warmup, autotune=autotune, graph_compare=False, launch=launch)
+            r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, graph_compare=False, launch=launch)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
                               "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
@@ -188,7 +257,7 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if not args.no_cpu:
+    if args.workload == "65k" and not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
