@@ -119,9 +119,11 @@ typedef struct {
     uint32_t wdtype;
 } eco_info;
 
-/* Per-kernel GPU time accumulated while ECO_RT_TIME_KERNELS is set. */
+/* Per-kernel GPU time accumulated while ECO_RT_TIME_KERNELS is set.  SENSE is the
+   per-cell pass that builds the window channels before the policy kernel; REGROW
+   runs fused into the BIRTH_CLAIM launch and stays at zero. */
 enum { ECO_K_FORWARD = 0, ECO_K_MOVE = 1, ECO_K_BIRTH_CLAIM = 2, ECO_K_BIRTH_SCAN = 3,
-       ECO_K_BIRTH_COMMIT = 4, ECO_K_REGROW = 5, ECO_K_COMPACT = 6, ECO_K_COUNT = 7 };
+       ECO_K_BIRTH_COMMIT = 4, ECO_K_REGROW = 5, ECO_K_COMPACT = 6, ECO_K_SENSE = 7, ECO_K_COUNT = 8 };
 typedef struct {
     double ms[8];
     uint64_t launches[8];
@@ -184,7 +186,8 @@ eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions);
 size_t eco_world_state_bytes(const eco_world* w, uint32_t world);
 eco_status eco_world_read_state(eco_world* w, uint32_t world, void* buf, size_t bytes);
 /* Replace the integer state; slots alive in buf but not before get the
- * initial weights of their slot index.  Must keep occ consistent with pos. */
+ * initial weights of their slot index.  Must keep occ consistent with pos;
+ * res and wall hold 0 or 1 per cell (ECO_EINVAL otherwise). */
 eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, size_t bytes);
 
 /* FP32 logits of the last step's forward, [cap][n_actions]; NaN for slots not

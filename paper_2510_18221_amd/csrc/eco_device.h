@@ -7,7 +7,8 @@
 //     act u8 (action applied), sampled u8 (policy's choice), act_in u8 (injected),
 //     uid u64, puid u64, trait f64 (|theta_master|^2)
 //   per cell (global cell = world.cell_off + y*W + x):
-//     occ i32 (local slot or -1), claim u32 (lowest claiming global slot), res u8, wall u8
+//     occ i32 (local slot or -1), claim u32 (lowest claiming global slot), res u8, wall u8,
+//     sense u8 (the cell's window channels at step start, built before the policy kernel)
 //   weights: storage[slot][storage_stride bytes] in the blocked layout below,
 //            master[slot][master_stride bytes] FP32 (BF16/FP8 only; FP32 storage is the master)
 //   per world: live list segment live[slot_off ..], birth lists, WorldVar, stats ring.
@@ -93,6 +94,7 @@ struct Dev {
   int32_t* occ;
   uint32_t* claim;
   uint8_t *res, *wall;
+  uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
   uint8_t* store;               // [total_slots][sstride]
   uint8_t* master;              // [total_slots][mstride] or == store for FP32
   int32_t* live;                // [total_slots], per-world segments at slot_off

@@ -10,7 +10,9 @@
 //     window around the agent, rotated so the agent faces the top row, four
 //     channels per cell (agent present, resource, wall, occupant energy bin),
 //     then the scalar sensors (energy, age, resource here, reproduction
-//     eligibility, and the 4-way compass when n_s = 8).  Written to LDS.
+//     eligibility, and the 4-way compass when n_s = 8).  Written to LDS.  The
+//     four channels of a cell come from its sense byte, built for the step by
+//     a per-cell pass before this kernel.
 //  2. h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), l = W3 h2 + b3 (Sec. 3.3).
 //     The weights of a layer are stored as 16-byte blocks [k-block][row]; lane
 //     l streams block it*64+l, so every load instruction of the wave reads one
@@ -267,16 +269,9 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
       if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
       if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
       const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
-      const int o = d.occ[cell];
-      const float rs = (float)d.res[cell];
-      const float wl = wp.has_walls ? (float)d.wall[cell] : 0.0f;
-      int eb = 0;
-      if (o >= 0) {
-        const long long e8 = (long long)d.energy[wp.slot_off + o] * 8;
-#pragma unroll
-        for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1 : 0;
-      }
-      reinterpret_cast<float4*>(xs)[i] = make_float4(o >= 0 ? 1.0f : 0.0f, rs, wl, (float)eb);
+      const uint32_t sv = d.sense[cell];  // agent | resource | wall | energy bin, built for this step
+      reinterpret_cast<float4*>(xs)[i] =
+          make_float4((float)(sv & 1u), (float)((sv >> 1) & 1u), (float)((sv >> 2) & 1u), (float)(sv >> 3));
     }
     if (lane < (int)L.ns) {
       float v;

@@ -28,6 +28,7 @@ hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts)
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
+hipError_t launch_cell_sense(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
@@ -343,6 +344,7 @@ eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
     return hipSuccess;
   };
   if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
+  HIPCHK(w, run(ECO_K_SENSE, [&] { return launch_cell_sense(s, d, w->ts); }), "cell sense kernel");
   HIPCHK(w, run(ECO_K_FORWARD, [&] { return launch_forward(w, s, d, w->launch); }), "forward kernel");
   HIPCHK(w, run(ECO_K_MOVE, [&] { return launch_move(s, d, w->ts); }), "move kernel");
   HIPCHK(w, run(ECO_K_BIRTH_CLAIM, [&] { return launch_birth_claim_regrow(s, d, w->ts, w->L.A); }),
@@ -548,6 +550,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.claim = (uint32_t*)A(4 * TC);
   d.res = (uint8_t*)A(TC);
   d.wall = (uint8_t*)A(TC);
+  d.sense = (uint8_t*)A(TC);
   d.live = (int32_t*)A(4 * TS);
   d.bparent = (int32_t*)A(4 * TS);
   d.freel = (int32_t*)A(4 * TS);
@@ -799,6 +802,10 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
   };
   eco_launch chosen = w->launch;
   float best_ms = 1e30f;
+  if (hipError_t e = launch_cell_sense(w->stream, d, w->ts); e != hipSuccess) {
+    destroy();
+    return dev_fail(w, e, "autotune");
+  }
   const uint32_t wpbs[] = {1, 2, 4, 8}, us[] = {4, 8, 16}, bpcs[] = {1, 2, 4, 8, 16};
   for (uint32_t wpb : wpbs)
     for (uint32_t u : us)
@@ -916,9 +923,13 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
     if (o < -1 || o >= (int32_t)cap || (o >= 0 && (!alive_new[o] || pos[o] != (int32_t)c)))
       return fail(ECO_EINVAL, "occ/pos mismatch");
   }
-  const uint8_t* wall = q + cap * 28 + cells * 4 + 3 * cap + cells;
+  const uint8_t* res = q + cap * 28 + cells * 4 + 3 * cap;
+  const uint8_t* wall = res + cells;
   bool walls = false;
-  for (size_t c = 0; c < cells; ++c) walls |= wall[c] != 0;
+  for (size_t c = 0; c < cells; ++c) {
+    if (res[c] > 1 || wall[c] > 1) return fail(ECO_EINVAL, "res and wall must be 0 or 1");
+    walls |= wall[c] != 0;
+  }
   std::vector<uint8_t> old(cap);
   hipStream_t s = w->stream;
   HIPCHK(w, hipMemcpyAsync(old.data(), w->d.flags + p.slot_off, cap, hipMemcpyDeviceToHost, s), "read flags");

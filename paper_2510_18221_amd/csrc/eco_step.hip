@@ -719,6 +719,45 @@ __global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
   }
 }
 
+// Window channels of every cell at the start of a step (Sec. 3.2 sensors, App. F
+// layout), one byte per cell: bit 0 agent present, bit 1 resource present, bit 2
+// wall (worlds with walls only), bits 3..5 the occupant's energy bin
+// min(floor(8 E / e_repro), 7).  The policy kernel's window gather then reads one
+// byte per cell instead of the occupancy, resource and wall arrays plus a
+// dependent read of each occupant's energy.  Threads take 4 consecutive cells
+// (cell_off and tile starts are multiples of 4); a ragged tail goes cell by cell.
+__device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d, int o, uint32_t r, uint32_t wl) {
+  uint32_t v = (r != 0 ? 2u : 0u) | (wp.has_walls && wl != 0 ? 4u : 0u);
+  if (o >= 0) {
+    const long long e8 = (long long)d.energy[wp.slot_off + (uint32_t)o] * 8;
+    uint32_t eb = 0;
+#pragma unroll
+    for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1u : 0u;
+    v |= 1u | (eb << 3);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_cell_sense(Dev d, const Tile* tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
+    const uint32_t cell = wp.cell_off + tl.start + i;
+    if (i + 4 <= tl.count) {
+      const int4 o = *reinterpret_cast<const int4*>(d.occ + cell);
+      const uint32_t r = *reinterpret_cast<const uint32_t*>(d.res + cell);
+      const uint32_t wl = *reinterpret_cast<const uint32_t*>(d.wall + cell);
+      const uint32_t v = sense_of(wp, d, o.x, r & 0xFFu, wl & 0xFFu) | sense_of(wp, d, o.y, (r >> 8) & 0xFFu, (wl >> 8) & 0xFFu) << 8 |
+                         sense_of(wp, d, o.z, (r >> 16) & 0xFFu, (wl >> 16) & 0xFFu) << 16 |
+                         sense_of(wp, d, o.w, r >> 24, wl >> 24) << 24;
+      *reinterpret_cast<uint32_t*>(d.sense + cell) = v;
+    } else {
+      for (uint32_t c = cell; c < wp.cell_off + tl.start + tl.count; ++c)
+        d.sense[c] = (uint8_t)sense_of(wp, d, d.occ[c], d.res[c], d.wall[c]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (used by eco_runtime.cpp)
 // ---------------------------------------------------------------------------
@@ -759,6 +798,11 @@ hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, in
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts, only_world);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_cell_sense(hipStream_t s, const Dev& d, const TileScratch& ts) {
+  if (ts.n_cell_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_sense, dim3(ts.n_cell_tiles), dim3(256), 0, s, d, ts.cell_tiles);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libeco.so")
 
 ECO_OK, ECO_EINVAL, ECO_ENOMEM, ECO_EDEVICE, ECO_ESTATE, ECO_ENOTSUP = 0, -1, -2, -3, -4, -5
 RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS = 1, 2, 4
-KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact"]
+KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact", "sense"]
 
 EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world_step", "eco_world_reset",
            "eco_world_stats", "eco_world_stats_history", "eco_world_info", "eco_world_set_flags",

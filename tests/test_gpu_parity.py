@@ -251,6 +251,12 @@ def test_errors(eco):
     st["occ"][:] = -1
     with pytest.raises(eco.EcoError):
         gw.write_state(st)
+    for field in ("res", "wall"):  # cells hold 0 or 1 of each (the sense byte has one bit per channel)
+        st = gw.read_state()
+        st[field][7] = 2
+        with pytest.raises(eco.EcoError) as e:
+            gw.write_state(st)
+        assert e.value.status == eco.ECO_EINVAL
     gw.step(2)
     assert gw.stats()[0]["step"] == 2
     gw.close()
