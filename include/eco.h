@@ -72,7 +72,7 @@ typedef struct {
     float resource_density;      /* initial P(cell holds one resource unit) */
     float regrow_prob;           /* per-step P(empty cell regrows one unit) */
     float mutation_sigma;        /* std of the child's Gaussian weight noise */
-    uint32_t window;             /* S, odd, S <= width, S <= height */
+    uint32_t window;             /* S, odd, S <= width, S <= height, S <= 15 (ECO_ENOTSUP above) */
     uint32_t n_scalars;          /* 4 (internal+external) or 8 (+compass) */
     uint32_t hidden1, hidden2;   /* each 32, 64 or 128 */
     uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack) */

@@ -224,6 +224,102 @@ __device__ __forceinline__ void world_offsets(const WorldVar* __restrict__ wv, u
   __syncthreads();
 }
 
+// Wave-uniform loads through the scalar cache.  None of these words is written by
+// this kernel before the agent they belong to is processed (turns write only the
+// processed agent's facing byte), so the scalar cache cannot return a stale value.
+template <typename T>
+__device__ __forceinline__ T sload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ WorldParams sload_params(const WorldParams* p) {
+  static_assert(sizeof(WorldParams) % 4 == 0, "word-sized params");
+  WorldParams r;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&r);
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(WorldParams) / 4); ++i) o[i] = sload(q + i);
+  return r;
+}
+
+// Uniform description of one agent of the wave's chunk.
+struct AgentCtx {
+  WorldParams wp;
+  uint32_t w, local, slot, step;
+  int pos, facing, energy, age;
+};
+
+// Agent g of the step's live list (woff in LDS: exclusive world offsets); w is a
+// world index not past g's world.
+__device__ __forceinline__ AgentCtx load_agent(const Dev& d, const uint32_t* woff, uint32_t g, uint32_t w) {
+  while (g >= uni(woff[w + 1])) ++w;
+  AgentCtx c;
+  c.w = w;
+  c.wp = sload_params(d.wp + w);
+  c.local = (uint32_t)sload(d.live + c.wp.slot_off + (g - uni(woff[w])));
+  c.slot = c.wp.slot_off + c.local;
+  c.step = (uint32_t)sload(&d.wv[w].step);
+  c.pos = sload(d.pos + c.slot);
+  c.energy = sload(d.energy + c.slot);
+  c.age = sload(d.age + c.slot);
+  const uint32_t fw = sload(reinterpret_cast<const uint32_t*>(d.facing + (c.slot & ~3u)));
+  c.facing = (int)((fw >> (8 * (c.slot & 3u))) & 0xFFu);
+  return c;
+}
+
+constexpr int kMaxWindowCellsPerLane = 4;  // S <= 15: S*S <= 256 cells over 64 lanes
+
+// Sense bytes of agent c's window (Sec. 3.2 sensors, App. F layout): lane owns
+// window cells lane + 64k, row r = i / S counted from the far front, column from
+// the agent's left; the window is rotated so the agent faces row 0.
+__device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, const AgentCtx& c, int lane,
+                                             uint32_t (&sv)[kMaxWindowCellsPerLane]) {
+  const WorldParams& wp = c.wp;
+  const int S = (int)L.S, R = (int)L.R, SS = S * S;
+  const int ax = c.pos % (int)wp.W, ay = c.pos / (int)wp.W;
+  const int dx = dir_dx(c.facing), dy = dir_dy(c.facing), rx = -dy, ry = dx;
+#pragma unroll
+  for (int k = 0; k < kMaxWindowCellsPerLane; ++k) {
+    const int i = lane + 64 * k;
+    sv[k] = 0;
+    if (i < SS) {
+      const int r = i / S, col = i - r * S;
+      const int fw = R - r, rt = col - R;
+      int cx = ax + fw * dx + rt * rx, cy = ay + fw * dy + rt * ry;
+      if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
+      if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
+      sv[k] = d.sense[wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx];
+    }
+  }
+}
+
+// Observation of agent c into LDS xs[0..D): four channels per window cell
+// (agent, resource, wall, energy bin) unpacked from its sense byte, then the
+// scalars (energy, age, resource here, eligibility, compass when n_s = 8).
+__device__ __forceinline__ void write_observation(const Layout& L, const AgentCtx& c, int lane,
+                                                  const uint32_t (&sv)[kMaxWindowCellsPerLane], float* xs) {
+  const int SS = (int)(L.S * L.S);
+#pragma unroll
+  for (int k = 0; k < kMaxWindowCellsPerLane; ++k) {
+    const int i = lane + 64 * k;
+    if (i < SS)
+      reinterpret_cast<float4*>(xs)[i] = make_float4((float)(sv[k] & 1u), (float)((sv[k] >> 1) & 1u),
+                                                     (float)((sv[k] >> 2) & 1u), (float)(sv[k] >> 3));
+  }
+  wave_sync();
+  if (lane < (int)L.ns) {
+    const int centre = (int)(L.R * L.S + L.R);  // the agent's own cell
+    float v;
+    if (lane == 0) v = ldexpf((float)c.energy, -8);
+    else if (lane == 1) v = ldexpf((float)min(c.age, 1024), -10);
+    else if (lane == 2) v = xs[4 * centre + 1];  // resource here: the centre cell's resource channel
+    else if (lane == 3) v = (c.energy >= c.wp.e_repro) ? 1.0f : 0.0f;
+    else v = (lane - 4 == c.facing) ? 1.0f : 0.0f;
+    xs[4 * SS + lane] = v;
+  }
+  wave_sync();
+}
+
 template <int WDT, int H, int U>
 __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
   constexpr int VPL = WTraits<WDT>::VPL;
@@ -246,52 +342,34 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
   const uint32_t g_lo = gw * chunk, g_hi = min(g_lo + chunk, total);
   if (g_lo >= g_hi) return;
 
-  const int S = (int)L.S, R = (int)L.R, SS = S * S;
-  uint32_t w = find_world(woff, d.n_worlds, g_lo);
-  for (uint32_t g = g_lo; g < g_hi; ++g) {
-    while (g >= woff[w + 1]) ++w;
-    const WorldParams wp = d.wp[w];
-    const uint32_t step = (uint32_t)d.wv[w].step;
-    const uint32_t local = (uint32_t)d.live[wp.slot_off + (g - woff[w])];
-    const uint32_t slot = wp.slot_off + local;
+  const int A = (int)L.A;
+  // Window cell ahead of the agent (row R-1, column R), when the window has one:
+  // the move claim reads its agent and wall channels from the observation.
+  const int front = (L.R >= 1) ? (int)((L.R - 1) * L.S + L.R) : -1;
 
-    // ---- 1. observation into LDS ----
-    const int pos = d.pos[slot];
-    const int f = d.facing[slot];
-    const int E = d.energy[slot];
-    const int age = d.age[slot];
-    const int ax = pos % (int)wp.W, ay = pos / (int)wp.W;
-    const int dx = dir_dx(f), dy = dir_dy(f), rx = -dy, ry = dx;
-    for (int i = lane; i < SS; i += 64) {
-      const int r = i / S, c = i - r * S;
-      const int fw = R - r, rt = c - R;
-      int cx = ax + fw * dx + rt * rx, cy = ay + fw * dy + rt * ry;
-      if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
-      if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
-      const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
-      const uint32_t sv = d.sense[cell];  // agent | resource | wall | energy bin, built for this step
-      reinterpret_cast<float4*>(xs)[i] =
-          make_float4((float)(sv & 1u), (float)((sv >> 1) & 1u), (float)((sv >> 2) & 1u), (float)(sv >> 3));
+  AgentCtx cur = load_agent(d, woff, g_lo, find_world(woff, d.n_worlds, g_lo));
+  uint32_t sv[kMaxWindowCellsPerLane];
+  gather_sense(d, L, cur, lane, sv);
+  for (uint32_t g = g_lo; g < g_hi; ++g) {
+    const WorldParams& wp = cur.wp;
+    // ---- 1. observation into LDS (window bytes fetched one agent ahead) ----
+    write_observation(L, cur, lane, sv, xs);
+    // the next agent's context and window bytes, in flight while this agent streams
+    const bool has_next = g + 1 < g_hi;
+    AgentCtx nxt = cur;
+    uint32_t sn[kMaxWindowCellsPerLane];
+    if (has_next) {
+      nxt = load_agent(d, woff, g + 1, cur.w);
+      gather_sense(d, L, nxt, lane, sn);
     }
-    if (lane < (int)L.ns) {
-      float v;
-      if (lane == 0) v = ldexpf((float)E, -8);
-      else if (lane == 1) v = ldexpf((float)min(age, 1024), -10);
-      else if (lane == 2) v = (float)d.res[wp.cell_off + pos];
-      else if (lane == 3) v = (E >= wp.e_repro) ? 1.0f : 0.0f;
-      else v = (lane - 4 == f) ? 1.0f : 0.0f;
-      xs[4 * SS + lane] = v;
-    }
-    wave_sync();
 
     // ---- 2. the agent's MLP, weights streamed once from HBM ----
-    const uint8_t* wbase = d.store + (uint64_t)slot * L.sstride;
+    const uint8_t* wbase = d.store + (uint64_t)cur.slot * L.sstride;
     hidden_layer<WDT, H, U>(wbase, L.s_w1, L.s_b1, L.s_sc1, (int)L.KBv, xs, h1s, lane);
     hidden_layer<WDT, H, U>(wbase, L.s_w2, L.s_b2, L.s_sc2, H / VPL, h1s, h2s, lane);
     const float lg = output_layer<WDT, H>(wbase, L, h2s, lane);
 
     // ---- 3. softmax inverse-CDF sample ----
-    const int A = (int)L.A;
     float l[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) l[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lg), 8 * a));
@@ -306,7 +384,7 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
       accum += wk[a];
       C[a] = accum;
     }
-    const uint32_t x0 = draw32(wp, local, step, ST_ACTION);
+    const uint32_t x0 = draw32(wp, cur.local, cur.step, ST_ACTION);
     const float u = (float)(x0 >> 8) * 0x1p-24f;
     const float t = u * C[A - 1];
     int as = -1;
@@ -320,24 +398,36 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
     }
 
     // ---- 4. bookkeeping, turn, move claim (lane 0) ----
+    const uint32_t slot = cur.slot;
     if (d.keep_logits && (lane & 7) == 0) d.logits[(uint64_t)slot * 8 + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
     if (lane == 0 && d.dry) d.sampled[slot] = (uint8_t)as;
     if (lane == 0 && !d.dry) {
       const int a = d.inject ? (int)d.act_in[slot] : as;
+      const int f = cur.facing;
       d.sampled[slot] = (uint8_t)as;
       d.act[slot] = (uint8_t)a;
       int tg = -1;
       if (a == TURN_L) d.facing[slot] = (uint8_t)((f + 3) & 3);
       else if (a == TURN_R) d.facing[slot] = (uint8_t)((f + 1) & 3);
       else if (a == FORWARD) {
-        const uint32_t tc = neighbour(wp, (uint32_t)pos, f, +1);
-        const bool walled = wp.has_walls && d.wall[wp.cell_off + tc];
-        if (d.occ[wp.cell_off + tc] == -1 && !walled) {
+        const uint32_t tc = neighbour(wp, (uint32_t)cur.pos, f, +1);
+        bool free_cell;
+        if (front >= 0) {  // the observation holds the cell ahead as seen at step start
+          free_cell = xs[4 * front] == 0.0f && xs[4 * front + 2] == 0.0f;
+        } else {
+          free_cell = d.occ[wp.cell_off + tc] == -1 && !(wp.has_walls && d.wall[wp.cell_off + tc]);
+        }
+        if (free_cell) {
           atomicMin(&d.claim[wp.cell_off + tc], slot);
           tg = (int)tc;
         }
       }
       d.tgt[slot] = tg;
+    }
+    if (has_next) {
+      cur = nxt;
+#pragma unroll
+      for (int k = 0; k < kMaxWindowCellsPerLane; ++k) sv[k] = sn[k];
     }
   }
 }

@@ -156,6 +156,7 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if ((uint64_t)d.n_agents_init > (uint64_t)d.width * d.height) return bad(ECO_EINVAL, "n_agents_init", "exceeds cells");
   if (d.window < 1 || d.window % 2 == 0) return bad(ECO_EINVAL, "window", "must be odd");
   if (d.window > d.width || d.window > d.height) return bad(ECO_EINVAL, "window", "larger than the grid");
+  if (d.window > 15) return bad(ECO_ENOTSUP, "window", "above 15 has no policy kernel");
   if (d.n_scalars != 4 && d.n_scalars != 8) return bad(ECO_EINVAL, "n_scalars", "must be 4 or 8");
   if (d.n_actions != 5 && d.n_actions != 7) return bad(ECO_EINVAL, "n_actions", "must be 5 or 7");
   if (d.e_repro <= 0) return bad(ECO_EINVAL, "e_repro", "must be > 0");

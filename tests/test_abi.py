@@ -37,7 +37,8 @@ def test_validation_errors_without_device():
     assert lib.eco_world_create(None, 0, None, None, ctypes.byref(out)) == eco.ECO_EINVAL
     for bad, status in [(dict(window=4), eco.ECO_EINVAL), (dict(n_scalars=3), eco.ECO_EINVAL),
                         (dict(hidden1=48, hidden2=48), eco.ECO_ENOTSUP), (dict(attack_enabled=1), eco.ECO_ENOTSUP),
-                        (dict(capacity=10), eco.ECO_EINVAL), (dict(e_repro=0), eco.ECO_EINVAL)]:
+                        (dict(capacity=10), eco.ECO_EINVAL), (dict(e_repro=0), eco.ECO_EINVAL),
+                        (dict(window=17), eco.ECO_ENOTSUP)]:
         d = (eco.Desc * 1)(eco.make_desc(wl.desc(**bad)))
         assert lib.eco_world_create(d, 1, None, None, ctypes.byref(out)) == status, bad
         assert lib.eco_last_error()
