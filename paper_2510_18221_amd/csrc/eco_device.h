@@ -117,7 +117,7 @@ struct Tile {
 };
 
 // Per-tile scratch of the multi-block passes (slot tiles of 256 slots, cell
-// tiles of 4096 cells; a world's tiles are contiguous: tile_rng[4w..4w+3] =
+// tiles of 1024 cells; a world's tiles are contiguous: tile_rng[4w..4w+3] =
 // first/last slot tile, first/last cell tile).
 struct TileScratch {
   const Tile* slot_tiles;

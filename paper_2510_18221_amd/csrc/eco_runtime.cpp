@@ -44,7 +44,7 @@ using namespace eco;
 namespace {
 
 constexpr uint32_t kSlotTileH = 256;
-constexpr uint32_t kCellTileH = 4096;
+constexpr uint32_t kCellTileH = 1024;
 constexpr uint32_t kSlotPartH = 16;
 constexpr uint32_t kCellPartH = 2;
 constexpr uint32_t kMaxWorldsH = 1024;

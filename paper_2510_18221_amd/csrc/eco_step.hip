@@ -21,7 +21,7 @@
 namespace eco {
 
 constexpr int kSlotTile = 256;   // slots per block in per-slot kernels
-// Cell tiles (4096 cells each) are built on the host; per-cell kernels take one tile per block.
+// Cell tiles (1024 cells each) are built on the host; per-cell kernels take one tile per block.
 constexpr int kScanThreads = 1024;
 constexpr int kSlotPart = 16;    // u32 counters per slot tile
 constexpr int kCellPart = 2;     // u32 counters per cell tile
