@@ -119,9 +119,9 @@ typedef struct {
     uint32_t wdtype;
 } eco_info;
 
-/* Per-kernel GPU time accumulated while ECO_RT_TIME_KERNELS is set.  SENSE is the
-   per-cell pass that builds the window channels before the policy kernel; REGROW
-   runs fused into the BIRTH_CLAIM launch and stays at zero. */
+/* Per-kernel GPU time accumulated while ECO_RT_TIME_KERNELS is set.  REGROW runs
+   fused into the BIRTH_CLAIM launch and SENSE (the per-cell window channels for
+   the next step) into the COMPACT launch; both stay at zero. */
 enum { ECO_K_FORWARD = 0, ECO_K_MOVE = 1, ECO_K_BIRTH_CLAIM = 2, ECO_K_BIRTH_SCAN = 3,
        ECO_K_BIRTH_COMMIT = 4, ECO_K_REGROW = 5, ECO_K_COMPACT = 6, ECO_K_SENSE = 7, ECO_K_COUNT = 8 };
 typedef struct {
@@ -132,7 +132,10 @@ typedef struct {
 /* Runtime flags (eco_world_set_flags). */
 #define ECO_RT_KEEP_LOGITS 1u   /* forward writes FP32 logits for read_logits */
 #define ECO_RT_USE_GRAPH 2u     /* eco_world_step replays a captured hipGraph (default on) */
-#define ECO_RT_TIME_KERNELS 4u  /* eager launches bracketed by hipEvents per kernel */
+#define ECO_RT_TIME_KERNELS 4u  /* hipEvents around every kernel group of eager launches; with
+                                   ECO_RT_USE_GRAPH, event-record nodes around the policy kernel
+                                   only, in a graph of the n steps of each eco_world_step call (one
+                                   graph kept per n).  The call synchronises to read the times. */
 
 /* Create n_worlds worlds (all with the same window, n_scalars, hidden sizes,
  * n_actions and wdtype) and run the deterministic init of Sec. 3.3 / placement.
@@ -144,8 +147,14 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
 void eco_world_destroy(eco_world* w);
 const char* eco_last_error(void);
 
-/* Advance every world by n_steps whole steps (asynchronous). */
+/* Advance every world by n_steps whole steps (asynchronous, except that
+ * ECO_RT_TIME_KERNELS synchronises at the end to read its timers). */
 eco_status eco_world_step(eco_world* w, uint32_t n_steps);
+/* Build, without running it, the graph eco_world_step(w, n_steps) replays under
+ * the current flags (the one-step graph, or the timed graph of n_steps), so the
+ * capture stays out of a caller's timed region.  No-op without ECO_RT_USE_GRAPH.
+ * A later eco_world_set_flags or eco_world_set_launch drops the built graphs. */
+eco_status eco_world_prepare(eco_world* w, uint32_t n_steps);
 
 /* Re-initialise every world; seeds = NULL keeps each world's seed, else
  * seeds[n_worlds] replaces them.  Clears ECO_ESTATE on success. */
@@ -163,8 +172,9 @@ eco_status eco_world_set_flags(eco_world* w, uint32_t flags);
 eco_status eco_world_set_launch(eco_world* w, const eco_launch* launch);
 eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
 /* Time every candidate launch shape on the forward pass of the current state
- * (the forward has no side effect on the world) and keep the fastest.  Every
- * candidate produces bit-identical actions.  *best may be NULL. */
+ * (the forward has no side effect on the world) in five rounds over all shapes
+ * and keep the shape with the lowest median.  Every candidate produces
+ * bit-identical actions.  *best may be NULL. */
 eco_status eco_world_autotune(eco_world* w, eco_launch* best);
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);
 

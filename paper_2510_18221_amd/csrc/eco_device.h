@@ -127,7 +127,6 @@ struct TileScratch {
   uint32_t* part_slot;   // [slot tiles][16] step counters (actions, moves, meals, deaths, blocked births)
   uint32_t* part_cell;   // [cell tiles][2] regrown, resource total
   uint32_t* scan;        // [slot tiles][4] claims, winners, free slots, live slots
-  uint32_t* off;         // [slot tiles][3] world-exclusive offsets: winners, free slots, live slots
   long long* esum;       // [slot tiles] energy sum of live slots
   double* tsum;          // [slot tiles] trait sum
   double* tsq;           // [slot tiles] trait sum of squares

@@ -451,4 +451,14 @@ hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 
 #undef ECO_CASE
   return hipErrorInvalidValue;
 }
+// The kernel a launch of this storage type with (H, U) runs (graph nodes name it).
+const void* ECO_CAT(forward_kernel_w, ECO_FWD_WDT)(int H, int U) {
+#define ECO_FN(HH, UU) \
+  if (H == HH && U == UU) return reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU>);
+  ECO_FN(32, 4) ECO_FN(32, 8) ECO_FN(32, 16)
+  ECO_FN(64, 4) ECO_FN(64, 8) ECO_FN(64, 16)
+  ECO_FN(128, 4) ECO_FN(128, 8) ECO_FN(128, 16)
+#undef ECO_FN
+  return nullptr;
+}
 }  // namespace eco

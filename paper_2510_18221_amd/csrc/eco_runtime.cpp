@@ -20,6 +20,9 @@ hipError_t launch_forward_w0(int H, int U, dim3 grid, dim3 block, size_t shmem, 
                              const Layout& L);
 hipError_t launch_forward_w1(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
+const void* forward_kernel_w0(int H, int U);
+const void* forward_kernel_w1(int H, int U);
+const void* forward_kernel_w2(int H, int U);
 hipError_t launch_forward_w2(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
 hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
@@ -28,7 +31,6 @@ hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts)
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
-hipError_t launch_cell_sense(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
@@ -102,6 +104,16 @@ struct eco_world {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   size_t ev_used = 0;
+  // Graphs of n whole steps with event-record nodes around every policy-kernel
+  // launch (ECO_RT_TIME_KERNELS together with ECO_RT_USE_GRAPH), one per n used.
+  struct TimedGraph {
+    uint32_t n = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pairs;
+  };
+  std::vector<TimedGraph> tgraphs;
   eco_kernel_times kt{};
   uint64_t device_bytes = 0;
 };
@@ -324,36 +336,49 @@ hipEvent_t take_event(eco_world* w) {
   return w->ev_pool[w->ev_used++];
 }
 
-// Enqueue one step's kernels.  timed: bracket each kernel with events.
+// Kernel groups of one step, in order (each id names one timed group).
+// (The sense bytes the policy kernel reads are built by the previous step's
+// compaction launch, or by init and state writes.)
+constexpr int kStepGroups[] = {ECO_K_FORWARD,    ECO_K_MOVE,         ECO_K_BIRTH_CLAIM,
+                               ECO_K_BIRTH_SCAN, ECO_K_BIRTH_COMMIT, ECO_K_COMPACT};
+const char* group_name(int k) {
+  switch (k) {
+    case ECO_K_FORWARD: return "forward kernel";
+    case ECO_K_MOVE: return "move kernel";
+    case ECO_K_BIRTH_CLAIM: return "birth claim / regrowth kernel";
+    case ECO_K_BIRTH_SCAN: return "birth ranking kernels";
+    case ECO_K_BIRTH_COMMIT: return "birth commit kernel";
+    default: return "compaction kernels";
+  }
+}
+hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, int k) {
+  switch (k) {
+    case ECO_K_FORWARD: return launch_forward(w, s, d, w->launch);
+    case ECO_K_MOVE: return launch_move(s, d, w->ts);
+    case ECO_K_BIRTH_CLAIM: return launch_birth_claim_regrow(s, d, w->ts, w->L.A);
+    case ECO_K_BIRTH_SCAN: return launch_birth_rank(s, d, w->ts);
+    case ECO_K_BIRTH_COMMIT: return launch_birth_commit(s, d, w->L, emit_blocks(w));
+    default: return launch_compact(s, d, w->ts, 0, -1);
+  }
+}
+
+// Enqueue one step's kernels.  timed: bracket each kernel group with events.
 eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
-  auto run = [&](int k, auto&& fn) -> hipError_t {
+  if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
+  for (int k : kStepGroups) {
     hipEvent_t a = nullptr, b = nullptr;
     if (timed) {
       a = take_event(w);
       b = take_event(w);
-      if (!a || !b) return hipErrorOutOfMemory;
-      hipError_t e = hipEventRecord(a, s);
-      if (e != hipSuccess) return e;
+      if (!a || !b) return dev_fail(w, hipErrorOutOfMemory, "timing events");
+      HIPCHK(w, hipEventRecord(a, s), "event record");
     }
-    hipError_t e = fn();
-    if (e != hipSuccess) return e;
+    HIPCHK(w, launch_group(w, s, d, k), group_name(k));
     if (timed) {
-      e = hipEventRecord(b, s);
-      if (e != hipSuccess) return e;
+      HIPCHK(w, hipEventRecord(b, s), "event record");
       w->ev_pending.push_back({k, {a, b}});
     }
-    return hipSuccess;
-  };
-  if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
-  HIPCHK(w, run(ECO_K_SENSE, [&] { return launch_cell_sense(s, d, w->ts); }), "cell sense kernel");
-  HIPCHK(w, run(ECO_K_FORWARD, [&] { return launch_forward(w, s, d, w->launch); }), "forward kernel");
-  HIPCHK(w, run(ECO_K_MOVE, [&] { return launch_move(s, d, w->ts); }), "move kernel");
-  HIPCHK(w, run(ECO_K_BIRTH_CLAIM, [&] { return launch_birth_claim_regrow(s, d, w->ts, w->L.A); }),
-         "birth claim / regrowth kernel");
-  HIPCHK(w, run(ECO_K_BIRTH_SCAN, [&] { return launch_birth_rank(s, d, w->ts); }), "birth ranking kernels");
-  HIPCHK(w, run(ECO_K_BIRTH_COMMIT, [&] { return launch_birth_commit(s, d, w->L, emit_blocks(w)); }),
-         "birth commit kernel");
-  HIPCHK(w, run(ECO_K_COMPACT, [&] { return launch_compact(s, d, w->ts, 0, -1); }), "compaction kernels");
+  }
   return ECO_OK;
 }
 
@@ -371,11 +396,20 @@ eco_status drain_events(eco_world* w) {
   return ECO_OK;
 }
 
+void destroy_timed(eco_world::TimedGraph& t) {
+  if (t.exec) (void)hipGraphExecDestroy(t.exec);
+  if (t.graph) (void)hipGraphDestroy(t.graph);
+  for (auto e : t.events) (void)hipEventDestroy(e);
+  t = eco_world::TimedGraph{};
+}
+
 void drop_graph(eco_world* w) {
   if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
   if (w->graph) (void)hipGraphDestroy(w->graph);
   w->gexec = nullptr;
   w->graph = nullptr;
+  for (auto& t : w->tgraphs) destroy_timed(t);
+  w->tgraphs.clear();
 }
 
 eco_status build_graph(eco_world* w) {
@@ -395,6 +429,87 @@ eco_status build_graph(eco_world* w) {
   if (e != hipSuccess) return dev_fail(w, e, "end capture");
   w->graph = g;
   HIPCHK(w, hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+  return ECO_OK;
+}
+
+// Graph of n steps (captured like the one-step graph) with an event-record node
+// before and after every policy-kernel node, kept per n.  Only the dominant
+// kernel is bracketed: each event node costs the replay several microseconds.
+eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {
+  for (auto& t : w->tgraphs)
+    if (t.n == n) {
+      *out = &t;
+      return ECO_OK;
+    }
+  if (w->tgraphs.size() >= 4) {
+    destroy_timed(w->tgraphs.front());
+    w->tgraphs.erase(w->tgraphs.begin());
+  }
+  Dev d = w->d;
+  d.inject = 0;
+  d.dry = 0;
+  d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  eco_world::TimedGraph t;
+  t.n = n;
+  HIPCHK(w, hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  eco_status st = ECO_OK;
+  for (uint32_t i = 0; i < n && st == ECO_OK; ++i) st = enqueue_step(w, w->cap_stream, d, false);
+  hipError_t e = hipStreamEndCapture(w->cap_stream, &t.graph);
+  if (st != ECO_OK) {
+    destroy_timed(t);
+    return st;
+  }
+  const int u = (int)w->launch.unroll, H = (int)w->L.H1;
+  const void* fwd = w->L.wdtype == 0 ? forward_kernel_w0(H, u) : w->L.wdtype == 1 ? forward_kernel_w1(H, u)
+                                                                                  : forward_kernel_w2(H, u);
+  size_t cnt = 0;
+  if (e == hipSuccess) e = hipGraphGetNodes(t.graph, nullptr, &cnt);
+  std::vector<hipGraphNode_t> nodes(cnt);
+  if (e == hipSuccess && cnt) e = hipGraphGetNodes(t.graph, nodes.data(), &cnt);
+  uint32_t found = 0;
+  for (size_t i = 0; i < cnt && e == hipSuccess; ++i) {
+    hipGraphNodeType ty;
+    e = hipGraphNodeGetType(nodes[i], &ty);
+    if (e != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    e = hipGraphKernelNodeGetParams(nodes[i], &kp);
+    if (e != hipSuccess || kp.func != fwd) continue;
+    const hipGraphNode_t f = nodes[i];
+    size_t np = 0, nd = 0;
+    e = hipGraphNodeGetDependencies(f, nullptr, &np);
+    if (e == hipSuccess) e = hipGraphNodeGetDependentNodes(f, nullptr, &nd);
+    std::vector<hipGraphNode_t> pre(np), post(nd);
+    if (e == hipSuccess && np) e = hipGraphNodeGetDependencies(f, pre.data(), &np);
+    if (e == hipSuccess && nd) e = hipGraphNodeGetDependentNodes(f, post.data(), &nd);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) t.events.push_back(a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) t.events.push_back(b);
+    hipGraphNode_t na = nullptr, nb = nullptr;
+    // pre -> f  becomes  pre -> a -> f;  f -> post  becomes  f -> b -> post
+    for (size_t j = 0; j < np && e == hipSuccess; ++j) e = hipGraphRemoveDependencies(t.graph, &pre[j], &f, 1);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&na, t.graph, np ? pre.data() : nullptr, np, a);
+    if (e == hipSuccess) e = hipGraphAddDependencies(t.graph, &na, &f, 1);
+    for (size_t j = 0; j < nd && e == hipSuccess; ++j) e = hipGraphRemoveDependencies(t.graph, &f, &post[j], 1);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&nb, t.graph, &f, 1, b);
+    for (size_t j = 0; j < nd && e == hipSuccess; ++j) e = hipGraphAddDependencies(t.graph, &nb, &post[j], 1);
+    if (e == hipSuccess) {
+      t.pairs.push_back({ECO_K_FORWARD, {a, b}});
+      ++found;
+    }
+  }
+  if (e == hipSuccess && found != n) {
+    destroy_timed(t);
+    return fail(ECO_EDEVICE, "timed graph: policy-kernel nodes not found in the capture");
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&t.exec, t.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    destroy_timed(t);
+    return dev_fail(w, e, "timed graph");
+  }
+  w->tgraphs.push_back(std::move(t));
+  *out = &w->tgraphs.back();
   return ECO_OK;
 }
 
@@ -576,7 +691,6 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     ts.part_slot = w->part_slot;
     ts.part_cell = w->part_cell;
     ts.scan = (uint32_t*)A(16 * T);
-    ts.off = (uint32_t*)A(12 * T);
     ts.esum = (long long*)A(8 * T);
     ts.tsum = (double*)A(8 * T);
     ts.tsq = (double*)A(8 * T);
@@ -641,11 +755,19 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps) {
   if (st != ECO_OK) return st;
   if (n_steps == 0) return ECO_OK;
   const bool timed = (w->rt_flags & ECO_RT_TIME_KERNELS) != 0;
-  const bool graph = (w->rt_flags & ECO_RT_USE_GRAPH) != 0 && !timed;
+  const bool graph = (w->rt_flags & ECO_RT_USE_GRAPH) != 0;
   Dev d = w->d;
   d.inject = 0;
   d.dry = 0;
   d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  if (graph && timed) {
+    eco_world::TimedGraph* t = nullptr;
+    st = timed_graph(w, n_steps, &t);
+    if (st != ECO_OK) return st;
+    HIPCHK(w, hipGraphLaunch(t->exec, w->stream), "graph launch");
+    w->ev_pending.insert(w->ev_pending.end(), t->pairs.begin(), t->pairs.end());
+    return drain_events(w);
+  }
   if (graph) {
     if (!w->gexec) {
       st = build_graph(w);
@@ -660,6 +782,18 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps) {
   }
   if (timed) return drain_events(w);
   return ECO_OK;
+}
+
+eco_status eco_world_prepare(eco_world* w, uint32_t n_steps) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (!(w->rt_flags & ECO_RT_USE_GRAPH)) return ECO_OK;
+  if (w->rt_flags & ECO_RT_TIME_KERNELS) {
+    if (n_steps == 0) return ECO_OK;
+    eco_world::TimedGraph* t = nullptr;
+    return timed_graph(w, n_steps, &t);
+  }
+  return w->gexec ? ECO_OK : build_graph(w);
 }
 
 eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions) {
@@ -795,46 +929,54 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
   d.dry = 1;
   d.inject = 0;
   d.keep_logits = 0;
-  constexpr int kReps = 5;
-  hipEvent_t ev[kReps + 1];
-  for (auto& e : ev) HIPCHK(w, hipEventCreate(&e), "event");
-  auto destroy = [&] {
-    for (auto& e : ev) (void)hipEventDestroy(e);
-  };
-  eco_launch chosen = w->launch;
-  float best_ms = 1e30f;
-  if (hipError_t e = launch_cell_sense(w->stream, d, w->ts); e != hipSuccess) {
-    destroy();
-    return dev_fail(w, e, "autotune");
-  }
+  std::vector<eco_launch> cand;
   const uint32_t wpbs[] = {1, 2, 4, 8}, us[] = {4, 8, 16}, bpcs[] = {1, 2, 4, 8, 16};
   for (uint32_t wpb : wpbs)
     for (uint32_t u : us)
       for (uint32_t bpc : bpcs) {
         if (wpb * bpc > 32 || wpb * bpc < 4) continue;  // 4..32 waves per CU
         if (forward_shmem(w, wpb) > 64 * 1024 || forward_shmem(w, wpb) * bpc > 160 * 1024) continue;
-        const eco_launch lc{wpb, bpc, u, 0};
-        hipError_t e = launch_forward(w, w->stream, d, lc);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(ev[0], w->stream);
-        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
-          e = launch_forward(w, w->stream, d, lc);
-          if (e == hipSuccess) e = hipEventRecord(ev[r + 1], w->stream);
-        }
-        if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
-        float t[kReps];
-        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
-        if (e != hipSuccess) {
-          destroy();
-          return dev_fail(w, e, "autotune");
-        }
-        std::sort(t, t + kReps);
-        const float med = t[kReps / 2];  // median launch time of this shape
-        if (med < best_ms) {
-          best_ms = med;
-          chosen = lc;
-        }
+        cand.push_back(eco_launch{wpb, bpc, u, 0});
       }
+  // Rounds over all candidates (one timed launch each per round), median per
+  // candidate: drifts of clock or memory state during tuning hit every shape alike.
+  constexpr int kRounds = 5;
+  const size_t n = cand.size();
+  std::vector<hipEvent_t> ev(n + 1, nullptr);
+  auto destroy = [&] {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  for (size_t i = 0; i < n && e == hipSuccess; ++i) e = launch_forward(w, w->stream, d, cand[i]);  // warm-up
+  std::vector<std::vector<float>> t(n);
+  for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
+    e = hipEventRecord(ev[0], w->stream);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+      e = launch_forward(w, w->stream, d, cand[i]);
+      if (e == hipSuccess) e = hipEventRecord(ev[i + 1], w->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      t[i].push_back(ms);
+    }
+  }
   destroy();
+  if (e != hipSuccess) return dev_fail(w, e, "autotune");
+  eco_launch chosen = w->launch;
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < n; ++i) {
+    std::sort(t[i].begin(), t[i].end());
+    const float med = t[i][t[i].size() / 2];
+    if (med < best_ms) {
+      best_ms = med;
+      chosen = cand[i];
+    }
+  }
   w->launch = chosen;
   drop_graph(w);
   if (best) *best = chosen;

@@ -411,26 +411,61 @@ __global__ __launch_bounds__(kSlotTile) void k_birth_rank_count(Dev d, TileScrat
   if (threadIdx.x < 3) ts.scan[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Birth ranking, pass 3 (slot tiles): winner k of the world (slot order) is
-// recorded as bparent[k], free slot f (ascending) as freel[f] while f < W.
-// Claims of this step are cleared.
+// Sum over the world's tiles [lo, hi) of pass-1 counter c (ts.scan[t][c]); all
+// threads of the block get the sum.
+template <int NT>
+__device__ __forceinline__ uint32_t tiles_sum(const TileScratch& ts, uint32_t lo, uint32_t hi, int c,
+                                              unsigned long long* red64, uint32_t* bcast) {
+  uint32_t v = 0;
+  for (uint32_t t = lo + threadIdx.x; t < hi; t += NT) v += ts.scan[t * 4 + c];
+  const unsigned long long tot = block_sum_u64<NT>(v, red64);
+  if (threadIdx.x == 0) *bcast = (uint32_t)tot;
+  __syncthreads();
+  const uint32_t r = *bcast;
+  __syncthreads();
+  return r;
+}
+
+// Birth ranking, pass 2 (slot tiles): winner k of the world (slot order) is
+// recorded as bparent[k], free slot f (ascending) as freel[f].  A tile's
+// offsets are the counts of the world's earlier tiles (pass 1), summed here;
+// the world's last tile also records the world's birth totals.  Claims of
+// this step are cleared.
 __global__ __launch_bounds__(kSlotTile) void k_birth_rank_write(Dev d, TileScratch ts) {
   __shared__ uint32_t red[kSlotTile / 64 + 1];
+  __shared__ unsigned long long red64[kSlotTile / 64];
+  __shared__ uint32_t bcast;
   const Tile tl = ts.slot_tiles[blockIdx.x];
-  const WorldParams wp = d.wp[tl.world];
-  const uint32_t W = d.wv[tl.world].n_win;
+  const uint32_t w = tl.world;
+  const WorldParams wp = d.wp[w];
+  const uint32_t t0 = ts.tile_rng[4 * w], t1 = ts.tile_rng[4 * w + 1];
+  const uint32_t ow = tiles_sum<kSlotTile>(ts, t0, blockIdx.x, 1, red64, &bcast);
+  const uint32_t of = tiles_sum<kSlotTile>(ts, t0, blockIdx.x, 2, red64, &bcast);
   const bool in = threadIdx.x < tl.count;
   const uint32_t local = tl.start + threadIdx.x;
   const uint32_t slot = wp.slot_off + local;
   const uint8_t fl = in ? d.flags[slot] : (uint8_t)kAlive;
   uint32_t tot;
-  const uint32_t rw = ts.off[blockIdx.x * 3 + 0] + block_exscan<kSlotTile>((fl & kBirthWon) ? 1u : 0u, red, &tot);
-  const uint32_t rf = ts.off[blockIdx.x * 3 + 1] + block_exscan<kSlotTile>((fl & kAlive) ? 0u : 1u, red, &tot);
+  const uint32_t rw = ow + block_exscan<kSlotTile>((fl & kBirthWon) ? 1u : 0u, red, &tot);
+  const uint32_t rf = of + block_exscan<kSlotTile>((fl & kAlive) ? 0u : 1u, red, &tot);
   if (in) {
     if (fl & kBirthClaim) d.claim[wp.cell_off + d.tgt[slot]] = 0xFFFFFFFFu;
     if (fl & kBirthWon) d.bparent[wp.slot_off + rw] = (int)local;
-    if (!(fl & kAlive) && rf < W) d.freel[wp.slot_off + rf] = (int)local;
+    if (!(fl & kAlive)) d.freel[wp.slot_off + rf] = (int)local;
     if (fl & (kBirthClaim | kBirthWon)) d.flags[slot] = fl & kAlive;
+  }
+  if (blockIdx.x + 1 == t1) {  // the world's totals
+    const uint32_t C = tiles_sum<kSlotTile>(ts, t0, t1, 0, red64, &bcast);
+    const uint32_t Wn = tiles_sum<kSlotTile>(ts, t0, t1, 1, red64, &bcast);
+    const uint32_t F = tiles_sum<kSlotTile>(ts, t0, t1, 2, red64, &bcast);
+    if (threadIdx.x == 0) {
+      const uint32_t nb = min(Wn, F);
+      d.wv[w].n_births = nb;
+      d.wv[w].n_win = Wn;
+      d.cnt[w].births = nb;
+      d.cnt[w].births_blocked_cell = C - Wn;
+      d.cnt[w].births_blocked_capacity = Wn - nb;
+    }
   }
 }
 
@@ -523,62 +558,58 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch 
   }
 }
 
-// Compaction, pass 3 (slot tiles): live slots of the tile at their offsets.
-__global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch ts, int only_world) {
-  __shared__ uint32_t red[kSlotTile / 64 + 1];
-  const Tile tl = ts.slot_tiles[blockIdx.x];
-  if (only_world >= 0 && (int)tl.world != only_world) return;
-  const WorldParams wp = d.wp[tl.world];
-  const bool in = threadIdx.x < tl.count;
-  const uint32_t local = tl.start + threadIdx.x;
-  const bool alive = in && (d.flags[wp.slot_off + local] & kAlive);
-  uint32_t tot;
-  const uint32_t r = ts.off[blockIdx.x * 3 + 2] + block_exscan<kSlotTile>(alive ? 1u : 0u, red, &tot);
-  if (alive) d.live[wp.slot_off + r] = (int)local;
+// Window channels of every cell at the start of a step (Sec. 3.2 sensors, App. F
+// layout), one byte per cell: bit 0 agent present, bit 1 resource present, bit 2
+// wall (worlds with walls only), bits 3..5 the occupant's energy bin
+// min(floor(8 E / e_repro), 7), built at the end of each step (and of init and
+// state writes) for the next one.  The policy kernel's window gather then reads one
+// byte per cell instead of the occupancy, resource and wall arrays plus a
+// dependent read of each occupant's energy.  Threads take 4 consecutive cells
+// (cell_off and tile starts are multiples of 4); a ragged tail goes cell by cell.
+__device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d, int o, uint32_t r, uint32_t wl) {
+  uint32_t v = (r != 0 ? 2u : 0u) | (wp.has_walls && wl != 0 ? 4u : 0u);
+  if (o >= 0) {
+    const long long e8 = (long long)d.energy[wp.slot_off + (uint32_t)o] * 8;
+    uint32_t eb = 0;
+#pragma unroll
+    for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1u : 0u;
+    v |= 1u | (eb << 3);
+  }
+  return v;
 }
 
-// Pass 2 of both tile scans (one block per world).
-//  mode 0: exclusive tile offsets of birth winners and free slots; birth totals.
-//  mode 1: exclusive tile offsets of live slots; the step's statistics record;
-//          the clock advances unless init != 0 (init / state writes).
-__global__ __launch_bounds__(kScanThreads) void k_world_scan(Dev d, TileScratch ts, int mode, int init, int only_world) {
-  __shared__ uint32_t red[kScanThreads / 64 + 1];
-  __shared__ unsigned long long red64[kScanThreads / 64];
-  __shared__ double redf[kScanThreads / 64];
+__device__ __forceinline__ void cell_sense_tile(const Dev& d, const Tile tl) {
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
+    const uint32_t cell = wp.cell_off + tl.start + i;
+    if (i + 4 <= tl.count) {
+      const int4 o = *reinterpret_cast<const int4*>(d.occ + cell);
+      const uint32_t r = *reinterpret_cast<const uint32_t*>(d.res + cell);
+      const uint32_t wl = *reinterpret_cast<const uint32_t*>(d.wall + cell);
+      const uint32_t v = sense_of(wp, d, o.x, r & 0xFFu, wl & 0xFFu) | sense_of(wp, d, o.y, (r >> 8) & 0xFFu, (wl >> 8) & 0xFFu) << 8 |
+                         sense_of(wp, d, o.z, (r >> 16) & 0xFFu, (wl >> 16) & 0xFFu) << 16 |
+                         sense_of(wp, d, o.w, r >> 24, wl >> 24) << 24;
+      *reinterpret_cast<uint32_t*>(d.sense + cell) = v;
+    } else {
+      for (uint32_t c = cell; c < wp.cell_off + tl.start + tl.count; ++c)
+        d.sense[c] = (uint8_t)sense_of(wp, d, d.occ[c], d.res[c], d.wall[c]);
+    }
+  }
+}
+
+// The step's statistics record of world w once its compaction counts are in
+// (pass 1), and the clock advance unless init != 0 (init / state writes).  Run
+// by the block of the world's last slot tile (NT threads).
+template <int NT>
+__device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, int init) {
+  __shared__ uint32_t red[NT / 64 + 1];
+  __shared__ unsigned long long red64[NT / 64];
+  __shared__ double redf[NT / 64];
   __shared__ uint32_t s_cnt[kSlotPart + kCellPart];
-  const uint32_t w = blockIdx.x;
-  if (only_world >= 0 && (int)w != only_world) return;
   const uint32_t t0 = ts.tile_rng[4 * w], t1 = ts.tile_rng[4 * w + 1];
   const uint32_t nt = t1 - t0;
-  const uint32_t per = (nt + kScanThreads - 1) / kScanThreads;
+  const uint32_t per = (nt + NT - 1) / NT;
   const uint32_t lo = t0 + threadIdx.x * per, hi = min(lo + per, t1);
-  if (mode == 0) {
-    uint32_t nc = 0, nw = 0, nf = 0;
-    for (uint32_t t = lo; t < hi; ++t) {
-      nc += ts.scan[t * 4 + 0];
-      nw += ts.scan[t * 4 + 1];
-      nf += ts.scan[t * 4 + 2];
-    }
-    uint32_t C, Wn, F;
-    uint32_t ow = block_exscan<kScanThreads>(nw, red, &Wn);
-    uint32_t of = block_exscan<kScanThreads>(nf, red, &F);
-    block_exscan<kScanThreads>(nc, red, &C);
-    for (uint32_t t = lo; t < hi; ++t) {
-      ts.off[t * 3 + 0] = ow;
-      ts.off[t * 3 + 1] = of;
-      ow += ts.scan[t * 4 + 1];
-      of += ts.scan[t * 4 + 2];
-    }
-    if (threadIdx.x == 0) {
-      const uint32_t nb = min(Wn, F);
-      d.wv[w].n_births = nb;
-      d.wv[w].n_win = Wn;
-      d.cnt[w].births = nb;
-      d.cnt[w].births_blocked_cell = C - Wn;
-      d.cnt[w].births_blocked_capacity = Wn - nb;
-    }
-    return;
-  }
   uint32_t n = 0;
   long long es = 0;
   double s1 = 0.0, s2 = 0.0;
@@ -589,14 +620,10 @@ __global__ __launch_bounds__(kScanThreads) void k_world_scan(Dev d, TileScratch 
     s2 += ts.tsq[t];
   }
   uint32_t N;
-  uint32_t o = block_exscan<kScanThreads>(n, red, &N);
-  for (uint32_t t = lo; t < hi; ++t) {
-    ts.off[t * 3 + 2] = o;
-    o += ts.scan[t * 4 + 3];
-  }
-  const unsigned long long E = block_sum_u64<kScanThreads>((unsigned long long)es, red64);
-  const double T1 = block_sum_f64<kScanThreads>(s1, redf);
-  const double T2 = block_sum_f64<kScanThreads>(s2, redf);
+  block_exscan<NT>(n, red, &N);
+  const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
+  const double T1 = block_sum_f64<NT>(s1, redf);
+  const double T2 = block_sum_f64<NT>(s2, redf);
   if (threadIdx.x < kSlotPart + kCellPart) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   if (!init) {
@@ -633,6 +660,35 @@ __global__ __launch_bounds__(kScanThreads) void k_world_scan(Dev d, TileScratch 
     st.trait_var = N ? fmax(T2 / (double)N - mean * mean, 0.0) : 0.0;
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
+}
+
+// Compaction, pass 2.  Slot-tile blocks: the tile's live slots at their
+// offsets in the world's live list (offset = live counts of the world's earlier
+// tiles, summed here); the world's last tile also writes the step's statistics.
+// Blocks past the slot tiles build the sense bytes of one cell tile each for the
+// next step (the grid is final here).  only_world >= 0 restricts both parts.
+__global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch ts, int init, int only_world) {
+  __shared__ uint32_t red[kSlotTile / 64 + 1];
+  __shared__ unsigned long long red64[kSlotTile / 64];
+  __shared__ uint32_t bcast;
+  if (blockIdx.x >= ts.n_slot_tiles) {
+    const Tile ct = ts.cell_tiles[blockIdx.x - ts.n_slot_tiles];
+    if (only_world < 0 || (int)ct.world == only_world) cell_sense_tile(d, ct);
+    return;
+  }
+  const Tile tl = ts.slot_tiles[blockIdx.x];
+  if (only_world >= 0 && (int)tl.world != only_world) return;
+  const uint32_t w = tl.world;
+  const WorldParams wp = d.wp[w];
+  const uint32_t t0 = ts.tile_rng[4 * w], t1 = ts.tile_rng[4 * w + 1];
+  const uint32_t ol = tiles_sum<kSlotTile>(ts, t0, blockIdx.x, 3, red64, &bcast);
+  const bool in = threadIdx.x < tl.count;
+  const uint32_t local = tl.start + threadIdx.x;
+  const bool alive = in && (d.flags[wp.slot_off + local] & kAlive);
+  uint32_t tot;
+  const uint32_t r = ol + block_exscan<kSlotTile>(alive ? 1u : 0u, red, &tot);
+  if (alive) d.live[wp.slot_off + r] = (int)local;
+  if (blockIdx.x + 1 == t1) world_finalize<kSlotTile>(d, ts, w, init);
 }
 
 // Resource total of each world (init / after state writes): one block per world.
@@ -719,45 +775,6 @@ __global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
   }
 }
 
-// Window channels of every cell at the start of a step (Sec. 3.2 sensors, App. F
-// layout), one byte per cell: bit 0 agent present, bit 1 resource present, bit 2
-// wall (worlds with walls only), bits 3..5 the occupant's energy bin
-// min(floor(8 E / e_repro), 7).  The policy kernel's window gather then reads one
-// byte per cell instead of the occupancy, resource and wall arrays plus a
-// dependent read of each occupant's energy.  Threads take 4 consecutive cells
-// (cell_off and tile starts are multiples of 4); a ragged tail goes cell by cell.
-__device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d, int o, uint32_t r, uint32_t wl) {
-  uint32_t v = (r != 0 ? 2u : 0u) | (wp.has_walls && wl != 0 ? 4u : 0u);
-  if (o >= 0) {
-    const long long e8 = (long long)d.energy[wp.slot_off + (uint32_t)o] * 8;
-    uint32_t eb = 0;
-#pragma unroll
-    for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1u : 0u;
-    v |= 1u | (eb << 3);
-  }
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_cell_sense(Dev d, const Tile* tiles) {
-  const Tile tl = tiles[blockIdx.x];
-  const WorldParams wp = d.wp[tl.world];
-  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
-    const uint32_t cell = wp.cell_off + tl.start + i;
-    if (i + 4 <= tl.count) {
-      const int4 o = *reinterpret_cast<const int4*>(d.occ + cell);
-      const uint32_t r = *reinterpret_cast<const uint32_t*>(d.res + cell);
-      const uint32_t wl = *reinterpret_cast<const uint32_t*>(d.wall + cell);
-      const uint32_t v = sense_of(wp, d, o.x, r & 0xFFu, wl & 0xFFu) | sense_of(wp, d, o.y, (r >> 8) & 0xFFu, (wl >> 8) & 0xFFu) << 8 |
-                         sense_of(wp, d, o.z, (r >> 16) & 0xFFu, (wl >> 16) & 0xFFu) << 16 |
-                         sense_of(wp, d, o.w, r >> 24, wl >> 24) << 24;
-      *reinterpret_cast<uint32_t*>(d.sense + cell) = v;
-    } else {
-      for (uint32_t c = cell; c < wp.cell_off + tl.start + tl.count; ++c)
-        d.sense[c] = (uint8_t)sense_of(wp, d, d.occ[c], d.res[c], d.wall[c]);
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers (used by eco_runtime.cpp)
 // ---------------------------------------------------------------------------
@@ -778,9 +795,6 @@ hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts)
   hipLaunchKernelGGL(k_birth_rank_count, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_world_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, ts, 0, 0, -1);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_birth_rank_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts);
   ECO_CHECK_LAUNCH();
 }
@@ -794,15 +808,8 @@ hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, in
   hipLaunchKernelGGL(k_compact_count, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts, only_world);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_world_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, d, ts, 1, init, only_world);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts, only_world);
-  ECO_CHECK_LAUNCH();
-}
-hipError_t launch_cell_sense(hipStream_t s, const Dev& d, const TileScratch& ts) {
-  if (ts.n_cell_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_sense, dim3(ts.n_cell_tiles), dim3(256), 0, s, d, ts.cell_tiles);
+  hipLaunchKernelGGL(k_compact_write, dim3(ts.n_slot_tiles + ts.n_cell_tiles), dim3(kSlotTile), 0, s, d, ts, init,
+                     only_world);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {

@@ -22,7 +22,7 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_set_launch", "eco_world_get_launch", "eco_world_autotune", "eco_world_kernel_times",
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
-           "eco_world_write_weights"]
+           "eco_world_write_weights", "eco_world_prepare"]
 
 
 class EcoError(RuntimeError):
@@ -101,6 +101,7 @@ def lib():
         L.eco_world_destroy.argtypes = [P]
         L.eco_world_destroy.restype = None
         L.eco_world_step.argtypes = [P, U32]
+        L.eco_world_prepare.argtypes = [P, U32]
         L.eco_world_reset.argtypes = [P, P]
         L.eco_world_stats.argtypes = [P, ctypes.POINTER(Stats), U32]
         L.eco_world_stats_history.argtypes = [P, U32, ctypes.POINTER(Stats), U32, ctypes.POINTER(ctypes.c_uint32)]
@@ -212,6 +213,9 @@ class World:
     # -- stepping ---------------------------------------------------------
     def step(self, n=1):
         _err(lib().eco_world_step(self._h, n))
+
+    def prepare(self, n=1):
+        _err(lib().eco_world_prepare(self._h, n))
 
     def step_with_actions(self, actions):
         a = np.ascontiguousarray(actions, dtype=np.uint8)

@@ -145,13 +145,21 @@ def test_graph_and_eager_paths_agree(eco):
     cfg = mid_world(seed=6, e_init=150)
     a = eco.World(cfg)
     b = eco.World(cfg)
+    c = eco.World(cfg)
     b.set_flags(0)  # eager
+    c.set_flags(eco.RT_USE_GRAPH | eco.RT_TIME_KERNELS)  # graphs of whole runs, events around the policy kernel
+    c.prepare(7)
     a.step(20)
     b.step(20)
+    for n in (7, 7, 6):
+        c.step(n)
     assert_same_state(a.read_state(), b.read_state(), "graph vs eager")
-    assert a.stats() == b.stats()
-    a.close()
-    b.close()
+    assert_same_state(a.read_state(), c.read_state(), "graph vs timed graph")
+    assert a.stats() == b.stats() == c.stats()
+    kt = c.kernel_times()
+    assert kt["forward"][1] == 20 and kt["forward"][0] > 0.0 and kt["compact"][1] == 0
+    for w in (a, b, c):
+        w.close()
 
 
 def test_resume_from_state_and_weights(eco):
