@@ -627,11 +627,25 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
   if (threadIdx.x < kSlotPart + kCellPart) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   if (!init) {
+    // per-thread sums over its tiles, then wave sums, then one LDS add per wave
+    uint32_t c[kSlotPart + kCellPart];
+#pragma unroll
+    for (int k = 0; k < kSlotPart + kCellPart; ++k) c[k] = 0;
+    for (uint32_t t = lo; t < hi; ++t)
+#pragma unroll
+      for (int k = 0; k < kSlotPart; ++k) c[k] += ts.part_slot[t * kSlotPart + k];
     const uint32_t ct0 = ts.tile_rng[4 * w + 2], ct1 = ts.tile_rng[4 * w + 3];
-    for (uint32_t i = threadIdx.x; i < nt * kSlotPart; i += blockDim.x)
-      atomicAdd(&s_cnt[i % kSlotPart], ts.part_slot[t0 * kSlotPart + i]);
-    for (uint32_t i = threadIdx.x; i < (ct1 - ct0) * kCellPart; i += blockDim.x)
-      atomicAdd(&s_cnt[kSlotPart + i % kCellPart], ts.part_cell[ct0 * kCellPart + i]);
+    for (uint32_t t = ct0 + threadIdx.x; t < ct1; t += NT)
+#pragma unroll
+      for (int k = 0; k < kCellPart; ++k) c[kSlotPart + k] += ts.part_cell[t * kCellPart + k];
+#pragma unroll
+    for (int k = 0; k < kSlotPart + kCellPart; ++k) {
+#pragma unroll
+      for (int dd = 32; dd >= 1; dd >>= 1) c[k] += __shfl_xor(c[k], dd);
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < kSlotPart + kCellPart; ++k) atomicAdd(&s_cnt[k], c[k]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
