@@ -97,32 +97,30 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None):
 
 
 def trajectory(eco, cfg, steps, chunk=1000, out_path=None):
-    """Long free-running run (graph replay): population and policy-kernel bandwidth per chunk."""
+    """Long free-running run: population, throughput and policy-kernel bandwidth per chunk
+    of steps (each chunk replayed from one graph with event nodes around the policy kernel)."""
     import torch
     w = eco.World(cfg)
     w.autotune()
+    w.set_flags(eco.RT_USE_GRAPH | eco.RT_TIME_KERNELS)
+    bytes_per_agent = w.info["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT
     rows = []
     for c0 in range(0, steps, chunk):
         n = min(chunk, steps - c0)
-        w.set_flags(eco.RT_USE_GRAPH)
+        w.prepare(n)
+        w.kernel_times(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        w.step(n - 1)
-        w.set_flags(eco.RT_TIME_KERNELS)
-        w.kernel_times(reset=True)
-        w.step(1)
+        w.step(n)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        kt = w.kernel_times(reset=True)
+        fwd_ms = w.kernel_times(reset=True)["forward"][0]
         hist = w.stats_history(0, n + 1)
         agent_steps = sum(h["population"] for h in hist[:-1])
-        fwd_ms = kt["forward"][0]
-        pop_last_start = hist[-2]["population"]
-        gbs = pop_last_start * (w.info["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT) / (fwd_ms * 1e-3) / 1e9
         row = {"step": hist[-1]["step"], "population": hist[-1]["population"],
                "births": sum(h["births"] for h in hist[1:]), "deaths": sum(h["deaths"] for h in hist[1:]),
                "agent_steps_per_s": round(agent_steps / dt, 1), "ms_per_step": round(dt * 1e3 / n, 4),
-               "forward_GBps_last_step": round(gbs, 1),
+               "forward_GBps": round(agent_steps * bytes_per_agent / (fwd_ms * 1e-3) / 1e9, 1) if fwd_ms > 0 else 0.0,
                "pop_min": min(h["population"] for h in hist), "pop_max": max(h["population"] for h in hist)}
         rows.append(row)
         log(f"[trajectory] {row}")
@@ -217,6 +215,7 @@ def main():
     ap.add_argument("--launch", default=None, help="fixed policy-kernel launch 'waves_per_block,blocks_per_cu,unroll'")
     ap.add_argument("--trajectory", type=int, default=0, help="instead: free-run this many steps, report per 1000")
     ap.add_argument("--trajectory-out", default=None)
+    ap.add_argument("--trajectory-chunk", type=int, default=1000, help="steps per trajectory row")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: worlds shard across GPUs by design but no multi-GPU path is "
@@ -231,7 +230,7 @@ def main():
 
     cfg = workload_cfg(wl, args.workload)
     if args.trajectory:
-        rows = trajectory(eco, cfg, args.trajectory, out_path=args.trajectory_out)
+        rows = trajectory(eco, cfg, args.trajectory, chunk=args.trajectory_chunk, out_path=args.trajectory_out)
         print(json.dumps({"workload": args.workload, "trajectory": rows}), flush=True)
         return
 
