@@ -57,3 +57,43 @@ def compare_world(gw, ow, what, world=0, weights_slots=8):
                              f"{what} master slot {s}")
         assert_weights_close(gw.read_weights(int(s), world), ow.weights(int(s)), f"{what} storage slot {s}")
     return gs
+
+
+def run_pair(eco, cfg, steps, actions_fn=None, check_logits=True, what="", every=1, launch=None):
+    """Step GPU and oracle together.  actions_fn(step) -> actions, or None for the
+    oracle's own sampled actions, which are injected into the GPU world.
+    launch: optional policy-kernel shape (waves per block, blocks per CU, unroll)."""
+    from oracle import oracle as orc
+    ow = orc.OracleWorld(cfg)
+    gw = eco.World(cfg)
+    if launch:
+        gw.set_launch(*launch)
+    gw.set_flags(eco.RT_KEEP_LOGITS)
+    compare_world(gw, ow, f"{what} init")
+    assert_stats_match(gw.stats()[0], ow.stats(), f"{what} init")
+    worst = 0.0
+    mismatched = 0
+    for t in range(steps):
+        pre_alive = ow.state()["alive"].astype(bool)
+        if actions_fn is None:
+            logits, sampled = ow.step(want_logits=True, want_sampled=True)
+            acts = sampled.copy()
+            acts[~pre_alive] = 0
+        else:
+            acts = actions_fn(t)
+            logits, sampled = ow.step(actions=acts, want_logits=True, want_sampled=True)
+        gw.step_with_actions(acts)
+        if check_logits:
+            gl = gw.read_logits()
+            err = logit_err(gl[pre_alive], logits[pre_alive])
+            worst = max(worst, float(err.max(initial=0.0)))
+            assert np.all(np.isnan(gl[~pre_alive]))
+            gs = gw.read_sampled()
+            mismatched += int((gs[pre_alive] != sampled[pre_alive]).sum())
+        if t % every == 0 or t == steps - 1:
+            compare_world(gw, ow, f"{what} step {t}")
+            assert_stats_match(gw.stats()[0], ow.stats(), f"{what} step {t}")
+    gw.close()
+    say(f"{what}: worst normwise logit error {worst:.3e}, sampled-action mismatches {mismatched}")
+    assert worst <= LOGIT_TOL
+    return worst, mismatched
