@@ -17,7 +17,9 @@ weight and state bytes) over its average launch duration, measured with HIP
 events on the library's stream over the next K steps, replayed from one graph
 that carries event-record nodes around every policy-kernel launch (those nodes
 slow the replay, so that region's own step time is reported apart as
-timing_region_ms_per_step).  Also reported: BF16 and FP8 weight storage on the
+timing_region_ms_per_step); it also gives the achieved rate as a fraction of
+the box's streaming-read rate, measured by the library's probe kernel (8 GiB
+read once per launch; best of three calls of five launches at three grid shapes).  Also reported: BF16 and FP8 weight storage on the
 same world, the frozen-population form (exactly 65,536 agents every step), a
 per-kernel breakdown from a few eager steps, and the CPU oracle on a bounded
 sample.
@@ -149,6 +151,9 @@ def profiled_traffic(name):
     return float(vals["traffic_bytes_per_launch"])
 
 
+READ_CEILING = {}  # measured once per run: the library's streaming-read probe
+
+
 def roofline(r, profile_name=None):
     ms, n = r["kernel_times"]["forward"]
     avg_ms = ms / max(n, 1)
@@ -159,7 +164,9 @@ def roofline(r, profile_name=None):
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": profiled_traffic(profile_name) if profile_name else None,
             "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
-            "bytes_per_agent": bytes_per_agent, "agents_per_launch": round(agents_per_launch, 1)}
+            "bytes_per_agent": bytes_per_agent, "agents_per_launch": round(agents_per_launch, 1),
+            "measured_read_ceiling_GBps": READ_CEILING.get("gbps"),
+            "frac_of_measured_ceiling": round(gbs / READ_CEILING["gbps"], 4) if READ_CEILING.get("gbps") else None}
 
 
 def cpu_baseline(min_seconds=10.0, max_steps=100):
@@ -227,6 +234,8 @@ def main():
     from paper_2510_18221_amd import workloads as wl
     assert torch.cuda.is_available(), "bench needs a GPU"
     eco.lib()
+    READ_CEILING["gbps"] = round(max(eco.stream_read_gbps(8 << 30) for _ in range(3)), 1)
+    log(f"[bench] streaming-read ceiling {READ_CEILING['gbps']} GB/s")
 
     cfg = workload_cfg(wl, args.workload)
     if args.trajectory:

@@ -178,6 +178,15 @@ eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
 eco_status eco_world_autotune(eco_world* w, eco_launch* best);
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);
 
+/* Measurement helper, not part of the step: the device's streaming-read rate.
+ * Allocates `bytes` of device memory (hipMalloc; rounded down to 16 B, at least
+ * 64 MiB), fills it, times five launches each of a kernel that reads it once
+ * with 16-byte non-temporal loads (grid-stride, 8 loads in flight per lane) at
+ * three grid shapes, frees it, and writes the best rate in GB/s (1e9 B/s) to *gbps.  hip_stream
+ * may be NULL (the default stream).  Errors: EINVAL (null gbps or too small),
+ * ENOMEM, EDEVICE. */
+eco_status eco_stream_read_gbps(void* hip_stream, uint64_t bytes, double* gbps);
+
 /* ---- parity / test hooks (not on the timed path) ------------------------ */
 
 /* One step with the given actions (host array, one per slot of every world,

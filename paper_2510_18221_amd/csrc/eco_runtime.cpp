@@ -31,6 +31,8 @@ hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts)
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
+hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32_t* sink, uint32_t blocks,
+                              uint32_t threads);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
@@ -1227,6 +1229,50 @@ eco_status eco_world_write_weights(eco_world* w, uint32_t world, uint32_t slot, 
   HIPCHK(w, launch_emit_list(s, w->d, L, w->emit_list, 1, EMIT_REQUANT, 0, 0, 0, 1), "requantise");
   st = sync(w);
   if (st != ECO_OK) return st;
+  return ECO_OK;
+}
+
+eco_status eco_stream_read_gbps(void* hip_stream, uint64_t bytes, double* gbps) {
+  if (!gbps) return fail(ECO_EINVAL, "gbps is NULL");
+  bytes &= ~15ull;
+  if (bytes < (64ull << 20)) return fail(ECO_EINVAL, "probe needs at least 64 MiB");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(ECO_EDEVICE, "no HIP device");
+  void* buf = nullptr;
+  uint32_t* sink = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(ECO_ENOMEM, "probe buffer");
+  if (hipMalloc(&sink, 64) != hipSuccess) {
+    (void)hipFree(buf);
+    return fail(ECO_ENOMEM, "probe sink");
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipMemsetAsync(buf, 0x5A, bytes, s);
+  // a few grid shapes (blocks per CU x threads), best rate over five launches of each
+  const uint32_t shapes[][2] = {{32, 256}, {64, 256}, {64, 512}};
+  double best = 0.0;
+  for (const auto& sh : shapes) {
+    const uint32_t blocks = (uint32_t)cus * sh[0];
+    if (e == hipSuccess) e = launch_stream_read(s, buf, bytes / 16, sink, blocks, sh[1]);  // warm-up
+    for (int r = 0; r < 5 && e == hipSuccess; ++r) {
+      e = hipEventRecord(a, s);
+      if (e == hipSuccess) e = launch_stream_read(s, buf, bytes / 16, sink, blocks, sh[1]);
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess && ms > 0.0f) best = std::max(best, (double)bytes / (ms * 1e-3) / 1e9);
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(sink);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(ECO_EDEVICE, hipGetErrorString(e));
+  *gbps = best;
   return ECO_OK;
 }
 

@@ -789,6 +789,29 @@ __global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
   }
 }
 
+// Streaming-read probe (measurement only): every 16-byte block of p read once,
+// grid-stride, 8 non-temporal loads in flight per lane; the XOR of the data
+// goes to *sink only if it equals a constant, so the loads cannot be dropped.
+typedef unsigned int probe_u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(512) void k_stream_read(const probe_u32x4* __restrict__ p, uint64_t n, uint32_t* sink) {
+  constexpr int U = 8;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    probe_u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(p + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (; i < n; i += stride) {
+    const probe_u32x4 v = __builtin_nontemporal_load(p + i);
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  if (acc == 0x9E3779B9u) *sink = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (used by eco_runtime.cpp)
 // ---------------------------------------------------------------------------
@@ -824,6 +847,12 @@ hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, in
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact_write, dim3(ts.n_slot_tiles + ts.n_cell_tiles), dim3(kSlotTile), 0, s, d, ts, init,
                      only_world);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32_t* sink, uint32_t blocks,
+                              uint32_t threads) {
+  hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(threads), 0, s, reinterpret_cast<const probe_u32x4*>(p), n16,
+                     sink);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {

@@ -22,7 +22,7 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_set_launch", "eco_world_get_launch", "eco_world_autotune", "eco_world_kernel_times",
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
-           "eco_world_write_weights", "eco_world_prepare"]
+           "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps"]
 
 
 class EcoError(RuntimeError):
@@ -102,6 +102,7 @@ def lib():
         L.eco_world_destroy.restype = None
         L.eco_world_step.argtypes = [P, U32]
         L.eco_world_prepare.argtypes = [P, U32]
+        L.eco_stream_read_gbps.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
         L.eco_world_reset.argtypes = [P, P]
         L.eco_world_stats.argtypes = [P, ctypes.POINTER(Stats), U32]
         L.eco_world_stats_history.argtypes = [P, U32, ctypes.POINTER(Stats), U32, ctypes.POINTER(ctypes.c_uint32)]
@@ -334,3 +335,12 @@ def pack_state(st, width, height, cap):
         assert a.size == n, name
         parts.append(a.view(np.uint8).ravel())
     return np.concatenate(parts)
+
+
+def stream_read_gbps(nbytes=8 << 30, stream=None):
+    """The device's streaming-read rate (GB/s) from the library's probe kernel."""
+    import torch
+    g = ctypes.c_double(0.0)
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _err(lib().eco_stream_read_gbps(ctypes.c_void_p(s), nbytes, ctypes.byref(g)))
+    return g.value

@@ -232,3 +232,12 @@ def test_errors(eco):
     gw.step(2)
     assert gw.stats()[0]["step"] == 2
     gw.close()
+
+
+def test_stream_read_probe(eco):
+    """The measurement helper: a plausible HBM read rate, and its argument checks."""
+    g = eco.stream_read_gbps(1 << 30)
+    assert 1000.0 < g < 8000.0, g
+    with pytest.raises(eco.EcoError) as e:
+        eco.stream_read_gbps(1 << 20)
+    assert e.value.status == eco.ECO_EINVAL
