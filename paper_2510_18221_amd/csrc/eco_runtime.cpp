@@ -942,7 +942,7 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
       }
   // Rounds over all candidates (one timed launch each per round), median per
   // candidate: drifts of clock or memory state during tuning hit every shape alike.
-  constexpr int kRounds = 5;
+  constexpr int kRounds = 9;
   const size_t n = cand.size();
   std::vector<hipEvent_t> ev(n + 1, nullptr);
   auto destroy = [&] {
