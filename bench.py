@@ -169,26 +169,49 @@ def roofline(r, profile_name=None):
             "frac_of_measured_ceiling": round(gbs / READ_CEILING["gbps"], 4) if READ_CEILING.get("gbps") else None}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(min_seconds=10.0, max_steps=100):
     """The oracle as it stands, on a bounded sample of the same workload: the
-    same 65,536-agent world (init not timed), stepped until ~10 s of CPU work."""
+    same 65,536-agent world (init not timed), stepped until ~10 s of CPU work
+    with OpenMP over agents on all threads, then ~10 s more on one thread."""
+    import ctypes
     from oracle import oracle as orc
     from paper_2510_18221_amd import workloads as wl
     cfg = wl.world_65k(seed=0)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     w = orc.OracleWorld(cfg)
-    pops = []
-    t0 = time.perf_counter()
-    while len(pops) < max_steps and (time.perf_counter() - t0 < min_seconds or len(pops) < 2):
-        pops.append(w.stats()["population"])
-        w.step()
-    dt = time.perf_counter() - t0
+
+    def sample(seconds):
+        pops = []
+        t0 = time.perf_counter()
+        while len(pops) < max_steps and (time.perf_counter() - t0 < seconds or len(pops) < 2):
+            pops.append(w.stats()["population"])
+            w.step()
+        return pops, time.perf_counter() - t0
+
+    pops, dt = sample(min_seconds)
+    gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle library runs on
+    gomp.omp_set_num_threads(1)
+    pops1, dt1 = sample(min_seconds)
+    gomp.omp_set_num_threads(threads)
     w.close()
     return {"value": round(sum(pops) / dt, 1), "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"the same 1024x1024 world with 65,536 agents, FP32 weights, {len(pops)} full steps "
                       f"(policy sampled by the oracle) after an untimed init; FP64 policy with OpenMP over "
                       f"agents, sequential world update",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2),
+            "single_thread": {"value": round(sum(pops1) / dt1, 1), "steps": len(pops1), "seconds": round(dt1, 2)},
+            "host": {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+                     "usable_cpus": len(os.sched_getaffinity(0))}}
 
 
 WORKLOADS = {
