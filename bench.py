@@ -221,6 +221,8 @@ WORKLOADS = {
               "occupancy (984,579 agents), capacity 1.125x, 492->64->64->7 BF16 weights + FP32 master", "bf16"),
     "large": ("single world 2048x2048, capacity 262,144 starting half full, density 0.03, regrowth 0.005, "
               "15x15x4 window + 8 scalars, 908->128->128->7 BF16 weights + FP32 master", "bf16"),
+    "small": ("single world 64x64 torus, 256 agents at start, capacity 4,096, density 0.1, regrowth 0.01, "
+              "5x5x4 window + 4 scalars, 104->32->32->5 FP32 weights (cache-resident: a latency test)", "f32"),
 }
 
 
@@ -229,6 +231,8 @@ def workload_cfg(wl, name):
         return wl.world_65k(seed=0)
     if name == "batch":
         return wl.world_batch(64)
+    if name == "small":
+        return wl.world_small(seed=0)
     return wl.world_large(seed=0)
 
 
@@ -283,6 +287,7 @@ def main():
         "config": {"workload": desc, "agents_start": main_r["pop_start"], "agents_end": main_r["pop_end"],
                    "births": main_r["births"], "deaths": main_r["deaths"], "launch": main_r["launch"]},
         "roofline": roofline(main_r, "65k_fp32" if args.workload == "65k" else None),
+        "world_steps_per_s": round(1e3 / ms_per_step, 1),
         "timing_region_ms_per_step": round(main_r["timing_region"]["seconds"] * 1e3 / main_r["steps"], 4),
         "kernel_ms_per_step_eager": {k: round(v[0] / max(v[1], 1), 4)
                                      for k, v in main_r["kernel_times_eager"].items()},
