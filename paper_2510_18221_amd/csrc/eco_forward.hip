@@ -129,18 +129,51 @@ __device__ __forceinline__ void stream_layer(const u32x4* __restrict__ blk, int 
   }
 }
 
+// Biases (BF16 for BF16 storage, FP32 otherwise) and FP8 row scales of one
+// agent, loaded as raw words when the agent starts and converted where they are
+// used, so no layer epilogue waits for memory.
 template <int WDT>
-__device__ __forceinline__ float load_bias(const uint8_t* __restrict__ p, int i) {
-  if (WDT == 1) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(p)[i] << 16);
-  return reinterpret_cast<const float*>(p)[i];
+__device__ __forceinline__ uint32_t load_bias_raw(const uint8_t* __restrict__ p, int i) {
+  if (WDT == 1) return reinterpret_cast<const uint16_t*>(p)[i];
+  return reinterpret_cast<const uint32_t*>(p)[i];
+}
+template <int WDT>
+__device__ __forceinline__ float bias_of(uint32_t raw) {
+  return (WDT == 1) ? __uint_as_float(raw << 16) : __uint_as_float(raw);
+}
+template <int WDT>
+__device__ __forceinline__ float scale_of(uint32_t raw) {
+  return (WDT == 2) ? __uint_as_float(raw) : 1.0f;
+}
+
+template <int WDT, int H>
+struct Tail {
+  static constexpr int RPL = (H == 128) ? 2 : 1;
+  uint32_t b1[RPL], b2[RPL], s1[RPL], s2[RPL], b3, s3;
+};
+
+template <int WDT, int H>
+__device__ __forceinline__ void load_tail(const uint8_t* __restrict__ wbase, const Layout& L, int lane,
+                                          Tail<WDT, H>& t) {
+#pragma unroll
+  for (int r = 0; r < Tail<WDT, H>::RPL; ++r) {
+    const int j = (H == 32) ? (lane & 31) : lane + 64 * r;
+    t.b1[r] = load_bias_raw<WDT>(wbase + L.s_b1, j);
+    t.b2[r] = load_bias_raw<WDT>(wbase + L.s_b2, j);
+    t.s1[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc1)[j] : 0u;
+    t.s2[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc2)[j] : 0u;
+  }
+  t.b3 = load_bias_raw<WDT>(wbase + L.s_b3, lane >> 3);
+  t.s3 = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[lane >> 3] : 0u;
 }
 
 // One hidden layer: streamed dot products, half-wave combine, scale, bias, ReLU,
 // result to LDS hs[0..ROWS).
 template <int WDT, int ROWS, int U>
-__device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, uint32_t w_off, uint32_t b_off,
-                                             uint32_t sc_off, int KB, const float* __restrict__ xs,
-                                             float* __restrict__ hs, int lane) {
+__device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, uint32_t w_off, int KB,
+                                             const float* __restrict__ xs, float* __restrict__ hs, int lane,
+                                             const uint32_t (&bias)[ROWS == 128 ? 2 : 1],
+                                             const uint32_t (&scale)[ROWS == 128 ? 2 : 1]) {
   float acc[ROWS == 128 ? 2 : 1];
 #pragma unroll
   for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) acc[r] = 0.0f;
@@ -150,8 +183,8 @@ __device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, 
   for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) {
     const int j = (ROWS == 32) ? (lane & 31) : lane + 64 * r;
     float v = acc[r];
-    if (WDT == 2) v *= reinterpret_cast<const float*>(wbase + sc_off)[j];
-    v += load_bias<WDT>(wbase + b_off, j);
+    if (WDT == 2) v *= scale_of<WDT>(scale[r]);
+    v += bias_of<WDT>(bias[r]);
     v = fmaxf(v, 0.0f);
     if (ROWS != 32 || lane < 32) hs[j] = v;
   }
@@ -159,44 +192,64 @@ __device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, 
 }
 
 // Output layer [8][H2] values: lane l = 8a + g sums H2/8 products of row a,
-// then a butterfly over g; returns logit a (rows a >= A are zero).
+// then a butterfly over g; logit a (rows a >= A are zero).  The lane's weight
+// words are loaded before layer 2 streams (load_w3) and used after it.
 template <int WDT, int H2>
-__device__ __forceinline__ float output_layer(const uint8_t* __restrict__ wbase, const Layout& L,
-                                              const float* __restrict__ h2, int lane) {
-  constexpr int NV = H2 / 8;
-  const int a = lane >> 3, g = lane & 7;
-  const int first = a * H2 + g * NV;
-  const float* hv = h2 + g * NV;
+struct W3 {
+  static constexpr int NV = H2 / 8;                                      // values per lane
+  static constexpr int NW = (WDT == 0) ? NV : (WDT == 1) ? NV / 2 : NV / 4;  // 32-bit words per lane
+  uint32_t w[NW];
+};
+
+template <int WDT, int H2>
+__device__ __forceinline__ void load_w3(const uint8_t* __restrict__ wbase, const Layout& L, int lane, W3<WDT, H2>& o) {
+  constexpr int NV = W3<WDT, H2>::NV, NW = W3<WDT, H2>::NW;
+  constexpr int VB = (WDT == 0) ? 4 : (WDT == 1) ? 2 : 1;  // bytes per value
+  const int first = (lane >> 3) * H2 + (lane & 7) * NV;
+  const uint8_t* p = wbase + L.s_w3 + (uint64_t)first * VB;  // 4 * NW bytes, aligned to min(16, 4 * NW)
+  if (NW >= 4) {
+#pragma unroll
+    for (int q = 0; q < NW / 4; ++q) {
+      const u32x4 v = reinterpret_cast<const u32x4*>(p)[q];
+      o.w[4 * q] = v.x;
+      o.w[4 * q + 1] = v.y;
+      o.w[4 * q + 2] = v.z;
+      o.w[4 * q + 3] = v.w;
+    }
+  } else if (NW == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    o.w[0] = v.x;
+    o.w[NW - 1] = v.y;
+  } else {
+    o.w[0] = *reinterpret_cast<const uint32_t*>(p);
+  }
+}
+
+template <int WDT, int H2>
+__device__ __forceinline__ float output_layer(const W3<WDT, H2>& o, const float* __restrict__ h2, int lane,
+                                              uint32_t b3, uint32_t s3) {
+  constexpr int NV = W3<WDT, H2>::NV;
+  const float* hv = h2 + (lane & 7) * NV;
   float part = 0.0f;
   if (WDT == 0) {
-    const float4* w = reinterpret_cast<const float4*>(wbase + L.s_w3) + first / 4;
 #pragma unroll
-    for (int q = 0; q < NV / 4; ++q) {
-      const float4 v = w[q];
-      part = __builtin_fmaf(v.x, hv[4 * q + 0], part);
-      part = __builtin_fmaf(v.y, hv[4 * q + 1], part);
-      part = __builtin_fmaf(v.z, hv[4 * q + 2], part);
-      part = __builtin_fmaf(v.w, hv[4 * q + 3], part);
-    }
+    for (int q = 0; q < NV; ++q) part = __builtin_fmaf(__uint_as_float(o.w[q]), hv[q], part);
   } else if (WDT == 1) {
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(wbase + L.s_w3) + first / 2;
 #pragma unroll
     for (int q = 0; q < NV / 2; ++q) {
-      const uint32_t v = w[q];
-      part = __builtin_fmaf(bf16lo(v), hv[2 * q + 0], part);
-      part = __builtin_fmaf(bf16hi(v), hv[2 * q + 1], part);
+      part = __builtin_fmaf(bf16lo(o.w[q]), hv[2 * q + 0], part);
+      part = __builtin_fmaf(bf16hi(o.w[q]), hv[2 * q + 1], part);
     }
   } else {
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(wbase + L.s_w3 + first);
 #pragma unroll
     for (int q = 0; q < NV / 4; ++q)
-      part = dot_fp8_word(w[q], make_float4(hv[4 * q], hv[4 * q + 1], hv[4 * q + 2], hv[4 * q + 3]), part);
+      part = dot_fp8_word(o.w[q], make_float4(hv[4 * q], hv[4 * q + 1], hv[4 * q + 2], hv[4 * q + 3]), part);
   }
   part += __shfl_xor(part, 1);
   part += __shfl_xor(part, 2);
   part += __shfl_xor(part, 4);
-  if (WDT == 2) part *= reinterpret_cast<const float*>(wbase + L.s_sc3)[a];
-  part += load_bias<WDT>(wbase + L.s_b3, a);
+  if (WDT == 2) part *= scale_of<WDT>(s3);
+  part += bias_of<WDT>(b3);
   return part;
 }
 
@@ -365,9 +418,13 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
 
     // ---- 2. the agent's MLP, weights streamed once from HBM ----
     const uint8_t* wbase = d.store + (uint64_t)cur.slot * L.sstride;
-    hidden_layer<WDT, H, U>(wbase, L.s_w1, L.s_b1, L.s_sc1, (int)L.KBv, xs, h1s, lane);
-    hidden_layer<WDT, H, U>(wbase, L.s_w2, L.s_b2, L.s_sc2, H / VPL, h1s, h2s, lane);
-    const float lg = output_layer<WDT, H>(wbase, L, h2s, lane);
+    Tail<WDT, H> tl;
+    load_tail<WDT, H>(wbase, L, lane, tl);
+    hidden_layer<WDT, H, U>(wbase, L.s_w1, (int)L.KBv, xs, h1s, lane, tl.b1, tl.s1);
+    W3<WDT, H> w3;
+    load_w3<WDT, H>(wbase, L, lane, w3);
+    hidden_layer<WDT, H, U>(wbase, L.s_w2, H / VPL, h1s, h2s, lane, tl.b2, tl.s2);
+    const float lg = output_layer<WDT, H>(w3, h2s, lane, tl.b3, tl.s3);
 
     // ---- 3. softmax inverse-CDF sample ----
     float l[8];
