@@ -434,10 +434,12 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
 #pragma unroll
     for (int a = 1; a < 8; ++a)
       if (a < A) m = fmaxf(m, l[a]);
+    // one exponential per lane (lane 8a + g holds logit a), then gathered in order
+    const float e_lane = ((lane >> 3) < A) ? expf(lg - m) : 0.0f;
     float C[8], wk[8], accum = 0.0f;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      wk[a] = (a < A) ? expf(l[a] - m) : 0.0f;
+      wk[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e_lane), 8 * a));
       accum += wk[a];
       C[a] = accum;
     }
