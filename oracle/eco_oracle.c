@@ -16,8 +16,12 @@
  *   - Policy (Sec. 3.3): per-agent memoryless MLP with two ReLU hidden layers
  *     and a linear head; actions drawn from the softmax (temperature 1).
  *   - Actions (Sec. 3.2 "Actions"): rest, rotate CCW/CW, forward, eat,
- *     reproduce (and an inert attack slot).  Contested or occupied targets do
- *     not move; here the lowest slot wins a contested empty cell.
+ *     reproduce, attack.  Contested or occupied targets do not move; here the
+ *     lowest slot wins a contested empty cell.  With attacks enabled (the "+A"
+ *     worlds), an attack kills every other agent in the 3x3 square of cells
+ *     directly ahead of the attacker; a dead agent's carried resource returns
+ *     to its cell (Sec. 3.2, health points; App. "Varying Attack Strength", full
+ *     strength).
  *   - Resources (Sec. 3.2 "Resources"): every step costs energy, eating moves a
  *     resource unit from the cell into the agent, energy slowly regrows on
  *     empty cells (Bernoulli per cell and step).
@@ -339,6 +343,8 @@ static int validate(const orc_desc* d) {
     if (d->window > d->width || d->window > d->height) return fail("window larger than the grid");
     if (d->n_scalars != 4 && d->n_scalars != 8) return fail("n_scalars must be 4 or 8");
     if (d->n_actions != 5 && d->n_actions != 7) return fail("n_actions must be 5 or 7");
+    if (d->attack_enabled > 1) return fail("attack_enabled must be 0 or 1");
+    if (d->attack_enabled && d->n_actions != 7) return fail("attacks need the seven-action head");
     if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
     if (d->capacity < d->n_agents_init) return fail("capacity below the initial population");
     if ((uint64_t)d->n_agents_init > (uint64_t)d->width * d->height) return fail("more agents than cells");
@@ -643,10 +649,43 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
         }
     }
 
-    /* 5. Eat, pay the step cost, die at energy <= 0; survivors age. */
+    /* 4b. Attacks, after every move.  An attacker (which neither turned nor
+     *     moved this step) strikes the cells 1, 2 and 3 ahead of it and one to
+     *     either side of those: the 3x3 square directly in front.  On a torus
+     *     smaller than the square it may wrap onto the attacker's own cell,
+     *     which is never struck by its own attack.  All attacks land at once:
+     *     an attacker standing in another attacker's square is killed too, and
+     *     its own attack still lands.  Full strength: every struck agent dies. */
+    uint8_t* struck = (uint8_t*)calloc(w->cells ? w->cells : 1, 1);
+    if (w->d.attack_enabled) {
+        for (uint32_t s = 0; s < cap; ++s) {
+            if (!live[s] || w->action[s] != ORC_ATTACK) continue;
+            const int f = w->facing[s], r = (f + 1) % 4;   /* the heading to the attacker's right */
+            const int64_t x = w->pos[s] % (int32_t)w->W, y = w->pos[s] / (int32_t)w->W;
+            for (int ahead = 1; ahead <= 3; ++ahead)
+                for (int side = -1; side <= 1; ++side) {
+                    uint32_t c = wrap_cell(w, x + ahead * DX[f] + side * DX[r], y + ahead * DY[f] + side * DY[r]);
+                    if (c != (uint32_t)w->pos[s]) struck[c] = 1;
+                }
+        }
+    }
+
+    /* 5. Struck agents die where they stand and their carried energy returns to
+     *    the cell as one resource unit (the resource layer holds 0 or 1 unit per
+     *    cell).  The others eat, pay the step cost and die at energy <= 0 (they
+     *    carry nothing then); survivors age. */
     for (uint32_t s = 0; s < cap; ++s) {
         if (!live[s]) continue;
         uint32_t cell = (uint32_t)w->pos[s];
+        if (struck[cell]) {
+            w->alive[s] = 0;
+            w->occ[cell] = -1;
+            w->res[cell] = 1;
+            w->energy[s] = 0;
+            st->deaths++;
+            st->killed++;
+            continue;
+        }
         if (w->action[s] == ORC_EAT && w->res[cell] > 0) {
             w->res[cell] -= 1;
             w->energy[s] += w->d.e_eat;
@@ -730,6 +769,7 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
     /* 8. Advance the clock and record the step's statistics. */
     w->step += 1;
     compute_stats_tail(w);
+    free(struck);
     free(claim);
     free(tgt);
     free(live);

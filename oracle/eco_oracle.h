@@ -25,7 +25,8 @@ extern "C" {
 /* Weight storage formats the oracle evaluates logits on. */
 enum { ORC_FP32 = 0, ORC_BF16 = 1, ORC_FP8 = 2 };
 
-/* Actions.  A = 5 uses 0..4; A = 7 adds REPRODUCE and ATTACK (inert). */
+/* Actions.  A = 5 uses 0..4; A = 7 adds REPRODUCE and ATTACK (ATTACK does
+ * nothing unless the world has attack_enabled). */
 enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 4,
        ORC_REPRODUCE = 5, ORC_ATTACK = 6 };
 
@@ -41,12 +42,14 @@ typedef struct {
     uint32_t hidden1, hidden2, n_actions;
     int32_t  e_init, e_cost, e_eat, e_repro, e_child;
     uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
+    uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 */
     uint64_t seed;
 } orc_desc;
 
-/* Per-step statistics (the measurement interface of App. E). */
+/* Per-step statistics (the measurement interface of App. E).  deaths counts
+ * every death of the step; killed is the part of it caused by attacks. */
 typedef struct {
-    uint64_t step, population, births, deaths, eaten, regrown, moves_ok, moves_blocked,
+    uint64_t step, population, births, deaths, killed, eaten, regrown, moves_ok, moves_blocked,
              births_blocked_cell, births_blocked_capacity, resource_total, action_hist[8];
     double   energy_total, trait_mean, trait_var;
 } orc_stats;

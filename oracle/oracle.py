@@ -26,13 +26,13 @@ class OrcDesc(ctypes.Structure):
         ("hidden1", ctypes.c_uint32), ("hidden2", ctypes.c_uint32), ("n_actions", ctypes.c_uint32),
         ("e_init", ctypes.c_int32), ("e_cost", ctypes.c_int32), ("e_eat", ctypes.c_int32),
         ("e_repro", ctypes.c_int32), ("e_child", ctypes.c_int32),
-        ("wdtype", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("wdtype", ctypes.c_uint32), ("attack_enabled", ctypes.c_uint32), ("seed", ctypes.c_uint64),
     ]
 
 
 class OrcStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
-        "step", "population", "births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+        "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
         ("action_hist", ctypes.c_uint64 * 8),
         ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double)]

@@ -12,6 +12,10 @@ worlds and to run the hand-traced cases.  Rules (paper sections):
   lowest slot wins a contested empty cell); every step costs energy; eating
   moves a resource unit into the agent; a child appears directly behind its
   single parent and receives a fixed amount of energy; death at energy <= 0.
+  With attacks enabled, an attacker kills every other agent in the 3x3 square
+  directly in front of it (rows 1..3 ahead, one column to either side), after
+  the moves; each victim leaves one resource unit on its cell (a dead agent's
+  carried resources return to the cell it stood on).
 * Sec. 3.3: per-agent MLP with two ReLU hidden layers and a linear head;
   softmax sampling; zero-mean Gaussian initial weights with zero biases;
   children copy the parent's weights plus Gaussian noise.
@@ -163,7 +167,7 @@ class SpecWorld:
     def step(self, actions=None):
         c = self.c
         n = self.step_no
-        st = {k: 0 for k in ("births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+        st = {k: 0 for k in ("births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
                              "births_blocked_cell", "births_blocked_capacity")}
         st["action_hist"] = [0] * 8
         live = sorted(self.agents)
@@ -204,9 +208,31 @@ class SpecWorld:
                 st["moves_ok"] += 1
             else:
                 st["moves_blocked"] += 1
+        # attacks land on the post-move positions, all at once
+        hit = set()
+        if c.get("attack_enabled", 0):
+            for s in live:
+                ag = self.agents[s]
+                if ag["action"] != ATTACK:
+                    continue
+                x, y = self._xy(ag["cell"])
+                fx, fy = HEADINGS[ag["facing"]]
+                rx, ry = -fy, fx
+                for ahead in (1, 2, 3):
+                    for side in (-1, 0, 1):
+                        cell = self._cell(x + ahead * fx + side * rx, y + ahead * fy + side * ry)
+                        if cell != ag["cell"]:
+                            hit.add(cell)
         # eat, cost, death, age
         for s in live:
             ag = self.agents[s]
+            if ag["cell"] in hit:
+                self.occ[ag["cell"]] = -1
+                self.res[ag["cell"]] = 1
+                del self.agents[s]
+                st["deaths"] += 1
+                st["killed"] += 1
+                continue
             if ag["action"] == EAT and self.res[ag["cell"]] > 0:
                 self.res[ag["cell"]] -= 1
                 ag["energy"] += c["e_eat"]

@@ -279,7 +279,7 @@ def run_both(cfg, st, actions):
     ost = o.state()
     assert_same_state(ost, sp.state(), "oracle vs spec")
     ostats = o.stats()
-    for k in ("births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked", "births_blocked_cell",
+    for k in ("births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked", "births_blocked_cell",
               "births_blocked_capacity", "population", "resource_total"):
         assert ostats[k] == sst[k], k
     return ost, ostats
@@ -432,12 +432,122 @@ def test_energy_bin_channel():
 
 
 # ---------------------------------------------------------------------------
+# Attacks ("+A" worlds): hand-traced steps on an 8x8 torus.  The attacker
+# strikes the 3x3 square directly ahead (rows 1..3 ahead, one column to either
+# side) after the moves; struck agents die and leave one resource unit.
+# ---------------------------------------------------------------------------
+ATK = 6
+
+
+def atk_cfg(**kw):
+    c = dict(width=8, height=8, n_actions=7, attack_enabled=1, capacity=8)
+    c.update(kw)
+    return tiny_cfg(**c)
+
+
+def test_A1_front_square_only():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 3, 5, N, 100)          # attacker: square x 2..4, y 2..4
+    place(st, 8, 1, 2, 4, E, 100)          # ahead 1, left: killed
+    place(st, 8, 2, 4, 2, S, 100)          # ahead 3, right: killed
+    place(st, 8, 3, 3, 1, N, 100)          # ahead 4: survives
+    place(st, 8, 4, 5, 3, N, 100)          # two to the right: survives
+    place(st, 8, 5, 3, 6, N, 100)          # behind: survives
+    out, s = run_both(atk_cfg(), st, [ATK, 0, 0, 0, 0, 0, 0, 0])
+    assert s["killed"] == 2 and s["deaths"] == 2 and s["population"] == 4
+    assert list(out["alive"][:6]) == [1, 0, 0, 1, 1, 1]
+    assert out["res"][4 * 8 + 2] == 1 and out["res"][2 * 8 + 4] == 1 and s["resource_total"] == 2
+    assert out["occ"][4 * 8 + 2] == -1 and out["occ"][2 * 8 + 4] == -1
+    assert all(out["energy"][k] == 99 for k in (0, 3, 4, 5))
+    assert s["action_hist"][ATK] == 1
+
+
+def test_A2_facing_east_and_torus_wrap():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 7, 3, E, 100)          # square x 0..2 (wrapped), y 2..4
+    place(st, 8, 1, 0, 4, N, 100)          # killed (wrap)
+    place(st, 8, 2, 2, 2, N, 100)          # killed
+    place(st, 8, 3, 3, 3, N, 100)          # x = 3: ahead 4, survives
+    place(st, 8, 4, 6, 0, N, 100)          # second attacker: square x 5..7, y 7, 6, 5 (wrapped)
+    place(st, 8, 5, 7, 6, W, 100)          # killed by slot 4
+    place(st, 8, 6, 5, 4, W, 100)          # y = 4: ahead 4 of slot 4, survives
+    out, s = run_both(atk_cfg(), st, [ATK, 0, 0, 0, ATK, 0, 0, 0])
+    assert s["killed"] == 3
+    assert list(out["alive"][:7]) == [1, 0, 0, 1, 1, 0, 1]
+    assert out["res"][4 * 8 + 0] == 1 and out["res"][2 * 8 + 2] == 1 and out["res"][6 * 8 + 7] == 1
+
+
+def test_A3_mutual_kills():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 3, 2, S, 100)          # strikes y 3..5
+    place(st, 8, 1, 3, 4, N, 100)          # strikes y 3..1
+    out, s = run_both(atk_cfg(), st, [ATK, ATK, 0, 0, 0, 0, 0, 0])
+    assert s["killed"] == 2 and s["population"] == 0
+    assert out["res"][2 * 8 + 3] == 1 and out["res"][4 * 8 + 3] == 1
+
+
+def test_A4_moves_resolve_before_attacks():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 3, 5, N, 100)          # square x 2..4, y 2..4
+    place(st, 8, 1, 3, 1, S, 100)          # moves into (3, 2): killed there
+    place(st, 8, 2, 2, 4, W, 100)          # moves out to (1, 4): survives
+    place(st, 8, 3, 4, 4, E, 100)          # blocked by slot 4, stays in the square: killed
+    place(st, 8, 4, 5, 4, N, 100)
+    out, s = run_both(atk_cfg(), st, [ATK, 3, 3, 3, 0, 0, 0, 0])
+    assert s["moves_ok"] == 2 and s["moves_blocked"] == 1 and s["killed"] == 2
+    assert list(out["alive"][:5]) == [1, 0, 1, 0, 1]
+    assert xy(out, 2, 8) == (1, 4) and out["energy"][2] == 99
+    assert out["res"][2 * 8 + 3] == 1 and out["res"][4 * 8 + 4] == 1 and out["occ"][1 * 8 + 3] == -1
+
+
+def test_A5_victims_do_not_eat_and_deposits_saturate():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 3, 5, N, 100)
+    place(st, 8, 1, 3, 4, N, 100)
+    st["res"][4 * 8 + 3] = 1
+    out, s = run_both(atk_cfg(), st, [ATK, 4, 0, 0, 0, 0, 0, 0])
+    assert s["eaten"] == 0 and s["killed"] == 1 and out["res"][4 * 8 + 3] == 1 and s["resource_total"] == 1
+
+
+def test_A6_attack_inert_when_disabled():
+    st = empty_state(8, 8, 8)
+    place(st, 8, 0, 3, 5, N, 100)
+    place(st, 8, 1, 3, 4, N, 100)
+    out, s = run_both(atk_cfg(attack_enabled=0), st, [ATK, 0, 0, 0, 0, 0, 0, 0])
+    assert s["killed"] == 0 and s["deaths"] == 0 and s["action_hist"][ATK] == 1
+    assert list(out["alive"][:2]) == [1, 1] and out["energy"][0] == 99
+
+
+def test_A7_square_wrapping_onto_the_attacker_spares_it():
+    st = empty_state(3, 3, 4)
+    place(st, 3, 0, 1, 1, N, 100)          # on a 3x3 torus the square is every cell
+    place(st, 3, 1, 0, 0, E, 100)
+    place(st, 3, 2, 2, 2, W, 100)
+    out, s = run_both(atk_cfg(width=3, height=3, window=1, capacity=4), st, [ATK, 0, 0, 0])
+    assert s["killed"] == 2 and list(out["alive"][:3]) == [1, 0, 0] and out["energy"][0] == 99
+    assert out["res"][0] == 1 and out["res"][8] == 1 and out["res"][4] == 0
+
+
+def test_A8_victims_slot_and_cell_reused_by_a_birth():
+    st = empty_state(8, 8, 3, uid_next=100)
+    place(st, 8, 0, 3, 5, N, 100)
+    place(st, 8, 1, 4, 2, N, 100)          # ahead 3, right: killed
+    place(st, 8, 2, 5, 2, E, 250, uid=42)  # outside the square; the cell behind it is (4, 2)
+    out, s = run_both(atk_cfg(capacity=3), st, [ATK, 0, 5])
+    assert s["killed"] == 1 and s["births"] == 1
+    assert out["alive"][1] == 1 and xy(out, 1, 8) == (4, 2) and out["parent_uid"][1] == 42
+    assert out["uid"][1] == 100 and out["energy"][1] == 100 and out["energy"][2] == 149
+    assert out["res"][2 * 8 + 4] == 1
+
+
+# ---------------------------------------------------------------------------
 # N-version: C oracle vs python spec on tiny worlds, policy-sampled actions
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("seed", [0, 1])
-def test_oracle_matches_spec_free_running(seed):
+@pytest.mark.parametrize("seed,attack", [(0, 0), (1, 0), (2, 1)])
+def test_oracle_matches_spec_free_running(seed, attack):
     cfg = wl.desc(width=12, height=10, n_agents_init=14, capacity=24, window=3, n_scalars=8, hidden1=32,
-                  hidden2=32, n_actions=5, resource_density=0.5, regrow_prob=0.05, e_init=185, seed=seed)
+                  hidden2=32, n_actions=7 if attack else 5, attack_enabled=attack, resource_density=0.5,
+                  regrow_prob=0.05, e_init=185, seed=seed)
     o = orc.OracleWorld(cfg)
     sp = spec.SpecWorld(cfg)
     assert_same_state(o.state(), sp.state(), "init")
@@ -449,7 +559,7 @@ def test_oracle_matches_spec_free_running(seed):
         for k in live:
             np.testing.assert_allclose(logits[k], spl[k], rtol=1e-12, atol=1e-12)
         assert_same_state(o.state(), sp.state(), f"step {s}")
-        assert o.stats()["births"] == sst["births"]
+        assert o.stats()["births"] == sst["births"] and o.stats()["killed"] == sst["killed"]
         for k in sp.agents:
             np.testing.assert_array_equal(o.weights(k, master=True), np.array(sp.agents[k]["theta"]))
 
@@ -566,6 +676,7 @@ def test_regrowth_rate():
 
 def test_invalid_descs_rejected():
     for bad in [dict(window=4), dict(n_scalars=5), dict(n_actions=6), dict(capacity=10, n_agents_init=20),
-                dict(e_repro=0), dict(wdtype=7), dict(window=99)]:
+                dict(e_repro=0), dict(wdtype=7), dict(window=99), dict(attack_enabled=1),
+                dict(n_actions=7, attack_enabled=2)]:
         with pytest.raises(ValueError):
             orc.OracleWorld(wl.desc(**bad))
