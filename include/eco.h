@@ -7,7 +7,8 @@
  * egocentric window plus scalar sensors (Sec. 3.2 "Sensors"), evaluates its own
  * MLP policy (Sec. 3.3), samples an action from the softmax, and the world then
  * applies turns, forward moves (one agent per cell; a contested empty cell goes
- * to the lowest slot), eating, the per-step energy cost and death, single-parent
+ * to the lowest slot), attacks where enabled (the victims' resources return to
+ * their cells), eating, the per-step energy cost and death, single-parent
  * births directly behind the parent with Gaussian weight mutation into recycled
  * slots (Sec. 3.2 "Actions", Sec. 3.3), and resource regrowth (Sec. 3.2
  * "Resources").  The population function of Sec. 3.1 is exposed as the alive
@@ -79,7 +80,12 @@ typedef struct {
     int32_t e_init, e_cost, e_eat, e_repro, e_child;  /* units of 0.1 energy; e_repro > 0 */
     uint32_t wdtype;             /* eco_wdtype; identical for all worlds of one object */
     uint32_t keep_master;        /* reserved: BF16/FP8 always keep an FP32 master */
-    uint32_t attack_enabled;     /* must be 0 (the attack action is inert) */
+    uint32_t attack_enabled;     /* 0: ATTACK does nothing; 1 (needs n_actions = 7): ATTACK kills
+                                    every other agent in the 3x3 square directly ahead of the
+                                    attacker (rows 1..3 ahead, one column to either side, torus),
+                                    after the moves of the step; each victim leaves one resource
+                                    unit on its cell (Sec. 3.2 actions and health points; App.
+                                    "Varying Attack Strength", full strength) */
     uint32_t flags;              /* ECO_DESC_* */
     uint64_t seed;               /* Philox key of this world */
 } eco_world_desc;
@@ -88,7 +94,9 @@ typedef struct {
 typedef struct {
     uint64_t step;                     /* steps completed */
     uint64_t population;               /* live agents after the step */
-    uint64_t births, deaths, eaten, regrown;
+    uint64_t births, deaths;           /* deaths: every death of the step, attacks included */
+    uint64_t killed;                   /* agents killed by an attack this step (part of deaths) */
+    uint64_t eaten, regrown;
     uint64_t moves_ok, moves_blocked;  /* FORWARD actions that did / did not move */
     uint64_t births_blocked_cell;      /* eligible parents whose cell behind was taken */
     uint64_t births_blocked_capacity;  /* winners left without a free slot */
@@ -140,8 +148,9 @@ typedef struct {
 /* Create n_worlds worlds (all with the same window, n_scalars, hidden sizes,
  * n_actions and wdtype) and run the deterministic init of Sec. 3.3 / placement.
  * hip_stream: a hipStream_t or NULL.  alloc: NULL = hipMalloc/hipFree.
- * Errors: EINVAL (bad desc, with the field named), ENOTSUP (attack, sizes
- * without a kernel), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (bad desc, with the field named; attack_enabled other than
+ * 0/1, or 1 with n_actions = 5), ENOTSUP (sizes without a kernel), ENOMEM,
+ * EDEVICE. */
 eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void* hip_stream,
                             const eco_allocator* alloc, eco_world** out);
 void eco_world_destroy(eco_world* w);

@@ -39,6 +39,8 @@ struct WorldParams {
   float sigma;
   uint32_t n_init;
   uint32_t has_walls;
+  uint32_t attack;              // 1: the attack action kills (the "+A" worlds), 0: it does nothing
+  uint32_t pad;
 };
 
 // Mutable per-world scalars.
@@ -93,6 +95,8 @@ struct Dev {
   double* trait;
   int32_t* occ;
   uint32_t* claim;
+  uint32_t* mark;               // [total_cells] step + 1 of the last attack that struck the cell, or
+                                // null when no world of the object has attacks
   uint8_t *res, *wall;
   uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
   uint8_t* store;               // [total_slots][sstride]
@@ -187,6 +191,20 @@ __device__ __forceinline__ uint32_t neighbour(const WorldParams& w, uint32_t cel
   y += sign * dir_dy(f);
   if (x < 0) x += (int)w.W; else if (x >= (int)w.W) x -= (int)w.W;
   if (y < 0) y += (int)w.H; else if (y >= (int)w.H) y -= (int)w.H;
+  return (uint32_t)y * w.W + (uint32_t)x;
+}
+
+// Local cell `ahead` steps along facing f and `side` steps to the right of that
+// heading (negative: to the left), torus; |ahead|, |side| <= 3.  Used for the
+// attack square, so not on the hot path of the step.
+__device__ __forceinline__ uint32_t offset_cell(const WorldParams& w, uint32_t cell, int f, int ahead, int side) {
+  const int r = (f + 1) & 3;
+  int x = (int)(cell % w.W) + ahead * dir_dx(f) + side * dir_dx(r);
+  int y = (int)(cell / w.W) + ahead * dir_dy(f) + side * dir_dy(r);
+  x %= (int)w.W;
+  y %= (int)w.H;
+  if (x < 0) x += (int)w.W;
+  if (y < 0) y += (int)w.H;
   return (uint32_t)y * w.W + (uint32_t)x;
 }
 

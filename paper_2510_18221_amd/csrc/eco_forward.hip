@@ -483,6 +483,18 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
       }
       d.tgt[slot] = tg;
     }
+    // An attacker (it neither turns nor moves) stamps the 3x3 square directly
+    // ahead of it, rows 1..3 ahead, one column to either side, with this step;
+    // the move kernel kills whoever stands on a stamped cell after the moves.
+    // The square can wrap onto the attacker's own cell on a small torus: that
+    // cell is skipped.  Equal stamps from several attackers are idempotent.
+    if (wp.attack && !d.dry) {
+      const int a = d.inject ? (int)d.act_in[slot] : as;
+      if (a == ATTACK && lane < 9) {
+        const uint32_t c = offset_cell(wp, (uint32_t)cur.pos, cur.facing, 1 + lane / 3, lane % 3 - 1);
+        if (c != (uint32_t)cur.pos) d.mark[wp.cell_off + c] = cur.step + 1u;
+      }
+    }
     if (has_next) {
       cur = nxt;
 #pragma unroll

@@ -178,7 +178,8 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (!(d.resource_density >= 0.0f && d.resource_density <= 1.0f)) return bad(ECO_EINVAL, "resource_density", "outside [0,1]");
   if (!(d.regrow_prob >= 0.0f && d.regrow_prob <= 1.0f)) return bad(ECO_EINVAL, "regrow_prob", "outside [0,1]");
   if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
-  if (d.attack_enabled) return bad(ECO_ENOTSUP, "attack_enabled", "is not supported");
+  if (d.attack_enabled > 1) return bad(ECO_EINVAL, "attack_enabled", "must be 0 or 1");
+  if (d.attack_enabled && d.n_actions != 7) return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7");
   auto okh = [](uint32_t h) { return h == 32 || h == 64 || h == 128; };
   if (!okh(d.hidden1) || !okh(d.hidden2)) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be 32, 64 or 128");
   if (d.hidden1 != d.hidden2) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be equal");
@@ -595,6 +596,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   uint64_t so = 0, co = 0;
   w->wp.resize(n_worlds);
   uint32_t max_cells = 0;
+  bool any_attack = false;
   for (uint32_t i = 0; i < n_worlds; ++i) {
     const eco_world_desc& d = descs[i];
     WorldParams& p = w->wp[i];
@@ -615,6 +617,8 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     p.sigma = d.mutation_sigma;
     p.n_init = d.n_agents_init;
     p.has_walls = 0;
+    p.attack = d.attack_enabled;
+    any_attack |= d.attack_enabled != 0;
     w->tile_rng_h.push_back(w->n_slot_tiles);
     for (uint32_t s = 0; s < p.cap; s += kSlotTileH) {
       w->slot_tiles_h.push_back(Tile{i, s, std::min(kSlotTileH, p.cap - s), 0});
@@ -666,6 +670,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.trait = (double*)A(8 * TS);
   d.occ = (int32_t*)A(4 * TC);
   d.claim = (uint32_t*)A(4 * TC);
+  d.mark = any_attack ? (uint32_t*)A(4 * TC) : nullptr;
   d.res = (uint8_t*)A(TC);
   d.wall = (uint8_t*)A(TC);
   d.sense = (uint8_t*)A(TC);
@@ -1104,6 +1109,7 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
   HIPCHK(w, cp(w->d.act + p.slot_off, cap), "write action");
   HIPCHK(w, cp(w->d.res + p.cell_off, cells), "write res");
   HIPCHK(w, cp(w->d.wall + p.cell_off, cells), "write wall");
+  if (p.attack) HIPCHK(w, hipMemsetAsync(w->d.mark + p.cell_off, 0, cells * 4, s), "clear attack stamps");
   if (walls != (w->wp[world].has_walls != 0)) {
     w->wp[world].has_walls = walls ? 1u : 0u;
     HIPCHK(w, hipMemcpyAsync((void*)(w->d.wp + world), &w->wp[world], sizeof(WorldParams), hipMemcpyHostToDevice, s),

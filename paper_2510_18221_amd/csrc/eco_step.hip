@@ -27,7 +27,8 @@ constexpr int kSlotPart = 16;    // u32 counters per slot tile
 constexpr int kCellPart = 2;     // u32 counters per cell tile
 
 // Per-slot-tile counters (index in the partials row).
-enum { PC_HIST = 0, PC_MOVES_OK = 8, PC_MOVES_BLOCKED = 9, PC_EATEN = 10, PC_DEATHS = 11, PC_BB_CELL = 12 };
+enum { PC_HIST = 0, PC_MOVES_OK = 8, PC_MOVES_BLOCKED = 9, PC_EATEN = 10, PC_DEATHS = 11, PC_BB_CELL = 12,
+       PC_KILLED = 13 };
 
 // ---------------------------------------------------------------------------
 // Small block helpers
@@ -287,6 +288,7 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
   const WorldParams wp = d.wp[tl.world];
+  const uint32_t stamp = (uint32_t)d.wv[tl.world].step + 1u;   // attack stamp of this step
   if (threadIdx.x < tl.count) {
     const uint32_t local = tl.start + threadIdx.x;
     const uint32_t slot = wp.slot_off + local;
@@ -308,24 +310,36 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
         }
       }
       int E = d.energy[slot];
-      if (a == EAT && d.res[wp.cell_off + cell] > 0) {
-        d.res[wp.cell_off + cell] -= 1;
-        E += wp.e_eat;
-        atomicAdd(&cnt[PC_EATEN], 1u);
-      }
-      E -= wp.e_cost;
-      if (E <= 0) {
+      if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
+        // struck after the moves: dies where it stands; its carried energy goes
+        // back to the cell as one resource unit (cells hold 0 or 1 unit)
         d.flags[slot] = 0;
         d.occ[wp.cell_off + cell] = -1;
+        d.res[wp.cell_off + cell] = 1;
+        E = 0;
         atomicAdd(&cnt[PC_DEATHS], 1u);
+        atomicAdd(&cnt[PC_KILLED], 1u);
       } else {
-        d.age[slot] += 1;
+        if (a == EAT && d.res[wp.cell_off + cell] > 0) {
+          d.res[wp.cell_off + cell] -= 1;
+          E += wp.e_eat;
+          atomicAdd(&cnt[PC_EATEN], 1u);
+        }
+        E -= wp.e_cost;
+        if (E <= 0) {
+          d.flags[slot] = 0;
+          d.occ[wp.cell_off + cell] = -1;
+          atomicAdd(&cnt[PC_DEATHS], 1u);
+        } else {
+          d.age[slot] += 1;
+        }
       }
       d.energy[slot] = E;
     }
   }
   __syncthreads();
-  if (threadIdx.x < 12) part[blockIdx.x * kSlotPart + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < 12 || threadIdx.x == PC_KILLED)
+    part[blockIdx.x * kSlotPart + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Eligible parents claim the empty cell directly behind them (slot tiles), and
@@ -658,6 +672,7 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
       st.births_blocked_cell = d.cnt[w].births_blocked_cell + s_cnt[PC_BB_CELL];
       st.births_blocked_capacity = d.cnt[w].births_blocked_capacity;
       st.deaths = s_cnt[PC_DEATHS];
+      st.killed = s_cnt[PC_KILLED];
       st.eaten = s_cnt[PC_EATEN];
       st.moves_ok = s_cnt[PC_MOVES_OK];
       st.moves_blocked = s_cnt[PC_MOVES_BLOCKED];
@@ -731,6 +746,7 @@ __global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restric
     d.res[g] = ((uint64_t)draw32(wp, c, 0u, ST_RESINIT) < wp.density_thr) ? 1 : 0;
     d.occ[g] = -1;
     d.claim[g] = 0xFFFFFFFFu;
+    if (wp.attack) d.mark[g] = 0;
     d.wall[g] = 0;
   }
 }

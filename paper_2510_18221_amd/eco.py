@@ -47,7 +47,7 @@ class Desc(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
-        "step", "population", "births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+        "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
         ("action_hist", ctypes.c_uint64 * 8),
         ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double)]

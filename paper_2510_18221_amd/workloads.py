@@ -83,13 +83,16 @@ def random_actions(cap, n_actions, seed, step):
     return rng.integers(0, n_actions, size=cap, dtype=np.uint8)
 
 
-def biased_actions(cap, n_actions, seed, step, p_forward=0.3, p_eat=0.3):
-    """Seeded actions with more moves and meals (exercises births and conflicts)."""
+def biased_actions(cap, n_actions, seed, step, p_forward=0.3, p_eat=0.3, p_attack=0.0):
+    """Seeded actions with more moves and meals (exercises births and conflicts);
+    with seven actions, p_attack more of them attack."""
     rng = np.random.default_rng([seed, step, 0xB1A5])
     u = rng.random(cap)
     a = rng.integers(0, n_actions, size=cap, dtype=np.uint8)
     a[u < p_forward] = 3
     a[(u >= p_forward) & (u < p_forward + p_eat)] = 4
     if n_actions == 7:
-        a[(u >= p_forward + p_eat) & (u < p_forward + p_eat + 0.2)] = 5
+        p0 = p_forward + p_eat
+        a[(u >= p0) & (u < p0 + 0.2)] = 5
+        a[(u >= p0 + 0.2) & (u < p0 + 0.2 + p_attack)] = 6
     return a

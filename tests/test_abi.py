@@ -36,7 +36,8 @@ def test_validation_errors_without_device():
     out = ctypes.c_void_p()
     assert lib.eco_world_create(None, 0, None, None, ctypes.byref(out)) == eco.ECO_EINVAL
     for bad, status in [(dict(window=4), eco.ECO_EINVAL), (dict(n_scalars=3), eco.ECO_EINVAL),
-                        (dict(hidden1=48, hidden2=48), eco.ECO_ENOTSUP), (dict(attack_enabled=1), eco.ECO_ENOTSUP),
+                        (dict(hidden1=48, hidden2=48), eco.ECO_ENOTSUP), (dict(attack_enabled=1), eco.ECO_EINVAL),
+                        (dict(n_actions=7, attack_enabled=2), eco.ECO_EINVAL),
                         (dict(capacity=10), eco.ECO_EINVAL), (dict(e_repro=0), eco.ECO_EINVAL),
                         (dict(window=17), eco.ECO_ENOTSUP)]:
         d = (eco.Desc * 1)(eco.make_desc(wl.desc(**bad)))
@@ -48,7 +49,26 @@ def test_validation_errors_without_device():
     assert b"struct_size" in lib.eco_last_error()
 
 
-def test_struct_sizes_match_header():
+def test_struct_sizes_match_header(tmp_path):
+    """The ctypes mirrors of eco_world_desc and eco_stats have the header's size and
+    field offsets (the header compiled by the host C compiler)."""
+    import subprocess
     from paper_2510_18221_amd import eco
-    assert ctypes.sizeof(eco.Desc) == 96
-    assert ctypes.sizeof(eco.Stats) == 19 * 8 + 3 * 8
+    fields = {"Desc": [n for n, _ in eco.Desc._fields_], "Stats": [n for n, _ in eco.Stats._fields_]}
+    cname = {"Desc": "eco_world_desc", "Stats": "eco_stats"}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "eco.h"', "int main(void) {"]
+    for k, names in fields.items():
+        src.append(f'printf("{k} %zu\\n", sizeof({cname[k]}));')
+        for n in names:
+            src.append(f'printf("{k}.{n} %zu\\n", offsetof({cname[k]}, {n}));')
+    src.append("return 0; }")
+    (tmp_path / "t.c").write_text("\n".join(src))
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, "-o", str(tmp_path / "t"), str(tmp_path / "t.c")], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(tmp_path / "t")], capture_output=True, text=True,
+                                                       check=True).stdout.split("\n") if l)
+    for k in fields:
+        cls = getattr(eco, k)
+        assert int(out[k]) == ctypes.sizeof(cls), k
+        for n in fields[k]:
+            assert int(out[f"{k}.{n}"]) == getattr(cls, n).offset, (k, n)

@@ -210,8 +210,8 @@ def test_errors(eco):
         eco.World(wl.desc(hidden1=48, hidden2=48))
     assert e.value.status == eco.ECO_ENOTSUP
     with pytest.raises(eco.EcoError) as e:
-        eco.World(wl.desc(attack_enabled=1))
-    assert e.value.status == eco.ECO_ENOTSUP
+        eco.World(wl.desc(attack_enabled=1))   # attacks need the seven-action head
+    assert e.value.status == eco.ECO_EINVAL
     with pytest.raises(eco.EcoError):
         eco.World([wl.desc(), wl.desc(hidden1=64, hidden2=64)])
     gw = eco.World(wl.world_small())
