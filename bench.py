@@ -20,9 +20,10 @@ slow the replay, so that region's own step time is reported apart as
 timing_region_ms_per_step); it also gives the achieved rate as a fraction of
 the box's streaming-read rate, measured by the library's probe kernel (8 GiB
 read once per launch; best of three calls of five launches at three grid shapes).  Also reported: BF16 and FP8 weight storage on the
-same world, the frozen-population form (exactly 65,536 agents every step), a
-per-kernel breakdown from a few eager steps, and the CPU oracle on a bounded
-sample.
+same world, the frozen-population form (exactly 65,536 agents every step), the
+same world with attacks enabled (the paper's "+A" worlds, with its predation
+measures: attacks per agent and homicides per attack), a per-kernel breakdown
+from a few eager steps, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -43,7 +44,7 @@ def log(*a):
 
 def run_history(w, steps, s_end):
     """Agent-steps and population bookkeeping of the last `steps` steps (ending at s_end)."""
-    out = dict(agent_steps=0, pop_start=0, pop_end=0, births=0, deaths=0)
+    out = dict(agent_steps=0, pop_start=0, pop_end=0, births=0, deaths=0, attacks=0, killed=0)
     for i in range(w.n_worlds):
         hist = w.stats_history(i, steps + 1)
         assert hist[-1]["step"] == s_end
@@ -52,6 +53,8 @@ def run_history(w, steps, s_end):
         out["pop_end"] += hist[-1]["population"]
         out["births"] += sum(h["births"] for h in hist[1:])
         out["deaths"] += sum(h["deaths"] for h in hist[1:])
+        out["attacks"] += sum(h["action_hist"][6] for h in hist[1:])
+        out["killed"] += sum(h["killed"] for h in hist[1:])
     return out
 
 
@@ -294,15 +297,21 @@ def main():
     }
     if args.workload == "65k" and not args.no_variants:
         variants = {}
+        attack_cfg = dict(wl.world_65k(seed=0), attack_enabled=1)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
-                           ("fp32_frozen", wl.world_65k(seed=0, frozen=True))]:
+                           ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
+                           ("fp32_attack", attack_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
                               "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
                               "launch": r["launch"]}
+            if vcfg.get("attack_enabled"):
+                # the predation measures of the paper's Table 3 over the timed steps
+                variants[name]["attacks_per_agent"] = round(r["attacks"] / max(r["agent_steps"], 1), 4)
+                variants[name]["homicides_per_attack"] = round(r["killed"] / max(r["attacks"], 1), 4)
             log(f"[bench] {name}: {v / 1e6:.2f} M agent-steps/s")
         out["variants"] = variants
     if args.copy_probe:
