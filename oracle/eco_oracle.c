@@ -72,7 +72,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* Stream tags of the counter's third word. */
 enum { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
-       ST_MUTATE = 5, ST_REGROW = 6 };
+       ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8 };
 
 static uint32_t draw_x0(const uint32_t key[2], uint32_t a, uint32_t step, uint32_t stream, uint32_t blk) {
     uint32_t ctr[4] = {a, step, stream, blk}, out[4];
@@ -171,13 +171,16 @@ struct orc_world {
     lineage_node *nodes;
     size_t n_nodes, nodes_cap;
     double *trait;            /* [cap] squared L2 norm of the FP32 master */
+    float *colour;            /* [cap][3] colour trait (colour vision only; kept in lineage mode too,
+                                 since every observation renders the occupants' colours) */
     orc_stats stats;
 };
 
 uint32_t orc_input_dim(const orc_desc* d) { return 4u * d->window * d->window + d->n_scalars; }
 uint64_t orc_param_count(const orc_desc* d) {
     uint64_t D = orc_input_dim(d), H1 = d->hidden1, H2 = d->hidden2, A = d->n_actions;
-    return D * H1 + H1 + H1 * H2 + H2 + H2 * A + A;
+    uint64_t net = D * H1 + H1 + H1 * H2 + H2 + H2 * A + A;
+    return net + ((d->flags & ORC_EVOLVE_TEMPERATURE) ? 1u : 0u);   /* + the log temperature */
 }
 
 /* Facing 0..3 = N, E, S, W; y grows downward. */
@@ -203,8 +206,9 @@ static void layers(const orc_world* w, layer_geom L[3]) {
     L[2].rows = w->A;  L[2].cols = w->H2; L[2].w_off = o; o += (uint64_t)w->A * w->H2;  L[2].b_off = o; o += w->A;
 }
 
-/* Initial weights of slot j: N(0, 1/fan_in) weights, zero biases.  The
- * Gaussian for logical parameter p is output p%4 of block p/4 of stream WINIT. */
+/* Initial weights of slot j: N(0, 1/fan_in) weights, zero biases, and a zero log
+ * temperature (temperature 1) when it evolves.  The Gaussian for logical
+ * parameter p is output p%4 of block p/4 of stream WINIT. */
 static void init_weights(const orc_world* w, uint32_t j, float* out) {
     layer_geom L[3];
     layers(w, L);
@@ -224,6 +228,31 @@ static void init_weights(const orc_world* w, uint32_t j, float* out) {
         }
         for (uint32_t r = 0; r < L[l].rows; ++r) out[L[l].b_off + r] = 0.0f;
     }
+    if (w->d.flags & ORC_EVOLVE_TEMPERATURE) out[w->P - 1] = 0.0f;
+}
+
+/* Initial colour of slot j: three uniforms in [0, 1) from one Philox block,
+ * c_k = (x_k >> 8) 2^-24 (exact in FP32). */
+static void init_colour(const orc_world* w, uint32_t j, float* c) {
+    uint32_t ctr[4] = {j, 0u, ST_COLOUR_INIT, 0u}, x[4];
+    orc_philox4x32_10(ctr, w->key, x);
+    for (int k = 0; k < 3; ++k) c[k] = (float)((double)(x[k] >> 8) * 0x1p-24);
+}
+
+/* The child's colour: the parent's plus sigma times a Gaussian per channel (the
+ * first three of one Box-Muller block), rounded like the weights. */
+static void mutate_colour(const orc_world* w, const float* parent, uint32_t parent_slot, uint32_t step, float* child) {
+    uint32_t ctr[4] = {parent_slot, step, ST_COLOUR_MUTATE, 0u};
+    double z[4];
+    orc_gauss4(ctr, w->key, z);
+    for (int k = 0; k < 3; ++k) child[k] = (float)fma((double)w->d.mutation_sigma, z[k], (double)parent[k]);
+}
+
+uint32_t orc_colour_byte(float c) {
+    double x = (double)c;
+    if (!(x > 0.0)) x = 0.0;
+    if (x > 1.0) x = 1.0;
+    return (uint32_t)floor(x * 255.0 + 0.5);   /* x * 255 and + 0.5 are exact in FP64 */
 }
 
 /* Mutation (Sec. 3.3): child = parent + sigma * z on every parameter, with one
@@ -270,6 +299,7 @@ static void quantize(const orc_world* w, const float* master, double* out) {
             out[L[l].b_off + r] = (double)master[L[l].b_off + r];
         }
     }
+    if (w->d.flags & ORC_EVOLVE_TEMPERATURE) out[w->P - 1] = (double)master[w->P - 1];   /* like a bias */
 }
 
 static double sqnorm(const float* v, uint64_t n) {
@@ -307,6 +337,7 @@ static int seed_slot(orc_world* w, uint32_t s) {
     int64_t id = new_node(w, -1, 0, 0, s);
     if (id < 0) return fail("out of memory");
     w->node[s] = id;
+    if (w->d.flags & ORC_COLOUR_VISION) init_colour(w, s, w->colour + 3 * (uint64_t)s);
     if (!w->materialize) { w->trait[s] = NAN; return 0; }   /* lineage mode: no traits */
     float* m = w->master + (uint64_t)s * w->P;
     init_weights(w, s, m);
@@ -345,6 +376,8 @@ static int validate(const orc_desc* d) {
     if (d->n_actions != 5 && d->n_actions != 7) return fail("n_actions must be 5 or 7");
     if (d->attack_enabled > 1) return fail("attack_enabled must be 0 or 1");
     if (d->attack_enabled && d->n_actions != 7) return fail("attacks need the seven-action head");
+    if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION))
+        return fail("unknown flags");
     if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
     if (d->capacity < d->n_agents_init) return fail("capacity below the initial population");
     if ((uint64_t)d->n_agents_init > (uint64_t)d->width * d->height) return fail("more agents than cells");
@@ -368,7 +401,7 @@ void orc_destroy(orc_world* w) {
     if (!w) return;
     free(w->pos); free(w->energy); free(w->age); free(w->facing); free(w->alive); free(w->action);
     free(w->uid); free(w->puid); free(w->occ); free(w->res); free(w->wall);
-    free(w->master); free(w->stored); free(w->node); free(w->nodes); free(w->trait);
+    free(w->master); free(w->stored); free(w->node); free(w->nodes); free(w->trait); free(w->colour);
     free(w);
 }
 
@@ -393,12 +426,13 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
     w->occ = (int32_t*)malloc((size_t)w->cells * 4);
     w->res = (uint8_t*)calloc(w->cells, 1);
     w->wall = (uint8_t*)calloc(w->cells, 1);
+    w->colour = (float*)calloc((size_t)(cap ? cap : 1) * 3, sizeof(float));
     if (materialize) {
         w->master = (float*)calloc((size_t)cap * w->P + 1, sizeof(float));
         if (d->wdtype != ORC_FP32) w->stored = (double*)calloc((size_t)cap * w->P + 1, sizeof(double));
     }
     if (!w->pos || !w->energy || !w->age || !w->facing || !w->alive || !w->action || !w->uid ||
-        !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall ||
+        !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall || !w->colour ||
         (materialize && (!w->master || (d->wdtype != ORC_FP32 && !w->stored)))) {
         orc_destroy(w);
         fail("out of memory");
@@ -428,6 +462,7 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
         if (id < 0) { free(ck); orc_destroy(w); fail("out of memory"); return NULL; }
         w->node[j] = id;
         w->trait[j] = NAN;
+        if (d->flags & ORC_COLOUR_VISION) init_colour(w, j, w->colour + 3 * (uint64_t)j);
     }
     free(ck);
     /* Initial weights: independent per agent, so the loop runs in parallel. */
@@ -450,6 +485,25 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
 /* ------------------------------------------------------------------------- */
 /* Observation and policy                                                    */
 /* ------------------------------------------------------------------------- */
+/* Colour vision (Sec. 3.2 "Sensors": a top-down rendered patch of three colour
+ * channels and the local elevation difference).  A cell is drawn in its
+ * occupant's colour; an empty cell holding a resource unit in green, a wall in
+ * grey, anything else black; each channel as its 8-bit value times 2^-8.  The
+ * torus is flat, so the elevation-difference channel is zero. */
+static void render_cell(const orc_world* w, uint32_t cell, double* v) {
+    uint32_t q[3] = {0u, 0u, 0u};
+    int32_t o = w->occ[cell];
+    if (o >= 0) {
+        for (int k = 0; k < 3; ++k) q[k] = orc_colour_byte(w->colour[3 * (uint64_t)o + k]);
+    } else if (w->res[cell]) {
+        q[1] = 255u;
+    } else if (w->wall[cell]) {
+        q[0] = q[1] = q[2] = 128u;
+    }
+    for (int k = 0; k < 3; ++k) v[k] = ldexp((double)q[k], -8);
+    v[3] = 0.0;
+}
+
 int orc_observe(const orc_world* w, uint32_t slot, double* x) {
     if (slot >= w->cap || !w->alive[slot]) return fail("slot not alive");
     int f = w->facing[slot];
@@ -457,12 +511,16 @@ int orc_observe(const orc_world* w, uint32_t slot, double* x) {
     int dx = DX[f], dy = DY[f];
     int rx = -dy, ry = dx;                     /* the agent's right-hand direction */
     int S = (int)w->S, R = (int)w->R;
+    /* Row 0 is the far front.  "Around": the agent's row is the middle one;
+     * "Front": the agent's row is the last, so nothing behind it is seen. */
+    int ahead0 = (w->d.flags & ORC_FRONT_VISION) ? S - 1 : R;
     for (int r = 0; r < S; ++r) {
         for (int c = 0; c < S; ++c) {
-            int fwd = R - r, right = c - R;   /* window row 0 is the far front */
+            int fwd = ahead0 - r, right = c - R;
             uint32_t cell = wrap_cell(w, ax + fwd * dx + right * rx, ay + fwd * dy + right * ry);
             int32_t o = w->occ[cell];
             double* v = x + 4 * (r * S + c);
+            if (w->d.flags & ORC_COLOUR_VISION) { render_cell(w, cell, v); continue; }
             v[0] = (o >= 0) ? 1.0 : 0.0;
             v[1] = (double)w->res[cell];
             v[2] = (double)w->wall[cell];
@@ -516,16 +574,25 @@ static void forward(const orc_world* w, const double* theta, const double* x, do
 
 /* Softmax inverse CDF: m = max l, w_k = exp(l_k - m), C_k = w_0 + ... + w_k,
  * t = u C_{A-1}; the least k with t < C_k, else the last k with w_k > 0. */
-int orc_sample(const double* l, int A, double u) {
+/* Softmax with temperature tau = exp(log_tau) (Sec. 3.3): weights
+ * exp((l_k - max l) / tau), the largest logits weighing exactly 1. */
+int orc_sample_tempered(const double* l, int A, double log_tau, double u) {
     double m = l[0];
     for (int k = 1; k < A; ++k) if (l[k] > m) m = l[k];
+    const double inv_tau = exp(-log_tau);
     double wk[8], C[8], acc = 0.0;
-    for (int k = 0; k < A; ++k) { wk[k] = exp(l[k] - m); acc += wk[k]; C[k] = acc; }
+    for (int k = 0; k < A; ++k) {
+        wk[k] = (l[k] == m) ? 1.0 : exp((l[k] - m) * inv_tau);
+        acc += wk[k];
+        C[k] = acc;
+    }
     double t = u * C[A - 1];
     for (int k = 0; k < A; ++k) if (t < C[k]) return k;
     for (int k = A - 1; k >= 0; --k) if (wk[k] > 0.0) return k;
     return A - 1;
 }
+
+int orc_sample(const double* l, int A, double u) { return orc_sample_tempered(l, A, 0.0, u); }
 
 /* Weights of live slot s in logical order: storage (which=0) or master (which=1). */
 static int slot_theta(orc_world* w, uint32_t s, int which, double* out) {
@@ -602,7 +669,8 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
                 forward(w, theta, x, l);
                 uint32_t x0 = draw_x0(w->key, s, step32, ST_ACTION, 0);
                 double u = (double)(x0 >> 8) * 0x1p-24;
-                int a = orc_sample(l, (int)A, u);
+                int a = (w->d.flags & ORC_EVOLVE_TEMPERATURE) ? orc_sample_tempered(l, (int)A, theta[w->P - 1], u)
+                                                              : orc_sample(l, (int)A, u);
                 if (logits_out) for (uint32_t k = 0; k < A; ++k) logits_out[(uint64_t)s * A + k] = l[k];
                 if (sampled_out) sampled_out[s] = (uint8_t)a;
                 w->action[s] = (uint8_t)a;
@@ -744,6 +812,8 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
         w->uid[c] = w->uid_next + k;
         w->puid[c] = w->uid[p];
         w->node[c] = new_node(w, w->node[p], p, step32, 0);
+        if (w->d.flags & ORC_COLOUR_VISION)
+            mutate_colour(w, w->colour + 3 * (uint64_t)p, p, step32, w->colour + 3 * (uint64_t)c);
         if (w->materialize) {
             float* cm = w->master + (uint64_t)c * w->P;
             mutate(w, w->master + (uint64_t)p * w->P, p, step32, cm);
@@ -836,5 +906,22 @@ int orc_write_state(orc_world* w, const void* buf, size_t bytes) {
 
 int orc_stats_get(const orc_world* w, orc_stats* out) {
     *out = w->stats;
+    return 0;
+}
+
+int orc_read_colour(const orc_world* w, uint32_t slot, float out[3]) {
+    if (!(w->d.flags & ORC_COLOUR_VISION)) return fail("the world has no colour trait");
+    if (slot >= w->cap || !w->alive[slot]) return fail("slot not alive");
+    for (int k = 0; k < 3; ++k) out[k] = w->colour[3 * (uint64_t)slot + k];
+    return 0;
+}
+
+int orc_write_colour(orc_world* w, uint32_t slot, const float in[3]) {
+    if (!(w->d.flags & ORC_COLOUR_VISION)) return fail("the world has no colour trait");
+    if (slot >= w->cap || !w->alive[slot]) return fail("slot not alive");
+    for (int k = 0; k < 3; ++k) {
+        if (!isfinite(in[k])) return fail("colour must be finite");
+        w->colour[3 * (uint64_t)slot + k] = in[k];
+    }
     return 0;
 }

@@ -30,6 +30,17 @@ enum { ORC_FP32 = 0, ORC_BF16 = 1, ORC_FP8 = 2 };
 enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 4,
        ORC_REPRODUCE = 5, ORC_ATTACK = 6 };
 
+/* Policy and sensor options (orc_desc.flags).
+ *   ORC_FRONT_VISION: the S x S window lies ahead of the agent, which sits in the
+ *     middle of its last row, instead of around it (App. "Varying Vision Range").
+ *   ORC_EVOLVE_TEMPERATURE: every agent carries one more mutable parameter, its
+ *     log softmax temperature, after the output biases (Sec. 3.3).
+ *   ORC_COLOUR_VISION: every agent carries a 3-channel colour trait that mutates
+ *     like its weights, and the window shows the rendered colour of each cell
+ *     plus an elevation-difference channel (zero on the flat torus) (Sec. 3.2
+ *     "Sensors", Sec. 3.3). */
+enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4 };
+
 /* One world's parameters.  Energies are integers in units of 0.1 energy. */
 typedef struct {
     uint32_t width, height;            /* toroidal grid */
@@ -43,6 +54,7 @@ typedef struct {
     int32_t  e_init, e_cost, e_eat, e_repro, e_child;
     uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
     uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 */
+    uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION */
     uint64_t seed;
 } orc_desc;
 
@@ -56,7 +68,8 @@ typedef struct {
 
 typedef struct orc_world orc_world;
 
-/* Sizes derived from a desc: D = 4*S*S + n_s inputs, P parameters. */
+/* Sizes derived from a desc: D = 4*S*S + n_s inputs, P parameters (the network's,
+ * plus the log temperature when it evolves). */
 uint32_t orc_input_dim(const orc_desc* d);
 uint64_t orc_param_count(const orc_desc* d);
 
@@ -84,7 +97,8 @@ int orc_agent_logits(orc_world* w, uint32_t slot, double* out /* [A] */);
 int orc_observe(const orc_world* w, uint32_t slot, double* out /* [D] */);
 
 /* Weights of live slot `slot` in logical nn.Linear order
- * (W1[H1][D], b1, W2[H2][H1], b2, W3[A][H2], b3).
+ * (W1[H1][D], b1, W2[H2][H1], b2, W3[A][H2], b3, then the log temperature when
+ * it evolves).
  * which = 0: storage values dequantised exactly (FP32 = master), 1: FP32 master. */
 int orc_read_weights(orc_world* w, uint32_t slot, int which, double* out /* [P] */);
 
@@ -103,14 +117,22 @@ int    orc_write_state(orc_world* w, const void* buf, size_t bytes);
 
 int orc_stats_get(const orc_world* w, orc_stats* out);
 
+/* Colour trait of live slot `slot` (FP32 R, G, B), and its overwrite. */
+int orc_read_colour(const orc_world* w, uint32_t slot, float out[3]);
+int orc_write_colour(orc_world* w, uint32_t slot, const float in[3]);
+
 /* Building blocks exposed for the pins. */
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void   orc_gauss4(const uint32_t ctr[4], const uint32_t key[2], double z[4]);
 uint16_t orc_bf16_rne(float x);
 uint8_t  orc_fp8e4m3_rne_sat(float x);
 double   orc_fp8e4m3_decode(uint8_t q);
-/* Inverse-CDF softmax sample of A logits with uniform u in [0,1). */
+/* Inverse-CDF softmax sample of A logits with uniform u in [0,1); the tempered
+ * form divides the logits by exp(log_tau). */
 int    orc_sample(const double* logits, int A, double u);
+int    orc_sample_tempered(const double* logits, int A, double log_tau, double u);
+/* The 8-bit rendering of one colour channel: round(clamp(c, 0, 1) * 255), ties up. */
+uint32_t orc_colour_byte(float c);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 FP32, BF16, FP8 = 0, 1, 2
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
+FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION = 1, 2, 4   # orc_desc.flags
 
 
 class OrcDesc(ctypes.Structure):
@@ -26,7 +27,8 @@ class OrcDesc(ctypes.Structure):
         ("hidden1", ctypes.c_uint32), ("hidden2", ctypes.c_uint32), ("n_actions", ctypes.c_uint32),
         ("e_init", ctypes.c_int32), ("e_cost", ctypes.c_int32), ("e_eat", ctypes.c_int32),
         ("e_repro", ctypes.c_int32), ("e_child", ctypes.c_int32),
-        ("wdtype", ctypes.c_uint32), ("attack_enabled", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("wdtype", ctypes.c_uint32), ("attack_enabled", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -81,6 +83,12 @@ def lib():
         _lib.orc_fp8e4m3_decode.argtypes = [ctypes.c_uint8]
         _lib.orc_sample.restype = ctypes.c_int
         _lib.orc_sample.argtypes = [P, ctypes.c_int, ctypes.c_double]
+        _lib.orc_sample_tempered.restype = ctypes.c_int
+        _lib.orc_sample_tempered.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        _lib.orc_colour_byte.restype = ctypes.c_uint32
+        _lib.orc_colour_byte.argtypes = [ctypes.c_float]
+        _lib.orc_read_colour.argtypes = [P, ctypes.c_uint32, P]
+        _lib.orc_write_colour.argtypes = [P, ctypes.c_uint32, P]
     return _lib
 
 
@@ -139,6 +147,15 @@ def sample(logits, u):
     return lib().orc_sample(_ptr(l), len(l), float(u))
 
 
+def sample_tempered(logits, log_tau, u):
+    l = np.ascontiguousarray(logits, dtype=np.float64)
+    return lib().orc_sample_tempered(_ptr(l), len(l), float(log_tau), float(u))
+
+
+def colour_byte(c: float) -> int:
+    return lib().orc_colour_byte(ctypes.c_float(c))
+
+
 class OracleWorld:
     """One oracle world.  materialize=True keeps all weights (can sample)."""
 
@@ -181,6 +198,15 @@ class OracleWorld:
         out = np.empty(self.A, dtype=np.float64)
         self._check(lib().orc_agent_logits(self._h, slot, _ptr(out)))
         return out
+
+    def colour(self, slot):
+        out = np.empty(3, dtype=np.float32)
+        self._check(lib().orc_read_colour(self._h, slot, _ptr(out)))
+        return out
+
+    def write_colour(self, slot, rgb):
+        v = np.ascontiguousarray(rgb, dtype=np.float32)
+        self._check(lib().orc_write_colour(self._h, slot, _ptr(v)))
 
     def observe(self, slot):
         out = np.empty(self.D, dtype=np.float64)

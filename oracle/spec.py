@@ -16,6 +16,12 @@ worlds and to run the hand-traced cases.  Rules (paper sections):
   directly in front of it (rows 1..3 ahead, one column to either side), after
   the moves; each victim leaves one resource unit on its cell (a dead agent's
   carried resources return to the cell it stood on).
+* Options (cfg["flags"]): 1 = "Front" vision (the window lies ahead, the agent
+  in the middle of its last row; App. "Varying Vision Range"); 2 = an evolving
+  softmax temperature, one more mutable parameter (log tau) after the output
+  biases (Sec. 3.3); 4 = a 3-channel colour trait that mutates like the
+  weights, seen by others through a rendered window (three colour channels and
+  an elevation-difference channel, zero on the flat torus; Sec. 3.2, 3.3).
 * Sec. 3.3: per-agent MLP with two ReLU hidden layers and a linear head;
   softmax sampling; zero-mean Gaussian initial weights with zero biases;
   children copy the parent's weights plus Gaussian noise.
@@ -28,6 +34,7 @@ from fractions import Fraction
 
 M32 = 0xFFFFFFFF
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
+FRONT, TEMPERATURE, COLOUR = 1, 2, 4
 HEADINGS = [(0, -1), (1, 0), (0, 1), (-1, 0)]  # N, E, S, W with y pointing down
 
 
@@ -78,7 +85,8 @@ class SpecWorld:
         self.key = [c["seed"] & M32, (c["seed"] >> 32) & M32]
         self.D = 4 * self.S * self.S + c["n_scalars"]
         self.shapes = [(c["hidden1"], self.D), (c["hidden2"], c["hidden1"]), (self.A, c["hidden2"])]
-        self.P = sum(r * k + r for r, k in self.shapes)
+        self.flags = c.get("flags", 0)
+        self.P = sum(r * k + r for r, k in self.shapes) + (1 if self.flags & TEMPERATURE else 0)
         self.step_no = 0
         self.uid_next = c["n_agents_init"]
         cells = self.W * self.H
@@ -91,6 +99,8 @@ class SpecWorld:
         for j in range(c["n_agents_init"]):
             self._spawn(j, order[j], philox4x32_10([j, 0, 1, 0], self.key)[0] >> 30, c["e_init"], j, None)
             self.agents[j]["theta"] = self._init_theta(j)
+            if self.flags & COLOUR:
+                self.agents[j]["colour"] = self._init_colour(j)
 
     def _spawn(self, slot, cell, facing, energy, uid, puid):
         self.agents[slot] = {"cell": cell, "facing": facing, "energy": energy, "age": 0,
@@ -107,7 +117,31 @@ class SpecWorld:
                 p += 1
             theta += [0.0] * rows
             p += rows
+        if self.flags & TEMPERATURE:
+            theta.append(0.0)     # log temperature 0: temperature 1
         return theta
+
+    def _init_colour(self, j):
+        x = philox4x32_10([j, 0, 7, 0], self.key)
+        return [(x[k] >> 8) / 16777216.0 for k in range(3)]
+
+    @staticmethod
+    def colour_byte(c):
+        c = min(max(c, 0.0), 1.0)
+        q = Fraction(c) * 255 + Fraction(1, 2)
+        return q.numerator // q.denominator
+
+    def _render(self, cell):
+        o = self.occ[cell]
+        if o >= 0:
+            q = [self.colour_byte(v) for v in self.agents[o]["colour"]]
+        elif self.res[cell]:
+            q = [0, 255, 0]
+        elif self.wall[cell]:
+            q = [128, 128, 128]
+        else:
+            q = [0, 0, 0]
+        return [v / 256.0 for v in q] + [0.0]
 
     def _xy(self, cell):
         return cell % self.W, cell // self.W
@@ -121,11 +155,15 @@ class SpecWorld:
         fx, fy = HEADINGS[ag["facing"]]
         rx, ry = -fy, fx
         R = self.S // 2
+        top = self.S - 1 if self.flags & FRONT else R   # distance ahead of window row 0
         obs = []
         for r in range(self.S):
             for col in range(self.S):
-                ahead, right = R - r, col - R
+                ahead, right = top - r, col - R
                 cell = self._cell(ax + ahead * fx + right * rx, ay + ahead * fy + right * ry)
+                if self.flags & COLOUR:
+                    obs += self._render(cell)
+                    continue
                 o = self.occ[cell]
                 eb = 0
                 if o >= 0:  # energy bin of the occupant, 8 bins up to the reproduction threshold
@@ -151,9 +189,10 @@ class SpecWorld:
         return h
 
     @staticmethod
-    def sample(logits, u):
+    def sample(logits, u, log_tau=0.0):
         m = max(logits)
-        w = [math.exp(v - m) for v in logits]
+        inv = math.exp(-log_tau)
+        w = [1.0 if v == m else math.exp((v - m) * inv) for v in logits]
         cum, acc = [], 0.0
         for v in w:
             acc += v
@@ -174,7 +213,8 @@ class SpecWorld:
         for s in live:
             if actions is None:
                 u = (philox4x32_10([s, n, 4, 0], self.key)[0] >> 8) / 16777216.0
-                a = self.sample(self.logits(s), u)
+                lt = self.agents[s]["theta"][-1] if self.flags & TEMPERATURE else 0.0
+                a = self.sample(self.logits(s), u, lt)
             else:
                 a = int(actions[s])
             self.agents[s]["action"] = a
@@ -276,6 +316,9 @@ class SpecWorld:
                 z = gauss4([p, n, 5, q // 4], self.key)[q % 4]
                 theta.append(f32(fma(sigma, z, v)))
             self.agents[child]["theta"] = theta
+            if self.flags & COLOUR:
+                z = gauss4([p, n, 8, 0], self.key)
+                self.agents[child]["colour"] = [f32(fma(sigma, z[k], v)) for k, v in enumerate(par["colour"])]
             nb += 1
         st["births"] = nb
         self.uid_next += nb
@@ -332,4 +375,6 @@ def from_state(cfg, st):
                        "age": int(st["age"][s]), "uid": int(st["uid"][s]),
                        "puid": None if puid == 0xFFFFFFFFFFFFFFFF else puid, "action": int(st["action"][s]),
                        "theta": w._init_theta(s)}
+        if w.flags & COLOUR:
+            w.agents[s]["colour"] = w._init_colour(s)
     return w

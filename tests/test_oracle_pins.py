@@ -156,23 +156,37 @@ def test_paper_parameter_table_reading():
 # ---------------------------------------------------------------------------
 # Observation window: independent construction with numpy roll + rot90
 # ---------------------------------------------------------------------------
-def _window_numpy(st, cfg, slot):
+def _window_numpy(st, cfg, slot, colours=None):
+    """Window by numpy: a (2S-1)^2 north-up patch centred on the agent, rotated so
+    the agent faces up; "Around" keeps its centre S x S, "Front" its top S rows.
+    colours: {slot: rgb} for colour vision (channels = rendered colour, zero)."""
     Wd, Ht, Sw = cfg["width"], cfg["height"], cfg["window"]
-    R = Sw // 2
+    R, M = Sw // 2, Sw - 1
     occ = st["occ"].reshape(Ht, Wd)
-    agent = (occ >= 0).astype(np.float64)
     res = st["res"].reshape(Ht, Wd).astype(np.float64)
     wall = st["wall"].reshape(Ht, Wd).astype(np.float64)
-    ebin = np.zeros((Ht, Wd))
-    o = occ[occ >= 0]
-    ebin[occ >= 0] = np.clip(st["energy"][o].astype(np.int64) * 8 // cfg["e_repro"], 0, 7)
+    if colours is None:
+        agent = (occ >= 0).astype(np.float64)
+        ebin = np.zeros((Ht, Wd))
+        o = occ[occ >= 0]
+        ebin[occ >= 0] = np.clip(st["energy"][o].astype(np.int64) * 8 // cfg["e_repro"], 0, 7)
+        layers = (agent, res, wall, ebin)
+    else:
+        rgb = np.zeros((Ht, Wd, 3))
+        rgb[(res > 0) & (occ < 0)] = [0, 255, 0]
+        rgb[(wall > 0) & (res == 0) & (occ < 0)] = [128, 128, 128]
+        for yy, xx in zip(*np.nonzero(occ >= 0)):
+            c = np.clip(np.asarray(colours[int(occ[yy, xx])], np.float64), 0.0, 1.0)
+            rgb[yy, xx] = np.floor(c * 255 + 0.5)
+        layers = (rgb[..., 0] / 256, rgb[..., 1] / 256, rgb[..., 2] / 256, np.zeros((Ht, Wd)))
     x, y = st["pos"][slot] % Wd, st["pos"][slot] // Wd
-    rows = (np.arange(y - R, y + R + 1)) % Ht
-    cols = (np.arange(x - R, x + R + 1)) % Wd
+    rows = (np.arange(y - M, y + M + 1)) % Ht
+    cols = (np.arange(x - M, x + M + 1)) % Wd
+    front = cfg.get("flags", 0) & orc.FRONT_VISION
     chans = []
-    for layer in (agent, res, wall, ebin):
-        patch = layer[np.ix_(rows, cols)]           # row 0 = north
-        chans.append(np.rot90(patch, k=int(st["facing"][slot])))  # facing becomes "up"
+    for layer in layers:
+        big = np.rot90(layer[np.ix_(rows, cols)], k=int(st["facing"][slot]))   # row 0 = M cells ahead
+        chans.append(big[0:Sw, M - R:M + R + 1] if front else big[M - R:M + R + 1, M - R:M + R + 1])
     win = np.stack(chans, axis=-1).reshape(-1)
     e = st["energy"][slot]
     sc = [e / 256.0, min(st["age"][slot], 1024) / 1024.0, float(st["res"][st["pos"][slot]]),
@@ -182,16 +196,147 @@ def _window_numpy(st, cfg, slot):
     return np.concatenate([win, sc])
 
 
-def test_observation_matches_numpy_rot90():
+@pytest.mark.parametrize("flags", [0, orc.FRONT_VISION, orc.COLOUR_VISION, orc.FRONT_VISION | orc.COLOUR_VISION])
+def test_observation_matches_numpy_rot90(flags):
     cfg = wl.desc(width=23, height=17, n_agents_init=120, capacity=200, window=7, n_scalars=8, seed=3,
-                  resource_density=0.4)
+                  resource_density=0.4, flags=flags, mutation_sigma=0.4, e_init=199)
     w = orc.OracleWorld(cfg)
-    acts = wl.biased_actions(cfg["capacity"], cfg["n_actions"], 3, 0)
     for step in range(3):
         st = w.state()
-        for s in np.nonzero(st["alive"])[0][:60]:
-            np.testing.assert_array_equal(w.observe(int(s)), _window_numpy(st, cfg, int(s)))
+        w.write_state(dict(st, wall=(np.arange(st["wall"].size) % 11 == 0).astype(np.uint8) * (st["occ"] < 0)))
+        st = w.state()
+        live = np.nonzero(st["alive"])[0]
+        colours = {int(s): w.colour(int(s)) for s in live} if flags & orc.COLOUR_VISION else None
+        for s in live[:60]:
+            np.testing.assert_array_equal(w.observe(int(s)), _window_numpy(st, cfg, int(s), colours))
         w.step(actions=wl.biased_actions(cfg["capacity"], cfg["n_actions"], 3, step))
+
+
+def test_colour_window_hand_traced():
+    """5x5 torus, 3x3 window: the rendered colours written out by hand."""
+    cfg = wl.desc(width=5, height=5, n_agents_init=0, capacity=4, window=3, n_scalars=4, n_actions=5,
+                  resource_density=0.0, regrow_prob=0.0, seed=1, flags=orc.COLOUR_VISION)
+    st = empty_state(5, 5, 4)
+    place(st, 5, 0, 2, 2, N, 100)
+    place(st, 5, 1, 2, 1, E, 100)                # ahead of slot 0
+    place(st, 5, 2, 3, 2, S, 100)                # to its right
+    st["res"][1 * 5 + 1] = 1                     # ahead-left: resource, no agent
+    st["res"][2 * 5 + 3] = 1                     # under slot 2: the agent is drawn
+    st["wall"][3 * 5 + 3] = 1                    # behind-right
+    w = orc.OracleWorld(cfg)
+    w.write_state(st)
+    w.write_colour(0, [0.0, 0.5, 1.0])           # -> 0, 128 (127.5 rounds up), 255
+    w.write_colour(1, [0.25, 0.75, 1.5])         # -> 64, 191, 255 (clamped)
+    w.write_colour(2, [-0.5, 0.125, 0.875])      # -> 0, 32, 223
+    x = w.observe(0).reshape(-1)
+    win = x[:36].reshape(3, 3, 4) * 256
+    expect = np.zeros((3, 3, 4))
+    expect[0, 0, :3] = [0, 255, 0]               # (1,1) resource
+    expect[0, 1, :3] = [64, 191, 255]            # (2,1) slot 1
+    expect[1, 1, :3] = [0, 128, 255]             # (2,2) itself
+    expect[1, 2, :3] = [0, 32, 223]              # (3,2) slot 2 over its resource
+    expect[2, 2, :3] = [128, 128, 128]           # (3,3) wall
+    np.testing.assert_array_equal(win, expect)
+    assert x[36 + 2] == 0.0                      # resource here (own cell): none
+    cf = dict(cfg, flags=orc.COLOUR_VISION | orc.FRONT_VISION)
+    wf = orc.OracleWorld(cf)
+    wf.write_state(st)
+    wf.write_colour(1, [0.25, 0.75, 1.5])
+    wf.write_colour(0, [0.0, 0.5, 1.0])
+    wf.write_colour(2, [-0.5, 0.125, 0.875])
+    winf = wf.observe(0)[:36].reshape(3, 3, 4) * 256   # rows: 2 ahead, 1 ahead, own row
+    ef = np.zeros((3, 3, 4))
+    ef[1] = expect[0]
+    ef[2] = expect[1]
+    np.testing.assert_array_equal(winf, ef)
+
+
+def test_colour_byte_rounding():
+    vals = np.array([0.0, 1.0, -0.3, 1.7, 0.5, 0.25, 0.75, 0.125, 1 / 255, 0.999] +
+                    [(k + 0.5) / 255 for k in range(0, 255, 17)] + [k / 255 for k in range(0, 256, 15)],
+                    dtype=np.float32)
+    from fractions import Fraction
+    for v in vals:
+        c = min(max(Fraction(float(v)), Fraction(0)), Fraction(1))
+        q = c * 255 + Fraction(1, 2)
+        assert orc.colour_byte(float(v)) == q.numerator // q.denominator, v
+
+
+def test_colour_trait_init_and_mutation():
+    """Initial colours U[0,1) on a 2^-24 grid; a child's colour = parent's + sigma N(0,1)."""
+    from scipy import stats
+    cfg = wl.desc(width=64, height=64, n_agents_init=1500, capacity=3000, window=3, n_actions=5, seed=13,
+                  flags=orc.COLOUR_VISION, e_init=300, mutation_sigma=0.05)
+    w = orc.OracleWorld(cfg)
+    c0 = np.array([w.colour(j) for j in range(1500)], np.float64)
+    assert np.all((c0 >= 0) & (c0 < 1)) and np.all(c0 * 2**24 == np.floor(c0 * 2**24))
+    assert stats.kstest(c0.reshape(-1), "uniform").pvalue > 1e-3
+    st0 = w.state()
+    w.step(actions=np.zeros(3000, np.uint8))
+    st = w.state()
+    born = np.nonzero(st["alive"] & ~st0["alive"].astype(bool))[0]
+    assert len(born) > 500
+    slot_of_uid = {int(st0["uid"][j]): j for j in np.nonzero(st0["alive"])[0]}
+    z = np.array([(w.colour(int(c)).astype(np.float64) - c0[slot_of_uid[int(st["parent_uid"][c])]]) / 0.05
+                  for c in born]).reshape(-1)
+    assert abs(z.mean()) < 0.1 and abs(z.std() - 1) < 0.05
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # sigma = 0: children wear the parent's colour exactly
+    w0 = orc.OracleWorld(dict(cfg, mutation_sigma=0.0))
+    w0.step(actions=np.zeros(3000, np.uint8))
+    s0 = w0.state()
+    for c in np.nonzero(s0["alive"] & ~st0["alive"].astype(bool))[0][:50]:
+        np.testing.assert_array_equal(w0.colour(int(c)), c0[slot_of_uid[int(s0["parent_uid"][c])]].astype(np.float32))
+
+
+def test_tempered_sampling():
+    from scipy import stats
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        l = rng.standard_normal(7) * 3
+        lt = rng.standard_normal() * 2
+        u = rng.random()
+        p = np.exp((l - l.max()) / np.exp(lt))
+        c = np.cumsum(p)
+        assert orc.sample_tempered(l, lt, u) == int(np.searchsorted(c, u * c[-1], side="right"))
+        assert orc.sample_tempered(l, 0.0, u) == orc.sample(l, u)
+    l = np.array([0.3, -1.0, 2.0, 0.0, 1.0])
+    key = [9, 9]
+    us = [(orc.philox([i, 0, 4, 0], key)[0] >> 8) / 2**24 for i in range(20000)]
+    for lt in (0.8, -0.8):
+        p = np.exp(l / np.exp(lt)); p /= p.sum()
+        counts = np.bincount([orc.sample_tempered(l, lt, u) for u in us], minlength=5)
+        assert stats.chisquare(counts, p * len(us)).pvalue > 1e-3
+    # a cold policy takes its argmax; a hot one samples all actions about equally
+    assert all(orc.sample_tempered(l, -60.0, u) == 2 for u in us[:200])
+    hot = np.bincount([orc.sample_tempered(l, 60.0, u) for u in us], minlength=5)
+    assert stats.chisquare(hot).pvalue > 1e-3
+
+
+def test_temperature_parameter():
+    """One more mutable parameter per agent: the log temperature, 0 at init, stored
+    like a bias (BF16 in BF16 storage, FP32 in FP8 storage), mutated like a weight."""
+    import torch
+    base = wl.desc(width=48, height=48, n_agents_init=400, capacity=900, window=3, n_actions=5, seed=17,
+                   e_init=300, mutation_sigma=0.5)
+    tcfg = dict(base, flags=orc.EVOLVE_TEMPERATURE)
+    assert orc.param_count(tcfg) == orc.param_count(base) + 1
+    w = orc.OracleWorld(tcfg)
+    P = orc.param_count(tcfg)
+    np.testing.assert_array_equal(w.weights(0, master=True)[:P - 1], orc.OracleWorld(base).weights(0, master=True))
+    assert w.weights(0, master=True)[P - 1] == 0.0
+    w.step(actions=np.zeros(900, np.uint8))
+    st = w.state()
+    born = [int(c) for c in np.nonzero(st["alive"])[0] if st["parent_uid"][c] != 0xFFFFFFFFFFFFFFFF]
+    lt = np.array([w.weights(c, master=True)[P - 1] for c in born])
+    assert len(born) > 200 and abs(lt.mean()) / 0.5 < 0.15 and abs(lt.std() / 0.5 - 1) < 0.1
+    for wdtype in (1, 2):
+        q = orc.OracleWorld(dict(tcfg, wdtype=wdtype))
+        q.step(actions=np.zeros(900, np.uint8))
+        for c in born[:20]:
+            m = np.float32(q.weights(c, master=True)[P - 1])
+            ref = float(torch.tensor(m).to(torch.bfloat16).double()) if wdtype == 1 else float(m)
+            assert q.weights(c)[P - 1] == ref
 
 
 # ---------------------------------------------------------------------------
@@ -543,11 +688,16 @@ def test_A8_victims_slot_and_cell_reused_by_a_birth():
 # ---------------------------------------------------------------------------
 # N-version: C oracle vs python spec on tiny worlds, policy-sampled actions
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("seed,attack", [(0, 0), (1, 0), (2, 1)])
-def test_oracle_matches_spec_free_running(seed, attack):
-    cfg = wl.desc(width=12, height=10, n_agents_init=14, capacity=24, window=3, n_scalars=8, hidden1=32,
+@pytest.mark.parametrize("seed,attack,flags", [(0, 0, 0), (1, 0, 0), (2, 1, 0), (3, 0, 7), (4, 1, 7), (5, 0, 1),
+                                              (6, 0, 2), (7, 0, 4)])
+def test_oracle_matches_spec_free_running(seed, attack, flags):
+    """Flags: 1 front vision, 2 evolving temperature, 4 colour vision.  Without
+    attacks the energies reach the threshold, so births mutate weights,
+    temperature and colour."""
+    cfg = wl.desc(width=12, height=10, n_agents_init=14, capacity=40, window=3, n_scalars=8, hidden1=32,
                   hidden2=32, n_actions=7 if attack else 5, attack_enabled=attack, resource_density=0.5,
-                  regrow_prob=0.05, e_init=185, seed=seed)
+                  regrow_prob=0.05, e_init=185 if attack else 300, seed=seed, flags=flags,
+                  mutation_sigma=0.02 if flags == 0 else 0.3)
     o = orc.OracleWorld(cfg)
     sp = spec.SpecWorld(cfg)
     assert_same_state(o.state(), sp.state(), "init")
@@ -562,6 +712,8 @@ def test_oracle_matches_spec_free_running(seed, attack):
         assert o.stats()["births"] == sst["births"] and o.stats()["killed"] == sst["killed"]
         for k in sp.agents:
             np.testing.assert_array_equal(o.weights(k, master=True), np.array(sp.agents[k]["theta"]))
+            if flags & orc.COLOUR_VISION:
+                np.testing.assert_array_equal(o.colour(k), np.array(sp.agents[k]["colour"], np.float32))
 
 
 # ---------------------------------------------------------------------------
@@ -677,6 +829,6 @@ def test_regrowth_rate():
 def test_invalid_descs_rejected():
     for bad in [dict(window=4), dict(n_scalars=5), dict(n_actions=6), dict(capacity=10, n_agents_init=20),
                 dict(e_repro=0), dict(wdtype=7), dict(window=99), dict(attack_enabled=1),
-                dict(n_actions=7, attack_enabled=2)]:
+                dict(n_actions=7, attack_enabled=2), dict(flags=8)]:
         with pytest.raises(ValueError):
             orc.OracleWorld(wl.desc(**bad))
