@@ -28,7 +28,9 @@
  *  - An eco_world is not thread-safe; use one per host thread.
  *  - Energies are int32 fixed point in units of 0.1 energy.
  *  - Logical weight order (read/write_weights): W1[H1][D], b1[H1], W2[H2][H1],
- *    b2[H2], W3[A][H2], b3[A] (row = output unit).  The device layout is private.
+ *    b2[H2], W3[A][H2], b3[A] (row = output unit), then the log temperature
+ *    when it evolves (ECO_DESC_EVOLVE_TEMPERATURE).  The device layout is
+ *    private.
  */
 #ifndef ECO_H
 #define ECO_H
@@ -64,6 +66,25 @@ typedef struct {
     void* ctx;
 } eco_allocator;
 
+/* Policy and sensor options (eco_world_desc.flags; identical for all worlds of
+ * one object).
+ *  ECO_DESC_FRONT_VISION: the S x S window lies ahead of the agent, which sits in
+ *    the middle of the window's last row, instead of around it (App. "Varying
+ *    Vision Range", "Front" configuration).
+ *  ECO_DESC_EVOLVE_TEMPERATURE: every agent carries one more mutable parameter,
+ *    theta_T, after the output biases; actions are drawn from the softmax of the
+ *    logits divided by exp(theta_T) (Sec. 3.3).  theta_T starts at 0, is mutated
+ *    like a weight and stored like a bias (BF16 in BF16 storage, FP32 otherwise).
+ *  ECO_DESC_COLOUR_VISION: every agent carries a 3-channel colour trait, U[0,1)
+ *    at init and the parent's plus mutation_sigma * N(0,1) per channel at birth;
+ *    the window shows each cell as others see it (Sec. 3.2 "Sensors", Sec. 3.3):
+ *    the occupant's colour, else green for a resource unit, grey for a wall,
+ *    black; channels R, G, B = round(clamp(c, 0, 1) * 255) * 2^-8 and an
+ *    elevation-difference channel, zero on the flat torus. */
+#define ECO_DESC_FRONT_VISION 1u
+#define ECO_DESC_EVOLVE_TEMPERATURE 2u
+#define ECO_DESC_COLOUR_VISION 4u
+
 /* One world (POD, copied at create).  Grid is a torus of width x height. */
 typedef struct {
     uint32_t struct_size;        /* = sizeof(eco_world_desc) */
@@ -86,7 +107,7 @@ typedef struct {
                                     after the moves of the step; each victim leaves one resource
                                     unit on its cell (Sec. 3.2 actions and health points; App.
                                     "Varying Attack Strength", full strength) */
-    uint32_t flags;              /* ECO_DESC_* */
+    uint32_t flags;              /* ECO_DESC_* (unknown bits: EINVAL) */
     uint64_t seed;               /* Philox key of this world */
 } eco_world_desc;
 
@@ -223,6 +244,13 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
 eco_status eco_world_read_logits(eco_world* w, uint32_t world, float* out, size_t n_floats);
 /* The policy's sampled action of the last step per slot (255 if not live). */
 eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, size_t n);
+
+/* Colour traits of one world (ECO_DESC_COLOUR_VISION objects only, else EINVAL):
+ * out[cap][3] FP32 R, G, B; NaN for slots not alive.  n_floats >= 3 * capacity. */
+eco_status eco_world_read_colours(eco_world* w, uint32_t world, float* out, size_t n_floats);
+/* Overwrite the colour of live slot `slot` (finite values; EINVAL otherwise) and
+ * re-render that world's window grid, so the next step's observations show it. */
+eco_status eco_world_write_colour(eco_world* w, uint32_t world, uint32_t slot, const float* rgb);
 
 /* Weights of one live slot in logical order as doubles: which = 0 the storage
  * values dequantised exactly, which = 1 the FP32 master. */

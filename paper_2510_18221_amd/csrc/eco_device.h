@@ -26,7 +26,7 @@ constexpr uint8_t kAlive = 1, kBirthClaim = 2, kBirthWon = 4;
 enum Action : uint8_t { REST = 0, TURN_L = 1, TURN_R = 2, FORWARD = 3, EAT = 4, REPRODUCE = 5, ATTACK = 6 };
 // Philox stream tags (third counter word).
 enum Stream : uint32_t { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
-                         ST_MUTATE = 5, ST_REGROW = 6 };
+                         ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8 };
 
 // Immutable per-world parameters (device table, one entry per world).
 struct WorldParams {
@@ -69,7 +69,11 @@ struct StepCounters {
 // KB1 = D/4 (D = 4 S^2 + n_s is a multiple of 4).
 struct Layout {
   uint32_t D, S, R, ns, H1, H2, A, wdtype;
-  uint32_t P;                   // logical parameters
+  uint32_t ahead0;              // cells ahead of window row 0: R ("Around") or S - 1 ("Front")
+  uint32_t temp;                // 1: log temperature stored after the output biases (b3[A])
+  uint32_t colour;              // 1: colour trait and rendered colour window
+  uint32_t pad0;
+  uint32_t P;                   // logical parameters (the log temperature included)
   uint32_t KB1;                 // FP32 16-byte blocks per L1 row
   uint32_t KBv;                 // storage 16-byte blocks per L1 row
   uint32_t Dpad;                // KBv * VPL (observation buffer length)
@@ -99,6 +103,8 @@ struct Dev {
                                 // null when no world of the object has attacks
   uint8_t *res, *wall;
   uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
+  uint32_t* rgb;                // [total_cells] colour vision only: R | G << 8 | B << 16 | sense bits 0..2 << 24
+  float4* colour;               // [total_slots] colour vision only: the colour trait (x, y, z = R, G, B)
   uint8_t* store;               // [total_slots][sstride]
   uint8_t* master;              // [total_slots][mstride] or == store for FP32
   int32_t* live;                // [total_slots], per-world segments at slot_off

@@ -322,9 +322,12 @@ __device__ __forceinline__ AgentCtx load_agent(const Dev& d, const uint32_t* wof
 
 constexpr int kMaxWindowCellsPerLane = 4;  // S <= 15: S*S <= 256 cells over 64 lanes
 
-// Sense bytes of agent c's window (Sec. 3.2 sensors, App. F layout): lane owns
-// window cells lane + 64k, row r = i / S counted from the far front, column from
-// the agent's left; the window is rotated so the agent faces row 0.
+// Sense bytes (or, with colour vision, rendered words) of agent c's window (Sec.
+// 3.2 sensors, App. F layout): lane owns window cells lane + 64k, row r = i / S
+// counted from the far front, column from the agent's left; the window is
+// rotated so the agent faces row 0.  Row 0 lies L.ahead0 cells ahead: R for the
+// "Around" layout (the agent in the middle), S - 1 for "Front" (the agent in the
+// middle of the last row, nothing behind it seen).
 __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, const AgentCtx& c, int lane,
                                              uint32_t (&sv)[kMaxWindowCellsPerLane]) {
   const WorldParams& wp = c.wp;
@@ -337,35 +340,51 @@ __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, cons
     sv[k] = 0;
     if (i < SS) {
       const int r = i / S, col = i - r * S;
-      const int fw = R - r, rt = col - R;
+      const int fw = (int)L.ahead0 - r, rt = col - R;
       int cx = ax + fw * dx + rt * rx, cy = ay + fw * dy + rt * ry;
       if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
       if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
-      sv[k] = d.sense[wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx];
+      const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
+      sv[k] = L.colour ? d.rgb[cell] : (uint32_t)d.sense[cell];
     }
   }
 }
 
-// Observation of agent c into LDS xs[0..D): four channels per window cell
-// (agent, resource, wall, energy bin) unpacked from its sense byte, then the
-// scalars (energy, age, resource here, eligibility, compass when n_s = 8).
+// Window word of cell i (uniform) from the lane that gathered it.
+__device__ __forceinline__ uint32_t window_word(const uint32_t (&sv)[kMaxWindowCellsPerLane], int i) {
+  const int k = i >> 6;
+  const uint32_t v = k == 0 ? sv[0] : (k == 1 ? sv[1] : (k == 2 ? sv[2] : sv[3]));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, i & 63);
+}
+
+// Observation of agent c into LDS xs[0..D): four channels per window cell, then
+// the scalars (energy, age, resource here, eligibility, compass when n_s = 8).
+// Cell channels: agent, resource, wall, energy bin from the sense byte; with
+// colour vision the rendered R, G, B (8-bit values times 2^-8) and the
+// elevation difference, zero on the flat torus.
 __device__ __forceinline__ void write_observation(const Layout& L, const AgentCtx& c, int lane,
                                                   const uint32_t (&sv)[kMaxWindowCellsPerLane], float* xs) {
   const int SS = (int)(L.S * L.S);
+  const int centre = (int)(L.ahead0 * L.S + L.R);  // the agent's own cell
 #pragma unroll
   for (int k = 0; k < kMaxWindowCellsPerLane; ++k) {
     const int i = lane + 64 * k;
-    if (i < SS)
-      reinterpret_cast<float4*>(xs)[i] = make_float4((float)(sv[k] & 1u), (float)((sv[k] >> 1) & 1u),
-                                                     (float)((sv[k] >> 2) & 1u), (float)(sv[k] >> 3));
+    if (i < SS) {
+      const uint32_t v = sv[k];
+      reinterpret_cast<float4*>(xs)[i] =
+          L.colour ? make_float4(ldexpf((float)(v & 0xFFu), -8), ldexpf((float)((v >> 8) & 0xFFu), -8),
+                                 ldexpf((float)((v >> 16) & 0xFFu), -8), 0.0f)
+                   : make_float4((float)(v & 1u), (float)((v >> 1) & 1u), (float)((v >> 2) & 1u), (float)(v >> 3));
+    }
   }
+  // colour words carry the cell's sense bits in their top byte
+  const float res_here = L.colour ? (float)((window_word(sv, centre) >> 25) & 1u) : 0.0f;
   wave_sync();
   if (lane < (int)L.ns) {
-    const int centre = (int)(L.R * L.S + L.R);  // the agent's own cell
     float v;
     if (lane == 0) v = ldexpf((float)c.energy, -8);
     else if (lane == 1) v = ldexpf((float)min(c.age, 1024), -10);
-    else if (lane == 2) v = xs[4 * centre + 1];  // resource here: the centre cell's resource channel
+    else if (lane == 2) v = L.colour ? res_here : xs[4 * centre + 1];  // resource here: the own cell's resource
     else if (lane == 3) v = (c.energy >= c.wp.e_repro) ? 1.0f : 0.0f;
     else v = (lane - 4 == c.facing) ? 1.0f : 0.0f;
     xs[4 * SS + lane] = v;
@@ -396,9 +415,10 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
   if (g_lo >= g_hi) return;
 
   const int A = (int)L.A;
-  // Window cell ahead of the agent (row R-1, column R), when the window has one:
-  // the move claim reads its agent and wall channels from the observation.
-  const int front = (L.R >= 1) ? (int)((L.R - 1) * L.S + L.R) : -1;
+  // Window cell ahead of the agent (row ahead0 - 1, column R), when the window has
+  // one: the move claim reads its agent and wall channels from the observation
+  // (with colour vision, from the sense bits of its rendered word).
+  const int front = (L.ahead0 >= 1) ? (int)((L.ahead0 - 1) * L.S + L.R) : -1;
 
   AgentCtx cur = load_agent(d, woff, g_lo, find_world(woff, d.n_worlds, g_lo));
   uint32_t sv[kMaxWindowCellsPerLane];
@@ -407,6 +427,7 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
     const WorldParams& wp = cur.wp;
     // ---- 1. observation into LDS (window bytes fetched one agent ahead) ----
     write_observation(L, cur, lane, sv, xs);
+    const uint32_t front_word = (L.colour && front >= 0) ? window_word(sv, front) : 0u;
     // the next agent's context and window bytes, in flight while this agent streams
     const bool has_next = g + 1 < g_hi;
     AgentCtx nxt = cur;
@@ -434,8 +455,21 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
 #pragma unroll
     for (int a = 1; a < 8; ++a)
       if (a < A) m = fmaxf(m, l[a]);
-    // one exponential per lane (lane 8a + g holds logit a), then gathered in order
-    const float e_lane = ((lane >> 3) < A) ? expf(lg - m) : 0.0f;
+    // one exponential per lane (lane 8a + g holds logit a), then gathered in order.
+    // An evolving temperature tau = exp(theta_T) divides the logits; theta_T is the
+    // stored parameter after the output biases, so logit A (a zero weight row plus
+    // that bias slot) equals it.  The largest logits weigh exactly 1.
+    float e_lane;
+    if (L.temp) {
+      float lt = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (a == A) lt = l[a];
+      const float inv_tau = expf(-lt), x = lg - m;
+      e_lane = ((lane >> 3) < A) ? (x == 0.0f ? 1.0f : expf(x * inv_tau)) : 0.0f;
+    } else {
+      e_lane = ((lane >> 3) < A) ? expf(lg - m) : 0.0f;
+    }
     float C[8], wk[8], accum = 0.0f;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -471,7 +505,9 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
       else if (a == FORWARD) {
         const uint32_t tc = neighbour(wp, (uint32_t)cur.pos, f, +1);
         bool free_cell;
-        if (front >= 0) {  // the observation holds the cell ahead as seen at step start
+        if (front >= 0 && L.colour) {  // agent and wall bits of the rendered word
+          free_cell = ((front_word >> 24) & 5u) == 0u;
+        } else if (front >= 0) {  // the observation holds the cell ahead as seen at step start
           free_cell = xs[4 * front] == 0.0f && xs[4 * front + 2] == 0.0f;
         } else {
           free_cell = d.occ[wp.cell_off + tc] == -1 && !(wp.has_walls && d.wall[wp.cell_off + tc]);

@@ -34,6 +34,7 @@ hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
 hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32_t* sink, uint32_t blocks,
                               uint32_t threads);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
+hipError_t launch_render(hipStream_t s, const Dev& d, const TileScratch& ts, int world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_emit_list(hipStream_t s, const Dev& d, const Layout& L, const uint32_t* list, uint32_t n, int mode,
@@ -180,6 +181,8 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
   if (d.attack_enabled > 1) return bad(ECO_EINVAL, "attack_enabled", "must be 0 or 1");
   if (d.attack_enabled && d.n_actions != 7) return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7");
+  if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION))
+    return bad(ECO_EINVAL, "flags", "has unknown bits");
   auto okh = [](uint32_t h) { return h == 32 || h == 64 || h == 128; };
   if (!okh(d.hidden1) || !okh(d.hidden2)) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be 32, 64 or 128");
   if (d.hidden1 != d.hidden2) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be equal");
@@ -197,7 +200,10 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
   L.H2 = d.hidden2;
   L.A = d.n_actions;
   L.wdtype = d.wdtype;
-  L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A;
+  L.ahead0 = (d.flags & ECO_DESC_FRONT_VISION) ? d.window - 1 : L.R;
+  L.temp = (d.flags & ECO_DESC_EVOLVE_TEMPERATURE) ? 1u : 0u;
+  L.colour = (d.flags & ECO_DESC_COLOUR_VISION) ? 1u : 0u;
+  L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A + L.temp;
   L.p_w1 = 0;
   L.p_b1 = L.p_w1 + L.H1 * L.D;
   L.p_w2 = L.p_b1 + L.H1;
@@ -534,7 +540,7 @@ HostUnit host_unit(const Layout& L, uint32_t u) {
   else if (u < L.u_b2) { uint32_t e = u - L.u_w2; r.layer = 1; r.kb = e / L.H2; r.row = e % L.H2; r.p = L.p_w2 + r.row * L.H1 + 4 * r.kb; r.nvalid = 4; }
   else if (u < L.u_w3) { r.layer = 4; r.row = 4 * (u - L.u_b2); r.p = L.p_b2 + r.row; r.nvalid = 4; }
   else if (u < L.u_b3) { uint32_t e = u - L.u_w3, per = L.H2 / 4; r.layer = 2; r.row = e / per; r.kb = e % per; r.p = L.p_w3 + r.row * L.H2 + 4 * r.kb; r.nvalid = r.row < L.A ? 4 : 0; }
-  else { uint32_t e = u - L.u_b3; r.layer = 5; r.row = 4 * e; r.p = L.p_b3 + r.row; r.nvalid = r.row < L.A ? std::min(4u, L.A - r.row) : 0; }
+  else { uint32_t e = u - L.u_b3, n3 = L.A + L.temp; r.layer = 5; r.row = 4 * e; r.p = L.p_b3 + r.row; r.nvalid = r.row < n3 ? std::min(4u, n3 - r.row) : 0; }
   return r;
 }
 
@@ -573,9 +579,9 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     const eco_world_desc& a = descs[0];
     const eco_world_desc& b = descs[i];
     if (a.window != b.window || a.n_scalars != b.n_scalars || a.hidden1 != b.hidden1 || a.hidden2 != b.hidden2 ||
-        a.n_actions != b.n_actions || a.wdtype != b.wdtype)
+        a.n_actions != b.n_actions || a.wdtype != b.wdtype || a.flags != b.flags)
       return fail(ECO_EINVAL, "all worlds of one object need the same window, n_scalars, hidden sizes, "
-                              "n_actions and wdtype");
+                              "n_actions, wdtype and flags");
   }
   eco_world* w = new eco_world();
   w->n_worlds = n_worlds;
@@ -674,6 +680,8 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.res = (uint8_t*)A(TC);
   d.wall = (uint8_t*)A(TC);
   d.sense = (uint8_t*)A(TC);
+  d.rgb = w->L.colour ? (uint32_t*)A(4 * TC) : nullptr;
+  d.colour = w->L.colour ? (float4*)A(16 * TS) : nullptr;
   d.live = (int32_t*)A(4 * TS);
   d.bparent = (int32_t*)A(4 * TS);
   d.freel = (int32_t*)A(4 * TS);
@@ -1154,6 +1162,46 @@ eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, si
   const WorldParams& p = w->wp[world];
   if (n < p.cap) return fail(ECO_EINVAL, "buffer too small");
   HIPCHK(w, hipMemcpyAsync(out, w->d.sampled + p.slot_off, p.cap, hipMemcpyDeviceToHost, w->stream), "read sampled");
+  return sync(w);
+}
+
+eco_status eco_world_read_colours(eco_world* w, uint32_t world, float* out, size_t n_floats) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !out) return fail(ECO_EINVAL, "bad world or buffer");
+  if (!w->L.colour) return fail(ECO_EINVAL, "the object has no colour trait (ECO_DESC_COLOUR_VISION)");
+  const WorldParams& p = w->wp[world];
+  if (n_floats < 3ull * p.cap) return fail(ECO_EINVAL, "colour buffer too small");
+  std::vector<float> tmp(4ull * p.cap);
+  std::vector<uint8_t> fl(p.cap);
+  HIPCHK(w, hipMemcpyAsync(tmp.data(), w->d.colour + p.slot_off, 16ull * p.cap, hipMemcpyDeviceToHost, w->stream),
+         "read colours");
+  HIPCHK(w, hipMemcpyAsync(fl.data(), w->d.flags + p.slot_off, p.cap, hipMemcpyDeviceToHost, w->stream), "read flags");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  for (size_t s = 0; s < p.cap; ++s)
+    for (int k = 0; k < 3; ++k) out[3 * s + k] = (fl[s] & kAlive) ? tmp[4 * s + k] : NAN;
+  return ECO_OK;
+}
+
+eco_status eco_world_write_colour(eco_world* w, uint32_t world, uint32_t slot, const float* rgb) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !rgb) return fail(ECO_EINVAL, "bad world or buffer");
+  if (!w->L.colour) return fail(ECO_EINVAL, "the object has no colour trait (ECO_DESC_COLOUR_VISION)");
+  const WorldParams& p = w->wp[world];
+  if (slot >= p.cap) return fail(ECO_EINVAL, "slot out of range");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(rgb[k])) return fail(ECO_EINVAL, "colour must be finite");
+  uint8_t fl = 0;
+  HIPCHK(w, hipMemcpyAsync(&fl, w->d.flags + p.slot_off + slot, 1, hipMemcpyDeviceToHost, w->stream), "read flag");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  if (!(fl & kAlive)) return fail(ECO_EINVAL, "slot not alive");
+  const float4 c = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+  hipStream_t s = w->stream;
+  HIPCHK(w, hipMemcpyAsync(w->d.colour + p.slot_off + slot, &c, 16, hipMemcpyHostToDevice, s), "write colour");
+  HIPCHK(w, launch_render(s, w->d, w->ts, (int)world), "render");   // the window grid shows it from now on
   return sync(w);
 }
 

@@ -122,11 +122,11 @@ __device__ __forceinline__ UnitInfo unit_info(const Layout& L, uint32_t u) {
     const uint32_t e = u - L.u_w3, per = L.H2 / 4;
     r.layer = 2; r.row = e / per; r.kb = e % per;
     r.p = L.p_w3 + r.row * L.H2 + 4 * r.kb; r.nvalid = (r.row < L.A) ? 4 : 0;
-  } else {                          // b3 (8 padded)
-    const uint32_t e = u - L.u_b3;
+  } else {                          // b3 (8 padded), then the log temperature in slot A when it evolves
+    const uint32_t e = u - L.u_b3, n3 = L.A + L.temp;
     r.layer = 5; r.row = 4 * e; r.kb = 0;
     r.p = L.p_b3 + r.row;
-    r.nvalid = (r.row < L.A) ? min(4u, L.A - r.row) : 0;
+    r.nvalid = (r.row < n3) ? min(4u, n3 - r.row) : 0;
   }
   return r;
 }
@@ -193,6 +193,21 @@ __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp,
     __syncthreads();
   }
   const double sigma = (double)wp.sigma;
+  if (L.colour && tid == 0 && mode != EMIT_REQUANT) {
+    // colour trait: U[0,1) per channel at init, the parent's plus sigma N(0,1) at birth
+    float4 c;
+    if (mode == EMIT_INIT) {
+      const uint4 x = philox10(rng_slot, 0u, ST_COLOUR_INIT, 0u, wp.key0, wp.key1);
+      c = make_float4((float)(x.x >> 8) * 0x1p-24f, (float)(x.y >> 8) * 0x1p-24f, (float)(x.z >> 8) * 0x1p-24f, 0.0f);
+    } else {
+      double z[4];
+      gauss4(wp, rng_slot, step, ST_COLOUR_MUTATE, 0u, z);
+      const float4 pc = d.colour[parent];
+      c = make_float4((float)__builtin_fma(sigma, z[0], (double)pc.x), (float)__builtin_fma(sigma, z[1], (double)pc.y),
+                      (float)__builtin_fma(sigma, z[2], (double)pc.z), 0.0f);
+    }
+    d.colour[child] = c;
+  }
   double tsum = 0.0;
   for (uint32_t u = tid; u < L.u_end; u += blockDim.x) {
     const UnitInfo ui = unit_info(L, u);
@@ -592,6 +607,35 @@ __device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d
   return v;
 }
 
+// Colour vision: the cell as others see it (occupant's colour, else a resource
+// unit in green, else a wall in grey, else black; 8 bits per channel), with the
+// cell's agent / resource / wall bits in the top byte for the move claim.
+__device__ __forceinline__ uint32_t colour_byte(float c) {
+  double x = (double)c;
+  if (!(x > 0.0)) x = 0.0;
+  if (x > 1.0) x = 1.0;
+  return (uint32_t)floor(x * 255.0 + 0.5);   // exact in FP64
+}
+
+__device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t cell = wp.cell_off + tl.start + i;
+    const int o = d.occ[cell];
+    const bool r = d.res[cell] != 0, wl = wp.has_walls && d.wall[cell] != 0;
+    uint32_t q = 0u;
+    if (o >= 0) {
+      const float4 c = d.colour[wp.slot_off + (uint32_t)o];
+      q = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+    } else if (r) {
+      q = 255u << 8;
+    } else if (wl) {
+      q = 0x808080u;
+    }
+    d.rgb[cell] = q | (((o >= 0 ? 1u : 0u) | (r ? 2u : 0u) | (wl ? 4u : 0u)) << 24);
+  }
+}
+
 __device__ __forceinline__ void cell_sense_tile(const Dev& d, const Tile tl) {
   const WorldParams wp = d.wp[tl.world];
   for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
@@ -702,7 +746,10 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   __shared__ uint32_t bcast;
   if (blockIdx.x >= ts.n_slot_tiles) {
     const Tile ct = ts.cell_tiles[blockIdx.x - ts.n_slot_tiles];
-    if (only_world < 0 || (int)ct.world == only_world) cell_sense_tile(d, ct);
+    if (only_world < 0 || (int)ct.world == only_world) {
+      if (d.rgb) cell_render_tile(d, ct);
+      else cell_sense_tile(d, ct);
+    }
     return;
   }
   const Tile tl = ts.slot_tiles[blockIdx.x];
@@ -718,6 +765,12 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   const uint32_t r = ol + block_exscan<kSlotTile>(alive ? 1u : 0u, red, &tot);
   if (alive) d.live[wp.slot_off + r] = (int)local;
   if (blockIdx.x + 1 == t1) world_finalize<kSlotTile>(d, ts, w, init);
+}
+
+// Rendered window words of one world's cells (after a colour write).
+__global__ __launch_bounds__(256) void k_render(Dev d, const Tile* __restrict__ tiles, int only_world) {
+  const Tile ct = tiles[blockIdx.x];
+  if ((int)ct.world == only_world) cell_render_tile(d, ct);
 }
 
 // Resource total of each world (init / after state writes): one block per world.
@@ -873,6 +926,11 @@ hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {
   hipLaunchKernelGGL(k_prestep_fill, dim3((d.total_slots + 255) / 256), dim3(256), 0, s, d);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_render(hipStream_t s, const Dev& d, const TileScratch& ts, int world) {
+  if (ts.n_cell_tiles == 0 || !d.rgb) return hipSuccess;
+  hipLaunchKernelGGL(k_render, dim3(ts.n_cell_tiles), dim3(256), 0, s, d, ts.cell_tiles, world);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world) {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libeco.so")
 
 ECO_OK, ECO_EINVAL, ECO_ENOMEM, ECO_EDEVICE, ECO_ESTATE, ECO_ENOTSUP = 0, -1, -2, -3, -4, -5
 RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS = 1, 2, 4
+DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION = 1, 2, 4   # eco_world_desc.flags
 KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact", "sense"]
 
 EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world_step", "eco_world_reset",
@@ -22,7 +23,8 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_set_launch", "eco_world_get_launch", "eco_world_autotune", "eco_world_kernel_times",
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
-           "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps"]
+           "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps", "eco_world_read_colours",
+           "eco_world_write_colour"]
 
 
 class EcoError(RuntimeError):
@@ -121,6 +123,8 @@ def lib():
         L.eco_world_read_sampled.argtypes = [P, U32, P, ctypes.c_size_t]
         L.eco_world_read_weights.argtypes = [P, U32, U32, I32, P, ctypes.c_size_t]
         L.eco_world_write_weights.argtypes = [P, U32, U32, P, ctypes.c_size_t]
+        L.eco_world_read_colours.argtypes = [P, U32, P, ctypes.c_size_t]
+        L.eco_world_write_colour.argtypes = [P, U32, U32, P]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -304,6 +308,17 @@ class World:
     def write_weights(self, slot, master, world=0):
         m = np.ascontiguousarray(master, dtype=np.float32)
         _err(lib().eco_world_write_weights(self._h, world, slot, _ptr(m), m.size))
+
+    def read_colours(self, world=0):
+        cap = self.cfgs[world]["capacity"]
+        out = np.empty((cap, 3), dtype=np.float32)
+        _err(lib().eco_world_read_colours(self._h, world, _ptr(out), out.size))
+        return out
+
+    def write_colour(self, slot, rgb, world=0):
+        v = np.ascontiguousarray(rgb, dtype=np.float32)
+        assert v.size == 3
+        _err(lib().eco_world_write_colour(self._h, world, slot, _ptr(v)))
 
 
 # State byte layout of include/eco.h (read_state / write_state).

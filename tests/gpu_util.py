@@ -56,6 +56,11 @@ def compare_world(gw, ow, what, world=0, weights_slots=8):
         assert_weights_close(gw.read_weights(int(s), world, master=True), ow.weights(int(s), master=True),
                              f"{what} master slot {s}")
         assert_weights_close(gw.read_weights(int(s), world), ow.weights(int(s)), f"{what} storage slot {s}")
+    if gw.cfgs[world].get("flags", 0) & 4:   # colour traits of every live slot
+        gc = gw.read_colours(world)
+        assert np.all(np.isnan(gc[~os_["alive"].astype(bool)]))
+        oc = np.array([ow.colour(int(s)) for s in live], np.float64).reshape(-1, 3)
+        assert_weights_close(gc[live].astype(np.float64).reshape(-1), oc.reshape(-1), f"{what} colours")
     return gs
 
 
