@@ -22,8 +22,10 @@ the box's streaming-read rate, measured by the library's probe kernel (8 GiB
 read once per launch; best of three calls of five launches at three grid shapes).  Also reported: BF16 and FP8 weight storage on the
 same world, the frozen-population form (exactly 65,536 agents every step), the
 same world with attacks enabled (the paper's "+A" worlds, with its predation
-measures: attacks per agent and homicides per attack), a per-kernel breakdown
-from a few eager steps, and the CPU oracle on a bounded sample.
+measures: attacks per agent and homicides per attack), the same world with the
+paper's own policy options (evolving softmax temperature, colour trait rendered
+into the windows), a per-kernel breakdown from a few eager steps, and the CPU
+oracle on a bounded sample.
 """
 import argparse
 import json
@@ -298,10 +300,13 @@ def main():
     if args.workload == "65k" and not args.no_variants:
         variants = {}
         attack_cfg = dict(wl.world_65k(seed=0), attack_enabled=1)
+        # the paper's own agent: evolving softmax temperature and colour trait seen in others' windows
+        paper_cfg = dict(wl.world_65k(seed=0), flags=eco.DESC_EVOLVE_TEMPERATURE | eco.DESC_COLOUR_VISION)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
-                           ("fp32_attack", attack_cfg)]:
+                           ("fp32_attack", attack_cfg),
+                           ("fp32_temperature_colour", paper_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
