@@ -25,6 +25,13 @@
  *   - Resources (Sec. 3.2 "Resources"): every step costs energy, eating moves a
  *     resource unit from the cell into the agent, energy slowly regrows on
  *     empty cells (Bernoulli per cell and step).
+ *   - The three-resource ecology (ORC_ECOLOGY; Sec. 3.2 "Resources" and health
+ *     points; App. "Varying Resource Rules", "Varying Agent HP"): water, energy
+ *     and biomass on the grid and in capped stomachs, three eat actions, every
+ *     action spends energy (least for rest, destroyed) and water (returned to
+ *     the cell), overspending and age damage health, energy heals it, death at
+ *     zero health returns everything carried to the cell, reproduction needs
+ *     spare biomass, energy grows on free-standing biomass (photosynthesis).
  *   - Reproduction (Sec. 3.2 "Actions", Sec. 3.3): single parent with enough
  *     energy, child placed directly behind the parent, child receives a fixed
  *     amount of the parent's energy, child weights = parent weights + Gaussian
@@ -173,6 +180,9 @@ struct orc_world {
     double *trait;            /* [cap] squared L2 norm of the FP32 master */
     float *colour;            /* [cap][3] colour trait (colour vision only; kept in lineage mode too,
                                  since every observation renders the occupants' colours) */
+    int eco;                  /* ORC_ECOLOGY */
+    int32_t *water, *biomass, *hp;      /* [cap] stomach water and biomass, health (ecology) */
+    int32_t *cw, *ce, *cb;              /* [cells] water, energy, biomass on the grid (ecology) */
     orc_stats stats;
 };
 
@@ -364,6 +374,17 @@ static void compute_stats_tail(orc_world* w) {
     uint64_t rsum = 0;
     for (uint32_t c = 0; c < w->cells; ++c) rsum += w->res[c];
     st->resource_total = rsum;
+    st->water_total = st->biomass_total = st->hp_total = 0;
+    if (w->eco) {
+        uint64_t ws = 0, es = 0, bs = 0, hs = 0;
+        for (uint32_t c = 0; c < w->cells; ++c) { ws += (uint64_t)w->cw[c]; es += (uint64_t)w->ce[c]; bs += (uint64_t)w->cb[c]; }
+        for (uint32_t s2 = 0; s2 < w->cap; ++s2)
+            if (w->alive[s2]) { ws += (uint64_t)w->water[s2]; bs += (uint64_t)w->biomass[s2]; hs += (uint64_t)w->hp[s2]; }
+        st->resource_total = es;
+        st->water_total = ws;
+        st->biomass_total = bs;
+        st->hp_total = hs;
+    }
 }
 
 static int validate(const orc_desc* d) {
@@ -372,12 +393,33 @@ static int validate(const orc_desc* d) {
     if ((uint64_t)d->width * d->height > (1ull << 31)) return fail("grid too large");
     if (d->window < 1 || d->window % 2 == 0) return fail("window must be odd");
     if (d->window > d->width || d->window > d->height) return fail("window larger than the grid");
-    if (d->n_scalars != 4 && d->n_scalars != 8) return fail("n_scalars must be 4 or 8");
-    if (d->n_actions != 5 && d->n_actions != 7) return fail("n_actions must be 5 or 7");
+    if (d->n_scalars != 4 && d->n_scalars != 8 && !((d->flags & ORC_ECOLOGY) && d->n_scalars == 12))
+        return fail("n_scalars must be 4 or 8 (8 or 12 in the ecology)");
+    if (d->n_actions != 5 && d->n_actions != 7 && d->n_actions != 8) return fail("n_actions must be 5, 7 or 8");
     if (d->attack_enabled > 1) return fail("attack_enabled must be 0 or 1");
     if (d->attack_enabled && d->n_actions != 7) return fail("attacks need the seven-action head");
-    if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION))
+    if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY))
         return fail("unknown flags");
+    if (d->flags & ORC_ECOLOGY) {
+        const orc_ecology* e = &d->eco;
+        if (d->n_actions != 8) return fail("the ecology has eight actions");
+        if (d->attack_enabled || (d->flags & ORC_COLOUR_VISION)) return fail("the ecology runs without attack and colour");
+        if (d->n_scalars != 8 && d->n_scalars != 12) return fail("the ecology has 8 or 12 scalars");
+        if (e->hp_max <= 0 || e->hp_child <= 0 || e->hp_child > e->hp_max) return fail("bad health limits");
+        if (e->age_shift < 0 || e->age_shift > 31) return fail("age_shift outside [0, 31]");
+        if (e->cap_water < 0 || e->cap_energy < 0 || e->cap_biomass < 0 || e->eat_water < 0 || e->eat_biomass < 0 ||
+            e->w_cost < 0 || e->e_cost_move < 0 || e->hp_overspend < 0 || e->hp_heal < 0 || e->heal_energy < 0 ||
+            e->w_init < 0 || e->b_init < 0 || e->w_child < 0 || e->b_child < 0 || e->b_repro < e->b_child ||
+            e->water_site < 0 || e->energy_site < 0 || e->biomass_site < 0 || e->cell_energy_max < 0 || d->e_eat < 0 ||
+            d->e_cost < 0 || d->e_child < 0)
+            return fail("negative ecology amount");
+        if (!(e->photo_rate >= 0.0f) || !(e->water_density >= 0.0f && e->water_density <= 1.0f) ||
+            !(e->energy_density >= 0.0f && e->energy_density <= 1.0f) ||
+            !(e->biomass_density >= 0.0f && e->biomass_density <= 1.0f))
+            return fail("bad ecology rate or density");
+    } else if (d->n_actions == 8) {
+        return fail("eight actions need the ecology");
+    }
     if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
     if (d->capacity < d->n_agents_init) return fail("capacity below the initial population");
     if ((uint64_t)d->n_agents_init > (uint64_t)d->width * d->height) return fail("more agents than cells");
@@ -402,6 +444,7 @@ void orc_destroy(orc_world* w) {
     free(w->pos); free(w->energy); free(w->age); free(w->facing); free(w->alive); free(w->action);
     free(w->uid); free(w->puid); free(w->occ); free(w->res); free(w->wall);
     free(w->master); free(w->stored); free(w->node); free(w->nodes); free(w->trait); free(w->colour);
+    free(w->water); free(w->biomass); free(w->hp); free(w->cw); free(w->ce); free(w->cb);
     free(w);
 }
 
@@ -427,12 +470,17 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
     w->res = (uint8_t*)calloc(w->cells, 1);
     w->wall = (uint8_t*)calloc(w->cells, 1);
     w->colour = (float*)calloc((size_t)(cap ? cap : 1) * 3, sizeof(float));
+    w->eco = (d->flags & ORC_ECOLOGY) != 0;
+    w->water = (int32_t*)calloc(cap ? cap : 1, 4);   w->biomass = (int32_t*)calloc(cap ? cap : 1, 4);
+    w->hp = (int32_t*)calloc(cap ? cap : 1, 4);
+    w->cw = (int32_t*)calloc(w->cells, 4); w->ce = (int32_t*)calloc(w->cells, 4); w->cb = (int32_t*)calloc(w->cells, 4);
     if (materialize) {
         w->master = (float*)calloc((size_t)cap * w->P + 1, sizeof(float));
         if (d->wdtype != ORC_FP32) w->stored = (double*)calloc((size_t)cap * w->P + 1, sizeof(double));
     }
     if (!w->pos || !w->energy || !w->age || !w->facing || !w->alive || !w->action || !w->uid ||
-        !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall || !w->colour ||
+        !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall || !w->colour || !w->water ||
+        !w->biomass || !w->hp || !w->cw || !w->ce || !w->cb ||
         (materialize && (!w->master || (d->wdtype != ORC_FP32 && !w->stored)))) {
         orc_destroy(w);
         fail("out of memory");
@@ -447,7 +495,21 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
     for (uint32_t c = 0; c < w->cells; ++c) { ck[c].key = draw_x0(w->key, c, 0, ST_CELLKEY, 0); ck[c].cell = c; }
     qsort(ck, w->cells, sizeof(cell_key), cmp_cell_key);
     uint64_t rho = bern_threshold(d->resource_density);
-    for (uint32_t c = 0; c < w->cells; ++c) w->res[c] = ((uint64_t)draw_x0(w->key, c, 0, ST_RESINIT, 0) < rho) ? 1 : 0;
+    if (!w->eco) {
+        for (uint32_t c = 0; c < w->cells; ++c) w->res[c] = ((uint64_t)draw_x0(w->key, c, 0, ST_RESINIT, 0) < rho) ? 1 : 0;
+    } else {
+        /* Water, energy and biomass sites from outputs 1, 2, 3 of the same block
+         * (the single resource layer stays empty). */
+        const uint64_t tw = bern_threshold(d->eco.water_density), te = bern_threshold(d->eco.energy_density),
+                       tb = bern_threshold(d->eco.biomass_density);
+        for (uint32_t c = 0; c < w->cells; ++c) {
+            uint32_t ctr[4] = {c, 0u, ST_RESINIT, 0u}, x[4];
+            orc_philox4x32_10(ctr, w->key, x);
+            w->cw[c] = ((uint64_t)x[1] < tw) ? d->eco.water_site : 0;
+            w->ce[c] = ((uint64_t)x[2] < te) ? d->eco.energy_site : 0;
+            w->cb[c] = ((uint64_t)x[3] < tb) ? d->eco.biomass_site : 0;
+        }
+    }
     for (uint32_t j = 0; j < d->n_agents_init; ++j) {
         uint32_t cell = ck[j].cell;
         w->alive[j] = 1;
@@ -456,6 +518,7 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
         w->facing[j] = (uint8_t)(draw_x0(w->key, j, 0, ST_FACING, 0) >> 30);
         w->energy[j] = d->e_init;
         w->age[j] = 0;
+        if (w->eco) { w->water[j] = d->eco.w_init; w->biomass[j] = d->eco.b_init; w->hp[j] = d->eco.hp_max; }
         w->uid[j] = j;
         w->puid[j] = UINT64_MAX;
         int64_t id = new_node(w, -1, 0, 0, j);
@@ -521,6 +584,13 @@ int orc_observe(const orc_world* w, uint32_t slot, double* x) {
             int32_t o = w->occ[cell];
             double* v = x + 4 * (r * S + c);
             if (w->d.flags & ORC_COLOUR_VISION) { render_cell(w, cell, v); continue; }
+            if (w->eco) {   /* agent present, then water, energy, biomass levels (capped at 255) / 16 */
+                v[0] = (o >= 0) ? 1.0 : 0.0;
+                v[1] = ldexp((double)(w->cw[cell] < 255 ? w->cw[cell] : 255), -4);
+                v[2] = ldexp((double)(w->ce[cell] < 255 ? w->ce[cell] : 255), -4);
+                v[3] = ldexp((double)(w->cb[cell] < 255 ? w->cb[cell] : 255), -4);
+                continue;
+            }
             v[0] = (o >= 0) ? 1.0 : 0.0;
             v[1] = (double)w->res[cell];
             v[2] = (double)w->wall[cell];
@@ -539,6 +609,22 @@ int orc_observe(const orc_world* w, uint32_t slot, double* x) {
     double* s = x + 4 * S * S;
     int32_t E = w->energy[slot];
     int32_t age = w->age[slot] < 1024 ? w->age[slot] : 1024;
+    if (w->eco) {
+        /* internal: energy, age, water, biomass, health; external: the own cell's
+         * water, energy, biomass levels; then the compass when n_s = 12. */
+        uint32_t here = (uint32_t)w->pos[slot];
+        s[0] = ldexp((double)E, -8);
+        s[1] = ldexp((double)age, -10);
+        s[2] = ldexp((double)w->water[slot], -8);
+        s[3] = ldexp((double)w->biomass[slot], -3);
+        s[4] = ldexp((double)w->hp[slot], -7);
+        s[5] = ldexp((double)(w->cw[here] < 255 ? w->cw[here] : 255), -4);
+        s[6] = ldexp((double)(w->ce[here] < 255 ? w->ce[here] : 255), -4);
+        s[7] = ldexp((double)(w->cb[here] < 255 ? w->cb[here] : 255), -4);
+        if (w->ns == 12)
+            for (int k = 0; k < 4; ++k) s[8 + k] = (k == f) ? 1.0 : 0.0;
+        return 0;
+    }
     s[0] = ldexp((double)E, -8);
     s[1] = ldexp((double)age, -10);
     s[2] = (double)w->res[w->pos[slot]];
@@ -635,6 +721,60 @@ int orc_agent_logits(orc_world* w, uint32_t slot, double* out) {
 /* ------------------------------------------------------------------------- */
 /* The step                                                                  */
 /* ------------------------------------------------------------------------- */
+static int32_t min3(int32_t a, int32_t b, int32_t c) { int32_t m = a < b ? a : b; return m < c ? m : c; }
+
+/* One live agent's resources and health after the moves (ecology).  It touches
+ * only the cell it stands on, so the agents' order does not matter.
+ *   eat: the chosen resource moves from the cell to the stomach, up to the eat
+ *        amount, what the cell holds and the room left under the cap;
+ *   costs: energy (rest the least) is destroyed; water is spent and returns to
+ *        the cell; a resource that runs short is overspent (energy clamps at 0);
+ *   damage: each overspent resource costs hp_overspend health, and age costs
+ *        age >> age_shift (small, growing with age);
+ *   death at health <= 0: water, energy and biomass carried go to the cell;
+ *   otherwise healing: below full health, heal_energy energy buys hp_heal health
+ *        (capped at hp_max); the agent ages. */
+static void ecology_agent(orc_world* w, uint32_t s, orc_stats* st) {
+    const orc_ecology* e = &w->d.eco;
+    const uint32_t cell = (uint32_t)w->pos[s];
+    const int a = w->action[s];
+    int32_t E = w->energy[s], Wt = w->water[s], B = w->biomass[s], hp = w->hp[s];
+    int32_t t = 0;
+    if (a == ORC_EAT_ENERGY) {
+        t = min3(w->d.e_eat, w->ce[cell], e->cap_energy - E);
+        if (t > 0) { w->ce[cell] -= t; E += t; }
+    } else if (a == ORC_EAT_WATER) {
+        t = min3(e->eat_water, w->cw[cell], e->cap_water - Wt);
+        if (t > 0) { w->cw[cell] -= t; Wt += t; }
+    } else if (a == ORC_EAT_BIOMASS) {
+        t = min3(e->eat_biomass, w->cb[cell], e->cap_biomass - B);
+        if (t > 0) { w->cb[cell] -= t; B += t; }
+    }
+    if (t > 0) st->eaten++;
+    int over = 0;
+    E -= (a == ORC_REST) ? w->d.e_cost : e->e_cost_move;
+    if (E < 0) { E = 0; over++; }
+    int32_t spend = Wt < e->w_cost ? Wt : e->w_cost;
+    Wt -= spend;
+    w->cw[cell] += spend;
+    if (spend < e->w_cost) over++;
+    hp -= over * e->hp_overspend + (w->age[s] >> e->age_shift);
+    if (hp <= 0) {
+        w->cw[cell] += Wt; w->ce[cell] += E; w->cb[cell] += B;
+        w->energy[s] = 0; w->water[s] = 0; w->biomass[s] = 0; w->hp[s] = 0;
+        w->alive[s] = 0;
+        w->occ[cell] = -1;
+        st->deaths++;
+        return;
+    }
+    if (hp < e->hp_max && E >= e->heal_energy) {
+        hp = (hp + e->hp_heal < e->hp_max) ? hp + e->hp_heal : e->hp_max;
+        E -= e->heal_energy;
+    }
+    w->energy[s] = E; w->water[s] = Wt; w->biomass[s] = B; w->hp[s] = hp;
+    w->age[s] += 1;
+}
+
 int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* sampled_out) {
     const uint32_t cap = w->cap, A = w->A;
     const uint32_t step32 = (uint32_t)w->step;
@@ -754,6 +894,7 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
             st->killed++;
             continue;
         }
+        if (w->eco) { ecology_agent(w, s, st); continue; }
         if (w->action[s] == ORC_EAT && w->res[cell] > 0) {
             w->res[cell] -= 1;
             w->energy[s] += w->d.e_eat;
@@ -777,6 +918,9 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
         tgt[s] = -1;
         if (!w->alive[s]) continue;
         int eligible = w->energy[s] >= w->d.e_repro && (A == 5 || w->action[s] == ORC_REPRODUCE);
+        if (w->eco)   /* spare biomass and enough water to give the child */
+            eligible = w->action[s] == ORC_REPRODUCE_ECO && w->energy[s] >= w->d.e_repro &&
+                       w->water[s] >= w->d.eco.w_child && w->biomass[s] >= w->d.eco.b_repro;
         if (!eligible) continue;
         uint32_t t = step_cell(w, (uint32_t)w->pos[s], w->facing[s], -1);
         if (w->occ[t] == -1 && !w->wall[t]) {
@@ -803,6 +947,13 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
         uint32_t c = freel[k];
         uint32_t t = (uint32_t)tgt[p];
         w->energy[p] -= w->d.e_child;
+        if (w->eco) {
+            w->water[p] -= w->d.eco.w_child;
+            w->biomass[p] -= w->d.eco.b_child;
+            w->water[c] = w->d.eco.w_child;
+            w->biomass[c] = w->d.eco.b_child;
+            w->hp[c] = w->d.eco.hp_child;
+        }
         w->alive[c] = 1;
         w->pos[c] = (int32_t)t;
         w->occ[t] = (int32_t)c;
@@ -829,11 +980,23 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
     free(winners);
     free(freel);
 
-    /* 7. Regrowth: an empty cell gets one unit with probability regrow_prob. */
-    uint64_t thr = bern_threshold(w->d.regrow_prob);
-    for (uint32_t c = 0; c < w->cells; ++c) {
-        if (w->res[c] != 0) continue;
-        if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->res[c] = 1; st->regrown++; }
+    /* 7. Regrowth: an empty cell gets one unit with probability regrow_prob.
+     *    Ecology: photosynthesis instead, one energy unit with probability
+     *    min(1, photo_rate * biomass) on every cell holding biomass, up to
+     *    cell_energy_max (photo_rate * biomass is exact in FP64). */
+    if (!w->eco) {
+        uint64_t thr = bern_threshold(w->d.regrow_prob);
+        for (uint32_t c = 0; c < w->cells; ++c) {
+            if (w->res[c] != 0) continue;
+            if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->res[c] = 1; st->regrown++; }
+        }
+    } else {
+        for (uint32_t c = 0; c < w->cells; ++c) {
+            if (w->cb[c] <= 0 || w->ce[c] >= w->d.eco.cell_energy_max) continue;
+            double p = (double)w->d.eco.photo_rate * (double)w->cb[c];
+            uint64_t thr = p >= 1.0 ? (1ull << 32) : (uint64_t)floor(p * 4294967296.0);
+            if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->ce[c] += 1; st->regrown++; }
+        }
     }
 
     /* 8. Advance the clock and record the step's statistics. */
@@ -850,7 +1013,9 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
 /* State access                                                              */
 /* ------------------------------------------------------------------------- */
 size_t orc_state_bytes(const orc_world* w) {
-    return 32 + (size_t)w->cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + (size_t)w->cells * (4 + 1 + 1);
+    size_t n = 32 + (size_t)w->cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + (size_t)w->cells * (4 + 1 + 1);
+    if (w->eco) n += (size_t)w->cap * 12 + (size_t)w->cells * 12;
+    return n;
 }
 
 int orc_read_state(const orc_world* w, void* buf, size_t bytes) {
@@ -870,7 +1035,15 @@ int orc_read_state(const orc_world* w, void* buf, size_t bytes) {
     memcpy(b, w->alive, cap); b += cap;
     memcpy(b, w->action, cap); b += cap;
     memcpy(b, w->res, cells); b += cells;
-    memcpy(b, w->wall, cells);
+    memcpy(b, w->wall, cells); b += cells;
+    if (w->eco) {
+        memcpy(b, w->water, cap * 4); b += cap * 4;
+        memcpy(b, w->biomass, cap * 4); b += cap * 4;
+        memcpy(b, w->hp, cap * 4); b += cap * 4;
+        memcpy(b, w->cw, cells * 4); b += cells * 4;
+        memcpy(b, w->ce, cells * 4); b += cells * 4;
+        memcpy(b, w->cb, cells * 4);
+    }
     return 0;
 }
 
@@ -895,7 +1068,15 @@ int orc_write_state(orc_world* w, const void* buf, size_t bytes) {
     memcpy(w->alive, b, cap); b += cap;
     memcpy(w->action, b, cap); b += cap;
     memcpy(w->res, b, cells); b += cells;
-    memcpy(w->wall, b, cells);
+    memcpy(w->wall, b, cells); b += cells;
+    if (w->eco) {
+        memcpy(w->water, b, cap * 4); b += cap * 4;
+        memcpy(w->biomass, b, cap * 4); b += cap * 4;
+        memcpy(w->hp, b, cap * 4); b += cap * 4;
+        memcpy(w->cw, b, cells * 4); b += cells * 4;
+        memcpy(w->ce, b, cells * 4); b += cells * 4;
+        memcpy(w->cb, b, cells * 4);
+    }
     for (uint32_t s = 0; s < w->cap; ++s) {
         if (w->alive[s] && !was_alive[s] && seed_slot(w, s)) { free(was_alive); return -1; }
     }

@@ -39,7 +39,31 @@ enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 
  *     like its weights, and the window shows the rendered colour of each cell
  *     plus an elevation-difference channel (zero on the flat torus) (Sec. 3.2
  *     "Sensors", Sec. 3.3). */
-enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4 };
+enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4, ORC_ECOLOGY = 8 };
+
+/* ORC_ECOLOGY: the paper's three-resource ecology with health (Sec. 3.2
+ * "Resources" and health points; App. "Varying Resource Rules", "Varying Agent
+ * HP").  Cells hold water, energy and biomass; agents carry the three in a
+ * capped stomach plus health.  Eight actions: rest, turn left, turn right,
+ * forward, eat energy, eat water, eat biomass, reproduce.  Amounts are integer
+ * units: energies in 0.1 energy (as e_*), health in 0.1 HP. */
+enum { ORC_EAT_ENERGY = 4, ORC_EAT_WATER = 5, ORC_EAT_BIOMASS = 6, ORC_REPRODUCE_ECO = 7 };
+typedef struct {
+    float    water_density, energy_density, biomass_density;  /* initial site densities */
+    int32_t  water_site, energy_site, biomass_site;            /* units on an initial site */
+    int32_t  eat_water, eat_biomass;                           /* units one eat moves (energy: e_eat) */
+    int32_t  cap_water, cap_energy, cap_biomass;               /* stomach capacities */
+    int32_t  e_cost_move;                                      /* energy cost of any action but rest (rest: e_cost) */
+    int32_t  w_cost;                                           /* water spent per step, returned to the cell */
+    float    photo_rate;                                       /* energy units per biomass unit per step */
+    int32_t  cell_energy_max;                                  /* photosynthesis fills a cell up to this */
+    int32_t  hp_max, hp_child;                                 /* health at init / at birth */
+    int32_t  hp_overspend;                                     /* damage per step per overspent resource */
+    int32_t  hp_heal, heal_energy;                             /* health gained / energy paid per healing step */
+    int32_t  age_shift;                                        /* age damage per step = age >> age_shift */
+    int32_t  w_init, b_init;                                   /* initial agents' water and biomass */
+    int32_t  w_child, b_child, b_repro;                        /* given to a child; biomass needed to reproduce */
+} orc_ecology;
 
 /* One world's parameters.  Energies are integers in units of 0.1 energy. */
 typedef struct {
@@ -54,16 +78,22 @@ typedef struct {
     int32_t  e_init, e_cost, e_eat, e_repro, e_child;
     uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
     uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 */
-    uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION */
+    uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY */
+    orc_ecology eco;                   /* used with ORC_ECOLOGY */
     uint64_t seed;
 } orc_desc;
 
 /* Per-step statistics (the measurement interface of App. E).  deaths counts
- * every death of the step; killed is the part of it caused by attacks. */
+ * every death of the step; killed is the part of it caused by attacks.  With
+ * ORC_ECOLOGY: eaten counts eat actions that moved a unit, regrown the energy
+ * units photosynthesis added, resource_total the energy on the grid, and
+ * water_total / biomass_total the water and biomass on the grid and in live
+ * agents (both conserved), hp_total the health of live agents; else 0. */
 typedef struct {
     uint64_t step, population, births, deaths, killed, eaten, regrown, moves_ok, moves_blocked,
              births_blocked_cell, births_blocked_capacity, resource_total, action_hist[8];
     double   energy_total, trait_mean, trait_var;
+    uint64_t water_total, biomass_total, hp_total;
 } orc_stats;
 
 typedef struct orc_world orc_world;
@@ -108,6 +138,8 @@ int orc_read_weights(orc_world* w, uint32_t slot, int which, double* out /* [P] 
  *   u64 uid[cap], u64 parent_uid[cap], i32 pos[cap], i32 energy[cap], i32 age[cap],
  *   i32 occ[cells], u8 facing[cap], u8 alive[cap], u8 action[cap], u8 res[cells],
  *   u8 wall[cells]
+ *   then with ORC_ECOLOGY: i32 water[cap], i32 biomass[cap], i32 hp[cap],
+ *   i32 cell_water[cells], i32 cell_energy[cells], i32 cell_biomass[cells]
  * pos = y*width + x. */
 size_t orc_state_bytes(const orc_world* w);
 int    orc_read_state(const orc_world* w, void* buf, size_t bytes);

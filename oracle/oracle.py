@@ -14,7 +14,18 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 FP32, BF16, FP8 = 0, 1, 2
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
-FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION = 1, 2, 4   # orc_desc.flags
+FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION, ECOLOGY = 1, 2, 4, 8   # orc_desc.flags
+EAT_ENERGY, EAT_WATER, EAT_BIOMASS, REPRODUCE_ECO = 4, 5, 6, 7             # the ecology's action set
+
+
+class OrcEcology(ctypes.Structure):
+    _fields_ = [("water_density", ctypes.c_float), ("energy_density", ctypes.c_float),
+                ("biomass_density", ctypes.c_float)] + [(n, ctypes.c_int32) for n in (
+                    "water_site", "energy_site", "biomass_site", "eat_water", "eat_biomass", "cap_water",
+                    "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
+                (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
+                                              "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
+                                              "b_repro")]
 
 
 class OrcDesc(ctypes.Structure):
@@ -28,7 +39,7 @@ class OrcDesc(ctypes.Structure):
         ("e_init", ctypes.c_int32), ("e_cost", ctypes.c_int32), ("e_eat", ctypes.c_int32),
         ("e_repro", ctypes.c_int32), ("e_child", ctypes.c_int32),
         ("wdtype", ctypes.c_uint32), ("attack_enabled", ctypes.c_uint32),
-        ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32), ("eco", OrcEcology), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -37,7 +48,8 @@ class OrcStats(ctypes.Structure):
         "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
         ("action_hist", ctypes.c_uint64 * 8),
-        ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double)]
+        ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double),
+        ("water_total", ctypes.c_uint64), ("biomass_total", ctypes.c_uint64), ("hp_total", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "action_hist"}
@@ -99,7 +111,11 @@ def _ptr(a):
 def make_desc(cfg: dict) -> OrcDesc:
     d = OrcDesc()
     for name, _ in OrcDesc._fields_:
-        if name in cfg:
+        if name == "eco":
+            for en, _ in OrcEcology._fields_:
+                if en in cfg.get("eco", {}):
+                    setattr(d.eco, en, cfg["eco"][en])
+        elif name in cfg:
             setattr(d, name, cfg[name])
     return d
 
@@ -231,7 +247,7 @@ class OracleWorld:
         self._check(lib().orc_write_state(self._h, _ptr(buf), buf.nbytes))
 
     def state(self):
-        return unpack_state(self.read_state_raw(), self.cap, self.W * self.H)
+        return unpack_state(self.read_state_raw(), self.cap, self.W * self.H, self.cfg.get("flags", 0) & ECOLOGY)
 
     def write_state(self, st: dict):
         self.write_state_raw(pack_state(st, self.W, self.H, self.cap))
@@ -249,14 +265,18 @@ _FIELDS = [("uid", np.uint64, "cap"), ("parent_uid", np.uint64, "cap"), ("pos", 
            ("energy", np.int32, "cap"), ("age", np.int32, "cap"), ("occ", np.int32, "cells"),
            ("facing", np.uint8, "cap"), ("alive", np.uint8, "cap"), ("action", np.uint8, "cap"),
            ("res", np.uint8, "cells"), ("wall", np.uint8, "cells")]
+# then, in the ecology, water, biomass, hp (i32) per slot and water, energy, biomass (i32) per cell
+ECO_FIELDS = [("water", np.int32, "cap"), ("biomass", np.int32, "cap"), ("hp", np.int32, "cap"),
+              ("cell_water", np.int32, "cells"), ("cell_energy", np.int32, "cells"),
+              ("cell_biomass", np.int32, "cells")]
 
 
-def unpack_state(buf, cap, cells):
+def unpack_state(buf, cap, cells, ecology=False):
     buf = np.asarray(buf, dtype=np.uint8)
     hdr = buf[:32]
     st = {"step": int(hdr[0:8].view(np.uint64)[0]), "uid_next": int(hdr[8:16].view(np.uint64)[0])}
     off = 32
-    for name, dt, kind in _FIELDS:
+    for name, dt, kind in _FIELDS + (ECO_FIELDS if ecology else []):
         n = cap if kind == "cap" else cells
         nb = n * np.dtype(dt).itemsize
         st[name] = buf[off:off + nb].view(dt).copy()
@@ -268,7 +288,7 @@ def pack_state(st, width, height, cap):
     cells = width * height
     parts = [np.array([st["step"], st["uid_next"]], dtype=np.uint64).view(np.uint8),
              np.array([width, height, cap, 0], dtype=np.uint32).view(np.uint8)]
-    for name, dt, kind in _FIELDS:
+    for name, dt, kind in _FIELDS + (ECO_FIELDS if "hp" in st else []):
         n = cap if kind == "cap" else cells
         a = np.ascontiguousarray(st[name], dtype=dt)
         assert a.size == n, name

@@ -21,7 +21,13 @@ worlds and to run the hand-traced cases.  Rules (paper sections):
   softmax temperature, one more mutable parameter (log tau) after the output
   biases (Sec. 3.3); 4 = a 3-channel colour trait that mutates like the
   weights, seen by others through a rendered window (three colour channels and
-  an elevation-difference channel, zero on the flat torus; Sec. 3.2, 3.3).
+  an elevation-difference channel, zero on the flat torus; Sec. 3.2, 3.3);
+  8 = the three-resource ecology with health (Sec. 3.2 "Resources" and health
+  points): water, energy and biomass on cells and in capped stomachs, three eat
+  actions, energy and water spent every step (the water back onto the cell),
+  damage from overspending and age, healing bought with energy, death at zero
+  health returning everything carried, reproduction needing spare biomass,
+  energy appearing on biomass (photosynthesis).
 * Sec. 3.3: per-agent MLP with two ReLU hidden layers and a linear head;
   softmax sampling; zero-mean Gaussian initial weights with zero biases;
   children copy the parent's weights plus Gaussian noise.
@@ -34,7 +40,8 @@ from fractions import Fraction
 
 M32 = 0xFFFFFFFF
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
-FRONT, TEMPERATURE, COLOUR = 1, 2, 4
+FRONT, TEMPERATURE, COLOUR, ECOLOGY = 1, 2, 4, 8
+EAT_E, EAT_W, EAT_B, REPRO8 = 4, 5, 6, 7
 HEADINGS = [(0, -1), (1, 0), (0, 1), (-1, 0)]  # N, E, S, W with y pointing down
 
 
@@ -93,12 +100,27 @@ class SpecWorld:
         self.occ = [-1] * cells
         self.wall = [0] * cells
         rho = math.floor(f32(c["resource_density"]) * 4294967296.0)  # descriptor fields are float32
-        self.res = [1 if philox4x32_10([i, 0, 2, 0], self.key)[0] < rho else 0 for i in range(cells)]
+        self.eco = c.get("eco", {}) if self.flags & ECOLOGY else None
+        if self.eco is None:
+            self.res = [1 if philox4x32_10([i, 0, 2, 0], self.key)[0] < rho else 0 for i in range(cells)]
+        else:
+            e = self.eco
+            self.res = [0] * cells
+            self.cw, self.ce, self.cb = [0] * cells, [0] * cells, [0] * cells
+            tw, te, tb = (math.floor(f32(e[k]) * 4294967296.0)
+                          for k in ("water_density", "energy_density", "biomass_density"))
+            for i in range(cells):
+                x = philox4x32_10([i, 0, 2, 0], self.key)
+                self.cw[i] = e["water_site"] if x[1] < tw else 0
+                self.ce[i] = e["energy_site"] if x[2] < te else 0
+                self.cb[i] = e["biomass_site"] if x[3] < tb else 0
         order = sorted(range(cells), key=lambda i: (philox4x32_10([i, 0, 0, 0], self.key)[0], i))
         self.agents = {}  # slot -> dict
         for j in range(c["n_agents_init"]):
             self._spawn(j, order[j], philox4x32_10([j, 0, 1, 0], self.key)[0] >> 30, c["e_init"], j, None)
             self.agents[j]["theta"] = self._init_theta(j)
+            if self.eco is not None:
+                self.agents[j].update(water=self.eco["w_init"], biomass=self.eco["b_init"], hp=self.eco["hp_max"])
             if self.flags & COLOUR:
                 self.agents[j]["colour"] = self._init_colour(j)
 
@@ -165,11 +187,21 @@ class SpecWorld:
                     obs += self._render(cell)
                     continue
                 o = self.occ[cell]
+                if self.eco is not None:
+                    obs += [1.0 if o >= 0 else 0.0] + [min(v[cell], 255) / 16.0 for v in (self.cw, self.ce, self.cb)]
+                    continue
                 eb = 0
                 if o >= 0:  # energy bin of the occupant, 8 bins up to the reproduction threshold
                     eb = min(max(self.agents[o]["energy"] * 8 // self.c["e_repro"], 0), 7)
                 obs += [1.0 if o >= 0 else 0.0, float(self.res[cell]), float(self.wall[cell]), float(eb)]
         e = ag["energy"]
+        if self.eco is not None:
+            here = ag["cell"]
+            obs += [e / 256.0, min(ag["age"], 1024) / 1024.0, ag["water"] / 256.0, ag["biomass"] / 8.0,
+                    ag["hp"] / 128.0] + [min(v[here], 255) / 16.0 for v in (self.cw, self.ce, self.cb)]
+            if self.c["n_scalars"] == 12:
+                obs += [1.0 if k == ag["facing"] else 0.0 for k in range(4)]
+            return obs
         obs += [e / 256.0, min(ag["age"], 1024) / 1024.0, float(self.res[ag["cell"]]),
                 1.0 if e >= self.c["e_repro"] else 0.0]
         if self.c["n_scalars"] == 8:
@@ -266,6 +298,9 @@ class SpecWorld:
         # eat, cost, death, age
         for s in live:
             ag = self.agents[s]
+            if self.eco is not None:
+                self._ecology_agent(s, st)
+                continue
             if ag["cell"] in hit:
                 self.occ[ag["cell"]] = -1
                 self.res[ag["cell"]] = 1
@@ -288,7 +323,12 @@ class SpecWorld:
         claims = {}
         for s in sorted(self.agents):
             ag = self.agents[s]
-            if ag["energy"] < c["e_repro"] or (self.A == 7 and ag["action"] != REPRODUCE):
+            if self.eco is not None:
+                e = self.eco
+                if (ag["action"] != REPRO8 or ag["energy"] < c["e_repro"] or ag["water"] < e["w_child"]
+                        or ag["biomass"] < e["b_repro"]):
+                    continue
+            elif ag["energy"] < c["e_repro"] or (self.A == 7 and ag["action"] != REPRODUCE):
                 continue
             x, y = self._xy(ag["cell"])
             fx, fy = HEADINGS[ag["facing"]]
@@ -311,6 +351,11 @@ class SpecWorld:
             par = self.agents[p]
             par["energy"] -= c["e_child"]
             self._spawn(child, target_of[p], par["facing"], c["e_child"], self.uid_next + k, par["uid"])
+            if self.eco is not None:
+                e = self.eco
+                par["water"] -= e["w_child"]
+                par["biomass"] -= e["b_child"]
+                self.agents[child].update(water=e["w_child"], biomass=e["b_child"], hp=e["hp_child"])
             theta = []
             for q, v in enumerate(par["theta"]):
                 z = gauss4([p, n, 5, q // 4], self.key)[q % 4]
@@ -322,17 +367,73 @@ class SpecWorld:
             nb += 1
         st["births"] = nb
         self.uid_next += nb
-        # regrowth
+        # regrowth (ecology: photosynthesis on biomass)
         thr = math.floor(f32(c["regrow_prob"]) * 4294967296.0)
         for i in range(self.W * self.H):
-            if self.res[i] == 0 and philox4x32_10([i, n, 6, 0], self.key)[0] < thr:
+            if self.eco is not None:
+                b = self.cb[i]
+                if b <= 0 or self.ce[i] >= self.eco["cell_energy_max"]:
+                    continue
+                p = Fraction(f32(self.eco["photo_rate"])) * b
+                t = 2 ** 32 if p >= 1 else math.floor(p * 2 ** 32)
+                if philox4x32_10([i, n, 6, 0], self.key)[0] < t:
+                    self.ce[i] += 1
+                    st["regrown"] += 1
+            elif self.res[i] == 0 and philox4x32_10([i, n, 6, 0], self.key)[0] < thr:
                 self.res[i] = 1
                 st["regrown"] += 1
         self.step_no += 1
         st["population"] = len(self.agents)
         st["resource_total"] = sum(self.res)
+        if self.eco is not None:
+            st["resource_total"] = sum(self.ce)
+            st["water_total"] = sum(self.cw) + sum(a["water"] for a in self.agents.values())
+            st["biomass_total"] = sum(self.cb) + sum(a["biomass"] for a in self.agents.values())
+            st["hp_total"] = sum(a["hp"] for a in self.agents.values())
         st["energy_total"] = float(sum(a["energy"] for a in self.agents.values()))
         return st
+
+    def _ecology_agent(self, s, st):
+        """Eat, pay energy (destroyed) and water (back to the cell), take damage for
+        each overspent resource and for age, die at zero health leaving everything
+        carried on the cell, else heal with energy and age."""
+        e, c = self.eco, self.c
+        ag = self.agents[s]
+        cell, a = ag["cell"], ag["action"]
+        moved = 0
+        for act, key, grid, amount, cap in ((EAT_E, "energy", self.ce, c["e_eat"], e["cap_energy"]),
+                                            (EAT_W, "water", self.cw, e["eat_water"], e["cap_water"]),
+                                            (EAT_B, "biomass", self.cb, e["eat_biomass"], e["cap_biomass"])):
+            if a == act:
+                moved = min(amount, grid[cell], cap - ag[key])
+                if moved > 0:
+                    grid[cell] -= moved
+                    ag[key] += moved
+        if moved > 0:
+            st["eaten"] += 1
+        over = 0
+        ag["energy"] -= c["e_cost"] if a == REST else e["e_cost_move"]
+        if ag["energy"] < 0:
+            ag["energy"] = 0
+            over += 1
+        spend = min(ag["water"], e["w_cost"])
+        ag["water"] -= spend
+        self.cw[cell] += spend
+        if spend < e["w_cost"]:
+            over += 1
+        ag["hp"] -= over * e["hp_overspend"] + (ag["age"] >> e["age_shift"])
+        if ag["hp"] <= 0:
+            self.cw[cell] += ag["water"]
+            self.ce[cell] += ag["energy"]
+            self.cb[cell] += ag["biomass"]
+            self.occ[cell] = -1
+            del self.agents[s]
+            st["deaths"] += 1
+            return
+        if ag["hp"] < e["hp_max"] and ag["energy"] >= e["heal_energy"]:
+            ag["hp"] = min(ag["hp"] + e["hp_heal"], e["hp_max"])
+            ag["energy"] -= e["heal_energy"]
+        ag["age"] += 1
 
     def state(self):
         """Same dictionary shape as oracle.unpack_state (dead slots zeroed)."""
@@ -354,6 +455,15 @@ class SpecWorld:
             out["facing"][s] = ag["facing"]
             out["alive"][s] = 1
             out["action"][s] = ag["action"]
+        if self.eco is not None:
+            out["water"] = np.zeros(cap, np.int32)
+            out["biomass"] = np.zeros(cap, np.int32)
+            out["hp"] = np.zeros(cap, np.int32)
+            for s, ag in self.agents.items():
+                out["water"][s], out["biomass"][s], out["hp"][s] = ag["water"], ag["biomass"], ag["hp"]
+            out["cell_water"] = np.array(self.cw, np.int32)
+            out["cell_energy"] = np.array(self.ce, np.int32)
+            out["cell_biomass"] = np.array(self.cb, np.int32)
         return out
 
 
@@ -377,4 +487,8 @@ def from_state(cfg, st):
                        "theta": w._init_theta(s)}
         if w.flags & COLOUR:
             w.agents[s]["colour"] = w._init_colour(s)
+        if w.eco is not None:
+            w.agents[s].update(water=int(st["water"][s]), biomass=int(st["biomass"][s]), hp=int(st["hp"][s]))
+    if w.eco is not None:
+        w.cw, w.ce, w.cb = ([int(v) for v in st[k]] for k in ("cell_water", "cell_energy", "cell_biomass"))
     return w

@@ -686,6 +686,189 @@ def test_A8_victims_slot_and_cell_reused_by_a_birth():
 
 
 # ---------------------------------------------------------------------------
+# Three-resource ecology with health: hand-traced steps on a 6x6 torus
+# ---------------------------------------------------------------------------
+ECO_HAND = dict(water_density=0.0, energy_density=0.0, biomass_density=0.0, water_site=0, energy_site=0,
+                biomass_site=0, eat_water=10, eat_biomass=1, cap_water=60, cap_energy=400, cap_biomass=8,
+                e_cost_move=2, w_cost=3, photo_rate=0.0, cell_energy_max=40, hp_max=100, hp_child=50,
+                hp_overspend=20, hp_heal=10, heal_energy=1, age_shift=31, w_init=30, b_init=2, w_child=10,
+                b_child=1, b_repro=2)
+
+
+def eco_cfg(**eco):
+    e = dict(ECO_HAND, **eco)
+    return tiny_cfg(width=6, height=6, capacity=4, n_actions=8, n_scalars=8, flags=orc.ECOLOGY, eco=e,
+                    e_eat=10, e_cost=1, e_repro=200, e_child=50)
+
+
+def eco_place(st, slot, x, y, f, E, W, B, hp, age=0):
+    place(st, 6, slot, x, y, f, E, age=age)
+    st["water"][slot], st["biomass"][slot], st["hp"][slot] = W, B, hp
+
+
+def cidx(x, y):
+    return y * 6 + x
+
+
+def test_E1_eat_caps_costs_and_water_return():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 1, 1, N, 395, 30, 2, 100)          # eat energy: room for 5 under the cap of 400
+    eco_place(st, 1, 3, 1, N, 100, 55, 2, 100)          # eat water: room for 5 under 60
+    eco_place(st, 2, 1, 3, N, 100, 30, 7, 100)          # eat biomass: room for 1 under 8
+    eco_place(st, 3, 3, 3, N, 100, 30, 2, 100)          # rest
+    st["cell_energy"][cidx(1, 1)] = 20
+    st["cell_water"][cidx(3, 1)] = 20
+    st["cell_biomass"][cidx(1, 3)] = 3
+    out, s = run_both(eco_cfg(), st, [4, 5, 6, 0])
+    assert list(out["energy"]) == [398, 98, 98, 99]      # +5 - 2;  - 2;  - 2;  rest - 1
+    assert list(out["water"]) == [27, 57, 27, 27]        # every agent spends 3 (slot 1: 55 + 5 - 3)
+    assert list(out["biomass"]) == [2, 2, 8, 2]
+    assert out["cell_energy"][cidx(1, 1)] == 15 and out["cell_biomass"][cidx(1, 3)] == 2
+    assert out["cell_water"][cidx(3, 1)] == 20 - 5 + 3   # the spent water lands where it is spent
+    assert out["cell_water"][cidx(1, 1)] == 3 and out["cell_water"][cidx(3, 3)] == 3
+    assert s["eaten"] == 3 and s["water_total"] == 30 + 55 + 30 + 30 + 20 and list(out["hp"]) == [100] * 4
+
+
+def test_E2_overspend_age_damage_healing_and_death_deposit():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 1, 1, N, 1, 1, 3, 30)              # rest: energy 0 (not short), water short: -20
+    eco_place(st, 1, 3, 1, N, 1, 0, 3, 30)              # short of both: -40, dies
+    eco_place(st, 2, 1, 3, N, 50, 30, 2, 75, age=8)     # age damage 8 >> 2 = 2, then heals 10 for 1 energy
+    eco_place(st, 3, 3, 3, N, 300, 30, 2, 100, age=3)   # 3 >> 2 = 0: no damage
+    out, s = run_both(eco_cfg(age_shift=2), st, [0, 4, 0, 0])
+    assert list(out["alive"]) == [1, 0, 1, 1] and s["deaths"] == 1
+    assert out["hp"][0] == 10 and out["energy"][0] == 0 and out["water"][0] == 0
+    assert out["cell_water"][cidx(1, 1)] == 1
+    assert out["hp"][2] == 83 and out["energy"][2] == 48 and out["age"][2] == 9
+    assert out["hp"][3] == 100 and out["energy"][3] == 299
+    assert out["cell_biomass"][cidx(3, 1)] == 3 and out["occ"][cidx(3, 1)] == -1   # the body's biomass
+    assert s["water_total"] == 61 and s["biomass_total"] == 10
+
+
+def test_E3_birth_transfers_and_eligibility():
+    st = empty_state(6, 6, 4, ecology=True, uid_next=100)
+    eco_place(st, 0, 2, 2, N, 250, 30, 2, 100)          # eligible after paying 2 energy and 3 water
+    eco_place(st, 2, 4, 4, N, 250, 30, 1, 100)          # no spare biomass
+    eco_place(st, 3, 0, 0, N, 250, 5, 2, 100)           # 2 water left after the step: too little to give 10
+    out, s = run_both(eco_cfg(), st, [7, 0, 7, 7])
+    assert s["births"] == 1 and out["alive"][1] == 1 and xy(out, 1, 6) == (2, 3) and out["uid"][1] == 100
+    assert (out["energy"][1], out["water"][1], out["biomass"][1], out["hp"][1]) == (50, 10, 1, 50)
+    assert (out["energy"][0], out["water"][0], out["biomass"][0]) == (198, 17, 1)
+    assert (out["energy"][2], out["water"][2], out["biomass"][2]) == (248, 27, 1)
+    assert s["water_total"] == 65 and s["biomass_total"] == 5
+
+
+def test_E4_photosynthesis_extremes():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 0, 0, N, 100, 30, 2, 100)
+    st["cell_biomass"][cidx(2, 2)] = 2                    # 0.5 * 2 = 1: always
+    st["cell_biomass"][cidx(4, 4)] = 3
+    st["cell_energy"][cidx(4, 4)] = 40                    # full: never
+    st["cell_energy"][cidx(1, 4)] = 7                     # no biomass: never
+    out, s = run_both(eco_cfg(photo_rate=0.5), st, [0, 0, 0, 0])
+    assert out["cell_energy"][cidx(2, 2)] == 1 and out["cell_energy"][cidx(4, 4)] == 40
+    assert out["cell_energy"][cidx(1, 4)] == 7 and s["regrown"] == 1 and s["resource_total"] == 48
+    out, s = run_both(eco_cfg(photo_rate=0.0), st, [0, 0, 0, 0])
+    assert s["regrown"] == 0
+
+
+def test_photosynthesis_rate():
+    e = dict(ECO_HAND, biomass_density=1.0, biomass_site=1, photo_rate=0.01)
+    cfg = wl.desc(width=100, height=100, n_agents_init=1, capacity=4, window=3, n_scalars=8, n_actions=8,
+                  flags=orc.ECOLOGY, eco=e, seed=21)
+    w = orc.OracleWorld(cfg, materialize=False)
+    n = 0
+    for t in range(5):
+        w.step(actions=np.zeros(4, np.uint8))
+        n += w.stats()["regrown"]
+    cells = 10000 * 5
+    assert abs(n - 0.01 * cells) < 5 * math.sqrt(cells * 0.01 * 0.99)
+
+
+def _eco_run_cfg(seed, **kw):
+    e = dict(water_density=0.15, energy_density=0.1, biomass_density=0.25, water_site=20, energy_site=20,
+             biomass_site=3, eat_water=10, eat_biomass=1, cap_water=60, cap_energy=400, cap_biomass=8,
+             e_cost_move=2, w_cost=3, photo_rate=0.01, cell_energy_max=40, hp_max=100, hp_child=50,
+             hp_overspend=20, hp_heal=10, heal_energy=1, age_shift=2, w_init=30, b_init=2, w_child=10, b_child=1,
+             b_repro=2)
+    d = dict(width=12, height=10, n_agents_init=14, capacity=40, window=3, n_scalars=12, hidden1=32, hidden2=32,
+             n_actions=8, flags=orc.ECOLOGY, e_init=250, seed=seed, mutation_sigma=0.1, e_repro=200, e_child=50)
+    d.update(kw)
+    return wl.desc(eco=e, **d)
+
+
+def test_ecology_invariants_over_random_run():
+    """Water and biomass are conserved; N' = N + births - deaths; health stays in
+    (0, hp_max]; stomachs stay under their caps; one agent per cell."""
+    cfg = _eco_run_cfg(5, width=40, height=30, n_agents_init=200, capacity=320, window=5, n_scalars=8)
+    w = orc.OracleWorld(cfg, materialize=False)
+    s0 = w.stats()
+    e = cfg["eco"]
+    births = deaths = 0
+    for t in range(60):
+        pop = w.stats()["population"]
+        w.step(actions=wl.biased_actions(cfg["capacity"], 8, 5, t, p_forward=0.3, p_eat=0.2))
+        s = w.stats()
+        st = w.state()
+        assert s["water_total"] == s0["water_total"] and s["biomass_total"] == s0["biomass_total"]
+        assert s["population"] == pop + s["births"] - s["deaths"]
+        live = st["alive"].astype(bool)
+        assert np.all((st["hp"][live] > 0) & (st["hp"][live] <= e["hp_max"]))
+        assert np.all(st["water"][live] <= e["cap_water"]) and np.all(st["biomass"][live] <= e["cap_biomass"])
+        assert np.all(st["energy"][live] >= 0) and np.all(st["biomass"][live] >= 1)
+        assert s["hp_total"] == int(st["hp"][live].sum())
+        check_invariants(st, 40, 30)
+        births += s["births"]
+        deaths += s["deaths"]
+    assert births > 0 and deaths > 0
+
+
+def test_ecology_observation_matches_numpy():
+    cfg = _eco_run_cfg(9, width=23, height=17, n_agents_init=80, capacity=120, window=7)
+    w = orc.OracleWorld(cfg)
+    for t in range(3):
+        st = w.state()
+        Wd, Ht, Sw, R = 23, 17, 7, 3
+        occ = st["occ"].reshape(Ht, Wd)
+        layers = [(occ >= 0).astype(float)] + [np.minimum(st[k], 255).reshape(Ht, Wd) / 16.0
+                                               for k in ("cell_water", "cell_energy", "cell_biomass")]
+        for s in np.nonzero(st["alive"])[0][:40]:
+            x, y, f = st["pos"][s] % Wd, st["pos"][s] // Wd, int(st["facing"][s])
+            rows, cols = np.arange(y - R, y + R + 1) % Ht, np.arange(x - R, x + R + 1) % Wd
+            win = np.stack([np.rot90(l[np.ix_(rows, cols)], k=f) for l in layers], axis=-1).reshape(-1)
+            here = st["pos"][s]
+            sc = [st["energy"][s] / 256, min(st["age"][s], 1024) / 1024, st["water"][s] / 256, st["biomass"][s] / 8,
+                  st["hp"][s] / 128] + [min(st[k][here], 255) / 16 for k in ("cell_water", "cell_energy",
+                                                                             "cell_biomass")]
+            sc += [1.0 if k == f else 0.0 for k in range(4)]
+            np.testing.assert_array_equal(w.observe(int(s)), np.concatenate([win, sc]))
+        w.step()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ecology_oracle_matches_spec(seed):
+    cfg = _eco_run_cfg(seed)
+    o, sp = orc.OracleWorld(cfg), spec.SpecWorld(cfg)
+    assert_same_state(o.state(), sp.state(), "init")
+    tot = dict(births=0, deaths=0, eaten=0, regrown=0)
+    for t in range(25):
+        logits, _ = o.step(want_logits=True, want_sampled=True)
+        live = sorted(sp.agents)
+        spl = {k: sp.logits(k) for k in live}
+        sst = sp.step()
+        for k in live:
+            np.testing.assert_allclose(logits[k], spl[k], rtol=1e-12, atol=1e-12)
+        assert_same_state(o.state(), sp.state(), f"step {t}")
+        os_ = o.stats()
+        for k in ("births", "deaths", "eaten", "regrown", "population", "resource_total", "water_total",
+                  "biomass_total", "hp_total"):
+            assert os_[k] == sst[k], (t, k)
+        for k in tot:
+            tot[k] += sst[k]
+    assert all(v > 0 for v in tot.values()), tot
+
+
+# ---------------------------------------------------------------------------
 # N-version: C oracle vs python spec on tiny worlds, policy-sampled actions
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("seed,attack,flags", [(0, 0, 0), (1, 0, 0), (2, 1, 0), (3, 0, 7), (4, 1, 7), (5, 0, 1),
@@ -829,6 +1012,9 @@ def test_regrowth_rate():
 def test_invalid_descs_rejected():
     for bad in [dict(window=4), dict(n_scalars=5), dict(n_actions=6), dict(capacity=10, n_agents_init=20),
                 dict(e_repro=0), dict(wdtype=7), dict(window=99), dict(attack_enabled=1),
-                dict(n_actions=7, attack_enabled=2), dict(flags=8)]:
+                dict(n_actions=7, attack_enabled=2), dict(flags=16), dict(n_actions=8),
+                dict(flags=orc.ECOLOGY, n_actions=7), dict(flags=orc.ECOLOGY, n_actions=8, n_scalars=4),
+                dict(flags=orc.ECOLOGY | orc.COLOUR_VISION, n_actions=8, n_scalars=8),
+                dict(flags=orc.ECOLOGY, n_actions=8, n_scalars=8, attack_enabled=1)]:
         with pytest.raises(ValueError):
             orc.OracleWorld(wl.desc(**bad))

@@ -4,13 +4,19 @@ import numpy as np
 N, E, S, W = 0, 1, 2, 3
 
 
-def empty_state(width, height, cap, step=0, uid_next=100):
+def empty_state(width, height, cap, step=0, uid_next=100, ecology=False):
     cells = width * height
-    return {"step": step, "uid_next": uid_next,
-            "uid": np.zeros(cap, np.uint64), "parent_uid": np.full(cap, 0xFFFFFFFFFFFFFFFF, np.uint64),
-            "pos": np.full(cap, -1, np.int32), "energy": np.zeros(cap, np.int32), "age": np.zeros(cap, np.int32),
-            "occ": np.full(cells, -1, np.int32), "facing": np.zeros(cap, np.uint8), "alive": np.zeros(cap, np.uint8),
-            "action": np.zeros(cap, np.uint8), "res": np.zeros(cells, np.uint8), "wall": np.zeros(cells, np.uint8)}
+    st = {"step": step, "uid_next": uid_next,
+          "uid": np.zeros(cap, np.uint64), "parent_uid": np.full(cap, 0xFFFFFFFFFFFFFFFF, np.uint64),
+          "pos": np.full(cap, -1, np.int32), "energy": np.zeros(cap, np.int32), "age": np.zeros(cap, np.int32),
+          "occ": np.full(cells, -1, np.int32), "facing": np.zeros(cap, np.uint8), "alive": np.zeros(cap, np.uint8),
+          "action": np.zeros(cap, np.uint8), "res": np.zeros(cells, np.uint8), "wall": np.zeros(cells, np.uint8)}
+    if ecology:
+        for f in ("water", "biomass", "hp"):
+            st[f] = np.zeros(cap, np.int32)
+        for f in ("cell_water", "cell_energy", "cell_biomass"):
+            st[f] = np.zeros(cells, np.int32)
+    return st
 
 
 def place(st, width, slot, x, y, facing, energy, age=0, uid=None):
@@ -39,6 +45,12 @@ def assert_same_state(a, b, what=""):
         np.testing.assert_array_equal(a[f][live], b[f][live], err_msg=f"{what} {f}")
     for f in ("occ", "res", "wall"):
         np.testing.assert_array_equal(a[f], b[f], err_msg=f"{what} {f}")
+    assert ("hp" in a) == ("hp" in b), (what, "ecology fields on one side only")
+    if "hp" in a:   # the three-resource ecology
+        for f in ("water", "biomass", "hp"):
+            np.testing.assert_array_equal(a[f][live], b[f][live], err_msg=f"{what} {f}")
+        for f in ("cell_water", "cell_energy", "cell_biomass"):
+            np.testing.assert_array_equal(a[f], b[f], err_msg=f"{what} {f}")
 
 
 def check_invariants(st, width, height):
