@@ -84,6 +84,45 @@ typedef struct {
 #define ECO_DESC_FRONT_VISION 1u
 #define ECO_DESC_EVOLVE_TEMPERATURE 2u
 #define ECO_DESC_COLOUR_VISION 4u
+/* ECO_DESC_ECOLOGY: the paper's three-resource ecology with health (Sec. 3.2
+ * "Resources" and health points; App. "Varying Resource Rules", "Varying Agent
+ * HP"), with the parameters of eco_world_desc.eco.  Cells hold water, energy and
+ * biomass; agents carry the three in a capped stomach and have health.  Eight
+ * actions: rest, turn left, turn right, forward, eat energy, eat water, eat
+ * biomass, reproduce (n_actions = 8; no attack, colour vision or evolving
+ * temperature with it).  Per live agent after the moves: the chosen resource
+ * moves from its cell to its stomach (up to the eat amount, the cell's content and
+ * the room under the cap); energy is spent (e_cost at rest, e_cost_move
+ * otherwise; clamped at 0) and destroyed; w_cost water is spent onto the cell;
+ * each resource that ran short costs hp_overspend health, and age costs
+ * age >> age_shift; at health <= 0 the agent dies and its water, energy and
+ * biomass go to its cell; otherwise, below full health, heal_energy energy buys
+ * hp_heal health.  Reproduction (action 7) needs energy >= e_repro, water >=
+ * w_child and biomass >= b_repro and gives the child e_child energy, w_child
+ * water, b_child biomass and hp_child health.  Instead of regrowth, a cell with
+ * biomass b below cell_energy_max energy gains one energy unit with probability
+ * min(1, photo_rate * b) per step.  The window's four channels are agent present
+ * and the cell's water, energy and biomass, each min(units, 255) * 2^-4; the
+ * scalars (n_scalars 8, or 12 with the compass) are energy * 2^-8,
+ * min(age, 1024) * 2^-10, water * 2^-8, biomass * 2^-3, health * 2^-7 and the own
+ * cell's three channels.  Water and biomass are conserved. */
+#define ECO_DESC_ECOLOGY 8u
+
+/* Parameters of ECO_DESC_ECOLOGY (integer units; energy in 0.1 energy as the
+ * e_* fields, health in 0.1 HP).  Initial cells: a water / energy / biomass site
+ * with the given density holds water_site / energy_site / biomass_site units;
+ * initial agents carry w_init water, b_init biomass and hp_max health. */
+typedef struct {
+    float water_density, energy_density, biomass_density;
+    int32_t water_site, energy_site, biomass_site;
+    int32_t eat_water, eat_biomass;              /* eat energy moves e_eat */
+    int32_t cap_water, cap_energy, cap_biomass;  /* stomach capacities */
+    int32_t e_cost_move, w_cost;
+    float photo_rate;
+    int32_t cell_energy_max;
+    int32_t hp_max, hp_child, hp_overspend, hp_heal, heal_energy, age_shift;
+    int32_t w_init, b_init, w_child, b_child, b_repro;
+} eco_ecology;
 
 /* One world (POD, copied at create).  Grid is a torus of width x height. */
 typedef struct {
@@ -95,9 +134,9 @@ typedef struct {
     float regrow_prob;           /* per-step P(empty cell regrows one unit) */
     float mutation_sigma;        /* std of the child's Gaussian weight noise */
     uint32_t window;             /* S, odd, S <= width, S <= height, S <= 15 (ECO_ENOTSUP above) */
-    uint32_t n_scalars;          /* 4 (internal+external) or 8 (+compass) */
+    uint32_t n_scalars;          /* 4 (internal+external) or 8 (+compass); ecology: 8 or 12 */
     uint32_t hidden1, hidden2;   /* each 32, 64 or 128 */
-    uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack) */
+    uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack); ecology: 8 */
     int32_t e_init, e_cost, e_eat, e_repro, e_child;  /* units of 0.1 energy; e_repro > 0 */
     uint32_t wdtype;             /* eco_wdtype; identical for all worlds of one object */
     uint32_t keep_master;        /* reserved: BF16/FP8 always keep an FP32 master */
@@ -108,6 +147,7 @@ typedef struct {
                                     unit on its cell (Sec. 3.2 actions and health points; App.
                                     "Varying Attack Strength", full strength) */
     uint32_t flags;              /* ECO_DESC_* (unknown bits: EINVAL) */
+    eco_ecology eco;             /* used with ECO_DESC_ECOLOGY */
     uint64_t seed;               /* Philox key of this world */
 } eco_world_desc;
 
@@ -125,6 +165,11 @@ typedef struct {
     uint64_t action_hist[8];           /* actions taken by the agents live at step start */
     double energy_total;               /* sum of live energies (units of 0.1; exact) */
     double trait_mean, trait_var;      /* mean / variance over live agents of |theta_master|^2 */
+    /* ECO_DESC_ECOLOGY (else 0): water and biomass on the grid and in live agents
+       (both conserved), health of live agents.  There eaten counts eat actions
+       that moved a unit, regrown the energy units photosynthesis added and
+       resource_total the energy on the grid. */
+    uint64_t water_total, biomass_total, hp_total;
 } eco_stats;
 
 /* Launch shape of the policy-forward kernel (tuned by eco_world_autotune). */
@@ -229,6 +274,8 @@ eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions);
  *   u64 step, u64 uid_next, u32 width, u32 height, u32 capacity, u32 0   (32 B)
  *   u64 uid[cap], u64 parent_uid[cap], i32 pos[cap], i32 energy[cap], i32 age[cap],
  *   i32 occ[cells], u8 facing[cap], u8 alive[cap], u8 action[cap], u8 res[cells], u8 wall[cells]
+ *   then with ECO_DESC_ECOLOGY: i32 water[cap], i32 biomass[cap], i32 hp[cap],
+ *   i32 cell_water[cells], i32 cell_energy[cells], i32 cell_biomass[cells]
  * pos = y*width + x; occ = slot or -1; facing 0..3 = N,E,S,W (y grows down);
  * parent_uid of initial agents = UINT64_MAX.  Fields of dead slots other than
  * alive are unspecified.  bytes must be >= eco_world_state_bytes(). */

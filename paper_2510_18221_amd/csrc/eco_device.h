@@ -24,6 +24,8 @@ namespace eco {
 constexpr int kStatsRing = 1024;
 constexpr uint8_t kAlive = 1, kBirthClaim = 2, kBirthWon = 4;
 enum Action : uint8_t { REST = 0, TURN_L = 1, TURN_R = 2, FORWARD = 3, EAT = 4, REPRODUCE = 5, ATTACK = 6 };
+// The ecology's eight actions: EAT (4) takes energy, then water, biomass, reproduce.
+enum EcologyAction : uint8_t { EAT_WATER = 5, EAT_BIOMASS = 6, REPRODUCE_ECO = 7 };
 // Philox stream tags (third counter word).
 enum Stream : uint32_t { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
                          ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8 };
@@ -72,7 +74,7 @@ struct Layout {
   uint32_t ahead0;              // cells ahead of window row 0: R ("Around") or S - 1 ("Front")
   uint32_t temp;                // 1: log temperature stored after the output biases (b3[A])
   uint32_t colour;              // 1: colour trait and rendered colour window
-  uint32_t pad0;
+  uint32_t ecology;             // 1: three-resource ecology (cell words of water / energy / biomass levels)
   uint32_t P;                   // logical parameters (the log temperature included)
   uint32_t KB1;                 // FP32 16-byte blocks per L1 row
   uint32_t KBv;                 // storage 16-byte blocks per L1 row
@@ -103,7 +105,12 @@ struct Dev {
                                 // null when no world of the object has attacks
   uint8_t *res, *wall;
   uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
-  uint32_t* rgb;                // [total_cells] colour vision only: R | G << 8 | B << 16 | sense bits 0..2 << 24
+  uint32_t* rgb;                // [total_cells] window words, colour vision: R | G << 8 | B << 16, ecology:
+                                // water | energy << 8 | biomass << 16 (levels capped at 255); both with the
+                                // agent / resource / wall bits << 24
+  const eco_ecology* ep;        // [n_worlds] ecology parameters (null without the ecology)
+  int32_t *water, *biomass, *hp;        // [total_slots] ecology: stomach water and biomass, health
+  int32_t *cw, *ce, *cb;                // [total_cells] ecology: water, energy, biomass on the grid
   float4* colour;               // [total_slots] colour vision only: the colour trait (x, y, z = R, G, B)
   uint8_t* store;               // [total_slots][sstride]
   uint8_t* master;              // [total_slots][mstride] or == store for FP32
@@ -135,9 +142,10 @@ struct TileScratch {
   const uint32_t* tile_rng;
   uint32_t n_slot_tiles, n_cell_tiles;
   uint32_t* part_slot;   // [slot tiles][16] step counters (actions, moves, meals, deaths, blocked births)
-  uint32_t* part_cell;   // [cell tiles][2] regrown, resource total
+  uint32_t* part_cell;   // [cell tiles][4] regrown, resource total (ecology: energy), water, biomass
   uint32_t* scan;        // [slot tiles][4] claims, winners, free slots, live slots
   long long* esum;       // [slot tiles] energy sum of live slots
+  unsigned long long* ecosum;  // [slot tiles][3] ecology: water, biomass, health of live slots
   double* tsum;          // [slot tiles] trait sum
   double* tsq;           // [slot tiles] trait sum of squares
 };

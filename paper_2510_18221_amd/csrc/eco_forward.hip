@@ -321,6 +321,7 @@ __device__ __forceinline__ AgentCtx load_agent(const Dev& d, const uint32_t* wof
 }
 
 constexpr int kMaxWindowCellsPerLane = 4;  // S <= 15: S*S <= 256 cells over 64 lanes
+constexpr int kEcoLane = 61;               // lanes 61..63 of the last window slot: cells 253..255, never in a window
 
 // Sense bytes (or, with colour vision, rendered words) of agent c's window (Sec.
 // 3.2 sensors, App. F layout): lane owns window cells lane + 64k, row r = i / S
@@ -328,6 +329,10 @@ constexpr int kMaxWindowCellsPerLane = 4;  // S <= 15: S*S <= 256 cells over 64 
 // rotated so the agent faces row 0.  Row 0 lies L.ahead0 cells ahead: R for the
 // "Around" layout (the agent in the middle), S - 1 for "Front" (the agent in the
 // middle of the last row, nothing behind it seen).
+// WORDS: the window is read as 4-byte words (colour vision or the ecology), else
+// as sense bytes; a compile-time choice, so the byte path carries none of the
+// word path's code.
+template <bool WORDS>
 __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, const AgentCtx& c, int lane,
                                              uint32_t (&sv)[kMaxWindowCellsPerLane]) {
   const WorldParams& wp = c.wp;
@@ -345,7 +350,13 @@ __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, cons
       if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
       if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
       const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
-      sv[k] = L.colour ? d.rgb[cell] : (uint32_t)d.sense[cell];
+      if constexpr (WORDS) sv[k] = d.rgb[cell];
+      else sv[k] = d.sense[cell];
+    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
+      // ecology: the agent's water, biomass and health ride in window slots no
+      // window reaches (S*S <= 225 < 253), fetched with the window
+      const int32_t* src = lane == kEcoLane ? d.water : (lane == kEcoLane + 1 ? d.biomass : d.hp);
+      sv[k] = (uint32_t)src[c.slot];
     }
   }
 }
@@ -362,6 +373,7 @@ __device__ __forceinline__ uint32_t window_word(const uint32_t (&sv)[kMaxWindowC
 // Cell channels: agent, resource, wall, energy bin from the sense byte; with
 // colour vision the rendered R, G, B (8-bit values times 2^-8) and the
 // elevation difference, zero on the flat torus.
+template <bool WORDS>
 __device__ __forceinline__ void write_observation(const Layout& L, const AgentCtx& c, int lane,
                                                   const uint32_t (&sv)[kMaxWindowCellsPerLane], float* xs) {
   const int SS = (int)(L.S * L.S);
@@ -371,20 +383,43 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
     const int i = lane + 64 * k;
     if (i < SS) {
       const uint32_t v = sv[k];
-      reinterpret_cast<float4*>(xs)[i] =
-          L.colour ? make_float4(ldexpf((float)(v & 0xFFu), -8), ldexpf((float)((v >> 8) & 0xFFu), -8),
-                                 ldexpf((float)((v >> 16) & 0xFFu), -8), 0.0f)
-                   : make_float4((float)(v & 1u), (float)((v >> 1) & 1u), (float)((v >> 2) & 1u), (float)(v >> 3));
+      float4 o;
+      if constexpr (!WORDS) {
+        o = make_float4((float)(v & 1u), (float)((v >> 1) & 1u), (float)((v >> 2) & 1u), (float)(v >> 3));
+      } else if (L.colour) {
+        o = make_float4(ldexpf((float)(v & 0xFFu), -8), ldexpf((float)((v >> 8) & 0xFFu), -8),
+                        ldexpf((float)((v >> 16) & 0xFFu), -8), 0.0f);
+      } else {   // ecology: agent present, then the water, energy, biomass levels
+        o = make_float4((float)((v >> 24) & 1u), ldexpf((float)(v & 0xFFu), -4), ldexpf((float)((v >> 8) & 0xFFu), -4),
+                        ldexpf((float)((v >> 16) & 0xFFu), -4));
+      }
+      reinterpret_cast<float4*>(xs)[i] = o;
+      if (WORDS && L.ecology && i == centre) {   // external sensor: the own cell's water, energy, biomass levels
+        xs[4 * SS + 5] = o.y;
+        xs[4 * SS + 6] = o.z;
+        xs[4 * SS + 7] = o.w;
+      }
+    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
+      // the agent's water, biomass, health (fetched into this unused window slot)
+      const int j = lane - kEcoLane;
+      xs[4 * SS + 2 + j] = ldexpf((float)(int)sv[k], j == 0 ? -8 : (j == 1 ? -3 : -7));
     }
   }
   // colour words carry the cell's sense bits in their top byte
-  const float res_here = L.colour ? (float)((window_word(sv, centre) >> 25) & 1u) : 0.0f;
+  const float res_here = (WORDS && L.colour) ? (float)((window_word(sv, centre) >> 25) & 1u) : 0.0f;
+
   wave_sync();
-  if (lane < (int)L.ns) {
+  if (WORDS && L.ecology) {
+    // internal: energy, age (here), water, biomass, health (written above by the
+    // lanes that fetched them); external: the own cell's levels (written above);
+    // the compass when n_s = 12
+    if (lane < 2) xs[4 * SS + lane] = lane == 0 ? ldexpf((float)c.energy, -8) : ldexpf((float)min(c.age, 1024), -10);
+    else if (lane >= 8 && lane < (int)L.ns) xs[4 * SS + lane] = (lane - 8 == c.facing) ? 1.0f : 0.0f;
+  } else if (lane < (int)L.ns) {
     float v;
     if (lane == 0) v = ldexpf((float)c.energy, -8);
     else if (lane == 1) v = ldexpf((float)min(c.age, 1024), -10);
-    else if (lane == 2) v = L.colour ? res_here : xs[4 * centre + 1];  // resource here: the own cell's resource
+    else if (lane == 2) v = (WORDS && L.colour) ? res_here : xs[4 * centre + 1];  // resource here: the own cell's resource
     else if (lane == 3) v = (c.energy >= c.wp.e_repro) ? 1.0f : 0.0f;
     else v = (lane - 4 == c.facing) ? 1.0f : 0.0f;
     xs[4 * SS + lane] = v;
@@ -392,8 +427,16 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
   wave_sync();
 }
 
-template <int WDT, int H, int U>
-__global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
+// At least three waves per SIMD (two for the 16-deep variants of the 128-wide
+// layers and of the word path, whose loads in flight need the registers): the
+// compiler's own register choice moves between these variants from build to
+// build, and a wave fewer costs more than the few registers it frees.
+template <int H, int U, bool WORDS>
+constexpr int kMinWavesPerSimd = (U == 16 && (H == 128 || WORDS)) ? 2 : 3;
+
+template <int WDT, int H, int U, bool WORDS>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kMinWavesPerSimd<H, U, WORDS>)))
+void k_forward(Dev d, Layout L) {
   constexpr int VPL = WTraits<WDT>::VPL;
   extern __shared__ __align__(16) float smem[];
   const int lane = threadIdx.x & 63;
@@ -422,19 +465,19 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
 
   AgentCtx cur = load_agent(d, woff, g_lo, find_world(woff, d.n_worlds, g_lo));
   uint32_t sv[kMaxWindowCellsPerLane];
-  gather_sense(d, L, cur, lane, sv);
+  gather_sense<WORDS>(d, L, cur, lane, sv);
   for (uint32_t g = g_lo; g < g_hi; ++g) {
     const WorldParams& wp = cur.wp;
     // ---- 1. observation into LDS (window bytes fetched one agent ahead) ----
-    write_observation(L, cur, lane, sv, xs);
-    const uint32_t front_word = (L.colour && front >= 0) ? window_word(sv, front) : 0u;
+    write_observation<WORDS>(L, cur, lane, sv, xs);
+    const uint32_t front_word = (WORDS && front >= 0) ? window_word(sv, front) : 0u;
     // the next agent's context and window bytes, in flight while this agent streams
     const bool has_next = g + 1 < g_hi;
     AgentCtx nxt = cur;
     uint32_t sn[kMaxWindowCellsPerLane];
     if (has_next) {
       nxt = load_agent(d, woff, g + 1, cur.w);
-      gather_sense(d, L, nxt, lane, sn);
+      gather_sense<WORDS>(d, L, nxt, lane, sn);
     }
 
     // ---- 2. the agent's MLP, weights streamed once from HBM ----
@@ -505,7 +548,7 @@ __global__ __launch_bounds__(512) void k_forward(Dev d, Layout L) {
       else if (a == FORWARD) {
         const uint32_t tc = neighbour(wp, (uint32_t)cur.pos, f, +1);
         bool free_cell;
-        if (front >= 0 && L.colour) {  // agent and wall bits of the rendered word
+        if (WORDS && front >= 0) {  // agent and wall bits of the window word
           free_cell = ((front_word >> 24) & 5u) == 0u;
         } else if (front >= 0) {  // the observation holds the cell ahead as seen at step start
           free_cell = xs[4 * front] == 0.0f && xs[4 * front + 2] == 0.0f;
@@ -547,9 +590,11 @@ namespace eco {
 #define ECO_CAT(a, b) ECO_CAT2(a, b)
 hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 block, size_t shmem,
                                                   hipStream_t s, const Dev& d, const Layout& L) {
+  const bool words = (L.colour | L.ecology) != 0;
 #define ECO_CASE(HH, UU)                                                                          \
   if (H == HH && U == UU) {                                                                       \
-    hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU>), grid, block, shmem, s, d, L);            \
+    if (words) hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, true>), grid, block, shmem, s, d, L);  \
+    else hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, false>), grid, block, shmem, s, d, L);       \
     return hipGetLastError();                                                                     \
   }
   ECO_CASE(32, 4) ECO_CASE(32, 8) ECO_CASE(32, 16)
@@ -559,9 +604,11 @@ hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 
   return hipErrorInvalidValue;
 }
 // The kernel a launch of this storage type with (H, U) runs (graph nodes name it).
-const void* ECO_CAT(forward_kernel_w, ECO_FWD_WDT)(int H, int U) {
-#define ECO_FN(HH, UU) \
-  if (H == HH && U == UU) return reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU>);
+const void* ECO_CAT(forward_kernel_w, ECO_FWD_WDT)(int H, int U, bool words) {
+#define ECO_FN(HH, UU)                                                                          \
+  if (H == HH && U == UU)                                                                       \
+    return words ? reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, true>)         \
+                 : reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, false>);
   ECO_FN(32, 4) ECO_FN(32, 8) ECO_FN(32, 16)
   ECO_FN(64, 4) ECO_FN(64, 8) ECO_FN(64, 16)
   ECO_FN(128, 4) ECO_FN(128, 8) ECO_FN(128, 16)

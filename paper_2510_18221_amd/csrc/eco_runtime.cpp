@@ -20,9 +20,9 @@ hipError_t launch_forward_w0(int H, int U, dim3 grid, dim3 block, size_t shmem, 
                              const Layout& L);
 hipError_t launch_forward_w1(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
-const void* forward_kernel_w0(int H, int U);
-const void* forward_kernel_w1(int H, int U);
-const void* forward_kernel_w2(int H, int U);
+const void* forward_kernel_w0(int H, int U, bool words);
+const void* forward_kernel_w1(int H, int U, bool words);
+const void* forward_kernel_w2(int H, int U, bool words);
 hipError_t launch_forward_w2(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
 hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
@@ -51,7 +51,7 @@ namespace {
 constexpr uint32_t kSlotTileH = 256;
 constexpr uint32_t kCellTileH = 1024;
 constexpr uint32_t kSlotPartH = 16;
-constexpr uint32_t kCellPartH = 2;
+constexpr uint32_t kCellPartH = 4;
 constexpr uint32_t kMaxWorldsH = 1024;
 enum { EMIT_INIT = 0, EMIT_MUTATE = 1, EMIT_REQUANT = 2 };
 
@@ -172,8 +172,10 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (d.window < 1 || d.window % 2 == 0) return bad(ECO_EINVAL, "window", "must be odd");
   if (d.window > d.width || d.window > d.height) return bad(ECO_EINVAL, "window", "larger than the grid");
   if (d.window > 15) return bad(ECO_ENOTSUP, "window", "above 15 has no policy kernel");
-  if (d.n_scalars != 4 && d.n_scalars != 8) return bad(ECO_EINVAL, "n_scalars", "must be 4 or 8");
-  if (d.n_actions != 5 && d.n_actions != 7) return bad(ECO_EINVAL, "n_actions", "must be 5 or 7");
+  if ((d.flags & ECO_DESC_ECOLOGY) ? (d.n_scalars != 8 && d.n_scalars != 12) : (d.n_scalars != 4 && d.n_scalars != 8))
+    return bad(ECO_EINVAL, "n_scalars", "must be 4 or 8 (8 or 12 in the ecology)");
+  if (d.n_actions != 5 && d.n_actions != 7 && d.n_actions != 8)
+    return bad(ECO_EINVAL, "n_actions", "must be 5 or 7 (8 in the ecology)");
   if (d.e_repro <= 0) return bad(ECO_EINVAL, "e_repro", "must be > 0");
   if (d.wdtype > ECO_W_FP8E4M3) return bad(ECO_EINVAL, "wdtype", "unknown");
   if (!(d.resource_density >= 0.0f && d.resource_density <= 1.0f)) return bad(ECO_EINVAL, "resource_density", "outside [0,1]");
@@ -181,8 +183,28 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
   if (d.attack_enabled > 1) return bad(ECO_EINVAL, "attack_enabled", "must be 0 or 1");
   if (d.attack_enabled && d.n_actions != 7) return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7");
-  if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION))
+  if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION | ECO_DESC_ECOLOGY))
     return bad(ECO_EINVAL, "flags", "has unknown bits");
+  if (d.flags & ECO_DESC_ECOLOGY) {
+    const eco_ecology& e = d.eco;
+    if (d.n_actions != 8) return bad(ECO_EINVAL, "n_actions", "must be 8 in the ecology");
+    if (d.attack_enabled || (d.flags & (ECO_DESC_COLOUR_VISION | ECO_DESC_EVOLVE_TEMPERATURE)))
+      return bad(ECO_EINVAL, "flags", "the ecology runs without attack, colour vision and evolving temperature");
+    if (e.hp_max <= 0 || e.hp_child <= 0 || e.hp_child > e.hp_max) return bad(ECO_EINVAL, "eco.hp_*", "bad limits");
+    if (e.age_shift < 0 || e.age_shift > 31) return bad(ECO_EINVAL, "eco.age_shift", "outside [0, 31]");
+    if (e.cap_water < 0 || e.cap_energy < 0 || e.cap_biomass < 0 || e.eat_water < 0 || e.eat_biomass < 0 ||
+        e.w_cost < 0 || e.e_cost_move < 0 || e.hp_overspend < 0 || e.hp_heal < 0 || e.heal_energy < 0 ||
+        e.w_init < 0 || e.b_init < 0 || e.w_child < 0 || e.b_child < 0 || e.b_repro < e.b_child ||
+        e.water_site < 0 || e.energy_site < 0 || e.biomass_site < 0 || e.cell_energy_max < 0 || d.e_eat < 0 ||
+        d.e_cost < 0 || d.e_child < 0)
+      return bad(ECO_EINVAL, "eco", "amounts must be >= 0 and b_repro >= b_child");
+    auto unit = [](float p) { return p >= 0.0f && p <= 1.0f; };
+    if (!(e.photo_rate >= 0.0f) || std::isinf(e.photo_rate) || !unit(e.water_density) || !unit(e.energy_density) ||
+        !unit(e.biomass_density))
+      return bad(ECO_EINVAL, "eco", "densities must lie in [0,1] and photo_rate be finite and >= 0");
+  } else if (d.n_actions == 8) {
+    return bad(ECO_EINVAL, "n_actions", "8 needs ECO_DESC_ECOLOGY");
+  }
   auto okh = [](uint32_t h) { return h == 32 || h == 64 || h == 128; };
   if (!okh(d.hidden1) || !okh(d.hidden2)) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be 32, 64 or 128");
   if (d.hidden1 != d.hidden2) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be equal");
@@ -203,6 +225,7 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
   L.ahead0 = (d.flags & ECO_DESC_FRONT_VISION) ? d.window - 1 : L.R;
   L.temp = (d.flags & ECO_DESC_EVOLVE_TEMPERATURE) ? 1u : 0u;
   L.colour = (d.flags & ECO_DESC_COLOUR_VISION) ? 1u : 0u;
+  L.ecology = (d.flags & ECO_DESC_ECOLOGY) ? 1u : 0u;
   L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A + L.temp;
   L.p_w1 = 0;
   L.p_b1 = L.p_w1 + L.H1 * L.D;
@@ -469,8 +492,10 @@ eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {
     return st;
   }
   const int u = (int)w->launch.unroll, H = (int)w->L.H1;
-  const void* fwd = w->L.wdtype == 0 ? forward_kernel_w0(H, u) : w->L.wdtype == 1 ? forward_kernel_w1(H, u)
-                                                                                  : forward_kernel_w2(H, u);
+  const bool words = (w->L.colour | w->L.ecology) != 0;
+  const void* fwd = w->L.wdtype == 0   ? forward_kernel_w0(H, u, words)
+                    : w->L.wdtype == 1 ? forward_kernel_w1(H, u, words)
+                                       : forward_kernel_w2(H, u, words);
   size_t cnt = 0;
   if (e == hipSuccess) e = hipGraphGetNodes(t.graph, nullptr, &cnt);
   std::vector<hipGraphNode_t> nodes(cnt);
@@ -680,7 +705,16 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.res = (uint8_t*)A(TC);
   d.wall = (uint8_t*)A(TC);
   d.sense = (uint8_t*)A(TC);
-  d.rgb = w->L.colour ? (uint32_t*)A(4 * TC) : nullptr;
+  d.rgb = (w->L.colour || w->L.ecology) ? (uint32_t*)A(4 * TC) : nullptr;
+  if (w->L.ecology) {
+    d.ep = (const eco_ecology*)A(sizeof(eco_ecology) * n_worlds);
+    d.water = (int32_t*)A(4 * TS);
+    d.biomass = (int32_t*)A(4 * TS);
+    d.hp = (int32_t*)A(4 * TS);
+    d.cw = (int32_t*)A(4 * TC);
+    d.ce = (int32_t*)A(4 * TC);
+    d.cb = (int32_t*)A(4 * TC);
+  }
   d.colour = w->L.colour ? (float4*)A(16 * TS) : nullptr;
   d.live = (int32_t*)A(4 * TS);
   d.bparent = (int32_t*)A(4 * TS);
@@ -707,6 +741,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     ts.part_cell = w->part_cell;
     ts.scan = (uint32_t*)A(16 * T);
     ts.esum = (long long*)A(8 * T);
+    ts.ecosum = w->L.ecology ? (unsigned long long*)A(3 * 8 * T) : nullptr;
     ts.tsum = (double*)A(8 * T);
     ts.tsq = (double*)A(8 * T);
   }
@@ -744,6 +779,13 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   chk(hipMemsetAsync(w->part_slot, 0, 4ull * kSlotPartH * std::max(1u, w->n_slot_tiles), s), "clear partials");
   chk(hipMemsetAsync(w->part_cell, 0, 4ull * kCellPartH * std::max(1u, w->n_cell_tiles), s), "clear partials");
   chk(hipMemsetAsync(d.cnt, 0, sizeof(StepCounters) * n_worlds, s), "clear counters");
+  if (d.ep) {
+    std::vector<eco_ecology> ep(n_worlds);
+    for (uint32_t i = 0; i < n_worlds; ++i) ep[i] = descs[i].eco;
+    chk(hipMemcpyAsync((void*)d.ep, ep.data(), sizeof(eco_ecology) * n_worlds, hipMemcpyHostToDevice, s),
+        "upload ecology parameters");
+    chk(hipStreamSynchronize(s), "upload ecology parameters");
+  }
   if (st == ECO_OK) st = run_init(w);
   if (st != ECO_OK) {
     std::string msg = g_err;
@@ -1010,7 +1052,7 @@ eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset
 size_t eco_world_state_bytes(const eco_world* w, uint32_t world) {
   if (!w || world >= w->n_worlds) return 0;
   const uint64_t cap = w->wp[world].cap, cells = w->wp[world].cells;
-  return 32 + cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + cells * (4 + 1 + 1);
+  return 32 + cap * (8 + 8 + 4 + 4 + 4 + 1 + 1 + 1) + cells * (4 + 1 + 1) + (w->L.ecology ? 12 * (cap + cells) : 0);
 }
 
 eco_status eco_world_read_state(eco_world* w, uint32_t world, void* buf, size_t bytes) {
@@ -1043,6 +1085,14 @@ eco_status eco_world_read_state(eco_world* w, uint32_t world, void* buf, size_t 
   HIPCHK(w, cp(w->d.act + p.slot_off, cap), "read action");
   HIPCHK(w, cp(w->d.res + p.cell_off, cells), "read res");
   HIPCHK(w, cp(w->d.wall + p.cell_off, cells), "read wall");
+  if (w->L.ecology) {
+    HIPCHK(w, cp(w->d.water + p.slot_off, cap * 4), "read water");
+    HIPCHK(w, cp(w->d.biomass + p.slot_off, cap * 4), "read biomass");
+    HIPCHK(w, cp(w->d.hp + p.slot_off, cap * 4), "read hp");
+    HIPCHK(w, cp(w->d.cw + p.cell_off, cells * 4), "read cell water");
+    HIPCHK(w, cp(w->d.ce + p.cell_off, cells * 4), "read cell energy");
+    HIPCHK(w, cp(w->d.cb + p.cell_off, cells * 4), "read cell biomass");
+  }
   st = sync(w);
   if (st != ECO_OK) return st;
   for (size_t i = 0; i < cap; ++i) alive[i] &= kAlive;
@@ -1088,6 +1138,14 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
     if (res[c] > 1 || wall[c] > 1) return fail(ECO_EINVAL, "res and wall must be 0 or 1");
     walls |= wall[c] != 0;
   }
+  if (w->L.ecology) {   // water, biomass, health per slot, then the grid's three layers
+    const uint8_t* e8 = wall + cells;
+    for (size_t i = 0; i < 3 * cap + 3 * cells; ++i) {
+      int32_t v;
+      std::memcpy(&v, e8 + 4 * i, 4);
+      if (v < 0) return fail(ECO_EINVAL, "ecology amounts and health must be >= 0");
+    }
+  }
   std::vector<uint8_t> old(cap);
   hipStream_t s = w->stream;
   HIPCHK(w, hipMemcpyAsync(old.data(), w->d.flags + p.slot_off, cap, hipMemcpyDeviceToHost, s), "read flags");
@@ -1117,6 +1175,14 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
   HIPCHK(w, cp(w->d.act + p.slot_off, cap), "write action");
   HIPCHK(w, cp(w->d.res + p.cell_off, cells), "write res");
   HIPCHK(w, cp(w->d.wall + p.cell_off, cells), "write wall");
+  if (w->L.ecology) {
+    HIPCHK(w, cp(w->d.water + p.slot_off, cap * 4), "write water");
+    HIPCHK(w, cp(w->d.biomass + p.slot_off, cap * 4), "write biomass");
+    HIPCHK(w, cp(w->d.hp + p.slot_off, cap * 4), "write hp");
+    HIPCHK(w, cp(w->d.cw + p.cell_off, cells * 4), "write cell water");
+    HIPCHK(w, cp(w->d.ce + p.cell_off, cells * 4), "write cell energy");
+    HIPCHK(w, cp(w->d.cb + p.cell_off, cells * 4), "write cell biomass");
+  }
   if (p.attack) HIPCHK(w, hipMemsetAsync(w->d.mark + p.cell_off, 0, cells * 4, s), "clear attack stamps");
   if (walls != (w->wp[world].has_walls != 0)) {
     w->wp[world].has_walls = walls ? 1u : 0u;

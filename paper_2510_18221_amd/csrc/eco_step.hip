@@ -24,7 +24,7 @@ constexpr int kSlotTile = 256;   // slots per block in per-slot kernels
 // Cell tiles (1024 cells each) are built on the host; per-cell kernels take one tile per block.
 constexpr int kScanThreads = 1024;
 constexpr int kSlotPart = 16;    // u32 counters per slot tile
-constexpr int kCellPart = 2;     // u32 counters per cell tile
+constexpr int kCellPart = 4;     // u32 counters per cell tile
 
 // Per-slot-tile counters (index in the partials row).
 enum { PC_HIST = 0, PC_MOVES_OK = 8, PC_MOVES_BLOCKED = 9, PC_EATEN = 10, PC_DEATHS = 11, PC_BB_CELL = 12,
@@ -297,6 +297,57 @@ __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp,
 // Step kernels
 // ---------------------------------------------------------------------------
 // Winners move, then EAT, step cost, death, age; per-tile counters.
+// Three-resource ecology, one live agent after the moves (it touches only its own
+// cell c, which no other agent touches in this launch): eat the chosen resource
+// (up to the eat amount, the cell's content and the room under the stomach cap);
+// pay energy (destroyed; rest costs least) and water (onto the cell); each
+// resource that ran short and the agent's age cost health; at zero health the
+// agent dies and leaves water, energy and biomass on its cell; otherwise energy
+// heals it below full health and it ages.  Returns the new energy.
+__device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e, const WorldParams& wp, uint32_t slot,
+                                             uint32_t c, int a, uint32_t* cnt) {
+  int E = d.energy[slot], Wt = d.water[slot], B = d.biomass[slot], hp = d.hp[slot];
+  int t = 0;
+  if (a == EAT) {
+    t = min(min(wp.e_eat, d.ce[c]), e.cap_energy - E);
+    if (t > 0) { d.ce[c] -= t; E += t; }
+  } else if (a == EAT_WATER) {
+    t = min(min(e.eat_water, d.cw[c]), e.cap_water - Wt);
+    if (t > 0) { d.cw[c] -= t; Wt += t; }
+  } else if (a == EAT_BIOMASS) {
+    t = min(min(e.eat_biomass, d.cb[c]), e.cap_biomass - B);
+    if (t > 0) { d.cb[c] -= t; B += t; }
+  }
+  if (t > 0) atomicAdd(&cnt[PC_EATEN], 1u);
+  int over = 0;
+  E -= (a == REST) ? wp.e_cost : e.e_cost_move;
+  if (E < 0) { E = 0; ++over; }
+  const int spend = min(Wt, e.w_cost);
+  Wt -= spend;
+  d.cw[c] += spend;
+  if (spend < e.w_cost) ++over;
+  hp -= over * e.hp_overspend + (d.age[slot] >> e.age_shift);
+  if (hp <= 0) {
+    d.cw[c] += Wt;
+    d.ce[c] += E;
+    d.cb[c] += B;
+    E = Wt = B = hp = 0;
+    d.flags[slot] = 0;
+    d.occ[c] = -1;
+    atomicAdd(&cnt[PC_DEATHS], 1u);
+  } else {
+    if (hp < e.hp_max && E >= e.heal_energy) {
+      hp = min(hp + e.hp_heal, e.hp_max);
+      E -= e.heal_energy;
+    }
+    d.age[slot] += 1;
+  }
+  d.water[slot] = Wt;
+  d.biomass[slot] = B;
+  d.hp[slot] = hp;
+  return E;
+}
+
 __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part) {
   __shared__ uint32_t cnt[kSlotPart];
   if (threadIdx.x < kSlotPart) cnt[threadIdx.x] = 0;
@@ -325,7 +376,9 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
         }
       }
       int E = d.energy[slot];
-      if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
+      if (d.ep) {
+        E = ecology_agent(d, d.ep[tl.world], wp, slot, wp.cell_off + (uint32_t)cell, a, cnt);
+      } else if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
         // struck after the moves: dies where it stands; its carried energy goes
         // back to the cell as one resource unit (cells hold 0 or 1 unit)
         d.flags[slot] = 0;
@@ -369,7 +422,12 @@ __device__ __forceinline__ void birth_claim_tile(const Dev& d, const TileScratch
     const uint32_t slot = wp.slot_off + local;
     const uint8_t fl = d.flags[slot];
     if (fl & kAlive) {
-      const bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
+      bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
+      if (d.ep) {   // ecology: the eighth action, and spare biomass and water to give the child
+        const eco_ecology& e = d.ep[tl.world];
+        eligible = d.act[slot] == REPRODUCE_ECO && d.energy[slot] >= wp.e_repro && d.water[slot] >= e.w_child &&
+                   d.biomass[slot] >= e.b_repro;
+      }
       if (eligible) {
         const uint32_t t = neighbour(wp, (uint32_t)d.pos[slot], d.facing[slot], -1);
         const bool walled = wp.has_walls && d.wall[wp.cell_off + t];
@@ -392,6 +450,36 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
   const WorldParams wp = d.wp[tl.world];
   const uint32_t step = (uint32_t)d.wv[tl.world].step;
   uint32_t grown = 0, total = 0;
+  if (d.ep) {
+    // ecology: photosynthesis, one energy unit with probability min(1, rate * biomass)
+    // on cells holding biomass below the energy ceiling (rate * biomass exact in FP64);
+    // the tile's grid totals of energy, water and biomass for the statistics
+    const eco_ecology& e = d.ep[tl.world];
+    uint32_t wsum = 0, bsum = 0;
+    for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+      const uint32_t c = tl.start + i, g = wp.cell_off + c;
+      const int b = d.cb[g];
+      int en = d.ce[g];
+      if (b > 0 && en < e.cell_energy_max) {
+        const double p = (double)e.photo_rate * (double)b;
+        const uint64_t thr = p >= 1.0 ? (1ull << 32) : (uint64_t)floor(p * 4294967296.0);
+        if ((uint64_t)draw32(wp, c, step, ST_REGROW) < thr) {
+          d.ce[g] = ++en;
+          ++grown;
+        }
+      }
+      total += (uint32_t)en;
+      wsum += (uint32_t)d.cw[g];
+      bsum += (uint32_t)b;
+    }
+    if (grown) atomicAdd(&cnt[0], grown);
+    atomicAdd(&cnt[1], total);
+    atomicAdd(&cnt[2], wsum);
+    atomicAdd(&cnt[3], bsum);
+    __syncthreads();
+    if (threadIdx.x < kCellPart) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
+    return;
+  }
   for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
     const uint32_t c = tl.start + i;
     uint8_t r = d.res[wp.cell_off + c];
@@ -405,12 +493,12 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
   if (grown) atomicAdd(&cnt[0], grown);
   atomicAdd(&cnt[1], total);
   __syncthreads();
-  if (threadIdx.x < 2) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < kCellPart) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_birth_claim_regrow(Dev d, TileScratch ts, uint32_t n_actions) {
-  __shared__ uint32_t cnt[2];
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __shared__ uint32_t cnt[kCellPart];
+  if (threadIdx.x < kCellPart) cnt[threadIdx.x] = 0;
   __syncthreads();
   if (blockIdx.x < ts.n_slot_tiles) birth_claim_tile(d, ts, blockIdx.x, n_actions, &cnt[0]);
   else regrow_tile(d, ts, blockIdx.x - ts.n_slot_tiles, cnt);
@@ -551,6 +639,14 @@ __global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
       d.age[cg] = 0;
       d.uid[cg] = d.wv[w].uid_next + k;
       d.puid[cg] = d.uid[pg];
+      if (d.ep) {   // ecology: the parent gives water and biomass; the child starts at hp_child
+        const eco_ecology& e = d.ep[w];
+        d.water[pg] -= e.w_child;
+        d.biomass[pg] -= e.b_child;
+        d.water[cg] = e.w_child;
+        d.biomass[cg] = e.b_child;
+        d.hp[cg] = e.hp_child;
+      }
     }
     emit_agent<WDT>(d, L, wp, cg, EMIT_MUTATE, pg, p_local, step, 0.0, 0.0, 0.0, s_amax, s_red);
     __syncthreads();
@@ -579,6 +675,18 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch 
   const unsigned long long es = block_sum_u64<kSlotTile>((unsigned long long)e, red64);
   const double s1 = block_sum_f64<kSlotTile>(t, redf);
   const double s2 = block_sum_f64<kSlotTile>(t * t, redf);
+  if (d.ep) {   // ecology: water, biomass and health carried by the tile's live agents
+    const uint32_t slot = wp.slot_off + tl.start + threadIdx.x;
+    const bool on = alive && threadIdx.x < tl.count;
+    const unsigned long long ws = block_sum_u64<kSlotTile>(on ? (unsigned long long)d.water[slot] : 0ull, red64);
+    const unsigned long long bs = block_sum_u64<kSlotTile>(on ? (unsigned long long)d.biomass[slot] : 0ull, red64);
+    const unsigned long long hs = block_sum_u64<kSlotTile>(on ? (unsigned long long)d.hp[slot] : 0ull, red64);
+    if (threadIdx.x == 0) {
+      ts.ecosum[3 * blockIdx.x] = ws;
+      ts.ecosum[3 * blockIdx.x + 1] = bs;
+      ts.ecosum[3 * blockIdx.x + 2] = hs;
+    }
+  }
   if (threadIdx.x == 0) {
     ts.scan[blockIdx.x * 4 + 3] = (uint32_t)n;
     ts.esum[blockIdx.x] = (long long)es;
@@ -636,6 +744,19 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
   }
 }
 
+// Ecology: the cell's water, energy and biomass levels (capped at 255) and its
+// agent / wall bits in the top byte.
+__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const Tile tl) {
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t cell = wp.cell_off + tl.start + i;
+    const uint32_t w8 = (uint32_t)min(max(d.cw[cell], 0), 255), e8 = (uint32_t)min(max(d.ce[cell], 0), 255),
+                   b8 = (uint32_t)min(max(d.cb[cell], 0), 255);
+    const bool wl = wp.has_walls && d.wall[cell] != 0;
+    d.rgb[cell] = w8 | (e8 << 8) | (b8 << 16) | (((d.occ[cell] >= 0 ? 1u : 0u) | (wl ? 4u : 0u)) << 24);
+  }
+}
+
 __device__ __forceinline__ void cell_sense_tile(const Dev& d, const Tile tl) {
   const WorldParams wp = d.wp[tl.world];
   for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
@@ -682,6 +803,18 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
   const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
   const double T1 = block_sum_f64<NT>(s1, redf);
   const double T2 = block_sum_f64<NT>(s2, redf);
+  unsigned long long eco_w = 0, eco_b = 0, eco_h = 0;   // ecology: carried water, biomass, health
+  if (d.ep) {
+    unsigned long long a = 0, b = 0, c = 0;
+    for (uint32_t t = lo; t < hi; ++t) {
+      a += ts.ecosum[3 * t];
+      b += ts.ecosum[3 * t + 1];
+      c += ts.ecosum[3 * t + 2];
+    }
+    eco_w = block_sum_u64<NT>(a, red64);
+    eco_b = block_sum_u64<NT>(b, red64);
+    eco_h = block_sum_u64<NT>(c, red64);
+  }
   if (threadIdx.x < kSlotPart + kCellPart) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   if (!init) {
@@ -723,7 +856,12 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
       for (int a = 0; a < 8; ++a) st.action_hist[a] = s_cnt[PC_HIST + a];
       st.regrown = s_cnt[kSlotPart + 0];
       st.resource_total = s_cnt[kSlotPart + 1];
+      if (d.ep) {
+        st.water_total = eco_w + s_cnt[kSlotPart + 2];
+        st.biomass_total = eco_b + s_cnt[kSlotPart + 3];
+      }
     }
+    if (d.ep) st.hp_total = eco_h;   // (init records get the grid parts from k_resource_total)
     const double mean = N ? T1 / (double)N : 0.0;
     v.n_live = N;
     st.step = v.step;
@@ -747,7 +885,8 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   if (blockIdx.x >= ts.n_slot_tiles) {
     const Tile ct = ts.cell_tiles[blockIdx.x - ts.n_slot_tiles];
     if (only_world < 0 || (int)ct.world == only_world) {
-      if (d.rgb) cell_render_tile(d, ct);
+      if (d.ep) cell_ecology_tile(d, ct);
+      else if (d.rgb) cell_render_tile(d, ct);
       else cell_sense_tile(d, ct);
     }
     return;
@@ -780,14 +919,47 @@ __global__ __launch_bounds__(kScanThreads) void k_resource_total(Dev d, int only
   if (only_world >= 0 && (int)w != only_world) return;
   const WorldParams wp = d.wp[w];
   unsigned long long s = 0;
+  eco_stats* rec = &d.ring[(uint64_t)w * kStatsRing + (d.wv[w].step % kStatsRing)];
+  if (d.ep) {   // ecology: energy on the grid; water and biomass on the grid and in live agents
+    unsigned long long sw = 0, sb = 0;
+    for (uint32_t c = threadIdx.x; c < wp.cells; c += blockDim.x) {
+      const uint32_t g = wp.cell_off + c;
+      s += (unsigned long long)d.ce[g];
+      sw += (unsigned long long)d.cw[g];
+      sb += (unsigned long long)d.cb[g];
+    }
+    for (uint32_t j = threadIdx.x; j < wp.cap; j += blockDim.x) {
+      const uint32_t g = wp.slot_off + j;
+      if (d.flags[g] & kAlive) {
+        sw += (unsigned long long)d.water[g];
+        sb += (unsigned long long)d.biomass[g];
+      }
+    }
+    const unsigned long long t = block_sum_u64<kScanThreads>(s, red64);
+    const unsigned long long tw = block_sum_u64<kScanThreads>(sw, red64);
+    const unsigned long long tb = block_sum_u64<kScanThreads>(sb, red64);
+    if (threadIdx.x == 0) {
+      rec->resource_total = t;
+      rec->water_total = tw;
+      rec->biomass_total = tb;
+    }
+    return;
+  }
   for (uint32_t c = threadIdx.x; c < wp.cells; c += blockDim.x) s += d.res[wp.cell_off + c];
   const unsigned long long t = block_sum_u64<kScanThreads>(s, red64);
-  if (threadIdx.x == 0) d.ring[(uint64_t)w * kStatsRing + (d.wv[w].step % kStatsRing)].resource_total = t;
+  if (threadIdx.x == 0) rec->resource_total = t;
 }
 
 // ---------------------------------------------------------------------------
 // Init kernels
 // ---------------------------------------------------------------------------
+// floor(p * 2^32) clamped to [0, 2^32]: a 32-bit draw x is a Bernoulli(p) success iff x < it.
+__device__ __forceinline__ uint64_t density_threshold(float p) {
+  double t = floor((double)p * 4294967296.0);
+  t = t < 0.0 ? 0.0 : (t > 4294967296.0 ? 4294967296.0 : t);
+  return (uint64_t)t;
+}
+
 // Cell keys (for placement), initial resources, empty occupancy and claims.
 __global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
@@ -797,6 +969,14 @@ __global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restric
     const uint32_t key = draw32(wp, c, 0u, ST_CELLKEY);
     d.cellkeys[g] = ((unsigned long long)key << 32) | c;
     d.res[g] = ((uint64_t)draw32(wp, c, 0u, ST_RESINIT) < wp.density_thr) ? 1 : 0;
+    if (d.ep) {   // ecology: water, energy, biomass sites from outputs 1..3 of the same block
+      const eco_ecology& e = d.ep[tl.world];
+      const uint4 x = philox10(c, 0u, ST_RESINIT, 0u, wp.key0, wp.key1);
+      d.res[g] = 0;
+      d.cw[g] = ((uint64_t)x.y < density_threshold(e.water_density)) ? e.water_site : 0;
+      d.ce[g] = ((uint64_t)x.z < density_threshold(e.energy_density)) ? e.energy_site : 0;
+      d.cb[g] = ((uint64_t)x.w < density_threshold(e.biomass_density)) ? e.biomass_site : 0;
+    }
     d.occ[g] = -1;
     d.claim[g] = 0xFFFFFFFFu;
     if (wp.attack) d.mark[g] = 0;
@@ -821,6 +1001,11 @@ __global__ __launch_bounds__(kSlotTile) void k_init_agents(Dev d, const Tile* __
     d.facing[g] = (uint8_t)(draw32(wp, j, 0u, ST_FACING) >> 30);
     d.energy[g] = wp.e_init;
     d.age[g] = 0;
+    if (d.ep) {
+      d.water[g] = d.ep[tl.world].w_init;
+      d.biomass[g] = d.ep[tl.world].b_init;
+      d.hp[g] = d.ep[tl.world].hp_max;
+    }
     d.uid[g] = j;
     d.puid[g] = ~0ull;
   } else {

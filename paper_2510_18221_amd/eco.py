@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libeco.so")
 
 ECO_OK, ECO_EINVAL, ECO_ENOMEM, ECO_EDEVICE, ECO_ESTATE, ECO_ENOTSUP = 0, -1, -2, -3, -4, -5
 RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS = 1, 2, 4
-DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION = 1, 2, 4   # eco_world_desc.flags
+DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION, DESC_ECOLOGY = 1, 2, 4, 8   # eco_world_desc.flags
 KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact", "sense"]
 
 EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world_step", "eco_world_reset",
@@ -33,6 +33,17 @@ class EcoError(RuntimeError):
         self.status = status
 
 
+class Ecology(ctypes.Structure):
+    """eco_ecology of include/eco.h."""
+    _fields_ = [("water_density", ctypes.c_float), ("energy_density", ctypes.c_float),
+                ("biomass_density", ctypes.c_float)] + [(n, ctypes.c_int32) for n in (
+                    "water_site", "energy_site", "biomass_site", "eat_water", "eat_biomass", "cap_water",
+                    "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
+                (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
+                                              "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
+                                              "b_repro")]
+
+
 class Desc(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
@@ -43,7 +54,7 @@ class Desc(ctypes.Structure):
         ("e_init", ctypes.c_int32), ("e_cost", ctypes.c_int32), ("e_eat", ctypes.c_int32),
         ("e_repro", ctypes.c_int32), ("e_child", ctypes.c_int32),
         ("wdtype", ctypes.c_uint32), ("keep_master", ctypes.c_uint32), ("attack_enabled", ctypes.c_uint32),
-        ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32), ("eco", Ecology), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -52,7 +63,8 @@ class Stats(ctypes.Structure):
         "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
         ("action_hist", ctypes.c_uint64 * 8),
-        ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double)]
+        ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double),
+        ("water_total", ctypes.c_uint64), ("biomass_total", ctypes.c_uint64), ("hp_total", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "action_hist"}
@@ -143,7 +155,11 @@ def _ptr(a):
 def make_desc(cfg: dict) -> Desc:
     d = Desc()
     for name, _ in Desc._fields_:
-        if name in cfg:
+        if name == "eco":
+            for en, _ in Ecology._fields_:
+                if en in cfg.get("eco", {}):
+                    setattr(d.eco, en, cfg["eco"][en])
+        elif name in cfg:
             setattr(d, name, cfg[name])
     d.struct_size = ctypes.sizeof(Desc)
     return d
@@ -281,7 +297,8 @@ class World:
 
     def read_state(self, world=0):
         c = self.cfgs[world]
-        return unpack_state(self.read_state_raw(world), c["capacity"], c["width"] * c["height"])
+        return unpack_state(self.read_state_raw(world), c["capacity"], c["width"] * c["height"],
+                            c.get("flags", 0) & DESC_ECOLOGY)
 
     def write_state(self, st, world=0):
         c = self.cfgs[world]
@@ -326,13 +343,17 @@ _FIELDS = [("uid", np.uint64, "cap"), ("parent_uid", np.uint64, "cap"), ("pos", 
            ("energy", np.int32, "cap"), ("age", np.int32, "cap"), ("occ", np.int32, "cells"),
            ("facing", np.uint8, "cap"), ("alive", np.uint8, "cap"), ("action", np.uint8, "cap"),
            ("res", np.uint8, "cells"), ("wall", np.uint8, "cells")]
+# appended with ECO_DESC_ECOLOGY
+_ECO_FIELDS = [("water", np.int32, "cap"), ("biomass", np.int32, "cap"), ("hp", np.int32, "cap"),
+               ("cell_water", np.int32, "cells"), ("cell_energy", np.int32, "cells"),
+               ("cell_biomass", np.int32, "cells")]
 
 
-def unpack_state(buf, cap, cells):
+def unpack_state(buf, cap, cells, ecology=False):
     buf = np.asarray(buf, dtype=np.uint8)
     st = {"step": int(buf[0:8].view(np.uint64)[0]), "uid_next": int(buf[8:16].view(np.uint64)[0])}
     off = 32
-    for name, dt, kind in _FIELDS:
+    for name, dt, kind in _FIELDS + (_ECO_FIELDS if ecology else []):
         n = cap if kind == "cap" else cells
         nb = n * np.dtype(dt).itemsize
         st[name] = buf[off:off + nb].view(dt).copy()
@@ -344,7 +365,7 @@ def pack_state(st, width, height, cap):
     cells = width * height
     parts = [np.array([st["step"], st["uid_next"]], dtype=np.uint64).view(np.uint8),
              np.array([width, height, cap, 0], dtype=np.uint32).view(np.uint8)]
-    for name, dt, kind in _FIELDS:
+    for name, dt, kind in _FIELDS + (_ECO_FIELDS if "hp" in st else []):
         n = cap if kind == "cap" else cells
         a = np.ascontiguousarray(st[name], dtype=dt)
         assert a.size == n, name

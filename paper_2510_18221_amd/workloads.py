@@ -26,6 +26,25 @@ def desc(**kw):
     return d
 
 
+# Three-resource ecology parameters (integer units: energy in 0.1 energy, health
+# in 0.1 HP).  The paper fixes the photosynthesis rate 0.01, the biomass site
+# density 1/4, health 10 HP at most and 5 HP at birth, and healing of 1 HP per
+# 0.1 energy; the other amounts are this build's choices.
+ECOLOGY = dict(water_density=0.1, energy_density=0.05, biomass_density=0.25, water_site=20, energy_site=20,
+               biomass_site=2, eat_water=10, eat_biomass=1, cap_water=200, cap_energy=400, cap_biomass=8,
+               e_cost_move=2, w_cost=1, photo_rate=0.01, cell_energy_max=40, hp_max=100, hp_child=50,
+               hp_overspend=20, hp_heal=10, heal_energy=1, age_shift=9, w_init=100, b_init=2, w_child=50, b_child=1,
+               b_repro=2)
+ECOLOGY_FLAG = 8
+
+
+def ecology_desc(eco=None, **kw):
+    """A world of the three-resource ecology: eight actions, 8 scalars."""
+    d = desc(n_actions=8, n_scalars=8, flags=ECOLOGY_FLAG, eco=dict(ECOLOGY, **(eco or {})))
+    d.update(kw)
+    return d
+
+
 def world_small(seed=0, wdtype=FP32):
     """64x64 torus, 256 agents, 5x5 window + 4 scalars (D = 104), 104->32->32->5, sigma 0.02."""
     return desc(seed=seed, wdtype=wdtype)
@@ -91,6 +110,11 @@ def biased_actions(cap, n_actions, seed, step, p_forward=0.3, p_eat=0.3, p_attac
     a = rng.integers(0, n_actions, size=cap, dtype=np.uint8)
     a[u < p_forward] = 3
     a[(u >= p_forward) & (u < p_forward + p_eat)] = 4
+    if n_actions == 8:   # the ecology: meals spread over energy, water, biomass; 15% reproduce
+        eat = (u >= p_forward) & (u < p_forward + p_eat)
+        a[eat] = 4 + (rng.integers(0, 3, size=cap)[eat]).astype(np.uint8)
+        p0 = p_forward + p_eat
+        a[(u >= p0) & (u < p0 + 0.15)] = 7
     if n_actions == 7:
         p0 = p_forward + p_eat
         a[(u >= p0) & (u < p0 + 0.2)] = 5

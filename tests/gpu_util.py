@@ -38,7 +38,8 @@ def assert_weights_close(gpu, ref, what, ulps=4):
 
 def assert_stats_match(g, o, what, check_trait=True):
     for k in ("step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
-              "births_blocked_cell", "births_blocked_capacity", "resource_total", "action_hist"):
+              "births_blocked_cell", "births_blocked_capacity", "resource_total", "action_hist", "water_total",
+              "biomass_total", "hp_total"):
         assert g[k] == o[k], (what, k, g[k], o[k])
     assert g["energy_total"] == o["energy_total"], (what, "energy_total")
     if check_trait:
