@@ -24,8 +24,9 @@ same world, the frozen-population form (exactly 65,536 agents every step), the
 same world with attacks enabled (the paper's "+A" worlds, with its predation
 measures: attacks per agent and homicides per attack), the same world with the
 paper's own policy options (evolving softmax temperature, colour trait rendered
-into the windows), a per-kernel breakdown from a few eager steps, and the CPU
-oracle on a bounded sample.
+into the windows), the same grid and population in the three-resource ecology
+with health, a per-kernel breakdown from a few eager steps, and the CPU oracle
+on a bounded sample.
 """
 import argparse
 import json
@@ -302,17 +303,23 @@ def main():
         attack_cfg = dict(wl.world_65k(seed=0), attack_enabled=1)
         # the paper's own agent: evolving softmax temperature and colour trait seen in others' windows
         paper_cfg = dict(wl.world_65k(seed=0), flags=eco.DESC_EVOLVE_TEMPERATURE | eco.DESC_COLOUR_VISION)
+        # the three-resource ecology with health on the same grid and population (496->64->64->8)
+        ecology_cfg = wl.ecology_desc(width=1024, height=1024, n_agents_init=65536, capacity=131072, window=11,
+                                      n_scalars=12, hidden1=64, hidden2=64, mutation_sigma=0.01, e_init=230, seed=0)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
                            ("fp32_attack", attack_cfg),
-                           ("fp32_temperature_colour", paper_cfg)]:
+                           ("fp32_temperature_colour", paper_cfg),
+                           ("fp32_ecology", ecology_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
                               "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
                               "launch": r["launch"]}
+            if vcfg.get("flags", 0) & eco.DESC_ECOLOGY:
+                variants[name]["births_deaths"] = [r["births"], r["deaths"]]
             if vcfg.get("attack_enabled"):
                 # the predation measures of the paper's Table 3 over the timed steps
                 variants[name]["attacks_per_agent"] = round(r["attacks"] / max(r["agent_steps"], 1), 4)
