@@ -32,6 +32,9 @@
  *     the cell), overspending and age damage health, energy heals it, death at
  *     zero health returns everything carried to the cell, reproduction needs
  *     spare biomass, energy grows on free-standing biomass (photosynthesis).
+ *   - Terrain (ORC_TERRAIN; Sec. 3.2 "Terrain"): a rock height per cell, water
+ *     first filling the cells below sea level, then flowing downhill every step
+ *     by a discrete rule; vision shows the local elevation difference.
  *   - Reproduction (Sec. 3.2 "Actions", Sec. 3.3): single parent with enough
  *     energy, child placed directly behind the parent, child receives a fixed
  *     amount of the parent's energy, child weights = parent weights + Gaussian
@@ -79,7 +82,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* Stream tags of the counter's third word. */
 enum { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
-       ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8 };
+       ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8, ST_TERRAIN = 9 };
 
 static uint32_t draw_x0(const uint32_t key[2], uint32_t a, uint32_t step, uint32_t stream, uint32_t blk) {
     uint32_t ctr[4] = {a, step, stream, blk}, out[4];
@@ -183,6 +186,8 @@ struct orc_world {
     int eco;                  /* ORC_ECOLOGY */
     int32_t *water, *biomass, *hp;      /* [cap] stomach water and biomass, health (ecology) */
     int32_t *cw, *ce, *cb;              /* [cells] water, energy, biomass on the grid (ecology) */
+    int32_t *rock;                      /* [cells] terrain heights 0..31 (ORC_TERRAIN) */
+    int8_t *flowdir;                    /* [cells] direction water leaves by, -1 = it stays (ORC_TERRAIN) */
     orc_stats stats;
 };
 
@@ -387,6 +392,55 @@ static void compute_stats_tail(orc_world* w) {
     }
 }
 
+/* Terrain (Sec. 3.2 "Terrain"; the paper's maps are figures, not a rule): a
+ * value-noise field.  Lattice values v(i, j) = Philox(i + j NX, 0, 9, 0).x0 >> 27
+ * (0..31) on an NX x NY torus lattice, NX = max(1, W / terrain_scale); a cell
+ * takes the bilinear blend of its four lattice corners, in exact integers with
+ * floor division, so heights stay in 0..31. */
+static int32_t terrain_height(const orc_world* w, uint32_t x, uint32_t y) {
+    const uint64_t W = w->W, H = w->H, L = (uint64_t)w->d.eco.terrain_scale;
+    const uint64_t NX = W / L > 0 ? W / L : 1, NY = H / L > 0 ? H / L : 1;
+    const uint64_t ax = (uint64_t)x * NX, ay = (uint64_t)y * NY;
+    const uint64_t i = ax / W, j = ay / H, fx = ax % W, fy = ay % H;
+    const uint64_t i1 = (i + 1) % NX, j1 = (j + 1) % NY;
+    uint64_t v[4];
+    const uint64_t corner[4][2] = {{i, j}, {i1, j}, {i, j1}, {i1, j1}};
+    for (int k = 0; k < 4; ++k)
+        v[k] = draw_x0(w->key, (uint32_t)(corner[k][0] + corner[k][1] * NX), 0, ST_TERRAIN, 0) >> 27;
+    const uint64_t num = v[0] * (W - fx) * (H - fy) + v[1] * fx * (H - fy) + v[2] * (W - fx) * fy + v[3] * fx * fy;
+    return (int32_t)(num / (W * H));
+}
+
+/* Flow directions: each cell's lowest 4-neighbour if strictly lower than the
+ * cell itself (the first of N, E, S, W among equals), else none (-1). */
+static uint32_t step_cell(const orc_world* w, uint32_t cell, int facing, int sign);
+static void set_flow(orc_world* w) {
+    for (uint32_t c = 0; c < w->cells; ++c) {
+        int best = -1;
+        int32_t bh = w->rock[c];
+        for (int dd = 0; dd < 4; ++dd) {
+            uint32_t n = step_cell(w, c, dd, +1);
+            if (w->rock[n] < bh) { bh = w->rock[n]; best = dd; }
+        }
+        w->flowdir[c] = (int8_t)best;
+    }
+}
+
+int orc_read_terrain(const orc_world* w, int32_t* rock) {
+    if (!(w->d.flags & ORC_TERRAIN)) return fail("the world has no terrain");
+    memcpy(rock, w->rock, (size_t)w->cells * 4);
+    return 0;
+}
+
+int orc_write_terrain(orc_world* w, const int32_t* rock) {
+    if (!(w->d.flags & ORC_TERRAIN)) return fail("the world has no terrain");
+    for (uint32_t c = 0; c < w->cells; ++c)
+        if (rock[c] < 0 || rock[c] > 31) return fail("heights must lie in 0..31");
+    memcpy(w->rock, rock, (size_t)w->cells * 4);
+    set_flow(w);
+    return 0;
+}
+
 static int validate(const orc_desc* d) {
     if (!d) return fail("null desc");
     if (d->width < 1 || d->height < 1) return fail("empty grid");
@@ -398,12 +452,16 @@ static int validate(const orc_desc* d) {
     if (d->n_actions != 5 && d->n_actions != 7 && d->n_actions != 8) return fail("n_actions must be 5, 7 or 8");
     if (d->attack_enabled > 1) return fail("attack_enabled must be 0 or 1");
     if (d->attack_enabled && d->n_actions != 7) return fail("attacks need the seven-action head");
-    if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY))
+    if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY | ORC_TERRAIN))
         return fail("unknown flags");
     if (d->flags & ORC_ECOLOGY) {
         const orc_ecology* e = &d->eco;
         if (d->n_actions != 8) return fail("the ecology has eight actions");
-        if (d->attack_enabled || (d->flags & ORC_COLOUR_VISION)) return fail("the ecology runs without attack and colour");
+        if (d->attack_enabled || (d->flags & ORC_EVOLVE_TEMPERATURE))
+            return fail("the ecology runs without attack and the evolving temperature");
+        if ((d->flags & ORC_TERRAIN) && (e->terrain_scale < 1 || e->sea_level < 0 || e->sea_level > 32 ||
+                                         e->water_per_depth < 0))
+            return fail("bad terrain parameters");
         if (d->n_scalars != 8 && d->n_scalars != 12) return fail("the ecology has 8 or 12 scalars");
         if (e->hp_max <= 0 || e->hp_child <= 0 || e->hp_child > e->hp_max) return fail("bad health limits");
         if (e->age_shift < 0 || e->age_shift > 31) return fail("age_shift outside [0, 31]");
@@ -420,6 +478,7 @@ static int validate(const orc_desc* d) {
     } else if (d->n_actions == 8) {
         return fail("eight actions need the ecology");
     }
+    if ((d->flags & ORC_TERRAIN) && !(d->flags & ORC_ECOLOGY)) return fail("terrain needs the ecology");
     if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
     if (d->capacity < d->n_agents_init) return fail("capacity below the initial population");
     if ((uint64_t)d->n_agents_init > (uint64_t)d->width * d->height) return fail("more agents than cells");
@@ -445,6 +504,7 @@ void orc_destroy(orc_world* w) {
     free(w->uid); free(w->puid); free(w->occ); free(w->res); free(w->wall);
     free(w->master); free(w->stored); free(w->node); free(w->nodes); free(w->trait); free(w->colour);
     free(w->water); free(w->biomass); free(w->hp); free(w->cw); free(w->ce); free(w->cb);
+    free(w->rock); free(w->flowdir);
     free(w);
 }
 
@@ -474,13 +534,14 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
     w->water = (int32_t*)calloc(cap ? cap : 1, 4);   w->biomass = (int32_t*)calloc(cap ? cap : 1, 4);
     w->hp = (int32_t*)calloc(cap ? cap : 1, 4);
     w->cw = (int32_t*)calloc(w->cells, 4); w->ce = (int32_t*)calloc(w->cells, 4); w->cb = (int32_t*)calloc(w->cells, 4);
+    w->rock = (int32_t*)calloc(w->cells, 4); w->flowdir = (int8_t*)calloc(w->cells, 1);
     if (materialize) {
         w->master = (float*)calloc((size_t)cap * w->P + 1, sizeof(float));
         if (d->wdtype != ORC_FP32) w->stored = (double*)calloc((size_t)cap * w->P + 1, sizeof(double));
     }
     if (!w->pos || !w->energy || !w->age || !w->facing || !w->alive || !w->action || !w->uid ||
         !w->puid || !w->node || !w->trait || !w->occ || !w->res || !w->wall || !w->colour || !w->water ||
-        !w->biomass || !w->hp || !w->cw || !w->ce || !w->cb ||
+        !w->biomass || !w->hp || !w->cw || !w->ce || !w->cb || !w->rock || !w->flowdir ||
         (materialize && (!w->master || (d->wdtype != ORC_FP32 && !w->stored)))) {
         orc_destroy(w);
         fail("out of memory");
@@ -508,6 +569,12 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
             w->cw[c] = ((uint64_t)x[1] < tw) ? d->eco.water_site : 0;
             w->ce[c] = ((uint64_t)x[2] < te) ? d->eco.energy_site : 0;
             w->cb[c] = ((uint64_t)x[3] < tb) ? d->eco.biomass_site : 0;
+        }
+        if (d->flags & ORC_TERRAIN) {   /* rock from the noise field; the sea instead of water sites */
+            for (uint32_t c = 0; c < w->cells; ++c) w->rock[c] = terrain_height(w, c % w->W, c / w->W);
+            for (uint32_t c = 0; c < w->cells; ++c)
+                w->cw[c] = (w->rock[c] < d->eco.sea_level) ? (d->eco.sea_level - w->rock[c]) * d->eco.water_per_depth : 0;
+            set_flow(w);
         }
     }
     for (uint32_t j = 0; j < d->n_agents_init; ++j) {
@@ -553,18 +620,31 @@ orc_world* orc_create(const orc_desc* d, int materialize) {
  * occupant's colour; an empty cell holding a resource unit in green, a wall in
  * grey, anything else black; each channel as its 8-bit value times 2^-8.  The
  * torus is flat, so the elevation-difference channel is zero. */
-static void render_cell(const orc_world* w, uint32_t cell, double* v) {
+static uint32_t sat255(int64_t v) { return v < 0 ? 0u : (v > 255 ? 255u : (uint32_t)v); }
+
+static void render_cell(const orc_world* w, uint32_t cell, uint32_t own, double* v) {
     uint32_t q[3] = {0u, 0u, 0u};
     int32_t o = w->occ[cell];
     if (o >= 0) {
         for (int k = 0; k < 3; ++k) q[k] = orc_colour_byte(w->colour[3 * (uint64_t)o + k]);
+    } else if (w->eco) {
+        /* the ecology's cells: wall grey, else energy in red, biomass in green,
+         * water in blue, each saturating at 255 */
+        if (w->wall[cell]) {
+            q[0] = q[1] = q[2] = 128u;
+        } else {
+            q[0] = sat255((int64_t)w->ce[cell] * 16);
+            q[1] = sat255((int64_t)w->cb[cell] * 64);
+            q[2] = sat255((int64_t)w->cw[cell] * 16);
+        }
     } else if (w->res[cell]) {
         q[1] = 255u;
     } else if (w->wall[cell]) {
         q[0] = q[1] = q[2] = 128u;
     }
     for (int k = 0; k < 3; ++k) v[k] = ldexp((double)q[k], -8);
-    v[3] = 0.0;
+    /* the local difference in elevation: zero on the flat torus */
+    v[3] = (w->d.flags & ORC_TERRAIN) ? ldexp((double)(w->rock[cell] - w->rock[own]), -3) : 0.0;
 }
 
 int orc_observe(const orc_world* w, uint32_t slot, double* x) {
@@ -583,7 +663,7 @@ int orc_observe(const orc_world* w, uint32_t slot, double* x) {
             uint32_t cell = wrap_cell(w, ax + fwd * dx + right * rx, ay + fwd * dy + right * ry);
             int32_t o = w->occ[cell];
             double* v = x + 4 * (r * S + c);
-            if (w->d.flags & ORC_COLOUR_VISION) { render_cell(w, cell, v); continue; }
+            if (w->d.flags & ORC_COLOUR_VISION) { render_cell(w, cell, (uint32_t)w->pos[slot], v); continue; }
             if (w->eco) {   /* agent present, then water, energy, biomass levels (capped at 255) / 16 */
                 v[0] = (o >= 0) ? 1.0 : 0.0;
                 v[1] = ldexp((double)(w->cw[cell] < 255 ? w->cw[cell] : 255), -4);
@@ -996,6 +1076,17 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
             double p = (double)w->d.eco.photo_rate * (double)w->cb[c];
             uint64_t thr = p >= 1.0 ? (1ull << 32) : (uint64_t)floor(p * 4294967296.0);
             if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->ce[c] += 1; st->regrown++; }
+        }
+        /* 7b. Terrain: all water on a cell with a flow direction moves one cell
+         *     downhill, every cell at once (water is conserved). */
+        if (w->d.flags & ORC_TERRAIN) {
+            int32_t* nw = (int32_t*)calloc(w->cells ? w->cells : 1, 4);
+            for (uint32_t c = 0; c < w->cells; ++c) {
+                if (w->flowdir[c] < 0) nw[c] += w->cw[c];
+                else nw[step_cell(w, c, w->flowdir[c], +1)] += w->cw[c];
+            }
+            memcpy(w->cw, nw, (size_t)w->cells * 4);
+            free(nw);
         }
     }
 

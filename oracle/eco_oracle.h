@@ -39,7 +39,15 @@ enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 
  *     like its weights, and the window shows the rendered colour of each cell
  *     plus an elevation-difference channel (zero on the flat torus) (Sec. 3.2
  *     "Sensors", Sec. 3.3). */
-enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4, ORC_ECOLOGY = 8 };
+enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4, ORC_ECOLOGY = 8, ORC_TERRAIN = 16 };
+
+/* ORC_TERRAIN (with ORC_ECOLOGY): a rock layer of heights 0..31 (Sec. 3.2
+ * "Terrain"), from a seeded value-noise field (lattice spacing terrain_scale,
+ * bilinear in exact integers) or written by the caller; water starts on the
+ * cells below sea_level, (sea_level - rock) * water_per_depth units each, and
+ * every step all water on a cell moves to its lowest 4-neighbour when that one
+ * lies strictly lower (ties: N, E, S, W), all cells at once.  With colour vision
+ * the window's fourth channel is the elevation difference to the agent's cell. */
 
 /* ORC_ECOLOGY: the paper's three-resource ecology with health (Sec. 3.2
  * "Resources" and health points; App. "Varying Resource Rules", "Varying Agent
@@ -63,6 +71,7 @@ typedef struct {
     int32_t  age_shift;                                        /* age damage per step = age >> age_shift */
     int32_t  w_init, b_init;                                   /* initial agents' water and biomass */
     int32_t  w_child, b_child, b_repro;                        /* given to a child; biomass needed to reproduce */
+    int32_t  terrain_scale, sea_level, water_per_depth;        /* ORC_TERRAIN */
 } orc_ecology;
 
 /* One world's parameters.  Energies are integers in units of 0.1 energy. */
@@ -78,7 +87,7 @@ typedef struct {
     int32_t  e_init, e_cost, e_eat, e_repro, e_child;
     uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
     uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 */
-    uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY */
+    uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY | ORC_TERRAIN */
     orc_ecology eco;                   /* used with ORC_ECOLOGY */
     uint64_t seed;
 } orc_desc;
@@ -148,6 +157,11 @@ int    orc_read_state(const orc_world* w, void* buf, size_t bytes);
 int    orc_write_state(orc_world* w, const void* buf, size_t bytes);
 
 int orc_stats_get(const orc_world* w, orc_stats* out);
+
+/* The rock layer (ORC_TERRAIN): read, or overwrite (heights 0..31; the flow
+ * directions follow; the water stays where it is). */
+int orc_read_terrain(const orc_world* w, int32_t* rock /* [cells] */);
+int orc_write_terrain(orc_world* w, const int32_t* rock);
 
 /* Colour trait of live slot `slot` (FP32 R, G, B), and its overwrite. */
 int orc_read_colour(const orc_world* w, uint32_t slot, float out[3]);

@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 FP32, BF16, FP8 = 0, 1, 2
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
-FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION, ECOLOGY = 1, 2, 4, 8   # orc_desc.flags
+FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION, ECOLOGY, TERRAIN = 1, 2, 4, 8, 16   # orc_desc.flags
 EAT_ENERGY, EAT_WATER, EAT_BIOMASS, REPRODUCE_ECO = 4, 5, 6, 7             # the ecology's action set
 
 
@@ -25,7 +25,7 @@ class OrcEcology(ctypes.Structure):
                     "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
                 (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
                                               "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
-                                              "b_repro")]
+                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth")]
 
 
 class OrcDesc(ctypes.Structure):
@@ -100,6 +100,8 @@ def lib():
         _lib.orc_colour_byte.restype = ctypes.c_uint32
         _lib.orc_colour_byte.argtypes = [ctypes.c_float]
         _lib.orc_read_colour.argtypes = [P, ctypes.c_uint32, P]
+        _lib.orc_read_terrain.argtypes = [P, P]
+        _lib.orc_write_terrain.argtypes = [P, P]
         _lib.orc_write_colour.argtypes = [P, ctypes.c_uint32, P]
     return _lib
 
@@ -223,6 +225,16 @@ class OracleWorld:
     def write_colour(self, slot, rgb):
         v = np.ascontiguousarray(rgb, dtype=np.float32)
         self._check(lib().orc_write_colour(self._h, slot, _ptr(v)))
+
+    def terrain(self):
+        out = np.empty(self.W * self.H, dtype=np.int32)
+        self._check(lib().orc_read_terrain(self._h, _ptr(out)))
+        return out
+
+    def write_terrain(self, rock):
+        v = np.ascontiguousarray(rock, dtype=np.int32)
+        assert v.size == self.W * self.H
+        self._check(lib().orc_write_terrain(self._h, _ptr(v)))
 
     def observe(self, slot):
         out = np.empty(self.D, dtype=np.float64)

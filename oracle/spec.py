@@ -27,7 +27,11 @@ worlds and to run the hand-traced cases.  Rules (paper sections):
   actions, energy and water spent every step (the water back onto the cell),
   damage from overspending and age, healing bought with energy, death at zero
   health returning everything carried, reproduction needing spare biomass,
-  energy appearing on biomass (photosynthesis).
+  energy appearing on biomass (photosynthesis);
+  16 = terrain (with 8; Sec. 3.2 "Terrain"): rock heights 0..31 from a seeded
+  value-noise field, the sea filling the cells below sea level, all water of a
+  cell moving each step to its lowest strictly lower neighbour, and the
+  elevation difference in the colour window's fourth channel.
 * Sec. 3.3: per-agent MLP with two ReLU hidden layers and a linear head;
   softmax sampling; zero-mean Gaussian initial weights with zero biases;
   children copy the parent's weights plus Gaussian noise.
@@ -40,7 +44,7 @@ from fractions import Fraction
 
 M32 = 0xFFFFFFFF
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
-FRONT, TEMPERATURE, COLOUR, ECOLOGY = 1, 2, 4, 8
+FRONT, TEMPERATURE, COLOUR, ECOLOGY, TERRAIN = 1, 2, 4, 8, 16
 EAT_E, EAT_W, EAT_B, REPRO8 = 4, 5, 6, 7
 HEADINGS = [(0, -1), (1, 0), (0, 1), (-1, 0)]  # N, E, S, W with y pointing down
 
@@ -114,6 +118,9 @@ class SpecWorld:
                 self.cw[i] = e["water_site"] if x[1] < tw else 0
                 self.ce[i] = e["energy_site"] if x[2] < te else 0
                 self.cb[i] = e["biomass_site"] if x[3] < tb else 0
+            if self.flags & TERRAIN:
+                self.rock = [self._height(i % self.W, i // self.W) for i in range(cells)]
+                self.cw = [(e["sea_level"] - r) * e["water_per_depth"] if r < e["sea_level"] else 0 for r in self.rock]
         order = sorted(range(cells), key=lambda i: (philox4x32_10([i, 0, 0, 0], self.key)[0], i))
         self.agents = {}  # slot -> dict
         for j in range(c["n_agents_init"]):
@@ -143,6 +150,27 @@ class SpecWorld:
             theta.append(0.0)     # log temperature 0: temperature 1
         return theta
 
+    def _height(self, x, y):
+        """Bilinear blend of the four surrounding lattice values (0..31) of a
+        seeded torus lattice, spacing terrain_scale, in exact integers."""
+        L = self.eco["terrain_scale"]
+        nx, ny = max(1, self.W // L), max(1, self.H // L)
+        i, fx = divmod(x * nx, self.W)
+        j, fy = divmod(y * ny, self.H)
+        v = lambda a, b: philox4x32_10([a % nx + (b % ny) * nx, 0, 9, 0], self.key)[0] >> 27
+        num = (v(i, j) * (self.W - fx) * (self.H - fy) + v(i + 1, j) * fx * (self.H - fy)
+               + v(i, j + 1) * (self.W - fx) * fy + v(i + 1, j + 1) * fx * fy)
+        return num // (self.W * self.H)
+
+    def _flow_target(self, i):
+        x, y = self._xy(i)
+        best, bh = None, self.rock[i]
+        for fx, fy in HEADINGS:
+            n = self._cell(x + fx, y + fy)
+            if self.rock[n] < bh:
+                best, bh = n, self.rock[n]
+        return best
+
     def _init_colour(self, j):
         x = philox4x32_10([j, 0, 7, 0], self.key)
         return [(x[k] >> 8) / 16777216.0 for k in range(3)]
@@ -153,17 +181,26 @@ class SpecWorld:
         q = Fraction(c) * 255 + Fraction(1, 2)
         return q.numerator // q.denominator
 
-    def _render(self, cell):
+    def _render(self, cell, own=None):
         o = self.occ[cell]
+        elev = 0.0
+        if self.flags & TERRAIN:
+            elev = (self.rock[cell] - self.rock[own]) / 8.0
         if o >= 0:
             q = [self.colour_byte(v) for v in self.agents[o]["colour"]]
+        elif self.eco is not None:
+            if self.wall[cell]:
+                q = [128, 128, 128]
+            else:
+                q = [min(self.ce[cell] * 16, 255), min(self.cb[cell] * 64, 255), min(self.cw[cell] * 16, 255)]
+            return [v / 256.0 for v in q] + [elev]
         elif self.res[cell]:
             q = [0, 255, 0]
         elif self.wall[cell]:
             q = [128, 128, 128]
         else:
             q = [0, 0, 0]
-        return [v / 256.0 for v in q] + [0.0]
+        return [v / 256.0 for v in q] + [elev]
 
     def _xy(self, cell):
         return cell % self.W, cell // self.W
@@ -184,7 +221,7 @@ class SpecWorld:
                 ahead, right = top - r, col - R
                 cell = self._cell(ax + ahead * fx + right * rx, ay + ahead * fy + right * ry)
                 if self.flags & COLOUR:
-                    obs += self._render(cell)
+                    obs += self._render(cell, ag["cell"])
                     continue
                 o = self.occ[cell]
                 if self.eco is not None:
@@ -382,6 +419,12 @@ class SpecWorld:
             elif self.res[i] == 0 and philox4x32_10([i, n, 6, 0], self.key)[0] < thr:
                 self.res[i] = 1
                 st["regrown"] += 1
+        if self.flags & TERRAIN:   # all water one cell downhill, every cell at once
+            nw = [0] * (self.W * self.H)
+            for i, wv in enumerate(self.cw):
+                t = self._flow_target(i)
+                nw[i if t is None else t] += wv
+            self.cw = nw
         self.step_no += 1
         st["population"] = len(self.agents)
         st["resource_total"] = sum(self.res)

@@ -845,9 +845,13 @@ def test_ecology_observation_matches_numpy():
         w.step()
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_ecology_oracle_matches_spec(seed):
-    cfg = _eco_run_cfg(seed)
+@pytest.mark.parametrize("seed,flags", [(0, orc.ECOLOGY), (1, orc.ECOLOGY),
+                                        (2, orc.ECOLOGY | orc.TERRAIN),
+                                        (3, orc.ECOLOGY | orc.TERRAIN | orc.COLOUR_VISION),
+                                        (4, orc.ECOLOGY | orc.COLOUR_VISION | orc.FRONT_VISION)])
+def test_ecology_oracle_matches_spec(seed, flags):
+    cfg = _eco_run_cfg(seed, flags=flags)
+    cfg["eco"].update(terrain_scale=4, sea_level=10, water_per_depth=3)
     o, sp = orc.OracleWorld(cfg), spec.SpecWorld(cfg)
     assert_same_state(o.state(), sp.state(), "init")
     tot = dict(births=0, deaths=0, eaten=0, regrown=0)
@@ -866,6 +870,92 @@ def test_ecology_oracle_matches_spec(seed):
         for k in tot:
             tot[k] += sst[k]
     assert all(v > 0 for v in tot.values()), tot
+
+
+# ---------------------------------------------------------------------------
+# Terrain: rock heights, the sea, downhill water flow, the elevation channel
+# ---------------------------------------------------------------------------
+def _terrain_cfg(width=40, height=30, flags=orc.ECOLOGY | orc.TERRAIN, **eco):
+    e = dict(ECO_HAND, terrain_scale=8, sea_level=12, water_per_depth=3)
+    e.update(eco)
+    return wl.desc(width=width, height=height, n_agents_init=20, capacity=40, window=5, n_scalars=8, n_actions=8,
+                   flags=flags, eco=e, seed=17, e_eat=10, e_cost=1, e_repro=200, e_child=50, e_init=150)
+
+
+def test_terrain_generator_properties():
+    """Heights in 0..31; the bilinear field changes by at most ceil(31 / scale) per
+    cell, also across the torus seam; one lattice cell per axis gives a flat map;
+    water starts exactly on the cells below sea level, (sea - rock) * k units."""
+    for W, H, L in ((40, 30, 8), (64, 64, 16), (33, 17, 5)):
+        o = orc.OracleWorld(_terrain_cfg(W, H, terrain_scale=L), materialize=False)
+        r = o.terrain().reshape(H, W).astype(np.int64)
+        assert r.min() >= 0 and r.max() <= 31 and r.max() > r.min()
+        nx, ny = max(1, W // L), max(1, H // L)
+        bx, by = math.ceil(31 * nx / W), math.ceil(31 * ny / H)
+        assert np.abs(np.diff(r, axis=1, append=r[:, :1])).max() <= bx
+        assert np.abs(np.diff(r, axis=0, append=r[:1, :])).max() <= by
+        st = o.state()
+        cw = st["cell_water"].reshape(H, W)
+        np.testing.assert_array_equal(cw, np.where(r < 12, (12 - r) * 3, 0))
+    flat = orc.OracleWorld(_terrain_cfg(20, 10, terrain_scale=64), materialize=False).terrain()
+    assert len(set(flat.tolist())) == 1
+
+
+def test_T12_water_flows_downhill_hand_traced():
+    """A written 6x6 rock layer: a valley at (2,2); water one cell downhill per step."""
+    cfg = _terrain_cfg(6, 6, terrain_scale=6, sea_level=0)
+    o, sp = orc.OracleWorld(cfg), None
+    rock = np.full((6, 6), 10, np.int32)
+    rock[2, 2] = 5          # the valley
+    rock[2, 3] = 7          # east of it: flows west into the valley
+    rock[3, 2] = 5          # south of the valley, as low: the valley keeps its water (not strictly lower)
+    rock[0, 4] = 9; rock[1, 5] = 9   # (4,1) has two equal lowest neighbours: N (4,0) wins over E (5,1)
+    o.write_terrain(rock.reshape(-1))
+    st = empty_state(6, 6, 40, ecology=True)
+    eco_place(st, 0, 0, 5, N, 100, 30, 2, 100)          # rests on flat ground: spends 3 water there
+    cw = np.zeros((6, 6), np.int32)
+    cw[2, 3] = 12; cw[2, 2] = 4; cw[1, 2] = 5; cw[1, 4] = 7; cw[4, 4] = 2
+    st["cell_water"] = cw.reshape(-1)
+    o.write_state(st)
+    o.step(actions=np.zeros(40, np.uint8))
+    out = o.state()["cell_water"].reshape(6, 6)
+    exp = np.zeros((6, 6), np.int32)
+    exp[2, 2] = 4 + 12 + 5  # its own, the east neighbour's, and (2,1)'s (rock 10 > 5, lowest neighbour south)
+    exp[0, 4] = 7           # from (4,1): N and E both 9, N first
+    exp[4, 4] = 2           # flat ground: stays
+    exp[5, 0] = 3           # the agent's spent water, on flat ground
+    np.testing.assert_array_equal(out, exp)
+    assert o.stats()["water_total"] == 30 - 3 + exp.sum()
+    with pytest.raises(RuntimeError):
+        o.write_terrain(np.full(36, 32, np.int32))
+
+
+def test_terrain_conservation_and_colour_window():
+    """Water conserved while it flows; the colour window's channels against numpy:
+    occupants in their colour, walls grey, energy / biomass / water in R / G / B
+    (x16, x64, x16, saturating), elevation difference / 8."""
+    cfg = _terrain_cfg(40, 30, flags=orc.ECOLOGY | orc.TERRAIN | orc.COLOUR_VISION, w_cost=2, w_init=40, w_child=8)
+    cfg.update(n_agents_init=150, capacity=240, energy_density=0.1, biomass_density=0.25, energy_site=20, biomass_site=3)
+    cfg["eco"].update(energy_density=0.1, biomass_density=0.25, energy_site=20, biomass_site=3, photo_rate=0.01)
+    w = orc.OracleWorld(cfg)
+    s0 = w.stats()
+    for t in range(6):
+        st = w.state()
+        rock = w.terrain().reshape(30, 40).astype(float)
+        occ = st["occ"].reshape(30, 40)
+        rgb = np.stack([np.minimum(st["cell_energy"] * 16, 255), np.minimum(st["cell_biomass"] * 64, 255),
+                        np.minimum(st["cell_water"] * 16, 255)], -1).reshape(30, 40, 3).astype(float)
+        rgb[(st["wall"].reshape(30, 40) > 0)] = 128
+        for yy, xx in zip(*np.nonzero(occ >= 0)):
+            rgb[yy, xx] = np.floor(np.clip(w.colour(int(occ[yy, xx])).astype(np.float64), 0, 1) * 255 + 0.5)
+        for s in np.nonzero(st["alive"])[0][:25]:
+            x, y, f = st["pos"][s] % 40, st["pos"][s] // 40, int(st["facing"][s])
+            rows, cols = np.arange(y - 2, y + 3) % 30, np.arange(x - 2, x + 3) % 40
+            chans = [np.rot90(rgb[..., k][np.ix_(rows, cols)], k=f) / 256 for k in range(3)]
+            chans.append(np.rot90((rock - rock[y, x])[np.ix_(rows, cols)], k=f) / 8)
+            np.testing.assert_array_equal(w.observe(int(s))[:100], np.stack(chans, -1).reshape(-1))
+        w.step(actions=wl.biased_actions(240, 8, 7, t, p_forward=0.4, p_eat=0.3))
+        assert w.stats()["water_total"] == s0["water_total"]
 
 
 # ---------------------------------------------------------------------------
@@ -1014,7 +1104,8 @@ def test_invalid_descs_rejected():
                 dict(e_repro=0), dict(wdtype=7), dict(window=99), dict(attack_enabled=1),
                 dict(n_actions=7, attack_enabled=2), dict(flags=16), dict(n_actions=8),
                 dict(flags=orc.ECOLOGY, n_actions=7), dict(flags=orc.ECOLOGY, n_actions=8, n_scalars=4),
-                dict(flags=orc.ECOLOGY | orc.COLOUR_VISION, n_actions=8, n_scalars=8),
+                dict(flags=orc.ECOLOGY | orc.EVOLVE_TEMPERATURE, n_actions=8, n_scalars=8),
+                dict(flags=orc.TERRAIN, n_actions=5),
                 dict(flags=orc.ECOLOGY, n_actions=8, n_scalars=8, attack_enabled=1)]:
         with pytest.raises(ValueError):
             orc.OracleWorld(wl.desc(**bad))
