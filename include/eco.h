@@ -89,8 +89,8 @@ typedef struct {
  * HP"), with the parameters of eco_world_desc.eco.  Cells hold water, energy and
  * biomass; agents carry the three in a capped stomach and have health.  Eight
  * actions: rest, turn left, turn right, forward, eat energy, eat water, eat
- * biomass, reproduce (n_actions = 8; no attack, colour vision or evolving
- * temperature with it).  Per live agent after the moves: the chosen resource
+ * biomass, reproduce (n_actions = 8; no attack or evolving temperature with
+ * it).  Per live agent after the moves: the chosen resource
  * moves from its cell to its stomach (up to the eat amount, the cell's content and
  * the room under the cap); energy is spent (e_cost at rest, e_cost_move
  * otherwise; clamped at 0) and destroyed; w_cost water is spent onto the cell;
@@ -105,8 +105,23 @@ typedef struct {
  * and the cell's water, energy and biomass, each min(units, 255) * 2^-4; the
  * scalars (n_scalars 8, or 12 with the compass) are energy * 2^-8,
  * min(age, 1024) * 2^-10, water * 2^-8, biomass * 2^-3, health * 2^-7 and the own
- * cell's three channels.  Water and biomass are conserved. */
+ * cell's three channels.  Water and biomass are conserved.  With
+ * ECO_DESC_COLOUR_VISION the window shows each cell as others see it instead:
+ * the occupant's colour, else grey for a wall, else energy, biomass and water as
+ * red, green, blue (min(16 e, 255), min(64 b, 255), min(16 w, 255)), each * 2^-8,
+ * and the elevation difference (zero without terrain). */
 #define ECO_DESC_ECOLOGY 8u
+/* ECO_DESC_TERRAIN (with ECO_DESC_ECOLOGY; Sec. 3.2 "Terrain"): a rock height
+ * 0..31 per cell, from a seeded value-noise field (lattice values
+ * Philox(i + j*NX, 0, 9, 0).x0 >> 27 on an NX x NY torus lattice with
+ * NX = max(1, width / terrain_scale), bilinear in exact integers with floor
+ * division) or written with eco_world_write_terrain.  Water starts on the cells
+ * below sea_level, (sea_level - rock) * water_per_depth units each (instead of
+ * water sites), and at the end of every step all water on a cell moves to its
+ * lowest 4-neighbour when that one lies strictly lower (the first of N, E, S, W
+ * among equals), every cell at once.  With colour vision the window's fourth
+ * channel is (rock(cell) - rock(agent's cell)) * 2^-3. */
+#define ECO_DESC_TERRAIN 16u
 
 /* Parameters of ECO_DESC_ECOLOGY (integer units; energy in 0.1 energy as the
  * e_* fields, health in 0.1 HP).  Initial cells: a water / energy / biomass site
@@ -122,6 +137,7 @@ typedef struct {
     int32_t cell_energy_max;
     int32_t hp_max, hp_child, hp_overspend, hp_heal, heal_energy, age_shift;
     int32_t w_init, b_init, w_child, b_child, b_repro;
+    int32_t terrain_scale, sea_level, water_per_depth;   /* ECO_DESC_TERRAIN */
 } eco_ecology;
 
 /* One world (POD, copied at create).  Grid is a torus of width x height. */
@@ -291,6 +307,12 @@ eco_status eco_world_write_state(eco_world* w, uint32_t world, const void* buf, 
 eco_status eco_world_read_logits(eco_world* w, uint32_t world, float* out, size_t n_floats);
 /* The policy's sampled action of the last step per slot (255 if not live). */
 eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, size_t n);
+
+/* The rock layer of one world (ECO_DESC_TERRAIN objects only, else EINVAL):
+ * rock[width * height] heights 0..31.  Writing it recomputes the flow
+ * directions and the window grid; the water stays where it is. */
+eco_status eco_world_read_terrain(eco_world* w, uint32_t world, int32_t* rock, size_t n);
+eco_status eco_world_write_terrain(eco_world* w, uint32_t world, const int32_t* rock, size_t n);
 
 /* Colour traits of one world (ECO_DESC_COLOUR_VISION objects only, else EINVAL):
  * out[cap][3] FP32 R, G, B; NaN for slots not alive.  n_floats >= 3 * capacity. */

@@ -28,7 +28,7 @@ enum Action : uint8_t { REST = 0, TURN_L = 1, TURN_R = 2, FORWARD = 3, EAT = 4, 
 enum EcologyAction : uint8_t { EAT_WATER = 5, EAT_BIOMASS = 6, REPRODUCE_ECO = 7 };
 // Philox stream tags (third counter word).
 enum Stream : uint32_t { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
-                         ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8 };
+                         ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8, ST_TERRAIN = 9 };
 
 // Immutable per-world parameters (device table, one entry per world).
 struct WorldParams {
@@ -107,10 +107,13 @@ struct Dev {
   uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
   uint32_t* rgb;                // [total_cells] window words, colour vision: R | G << 8 | B << 16, ecology:
                                 // water | energy << 8 | biomass << 16 (levels capped at 255); both with the
-                                // agent / resource / wall bits << 24
+                                // agent / resource / wall bits << 24 and, with terrain, the rock height << 27
   const eco_ecology* ep;        // [n_worlds] ecology parameters (null without the ecology)
   int32_t *water, *biomass, *hp;        // [total_slots] ecology: stomach water and biomass, health
   int32_t *cw, *ce, *cb;                // [total_cells] ecology: water, energy, biomass on the grid
+  int32_t* rock;                        // [total_cells] terrain: heights 0..31 (null without terrain)
+  int8_t* flowdir;                      // [total_cells] terrain: direction the water leaves by, -1 = stays
+  int32_t* cw_next;                     // [total_cells] terrain: the water after this step's flow
   float4* colour;               // [total_slots] colour vision only: the colour trait (x, y, z = R, G, B)
   uint8_t* store;               // [total_slots][sstride]
   uint8_t* master;              // [total_slots][mstride] or == store for FP32

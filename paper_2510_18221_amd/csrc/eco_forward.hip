@@ -321,7 +321,7 @@ __device__ __forceinline__ AgentCtx load_agent(const Dev& d, const uint32_t* wof
 }
 
 constexpr int kMaxWindowCellsPerLane = 4;  // S <= 15: S*S <= 256 cells over 64 lanes
-constexpr int kEcoLane = 61;               // lanes 61..63 of the last window slot: cells 253..255, never in a window
+constexpr int kEcoLane = 58;               // lanes 58..63 of the last window slot: cells 250..255, never in a window
 
 // Sense bytes (or, with colour vision, rendered words) of agent c's window (Sec.
 // 3.2 sensors, App. F layout): lane owns window cells lane + 64k, row r = i / S
@@ -353,10 +353,12 @@ __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, cons
       if constexpr (WORDS) sv[k] = d.rgb[cell];
       else sv[k] = d.sense[cell];
     } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
-      // ecology: the agent's water, biomass and health ride in window slots no
-      // window reaches (S*S <= 225 < 253), fetched with the window
-      const int32_t* src = lane == kEcoLane ? d.water : (lane == kEcoLane + 1 ? d.biomass : d.hp);
-      sv[k] = (uint32_t)src[c.slot];
+      // ecology: the own cell's water, energy, biomass and the agent's water,
+      // biomass, health ride in window slots no window reaches (S*S <= 225 < 250),
+      // fetched with the window
+      const int j = lane - kEcoLane;
+      const int32_t* src = j == 0 ? d.cw : j == 1 ? d.ce : j == 2 ? d.cb : j == 3 ? d.water : j == 4 ? d.biomass : d.hp;
+      sv[k] = (uint32_t)src[j < 3 ? wp.cell_off + (uint32_t)c.pos : c.slot];
     }
   }
 }
@@ -378,6 +380,9 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
                                                   const uint32_t (&sv)[kMaxWindowCellsPerLane], float* xs) {
   const int SS = (int)(L.S * L.S);
   const int centre = (int)(L.ahead0 * L.S + L.R);  // the agent's own cell
+  // colour words carry the cell's sense bits and rock height in their top byte
+  const uint32_t here = (WORDS && L.colour) ? window_word(sv, centre) : 0u;
+  const int own_rock = (int)(here >> 27);
 #pragma unroll
   for (int k = 0; k < kMaxWindowCellsPerLane; ++k) {
     const int i = lane + 64 * k;
@@ -386,27 +391,23 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
       float4 o;
       if constexpr (!WORDS) {
         o = make_float4((float)(v & 1u), (float)((v >> 1) & 1u), (float)((v >> 2) & 1u), (float)(v >> 3));
-      } else if (L.colour) {
+      } else if (L.colour) {   // rendered colour; the elevation difference from the rock bits (0 without terrain)
         o = make_float4(ldexpf((float)(v & 0xFFu), -8), ldexpf((float)((v >> 8) & 0xFFu), -8),
-                        ldexpf((float)((v >> 16) & 0xFFu), -8), 0.0f);
+                        ldexpf((float)((v >> 16) & 0xFFu), -8), ldexpf((float)((int)(v >> 27) - own_rock), -3));
       } else {   // ecology: agent present, then the water, energy, biomass levels
         o = make_float4((float)((v >> 24) & 1u), ldexpf((float)(v & 0xFFu), -4), ldexpf((float)((v >> 8) & 0xFFu), -4),
                         ldexpf((float)((v >> 16) & 0xFFu), -4));
       }
       reinterpret_cast<float4*>(xs)[i] = o;
-      if (WORDS && L.ecology && i == centre) {   // external sensor: the own cell's water, energy, biomass levels
-        xs[4 * SS + 5] = o.y;
-        xs[4 * SS + 6] = o.z;
-        xs[4 * SS + 7] = o.w;
-      }
     } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
-      // the agent's water, biomass, health (fetched into this unused window slot)
-      const int j = lane - kEcoLane;
-      xs[4 * SS + 2 + j] = ldexpf((float)(int)sv[k], j == 0 ? -8 : (j == 1 ? -3 : -7));
+      // fetched into this unused window slot: the own cell's levels (external
+      // sensor, min(units, 255) * 2^-4) and the agent's water, biomass, health
+      const int j = lane - kEcoLane, u = (int)sv[k];
+      if (j < 3) xs[4 * SS + 5 + j] = ldexpf((float)min(u, 255), -4);
+      else xs[4 * SS + 2 + (j - 3)] = ldexpf((float)u, j == 3 ? -8 : (j == 4 ? -3 : -7));
     }
   }
-  // colour words carry the cell's sense bits in their top byte
-  const float res_here = (WORDS && L.colour) ? (float)((window_word(sv, centre) >> 25) & 1u) : 0.0f;
+  const float res_here = (float)((here >> 25) & 1u);
 
   wave_sync();
   if (WORDS && L.ecology) {

@@ -35,6 +35,7 @@ hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32
                               uint32_t threads);
 hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world);
 hipError_t launch_render(hipStream_t s, const Dev& d, const TileScratch& ts, int world);
+hipError_t launch_flowdir(hipStream_t s, const Dev& d, const TileScratch& ts, int world);
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_emit_list(hipStream_t s, const Dev& d, const Layout& L, const uint32_t* list, uint32_t n, int mode,
@@ -183,13 +184,17 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
   if (d.attack_enabled > 1) return bad(ECO_EINVAL, "attack_enabled", "must be 0 or 1");
   if (d.attack_enabled && d.n_actions != 7) return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7");
-  if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION | ECO_DESC_ECOLOGY))
+  if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION | ECO_DESC_ECOLOGY |
+                  ECO_DESC_TERRAIN))
     return bad(ECO_EINVAL, "flags", "has unknown bits");
   if (d.flags & ECO_DESC_ECOLOGY) {
     const eco_ecology& e = d.eco;
     if (d.n_actions != 8) return bad(ECO_EINVAL, "n_actions", "must be 8 in the ecology");
-    if (d.attack_enabled || (d.flags & (ECO_DESC_COLOUR_VISION | ECO_DESC_EVOLVE_TEMPERATURE)))
-      return bad(ECO_EINVAL, "flags", "the ecology runs without attack, colour vision and evolving temperature");
+    if (d.attack_enabled || (d.flags & ECO_DESC_EVOLVE_TEMPERATURE))
+      return bad(ECO_EINVAL, "flags", "the ecology runs without attack and evolving temperature");
+    if ((d.flags & ECO_DESC_TERRAIN) && (e.terrain_scale < 1 || e.sea_level < 0 || e.sea_level > 32 ||
+                                         e.water_per_depth < 0))
+      return bad(ECO_EINVAL, "eco.terrain_*", "terrain_scale >= 1, sea_level in [0, 32], water_per_depth >= 0");
     if (e.hp_max <= 0 || e.hp_child <= 0 || e.hp_child > e.hp_max) return bad(ECO_EINVAL, "eco.hp_*", "bad limits");
     if (e.age_shift < 0 || e.age_shift > 31) return bad(ECO_EINVAL, "eco.age_shift", "outside [0, 31]");
     if (e.cap_water < 0 || e.cap_energy < 0 || e.cap_biomass < 0 || e.eat_water < 0 || e.eat_biomass < 0 ||
@@ -205,6 +210,8 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   } else if (d.n_actions == 8) {
     return bad(ECO_EINVAL, "n_actions", "8 needs ECO_DESC_ECOLOGY");
   }
+  if ((d.flags & ECO_DESC_TERRAIN) && !(d.flags & ECO_DESC_ECOLOGY))
+    return bad(ECO_EINVAL, "flags", "terrain needs ECO_DESC_ECOLOGY");
   auto okh = [](uint32_t h) { return h == 32 || h == 64 || h == 128; };
   if (!okh(d.hidden1) || !okh(d.hidden2)) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be 32, 64 or 128");
   if (d.hidden1 != d.hidden2) return bad(ECO_ENOTSUP, "hidden1/hidden2", "must be equal");
@@ -319,6 +326,7 @@ eco_status run_init(eco_world* w) {
   HIPCHK(w, hipMemsetAsync(d.flags, 0, w->total_slots, s), "clear flags");
   HIPCHK(w, hipMemsetAsync(d.ring, 0, sizeof(eco_stats) * kStatsRing * w->n_worlds, s), "clear stats");
   HIPCHK(w, launch_init_cells(s, d, w->cell_tiles, w->n_cell_tiles), "init cells");
+  HIPCHK(w, launch_flowdir(s, d, w->ts, -1), "flow directions");
   for (uint32_t i = 0; i < w->n_worlds; ++i) {
     const WorldParams& p = w->wp[i];
     HIPCHK(w, sort_keys(w->sort_tmp, w->sort_tmp_bytes, d.cellkeys + p.cell_off, d.sorted + p.cell_off, p.cells, s),
@@ -714,6 +722,11 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     d.cw = (int32_t*)A(4 * TC);
     d.ce = (int32_t*)A(4 * TC);
     d.cb = (int32_t*)A(4 * TC);
+    if (descs[0].flags & ECO_DESC_TERRAIN) {
+      d.rock = (int32_t*)A(4 * TC);
+      d.flowdir = (int8_t*)A(TC);
+      d.cw_next = (int32_t*)A(4 * TC);
+    }
   }
   d.colour = w->L.colour ? (float4*)A(16 * TS) : nullptr;
   d.live = (int32_t*)A(4 * TS);
@@ -1228,6 +1241,33 @@ eco_status eco_world_read_sampled(eco_world* w, uint32_t world, uint8_t* out, si
   const WorldParams& p = w->wp[world];
   if (n < p.cap) return fail(ECO_EINVAL, "buffer too small");
   HIPCHK(w, hipMemcpyAsync(out, w->d.sampled + p.slot_off, p.cap, hipMemcpyDeviceToHost, w->stream), "read sampled");
+  return sync(w);
+}
+
+eco_status eco_world_read_terrain(eco_world* w, uint32_t world, int32_t* rock, size_t n) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !rock) return fail(ECO_EINVAL, "bad world or buffer");
+  if (!w->d.rock) return fail(ECO_EINVAL, "the object has no terrain (ECO_DESC_TERRAIN)");
+  const WorldParams& p = w->wp[world];
+  if (n < p.cells) return fail(ECO_EINVAL, "rock buffer too small");
+  HIPCHK(w, hipMemcpyAsync(rock, w->d.rock + p.cell_off, 4ull * p.cells, hipMemcpyDeviceToHost, w->stream), "read rock");
+  return sync(w);
+}
+
+eco_status eco_world_write_terrain(eco_world* w, uint32_t world, const int32_t* rock, size_t n) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (world >= w->n_worlds || !rock) return fail(ECO_EINVAL, "bad world or buffer");
+  if (!w->d.rock) return fail(ECO_EINVAL, "the object has no terrain (ECO_DESC_TERRAIN)");
+  const WorldParams& p = w->wp[world];
+  if (n < p.cells) return fail(ECO_EINVAL, "rock buffer too small");
+  for (size_t c = 0; c < p.cells; ++c)
+    if (rock[c] < 0 || rock[c] > 31) return fail(ECO_EINVAL, "rock heights must lie in 0..31");
+  hipStream_t s = w->stream;
+  HIPCHK(w, hipMemcpyAsync(w->d.rock + p.cell_off, rock, 4ull * p.cells, hipMemcpyHostToDevice, s), "write rock");
+  HIPCHK(w, launch_flowdir(s, w->d, w->ts, (int)world), "flow directions");
+  HIPCHK(w, launch_render(s, w->d, w->ts, (int)world), "window grid");
   return sync(w);
 }
 

@@ -472,6 +472,22 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
       wsum += (uint32_t)d.cw[g];
       bsum += (uint32_t)b;
     }
+    if (d.rock) {
+      // terrain: all water of a cell moves one cell downhill, every cell at once,
+      // as a gather (a cell keeps its water if it has no way down, and takes that
+      // of each neighbour whose way down leads here); the compaction's cell pass
+      // copies it back, after this launch has read the old layer everywhere
+      for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+        const uint32_t c = tl.start + i, g = wp.cell_off + c;
+        int acc = d.flowdir[g] < 0 ? d.cw[g] : 0;
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+          const uint32_t n = wp.cell_off + neighbour(wp, c, dd, +1);
+          if (d.flowdir[n] == ((dd + 2) & 3)) acc += d.cw[n];
+        }
+        d.cw_next[g] = acc;
+      }
+    }
     if (grown) atomicAdd(&cnt[0], grown);
     atomicAdd(&cnt[1], total);
     atomicAdd(&cnt[2], wsum);
@@ -744,16 +760,34 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
   }
 }
 
-// Ecology: the cell's water, energy and biomass levels (capped at 255) and its
-// agent / wall bits in the top byte.
-__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const Tile tl) {
+// Ecology: the cell's water, energy and biomass levels (capped at 255), or with
+// colour vision the cell as others see it (occupant's colour, wall grey, else
+// energy / biomass / water as red / green / blue); the agent / wall bits and the
+// rock height in the top byte.  flowed != 0 (the end of a step with terrain):
+// first take the water the step's flow left on the cell.
+__device__ __forceinline__ uint32_t sat255(int v) { return (uint32_t)min(max(v, 0), 255); }
+
+__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const Tile tl, int flowed) {
   const WorldParams wp = d.wp[tl.world];
   for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
     const uint32_t cell = wp.cell_off + tl.start + i;
-    const uint32_t w8 = (uint32_t)min(max(d.cw[cell], 0), 255), e8 = (uint32_t)min(max(d.ce[cell], 0), 255),
-                   b8 = (uint32_t)min(max(d.cb[cell], 0), 255);
+    if (flowed && d.rock) d.cw[cell] = d.cw_next[cell];
+    const int o = d.occ[cell];
     const bool wl = wp.has_walls && d.wall[cell] != 0;
-    d.rgb[cell] = w8 | (e8 << 8) | (b8 << 16) | (((d.occ[cell] >= 0 ? 1u : 0u) | (wl ? 4u : 0u)) << 24);
+    uint32_t q;
+    if (!d.colour) {
+      q = sat255(d.cw[cell]) | (sat255(d.ce[cell]) << 8) | (sat255(d.cb[cell]) << 16);
+    } else if (o >= 0) {
+      const float4 c = d.colour[wp.slot_off + (uint32_t)o];
+      q = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+    } else if (wl) {
+      q = 0x808080u;
+    } else {
+      q = sat255(16 * min(d.ce[cell], 1 << 20)) | (sat255(64 * min(d.cb[cell], 1 << 20)) << 8) |
+          (sat255(16 * min(d.cw[cell], 1 << 20)) << 16);
+    }
+    const uint32_t rk = d.rock ? (uint32_t)d.rock[cell] : 0u;
+    d.rgb[cell] = q | (((o >= 0 ? 1u : 0u) | (wl ? 4u : 0u) | (rk << 3)) << 24);
   }
 }
 
@@ -885,7 +919,7 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   if (blockIdx.x >= ts.n_slot_tiles) {
     const Tile ct = ts.cell_tiles[blockIdx.x - ts.n_slot_tiles];
     if (only_world < 0 || (int)ct.world == only_world) {
-      if (d.ep) cell_ecology_tile(d, ct);
+      if (d.ep) cell_ecology_tile(d, ct, !init);
       else if (d.rgb) cell_render_tile(d, ct);
       else cell_sense_tile(d, ct);
     }
@@ -909,7 +943,26 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
 // Rendered window words of one world's cells (after a colour write).
 __global__ __launch_bounds__(256) void k_render(Dev d, const Tile* __restrict__ tiles, int only_world) {
   const Tile ct = tiles[blockIdx.x];
-  if ((int)ct.world == only_world) cell_render_tile(d, ct);
+  if ((int)ct.world != only_world) return;
+  if (d.ep) cell_ecology_tile(d, ct, 0);
+  else cell_render_tile(d, ct);
+}
+
+// Terrain: each cell's way down, the lowest 4-neighbour if strictly lower (the
+// first of N, E, S, W among equals), else -1.
+__global__ __launch_bounds__(256) void k_flowdir(Dev d, const Tile* __restrict__ tiles, int only_world) {
+  const Tile tl = tiles[blockIdx.x];
+  if (only_world >= 0 && (int)tl.world != only_world) return;
+  const WorldParams wp = d.wp[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i;
+    int best = -1, bh = d.rock[wp.cell_off + c];
+    for (int dd = 0; dd < 4; ++dd) {
+      const int h = d.rock[wp.cell_off + neighbour(wp, c, dd, +1)];
+      if (h < bh) { bh = h; best = dd; }
+    }
+    d.flowdir[wp.cell_off + c] = (int8_t)best;
+  }
 }
 
 // Resource total of each world (init / after state writes): one block per world.
@@ -953,6 +1006,23 @@ __global__ __launch_bounds__(kScanThreads) void k_resource_total(Dev d, int only
 // ---------------------------------------------------------------------------
 // Init kernels
 // ---------------------------------------------------------------------------
+// Terrain height of local cell (x, y): bilinear blend, in exact integers with
+// floor division, of the four surrounding values (0..31) of a torus lattice of
+// NX x NY seeded values, NX = max(1, W / terrain_scale).
+__device__ __forceinline__ int terrain_height(const WorldParams& wp, const eco_ecology& e, uint32_t x, uint32_t y) {
+  const uint64_t W = wp.W, H = wp.H, L = (uint64_t)e.terrain_scale;
+  const uint64_t NX = W / L > 0 ? W / L : 1, NY = H / L > 0 ? H / L : 1;
+  const uint64_t ax = (uint64_t)x * NX, ay = (uint64_t)y * NY;
+  const uint64_t i = ax / W, j = ay / H, fx = ax % W, fy = ay % H;
+  const uint64_t i1 = (i + 1) % NX, j1 = (j + 1) % NY;
+  const uint64_t v00 = draw32(wp, (uint32_t)(i + j * NX), 0u, ST_TERRAIN) >> 27;
+  const uint64_t v10 = draw32(wp, (uint32_t)(i1 + j * NX), 0u, ST_TERRAIN) >> 27;
+  const uint64_t v01 = draw32(wp, (uint32_t)(i + j1 * NX), 0u, ST_TERRAIN) >> 27;
+  const uint64_t v11 = draw32(wp, (uint32_t)(i1 + j1 * NX), 0u, ST_TERRAIN) >> 27;
+  const uint64_t num = v00 * (W - fx) * (H - fy) + v10 * fx * (H - fy) + v01 * (W - fx) * fy + v11 * fx * fy;
+  return (int)(num / (W * H));
+}
+
 // floor(p * 2^32) clamped to [0, 2^32]: a 32-bit draw x is a Bernoulli(p) success iff x < it.
 __device__ __forceinline__ uint64_t density_threshold(float p) {
   double t = floor((double)p * 4294967296.0);
@@ -976,6 +1046,11 @@ __global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restric
       d.cw[g] = ((uint64_t)x.y < density_threshold(e.water_density)) ? e.water_site : 0;
       d.ce[g] = ((uint64_t)x.z < density_threshold(e.energy_density)) ? e.energy_site : 0;
       d.cb[g] = ((uint64_t)x.w < density_threshold(e.biomass_density)) ? e.biomass_site : 0;
+      if (d.rock) {   // terrain: the rock layer, and the sea instead of water sites
+        const int r = terrain_height(wp, e, c % wp.W, c / wp.W);
+        d.rock[g] = r;
+        d.cw[g] = r < e.sea_level ? (e.sea_level - r) * e.water_per_depth : 0;
+      }
     }
     d.occ[g] = -1;
     d.claim[g] = 0xFFFFFFFFu;
@@ -1111,6 +1186,11 @@ hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32
 }
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d) {
   hipLaunchKernelGGL(k_prestep_fill, dim3((d.total_slots + 255) / 256), dim3(256), 0, s, d);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_flowdir(hipStream_t s, const Dev& d, const TileScratch& ts, int world) {
+  if (ts.n_cell_tiles == 0 || !d.rock) return hipSuccess;
+  hipLaunchKernelGGL(k_flowdir, dim3(ts.n_cell_tiles), dim3(256), 0, s, d, ts.cell_tiles, world);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_render(hipStream_t s, const Dev& d, const TileScratch& ts, int world) {

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libeco.so")
 
 ECO_OK, ECO_EINVAL, ECO_ENOMEM, ECO_EDEVICE, ECO_ESTATE, ECO_ENOTSUP = 0, -1, -2, -3, -4, -5
 RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS = 1, 2, 4
-DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION, DESC_ECOLOGY = 1, 2, 4, 8   # eco_world_desc.flags
+DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION, DESC_ECOLOGY, DESC_TERRAIN = 1, 2, 4, 8, 16
 KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact", "sense"]
 
 EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world_step", "eco_world_reset",
@@ -24,7 +24,7 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
            "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps", "eco_world_read_colours",
-           "eco_world_write_colour"]
+           "eco_world_write_colour", "eco_world_read_terrain", "eco_world_write_terrain"]
 
 
 class EcoError(RuntimeError):
@@ -41,7 +41,7 @@ class Ecology(ctypes.Structure):
                     "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
                 (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
                                               "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
-                                              "b_repro")]
+                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth")]
 
 
 class Desc(ctypes.Structure):
@@ -137,6 +137,8 @@ def lib():
         L.eco_world_write_weights.argtypes = [P, U32, U32, P, ctypes.c_size_t]
         L.eco_world_read_colours.argtypes = [P, U32, P, ctypes.c_size_t]
         L.eco_world_write_colour.argtypes = [P, U32, U32, P]
+        L.eco_world_read_terrain.argtypes = [P, U32, P, ctypes.c_size_t]
+        L.eco_world_write_terrain.argtypes = [P, U32, P, ctypes.c_size_t]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -325,6 +327,16 @@ class World:
     def write_weights(self, slot, master, world=0):
         m = np.ascontiguousarray(master, dtype=np.float32)
         _err(lib().eco_world_write_weights(self._h, world, slot, _ptr(m), m.size))
+
+    def read_terrain(self, world=0):
+        c = self.cfgs[world]
+        out = np.empty(c["width"] * c["height"], dtype=np.int32)
+        _err(lib().eco_world_read_terrain(self._h, world, _ptr(out), out.size))
+        return out
+
+    def write_terrain(self, rock, world=0):
+        v = np.ascontiguousarray(rock, dtype=np.int32)
+        _err(lib().eco_world_write_terrain(self._h, world, _ptr(v), v.size))
 
     def read_colours(self, world=0):
         cap = self.cfgs[world]["capacity"]

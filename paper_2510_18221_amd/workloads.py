@@ -34,7 +34,7 @@ ECOLOGY = dict(water_density=0.1, energy_density=0.05, biomass_density=0.25, wat
                biomass_site=2, eat_water=10, eat_biomass=1, cap_water=200, cap_energy=400, cap_biomass=8,
                e_cost_move=2, w_cost=1, photo_rate=0.01, cell_energy_max=40, hp_max=100, hp_child=50,
                hp_overspend=20, hp_heal=10, heal_energy=1, age_shift=9, w_init=100, b_init=2, w_child=50, b_child=1,
-               b_repro=2)
+               b_repro=2, terrain_scale=32, sea_level=8, water_per_depth=4)
 ECOLOGY_FLAG = 8
 
 

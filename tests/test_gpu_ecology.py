@@ -181,8 +181,8 @@ def test_conservation_free_running_full_size(eco):
 
 
 def test_ecology_errors(eco):
-    for bad in [dict(n_actions=8), dict(n_actions=8, n_scalars=8, flags=8 | 4, eco=wl.ECOLOGY),
-                dict(n_actions=8, n_scalars=8, flags=8 | 2, eco=wl.ECOLOGY),
+    for bad in [dict(n_actions=8), dict(n_actions=8, n_scalars=8, flags=8 | 2, eco=wl.ECOLOGY),
+                dict(n_actions=8, n_scalars=8, flags=8, attack_enabled=1, eco=wl.ECOLOGY),
                 dict(n_actions=7, n_scalars=8, flags=8, eco=wl.ECOLOGY),
                 dict(n_actions=8, n_scalars=4, flags=8, eco=wl.ECOLOGY),
                 dict(n_actions=8, n_scalars=8, flags=8, eco=dict(wl.ECOLOGY, hp_child=0))]:
@@ -194,4 +194,99 @@ def test_ecology_errors(eco):
     st["cell_water"][5] = -1
     with pytest.raises(eco.EcoError):
         gw.write_state(st)
+    gw.close()
+
+
+# ---------------------------------------------------------------------------
+# Terrain: rock layer, sea, downhill water flow; colour windows in the ecology
+# with the elevation channel
+# ---------------------------------------------------------------------------
+TERRAIN, COLOUR = 16, 4
+
+
+def _terrain_world(seed, flags, wdtype=0, **kw):
+    d = _world(seed=seed, wdtype=wdtype, flags=8 | flags)
+    d["eco"] = dict(d["eco"], terrain_scale=12, sea_level=12, water_per_depth=3)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("size,scale", [((96, 80), 12), ((33, 17), 5), ((64, 64), 200)])
+def test_terrain_generator_parity(eco, size, scale):
+    cfg = _terrain_world(7, TERRAIN, width=size[0], height=size[1], n_agents_init=40, capacity=64)
+    cfg["eco"]["terrain_scale"] = scale
+    ow, gw = orc.OracleWorld(cfg, materialize=False), eco.World(cfg)
+    np.testing.assert_array_equal(gw.read_terrain(), ow.terrain())
+    assert_same_state(gw.read_state(), ow.state(), "init")   # the sea's water included
+    gw.close()
+
+
+def test_flow_hand_traced(eco):
+    cfg = wl.ecology_desc(eco=dict(HAND, terrain_scale=6, sea_level=0, water_per_depth=3), flags=8 | TERRAIN,
+                          width=6, height=6, n_agents_init=0, capacity=4, window=3, hidden1=32, hidden2=32, seed=1,
+                          e_eat=10, e_cost=1, e_repro=200, e_child=50)
+    rock = np.full((6, 6), 10, np.int32)
+    rock[2, 2] = 5; rock[2, 3] = 7; rock[3, 2] = 5; rock[0, 4] = 9; rock[1, 5] = 9
+    st = empty_state(6, 6, 4, ecology=True)
+    _put(st, 0, 0, 5, N, 100, 30, 2, 100)
+    cw = np.zeros((6, 6), np.int32)
+    cw[2, 3] = 12; cw[2, 2] = 4; cw[1, 2] = 5; cw[1, 4] = 7; cw[4, 4] = 2
+    st["cell_water"] = cw.reshape(-1)
+    ow, gw = orc.OracleWorld(cfg), eco.World(cfg)
+    for w in (ow, gw):
+        w.write_terrain(rock.reshape(-1))
+        w.write_state(st)
+    for t in range(3):
+        a = np.zeros(4, np.uint8)
+        ow.step(actions=a)
+        gw.step_with_actions(a)
+        assert_same_state(gw.read_state(), ow.state(), f"flow step {t}")
+        assert_stats_match(gw.stats()[0], ow.stats(), f"flow step {t}")
+    assert gw.read_state()["cell_water"].reshape(6, 6)[2, 2] == 21
+    with pytest.raises(eco.EcoError):
+        gw.write_terrain(np.full(36, 40, np.int32))
+    gw.close()
+
+
+@pytest.mark.parametrize("flags,wdtype", [(TERRAIN, 0), (TERRAIN | COLOUR, 0), (TERRAIN | COLOUR, 2), (COLOUR, 1),
+                                          (TERRAIN | COLOUR | 1, 0)])
+def test_terrain_seeded_actions(eco, flags, wdtype):
+    """Seeded actions on the 96x80 world with terrain (water flowing) and/or colour
+    windows (with the elevation channel), several policy tiles and a ragged tail."""
+    cfg = _terrain_world(100 + flags, flags, wdtype=wdtype)
+    acts = lambda t: wl.biased_actions(cfg["capacity"], 8, 100 + flags, t, p_forward=0.3, p_eat=0.35)
+    run_pair(eco, cfg, 15, actions_fn=acts, what=f"terrain flags {flags} wdtype {wdtype}", every=3)
+
+
+def test_terrain_policy_actions(eco):
+    cfg = _terrain_world(120, TERRAIN | COLOUR, e_init=260)
+    _, mism = run_pair(eco, cfg, 10, what="terrain + colour free-running")
+    assert mism <= 3
+
+
+def test_terrain_graph_eager_agree_and_conserve(eco):
+    cfg = _terrain_world(121, TERRAIN | COLOUR)
+    a, b = eco.World(cfg), eco.World(cfg)
+    b.set_flags(0)
+    s0 = a.stats()[0]
+    a.step(30)
+    b.step(30)
+    assert_same_state(a.read_state(), b.read_state(), "graph vs eager")
+    assert a.stats() == b.stats()
+    for h in a.stats_history(0, 31):
+        assert h["water_total"] == s0["water_total"] and h["biomass_total"] == s0["biomass_total"]
+    a.close()
+    b.close()
+
+
+def test_terrain_errors(eco):
+    with pytest.raises(eco.EcoError) as e:
+        eco.World(wl.desc(flags=TERRAIN))
+    assert e.value.status == eco.ECO_EINVAL
+    with pytest.raises(eco.EcoError) as e:
+        eco.World(wl.ecology_desc(flags=8 | TERRAIN, eco=dict(wl.ECOLOGY, terrain_scale=0)))
+    assert e.value.status == eco.ECO_EINVAL
+    gw = eco.World(wl.ecology_desc(seed=5))
+    with pytest.raises(eco.EcoError):
+        gw.read_terrain()
     gw.close()
