@@ -25,8 +25,8 @@ same world with attacks enabled (the paper's "+A" worlds, with its predation
 measures: attacks per agent and homicides per attack), the same world with the
 paper's own policy options (evolving softmax temperature, colour trait rendered
 into the windows), the same grid and population in the three-resource ecology
-with health, a per-kernel breakdown from a few eager steps, and the CPU oracle
-on a bounded sample.
+with health, and with terrain and the paper's 7x7 colour window, a per-kernel
+breakdown from a few eager steps, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -306,12 +306,16 @@ def main():
         # the three-resource ecology with health on the same grid and population (496->64->64->8)
         ecology_cfg = wl.ecology_desc(width=1024, height=1024, n_agents_init=65536, capacity=131072, window=11,
                                       n_scalars=12, hidden1=64, hidden2=64, mutation_sigma=0.01, e_init=230, seed=0)
+        # the paper's vision agent (RCV) in a world with terrain: a 7x7 window of rendered colour and
+        # elevation difference, the compass, the ecology with water flowing downhill (208->64->64->8)
+        terrain_cfg = dict(ecology_cfg, window=7, flags=eco.DESC_ECOLOGY | eco.DESC_TERRAIN | eco.DESC_COLOUR_VISION)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
                            ("fp32_attack", attack_cfg),
                            ("fp32_temperature_colour", paper_cfg),
-                           ("fp32_ecology", ecology_cfg)]:
+                           ("fp32_ecology", ecology_cfg),
+                           ("fp32_terrain_rcv_7x7", terrain_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
