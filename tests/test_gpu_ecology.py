@@ -290,3 +290,33 @@ def test_terrain_errors(eco):
     with pytest.raises(eco.EcoError):
         gw.read_terrain()
     gw.close()
+
+
+def test_multi_world_ecology_object(eco):
+    """Four ecology worlds of uneven size in one object, each with its own
+    parameters (costs, caps, photosynthesis rate, sea level, terrain scale), stepped
+    together; each against its own oracle, statistics every step, full state and
+    sampled weights every other step."""
+    base = _terrain_world(0, TERRAIN | COLOUR)
+    cfgs = []
+    for i, (w, h, n, cap) in enumerate([(40, 30, 70, 128), (96, 80, 450, 700), (17, 23, 20, 64), (60, 60, 200, 320)]):
+        d = dict(base, width=w, height=h, n_agents_init=n, capacity=cap, seed=200 + i)
+        d["eco"] = dict(base["eco"], w_cost=1 + i % 2, photo_rate=0.01 * (i + 1), cap_water=60 + 20 * i,
+                        sea_level=8 + 2 * i, terrain_scale=5 + 3 * i, age_shift=4 + i)
+        cfgs.append(d)
+    gw = eco.World(cfgs)
+    ows = [orc.OracleWorld(c) for c in cfgs]
+    for i, ow in enumerate(ows):
+        np.testing.assert_array_equal(gw.read_terrain(i), ow.terrain())
+        compare_world(gw, ow, f"world {i} init", world=i, weights_slots=2)
+    for t in range(10):
+        acts = [wl.biased_actions(c["capacity"], 8, 200 + i, t, p_forward=0.3, p_eat=0.35) for i, c in enumerate(cfgs)]
+        for ow, a in zip(ows, acts):
+            ow.step(actions=a)
+        gw.step_with_actions(np.concatenate(acts))
+        stats = gw.stats()
+        for i, ow in enumerate(ows):
+            assert_stats_match(stats[i], ow.stats(), f"world {i} step {t}")
+            if t % 2:
+                compare_world(gw, ow, f"world {i} step {t}", world=i, weights_slots=2)
+    gw.close()
