@@ -39,7 +39,13 @@ def test_validation_errors_without_device():
                         (dict(hidden1=48, hidden2=48), eco.ECO_ENOTSUP), (dict(attack_enabled=1), eco.ECO_EINVAL),
                         (dict(n_actions=7, attack_enabled=2), eco.ECO_EINVAL),
                         (dict(capacity=10), eco.ECO_EINVAL), (dict(e_repro=0), eco.ECO_EINVAL),
-                        (dict(window=17), eco.ECO_ENOTSUP)]:
+                        (dict(window=17), eco.ECO_ENOTSUP), (dict(flags=32), eco.ECO_EINVAL),
+                        (dict(n_actions=8), eco.ECO_EINVAL), (dict(flags=16), eco.ECO_EINVAL),
+                        (dict(flags=8, n_actions=8, n_scalars=4, eco=wl.ECOLOGY), eco.ECO_EINVAL),
+                        (dict(flags=8 | 2, n_actions=8, n_scalars=8, eco=wl.ECOLOGY), eco.ECO_EINVAL),
+                        (dict(flags=8 | 16, n_actions=8, n_scalars=8, eco=dict(wl.ECOLOGY, sea_level=40)),
+                         eco.ECO_EINVAL),
+                        (dict(flags=8, n_actions=8, n_scalars=8, eco=dict(wl.ECOLOGY, b_repro=0)), eco.ECO_EINVAL)]:
         d = (eco.Desc * 1)(eco.make_desc(wl.desc(**bad)))
         assert lib.eco_world_create(d, 1, None, None, ctypes.byref(out)) == status, bad
         assert lib.eco_last_error()

@@ -135,3 +135,40 @@ def test_large_world(eco):
     gw.set_flags(eco.RT_USE_GRAPH)
     free_running_invariants(gw, [cfg], 10)
     gw.close()
+
+
+def test_65k_world_1000_steps(eco):
+    """The 65,536-agent FP32 world over the configuration's 1,000 steps under seeded
+    actions (energies perturbed so births and deaths start at once): statistics
+    equal every step, the whole integer state every 250 steps, and the logits of
+    sampled agents (weights rebuilt from their lineages) at the end."""
+    cfg = wl.world_65k(seed=5)
+    gw = eco.World(cfg)
+    ow = orc.OracleWorld(cfg, materialize=False)
+    st = perturb_energies(ow.state(), 5)
+    ow.write_state(st)
+    gw.write_state(st)
+    births = deaths = 0
+    for t in range(1000):
+        acts = wl.biased_actions(cfg["capacity"], 7, 5, t)
+        if t == 999:
+            gw.set_flags(eco.RT_KEEP_LOGITS)
+            st_pre = ow.state()
+            slots = sample_slots(st_pre, 48, 55)
+            ref = np.stack([ow.agent_logits(int(s)) for s in slots])
+        ow.step(actions=acts)
+        gw.step_with_actions(acts)
+        g, o = gw.stats()[0], ow.stats()
+        for k in ("population", "births", "deaths", "eaten", "regrown", "moves_ok", "moves_blocked",
+                  "births_blocked_cell", "births_blocked_capacity", "resource_total", "action_hist", "energy_total"):
+            assert g[k] == o[k], (t, k, g[k], o[k])
+        births += o["births"]
+        deaths += o["deaths"]
+        if t % 250 == 249:
+            assert_same_state(gw.read_state(), ow.state(), f"step {t}")
+            say(f"[fullsize] 1000-step run: step {t + 1} population {o['population']}, births {births}, "
+                f"deaths {deaths}")
+    err = logit_err(gw.read_logits()[slots], ref)
+    say(f"[fullsize] 1000-step run: max normwise logit error {err.max():.2e} over {len(slots)} agents at step 1000")
+    assert err.max() <= LOGIT_TOL and births > 0 and deaths > 0
+    gw.close()
