@@ -124,7 +124,7 @@ def test_batch_of_64_worlds(eco):
     checked = [int(order[0]), int(order[31]), int(order[-1])]
     gw = fullsize_parity(eco, cfgs, checked, steps=2, n_sample=24, seed=3)
     gw.set_flags(eco.RT_USE_GRAPH)
-    free_running_invariants(gw, cfgs, 10)
+    free_running_invariants(gw, cfgs, 498)   # the configuration's 500 steps in all
     gw.close()
 
 
@@ -133,7 +133,8 @@ def test_large_world(eco):
     cfg = wl.world_large(seed=0)
     gw = fullsize_parity(eco, [cfg], [0], steps=2, n_sample=32, seed=4)
     gw.set_flags(eco.RT_USE_GRAPH)
-    free_running_invariants(gw, [cfg], 10)
+    free_running_invariants(gw, [cfg], 9998)   # the configuration's 10,000 steps in all
+    say(f"[fullsize] large world after 10,000 steps: population {gw.stats()[0]['population']}")
     gw.close()
 
 
