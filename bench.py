@@ -232,9 +232,9 @@ WORKLOADS = {
 }
 
 
-def workload_cfg(wl, name):
+def workload_cfg(wl, name, wdtype=None):
     if name == "65k":
-        return wl.world_65k(seed=0)
+        return wl.world_65k(seed=0, wdtype={None: wl.FP32, "f32": wl.FP32, "bf16": wl.BF16, "fp8": wl.FP8}[wdtype])
     if name == "batch":
         return wl.world_batch(64)
     if name == "small":
@@ -251,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--wdtype", choices=["f32", "bf16", "fp8"], default=None,
+                    help="weight storage of the 65k world's main line (default FP32, the metric's form)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 4 GiB device copy (PMC scaling)")
     ap.add_argument("--launch", default=None, help="fixed policy-kernel launch 'waves_per_block,blocks_per_cu,unroll'")
     ap.add_argument("--trajectory", type=int, default=0, help="instead: free-run this many steps, report per 1000")
@@ -270,7 +272,7 @@ def main():
     READ_CEILING["gbps"] = round(max(eco.stream_read_gbps(8 << 30) for _ in range(3)), 1)
     log(f"[bench] streaming-read ceiling {READ_CEILING['gbps']} GB/s")
 
-    cfg = workload_cfg(wl, args.workload)
+    cfg = workload_cfg(wl, args.workload, args.wdtype)
     if args.trajectory:
         rows = trajectory(eco, cfg, args.trajectory, chunk=args.trajectory_chunk, out_path=args.trajectory_out)
         print(json.dumps({"workload": args.workload, "trajectory": rows}), flush=True)
@@ -285,6 +287,10 @@ def main():
     log(f"[bench] {args.workload}: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, "
         f"launch {main_r['launch']}")
     desc, dtype = WORKLOADS[args.workload]
+    if args.workload == "65k" and args.wdtype in ("bf16", "fp8"):
+        desc = desc.replace("FP32 weights", {"bf16": "BF16 weights + FP32 master",
+                                             "fp8": "FP8-E4M3 weights + row scales + FP32 master"}[args.wdtype])
+        dtype = args.wdtype
     out = {
         "metric": "agent-steps/s at 65,536 agents, FP32 vs BF16 weights; % of HBM peak",
         "value": round(value, 1), "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -292,7 +298,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": desc, "agents_start": main_r["pop_start"], "agents_end": main_r["pop_end"],
                    "births": main_r["births"], "deaths": main_r["deaths"], "launch": main_r["launch"]},
-        "roofline": roofline(main_r, "65k_fp32" if args.workload == "65k" else None),
+        "roofline": roofline(main_r, {None: "65k_fp32", "f32": "65k_fp32", "bf16": "65k_bf16",
+                                      "fp8": "65k_fp8"}[args.wdtype] if args.workload == "65k" else None),
         "world_steps_per_s": round(1e3 / ms_per_step, 1),
         "timing_region_ms_per_step": round(main_r["timing_region"]["seconds"] * 1e3 / main_r["steps"], 4),
         "kernel_ms_per_step_eager": {k: round(v[0] / max(v[1], 1), 4)
@@ -320,7 +327,8 @@ def main():
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
-                              "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
+                              "roofline": roofline(r, {"bf16": "65k_bf16", "fp8": "65k_fp8"}.get(name)),
+                              "agents_start": r["pop_start"], "agents_end": r["pop_end"],
                               "launch": r["launch"]}
             if vcfg.get("flags", 0) & eco.DESC_ECOLOGY:
                 variants[name]["births_deaths"] = [r["births"], r["deaths"]]
