@@ -1008,43 +1008,56 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
         if (forward_shmem(w, wpb) > 64 * 1024 || forward_shmem(w, wpb) * bpc > 160 * 1024) continue;
         cand.push_back(eco_launch{wpb, bpc, u, 0});
       }
-  // Rounds over all candidates (one timed launch each per round), median per
-  // candidate: drifts of clock or memory state during tuning hit every shape alike.
-  constexpr int kRounds = 9;
-  const size_t n = cand.size();
-  std::vector<hipEvent_t> ev(n + 1, nullptr);
-  auto destroy = [&] {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
+  // Rounds over the candidates (one timed launch each per round), median per
+  // candidate: drifts of clock or memory state during tuning hit every shape
+  // alike.  Then the four best shapes again, over more rounds, since the best
+  // few often lie within the launch-to-launch spread of the first pass.
+  auto medians = [&](const std::vector<eco_launch>& c, int rounds, std::vector<float>& med) -> hipError_t {
+    const size_t n = c.size();
+    std::vector<hipEvent_t> ev(n + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+      if (e == hipSuccess) e = hipEventCreate(&x);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) e = launch_forward(w, w->stream, d, c[i]);  // warm-up
+    std::vector<std::vector<float>> t(n);
+    for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+      e = hipEventRecord(ev[0], w->stream);
+      for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        e = launch_forward(w, w->stream, d, c[i]);
+        if (e == hipSuccess) e = hipEventRecord(ev[i + 1], w->stream);
+      }
+      if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
+      for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        t[i].push_back(ms);
+      }
+    }
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+    med.assign(n, 1e30f);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+      std::sort(t[i].begin(), t[i].end());
+      med[i] = t[i][t[i].size() / 2];
+    }
+    return e;
   };
-  hipError_t e = hipSuccess;
-  for (auto& x : ev)
-    if (e == hipSuccess) e = hipEventCreate(&x);
-  for (size_t i = 0; i < n && e == hipSuccess; ++i) e = launch_forward(w, w->stream, d, cand[i]);  // warm-up
-  std::vector<std::vector<float>> t(n);
-  for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
-    e = hipEventRecord(ev[0], w->stream);
-    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
-      e = launch_forward(w, w->stream, d, cand[i]);
-      if (e == hipSuccess) e = hipEventRecord(ev[i + 1], w->stream);
-    }
-    if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
-    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
-      float ms = 0.0f;
-      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-      t[i].push_back(ms);
-    }
-  }
-  destroy();
+  std::vector<float> med1, med2;
+  hipError_t e = medians(cand, 9, med1);
+  if (e != hipSuccess) return dev_fail(w, e, "autotune");
+  std::vector<size_t> order(cand.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return med1[a] < med1[b]; });
+  std::vector<eco_launch> top;
+  for (size_t i = 0; i < order.size() && i < 4; ++i) top.push_back(cand[order[i]]);
+  e = medians(top, 15, med2);
   if (e != hipSuccess) return dev_fail(w, e, "autotune");
   eco_launch chosen = w->launch;
   float best_ms = 1e30f;
-  for (size_t i = 0; i < n; ++i) {
-    std::sort(t[i].begin(), t[i].end());
-    const float med = t[i][t[i].size() / 2];
-    if (med < best_ms) {
-      best_ms = med;
-      chosen = cand[i];
+  for (size_t i = 0; i < top.size(); ++i) {
+    if (med2[i] < best_ms) {
+      best_ms = med2[i];
+      chosen = top[i];
     }
   }
   w->launch = chosen;
