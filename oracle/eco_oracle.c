@@ -21,6 +21,8 @@
  *     worlds), an attack kills every other agent in the 3x3 square of cells
  *     directly ahead of the attacker; a dead agent's carried resource returns
  *     to its cell (Sec. 3.2, health points; App. "Varying Attack Strength", full
+ *     strength).  In the ecology the attack is the ninth action and each strike
+ *     costs the struck agent a set amount of health (full, half or quarter
  *     strength).
  *   - Resources (Sec. 3.2 "Resources"): every step costs energy, eating moves a
  *     resource unit from the cell into the agent, energy slowly regrows on
@@ -449,16 +451,17 @@ static int validate(const orc_desc* d) {
     if (d->window > d->width || d->window > d->height) return fail("window larger than the grid");
     if (d->n_scalars != 4 && d->n_scalars != 8 && !((d->flags & ORC_ECOLOGY) && d->n_scalars == 12))
         return fail("n_scalars must be 4 or 8 (8 or 12 in the ecology)");
-    if (d->n_actions != 5 && d->n_actions != 7 && d->n_actions != 8) return fail("n_actions must be 5, 7 or 8");
+    if (d->n_actions < 5 || d->n_actions > 9 || d->n_actions == 6) return fail("n_actions must be 5, 7, 8 or 9");
     if (d->attack_enabled > 1) return fail("attack_enabled must be 0 or 1");
-    if (d->attack_enabled && d->n_actions != 7) return fail("attacks need the seven-action head");
+    if (d->attack_enabled && d->n_actions != ((d->flags & ORC_ECOLOGY) ? 9u : 7u))
+        return fail("attacks need the seven-action head (nine in the ecology)");
     if (d->flags & ~(uint32_t)(ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY | ORC_TERRAIN))
         return fail("unknown flags");
     if (d->flags & ORC_ECOLOGY) {
         const orc_ecology* e = &d->eco;
-        if (d->n_actions != 8) return fail("the ecology has eight actions");
-        if (d->attack_enabled || (d->flags & ORC_EVOLVE_TEMPERATURE))
-            return fail("the ecology runs without attack and the evolving temperature");
+        if (d->n_actions != (d->attack_enabled ? 9u : 8u)) return fail("the ecology has eight actions (nine with attack)");
+        if (d->flags & ORC_EVOLVE_TEMPERATURE) return fail("the ecology runs without the evolving temperature");
+        if (e->attack_damage < 0 || e->attack_damage > (1 << 20)) return fail("attack_damage outside [0, 2^20]");
         if ((d->flags & ORC_TERRAIN) && (e->terrain_scale < 1 || e->sea_level < 0 || e->sea_level > 32 ||
                                          e->water_per_depth < 0))
             return fail("bad terrain parameters");
@@ -475,8 +478,8 @@ static int validate(const orc_desc* d) {
             !(e->energy_density >= 0.0f && e->energy_density <= 1.0f) ||
             !(e->biomass_density >= 0.0f && e->biomass_density <= 1.0f))
             return fail("bad ecology rate or density");
-    } else if (d->n_actions == 8) {
-        return fail("eight actions need the ecology");
+    } else if (d->n_actions >= 8) {
+        return fail("eight or nine actions need the ecology");
     }
     if ((d->flags & ORC_TERRAIN) && !(d->flags & ORC_ECOLOGY)) return fail("terrain needs the ecology");
     if (d->hidden1 < 1 || d->hidden2 < 1) return fail("hidden sizes must be positive");
@@ -743,10 +746,11 @@ static void forward(const orc_world* w, const double* theta, const double* x, do
 /* Softmax with temperature tau = exp(log_tau) (Sec. 3.3): weights
  * exp((l_k - max l) / tau), the largest logits weighing exactly 1. */
 int orc_sample_tempered(const double* l, int A, double log_tau, double u) {
+    if (A < 1 || A > 9) return -1;
     double m = l[0];
     for (int k = 1; k < A; ++k) if (l[k] > m) m = l[k];
     const double inv_tau = exp(-log_tau);
-    double wk[8], C[8], acc = 0.0;
+    double wk[9], C[9], acc = 0.0;
     for (int k = 0; k < A; ++k) {
         wk[k] = (l[k] == m) ? 1.0 : exp((l[k] - m) * inv_tau);
         acc += wk[k];
@@ -809,12 +813,14 @@ static int32_t min3(int32_t a, int32_t b, int32_t c) { int32_t m = a < b ? a : b
  *        amount, what the cell holds and the room left under the cap;
  *   costs: energy (rest the least) is destroyed; water is spent and returns to
  *        the cell; a resource that runs short is overspent (energy clamps at 0);
- *   damage: each overspent resource costs hp_overspend health, and age costs
- *        age >> age_shift (small, growing with age);
- *   death at health <= 0: water, energy and biomass carried go to the cell;
+ *   damage: each overspent resource costs hp_overspend health, age costs
+ *        age >> age_shift (small, growing with age), and each attack that
+ *        struck the agent's cell this step costs attack_damage;
+ *   death at health <= 0: water, energy and biomass carried go to the cell
+ *        (a struck agent that dies counts as killed);
  *   otherwise healing: below full health, heal_energy energy buys hp_heal health
  *        (capped at hp_max); the agent ages. */
-static void ecology_agent(orc_world* w, uint32_t s, orc_stats* st) {
+static void ecology_agent(orc_world* w, uint32_t s, uint32_t hits, orc_stats* st) {
     const orc_ecology* e = &w->d.eco;
     const uint32_t cell = (uint32_t)w->pos[s];
     const int a = w->action[s];
@@ -838,15 +844,17 @@ static void ecology_agent(orc_world* w, uint32_t s, orc_stats* st) {
     Wt -= spend;
     w->cw[cell] += spend;
     if (spend < e->w_cost) over++;
-    hp -= over * e->hp_overspend + (w->age[s] >> e->age_shift);
-    if (hp <= 0) {
+    int64_t damage = (int64_t)over * e->hp_overspend + (w->age[s] >> e->age_shift) + (int64_t)hits * e->attack_damage;
+    if ((int64_t)hp - damage <= 0) {
         w->cw[cell] += Wt; w->ce[cell] += E; w->cb[cell] += B;
         w->energy[s] = 0; w->water[s] = 0; w->biomass[s] = 0; w->hp[s] = 0;
         w->alive[s] = 0;
         w->occ[cell] = -1;
         st->deaths++;
+        if (hits > 0) st->killed++;
         return;
     }
+    hp -= (int32_t)damage;
     if (hp < e->hp_max && E >= e->heal_energy) {
         hp = (hp + e->hp_heal < e->hp_max) ? hp + e->hp_heal : e->hp_max;
         E -= e->heal_energy;
@@ -879,7 +887,7 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
         {
             double* x = (double*)malloc(w->D * sizeof(double));
             double* theta = (double*)malloc(w->P * sizeof(double));
-            double l[8];
+            double l[9];
 #pragma omp for schedule(dynamic, 16)
             for (int64_t si = 0; si < (int64_t)cap; ++si) {
                 uint32_t s = (uint32_t)si;
@@ -943,28 +951,33 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
      *     smaller than the square it may wrap onto the attacker's own cell,
      *     which is never struck by its own attack.  All attacks land at once:
      *     an attacker standing in another attacker's square is killed too, and
-     *     its own attack still lands.  Full strength: every struck agent dies. */
-    uint8_t* struck = (uint8_t*)calloc(w->cells ? w->cells : 1, 1);
+     *     its own attack still lands.  Full strength: every struck agent dies.
+     *     Ecology: the strikes on each cell are counted and cost health (5). */
+    uint32_t* struck = (uint32_t*)calloc(w->cells ? w->cells : 1, sizeof(uint32_t));
     if (w->d.attack_enabled) {
+        const int attack = w->eco ? ORC_ATTACK_ECO : ORC_ATTACK;
         for (uint32_t s = 0; s < cap; ++s) {
-            if (!live[s] || w->action[s] != ORC_ATTACK) continue;
+            if (!live[s] || w->action[s] != attack) continue;
             const int f = w->facing[s], r = (f + 1) % 4;   /* the heading to the attacker's right */
             const int64_t x = w->pos[s] % (int32_t)w->W, y = w->pos[s] / (int32_t)w->W;
             for (int ahead = 1; ahead <= 3; ++ahead)
                 for (int side = -1; side <= 1; ++side) {
                     uint32_t c = wrap_cell(w, x + ahead * DX[f] + side * DX[r], y + ahead * DY[f] + side * DY[r]);
-                    if (c != (uint32_t)w->pos[s]) struck[c] = 1;
+                    if (c != (uint32_t)w->pos[s]) struck[c] += 1;
                 }
         }
     }
 
-    /* 5. Struck agents die where they stand and their carried energy returns to
-     *    the cell as one resource unit (the resource layer holds 0 or 1 unit per
-     *    cell).  The others eat, pay the step cost and die at energy <= 0 (they
-     *    carry nothing then); survivors age. */
+    /* 5. Ecology: every agent updates its resources and health (with the
+     *    strikes on its cell).  Otherwise struck agents die where they stand and
+     *    their carried energy returns to the cell as one resource unit (the
+     *    resource layer holds 0 or 1 unit per cell); the others eat, pay the
+     *    step cost and die at energy <= 0 (they carry nothing then); survivors
+     *    age. */
     for (uint32_t s = 0; s < cap; ++s) {
         if (!live[s]) continue;
         uint32_t cell = (uint32_t)w->pos[s];
+        if (w->eco) { ecology_agent(w, s, struck[cell], st); continue; }
         if (struck[cell]) {
             w->alive[s] = 0;
             w->occ[cell] = -1;
@@ -974,7 +987,6 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
             st->killed++;
             continue;
         }
-        if (w->eco) { ecology_agent(w, s, st); continue; }
         if (w->action[s] == ORC_EAT && w->res[cell] > 0) {
             w->res[cell] -= 1;
             w->energy[s] += w->d.e_eat;

@@ -26,7 +26,8 @@ extern "C" {
 enum { ORC_FP32 = 0, ORC_BF16 = 1, ORC_FP8 = 2 };
 
 /* Actions.  A = 5 uses 0..4; A = 7 adds REPRODUCE and ATTACK (ATTACK does
- * nothing unless the world has attack_enabled). */
+ * nothing unless the world has attack_enabled).  The ecology's eight or nine
+ * actions follow below. */
 enum { ORC_REST = 0, ORC_TURN_L = 1, ORC_TURN_R = 2, ORC_FORWARD = 3, ORC_EAT = 4,
        ORC_REPRODUCE = 5, ORC_ATTACK = 6 };
 
@@ -53,9 +54,16 @@ enum { ORC_FRONT_VISION = 1, ORC_EVOLVE_TEMPERATURE = 2, ORC_COLOUR_VISION = 4, 
  * "Resources" and health points; App. "Varying Resource Rules", "Varying Agent
  * HP").  Cells hold water, energy and biomass; agents carry the three in a
  * capped stomach plus health.  Eight actions: rest, turn left, turn right,
- * forward, eat energy, eat water, eat biomass, reproduce.  Amounts are integer
+ * forward, eat energy, eat water, eat biomass, reproduce (and attack, with
+ * attack_enabled).  Amounts are integer
  * units: energies in 0.1 energy (as e_*), health in 0.1 HP. */
-enum { ORC_EAT_ENERGY = 4, ORC_EAT_WATER = 5, ORC_EAT_BIOMASS = 6, ORC_REPRODUCE_ECO = 7 };
+enum { ORC_EAT_ENERGY = 4, ORC_EAT_WATER = 5, ORC_EAT_BIOMASS = 6, ORC_REPRODUCE_ECO = 7, ORC_ATTACK_ECO = 8 };
+/* With attack_enabled the ecology has a ninth action, ORC_ATTACK_ECO: it strikes
+ * the same 3x3 square ahead as ORC_ATTACK, and every struck agent loses
+ * attack_damage health per attacker that struck its cell, in the same health
+ * update as its overspend and age damage (App. "Varying Attack Strength": full
+ * strength 10 HP = 100 units kills any agent of full health, half 50, quarter
+ * 25). */
 typedef struct {
     float    water_density, energy_density, biomass_density;  /* initial site densities */
     int32_t  water_site, energy_site, biomass_site;            /* units on an initial site */
@@ -72,6 +80,7 @@ typedef struct {
     int32_t  w_init, b_init;                                   /* initial agents' water and biomass */
     int32_t  w_child, b_child, b_repro;                        /* given to a child; biomass needed to reproduce */
     int32_t  terrain_scale, sea_level, water_per_depth;        /* ORC_TERRAIN */
+    int32_t  attack_damage;                                    /* health per strike (with attack_enabled) */
 } orc_ecology;
 
 /* One world's parameters.  Energies are integers in units of 0.1 energy. */
@@ -86,21 +95,22 @@ typedef struct {
     uint32_t hidden1, hidden2, n_actions;
     int32_t  e_init, e_cost, e_eat, e_repro, e_child;
     uint32_t wdtype;                   /* ORC_FP32 / ORC_BF16 / ORC_FP8 */
-    uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 */
+    uint32_t attack_enabled;           /* 0 or 1; 1 needs n_actions == 7 (ecology: 9) */
     uint32_t flags;                    /* ORC_FRONT_VISION | ORC_EVOLVE_TEMPERATURE | ORC_COLOUR_VISION | ORC_ECOLOGY | ORC_TERRAIN */
     orc_ecology eco;                   /* used with ORC_ECOLOGY */
     uint64_t seed;
 } orc_desc;
 
 /* Per-step statistics (the measurement interface of App. E).  deaths counts
- * every death of the step; killed is the part of it caused by attacks.  With
+ * every death of the step; killed is the part of it caused by attacks (in the
+ * ecology: the deaths of agents struck this step).  With
  * ORC_ECOLOGY: eaten counts eat actions that moved a unit, regrown the energy
  * units photosynthesis added, resource_total the energy on the grid, and
  * water_total / biomass_total the water and biomass on the grid and in live
  * agents (both conserved), hp_total the health of live agents; else 0. */
 typedef struct {
     uint64_t step, population, births, deaths, killed, eaten, regrown, moves_ok, moves_blocked,
-             births_blocked_cell, births_blocked_capacity, resource_total, action_hist[8];
+             births_blocked_cell, births_blocked_capacity, resource_total, action_hist[9];
     double   energy_total, trait_mean, trait_var;
     uint64_t water_total, biomass_total, hp_total;
 } orc_stats;

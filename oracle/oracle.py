@@ -15,7 +15,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 FP32, BF16, FP8 = 0, 1, 2
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
 FRONT_VISION, EVOLVE_TEMPERATURE, COLOUR_VISION, ECOLOGY, TERRAIN = 1, 2, 4, 8, 16   # orc_desc.flags
-EAT_ENERGY, EAT_WATER, EAT_BIOMASS, REPRODUCE_ECO = 4, 5, 6, 7             # the ecology's action set
+EAT_ENERGY, EAT_WATER, EAT_BIOMASS, REPRODUCE_ECO, ATTACK_ECO = 4, 5, 6, 7, 8   # the ecology's action set
 
 
 class OrcEcology(ctypes.Structure):
@@ -25,7 +25,8 @@ class OrcEcology(ctypes.Structure):
                     "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
                 (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
                                               "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
-                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth")]
+                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth",
+                                              "attack_damage")]
 
 
 class OrcDesc(ctypes.Structure):
@@ -47,7 +48,7 @@ class OrcStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
-        ("action_hist", ctypes.c_uint64 * 8),
+        ("action_hist", ctypes.c_uint64 * 9),
         ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double),
         ("water_total", ctypes.c_uint64), ("biomass_total", ctypes.c_uint64), ("hp_total", ctypes.c_uint64)]
 

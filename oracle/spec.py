@@ -27,7 +27,10 @@ worlds and to run the hand-traced cases.  Rules (paper sections):
   actions, energy and water spent every step (the water back onto the cell),
   damage from overspending and age, healing bought with energy, death at zero
   health returning everything carried, reproduction needing spare biomass,
-  energy appearing on biomass (photosynthesis);
+  energy appearing on biomass (photosynthesis); with attacks enabled the
+  ecology has a ninth action, attack, over the same 3x3 square, and every
+  strike costs the struck agent eco["attack_damage"] health, in the same health
+  update as its other damage (App. "Varying Attack Strength");
   16 = terrain (with 8; Sec. 3.2 "Terrain"): rock heights 0..31 from a seeded
   value-noise field, the sea filling the cells below sea level, all water of a
   cell moving each step to its lowest strictly lower neighbour, and the
@@ -45,7 +48,7 @@ from fractions import Fraction
 M32 = 0xFFFFFFFF
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)
 FRONT, TEMPERATURE, COLOUR, ECOLOGY, TERRAIN = 1, 2, 4, 8, 16
-EAT_E, EAT_W, EAT_B, REPRO8 = 4, 5, 6, 7
+EAT_E, EAT_W, EAT_B, REPRO8, ATTACK9 = 4, 5, 6, 7, 8
 HEADINGS = [(0, -1), (1, 0), (0, 1), (-1, 0)]  # N, E, S, W with y pointing down
 
 
@@ -277,7 +280,7 @@ class SpecWorld:
         n = self.step_no
         st = {k: 0 for k in ("births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
                              "births_blocked_cell", "births_blocked_capacity")}
-        st["action_hist"] = [0] * 8
+        st["action_hist"] = [0] * 9
         live = sorted(self.agents)
         for s in live:
             if actions is None:
@@ -318,11 +321,11 @@ class SpecWorld:
             else:
                 st["moves_blocked"] += 1
         # attacks land on the post-move positions, all at once
-        hit = set()
+        hit = {}   # cell -> number of strikes
         if c.get("attack_enabled", 0):
             for s in live:
                 ag = self.agents[s]
-                if ag["action"] != ATTACK:
+                if ag["action"] != (ATTACK9 if self.eco is not None else ATTACK):
                     continue
                 x, y = self._xy(ag["cell"])
                 fx, fy = HEADINGS[ag["facing"]]
@@ -331,12 +334,12 @@ class SpecWorld:
                     for side in (-1, 0, 1):
                         cell = self._cell(x + ahead * fx + side * rx, y + ahead * fy + side * ry)
                         if cell != ag["cell"]:
-                            hit.add(cell)
+                            hit[cell] = hit.get(cell, 0) + 1
         # eat, cost, death, age
         for s in live:
             ag = self.agents[s]
             if self.eco is not None:
-                self._ecology_agent(s, st)
+                self._ecology_agent(s, st, hit.get(ag["cell"], 0))
                 continue
             if ag["cell"] in hit:
                 self.occ[ag["cell"]] = -1
@@ -436,10 +439,11 @@ class SpecWorld:
         st["energy_total"] = float(sum(a["energy"] for a in self.agents.values()))
         return st
 
-    def _ecology_agent(self, s, st):
+    def _ecology_agent(self, s, st, strikes=0):
         """Eat, pay energy (destroyed) and water (back to the cell), take damage for
-        each overspent resource and for age, die at zero health leaving everything
-        carried on the cell, else heal with energy and age."""
+        each overspent resource, for age and for each strike, die at zero health
+        leaving everything carried on the cell (killed, when struck), else heal
+        with energy and age."""
         e, c = self.eco, self.c
         ag = self.agents[s]
         cell, a = ag["cell"], ag["action"]
@@ -464,7 +468,7 @@ class SpecWorld:
         self.cw[cell] += spend
         if spend < e["w_cost"]:
             over += 1
-        ag["hp"] -= over * e["hp_overspend"] + (ag["age"] >> e["age_shift"])
+        ag["hp"] -= over * e["hp_overspend"] + (ag["age"] >> e["age_shift"]) + strikes * e.get("attack_damage", 0)
         if ag["hp"] <= 0:
             self.cw[cell] += ag["water"]
             self.ce[cell] += ag["energy"]
@@ -472,6 +476,7 @@ class SpecWorld:
             self.occ[cell] = -1
             del self.agents[s]
             st["deaths"] += 1
+            st["killed"] += strikes > 0
             return
         if ag["hp"] < e["hp_max"] and ag["energy"] >= e["heal_energy"]:
             ag["hp"] = min(ag["hp"] + e["hp_heal"], e["hp_max"])

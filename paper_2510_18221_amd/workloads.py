@@ -34,14 +34,20 @@ ECOLOGY = dict(water_density=0.1, energy_density=0.05, biomass_density=0.25, wat
                biomass_site=2, eat_water=10, eat_biomass=1, cap_water=200, cap_energy=400, cap_biomass=8,
                e_cost_move=2, w_cost=1, photo_rate=0.01, cell_energy_max=40, hp_max=100, hp_child=50,
                hp_overspend=20, hp_heal=10, heal_energy=1, age_shift=9, w_init=100, b_init=2, w_child=50, b_child=1,
-               b_repro=2, terrain_scale=32, sea_level=8, water_per_depth=4)
+               b_repro=2, terrain_scale=32, sea_level=8, water_per_depth=4, attack_damage=100)
 ECOLOGY_FLAG = 8
+# Attack strengths of the ecology (health per strike): the paper's full (10 HP,
+# kills any agent), half (5 HP) and quarter (2.5 HP) settings.
+ATTACK_FULL, ATTACK_HALF, ATTACK_QUARTER = 100, 50, 25
 
 
 def ecology_desc(eco=None, **kw):
-    """A world of the three-resource ecology: eight actions, 8 scalars."""
+    """A world of the three-resource ecology: eight actions, 8 scalars (nine
+    actions when attack_enabled=1 is passed)."""
     d = desc(n_actions=8, n_scalars=8, flags=ECOLOGY_FLAG, eco=dict(ECOLOGY, **(eco or {})))
     d.update(kw)
+    if d.get("attack_enabled") and "n_actions" not in kw:
+        d["n_actions"] = 9
     return d
 
 
@@ -104,17 +110,19 @@ def random_actions(cap, n_actions, seed, step):
 
 def biased_actions(cap, n_actions, seed, step, p_forward=0.3, p_eat=0.3, p_attack=0.0):
     """Seeded actions with more moves and meals (exercises births and conflicts);
-    with seven actions, p_attack more of them attack."""
+    with seven (nine) actions, p_attack more of them attack."""
     rng = np.random.default_rng([seed, step, 0xB1A5])
     u = rng.random(cap)
     a = rng.integers(0, n_actions, size=cap, dtype=np.uint8)
     a[u < p_forward] = 3
     a[(u >= p_forward) & (u < p_forward + p_eat)] = 4
-    if n_actions == 8:   # the ecology: meals spread over energy, water, biomass; 15% reproduce
+    if n_actions >= 8:   # the ecology: meals spread over energy, water, biomass; 15% reproduce
         eat = (u >= p_forward) & (u < p_forward + p_eat)
         a[eat] = 4 + (rng.integers(0, 3, size=cap)[eat]).astype(np.uint8)
         p0 = p_forward + p_eat
         a[(u >= p0) & (u < p0 + 0.15)] = 7
+        if n_actions == 9:
+            a[(u >= p0 + 0.15) & (u < p0 + 0.15 + p_attack)] = 8
     if n_actions == 7:
         p0 = p_forward + p_eat
         a[(u >= p0) & (u < p0 + 0.2)] = 5

@@ -1,7 +1,8 @@
 """Property-based cross-check of the two independently written statements of the
 rules (the C oracle and the pure-Python one) on random tiny worlds: random grid
 sizes, windows, option combinations (attack, "Front" window, evolving
-temperature, colour vision, the three-resource ecology, terrain), random states
+temperature, colour vision, the three-resource ecology with or without attack
+at four strike strengths, terrain), random states
 written into both (agents, resources, walls, stomachs, health), random actions
 or the policies' own samples.  Every step both must give the same state,
 statistics and logits.  (CPU only.)"""
@@ -35,7 +36,8 @@ def worlds(draw):
         flags |= orc.ECOLOGY
         if draw(st.booleans()):
             flags |= orc.TERRAIN
-        n_actions, n_scalars = 8, draw(st.sampled_from([8, 12]))
+        attack = int(draw(st.booleans()))
+        n_actions, n_scalars = 8 + attack, draw(st.sampled_from([8, 12]))
     else:
         if draw(st.booleans()):
             flags |= orc.EVOLVE_TEMPERATURE
@@ -46,7 +48,8 @@ def worlds(draw):
     eco = dict(wl.ECOLOGY, w_cost=draw(st.integers(0, 3)), age_shift=draw(st.integers(0, 6)),
                cap_water=draw(st.integers(5, 60)), photo_rate=draw(st.sampled_from([0.0, 0.05, 0.5])),
                w_child=draw(st.integers(0, 20)), terrain_scale=draw(st.integers(1, 6)),
-               sea_level=draw(st.integers(0, 20)), water_per_depth=draw(st.integers(0, 3)))
+               sea_level=draw(st.integers(0, 20)), water_per_depth=draw(st.integers(0, 3)),
+               attack_damage=draw(st.sampled_from([0, 25, 50, 100])))
     cfg = wl.desc(width=W, height=H, n_agents_init=0, capacity=cap, window=window, n_scalars=n_scalars,
                   hidden1=32, hidden2=32, n_actions=n_actions, attack_enabled=attack, flags=flags, eco=eco,
                   resource_density=0.0, regrow_prob=draw(st.sampled_from([0.0, 0.2, 1.0])),

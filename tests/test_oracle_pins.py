@@ -292,8 +292,8 @@ def test_colour_trait_init_and_mutation():
 def test_tempered_sampling():
     from scipy import stats
     rng = np.random.default_rng(5)
-    for _ in range(300):
-        l = rng.standard_normal(7) * 3
+    for i in range(300):
+        l = rng.standard_normal((5, 7, 8, 9)[i % 4]) * 3
         lt = rng.standard_normal() * 2
         u = rng.random()
         p = np.exp((l - l.max()) / np.exp(lt))
@@ -389,8 +389,8 @@ def test_quantised_weights_match_torch_casts():
 def test_sample_inverse_cdf_and_frequencies():
     from scipy import stats
     rng = np.random.default_rng(3)
-    for _ in range(300):
-        l = rng.standard_normal(7) * 3
+    for i in range(300):
+        l = rng.standard_normal((5, 7, 8, 9)[i % 4]) * 3
         u = rng.random()
         p = np.exp(l - l.max())
         c = np.cumsum(p)
@@ -772,6 +772,86 @@ def test_E4_photosynthesis_extremes():
     assert s["regrown"] == 0
 
 
+# Attacks in the ecology (nine actions, attack = 8): each strike costs the struck
+# agent attack_damage health in its one health update of the step, after its own
+# meal and costs; the paper's full (100 = 10 HP), half (50) and quarter (25)
+# strengths.  6x6 torus; facing N an attacker at (x, y) strikes x-1..x+1, y-1..y-3.
+ATK9 = 8
+ATTACK_HALF, ATTACK_FULL = 1 << 8, 1 << 9   # test-only markers in the parametrization below
+
+
+def eco_atk_cfg(damage):
+    return tiny_cfg(width=6, height=6, capacity=4, n_actions=9, attack_enabled=1, n_scalars=8, flags=orc.ECOLOGY,
+                    eco=dict(ECO_HAND, attack_damage=damage), e_eat=10, e_cost=1, e_repro=200, e_child=50)
+
+
+def test_H1_full_strength_kills_and_the_body_feeds_the_cell():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 2, 4, N, 100, 30, 2, 100)          # attacker: square x 1..3, y 1..3
+    eco_place(st, 1, 2, 3, N, 100, 30, 2, 100)          # struck while eating biomass
+    eco_place(st, 2, 5, 5, N, 100, 30, 2, 100)          # outside: rests
+    st["cell_biomass"][cidx(2, 3)] = 3
+    out, s = run_both(eco_atk_cfg(100), st, [ATK9, 6, 0, 0])
+    assert list(out["alive"][:3]) == [1, 0, 1] and s["deaths"] == 1 and s["killed"] == 1 and s["eaten"] == 1
+    assert (out["energy"][0], out["water"][0], out["hp"][0]) == (98, 27, 100)   # attack costs like a move
+    assert (out["energy"][2], out["water"][2], out["hp"][2]) == (99, 27, 100)
+    # the victim ate (biomass 3), paid 2 energy and 3 water, then everything went to its cell
+    c = cidx(2, 3)
+    assert (out["cell_energy"][c], out["cell_water"][c], out["cell_biomass"][c]) == (98, 3 + 27, 3 - 1 + 3)
+    assert out["occ"][c] == -1 and s["action_hist"][ATK9] == 1 and s["action_hist"][6] == 1
+    assert s["water_total"] == 90 and s["biomass_total"] == 9 and s["resource_total"] == 98
+
+
+def test_H2_half_strength_wounds_once_kills_twice():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 1, 4, N, 100, 30, 2, 100)          # square x 0..2, y 1..3
+    eco_place(st, 1, 3, 4, N, 100, 30, 2, 100)          # square x 2..4, y 1..3
+    eco_place(st, 2, 2, 2, N, 100, 30, 2, 100)          # in both: 2 x 50
+    eco_place(st, 3, 4, 1, N, 100, 30, 2, 100)          # in slot 1's only: 50, then heals 10 for 1 energy
+    out, s = run_both(eco_atk_cfg(50), st, [ATK9, ATK9, 0, 0])
+    assert list(out["alive"]) == [1, 1, 0, 1] and s["killed"] == 1 and s["deaths"] == 1
+    assert (out["hp"][3], out["energy"][3], out["water"][3], out["age"][3]) == (60, 98, 27, 1)
+    assert (out["hp"][0], out["energy"][0]) == (100, 98) and (out["hp"][1], out["energy"][1]) == (100, 98)
+    c = cidx(2, 2)
+    assert (out["cell_energy"][c], out["cell_water"][c], out["cell_biomass"][c]) == (99, 30, 2)
+    assert s["hp_total"] == 260 and s["population"] == 3
+
+
+def test_H3_quarter_strength_attackers_strike_each_other():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 2, 4, N, 100, 30, 2, 100)          # square x 1..3, y 1..3: strikes slots 1, 2
+    eco_place(st, 1, 2, 1, S, 100, 30, 2, 100)          # facing S: square x 1..3, y 2..4: strikes slots 0, 2
+    eco_place(st, 2, 3, 2, N, 100, 30, 2, 40)           # two strikes: 40 - 50 <= 0, killed
+    eco_place(st, 3, 0, 0, N, 100, 0, 2, 15)            # not struck, short of water: 15 - 20, dies (not killed)
+    out, s = run_both(eco_atk_cfg(25), st, [ATK9, ATK9, 0, 0])
+    assert list(out["alive"]) == [1, 1, 0, 0] and s["deaths"] == 2 and s["killed"] == 1
+    for k in (0, 1):      # 100 - 25 = 75, healed to 85 for 1 energy; 100 - 2 - 1 = 97
+        assert (out["hp"][k], out["energy"][k], out["water"][k]) == (85, 97, 27)
+    assert out["cell_water"][cidx(3, 2)] == 30 and out["cell_energy"][cidx(0, 0)] == 99
+    assert s["hp_total"] == 170 and s["water_total"] == 90 and s["biomass_total"] == 8
+
+
+def test_H4_moves_resolve_before_the_strikes():
+    st = empty_state(6, 6, 4, ecology=True)
+    eco_place(st, 0, 2, 4, N, 100, 30, 2, 100)          # square x 1..3, y 1..3
+    eco_place(st, 1, 2, 0, S, 100, 30, 2, 100)          # moves into (2, 1): killed there
+    eco_place(st, 2, 1, 3, W, 100, 30, 2, 100)          # moves out to (0, 3): survives
+    eco_place(st, 3, 3, 2, N, 100, 30, 2, 100)          # moves to (3, 1), still inside: killed
+    out, s = run_both(eco_atk_cfg(100), st, [ATK9, 3, 3, 3])
+    assert s["moves_ok"] == 3 and s["killed"] == 2 and list(out["alive"]) == [1, 0, 1, 0]
+    assert xy(out, 2, 6) == (0, 3) and (out["energy"][2], out["hp"][2]) == (98, 100)
+    assert out["cell_water"][cidx(2, 1)] == 30 and out["cell_energy"][cidx(3, 1)] == 98
+    assert out["occ"][cidx(2, 1)] == -1 and out["occ"][cidx(3, 1)] == -1 and out["occ"][cidx(2, 0)] == -1
+
+
+def test_H5_nine_actions_and_attack_go_together_in_the_ecology():
+    base = eco_atk_cfg(100)
+    for bad in (dict(n_actions=8), dict(attack_enabled=0), dict(eco=dict(ECO_HAND, attack_damage=-1))):
+        with pytest.raises(Exception):
+            orc.OracleWorld(dict(base, **bad))
+    orc.OracleWorld(dict(base, attack_enabled=0, n_actions=8))
+
+
 def test_photosynthesis_rate():
     e = dict(ECO_HAND, biomass_density=1.0, biomass_site=1, photo_rate=0.01)
     cfg = wl.desc(width=100, height=100, n_agents_init=1, capacity=4, window=3, n_scalars=8, n_actions=8,
@@ -797,17 +877,22 @@ def _eco_run_cfg(seed, **kw):
     return wl.desc(eco=e, **d)
 
 
-def test_ecology_invariants_over_random_run():
+@pytest.mark.parametrize("damage", [0, 25, 100])
+def test_ecology_invariants_over_random_run(damage):
     """Water and biomass are conserved; N' = N + births - deaths; health stays in
-    (0, hp_max]; stomachs stay under their caps; one agent per cell."""
-    cfg = _eco_run_cfg(5, width=40, height=30, n_agents_init=200, capacity=320, window=5, n_scalars=8)
+    (0, hp_max]; stomachs stay under their caps; one agent per cell; with attacks
+    (nine actions) 0 < killed <= deaths."""
+    A = 9 if damage else 8
+    cfg = _eco_run_cfg(5, width=40, height=30, n_agents_init=200, capacity=320, window=5, n_scalars=8,
+                       n_actions=A, attack_enabled=int(damage > 0))
+    cfg["eco"]["attack_damage"] = damage
     w = orc.OracleWorld(cfg, materialize=False)
     s0 = w.stats()
     e = cfg["eco"]
-    births = deaths = 0
+    births = deaths = killed = 0
     for t in range(60):
         pop = w.stats()["population"]
-        w.step(actions=wl.biased_actions(cfg["capacity"], 8, 5, t, p_forward=0.3, p_eat=0.2))
+        w.step(actions=wl.biased_actions(cfg["capacity"], A, 5, t, p_forward=0.3, p_eat=0.2, p_attack=0.1))
         s = w.stats()
         st = w.state()
         assert s["water_total"] == s0["water_total"] and s["biomass_total"] == s0["biomass_total"]
@@ -820,7 +905,9 @@ def test_ecology_invariants_over_random_run():
         check_invariants(st, 40, 30)
         births += s["births"]
         deaths += s["deaths"]
-    assert births > 0 and deaths > 0
+        killed += s["killed"]
+        assert s["killed"] <= s["deaths"]
+    assert births > 0 and deaths > 0 and (killed > 0) == (damage > 0)
 
 
 def test_ecology_observation_matches_numpy():
@@ -848,10 +935,17 @@ def test_ecology_observation_matches_numpy():
 @pytest.mark.parametrize("seed,flags", [(0, orc.ECOLOGY), (1, orc.ECOLOGY),
                                         (2, orc.ECOLOGY | orc.TERRAIN),
                                         (3, orc.ECOLOGY | orc.TERRAIN | orc.COLOUR_VISION),
-                                        (4, orc.ECOLOGY | orc.COLOUR_VISION | orc.FRONT_VISION)])
+                                        (4, orc.ECOLOGY | orc.COLOUR_VISION | orc.FRONT_VISION),
+                                        (5, orc.ECOLOGY | orc.COLOUR_VISION | ATTACK_HALF),
+                                        (6, orc.ECOLOGY | orc.TERRAIN | ATTACK_FULL)])
 def test_ecology_oracle_matches_spec(seed, flags):
+    """The policies' own samples; with attack (nine actions) at half or full strength."""
+    damage = {ATTACK_HALF: 50, ATTACK_FULL: 100}.get(flags & (ATTACK_HALF | ATTACK_FULL), 0)
+    flags &= ~(ATTACK_HALF | ATTACK_FULL)
     cfg = _eco_run_cfg(seed, flags=flags)
-    cfg["eco"].update(terrain_scale=4, sea_level=10, water_per_depth=3)
+    if damage:
+        cfg.update(n_actions=9, attack_enabled=1)
+    cfg["eco"].update(terrain_scale=4, sea_level=10, water_per_depth=3, attack_damage=damage)
     o, sp = orc.OracleWorld(cfg), spec.SpecWorld(cfg)
     assert_same_state(o.state(), sp.state(), "init")
     tot = dict(births=0, deaths=0, eaten=0, regrown=0)
@@ -864,12 +958,14 @@ def test_ecology_oracle_matches_spec(seed, flags):
             np.testing.assert_allclose(logits[k], spl[k], rtol=1e-12, atol=1e-12)
         assert_same_state(o.state(), sp.state(), f"step {t}")
         os_ = o.stats()
-        for k in ("births", "deaths", "eaten", "regrown", "population", "resource_total", "water_total",
-                  "biomass_total", "hp_total"):
+        for k in ("births", "deaths", "killed", "eaten", "regrown", "population", "resource_total", "water_total",
+                  "biomass_total", "hp_total", "action_hist"):
             assert os_[k] == sst[k], (t, k)
         for k in tot:
             tot[k] += sst[k]
-    assert all(v > 0 for v in tot.values()), tot
+        tot["killed"] = tot.get("killed", 0) + sst["killed"]
+    assert all(v > 0 for k, v in tot.items() if k != "killed"), tot
+    assert (tot["killed"] > 0) == bool(damage), tot
 
 
 # ---------------------------------------------------------------------------
