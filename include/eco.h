@@ -89,13 +89,18 @@ typedef struct {
  * HP"), with the parameters of eco_world_desc.eco.  Cells hold water, energy and
  * biomass; agents carry the three in a capped stomach and have health.  Eight
  * actions: rest, turn left, turn right, forward, eat energy, eat water, eat
- * biomass, reproduce (n_actions = 8; no attack or evolving temperature with
- * it).  Per live agent after the moves: the chosen resource
+ * biomass, reproduce (n_actions = 8; no evolving temperature with it).  With
+ * attack_enabled a ninth action, attack (index 8, n_actions = 9), strikes the
+ * same 3x3 square as in the single-resource worlds, after the moves; an agent
+ * on a cell struck k times loses k * attack_damage health in its health update
+ * below (App. "Varying Attack Strength": full 100 = 10 HP, half 50, quarter 25),
+ * and stats.killed counts the deaths of struck agents.  The attacker pays
+ * e_cost_move.  Per live agent after the moves: the chosen resource
  * moves from its cell to its stomach (up to the eat amount, the cell's content and
  * the room under the cap); energy is spent (e_cost at rest, e_cost_move
  * otherwise; clamped at 0) and destroyed; w_cost water is spent onto the cell;
- * each resource that ran short costs hp_overspend health, and age costs
- * age >> age_shift; at health <= 0 the agent dies and its water, energy and
+ * each resource that ran short costs hp_overspend health, age costs
+ * age >> age_shift (and strikes as above); at health <= 0 the agent dies and its water, energy and
  * biomass go to its cell; otherwise, below full health, heal_energy energy buys
  * hp_heal health.  Reproduction (action 7) needs energy >= e_repro, water >=
  * w_child and biomass >= b_repro and gives the child e_child energy, w_child
@@ -138,6 +143,7 @@ typedef struct {
     int32_t hp_max, hp_child, hp_overspend, hp_heal, heal_energy, age_shift;
     int32_t w_init, b_init, w_child, b_child, b_repro;
     int32_t terrain_scale, sea_level, water_per_depth;   /* ECO_DESC_TERRAIN */
+    int32_t attack_damage;                       /* health per strike, 0..2^20 (attack_enabled) */
 } eco_ecology;
 
 /* One world (POD, copied at create).  Grid is a torus of width x height. */
@@ -152,11 +158,13 @@ typedef struct {
     uint32_t window;             /* S, odd, S <= width, S <= height, S <= 15 (ECO_ENOTSUP above) */
     uint32_t n_scalars;          /* 4 (internal+external) or 8 (+compass); ecology: 8 or 12 */
     uint32_t hidden1, hidden2;   /* each 32, 64 or 128 */
-    uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack); ecology: 8 */
+    uint32_t n_actions;          /* 5 (rest,L,R,fwd,eat) or 7 (+reproduce,+attack); ecology: 8, or 9
+                                    with attack_enabled (+attack) */
     int32_t e_init, e_cost, e_eat, e_repro, e_child;  /* units of 0.1 energy; e_repro > 0 */
     uint32_t wdtype;             /* eco_wdtype; identical for all worlds of one object */
     uint32_t keep_master;        /* reserved: BF16/FP8 always keep an FP32 master */
-    uint32_t attack_enabled;     /* 0: ATTACK does nothing; 1 (needs n_actions = 7): ATTACK kills
+    uint32_t attack_enabled;     /* 0: ATTACK does nothing; 1 (needs n_actions = 7; for the ecology,
+                                    9 and the health damage described there): ATTACK kills
                                     every other agent in the 3x3 square directly ahead of the
                                     attacker (rows 1..3 ahead, one column to either side, torus),
                                     after the moves of the step; each victim leaves one resource
@@ -178,7 +186,7 @@ typedef struct {
     uint64_t births_blocked_cell;      /* eligible parents whose cell behind was taken */
     uint64_t births_blocked_capacity;  /* winners left without a free slot */
     uint64_t resource_total;           /* resource units on the grid after regrowth */
-    uint64_t action_hist[8];           /* actions taken by the agents live at step start */
+    uint64_t action_hist[9];           /* actions taken by the agents live at step start */
     double energy_total;               /* sum of live energies (units of 0.1; exact) */
     double trait_mean, trait_var;      /* mean / variance over live agents of |theta_master|^2 */
     /* ECO_DESC_ECOLOGY (else 0): water and biomass on the grid and in live agents

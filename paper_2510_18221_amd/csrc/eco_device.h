@@ -24,8 +24,9 @@ namespace eco {
 constexpr int kStatsRing = 1024;
 constexpr uint8_t kAlive = 1, kBirthClaim = 2, kBirthWon = 4;
 enum Action : uint8_t { REST = 0, TURN_L = 1, TURN_R = 2, FORWARD = 3, EAT = 4, REPRODUCE = 5, ATTACK = 6 };
-// The ecology's eight actions: EAT (4) takes energy, then water, biomass, reproduce.
-enum EcologyAction : uint8_t { EAT_WATER = 5, EAT_BIOMASS = 6, REPRODUCE_ECO = 7 };
+// The ecology's eight actions: EAT (4) takes energy, then water, biomass, reproduce;
+// with attacks a ninth, attack.
+enum EcologyAction : uint8_t { EAT_WATER = 5, EAT_BIOMASS = 6, REPRODUCE_ECO = 7, ATTACK_ECO = 8 };
 // Philox stream tags (third counter word).
 enum Stream : uint32_t { ST_CELLKEY = 0, ST_FACING = 1, ST_RESINIT = 2, ST_WINIT = 3, ST_ACTION = 4,
                          ST_MUTATE = 5, ST_REGROW = 6, ST_COLOUR_INIT = 7, ST_COLOUR_MUTATE = 8, ST_TERRAIN = 9 };
@@ -59,15 +60,16 @@ struct WorldVar {
 // into the eco_stats ring by the compaction kernel.
 struct StepCounters {
   unsigned long long births, deaths, eaten, regrown, moves_ok, moves_blocked, births_blocked_cell,
-      births_blocked_capacity, resource_total, action_hist[8];
+      births_blocked_capacity, resource_total;
 };
 
 // Weight layouts.  VPL = values per 16-byte block (FP32 4, BF16 8, FP8 16).
 // Master (FP32, and FP32 storage):  L1 [KB1][H1][4] | b1[H1] | L2 [H1/4][H2][4] | b2[H2] |
-//                                   L3 [8][H2] | b3[8]     (rows a >= A of L3/b3 are zero)
-// BF16 storage: L1 [ceil(KB1/2)][H1][8] | b1[H1] | L2 [H1/8][H2][8] | b2[H2] | L3 [8][H2] | b3[8]
-// FP8 storage:  L1 [ceil(KB1/4)][H1][16] | L2 [H1/16][H2][16] | L3 [8][H2] (bytes) |
-//               b1,b2,b3 FP32 | sc1[H1], sc2[H2], sc3[8] FP32 per-row scales
+//                                   L3 [R3][H2] | b3[R3]   (rows a >= A of L3/b3 are zero)
+// BF16 storage: L1 [ceil(KB1/2)][H1][8] | b1[H1] | L2 [H1/8][H2][8] | b2[H2] | L3 [R3][H2] | b3[R3]
+// FP8 storage:  L1 [ceil(KB1/4)][H1][16] | L2 [H1/16][H2][16] | L3 [R3][H2] (bytes) |
+//               b1,b2,b3 FP32 | sc1[H1], sc2[H2], sc3[R3] FP32 per-row scales
+// R3 = 8 output rows, or 16 with a ninth action (rows 9..15 zero and never read).
 // KB1 = D/4 (D = 4 S^2 + n_s is a multiple of 4).
 struct Layout {
   uint32_t D, S, R, ns, H1, H2, A, wdtype;
@@ -75,6 +77,7 @@ struct Layout {
   uint32_t temp;                // 1: log temperature stored after the output biases (b3[A])
   uint32_t colour;              // 1: colour trait and rendered colour window
   uint32_t ecology;             // 1: three-resource ecology (cell words of water / energy / biomass levels)
+  uint32_t R3;                  // output rows in the weight blocks: 8, or 16 when A = 9
   uint32_t P;                   // logical parameters (the log temperature included)
   uint32_t KB1;                 // FP32 16-byte blocks per L1 row
   uint32_t KBv;                 // storage 16-byte blocks per L1 row
@@ -101,8 +104,9 @@ struct Dev {
   double* trait;
   int32_t* occ;
   uint32_t* claim;
-  uint32_t* mark;               // [total_cells] step + 1 of the last attack that struck the cell, or
-                                // null when no world of the object has attacks
+  uint32_t* mark;               // [total_cells] step + 1 of the last attack that struck the cell (the
+                                // ecology: strikes on the cell this step, cleared by the regrowth
+                                // tiles), or null when no world of the object has attacks
   uint8_t *res, *wall;
   uint8_t* sense;               // [total_cells] bit0 agent, bit1 resource, bit2 wall, bits3..5 energy bin
   uint32_t* rgb;                // [total_cells] window words, colour vision: R | G << 8 | B << 16, ecology:
@@ -120,7 +124,8 @@ struct Dev {
   int32_t* live;                // [total_slots], per-world segments at slot_off
   int32_t* bparent;             // [total_slots] birth winners (local slots) by rank
   int32_t* freel;               // [total_slots] free slots (local) ascending
-  float* logits;                // [total_slots][8] or null
+  float* logits;                // [total_slots][lgs]
+  uint32_t lgs;                 // logits per slot in that buffer: 8, or 16 with a ninth action
   unsigned long long* cellkeys; // init scratch: [total_cells] (key << 32 | local cell)
   unsigned long long* sorted;   // init scratch
   uint32_t n_worlds;

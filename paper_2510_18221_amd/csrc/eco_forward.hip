@@ -253,6 +253,30 @@ __device__ __forceinline__ float output_layer(const W3<WDT, H2>& o, const float*
   return part;
 }
 
+// The ninth output row (the ecology's attack logit), after layer 2: lane l takes
+// h2 entries l (and l + 64 when H2 = 128; lanes >= 32 idle when H2 = 32), then a
+// sum over the whole wave; every lane returns the logit.
+template <int WDT, int H2>
+__device__ __forceinline__ float ninth_logit(const uint8_t* __restrict__ wbase, const Layout& L,
+                                             const float* __restrict__ h2, int lane) {
+  float part = 0.0f;
+#pragma unroll
+  for (int r = 0; r < (H2 == 128 ? 2 : 1); ++r) {
+    const int j = lane + 64 * r;
+    if (H2 == 32 && lane >= 32) continue;
+    const uint32_t e = 8u * H2 + (uint32_t)j;   // element of row 8
+    float v;
+    if (WDT == 0) v = reinterpret_cast<const float*>(wbase + L.s_w3)[e];
+    else if (WDT == 1) v = bf16lo(reinterpret_cast<const uint16_t*>(wbase + L.s_w3)[e]);
+    else v = __builtin_amdgcn_cvt_pk_f32_fp8((uint32_t)(wbase + L.s_w3)[e], false)[0];
+    part = __builtin_fmaf(v, h2[j], part);
+  }
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) part += __shfl_xor(part, dd);
+  if (WDT == 2) part *= __uint_as_float(reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[8]);
+  return part + bias_of<WDT>(load_bias_raw<WDT>(wbase + L.s_b3, 8));
+}
+
 // Exclusive prefix of the per-world live counts into off[0..n] (wave 0 of the block).
 __device__ __forceinline__ void world_offsets(const WorldVar* __restrict__ wv, uint32_t n, uint32_t* off) {
   const int tid = threadIdx.x;
@@ -435,7 +459,9 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
 template <int H, int U, bool WORDS>
 constexpr int kMinWavesPerSimd = (U == 16 && (H == 128 || WORDS)) ? 2 : 3;
 
-template <int WDT, int H, int U, bool WORDS>
+// NINE: the ecology with attack (a ninth action, its logit from ninth_logit); a
+// separate instantiation, so that the other kernels carry none of its code.
+template <int WDT, int H, int U, bool WORDS, bool NINE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kMinWavesPerSimd<H, U, WORDS>)))
 void k_forward(Dev d, Layout L) {
   constexpr int VPL = WTraits<WDT>::VPL;
@@ -458,6 +484,8 @@ void k_forward(Dev d, Layout L) {
   const uint32_t g_lo = gw * chunk, g_hi = min(g_lo + chunk, total);
   if (g_lo >= g_hi) return;
 
+  static_assert(WORDS || !NINE, "a ninth action needs the ecology's window words");
+  constexpr int NA = NINE ? 9 : 8;   // the most actions this instantiation samples from
   const int A = (int)L.A;
   // Window cell ahead of the agent (row ahead0 - 1, column R), when the window has
   // one: the move claim reads its agent and wall channels from the observation
@@ -490,14 +518,16 @@ void k_forward(Dev d, Layout L) {
     load_w3<WDT, H>(wbase, L, lane, w3);
     hidden_layer<WDT, H, U>(wbase, L.s_w2, H / VPL, h1s, h2s, lane, tl.b2, tl.s2);
     const float lg = output_layer<WDT, H>(w3, h2s, lane, tl.b3, tl.s3);
+    const float l8 = NINE ? ninth_logit<WDT, H>(wbase, L, h2s, lane) : 0.0f;
 
     // ---- 3. softmax inverse-CDF sample ----
-    float l[8];
+    float l[9];
 #pragma unroll
     for (int a = 0; a < 8; ++a) l[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lg), 8 * a));
+    l[8] = l8;
     float m = l[0];
 #pragma unroll
-    for (int a = 1; a < 8; ++a)
+    for (int a = 1; a < NA; ++a)
       if (a < A) m = fmaxf(m, l[a]);
     // one exponential per lane (lane 8a + g holds logit a), then gathered in order.
     // An evolving temperature tau = exp(theta_T) divides the logits; theta_T is the
@@ -514,29 +544,35 @@ void k_forward(Dev d, Layout L) {
     } else {
       e_lane = ((lane >> 3) < A) ? expf(lg - m) : 0.0f;
     }
-    float C[8], wk[8], accum = 0.0f;
+    float C[9], wk[9], accum = 0.0f;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       wk[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e_lane), 8 * a));
       accum += wk[a];
       C[a] = accum;
     }
+    if (NINE) {
+      wk[8] = expf(l8 - m);
+      C[8] = accum + wk[8];
+    }
     const uint32_t x0 = draw32(wp, cur.local, cur.step, ST_ACTION);
     const float u = (float)(x0 >> 8) * 0x1p-24f;
-    const float t = u * C[A - 1];
+    const float t = u * C[NA - 1];   // = C[A - 1]: the weights of actions >= A are zero
     int as = -1;
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < NA; ++a)
       if (as < 0 && a < A && t < C[a]) as = a;
     if (as < 0) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int a = 0; a < NA; ++a)
         if (a < A && wk[a] > 0.0f) as = a;
     }
 
     // ---- 4. bookkeeping, turn, move claim (lane 0) ----
     const uint32_t slot = cur.slot;
-    if (d.keep_logits && (lane & 7) == 0) d.logits[(uint64_t)slot * 8 + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
+    constexpr uint32_t lgs = NINE ? 16u : 8u;   // the logit buffer's stride (Dev::lgs)
+    if (d.keep_logits && (lane & 7) == 0) d.logits[(uint64_t)slot * lgs + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
+    if (NINE && d.keep_logits && lane == 0) d.logits[(uint64_t)slot * lgs + 8] = l8;
     if (lane == 0 && d.dry) d.sampled[slot] = (uint8_t)as;
     if (lane == 0 && !d.dry) {
       const int a = d.inject ? (int)d.act_in[slot] : as;
@@ -567,12 +603,17 @@ void k_forward(Dev d, Layout L) {
     // ahead of it, rows 1..3 ahead, one column to either side, with this step;
     // the move kernel kills whoever stands on a stamped cell after the moves.
     // The square can wrap onto the attacker's own cell on a small torus: that
-    // cell is skipped.  Equal stamps from several attackers are idempotent.
+    // cell is skipped.  Equal stamps from several attackers are idempotent.  In
+    // the ecology (whose attack is the ninth action) the strikes are counted
+    // instead, each costing health.
     if (wp.attack && !d.dry) {
       const int a = d.inject ? (int)d.act_in[slot] : as;
-      if (a == ATTACK && lane < 9) {
+      if (a == (NINE ? (int)ATTACK_ECO : (int)ATTACK) && lane < 9) {
         const uint32_t c = offset_cell(wp, (uint32_t)cur.pos, cur.facing, 1 + lane / 3, lane % 3 - 1);
-        if (c != (uint32_t)cur.pos) d.mark[wp.cell_off + c] = cur.step + 1u;
+        if (c != (uint32_t)cur.pos) {
+          if (NINE) atomicAdd(&d.mark[wp.cell_off + c], 1u);
+          else d.mark[wp.cell_off + c] = cur.step + 1u;
+        }
       }
     }
     if (has_next) {
@@ -591,12 +632,13 @@ namespace eco {
 #define ECO_CAT(a, b) ECO_CAT2(a, b)
 hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 block, size_t shmem,
                                                   hipStream_t s, const Dev& d, const Layout& L) {
-  const bool words = (L.colour | L.ecology) != 0;
-#define ECO_CASE(HH, UU)                                                                          \
-  if (H == HH && U == UU) {                                                                       \
-    if (words) hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, true>), grid, block, shmem, s, d, L);  \
-    else hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, false>), grid, block, shmem, s, d, L);       \
-    return hipGetLastError();                                                                     \
+  const bool words = (L.colour | L.ecology) != 0, nine = L.A > 8;
+#define ECO_CASE(HH, UU)                                                                                  \
+  if (H == HH && U == UU) {                                                                               \
+    if (nine) hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, true, true>), grid, block, shmem, s, d, L);  \
+    else if (words) hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, true, false>), grid, block, shmem, s, d, L); \
+    else hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, false, false>), grid, block, shmem, s, d, L);     \
+    return hipGetLastError();                                                                             \
   }
   ECO_CASE(32, 4) ECO_CASE(32, 8) ECO_CASE(32, 16)
   ECO_CASE(64, 4) ECO_CASE(64, 8) ECO_CASE(64, 16)
@@ -604,12 +646,14 @@ hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 
 #undef ECO_CASE
   return hipErrorInvalidValue;
 }
-// The kernel a launch of this storage type with (H, U) runs (graph nodes name it).
-const void* ECO_CAT(forward_kernel_w, ECO_FWD_WDT)(int H, int U, bool words) {
-#define ECO_FN(HH, UU)                                                                          \
-  if (H == HH && U == UU)                                                                       \
-    return words ? reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, true>)         \
-                 : reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, false>);
+// The kernel a launch of this storage type with (H, U) runs (graph nodes name it);
+// mode 0: sense bytes, 1: window words, 2: window words and a ninth action.
+const void* ECO_CAT(forward_kernel_w, ECO_FWD_WDT)(int H, int U, int mode) {
+#define ECO_FN(HH, UU)                                                                                \
+  if (H == HH && U == UU)                                                                             \
+    return mode == 2 ? reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, true, true>)      \
+           : mode == 1 ? reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, true, false>)   \
+                       : reinterpret_cast<const void*>(&k_forward<ECO_FWD_WDT, HH, UU, false, false>);
   ECO_FN(32, 4) ECO_FN(32, 8) ECO_FN(32, 16)
   ECO_FN(64, 4) ECO_FN(64, 8) ECO_FN(64, 16)
   ECO_FN(128, 4) ECO_FN(128, 8) ECO_FN(128, 16)

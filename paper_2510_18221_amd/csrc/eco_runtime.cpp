@@ -20,9 +20,9 @@ hipError_t launch_forward_w0(int H, int U, dim3 grid, dim3 block, size_t shmem, 
                              const Layout& L);
 hipError_t launch_forward_w1(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
-const void* forward_kernel_w0(int H, int U, bool words);
-const void* forward_kernel_w1(int H, int U, bool words);
-const void* forward_kernel_w2(int H, int U, bool words);
+const void* forward_kernel_w0(int H, int U, int mode);
+const void* forward_kernel_w1(int H, int U, int mode);
+const void* forward_kernel_w2(int H, int U, int mode);
 hipError_t launch_forward_w2(int H, int U, dim3 grid, dim3 block, size_t shmem, hipStream_t s, const Dev& d,
                              const Layout& L);
 hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
@@ -175,23 +175,27 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
   if (d.window > 15) return bad(ECO_ENOTSUP, "window", "above 15 has no policy kernel");
   if ((d.flags & ECO_DESC_ECOLOGY) ? (d.n_scalars != 8 && d.n_scalars != 12) : (d.n_scalars != 4 && d.n_scalars != 8))
     return bad(ECO_EINVAL, "n_scalars", "must be 4 or 8 (8 or 12 in the ecology)");
-  if (d.n_actions != 5 && d.n_actions != 7 && d.n_actions != 8)
-    return bad(ECO_EINVAL, "n_actions", "must be 5 or 7 (8 in the ecology)");
+  if (d.n_actions != 5 && d.n_actions != 7 && d.n_actions != 8 && d.n_actions != 9)
+    return bad(ECO_EINVAL, "n_actions", "must be 5 or 7 (8, or 9 with attack, in the ecology)");
   if (d.e_repro <= 0) return bad(ECO_EINVAL, "e_repro", "must be > 0");
   if (d.wdtype > ECO_W_FP8E4M3) return bad(ECO_EINVAL, "wdtype", "unknown");
   if (!(d.resource_density >= 0.0f && d.resource_density <= 1.0f)) return bad(ECO_EINVAL, "resource_density", "outside [0,1]");
   if (!(d.regrow_prob >= 0.0f && d.regrow_prob <= 1.0f)) return bad(ECO_EINVAL, "regrow_prob", "outside [0,1]");
   if (!(d.mutation_sigma >= 0.0f) || std::isinf(d.mutation_sigma)) return bad(ECO_EINVAL, "mutation_sigma", "must be finite and >= 0");
   if (d.attack_enabled > 1) return bad(ECO_EINVAL, "attack_enabled", "must be 0 or 1");
-  if (d.attack_enabled && d.n_actions != 7) return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7");
+  if (d.attack_enabled && d.n_actions != ((d.flags & ECO_DESC_ECOLOGY) ? 9u : 7u))
+    return bad(ECO_EINVAL, "attack_enabled", "needs n_actions = 7 (9 in the ecology)");
   if (d.flags & ~(ECO_DESC_FRONT_VISION | ECO_DESC_EVOLVE_TEMPERATURE | ECO_DESC_COLOUR_VISION | ECO_DESC_ECOLOGY |
                   ECO_DESC_TERRAIN))
     return bad(ECO_EINVAL, "flags", "has unknown bits");
   if (d.flags & ECO_DESC_ECOLOGY) {
     const eco_ecology& e = d.eco;
-    if (d.n_actions != 8) return bad(ECO_EINVAL, "n_actions", "must be 8 in the ecology");
-    if (d.attack_enabled || (d.flags & ECO_DESC_EVOLVE_TEMPERATURE))
-      return bad(ECO_EINVAL, "flags", "the ecology runs without attack and evolving temperature");
+    if (d.n_actions != (d.attack_enabled ? 9u : 8u))
+      return bad(ECO_EINVAL, "n_actions", "must be 8 in the ecology (9 with attack)");
+    if (d.flags & ECO_DESC_EVOLVE_TEMPERATURE)
+      return bad(ECO_EINVAL, "flags", "the ecology runs without the evolving temperature");
+    if (e.attack_damage < 0 || e.attack_damage > (1 << 20))
+      return bad(ECO_EINVAL, "eco.attack_damage", "outside [0, 2^20]");
     if ((d.flags & ECO_DESC_TERRAIN) && (e.terrain_scale < 1 || e.sea_level < 0 || e.sea_level > 32 ||
                                          e.water_per_depth < 0))
       return bad(ECO_EINVAL, "eco.terrain_*", "terrain_scale >= 1, sea_level in [0, 32], water_per_depth >= 0");
@@ -207,8 +211,8 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
     if (!(e.photo_rate >= 0.0f) || std::isinf(e.photo_rate) || !unit(e.water_density) || !unit(e.energy_density) ||
         !unit(e.biomass_density))
       return bad(ECO_EINVAL, "eco", "densities must lie in [0,1] and photo_rate be finite and >= 0");
-  } else if (d.n_actions == 8) {
-    return bad(ECO_EINVAL, "n_actions", "8 needs ECO_DESC_ECOLOGY");
+  } else if (d.n_actions >= 8) {
+    return bad(ECO_EINVAL, "n_actions", "8 or 9 needs ECO_DESC_ECOLOGY");
   }
   if ((d.flags & ECO_DESC_TERRAIN) && !(d.flags & ECO_DESC_ECOLOGY))
     return bad(ECO_EINVAL, "flags", "terrain needs ECO_DESC_ECOLOGY");
@@ -233,6 +237,7 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
   L.temp = (d.flags & ECO_DESC_EVOLVE_TEMPERATURE) ? 1u : 0u;
   L.colour = (d.flags & ECO_DESC_COLOUR_VISION) ? 1u : 0u;
   L.ecology = (d.flags & ECO_DESC_ECOLOGY) ? 1u : 0u;
+  L.R3 = (L.A > 8) ? 16u : 8u;
   L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A + L.temp;
   L.p_w1 = 0;
   L.p_b1 = L.p_w1 + L.H1 * L.D;
@@ -246,8 +251,8 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
   L.u_w2 = L.u_b1 + L.H1 / 4;
   L.u_b2 = L.u_w2 + (L.H1 / 4) * L.H2;
   L.u_w3 = L.u_b2 + L.H2 / 4;
-  L.u_b3 = L.u_w3 + 8 * (L.H2 / 4);
-  L.u_end = L.u_b3 + 2;
+  L.u_b3 = L.u_w3 + L.R3 * (L.H2 / 4);
+  L.u_end = L.u_b3 + L.R3 / 4;
   const uint32_t vpl = d.wdtype == ECO_W_FP32 ? 4 : (d.wdtype == ECO_W_BF16 ? 8 : 16);
   L.KBv = (L.D + vpl - 1) / vpl;
   L.Dpad = L.KBv * vpl;
@@ -261,25 +266,25 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
     put(L.s_b1, 4ull * L.H1);
     put(L.s_w2, (uint64_t)(L.H1 / 4) * L.H2 * 16);
     put(L.s_b2, 4ull * L.H2);
-    put(L.s_w3, 4ull * 8 * L.H2);
-    put(L.s_b3, 4ull * 8);
+    put(L.s_w3, 4ull * L.R3 * L.H2);
+    put(L.s_b3, 4ull * L.R3);
   } else if (d.wdtype == ECO_W_BF16) {
     put(L.s_w1, (uint64_t)L.KBv * L.H1 * 16);
     put(L.s_b1, 2ull * L.H1);
     put(L.s_w2, (uint64_t)(L.H1 / 8) * L.H2 * 16);
     put(L.s_b2, 2ull * L.H2);
-    put(L.s_w3, 2ull * 8 * L.H2);
-    put(L.s_b3, 2ull * 8);
+    put(L.s_w3, 2ull * L.R3 * L.H2);
+    put(L.s_b3, 2ull * L.R3);
   } else {
     put(L.s_w1, (uint64_t)L.KBv * L.H1 * 16);
     put(L.s_w2, (uint64_t)(L.H1 / 16) * L.H2 * 16);
-    put(L.s_w3, 1ull * 8 * L.H2);
+    put(L.s_w3, 1ull * L.R3 * L.H2);
     put(L.s_b1, 4ull * L.H1);
     put(L.s_b2, 4ull * L.H2);
-    put(L.s_b3, 4ull * 8);
+    put(L.s_b3, 4ull * L.R3);
     put(L.s_sc1, 4ull * L.H1);
     put(L.s_sc2, 4ull * L.H2);
-    put(L.s_sc3, 4ull * 8);
+    put(L.s_sc3, 4ull * L.R3);
   }
   L.sstride = round_up(o, 256);
   L.mstride = (d.wdtype == ECO_W_FP32) ? L.sstride : round_up(16ull * L.u_end, 256);
@@ -500,10 +505,10 @@ eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {
     return st;
   }
   const int u = (int)w->launch.unroll, H = (int)w->L.H1;
-  const bool words = (w->L.colour | w->L.ecology) != 0;
-  const void* fwd = w->L.wdtype == 0   ? forward_kernel_w0(H, u, words)
-                    : w->L.wdtype == 1 ? forward_kernel_w1(H, u, words)
-                                       : forward_kernel_w2(H, u, words);
+  const int mode = w->L.A > 8 ? 2 : ((w->L.colour | w->L.ecology) != 0 ? 1 : 0);
+  const void* fwd = w->L.wdtype == 0   ? forward_kernel_w0(H, u, mode)
+                    : w->L.wdtype == 1 ? forward_kernel_w1(H, u, mode)
+                                       : forward_kernel_w2(H, u, mode);
   size_t cnt = 0;
   if (e == hipSuccess) e = hipGraphGetNodes(t.graph, nullptr, &cnt);
   std::vector<hipGraphNode_t> nodes(cnt);
@@ -732,7 +737,8 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.live = (int32_t*)A(4 * TS);
   d.bparent = (int32_t*)A(4 * TS);
   d.freel = (int32_t*)A(4 * TS);
-  d.logits = (float*)A(4 * 8 * TS);
+  d.lgs = w->L.R3;
+  d.logits = (float*)A(4ull * d.lgs * TS);
   d.cellkeys = (unsigned long long*)A(8 * TC);
   d.sorted = (unsigned long long*)A(8 * TC);
   d.store = (uint8_t*)A(w->L.sstride * TS);
@@ -1237,13 +1243,14 @@ eco_status eco_world_read_logits(eco_world* w, uint32_t world, float* out, size_
   if (world >= w->n_worlds || !out) return fail(ECO_EINVAL, "bad world or buffer");
   const WorldParams& p = w->wp[world];
   if (n_floats < (size_t)p.cap * w->L.A) return fail(ECO_EINVAL, "logits buffer too small");
-  std::vector<float> tmp((size_t)p.cap * 8);
-  HIPCHK(w, hipMemcpyAsync(tmp.data(), w->d.logits + (uint64_t)p.slot_off * 8, tmp.size() * 4, hipMemcpyDeviceToHost,
-                           w->stream), "read logits");
+  const uint32_t lgs = w->d.lgs;
+  std::vector<float> tmp((size_t)p.cap * lgs);
+  HIPCHK(w, hipMemcpyAsync(tmp.data(), w->d.logits + (uint64_t)p.slot_off * lgs, tmp.size() * 4,
+                           hipMemcpyDeviceToHost, w->stream), "read logits");
   st = sync(w);
   if (st != ECO_OK) return st;
   for (size_t s = 0; s < p.cap; ++s)
-    for (uint32_t a = 0; a < w->L.A; ++a) out[s * w->L.A + a] = tmp[s * 8 + a];
+    for (uint32_t a = 0; a < w->L.A; ++a) out[s * w->L.A + a] = tmp[s * lgs + a];
   return ECO_OK;
 }
 

@@ -27,8 +27,8 @@ constexpr int kSlotPart = 16;    // u32 counters per slot tile
 constexpr int kCellPart = 4;     // u32 counters per cell tile
 
 // Per-slot-tile counters (index in the partials row).
-enum { PC_HIST = 0, PC_MOVES_OK = 8, PC_MOVES_BLOCKED = 9, PC_EATEN = 10, PC_DEATHS = 11, PC_BB_CELL = 12,
-       PC_KILLED = 13 };
+enum { PC_HIST = 0, PC_MOVES_OK = 9, PC_MOVES_BLOCKED = 10, PC_EATEN = 11, PC_DEATHS = 12, PC_BB_CELL = 13,
+       PC_KILLED = 14 };
 
 // ---------------------------------------------------------------------------
 // Small block helpers
@@ -122,7 +122,7 @@ __device__ __forceinline__ UnitInfo unit_info(const Layout& L, uint32_t u) {
     const uint32_t e = u - L.u_w3, per = L.H2 / 4;
     r.layer = 2; r.row = e / per; r.kb = e % per;
     r.p = L.p_w3 + r.row * L.H2 + 4 * r.kb; r.nvalid = (r.row < L.A) ? 4 : 0;
-  } else {                          // b3 (8 padded), then the log temperature in slot A when it evolves
+  } else {                          // b3 (R3 padded), then the log temperature in slot A when it evolves
     const uint32_t e = u - L.u_b3, n3 = L.A + L.temp;
     r.layer = 5; r.row = 4 * e; r.kb = 0;
     r.p = L.p_b3 + r.row;
@@ -187,7 +187,7 @@ __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp,
   float* mc = reinterpret_cast<float*>(d.master + (uint64_t)child * L.mstride);
   const float* mp = reinterpret_cast<const float*>(d.master + (uint64_t)parent * L.mstride);
   uint8_t* sc = d.store + (uint64_t)child * L.sstride;
-  const uint32_t nrows = L.H1 + L.H2 + 8;
+  const uint32_t nrows = L.H1 + L.H2 + L.R3;
   if (WDT == 2) {
     for (uint32_t i = tid; i < nrows; i += blockDim.x) s_amax[i] = 0u;
     __syncthreads();
@@ -301,11 +301,12 @@ __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp,
 // cell c, which no other agent touches in this launch): eat the chosen resource
 // (up to the eat amount, the cell's content and the room under the stomach cap);
 // pay energy (destroyed; rest costs least) and water (onto the cell); each
-// resource that ran short and the agent's age cost health; at zero health the
-// agent dies and leaves water, energy and biomass on its cell; otherwise energy
-// heals it below full health and it ages.  Returns the new energy.
+// resource that ran short, the agent's age and each of the `hits` strikes on its
+// cell this step cost health; at zero health the agent dies and leaves water,
+// energy and biomass on its cell (killed, when struck); otherwise energy heals
+// it below full health and it ages.  Returns the new energy.
 __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e, const WorldParams& wp, uint32_t slot,
-                                             uint32_t c, int a, uint32_t* cnt) {
+                                             uint32_t c, int a, uint32_t hits, uint32_t* cnt) {
   int E = d.energy[slot], Wt = d.water[slot], B = d.biomass[slot], hp = d.hp[slot];
   int t = 0;
   if (a == EAT) {
@@ -326,8 +327,9 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
   Wt -= spend;
   d.cw[c] += spend;
   if (spend < e.w_cost) ++over;
-  hp -= over * e.hp_overspend + (d.age[slot] >> e.age_shift);
-  if (hp <= 0) {
+  const long long damage =
+      (long long)over * e.hp_overspend + (d.age[slot] >> e.age_shift) + (long long)hits * e.attack_damage;
+  if ((long long)hp - damage <= 0) {
     d.cw[c] += Wt;
     d.ce[c] += E;
     d.cb[c] += B;
@@ -335,7 +337,9 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
     d.flags[slot] = 0;
     d.occ[c] = -1;
     atomicAdd(&cnt[PC_DEATHS], 1u);
+    if (hits) atomicAdd(&cnt[PC_KILLED], 1u);
   } else {
+    hp -= (int)damage;
     if (hp < e.hp_max && E >= e.heal_energy) {
       hp = min(hp + e.hp_heal, e.hp_max);
       E -= e.heal_energy;
@@ -377,7 +381,8 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
       }
       int E = d.energy[slot];
       if (d.ep) {
-        E = ecology_agent(d, d.ep[tl.world], wp, slot, wp.cell_off + (uint32_t)cell, a, cnt);
+        const uint32_t g = wp.cell_off + (uint32_t)cell;
+        E = ecology_agent(d, d.ep[tl.world], wp, slot, g, a, wp.attack ? d.mark[g] : 0u, cnt);
       } else if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
         // struck after the moves: dies where it stands; its carried energy goes
         // back to the cell as one resource unit (cells hold 0 or 1 unit)
@@ -406,7 +411,7 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
     }
   }
   __syncthreads();
-  if (threadIdx.x < 12 || threadIdx.x == PC_KILLED)
+  if (threadIdx.x < kSlotPart && threadIdx.x != PC_BB_CELL)   // the birth claims write PC_BB_CELL
     part[blockIdx.x * kSlotPart + threadIdx.x] = cnt[threadIdx.x];
 }
 
@@ -471,6 +476,7 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
       total += (uint32_t)en;
       wsum += (uint32_t)d.cw[g];
       bsum += (uint32_t)b;
+      if (wp.attack) d.mark[g] = 0;   // the strikes of this step have been counted
     }
     if (d.rock) {
       // terrain: all water of a cell moves one cell downhill, every cell at once,
@@ -632,7 +638,7 @@ constexpr int kMaxWorlds = 1024;
 template <int WDT>
 __global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
   __shared__ uint32_t off[kMaxWorlds + 1];
-  __shared__ uint32_t s_amax[128 + 128 + 8];
+  __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];
   birth_offsets(d.wv, d.n_worlds, off);
   const uint32_t total = off[d.n_worlds];
@@ -887,7 +893,7 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
       st.eaten = s_cnt[PC_EATEN];
       st.moves_ok = s_cnt[PC_MOVES_OK];
       st.moves_blocked = s_cnt[PC_MOVES_BLOCKED];
-      for (int a = 0; a < 8; ++a) st.action_hist[a] = s_cnt[PC_HIST + a];
+      for (int a = 0; a < 9; ++a) st.action_hist[a] = s_cnt[PC_HIST + a];
       st.regrown = s_cnt[kSlotPart + 0];
       st.resource_total = s_cnt[kSlotPart + 1];
       if (d.ep) {
@@ -1095,7 +1101,7 @@ __global__ __launch_bounds__(kSlotTile) void k_init_agents(Dev d, const Tile* __
 template <int WDT>
 __global__ __launch_bounds__(256) void k_emit_list(Dev d, Layout L, const uint32_t* __restrict__ list, uint32_t n,
                                                    int mode, double std1, double std2, double std3) {
-  __shared__ uint32_t s_amax[128 + 128 + 8];
+  __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];
   for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
     const uint32_t w = list[2 * e], j = list[2 * e + 1];
@@ -1113,8 +1119,7 @@ __global__ __launch_bounds__(256) void k_prestep_fill(Dev d) {
   d.sampled[i] = 255;
   if (d.keep_logits) {
     const float nan = __builtin_nanf("");
-#pragma unroll
-    for (int a = 0; a < 8; ++a) d.logits[(uint64_t)i * 8 + a] = nan;
+    for (uint32_t a = 0; a < d.lgs; ++a) d.logits[(uint64_t)i * d.lgs + a] = nan;
   }
 }
 

@@ -41,7 +41,8 @@ class Ecology(ctypes.Structure):
                     "cap_energy", "cap_biomass", "e_cost_move", "w_cost")] + [("photo_rate", ctypes.c_float)] + [
                 (n, ctypes.c_int32) for n in ("cell_energy_max", "hp_max", "hp_child", "hp_overspend", "hp_heal",
                                               "heal_energy", "age_shift", "w_init", "b_init", "w_child", "b_child",
-                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth")]
+                                              "b_repro", "terrain_scale", "sea_level", "water_per_depth",
+                                              "attack_damage")]
 
 
 class Desc(ctypes.Structure):
@@ -62,7 +63,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "step", "population", "births", "deaths", "killed", "eaten", "regrown", "moves_ok", "moves_blocked",
         "births_blocked_cell", "births_blocked_capacity", "resource_total")] + [
-        ("action_hist", ctypes.c_uint64 * 8),
+        ("action_hist", ctypes.c_uint64 * 9),
         ("energy_total", ctypes.c_double), ("trait_mean", ctypes.c_double), ("trait_var", ctypes.c_double),
         ("water_total", ctypes.c_uint64), ("biomass_total", ctypes.c_uint64), ("hp_total", ctypes.c_uint64)]
 
