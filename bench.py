@@ -25,8 +25,9 @@ same world with attacks enabled (the paper's "+A" worlds, with its predation
 measures: attacks per agent and homicides per attack), the same world with the
 paper's own policy options (evolving softmax temperature, colour trait rendered
 into the windows), the same grid and population in the three-resource ecology
-with health, and with terrain and the paper's 7x7 colour window, a per-kernel
-breakdown from a few eager steps, and the CPU oracle on a bounded sample.
+with health, and with terrain and the paper's 7x7 colour window (with and
+without full-strength attacks), a per-kernel breakdown from a few eager steps,
+and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -56,7 +57,8 @@ def run_history(w, steps, s_end):
         out["pop_end"] += hist[-1]["population"]
         out["births"] += sum(h["births"] for h in hist[1:])
         out["deaths"] += sum(h["deaths"] for h in hist[1:])
-        out["attacks"] += sum(h["action_hist"][6] for h in hist[1:])
+        atk = 8 if w.A == 9 else 6   # the attack action: ninth in the ecology, seventh otherwise
+        out["attacks"] += sum(h["action_hist"][atk] for h in hist[1:])
         out["killed"] += sum(h["killed"] for h in hist[1:])
     return out
 
@@ -316,13 +318,16 @@ def main():
         # the paper's vision agent (RCV) in a world with terrain: a 7x7 window of rendered colour and
         # elevation difference, the compass, the ecology with water flowing downhill (208->64->64->8)
         terrain_cfg = dict(ecology_cfg, window=7, flags=eco.DESC_ECOLOGY | eco.DESC_TERRAIN | eco.DESC_COLOUR_VISION)
+        # the paper's "Ocean" agent (RCV+A): the same, with full-strength attacks as a ninth action (208->64->64->9)
+        ocean_cfg = dict(terrain_cfg, n_actions=9, attack_enabled=1)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
                            ("fp32_attack", attack_cfg),
                            ("fp32_temperature_colour", paper_cfg),
                            ("fp32_ecology", ecology_cfg),
-                           ("fp32_terrain_rcv_7x7", terrain_cfg)]:
+                           ("fp32_terrain_rcv_7x7", terrain_cfg),
+                           ("fp32_terrain_rcv_a_7x7", ocean_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]

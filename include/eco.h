@@ -271,10 +271,10 @@ eco_status eco_world_set_flags(eco_world* w, uint32_t flags);
 eco_status eco_world_set_launch(eco_world* w, const eco_launch* launch);
 eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
 /* Time every candidate launch shape on the forward pass of the current state
- * (the forward has no side effect on the world) in nine rounds over all shapes,
- * then the four fastest again in fifteen rounds, and keep the shape with the
- * lowest median of the second pass.  Every candidate produces bit-identical
- * actions.  *best may be NULL. */
+ * (the forward has no side effect on the world) in nine rounds over all shapes
+ * (median per shape), then the four fastest again as runs of three launches in
+ * eleven rounds, and keep the shape with the lowest mean of the second pass.
+ * Every candidate produces bit-identical actions.  *best may be NULL. */
 eco_status eco_world_autotune(eco_world* w, eco_launch* best);
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);
 

@@ -1014,11 +1014,14 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
         if (forward_shmem(w, wpb) > 64 * 1024 || forward_shmem(w, wpb) * bpc > 160 * 1024) continue;
         cand.push_back(eco_launch{wpb, bpc, u, 0});
       }
-  // Rounds over the candidates (one timed launch each per round), median per
-  // candidate: drifts of clock or memory state during tuning hit every shape
-  // alike.  Then the four best shapes again, over more rounds, since the best
-  // few often lie within the launch-to-launch spread of the first pass.
-  auto medians = [&](const std::vector<eco_launch>& c, int rounds, std::vector<float>& med) -> hipError_t {
+  // Rounds over the candidates, each timed over `reps` consecutive launches per
+  // round: drifts of clock or memory state during tuning hit every shape alike.
+  // The first pass (one launch, median over rounds) keeps the four fastest; the
+  // second times those as runs of three launches, as a step loop repeats one
+  // shape, and ranks them by the mean over more rounds, the statistic a step's
+  // cost follows (a median hides a shape that is only sometimes slow).
+  auto timings = [&](const std::vector<eco_launch>& c, int rounds, int reps, bool mean,
+                     std::vector<float>& score) -> hipError_t {
     const size_t n = c.size();
     std::vector<hipEvent_t> ev(n + 1, nullptr);
     hipError_t e = hipSuccess;
@@ -1029,34 +1032,36 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
     for (int r = 0; r < rounds && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[0], w->stream);
       for (size_t i = 0; i < n && e == hipSuccess; ++i) {
-        e = launch_forward(w, w->stream, d, c[i]);
+        for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_forward(w, w->stream, d, c[i]);
         if (e == hipSuccess) e = hipEventRecord(ev[i + 1], w->stream);
       }
       if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
       for (size_t i = 0; i < n && e == hipSuccess; ++i) {
         float ms = 0.0f;
         e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-        t[i].push_back(ms);
+        t[i].push_back(ms / (float)reps);
       }
     }
     for (auto& x : ev)
       if (x) (void)hipEventDestroy(x);
-    med.assign(n, 1e30f);
+    score.assign(n, 1e30f);
     for (size_t i = 0; i < n && e == hipSuccess; ++i) {
       std::sort(t[i].begin(), t[i].end());
-      med[i] = t[i][t[i].size() / 2];
+      double sum = 0.0;
+      for (float v : t[i]) sum += v;
+      score[i] = mean ? (float)(sum / (double)t[i].size()) : t[i][t[i].size() / 2];
     }
     return e;
   };
   std::vector<float> med1, med2;
-  hipError_t e = medians(cand, 9, med1);
+  hipError_t e = timings(cand, 9, 1, false, med1);
   if (e != hipSuccess) return dev_fail(w, e, "autotune");
   std::vector<size_t> order(cand.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return med1[a] < med1[b]; });
   std::vector<eco_launch> top;
   for (size_t i = 0; i < order.size() && i < 4; ++i) top.push_back(cand[order[i]]);
-  e = medians(top, 15, med2);
+  e = timings(top, 11, 3, true, med2);
   if (e != hipSuccess) return dev_fail(w, e, "autotune");
   eco_launch chosen = w->launch;
   float best_ms = 1e30f;
