@@ -253,28 +253,46 @@ __device__ __forceinline__ float output_layer(const W3<WDT, H2>& o, const float*
   return part;
 }
 
-// The ninth output row (the ecology's attack logit), after layer 2: lane l takes
-// h2 entries l (and l + 64 when H2 = 128; lanes >= 32 idle when H2 = 32), then a
-// sum over the whole wave; every lane returns the logit.
+// The ninth output row (the ecology's attack logit).  Its raw weights (lane l
+// takes h2 entries l, and l + 64 when H2 = 128; lanes >= 32 idle when H2 = 32),
+// bias and FP8 scale are loaded with the output layer's, before layer 2 streams;
+// after it, a sum over the whole wave, which every lane returns.
 template <int WDT, int H2>
-__device__ __forceinline__ float ninth_logit(const uint8_t* __restrict__ wbase, const Layout& L,
-                                             const float* __restrict__ h2, int lane) {
+struct Row9 {
+  uint32_t w[H2 == 128 ? 2 : 1];
+  uint32_t b, s;
+};
+
+template <int WDT, int H2>
+__device__ __forceinline__ void load_row9(const uint8_t* __restrict__ wbase, const Layout& L, int lane,
+                                          Row9<WDT, H2>& o) {
+#pragma unroll
+  for (int r = 0; r < (H2 == 128 ? 2 : 1); ++r) {
+    const uint32_t e = 8u * H2 + (uint32_t)(lane + 64 * r);   // element of row 8
+    if (H2 == 32 && lane >= 32) o.w[r] = 0u;
+    else if (WDT == 0) o.w[r] = reinterpret_cast<const uint32_t*>(wbase + L.s_w3)[e];
+    else if (WDT == 1) o.w[r] = reinterpret_cast<const uint16_t*>(wbase + L.s_w3)[e];
+    else o.w[r] = (wbase + L.s_w3)[e];
+  }
+  o.b = load_bias_raw<WDT>(wbase + L.s_b3, 8);
+  o.s = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[8] : 0u;
+}
+
+template <int WDT, int H2>
+__device__ __forceinline__ float ninth_logit(const Row9<WDT, H2>& o, const float* __restrict__ h2, int lane) {
   float part = 0.0f;
 #pragma unroll
   for (int r = 0; r < (H2 == 128 ? 2 : 1); ++r) {
-    const int j = lane + 64 * r;
-    if (H2 == 32 && lane >= 32) continue;
-    const uint32_t e = 8u * H2 + (uint32_t)j;   // element of row 8
-    float v;
-    if (WDT == 0) v = reinterpret_cast<const float*>(wbase + L.s_w3)[e];
-    else if (WDT == 1) v = bf16lo(reinterpret_cast<const uint16_t*>(wbase + L.s_w3)[e]);
-    else v = __builtin_amdgcn_cvt_pk_f32_fp8((uint32_t)(wbase + L.s_w3)[e], false)[0];
-    part = __builtin_fmaf(v, h2[j], part);
+    const int j = (H2 == 32) ? (lane & 31) : lane + 64 * r;
+    const float v = (WDT == 0) ? __uint_as_float(o.w[r])
+                    : (WDT == 1) ? bf16lo(o.w[r])
+                                 : __builtin_amdgcn_cvt_pk_f32_fp8(o.w[r], false)[0];
+    part = __builtin_fmaf(v, h2[j], part);   // lanes >= 32 of H2 = 32 hold a zero weight
   }
 #pragma unroll
   for (int dd = 1; dd < 64; dd <<= 1) part += __shfl_xor(part, dd);
-  if (WDT == 2) part *= __uint_as_float(reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[8]);
-  return part + bias_of<WDT>(load_bias_raw<WDT>(wbase + L.s_b3, 8));
+  if (WDT == 2) part *= scale_of<WDT>(o.s);
+  return part + bias_of<WDT>(o.b);
 }
 
 // Exclusive prefix of the per-world live counts into off[0..n] (wave 0 of the block).
@@ -516,9 +534,11 @@ void k_forward(Dev d, Layout L) {
     hidden_layer<WDT, H, U>(wbase, L.s_w1, (int)L.KBv, xs, h1s, lane, tl.b1, tl.s1);
     W3<WDT, H> w3;
     load_w3<WDT, H>(wbase, L, lane, w3);
+    Row9<WDT, H> r9;
+    if (NINE) load_row9<WDT, H>(wbase, L, lane, r9);
     hidden_layer<WDT, H, U>(wbase, L.s_w2, H / VPL, h1s, h2s, lane, tl.b2, tl.s2);
     const float lg = output_layer<WDT, H>(w3, h2s, lane, tl.b3, tl.s3);
-    const float l8 = NINE ? ninth_logit<WDT, H>(wbase, L, h2s, lane) : 0.0f;
+    const float l8 = NINE ? ninth_logit<WDT, H>(r9, h2s, lane) : 0.0f;
 
     // ---- 3. softmax inverse-CDF sample ----
     float l[9];
