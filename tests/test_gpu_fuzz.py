@@ -1,7 +1,7 @@
 """Property-based parity of the HIP world step with the oracle on random tiny
 worlds (the same strategy as the oracle cross-check: random sizes, windows,
 option combinations, written states, random or sampled actions), each at a random
-launch shape of the policy kernel.  Derandomized: the same 40 cases every run.
+launch shape of the policy kernel.  Derandomized: the same 100 cases every run.
 Integer state bit-exact, statistics equal, weights and colour traits within a
 few FP32 ulps, logits within the FP32 tolerance."""
 import numpy as np
@@ -29,7 +29,7 @@ LAUNCHES = [(1, 4, 4), (2, 2, 8), (4, 2, 16), (8, 1, 4), (8, 4, 8), (4, 8, 4)]
 
 
 def test_random_worlds(eco):
-    @settings(max_examples=40, deadline=None, derandomize=True, database=None,
+    @settings(max_examples=100, deadline=None, derandomize=True, database=None,
               suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large,
                                      HealthCheck.function_scoped_fixture])
     @given(worlds(), st.sampled_from(LAUNCHES))
