@@ -29,7 +29,7 @@ def desc(**kw):
 # Three-resource ecology parameters (integer units: energy in 0.1 energy, health
 # in 0.1 HP).  The paper fixes the photosynthesis rate 0.01, the biomass site
 # density 1/4, health 10 HP at most and 5 HP at birth, and healing of 1 HP per
-# 0.1 energy; the other amounts are this build's choices.
+# 0.1 energy; the other amounts are chosen here.
 ECOLOGY = dict(water_density=0.1, energy_density=0.05, biomass_density=0.25, water_site=20, energy_site=20,
                biomass_site=2, eat_water=10, eat_biomass=1, cap_water=200, cap_energy=400, cap_biomass=8,
                e_cost_move=2, w_cost=1, photo_rate=0.01, cell_energy_max=40, hp_max=100, hp_child=50,
