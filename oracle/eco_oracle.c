@@ -952,7 +952,9 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
      *     which is never struck by its own attack.  All attacks land at once:
      *     an attacker standing in another attacker's square is killed too, and
      *     its own attack still lands.  Full strength: every struck agent dies.
-     *     Ecology: the strikes on each cell are counted and cost health (5). */
+     *     Ecology: the strikes on each cell are counted and cost health (5);
+     *     an attacker strikes each distinct cell of its square once (on a torus
+     *     narrower than three cells the square lists some cell twice). */
     uint32_t* struck = (uint32_t*)calloc(w->cells ? w->cells : 1, sizeof(uint32_t));
     if (w->d.attack_enabled) {
         const int attack = w->eco ? ORC_ATTACK_ECO : ORC_ATTACK;
@@ -960,10 +962,16 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
             if (!live[s] || w->action[s] != attack) continue;
             const int f = w->facing[s], r = (f + 1) % 4;   /* the heading to the attacker's right */
             const int64_t x = w->pos[s] % (int32_t)w->W, y = w->pos[s] / (int32_t)w->W;
+            uint32_t seen[9];
+            int n_seen = 0;
             for (int ahead = 1; ahead <= 3; ++ahead)
                 for (int side = -1; side <= 1; ++side) {
                     uint32_t c = wrap_cell(w, x + ahead * DX[f] + side * DX[r], y + ahead * DY[f] + side * DY[r]);
-                    if (c != (uint32_t)w->pos[s]) struck[c] += 1;
+                    int dup = c == (uint32_t)w->pos[s];
+                    for (int k = 0; k < n_seen; ++k) dup |= seen[k] == c;
+                    if (dup) continue;
+                    seen[n_seen++] = c;
+                    struck[c] += 1;
                 }
         }
     }

@@ -330,11 +330,10 @@ class SpecWorld:
                 x, y = self._xy(ag["cell"])
                 fx, fy = HEADINGS[ag["facing"]]
                 rx, ry = -fy, fx
-                for ahead in (1, 2, 3):
-                    for side in (-1, 0, 1):
-                        cell = self._cell(x + ahead * fx + side * rx, y + ahead * fy + side * ry)
-                        if cell != ag["cell"]:
-                            hit[cell] = hit.get(cell, 0) + 1
+                square = {self._cell(x + ahead * fx + side * rx, y + ahead * fy + side * ry)
+                          for ahead in (1, 2, 3) for side in (-1, 0, 1)}   # each distinct cell once
+                for cell in square - {ag["cell"]}:
+                    hit[cell] = hit.get(cell, 0) + 1
         # eat, cost, death, age
         for s in live:
             ag = self.agents[s]

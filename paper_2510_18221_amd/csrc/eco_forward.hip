@@ -625,12 +625,21 @@ void k_forward(Dev d, Layout L) {
     // The square can wrap onto the attacker's own cell on a small torus: that
     // cell is skipped.  Equal stamps from several attackers are idempotent.  In
     // the ecology (whose attack is the ninth action) the strikes are counted
-    // instead, each costing health.
+    // instead, each costing health, and an attacker strikes each distinct cell
+    // once: lane (ahead, side) is cell (ahead mod Lf, side mod Lr) of the square,
+    // Lf and Lr the torus lengths along and across the facing, so it repeats an
+    // earlier lane exactly when side + 1 >= Lr or ahead > Lf (sides below 3).
     if (wp.attack && !d.dry) {
       const int a = d.inject ? (int)d.act_in[slot] : as;
       if (a == (NINE ? (int)ATTACK_ECO : (int)ATTACK) && lane < 9) {
-        const uint32_t c = offset_cell(wp, (uint32_t)cur.pos, cur.facing, 1 + lane / 3, lane % 3 - 1);
-        if (c != (uint32_t)cur.pos) {
+        const int ahead = 1 + lane / 3, side = lane % 3 - 1;
+        const uint32_t c = offset_cell(wp, (uint32_t)cur.pos, cur.facing, ahead, side);
+        bool skip = c == (uint32_t)cur.pos;
+        if (NINE) {
+          const int lf = (cur.facing & 1) ? (int)wp.W : (int)wp.H, lr = (cur.facing & 1) ? (int)wp.H : (int)wp.W;
+          skip |= side + 1 >= lr || ahead > lf;
+        }
+        if (!skip) {
           if (NINE) atomicAdd(&d.mark[wp.cell_off + c], 1u);
           else d.mark[wp.cell_off + c] = cur.step + 1u;
         }

@@ -2,7 +2,9 @@
 actions and health points; App. "Varying Attack Strength"): the ninth action
 strikes the 3x3 square ahead after the moves, each strike costs the struck agent
 attack_damage health (full 100, half 50, quarter 25) in its health update, and a
-struck agent that dies leaves everything it carries on its cell.  Integer state
+struck agent that dies leaves everything it carries on its cell; an attacker
+strikes each distinct cell of its square once, also where a narrow torus folds
+the square onto itself.  Integer state
 bit-exact, statistics (killed included) equal, logits (nine of them) within the
 FP32 tolerance.  The hand-built cases are the oracle's hand-traced pins, replayed
 through the C ABI.
@@ -64,6 +66,15 @@ def _case(name):
         _put(st, 0, 2, 4, N, 100, 30, 2, 100); _put(st, 1, 2, 0, S, 100, 30, 2, 100)
         _put(st, 2, 1, 3, W, 100, 30, 2, 100); _put(st, 3, 3, 2, N, 100, 30, 2, 100)
         return _hand_cfg(100), st, [ATK, 3, 3, 3]
+    if name == "narrow":        # a 2-wide torus: the square's two side columns are one; each cell struck once
+        cfg = wl.ecology_desc(eco=dict(HAND, attack_damage=50), width=2, height=5, n_agents_init=0, capacity=4,
+                              window=1, hidden1=32, hidden2=32, resource_density=0.0, regrow_prob=0.0, seed=1,
+                              e_eat=10, e_cost=1, e_repro=200, e_child=50, attack_enabled=1)
+        st = empty_state(2, 5, 4, ecology=True, uid_next=100)
+        for slot, (x, y) in enumerate([(0, 4), (1, 2), (0, 0)]):
+            place(st, 2, slot, x, y, N, 100)
+            st["water"][slot], st["biomass"][slot], st["hp"][slot] = 30, 2, 100
+        return cfg, st, [ATK, 0, 0, 0]
     if name == "wall":          # a wall does not shield (no line of sight)
         _put(st, 0, 2, 4, N, 100, 30, 2, 100); _put(st, 1, 2, 1, N, 100, 30, 2, 100)
         st["wall"][3 * 6 + 2] = 1
@@ -71,7 +82,7 @@ def _case(name):
     raise ValueError(name)
 
 
-@pytest.mark.parametrize("case", ["full", "half", "quarter", "moves", "wall"])
+@pytest.mark.parametrize("case", ["full", "half", "quarter", "moves", "wall", "narrow"])
 def test_hand_built(eco, case):
     cfg, st, acts = _case(case)
     ow, gw = orc.OracleWorld(cfg), eco.World(cfg)
@@ -84,7 +95,9 @@ def test_hand_built(eco, case):
     gw.step_with_actions(a)
     assert_same_state(gw.read_state(), ow.state(), case)
     assert_stats_match(gw.stats()[0], ow.stats(), case)
-    assert gw.stats()[0]["killed"] >= 1 and gw.stats()[0]["action_hist"][ATK] >= 1
+    assert gw.stats()[0]["killed"] >= (case != "narrow") and gw.stats()[0]["action_hist"][ATK] >= 1
+    if case == "narrow":
+        assert gw.read_state()["hp"][1] == 60   # one half-strength strike, then healing
     gl = gw.read_logits()
     assert gl.shape == (4, 9)
     live = ~np.isnan(lo[:, 0])

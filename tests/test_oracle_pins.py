@@ -844,6 +844,23 @@ def test_H4_moves_resolve_before_the_strikes():
     assert out["occ"][cidx(2, 1)] == -1 and out["occ"][cidx(3, 1)] == -1 and out["occ"][cidx(2, 0)] == -1
 
 
+def test_H6_each_distinct_cell_struck_once_on_a_narrow_torus():
+    """On a 2-wide torus the square's columns x - 1 and x + 1 are one column: the
+    attacker still strikes each distinct cell once (one half-strength strike, not
+    two, so the agent survives and heals)."""
+    cfg = tiny_cfg(width=2, height=5, capacity=4, window=1, n_actions=9, attack_enabled=1, n_scalars=8,
+                   flags=orc.ECOLOGY, eco=dict(ECO_HAND, attack_damage=50), e_eat=10, e_cost=1, e_repro=200,
+                   e_child=50)
+    st = empty_state(2, 5, 4, ecology=True)
+    for slot, (x, y) in enumerate([(0, 4), (1, 2), (0, 0)]):
+        place(st, 2, slot, x, y, N, 100)
+        st["water"][slot], st["biomass"][slot], st["hp"][slot] = 30, 2, 100
+    out, s = run_both(cfg, st, [ATK9, 0, 0, 0])
+    assert s["deaths"] == 0 and s["killed"] == 0
+    assert (out["hp"][1], out["energy"][1], out["water"][1]) == (60, 98, 27)   # 100 - 50, healed 10 for 1 energy
+    assert (out["hp"][2], out["energy"][2]) == (100, 99)                      # row 0 lies outside rows 1..3
+
+
 def test_H5_nine_actions_and_attack_go_together_in_the_ecology():
     base = eco_atk_cfg(100)
     for bad in (dict(n_actions=8), dict(attack_enabled=0), dict(eco=dict(ECO_HAND, attack_damage=-1))):
