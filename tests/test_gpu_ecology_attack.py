@@ -222,6 +222,39 @@ def test_conservation_free_running_full_size(eco):
     gw.close()
 
 
+def test_long_run_half_strength(eco):
+    """The 65,536-agent ecology with half-strength attacks free-running for 300
+    steps (the policies' own actions, births mutating the nine-logit heads), with
+    no energy or water costs and no overspend or age damage, so that strikes are
+    the only harm and the population lives on (≈84k at its peak, ≈32k at the end,
+    ≈95k kills): every death is a kill; conservation and bookkeeping every step
+    from the statistics ring; the integer state's invariants at the end."""
+    e = dict(attack_damage=wl.ATTACK_HALF, e_cost_move=0, w_cost=0, hp_overspend=0, age_shift=31)
+    cfg = wl.ecology_desc(eco=e, width=1024, height=1024, n_agents_init=65536, capacity=131072, window=11,
+                          n_scalars=12, hidden1=64, hidden2=64, mutation_sigma=0.01, e_init=230, e_cost=0, seed=11,
+                          attack_enabled=1)
+    gw = eco.World(cfg)
+    s0 = gw.stats()[0]
+    gw.step(300)
+    hist = gw.stats_history(0, 301)
+    assert len(hist) == 301 and hist[-1]["step"] == 300
+    for prev, h in zip(hist, hist[1:]):
+        assert h["water_total"] == s0["water_total"] and h["biomass_total"] == s0["biomass_total"]
+        assert h["population"] == prev["population"] + h["births"] - h["deaths"]
+        assert h["killed"] == h["deaths"] and sum(h["action_hist"]) == prev["population"]
+    st = gw.read_state()
+    check_invariants(st, 1024, 1024)
+    live = st["alive"].astype(bool)
+    assert np.all((st["hp"][live] > 0) & (st["hp"][live] <= cfg["eco"]["hp_max"]))
+    assert int(st["cell_biomass"].sum()) + int(st["biomass"][live].sum()) == s0["biomass_total"]
+    kills = sum(h["killed"] for h in hist[1:])
+    births = sum(h["births"] for h in hist[1:])
+    say(f"ecology half-strength attack, 300 steps: population {hist[0]['population']} -> {hist[-1]['population']}, "
+        f"{births} births, {kills} kills")
+    assert kills > 10000 and births > 10000 and hist[-1]["population"] > 1000
+    gw.close()
+
+
 def test_errors(eco):
     e = dict(wl.ECOLOGY)
     for bad in [dict(n_actions=9, n_scalars=8, flags=8, eco=e),                          # nine without attack
