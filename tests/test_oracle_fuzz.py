@@ -5,7 +5,8 @@ temperature, colour vision, the three-resource ecology with or without attack
 at four strike strengths, terrain), random states
 written into both (agents, resources, walls, stomachs, health), random actions
 or the policies' own samples.  Every step both must give the same state,
-statistics and logits.  (CPU only.)"""
+statistics and logits.  (CPU only; a fixed, derandomized set of 100 worlds per
+run, so the suite's result does not depend on the run.)"""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -82,7 +83,8 @@ def worlds(draw):
     return cfg, s, acts, sampled
 
 
-@settings(max_examples=100, deadline=None, suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@settings(max_examples=100, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(worlds())
 def test_oracle_and_python_statement_agree(w):
     cfg, s, acts, sampled = w
