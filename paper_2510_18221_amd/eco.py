@@ -108,6 +108,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_18221_amd.build`")
+        try:   # torch's HIP runtime first, so that the library binds to the same one torch's memory comes from
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, U32, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
         L.eco_last_error.restype = ctypes.c_char_p
