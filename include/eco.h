@@ -89,7 +89,8 @@ typedef struct {
  * HP"), with the parameters of eco_world_desc.eco.  Cells hold water, energy and
  * biomass; agents carry the three in a capped stomach and have health.  Eight
  * actions: rest, turn left, turn right, forward, eat energy, eat water, eat
- * biomass, reproduce (n_actions = 8; no evolving temperature with it).  With
+ * biomass, reproduce (n_actions = 8; with ECO_DESC_EVOLVE_TEMPERATURE the log
+ * temperature follows the eight or nine output biases).  With
  * attack_enabled a ninth action, attack (index 8, n_actions = 9), strikes the
  * same 3x3 square as in the single-resource worlds, after the moves; an agent
  * on a cell struck k times loses k * attack_damage health in its health update

@@ -460,7 +460,6 @@ static int validate(const orc_desc* d) {
     if (d->flags & ORC_ECOLOGY) {
         const orc_ecology* e = &d->eco;
         if (d->n_actions != (d->attack_enabled ? 9u : 8u)) return fail("the ecology has eight actions (nine with attack)");
-        if (d->flags & ORC_EVOLVE_TEMPERATURE) return fail("the ecology runs without the evolving temperature");
         if (e->attack_damage < 0 || e->attack_damage > (1 << 20)) return fail("attack_damage outside [0, 2^20]");
         if ((d->flags & ORC_TERRAIN) && (e->terrain_scale < 1 || e->sea_level < 0 || e->sea_level > 32 ||
                                          e->water_per_depth < 0))

@@ -69,7 +69,8 @@ struct StepCounters {
 // BF16 storage: L1 [ceil(KB1/2)][H1][8] | b1[H1] | L2 [H1/8][H2][8] | b2[H2] | L3 [R3][H2] | b3[R3]
 // FP8 storage:  L1 [ceil(KB1/4)][H1][16] | L2 [H1/16][H2][16] | L3 [R3][H2] (bytes) |
 //               b1,b2,b3 FP32 | sc1[H1], sc2[H2], sc3[R3] FP32 per-row scales
-// R3 = 8 output rows, or 16 with a ninth action (rows 9..15 zero and never read).
+// R3 = 8 output rows, or 16 with a ninth row: a ninth action, or the log temperature
+// after eight (rows and bias slots beyond the head and the temperature are zero).
 // KB1 = D/4 (D = 4 S^2 + n_s is a multiple of 4).
 struct Layout {
   uint32_t D, S, R, ns, H1, H2, A, wdtype;
@@ -77,7 +78,7 @@ struct Layout {
   uint32_t temp;                // 1: log temperature stored after the output biases (b3[A])
   uint32_t colour;              // 1: colour trait and rendered colour window
   uint32_t ecology;             // 1: three-resource ecology (cell words of water / energy / biomass levels)
-  uint32_t R3;                  // output rows in the weight blocks: 8, or 16 when A = 9
+  uint32_t R3;                  // output rows in the weight blocks: 8, or 16 when A + temp > 8
   uint32_t P;                   // logical parameters (the log temperature included)
   uint32_t KB1;                 // FP32 16-byte blocks per L1 row
   uint32_t KBv;                 // storage 16-byte blocks per L1 row

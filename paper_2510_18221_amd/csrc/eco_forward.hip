@@ -260,7 +260,7 @@ __device__ __forceinline__ float output_layer(const W3<WDT, H2>& o, const float*
 template <int WDT, int H2>
 struct Row9 {
   uint32_t w[H2 == 128 ? 2 : 1];
-  uint32_t b, s;
+  uint32_t b, s, t;   // t: bias slot 9, the log temperature of a nine-action head
 };
 
 template <int WDT, int H2>
@@ -276,6 +276,7 @@ __device__ __forceinline__ void load_row9(const uint8_t* __restrict__ wbase, con
   }
   o.b = load_bias_raw<WDT>(wbase + L.s_b3, 8);
   o.s = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[8] : 0u;
+  o.t = (L.temp && L.A > 8) ? load_bias_raw<WDT>(wbase + L.s_b3, 9) : 0u;
 }
 
 template <int WDT, int H2>
@@ -477,8 +478,10 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
 template <int H, int U, bool WORDS>
 constexpr int kMinWavesPerSimd = (U == 16 && (H == 128 || WORDS)) ? 2 : 3;
 
-// NINE: the ecology with attack (a ninth action, its logit from ninth_logit); a
-// separate instantiation, so that the other kernels carry none of its code.
+// NINE: a ninth output row (the ecology with attack: a ninth action; with the
+// evolving temperature and eight actions: the log temperature), from
+// ninth_logit; a separate instantiation, so that the other kernels carry none of
+// its code.
 template <int WDT, int H, int U, bool WORDS, bool NINE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kMinWavesPerSimd<H, U, WORDS>)))
 void k_forward(Dev d, Layout L) {
@@ -552,14 +555,18 @@ void k_forward(Dev d, Layout L) {
     // one exponential per lane (lane 8a + g holds logit a), then gathered in order.
     // An evolving temperature tau = exp(theta_T) divides the logits; theta_T is the
     // stored parameter after the output biases, so logit A (a zero weight row plus
-    // that bias slot) equals it.  The largest logits weigh exactly 1.
-    float e_lane;
+    // that bias slot) equals it: one of the eight logits, the ninth one (the
+    // ecology's eight actions), or bias slot 9 itself (its nine).  The largest
+    // logits weigh exactly 1.
+    float e_lane, inv_tau = 1.0f;
     if (L.temp) {
       float lt = 0.0f;
 #pragma unroll
       for (int a = 0; a < 8; ++a)
         if (a == A) lt = l[a];
-      const float inv_tau = expf(-lt), x = lg - m;
+      if (NINE) lt = (A == 8) ? l8 : bias_of<WDT>(r9.t);
+      inv_tau = expf(-lt);
+      const float x = lg - m;
       e_lane = ((lane >> 3) < A) ? (x == 0.0f ? 1.0f : expf(x * inv_tau)) : 0.0f;
     } else {
       e_lane = ((lane >> 3) < A) ? expf(lg - m) : 0.0f;
@@ -571,8 +578,9 @@ void k_forward(Dev d, Layout L) {
       accum += wk[a];
       C[a] = accum;
     }
-    if (NINE) {
-      wk[8] = expf(l8 - m);
+    if (NINE) {   // the ninth action's weight (zero when logit 8 is the log temperature)
+      const float x8 = l8 - m;
+      wk[8] = (A > 8) ? (L.temp ? (x8 == 0.0f ? 1.0f : expf(x8 * inv_tau)) : expf(x8)) : 0.0f;
       C[8] = accum + wk[8];
     }
     const uint32_t x0 = draw32(wp, cur.local, cur.step, ST_ACTION);
@@ -661,7 +669,7 @@ namespace eco {
 #define ECO_CAT(a, b) ECO_CAT2(a, b)
 hipError_t ECO_CAT(launch_forward_w, ECO_FWD_WDT)(int H, int U, dim3 grid, dim3 block, size_t shmem,
                                                   hipStream_t s, const Dev& d, const Layout& L) {
-  const bool words = (L.colour | L.ecology) != 0, nine = L.A > 8;
+  const bool words = (L.colour | L.ecology) != 0, nine = L.A + L.temp > 8;
 #define ECO_CASE(HH, UU)                                                                                  \
   if (H == HH && U == UU) {                                                                               \
     if (nine) hipLaunchKernelGGL((k_forward<ECO_FWD_WDT, HH, UU, true, true>), grid, block, shmem, s, d, L);  \

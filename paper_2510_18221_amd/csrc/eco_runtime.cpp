@@ -192,8 +192,6 @@ eco_status check_desc(const eco_world_desc& d, uint32_t i) {
     const eco_ecology& e = d.eco;
     if (d.n_actions != (d.attack_enabled ? 9u : 8u))
       return bad(ECO_EINVAL, "n_actions", "must be 8 in the ecology (9 with attack)");
-    if (d.flags & ECO_DESC_EVOLVE_TEMPERATURE)
-      return bad(ECO_EINVAL, "flags", "the ecology runs without the evolving temperature");
     if (e.attack_damage < 0 || e.attack_damage > (1 << 20))
       return bad(ECO_EINVAL, "eco.attack_damage", "outside [0, 2^20]");
     if ((d.flags & ECO_DESC_TERRAIN) && (e.terrain_scale < 1 || e.sea_level < 0 || e.sea_level > 32 ||
@@ -237,7 +235,7 @@ void make_layout(const eco_world_desc& d, Layout& L, double& s1, double& s2, dou
   L.temp = (d.flags & ECO_DESC_EVOLVE_TEMPERATURE) ? 1u : 0u;
   L.colour = (d.flags & ECO_DESC_COLOUR_VISION) ? 1u : 0u;
   L.ecology = (d.flags & ECO_DESC_ECOLOGY) ? 1u : 0u;
-  L.R3 = (L.A > 8) ? 16u : 8u;
+  L.R3 = (L.A + L.temp > 8) ? 16u : 8u;   // output rows and bias slots, the log temperature included
   L.P = L.D * L.H1 + L.H1 + L.H1 * L.H2 + L.H2 + L.H2 * L.A + L.A + L.temp;
   L.p_w1 = 0;
   L.p_b1 = L.p_w1 + L.H1 * L.D;
@@ -505,7 +503,7 @@ eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {
     return st;
   }
   const int u = (int)w->launch.unroll, H = (int)w->L.H1;
-  const int mode = w->L.A > 8 ? 2 : ((w->L.colour | w->L.ecology) != 0 ? 1 : 0);
+  const int mode = w->L.A + w->L.temp > 8 ? 2 : ((w->L.colour | w->L.ecology) != 0 ? 1 : 0);
   const void* fwd = w->L.wdtype == 0   ? forward_kernel_w0(H, u, mode)
                     : w->L.wdtype == 1 ? forward_kernel_w1(H, u, mode)
                                        : forward_kernel_w2(H, u, mode);

@@ -42,7 +42,9 @@ def test_validation_errors_without_device():
                         (dict(window=17), eco.ECO_ENOTSUP), (dict(flags=32), eco.ECO_EINVAL),
                         (dict(n_actions=8), eco.ECO_EINVAL), (dict(flags=16), eco.ECO_EINVAL),
                         (dict(flags=8, n_actions=8, n_scalars=4, eco=wl.ECOLOGY), eco.ECO_EINVAL),
-                        (dict(flags=8 | 2, n_actions=8, n_scalars=8, eco=wl.ECOLOGY), eco.ECO_EINVAL),
+                        (dict(flags=8, n_actions=9, n_scalars=8, eco=wl.ECOLOGY), eco.ECO_EINVAL),
+                        (dict(flags=8, n_actions=9, n_scalars=8, attack_enabled=1,
+                              eco=dict(wl.ECOLOGY, attack_damage=-1)), eco.ECO_EINVAL),
                         (dict(flags=8 | 16, n_actions=8, n_scalars=8, eco=dict(wl.ECOLOGY, sea_level=40)),
                          eco.ECO_EINVAL),
                         (dict(flags=8, n_actions=8, n_scalars=8, eco=dict(wl.ECOLOGY, b_repro=0)), eco.ECO_EINVAL)]:

@@ -181,7 +181,7 @@ def test_conservation_free_running_full_size(eco):
 
 
 def test_ecology_errors(eco):
-    for bad in [dict(n_actions=8), dict(n_actions=8, n_scalars=8, flags=8 | 2, eco=wl.ECOLOGY),
+    for bad in [dict(n_actions=8),
                 dict(n_actions=8, n_scalars=8, flags=8, attack_enabled=1, eco=wl.ECOLOGY),
                 dict(n_actions=7, n_scalars=8, flags=8, eco=wl.ECOLOGY),
                 dict(n_actions=8, n_scalars=4, flags=8, eco=wl.ECOLOGY),

@@ -255,13 +255,29 @@ def test_long_run_half_strength(eco):
     gw.close()
 
 
+@pytest.mark.parametrize("attack,wdtype", [(0, 0), (0, 1), (1, 0), (1, 2)])
+def test_evolving_temperature(eco, attack, wdtype):
+    """The paper's evolving softmax temperature in the ecology: its parameter follows
+    the eight output biases (read as the ninth logit of a zero weight row) or the
+    nine (bias slot 9); births mutate it with the weights.  Seeded actions, then the
+    policies' own tempered samples."""
+    seed = 500 + 10 * attack + wdtype
+    cfg = _world(seed=seed, wdtype=wdtype, damage=50, flags=8 | 2)
+    if not attack:
+        cfg.update(attack_enabled=0, n_actions=8)
+    A = cfg["n_actions"]
+    acts = lambda t: wl.biased_actions(cfg["capacity"], A, seed, t, p_forward=0.3, p_eat=0.3, p_attack=0.1)
+    run_pair(eco, cfg, 12, actions_fn=acts, what=f"ecology temperature A={A} wdtype {wdtype}", every=3)
+    _, mism = run_pair(eco, dict(cfg, seed=seed + 1, e_init=260), 6, what=f"ecology temperature A={A} sampled")
+    assert mism <= 3
+
+
 def test_errors(eco):
     e = dict(wl.ECOLOGY)
     for bad in [dict(n_actions=9, n_scalars=8, flags=8, eco=e),                          # nine without attack
                 dict(n_actions=9, n_scalars=8, attack_enabled=1),                         # nine without the ecology
                 dict(n_actions=8, n_scalars=8, flags=8, attack_enabled=1, eco=e),         # attack needs nine
-                dict(n_actions=9, n_scalars=8, flags=8, attack_enabled=1, eco=dict(e, attack_damage=-1)),
-                dict(n_actions=9, n_scalars=8, flags=8 | 2, attack_enabled=1, eco=e)]:     # no evolving temperature
+                dict(n_actions=9, n_scalars=8, flags=8, attack_enabled=1, eco=dict(e, attack_damage=-1))]:
         with pytest.raises(eco.EcoError) as err:
             eco.World(wl.desc(**bad))
         assert err.value.status == eco.ECO_EINVAL, bad

@@ -33,6 +33,8 @@ def worlds(draw):
     if draw(st.booleans()):
         flags |= orc.COLOUR_VISION
     attack = 0
+    if draw(st.booleans()):
+        flags |= orc.EVOLVE_TEMPERATURE
     if ecology:
         flags |= orc.ECOLOGY
         if draw(st.booleans()):
@@ -40,8 +42,6 @@ def worlds(draw):
         attack = int(draw(st.booleans()))
         n_actions, n_scalars = 8 + attack, draw(st.sampled_from([8, 12]))
     else:
-        if draw(st.booleans()):
-            flags |= orc.EVOLVE_TEMPERATURE
         n_actions = draw(st.sampled_from([5, 7]))
         attack = int(n_actions == 7 and draw(st.booleans()))
         n_scalars = draw(st.sampled_from([4, 8]))

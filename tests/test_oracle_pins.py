@@ -954,9 +954,12 @@ def test_ecology_observation_matches_numpy():
                                         (3, orc.ECOLOGY | orc.TERRAIN | orc.COLOUR_VISION),
                                         (4, orc.ECOLOGY | orc.COLOUR_VISION | orc.FRONT_VISION),
                                         (5, orc.ECOLOGY | orc.COLOUR_VISION | ATTACK_HALF),
-                                        (6, orc.ECOLOGY | orc.TERRAIN | ATTACK_FULL)])
+                                        (6, orc.ECOLOGY | orc.TERRAIN | ATTACK_FULL),
+                                        (7, orc.ECOLOGY | orc.EVOLVE_TEMPERATURE),
+                                        (8, orc.ECOLOGY | orc.EVOLVE_TEMPERATURE | orc.COLOUR_VISION | ATTACK_HALF)])
 def test_ecology_oracle_matches_spec(seed, flags):
-    """The policies' own samples; with attack (nine actions) at half or full strength."""
+    """The policies' own samples; with attack (nine actions) at half or full strength;
+    with the evolving temperature (its parameter after the eight or nine output biases)."""
     damage = {ATTACK_HALF: 50, ATTACK_FULL: 100}.get(flags & (ATTACK_HALF | ATTACK_FULL), 0)
     flags &= ~(ATTACK_HALF | ATTACK_FULL)
     cfg = _eco_run_cfg(seed, flags=flags)
