@@ -318,8 +318,10 @@ def main():
         # the paper's vision agent (RCV) in a world with terrain: a 7x7 window of rendered colour and
         # elevation difference, the compass, the ecology with water flowing downhill (208->64->64->8)
         terrain_cfg = dict(ecology_cfg, window=7, flags=eco.DESC_ECOLOGY | eco.DESC_TERRAIN | eco.DESC_COLOUR_VISION)
-        # the paper's "Ocean" agent (RCV+A): the same, with full-strength attacks as a ninth action (208->64->64->9)
-        ocean_cfg = dict(terrain_cfg, n_actions=9, attack_enabled=1)
+        # the paper's "Ocean" agent (RCV+A): the same, with full-strength attacks as a ninth action and the
+        # paper's evolving softmax temperature (208->64->64->9, + log tau)
+        ocean_cfg = dict(terrain_cfg, n_actions=9, attack_enabled=1,
+                         flags=terrain_cfg["flags"] | eco.DESC_EVOLVE_TEMPERATURE)
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
