@@ -26,7 +26,8 @@ measures: attacks per agent and homicides per attack), the same world with the
 paper's own policy options (evolving softmax temperature, colour trait rendered
 into the windows), the same grid and population in the three-resource ecology
 with health, and with terrain and the paper's 7x7 colour window (with and
-without full-strength attacks), a per-kernel breakdown from a few eager steps,
+without full-strength attacks; the latter also with its population held at 65,536), a per-kernel
+breakdown from a few eager steps,
 and the CPU oracle on a bounded sample.
 """
 import argparse
@@ -322,6 +323,11 @@ def main():
         # paper's evolving softmax temperature (208->64->64->9, + log tau)
         ocean_cfg = dict(terrain_cfg, n_actions=9, attack_enabled=1,
                          flags=terrain_cfg["flags"] | eco.DESC_EVOLVE_TEMPERATURE)
+        # the same agent with the population held at 65,536 (no costs, no births, harmless strikes: the same
+        # kernels, their cost at full size)
+        ocean_held_cfg = dict(ocean_cfg, e_cost=0, e_repro=1 << 30,
+                              eco=dict(ocean_cfg["eco"], e_cost_move=0, w_cost=0, hp_overspend=0, age_shift=31,
+                                       attack_damage=0))
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
@@ -329,7 +335,8 @@ def main():
                            ("fp32_temperature_colour", paper_cfg),
                            ("fp32_ecology", ecology_cfg),
                            ("fp32_terrain_rcv_7x7", terrain_cfg),
-                           ("fp32_terrain_rcv_a_7x7", ocean_cfg)]:
+                           ("fp32_terrain_rcv_a_7x7", ocean_cfg),
+                           ("fp32_terrain_rcv_a_7x7_held", ocean_held_cfg)]:
             log(f"[bench] variant {name}")
             r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
             v = r["agent_steps"] / r["seconds"]
