@@ -239,12 +239,19 @@ typedef struct {
 /* Create n_worlds worlds (all with the same window, n_scalars, hidden sizes,
  * n_actions and wdtype) and run the deterministic init of Sec. 3.3 / placement.
  * hip_stream: a hipStream_t or NULL.  alloc: NULL = hipMalloc/hipFree.
+ * descs[n_worlds] is copied (the caller keeps ownership); *out receives the new
+ * object, owned by the caller until eco_world_destroy.  The object's device
+ * memory comes from alloc (or hipMalloc) and stays with the object.
  * Errors: EINVAL (bad desc, with the field named; attack_enabled other than
- * 0/1, or 1 with n_actions = 5), ENOTSUP (sizes without a kernel), ENOMEM,
- * EDEVICE. */
+ * 0/1, or 1 without n_actions = 7, 9 in the ecology), ENOTSUP (sizes without a
+ * kernel), ENOMEM, EDEVICE (no current HIP device); *out is untouched then. */
 eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void* hip_stream,
                             const eco_allocator* alloc, eco_world** out);
+/* Wait for the object's stream, then release its graphs, events, streams and
+ * device memory.  NULL is ignored. */
 void eco_world_destroy(eco_world* w);
+/* Text of the last error of the calling thread ("" if none); valid until the
+ * thread's next failing call. */
 const char* eco_last_error(void);
 
 /* Advance every world by n_steps whole steps (asynchronous, except that
@@ -267,8 +274,12 @@ eco_status eco_world_stats(eco_world* w, eco_stats* out, uint32_t max_worlds);
 eco_status eco_world_stats_history(eco_world* w, uint32_t world, eco_stats* out,
                                    uint32_t max_records, uint32_t* n_out);
 
+/* Static facts of the object (sizes, bytes per agent; eco_info above). */
 eco_status eco_world_info(const eco_world* w, eco_info* out);
+/* Runtime flags (ECO_RT_*); unknown bits: EINVAL.  Drops the built graphs. */
 eco_status eco_world_set_flags(eco_world* w, uint32_t flags);
+/* Policy-kernel launch shape; shapes outside the documented ranges: EINVAL.
+ * Every shape gives bit-identical results.  Drops the built graphs. */
 eco_status eco_world_set_launch(eco_world* w, const eco_launch* launch);
 eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
 /* Time every candidate launch shape on the forward pass of the current state
@@ -277,6 +288,8 @@ eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
  * eleven rounds, and keep the shape with the lowest mean of the second pass.
  * Every candidate produces bit-identical actions.  *best may be NULL. */
 eco_status eco_world_autotune(eco_world* w, eco_launch* best);
+/* Accumulated per-kernel-group times of the steps run with ECO_RT_TIME_KERNELS
+ * (milliseconds and launch counts); reset != 0 zeroes them after reading. */
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);
 
 /* Measurement helper, not part of the step: the device's streaming-read rate.
