@@ -100,8 +100,12 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None):
     res["timing_region"] = dict(seconds=u1 - u0, **run_history(w, steps, s1 + steps))
     # per-kernel breakdown: a few eager steps with events around every kernel group
     w.set_flags(eco.RT_TIME_KERNELS)
-    w.step(min(steps, 10))
+    n_eager = min(steps, 10)
+    s2 = w.stats()[0]["step"]
+    w.step(n_eager)
     res["kernel_times_eager"] = w.kernel_times(reset=True)
+    res["eager"] = run_history(w, n_eager, s2 + n_eager)
+    res["eager"]["steps"] = n_eager
     w.close()
     torch.cuda.empty_cache()
     return res
@@ -178,6 +182,24 @@ def roofline(r, profile_name=None):
             "frac_of_measured_ceiling": round(gbs / READ_CEILING["gbps"], 4) if READ_CEILING.get("gbps") else None}
 
 
+def birth_roofline(r):
+    """The birth-commit kernel over the eager steps (HIP events around each launch):
+    algorithmic bytes per birth = the parent's FP32 master read (4P), the child's
+    master written (4P) and, when the storage is a separate BF16 / FP8 copy, that
+    copy written (the per-agent weight bytes of the forward)."""
+    ms, n = r["kernel_times_eager"]["birth_commit"]
+    births = r["eager"]["births"]
+    info = r["info"]
+    P = info["param_count"]
+    per_birth = 8 * P + (info["weight_bytes_per_agent"] if info["wdtype"] != 0 else 0)
+    avg_ms = ms / max(n, 1)
+    per_launch = births / max(n, 1)
+    gbs = per_launch * per_birth / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_birth_commit", "births_per_launch": round(per_launch, 1),
+            "bytes_per_birth": per_birth, "avg_launch_ms": round(avg_ms, 4), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -232,12 +254,22 @@ WORKLOADS = {
               "15x15x4 window + 8 scalars, 908->128->128->7 BF16 weights + FP32 master", "bf16"),
     "small": ("single world 64x64 torus, 256 agents at start, capacity 4,096, density 0.1, regrowth 0.01, "
               "5x5x4 window + 4 scalars, 104->32->32->5 FP32 weights (cache-resident: a latency test)", "f32"),
+    "turnover": ("single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, 11x11x4 window + 8 "
+                 "scalars, per-agent 492->64->64->7 MLP, FP32 weights; no step cost and no transfer to the "
+                 "child (every agent at the reproduction threshold, children born with zero energy die at "
+                 "their first step): a steady stream of ~9k births with mutation and as many deaths per step",
+                 "f32"),
 }
+# the turnover world's changes to the 65k world's energies
+TURNOVER = dict(e_init=200, e_cost=0, e_child=0)
 
 
 def workload_cfg(wl, name, wdtype=None):
+    wdt = {None: wl.FP32, "f32": wl.FP32, "bf16": wl.BF16, "fp8": wl.FP8}[wdtype]
     if name == "65k":
-        return wl.world_65k(seed=0, wdtype={None: wl.FP32, "f32": wl.FP32, "bf16": wl.BF16, "fp8": wl.FP8}[wdtype])
+        return wl.world_65k(seed=0, wdtype=wdt)
+    if name == "turnover":
+        return dict(wl.world_65k(seed=0, wdtype=wdt), **TURNOVER)
     if name == "batch":
         return wl.world_batch(64)
     if name == "small":
@@ -290,7 +322,7 @@ def main():
     log(f"[bench] {args.workload}: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, "
         f"launch {main_r['launch']}")
     desc, dtype = WORKLOADS[args.workload]
-    if args.workload == "65k" and args.wdtype in ("bf16", "fp8"):
+    if args.workload in ("65k", "turnover") and args.wdtype in ("bf16", "fp8"):
         desc = desc.replace("FP32 weights", {"bf16": "BF16 weights + FP32 master",
                                              "fp8": "FP8-E4M3 weights + row scales + FP32 master"}[args.wdtype])
         dtype = args.wdtype
@@ -308,6 +340,9 @@ def main():
         "kernel_ms_per_step_eager": {k: round(v[0] / max(v[1], 1), 4)
                                      for k, v in main_r["kernel_times_eager"].items()},
     }
+    if args.workload == "turnover":
+        out["config"]["births_deaths"] = [main_r["births"], main_r["deaths"]]
+        out["birth_roofline"] = birth_roofline(main_r)
     if args.workload == "65k" and not args.no_variants:
         variants = {}
         attack_cfg = dict(wl.world_65k(seed=0), attack_enabled=1)
@@ -328,7 +363,14 @@ def main():
         ocean_held_cfg = dict(ocean_cfg, e_cost=0, e_repro=1 << 30,
                               eco=dict(ocean_cfg["eco"], e_cost_move=0, w_cost=0, hp_overspend=0, age_shift=31,
                                        attack_damage=0))
+        # a steady birth stream at ~65k agents: no step cost and no transfer, so every agent stays at
+        # the reproduction threshold and a parent needs only the REPRODUCE action and a free cell behind
+        # it; children start with zero energy and die at their first step, so ~9k births with mutation
+        # into recycled slots and as many deaths happen every step
+        turnover = TURNOVER
         for name, vcfg in [("bf16", wl.world_65k(seed=0, wdtype=wl.BF16)),
+                           ("fp32_turnover", dict(wl.world_65k(seed=0), **turnover)),
+                           ("bf16_turnover", dict(wl.world_65k(seed=0, wdtype=wl.BF16), **turnover)),
                            ("fp8", wl.world_65k(seed=0, wdtype=wl.FP8)),
                            ("fp32_frozen", wl.world_65k(seed=0, frozen=True)),
                            ("fp32_attack", attack_cfg),
@@ -344,8 +386,9 @@ def main():
                               "roofline": roofline(r, {"bf16": "65k_bf16", "fp8": "65k_fp8"}.get(name)),
                               "agents_start": r["pop_start"], "agents_end": r["pop_end"],
                               "launch": r["launch"]}
-            if vcfg.get("flags", 0) & eco.DESC_ECOLOGY:
+            if vcfg.get("flags", 0) & eco.DESC_ECOLOGY or name.endswith("turnover"):
                 variants[name]["births_deaths"] = [r["births"], r["deaths"]]
+                variants[name]["birth_roofline"] = birth_roofline(r)
             if vcfg.get("attack_enabled"):
                 # the predation measures of the paper's Table 3 over the timed steps
                 variants[name]["attacks_per_agent"] = round(r["attacks"] / max(r["agent_steps"], 1), 4)

@@ -151,12 +151,12 @@ struct TileScratch {
   const uint32_t* tile_rng;
   uint32_t n_slot_tiles, n_cell_tiles;
   uint32_t* part_slot;   // [slot tiles][16] step counters (actions, moves, meals, deaths, blocked births)
-  uint32_t* part_cell;   // [cell tiles][4] regrown, resource total (ecology: energy), water, biomass
+  unsigned long long* part_cell;   // [cell tiles][4] regrown, resource total (ecology: energy), water, biomass
   uint32_t* scan;        // [slot tiles][4] claims, winners, free slots, live slots
   long long* esum;       // [slot tiles] energy sum of live slots
   unsigned long long* ecosum;  // [slot tiles][3] ecology: water, biomass, health of live slots
-  double* tsum;          // [slot tiles] trait sum
-  double* tsq;           // [slot tiles] trait sum of squares
+  double* tmean;         // [slot tiles] mean of the live slots' traits
+  double* tm2;           // [slot tiles] sum of squared deviations from that mean
 };
 
 // ---------------------------------------------------------------------------

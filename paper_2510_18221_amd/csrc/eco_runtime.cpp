@@ -93,7 +93,7 @@ struct eco_world {
   Tile* cell_tiles = nullptr;
   uint32_t n_slot_tiles = 0, n_cell_tiles = 0;
   uint32_t* part_slot = nullptr;
-  uint32_t* part_cell = nullptr;
+  unsigned long long* part_cell = nullptr;
   uint32_t* tile_rng = nullptr;
   TileScratch ts{};
   void* sort_tmp = nullptr;
@@ -744,7 +744,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   w->slot_tiles = (Tile*)A(sizeof(Tile) * std::max<size_t>(1, w->slot_tiles_h.size()));
   w->cell_tiles = (Tile*)A(sizeof(Tile) * std::max<size_t>(1, w->cell_tiles_h.size()));
   w->part_slot = (uint32_t*)A(4ull * kSlotPartH * std::max(1u, w->n_slot_tiles));
-  w->part_cell = (uint32_t*)A(4ull * kCellPartH * std::max(1u, w->n_cell_tiles));
+  w->part_cell = (unsigned long long*)A(8ull * kCellPartH * std::max(1u, w->n_cell_tiles));
   w->tile_rng = (uint32_t*)A(4ull * w->tile_rng_h.size());
   {
     const uint64_t T = std::max(1u, w->n_slot_tiles);
@@ -759,8 +759,8 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     ts.scan = (uint32_t*)A(16 * T);
     ts.esum = (long long*)A(8 * T);
     ts.ecosum = w->L.ecology ? (unsigned long long*)A(3 * 8 * T) : nullptr;
-    ts.tsum = (double*)A(8 * T);
-    ts.tsq = (double*)A(8 * T);
+    ts.tmean = (double*)A(8 * T);
+    ts.tm2 = (double*)A(8 * T);
   }
   w->emit_list = (uint32_t*)A(8 * TS);
   if (ok && sort_keys_temp_bytes(max_cells, &w->sort_tmp_bytes) != hipSuccess) ok = false;
@@ -794,7 +794,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   chk(hipMemsetAsync(d.sampled, 0xFF, TS, s), "clear sampled");
   chk(hipMemsetAsync(d.act_in, 0, TS, s), "clear act_in");
   chk(hipMemsetAsync(w->part_slot, 0, 4ull * kSlotPartH * std::max(1u, w->n_slot_tiles), s), "clear partials");
-  chk(hipMemsetAsync(w->part_cell, 0, 4ull * kCellPartH * std::max(1u, w->n_cell_tiles), s), "clear partials");
+  chk(hipMemsetAsync(w->part_cell, 0, 8ull * kCellPartH * std::max(1u, w->n_cell_tiles), s), "clear partials");
   chk(hipMemsetAsync(d.cnt, 0, sizeof(StepCounters) * n_worlds, s), "clear counters");
   if (d.ep) {
     std::vector<eco_ecology> ep(n_worlds);

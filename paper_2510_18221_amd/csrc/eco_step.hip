@@ -24,7 +24,7 @@ constexpr int kSlotTile = 256;   // slots per block in per-slot kernels
 // Cell tiles (1024 cells each) are built on the host; per-cell kernels take one tile per block.
 constexpr int kScanThreads = 1024;
 constexpr int kSlotPart = 16;    // u32 counters per slot tile
-constexpr int kCellPart = 4;     // u32 counters per cell tile
+constexpr int kCellPart = 4;     // u64 counters per cell tile
 
 // Per-slot-tile counters (index in the partials row).
 enum { PC_HIST = 0, PC_MOVES_OK = 9, PC_MOVES_BLOCKED = 10, PC_EATEN = 11, PC_DEATHS = 12, PC_BB_CELL = 13,
@@ -450,32 +450,48 @@ __device__ __forceinline__ void birth_claim_tile(const Dev& d, const TileScratch
   if (threadIdx.x == 0) ts.part_slot[tile * kSlotPart + PC_BB_CELL] = *blocked;
 }
 
-__device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile, uint32_t* cnt) {
+// floor(min(1, rate * b) * 2^32) in exact integer arithmetic, for a finite rate >= 0
+// and b >= 1: rate = M 2^E with an integer M < 2^24, so rate * b * 2^32 is the
+// integer M b (< 2^55) scaled by 2^(E + 32), floored.
+__device__ __forceinline__ uint64_t photo_threshold(float rate, int b) {
+  const uint32_t u = __float_as_uint(rate);
+  const uint32_t ex = (u >> 23) & 0xFFu;
+  const uint64_t M = ex ? ((u & 0x7FFFFFu) | 0x800000u) : (u & 0x7FFFFFu);
+  const int k = (ex ? (int)ex - 150 : -149) + 32;   // rate = M 2^(k - 32)
+  const uint64_t mb = M * (uint64_t)(uint32_t)b;
+  constexpr uint64_t one = 1ull << 32;
+  if (mb == 0) return 0;
+  if (k >= 0) return (k >= 32 || mb >= (one >> k)) ? one : (mb << k);
+  if (k <= -64) return 0;
+  const uint64_t v = mb >> (-k);
+  return v > one ? one : v;
+}
+
+__device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile,
+                                            unsigned long long* cnt) {
   const Tile tl = ts.cell_tiles[tile];
   const WorldParams wp = d.wp[tl.world];
   const uint32_t step = (uint32_t)d.wv[tl.world].step;
-  uint32_t grown = 0, total = 0;
+  unsigned long long grown = 0, total = 0;
   if (d.ep) {
     // ecology: photosynthesis, one energy unit with probability min(1, rate * biomass)
-    // on cells holding biomass below the energy ceiling (rate * biomass exact in FP64);
-    // the tile's grid totals of energy, water and biomass for the statistics
+    // on cells holding biomass below the energy ceiling (the threshold in exact
+    // integers); the tile's grid totals of energy, water and biomass for the statistics
     const eco_ecology& e = d.ep[tl.world];
-    uint32_t wsum = 0, bsum = 0;
+    unsigned long long wsum = 0, bsum = 0;
     for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
       const uint32_t c = tl.start + i, g = wp.cell_off + c;
       const int b = d.cb[g];
       int en = d.ce[g];
       if (b > 0 && en < e.cell_energy_max) {
-        const double p = (double)e.photo_rate * (double)b;
-        const uint64_t thr = p >= 1.0 ? (1ull << 32) : (uint64_t)floor(p * 4294967296.0);
-        if ((uint64_t)draw32(wp, c, step, ST_REGROW) < thr) {
+        if ((uint64_t)draw32(wp, c, step, ST_REGROW) < photo_threshold(e.photo_rate, b)) {
           d.ce[g] = ++en;
           ++grown;
         }
       }
-      total += (uint32_t)en;
-      wsum += (uint32_t)d.cw[g];
-      bsum += (uint32_t)b;
+      total += (unsigned long long)(uint32_t)en;
+      wsum += (unsigned long long)(uint32_t)d.cw[g];
+      bsum += (unsigned long long)(uint32_t)b;
       if (wp.attack) d.mark[g] = 0;   // the strikes of this step have been counted
     }
     if (d.rock) {
@@ -519,10 +535,12 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
 }
 
 __global__ __launch_bounds__(256) void k_birth_claim_regrow(Dev d, TileScratch ts, uint32_t n_actions) {
-  __shared__ uint32_t cnt[kCellPart];
+  __shared__ uint32_t blocked;
+  __shared__ unsigned long long cnt[kCellPart];
+  if (threadIdx.x == 0) blocked = 0;
   if (threadIdx.x < kCellPart) cnt[threadIdx.x] = 0;
   __syncthreads();
-  if (blockIdx.x < ts.n_slot_tiles) birth_claim_tile(d, ts, blockIdx.x, n_actions, &cnt[0]);
+  if (blockIdx.x < ts.n_slot_tiles) birth_claim_tile(d, ts, blockIdx.x, n_actions, &blocked);
   else regrow_tile(d, ts, blockIdx.x - ts.n_slot_tiles, cnt);
 }
 
@@ -675,10 +693,52 @@ __global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
   }
 }
 
-// Compaction, pass 1 (slot tiles): live count, energy sum, trait sums of the tile.
+// Trait moments of a group of agents: count, mean and the sum of squared
+// deviations from that mean.  Two groups combine by the pairwise update of
+// Chan, Golub and LeVeque (1979): with delta = mean_b - mean_a and n = n_a + n_b,
+// mean = mean_a + delta n_b / n and M2 = M2_a + M2_b + delta^2 n_a n_b / n, which
+// never subtracts two large sums (the variance of the whole is M2 / n).
+struct Moments {
+  double n, mean, m2;
+};
+
+__device__ __forceinline__ Moments merge_moments(const Moments& a, const Moments& b) {
+  if (b.n == 0.0) return a;
+  if (a.n == 0.0) return b;
+  const double n = a.n + b.n, delta = b.mean - a.mean;
+  return Moments{n, a.mean + delta * (b.n / n), a.m2 + b.m2 + delta * delta * (a.n * b.n / n)};
+}
+
+// Merge of one Moments per thread over the block, in a fixed order (a tree within
+// each wave, then the waves in order); the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ Moments block_merge_moments(Moments m, double (*red)[3]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const Moments o{__shfl_down(m.n, d), __shfl_down(m.mean, d), __shfl_down(m.m2, d)};
+    if (lane < d) m = merge_moments(m, o);
+  }
+  if (lane == 0) {
+    red[wave][0] = m.n;
+    red[wave][1] = m.mean;
+    red[wave][2] = m.m2;
+  }
+  __syncthreads();
+  Moments t{0.0, 0.0, 0.0};
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) t = merge_moments(t, Moments{red[i][0], red[i][1], red[i][2]});
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// Compaction, pass 1 (slot tiles): live count, energy sum and the trait moments of
+// the tile (its mean, then the squared deviations from it: two passes over the
+// tile's values, which stay in registers).
 __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch ts, int only_world) {
   __shared__ unsigned long long red64[kSlotTile / 64];
   __shared__ double redf[kSlotTile / 64];
+  __shared__ double bcastf;
   const Tile tl = ts.slot_tiles[blockIdx.x];
   if (only_world >= 0 && (int)tl.world != only_world) return;
   const WorldParams wp = d.wp[tl.world];
@@ -696,7 +756,11 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch 
   const unsigned long long n = block_sum_u64<kSlotTile>(alive ? 1ull : 0ull, red64);
   const unsigned long long es = block_sum_u64<kSlotTile>((unsigned long long)e, red64);
   const double s1 = block_sum_f64<kSlotTile>(t, redf);
-  const double s2 = block_sum_f64<kSlotTile>(t * t, redf);
+  if (threadIdx.x == 0) bcastf = n ? s1 / (double)n : 0.0;
+  __syncthreads();
+  const double tile_mean = bcastf;
+  const double dv = alive ? t - tile_mean : 0.0;
+  const double m2 = block_sum_f64<kSlotTile>(dv * dv, redf);
   if (d.ep) {   // ecology: water, biomass and health carried by the tile's live agents
     const uint32_t slot = wp.slot_off + tl.start + threadIdx.x;
     const bool on = alive && threadIdx.x < tl.count;
@@ -712,8 +776,8 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch 
   if (threadIdx.x == 0) {
     ts.scan[blockIdx.x * 4 + 3] = (uint32_t)n;
     ts.esum[blockIdx.x] = (long long)es;
-    ts.tsum[blockIdx.x] = s1;
-    ts.tsq[blockIdx.x] = s2;
+    ts.tmean[blockIdx.x] = tile_mean;
+    ts.tm2[blockIdx.x] = m2;
   }
 }
 
@@ -740,11 +804,18 @@ __device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d
 // Colour vision: the cell as others see it (occupant's colour, else a resource
 // unit in green, else a wall in grey, else black; 8 bits per channel), with the
 // cell's agent / resource / wall bits in the top byte for the move claim.
+// round(clamp(c, 0, 1) * 255) with ties up, in exact integer arithmetic: a c in
+// (0, 1) is M 2^-s with an integer M < 2^24 and s >= 24, so the result is
+// floor((255 M + 2^(s-1)) / 2^s).
 __device__ __forceinline__ uint32_t colour_byte(float c) {
-  double x = (double)c;
-  if (!(x > 0.0)) x = 0.0;
-  if (x > 1.0) x = 1.0;
-  return (uint32_t)floor(x * 255.0 + 0.5);   // exact in FP64
+  if (!(c > 0.0f)) return 0u;   // also NaN
+  if (c >= 1.0f) return 255u;
+  const uint32_t u = __float_as_uint(c);
+  const uint32_t ex = u >> 23;   // c > 0: sign bit clear
+  const uint64_t M = ex ? ((u & 0x7FFFFFu) | 0x800000u) : (u & 0x7FFFFFu);
+  const int s = ex ? 150 - (int)ex : 149;   // c = M 2^-s, s >= 24
+  if (s >= 64) return 0u;
+  return (uint32_t)((255ull * M + (1ull << (s - 1))) >> s);
 }
 
 __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
@@ -823,26 +894,25 @@ template <int NT>
 __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, int init) {
   __shared__ uint32_t red[NT / 64 + 1];
   __shared__ unsigned long long red64[NT / 64];
-  __shared__ double redf[NT / 64];
-  __shared__ uint32_t s_cnt[kSlotPart + kCellPart];
+  __shared__ double redm[NT / 64][3];
+  __shared__ unsigned long long s_cnt[kSlotPart + kCellPart];
   const uint32_t t0 = ts.tile_rng[4 * w], t1 = ts.tile_rng[4 * w + 1];
   const uint32_t nt = t1 - t0;
   const uint32_t per = (nt + NT - 1) / NT;
   const uint32_t lo = t0 + threadIdx.x * per, hi = min(lo + per, t1);
   uint32_t n = 0;
   long long es = 0;
-  double s1 = 0.0, s2 = 0.0;
+  Moments tm{0.0, 0.0, 0.0};   // the trait moments of this thread's tiles, merged in tile order
   for (uint32_t t = lo; t < hi; ++t) {
-    n += ts.scan[t * 4 + 3];
+    const uint32_t nl = ts.scan[t * 4 + 3];
+    n += nl;
     es += ts.esum[t];
-    s1 += ts.tsum[t];
-    s2 += ts.tsq[t];
+    tm = merge_moments(tm, Moments{(double)nl, ts.tmean[t], ts.tm2[t]});
   }
   uint32_t N;
   block_exscan<NT>(n, red, &N);
   const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
-  const double T1 = block_sum_f64<NT>(s1, redf);
-  const double T2 = block_sum_f64<NT>(s2, redf);
+  const Moments TM = block_merge_moments<NT>(tm, redm);
   unsigned long long eco_w = 0, eco_b = 0, eco_h = 0;   // ecology: carried water, biomass, health
   if (d.ep) {
     unsigned long long a = 0, b = 0, c = 0;
@@ -859,24 +929,36 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
   __syncthreads();
   if (!init) {
     // per-thread sums over its tiles, then wave sums, then one LDS add per wave
-    uint32_t c[kSlotPart + kCellPart];
+    // (slot counters count agents, below 2^31 per world; the grid totals are u64)
+    uint32_t c[kSlotPart];
+    unsigned long long cc[kCellPart];
 #pragma unroll
-    for (int k = 0; k < kSlotPart + kCellPart; ++k) c[k] = 0;
+    for (int k = 0; k < kSlotPart; ++k) c[k] = 0;
+#pragma unroll
+    for (int k = 0; k < kCellPart; ++k) cc[k] = 0;
     for (uint32_t t = lo; t < hi; ++t)
 #pragma unroll
       for (int k = 0; k < kSlotPart; ++k) c[k] += ts.part_slot[t * kSlotPart + k];
     const uint32_t ct0 = ts.tile_rng[4 * w + 2], ct1 = ts.tile_rng[4 * w + 3];
     for (uint32_t t = ct0 + threadIdx.x; t < ct1; t += NT)
 #pragma unroll
-      for (int k = 0; k < kCellPart; ++k) c[kSlotPart + k] += ts.part_cell[t * kCellPart + k];
+      for (int k = 0; k < kCellPart; ++k) cc[k] += ts.part_cell[t * kCellPart + k];
 #pragma unroll
-    for (int k = 0; k < kSlotPart + kCellPart; ++k) {
+    for (int k = 0; k < kSlotPart; ++k) {
 #pragma unroll
       for (int dd = 32; dd >= 1; dd >>= 1) c[k] += __shfl_xor(c[k], dd);
     }
-    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int k = 0; k < kSlotPart + kCellPart; ++k) atomicAdd(&s_cnt[k], c[k]);
+    for (int k = 0; k < kCellPart; ++k) {
+#pragma unroll
+      for (int dd = 32; dd >= 1; dd >>= 1) cc[k] += __shfl_xor(cc[k], dd);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < kSlotPart; ++k) atomicAdd(&s_cnt[k], (unsigned long long)c[k]);
+#pragma unroll
+      for (int k = 0; k < kCellPart; ++k) atomicAdd(&s_cnt[kSlotPart + k], cc[k]);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -902,13 +984,12 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
       }
     }
     if (d.ep) st.hp_total = eco_h;   // (init records get the grid parts from k_resource_total)
-    const double mean = N ? T1 / (double)N : 0.0;
     v.n_live = N;
     st.step = v.step;
     st.population = N;
     st.energy_total = (double)(long long)E;
-    st.trait_mean = mean;
-    st.trait_var = N ? fmax(T2 / (double)N - mean * mean, 0.0) : 0.0;
+    st.trait_mean = N ? TM.mean : 0.0;
+    st.trait_var = N ? TM.m2 / (double)N : 0.0;
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
 }
