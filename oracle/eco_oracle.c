@@ -92,19 +92,43 @@ static uint32_t draw_x0(const uint32_t key[2], uint32_t a, uint32_t step, uint32
     return out[0];
 }
 
+/* cos and sin of 2 pi j 2^-24 for 0 <= j < 2^24.  The whole quarter turns
+ * q = j >> 22 come off exactly; of the rest r (a fraction r 2^-22 of a quarter
+ * turn) libm gets the angle from the nearer end of the quarter, 2 pi r 2^-24 or
+ * its complement 2 pi (2^22 - r) 2^-24 (swapping cos and sin), so every
+ * argument lies in [0, pi/4], where cos and sin keep their relative accuracy,
+ * and the zeros at the quarter turns are exact. */
+void orc_cos_sin_2pi_u24(uint32_t j, double cs[2]) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const uint32_t q = (j >> 22) & 3u, r = j & 0x3FFFFFu;
+    double c, s;
+    if (r <= 0x200000u) {
+        const double th = two_pi * (double)r * 0x1p-24;
+        c = cos(th);
+        s = sin(th);
+    } else {
+        const double th = two_pi * (double)(0x400000u - r) * 0x1p-24;
+        c = sin(th);
+        s = cos(th);
+    }
+    /* a quarter turn maps (cos, sin) to (-sin, cos) */
+    cs[0] = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+    cs[1] = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+}
+
 /* Box-Muller on one Philox block: (x0,x1) -> z0,z1 and (x2,x3) -> z2,z3.
- * u1 = ((x>>8)+1) 2^-24 lies in (0,1] so log(u1) is finite; u2 = (y>>8) 2^-24. */
+ * u1 = ((x>>8)+1) 2^-24 lies in (0,1] so log(u1) is finite; u2 = (y>>8) 2^-24,
+ * and z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2). */
 void orc_gauss4(const uint32_t ctr[4], const uint32_t key[2], double z[4]) {
     uint32_t x[4];
     orc_philox4x32_10(ctr, key, x);
-    const double two_pi = 6.283185307179586476925286766559;
     for (int pair = 0; pair < 2; ++pair) {
         double u1 = (double)((x[2 * pair] >> 8) + 1u) * 0x1p-24;
-        double u2 = (double)(x[2 * pair + 1] >> 8) * 0x1p-24;
         double r = sqrt(-2.0 * log(u1));
-        double th = two_pi * u2;
-        z[2 * pair] = r * cos(th);
-        z[2 * pair + 1] = r * sin(th);
+        double cs[2];
+        orc_cos_sin_2pi_u24(x[2 * pair + 1] >> 8, cs);
+        z[2 * pair] = r * cs[0];
+        z[2 * pair + 1] = r * cs[1];
     }
 }
 

@@ -180,6 +180,7 @@ int orc_write_colour(orc_world* w, uint32_t slot, const float in[3]);
 /* Building blocks exposed for the pins. */
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void   orc_gauss4(const uint32_t ctr[4], const uint32_t key[2], double z[4]);
+void   orc_cos_sin_2pi_u24(uint32_t j, double cs[2]);   /* cos, sin of 2 pi j 2^-24 */
 uint16_t orc_bf16_rne(float x);
 uint8_t  orc_fp8e4m3_rne_sat(float x);
 double   orc_fp8e4m3_decode(uint8_t q);

@@ -88,6 +88,7 @@ def lib():
         _lib.orc_param_count.argtypes = [ctypes.POINTER(OrcDesc)]
         _lib.orc_philox4x32_10.argtypes = [P, P, P]
         _lib.orc_gauss4.argtypes = [P, P, P]
+        _lib.orc_cos_sin_2pi_u24.argtypes = [ctypes.c_uint32, P]
         _lib.orc_bf16_rne.restype = ctypes.c_uint16
         _lib.orc_bf16_rne.argtypes = [ctypes.c_float]
         _lib.orc_fp8e4m3_rne_sat.restype = ctypes.c_uint8
@@ -146,6 +147,12 @@ def gauss4(ctr, key):
     k = np.asarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.float64)
     lib().orc_gauss4(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def cos_sin_2pi_u24(j):
+    out = np.zeros(2, dtype=np.float64)
+    lib().orc_cos_sin_2pi_u24(int(j), _ptr(out))
     return out
 
 

@@ -65,14 +65,31 @@ def philox4x32_10(ctr, key):
     return x
 
 
+def cos_sin_2pi_u24(j):
+    """cos and sin of 2 pi j / 2^24: whole quarter turns removed exactly, the rest
+    measured from the nearer end of its quarter, so math.cos / math.sin only see
+    angles in [0, pi/4] and the quarter turns give exact zeros."""
+    q, r = (j >> 22) & 3, j & 0x3FFFFF
+    if r <= 0x200000:
+        th = 6.283185307179586 * r / 16777216.0
+        c, s = math.cos(th), math.sin(th)
+    else:
+        th = 6.283185307179586 * (0x400000 - r) / 16777216.0
+        c, s = math.sin(th), math.cos(th)
+    for _ in range(q):   # a quarter turn: (cos, sin) -> (-sin, cos)
+        c, s = -s, c
+    return c, s
+
+
 def gauss4(ctr, key):
+    """Box-Muller: z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) for two pairs of draws."""
     x = philox4x32_10(ctr, key)
     out = []
     for i in (0, 2):
         u1 = ((x[i] >> 8) + 1) / 16777216.0
-        u2 = (x[i + 1] >> 8) / 16777216.0
         r = math.sqrt(-2.0 * math.log(u1))
-        out += [r * math.cos(6.283185307179586 * u2), r * math.sin(6.283185307179586 * u2)]
+        c, s = cos_sin_2pi_u24(x[i + 1] >> 8)
+        out += [r * c, r * s]
     return out
 
 

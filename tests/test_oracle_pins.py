@@ -94,6 +94,59 @@ def test_gauss_moments_and_ks():
         np.testing.assert_allclose(a, b, rtol=1e-14, atol=1e-15)
 
 
+def _cos_sin_decimal(j):
+    """cos and sin of 2 pi j / 2^24 by their Taylor series in 50-digit decimal
+    arithmetic (pi from Machin's formula), the argument first reduced below pi/4
+    in magnitude by whole quarter turns, which are exact at this precision."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+
+    def arctan_inv(n):   # arctan(1/n) by its series, to 1e-55
+        x, t, k, total = Decimal(1) / n, Decimal(1) / n, 1, Decimal(0)
+        while t > Decimal(10) ** -55:
+            total += t / k if (k // 2) % 2 == 0 else -t / k
+            t *= x * x
+            k += 2
+        return total
+    pi = 16 * arctan_inv(5) - 4 * arctan_inv(239)
+    quarter = round(Decimal(4 * j) / Decimal(1 << 24))       # nearest whole quarter turn
+    x = 2 * pi * (Decimal(j) / Decimal(1 << 24) - Decimal(quarter) / 4)
+    c, s, term, k = Decimal(0), Decimal(0), Decimal(1), 0
+    while True:                                                # term = x^k / k!
+        if k % 4 == 0: c += term
+        elif k % 4 == 1: s += term
+        elif k % 4 == 2: c -= term
+        else: s -= term
+        k += 1
+        term = term * x / k
+        if abs(term) < Decimal(10) ** -45:
+            break
+    for _ in range(quarter % 4):                               # (cos, sin) -> (-sin, cos)
+        c, s = -s, c
+    return c, s
+
+
+def test_box_muller_angle_relative_accuracy_and_exact_quarter_turns():
+    """cos and sin of 2 pi u2 (u2 = j 2^-24) against a 50-digit evaluation,
+    relative to the value itself: within 2 double ulps everywhere, including next
+    to the zeros, and exactly 0 / +-1 at the quarter turns."""
+    from decimal import Decimal
+    rng = np.random.default_rng(5)
+    near = [k * (1 << 22) + d for k in range(4) for d in (-3, -2, -1, 1, 2, 3, 1 << 20, (1 << 21) + 1)]
+    js = np.concatenate([rng.integers(0, 1 << 24, 1500), np.array(near) % (1 << 24)])
+    for j in js:
+        cs = orc.cos_sin_2pi_u24(int(j))
+        for got, want in zip(cs, _cos_sin_decimal(int(j))):
+            err = abs(Decimal(float(got)) - want)
+            assert err <= 2 * Decimal(float(np.spacing(abs(float(want))))), (int(j), got, want)
+        # the Python statement: the same reduction through Python's libm calls (the C
+        # compiler may pair cos and sin into one sincos call, an ulp apart at times)
+        np.testing.assert_allclose(cs, spec.cos_sin_2pi_u24(int(j)), rtol=3e-16, atol=0)
+    for k, (c, s) in enumerate([(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)]):
+        got = orc.cos_sin_2pi_u24(k << 22)
+        assert got[0] == c and got[1] == s, (k, got)
+
+
 # ---------------------------------------------------------------------------
 # Number formats against torch's CPU casts
 # ---------------------------------------------------------------------------
