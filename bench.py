@@ -165,6 +165,27 @@ def profiled_traffic(name):
 
 
 READ_CEILING = {}  # measured once per run: the library's streaming-read probe
+COPY_CEILING = {}  # measured once per run: a device-to-device copy (half reads, half writes)
+
+
+def measure_copy_ceiling(nbytes=4 << 30, reps=5):
+    """Read + write bytes per second of torch's device copy of nbytes (best of reps),
+    the ceiling of a kernel whose traffic is half reads and half writes."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
 
 
 def roofline(r, profile_name=None):
@@ -195,9 +216,13 @@ def birth_roofline(r):
     avg_ms = ms / max(n, 1)
     per_launch = births / max(n, 1)
     gbs = per_launch * per_birth / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return {"bound": "hbm", "kernel": "k_birth_commit", "births_per_launch": round(per_launch, 1),
-            "bytes_per_birth": per_birth, "avg_launch_ms": round(avg_ms, 4), "achieved": round(gbs, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"bound": "hbm", "kernel": "k_birth_commit", "births_per_launch": round(per_launch, 1),
+           "bytes_per_birth": per_birth, "avg_launch_ms": round(avg_ms, 4), "achieved": round(gbs, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if COPY_CEILING.get("gbps"):
+        out["measured_copy_ceiling_GBps"] = COPY_CEILING["gbps"]
+        out["frac_of_measured_copy_ceiling"] = round(gbs / COPY_CEILING["gbps"], 4)
+    return out
 
 
 def cpu_model():
@@ -306,6 +331,9 @@ def main():
     eco.lib()
     READ_CEILING["gbps"] = round(max(eco.stream_read_gbps(8 << 30) for _ in range(3)), 1)
     log(f"[bench] streaming-read ceiling {READ_CEILING['gbps']} GB/s")
+    if args.workload in ("65k", "turnover"):
+        COPY_CEILING["gbps"] = round(measure_copy_ceiling(), 1)
+        log(f"[bench] device-copy ceiling {COPY_CEILING['gbps']} GB/s (reads + writes)")
 
     cfg = workload_cfg(wl, args.workload, args.wdtype)
     if args.trajectory:

@@ -244,7 +244,10 @@ typedef struct {
  * memory comes from alloc (or hipMalloc) and stays with the object.
  * Errors: EINVAL (bad desc, with the field named; attack_enabled other than
  * 0/1, or 1 without n_actions = 7, 9 in the ecology), ENOTSUP (sizes without a
- * kernel), ENOMEM, EDEVICE (no current HIP device); *out is untouched then. */
+ * kernel), ENOMEM (an allocation returned NULL; what was allocated before it is
+ * given back through alloc->free), EDEVICE (no current HIP device; with a
+ * caller allocator this is found after allocating, and the memory is given
+ * back).  *out is set to NULL first, so it is NULL after any error. */
 eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void* hip_stream,
                             const eco_allocator* alloc, eco_world** out);
 /* Wait for the object's stream, then release its graphs, events, streams and
@@ -263,8 +266,11 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps);
  * A later eco_world_set_flags or eco_world_set_launch drops the built graphs. */
 eco_status eco_world_prepare(eco_world* w, uint32_t n_steps);
 
-/* Re-initialise every world; seeds = NULL keeps each world's seed, else
- * seeds[n_worlds] replaces them.  Clears ECO_ESTATE on success. */
+/* Re-initialise every world (the init of Sec. 3.3 and the placement of
+ * Sec. 3.2: initial weights, positions, facings and resources, all from the
+ * world's seed); seeds = NULL keeps each world's seed, else seeds[n_worlds]
+ * replaces them.  Keeps the object's allocations and launch settings.  Clears
+ * ECO_ESTATE on success; a device error leaves the object in ECO_ESTATE. */
 eco_status eco_world_reset(eco_world* w, const uint64_t* seeds);
 
 /* Latest step's statistics of worlds 0..min(n_worlds, max_worlds)-1 (synchronises). */

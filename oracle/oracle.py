@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ECO_ORACLE_LIB: another build of the same source (the sanitizer test uses one)
+_LIB_PATH = os.environ.get("ECO_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 FP32, BF16, FP8 = 0, 1, 2
 REST, TURN_L, TURN_R, FORWARD, EAT, REPRODUCE, ATTACK = range(7)

@@ -29,7 +29,6 @@ def _units():
         units.append((os.path.join(CSRC, "eco_forward.hip"), os.path.join(OBJ, f"eco_forward_w{wdt}.o"),
                       DEVICE + [f"-DECO_FWD_WDT={wdt}"]))
     units.append((os.path.join(CSRC, "eco_step.hip"), os.path.join(OBJ, "eco_step.o"), DEVICE))
-    units.append((os.path.join(CSRC, "eco_sort.hip"), os.path.join(OBJ, "eco_sort.o"), DEVICE))
     units.append((os.path.join(CSRC, "eco_runtime.cpp"), os.path.join(OBJ, "eco_runtime.o"), []))
     return units
 

@@ -127,6 +127,7 @@ struct Dev {
   int32_t* freel;               // [total_slots] free slots (local) ascending
   float* logits;                // [total_slots][lgs]
   uint32_t lgs;                 // logits per slot in that buffer: 8, or 16 with a ninth action
+  const double2* trig;          // [256] cos, sin of 2 pi a / 256 (the Box-Muller angle table)
   unsigned long long* cellkeys; // init scratch: [total_cells] (key << 32 | local cell)
   unsigned long long* sorted;   // init scratch
   uint32_t n_worlds;
@@ -167,48 +168,143 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    // each 32x32 -> 64-bit product in one multiply-add instruction (both halves)
+    const uint64_t m0 = (uint64_t)0xD2511F53u * c0, m1 = (uint64_t)0xCD9E8D57u * c2;
+    // three-input XOR in one instruction (gfx950 bitop3, truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c3, k1, 0x96);
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)m1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)m0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
   return make_uint4(c0, c1, c2, c3);
 }
 
-__device__ __forceinline__ uint32_t draw32(const WorldParams& w, uint32_t a, uint32_t step, uint32_t stream) {
+template <typename WP>   // WorldParams, or any struct with the world's key0 / key1
+__device__ __forceinline__ uint32_t draw32(const WP& w, uint32_t a, uint32_t step, uint32_t stream) {
   return philox10(a, step, stream, 0u, w.key0, w.key1).x;
 }
 
-// Four standard normals from one Philox block by the Box-Muller transform
-// (Box & Muller 1958), evaluated in FP64 so the noise is the correctly
-// rounded transform up to the last bit of log/sin/cos.
-__device__ __forceinline__ void gauss4(const WorldParams& w, uint32_t a, uint32_t step, uint32_t stream,
-                                       uint32_t blk, double z[4]) {
-  const uint4 x = philox10(a, step, stream, blk, w.key0, w.key1);
-  const double two_pi = 6.283185307179586476925286766559;
+// Standard normals by the Box-Muller transform (Box & Muller 1958):
+// z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2), evaluated in FP64, so that a
+// mutated FP32 parameter is the correctly rounded parent + sigma z up to the
+// last bits of the FP64 evaluation.  u1 and u2 are 24-bit dyadic fractions,
+// which the two functions below use: the logarithm of an integer times a power
+// of two, and the angle split at a table of 256 exact multiples of 2 pi / 256.
+// ln(m 2^-24) for an integer 1 <= m <= 2^24, in FP64 to about an ulp: m = 2^e f
+// with f in [sqrt(1/2), sqrt(2)], so ln(m 2^-24) = (e - 24) ln 2 + ln f with
+// ln f = 2 atanh(s), s = (f - 1) / (f + 1), |s| <= 0.1716, from the odd series
+// 2 (s + s^3/3 + ... + s^19/19), whose next term is below 2^-55 relative; ln 2
+// in two parts, the first with trailing zeros so that (e - 24) times it is exact.
+__device__ __forceinline__ double ln_u24(uint32_t m) {
+  int e = 31 - __builtin_clz(m);
+  double f = ldexp((double)m, -e);   // exact, in [1, 2)
+  if (f > 1.4142135623730951) {
+    f *= 0.5;
+    ++e;
+  }
+  // s = (f - 1) / (f + 1) (both exact; the divisor lies in [1.7, 2.5]): the
+  // hardware reciprocal refined by two Newton steps, then one correction of the
+  // quotient by its residual
+  const double num = f - 1.0, den = f + 1.0;
+  double rc = __builtin_amdgcn_rcp(den);
+  rc = __builtin_fma(rc, __builtin_fma(-den, rc, 1.0), rc);
+  rc = __builtin_fma(rc, __builtin_fma(-den, rc, 1.0), rc);
+  double s = num * rc;
+  s = __builtin_fma(rc, __builtin_fma(-den, s, num), s);
+  const double s2 = s * s;
+  double q = 1.0 / 19.0;
+  q = __builtin_fma(q, s2, 1.0 / 17.0);
+  q = __builtin_fma(q, s2, 1.0 / 15.0);
+  q = __builtin_fma(q, s2, 1.0 / 13.0);
+  q = __builtin_fma(q, s2, 1.0 / 11.0);
+  q = __builtin_fma(q, s2, 1.0 / 9.0);
+  q = __builtin_fma(q, s2, 1.0 / 7.0);
+  q = __builtin_fma(q, s2, 1.0 / 5.0);
+  q = __builtin_fma(q, s2, 1.0 / 3.0);
+  const double two_s = 2.0 * s;
+  const double lnf = __builtin_fma(two_s * s2, q, two_s);
+  const double k = (double)(e - 24);
+  constexpr double ln2_hi = 0x1.62e42fefa38p-1, ln2_lo = 0x1.ef35793c7673p-45;
+  return __builtin_fma(k, ln2_hi, __builtin_fma(k, ln2_lo, lnf));
+}
+
+// cos and sin of 2 pi j 2^-24 for a 24-bit integer j, in FP64 to a few ulps of
+// the value itself: j = 2^16 a + b with a the nearest multiple (b in [-2^15,
+// 2^15)), the angle is 2 pi a / 256 (cos, sin from the 256-entry table `tab`)
+// plus phi = 2 pi b 2^-24, |phi| <= pi / 256, whose cos and sin come from their
+// Taylor series (the first omitted terms, phi^8 / 8! and phi^9 / 9!, are below
+// 2^-64), joined by the angle-sum formulas.  The zeros of cos and sin, at the
+// quarter turns, are table points with an exact 0 and 1, so next to them the
+// result is +-sin phi or +-cos phi and keeps its relative accuracy.
+constexpr int kTrigTable = 256;
+
+__device__ __forceinline__ void cossin_2pi_u24(uint32_t j, const double2* __restrict__ tab, double& c, double& s) {
+  const uint32_t a = (j + 0x8000u) >> 16;                               // 0..256
+  const double2 t = tab[a & (kTrigTable - 1)];
+  const double phi = (double)((int)j - (int)(a << 16)) * 0x1.921fb54442d18p-22;   // 2 pi 2^-24
+  const double p2 = phi * phi;
+  double sp = __builtin_fma(p2, -1.0 / 5040.0, 1.0 / 120.0);
+  sp = __builtin_fma(p2, sp, -1.0 / 6.0);
+  sp = __builtin_fma(phi * p2, sp, phi);                         // sin phi
+  double cp = __builtin_fma(p2, -1.0 / 720.0, 1.0 / 24.0);
+  cp = __builtin_fma(p2, cp, -0.5);
+  cp = __builtin_fma(p2, cp, 1.0);                               // cos phi
+  c = __builtin_fma(t.x, cp, -t.y * sp);
+  s = __builtin_fma(t.y, cp, t.x * sp);
+}
+
+// sqrt(y) for 0 <= y < 2^10 in FP64, to about an ulp: Goldschmidt's iteration
+// (g -> sqrt(y), h -> 1 / (2 sqrt(y))) from the hardware reciprocal square root,
+// twice, then one correction by the residual y - g^2.  y = 0 gives 0.
+__device__ __forceinline__ double sqrt_small(double y) {
+  const double r0 = __builtin_amdgcn_rsq(y);
+  double g = y * r0, h = 0.5 * r0;
+  double e = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, e, g);
+  h = __builtin_fma(h, e, h);
+  e = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, e, g);
+  h = __builtin_fma(h, e, h);
+  g = __builtin_fma(__builtin_fma(-g, g, y), h, g);
+  return y > 0.0 ? g : 0.0;
+}
+
+// Four standard normals from one Philox block (tab: the angle table above, in LDS).
+__device__ __forceinline__ void gauss4k(uint32_t key0, uint32_t key1, uint32_t a, uint32_t step, uint32_t stream,
+                                        uint32_t blk, const double2* __restrict__ tab, double z[4]) {
+  const uint4 x = philox10(a, step, stream, blk, key0, key1);
   const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
-    const double u1 = (double)((xs[2 * p] >> 8) + 1u) * 0x1p-24;
-    const double u2 = (double)(xs[2 * p + 1] >> 8) * 0x1p-24;
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt_small(-2.0 * ln_u24((xs[2 * p] >> 8) + 1u));   // u1 = ((x >> 8) + 1) 2^-24
     double s, c;
-    sincos(two_pi * u2, &s, &c);
+    cossin_2pi_u24(xs[2 * p + 1] >> 8, tab, c, s);                 // u2 = (x >> 8) 2^-24
     z[2 * p] = r * c;
     z[2 * p + 1] = r * s;
   }
+}
+
+__device__ __forceinline__ void gauss4(const WorldParams& w, uint32_t a, uint32_t step, uint32_t stream,
+                                       uint32_t blk, const double2* __restrict__ tab, double z[4]) {
+  gauss4k(w.key0, w.key1, a, step, stream, blk, tab, z);
+}
+
+// The angle table into LDS (all threads of the block take part).
+__device__ __forceinline__ void load_trig(const double2* __restrict__ src, double2* dst) {
+  for (int i = threadIdx.x; i < kTrigTable; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
 }
 
 __device__ __forceinline__ int dir_dx(int f) { return f == 1 ? 1 : (f == 3 ? -1 : 0); }
 __device__ __forceinline__ int dir_dy(int f) { return f == 0 ? -1 : (f == 2 ? 1 : 0); }
 
 // Local cell one step from `cell` along facing f (sign = +1 ahead, -1 behind), torus.
-__device__ __forceinline__ uint32_t neighbour(const WorldParams& w, uint32_t cell, int f, int sign) {
+template <typename WP>   // WorldParams, or any struct with the world's W and H
+__device__ __forceinline__ uint32_t neighbour(const WP& w, uint32_t cell, int f, int sign) {
   int x = (int)(cell % w.W), y = (int)(cell / w.W);
   x += sign * dir_dx(f);
   y += sign * dir_dy(f);
@@ -220,7 +316,8 @@ __device__ __forceinline__ uint32_t neighbour(const WorldParams& w, uint32_t cel
 // Local cell `ahead` steps along facing f and `side` steps to the right of that
 // heading (negative: to the left), torus; |ahead|, |side| <= 3.  Used for the
 // attack square, so not on the hot path of the step.
-__device__ __forceinline__ uint32_t offset_cell(const WorldParams& w, uint32_t cell, int f, int ahead, int side) {
+template <typename WP>
+__device__ __forceinline__ uint32_t offset_cell(const WP& w, uint32_t cell, int f, int ahead, int side) {
   const int r = (f + 1) & 3;
   int x = (int)(cell % w.W) + ahead * dir_dx(f) + side * dir_dx(r);
   int y = (int)(cell / w.W) + ahead * dir_dy(f) + side * dir_dy(r);

@@ -29,6 +29,7 @@ hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_claim_regrow(hipStream_t s, const Dev& d, const TileScratch& ts, uint32_t A);
 hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
+hipError_t birth_commit_blocks_per_cu(const Layout& L, int* blocks);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
 hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32_t* sink, uint32_t blocks,
@@ -40,9 +41,8 @@ hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uin
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt);
 hipError_t launch_emit_list(hipStream_t s, const Dev& d, const Layout& L, const uint32_t* list, uint32_t n, int mode,
                             double std1, double std2, double std3, uint32_t blocks);
-hipError_t sort_keys_temp_bytes(uint32_t n, size_t* bytes);
-hipError_t sort_keys(void* tmp, size_t bytes, const unsigned long long* in, unsigned long long* out, uint32_t n,
-                     hipStream_t s);
+hipError_t launch_placement(hipStream_t s, const Dev& d, const Tile* cell_tiles, uint32_t nt, const void* pinfo,
+                            uint32_t* cnt, uint32_t* start);
 }  // namespace eco
 
 using namespace eco;
@@ -54,7 +54,7 @@ constexpr uint32_t kCellTileH = 1024;
 constexpr uint32_t kSlotPartH = 16;
 constexpr uint32_t kCellPartH = 4;
 constexpr uint32_t kMaxWorldsH = 1024;
-enum { EMIT_INIT = 0, EMIT_MUTATE = 1, EMIT_REQUANT = 2 };
+enum { EMIT_INIT = 0, EMIT_REQUANT = 2 };
 
 thread_local std::string g_err;
 
@@ -96,10 +96,16 @@ struct eco_world {
   unsigned long long* part_cell = nullptr;
   uint32_t* tile_rng = nullptr;
   TileScratch ts{};
-  void* sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
+  // placement (init): per-world bucket table {first bucket, key shift} (+ a sentinel),
+  // bucket counts and starts
+  void* place_info = nullptr;
+  uint32_t* place_cnt = nullptr;
+  uint32_t* place_start = nullptr;
+  uint32_t n_buckets = 0;
+  std::vector<uint32_t> place_info_h;
   uint32_t* emit_list = nullptr;
   int n_cus = 256;
+  int birth_bpc = 4;        // resident birth-commit blocks per CU
   eco_launch launch{4, 4, 8, 0};
   uint32_t rt_flags = ECO_RT_USE_GRAPH;
   hipGraph_t graph = nullptr;
@@ -300,6 +306,31 @@ uint64_t weight_bytes(const Layout& L) {
   return nw + 4 * nb + 4 * nb;  // FP8 weights, FP32 biases and row scales
 }
 
+// The Box-Muller angle table: cos and sin of 2 pi a / 256, a = 0..255.  The
+// angle is reduced exactly by quarter turns and octant symmetry, so libm only
+// sees arguments in [0, pi / 4] and the multiples of a quarter turn are exact.
+std::vector<double2> angle_table() {
+  std::vector<double2> t(kTrigTable);
+  const int quarter = kTrigTable / 4;
+  for (int a = 0; a < kTrigTable; ++a) {
+    const int q = a / quarter, m = a % quarter;   // a = q quarter + m, m in [0, 64)
+    double cb, sb;                                // cos, sin of 2 pi m / 256 in [0, pi / 2)
+    if (2 * m <= quarter) {
+      const double b = 2.0 * M_PI * (double)m / (double)kTrigTable;
+      cb = std::cos(b);
+      sb = std::sin(b);
+    } else {                                      // pi / 2 - b = 2 pi (64 - m) / 256
+      const double b = 2.0 * M_PI * (double)(quarter - m) / (double)kTrigTable;
+      cb = std::sin(b);
+      sb = std::cos(b);
+    }
+    const double c = q == 0 ? cb : (q == 1 ? -sb : (q == 2 ? -cb : sb));
+    const double s = q == 0 ? sb : (q == 1 ? cb : (q == 2 ? -sb : -cb));
+    t[a] = make_double2(c, s);
+  }
+  return t;
+}
+
 void upload_world_params(eco_world* w) {
   for (uint32_t i = 0; i < w->n_worlds; ++i) {
     w->wp[i].key0 = (uint32_t)(w->descs[i].seed & 0xFFFFFFFFu);
@@ -313,6 +344,11 @@ eco_status sync(eco_world* w) {
 }
 
 uint32_t emit_blocks(eco_world* w) { return (uint32_t)std::max(1, w->n_cus * 4); }
+// Birth commit: one 256-thread block per birth, persistent, as many blocks as
+// can be resident at once (the kernel is bound by its noise arithmetic; more
+// resident waves hide the parent reads, and a grid beyond residency would start
+// its last blocks late and leave the chip idle behind them).
+uint32_t birth_blocks(eco_world* w) { return (uint32_t)std::max(1, w->n_cus * w->birth_bpc); }
 
 // Full deterministic init of every world.
 eco_status run_init(eco_world* w) {
@@ -330,11 +366,9 @@ eco_status run_init(eco_world* w) {
   HIPCHK(w, hipMemsetAsync(d.ring, 0, sizeof(eco_stats) * kStatsRing * w->n_worlds, s), "clear stats");
   HIPCHK(w, launch_init_cells(s, d, w->cell_tiles, w->n_cell_tiles), "init cells");
   HIPCHK(w, launch_flowdir(s, d, w->ts, -1), "flow directions");
-  for (uint32_t i = 0; i < w->n_worlds; ++i) {
-    const WorldParams& p = w->wp[i];
-    HIPCHK(w, sort_keys(w->sort_tmp, w->sort_tmp_bytes, d.cellkeys + p.cell_off, d.sorted + p.cell_off, p.cells, s),
-           "placement sort");
-  }
+  HIPCHK(w, hipMemsetAsync(w->place_cnt, 0, 4ull * w->n_buckets, s), "clear placement counts");
+  HIPCHK(w, launch_placement(s, d, w->cell_tiles, w->n_cell_tiles, w->place_info, w->place_cnt, w->place_start),
+         "placement");
   HIPCHK(w, launch_init_agents(s, d, w->slot_tiles, w->n_slot_tiles), "init agents");
   std::vector<uint32_t> list;
   for (uint32_t i = 0; i < w->n_worlds; ++i)
@@ -400,7 +434,7 @@ hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, int k) {
     case ECO_K_MOVE: return launch_move(s, d, w->ts);
     case ECO_K_BIRTH_CLAIM: return launch_birth_claim_regrow(s, d, w->ts, w->L.A);
     case ECO_K_BIRTH_SCAN: return launch_birth_rank(s, d, w->ts);
-    case ECO_K_BIRTH_COMMIT: return launch_birth_commit(s, d, w->L, emit_blocks(w));
+    case ECO_K_BIRTH_COMMIT: return launch_birth_commit(s, d, w->L, birth_blocks(w));
     default: return launch_compact(s, d, w->ts, 0, -1);
   }
 }
@@ -629,15 +663,14 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   }
   make_layout(descs[0], w->L, w->std1, w->std2, w->std3);
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&w->n_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+  if (!alloc && hipGetDevice(&dev) != hipSuccess) {   // (with the caller's allocator: after allocating)
+    (void)hipGetLastError();
     delete w;
     return fail(ECO_EDEVICE, "no HIP device");
   }
   // world tables: slot and cell ranges aligned to 64
   uint64_t so = 0, co = 0;
   w->wp.resize(n_worlds);
-  uint32_t max_cells = 0;
   bool any_attack = false;
   for (uint32_t i = 0; i < n_worlds; ++i) {
     const eco_world_desc& d = descs[i];
@@ -675,7 +708,6 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     w->tile_rng_h.push_back(w->n_cell_tiles);
     so = round_up(so + p.cap, 64);
     co = round_up(co + p.cells, 64);
-    max_cells = std::max(max_cells, p.cells);
   }
   if (so >= (1ull << 31) || co >= (1ull << 31)) {
     delete w;
@@ -737,6 +769,7 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
   d.freel = (int32_t*)A(4 * TS);
   d.lgs = w->L.R3;
   d.logits = (float*)A(4ull * d.lgs * TS);
+  d.trig = (const double2*)A(sizeof(double2) * kTrigTable);
   d.cellkeys = (unsigned long long*)A(8 * TC);
   d.sorted = (unsigned long long*)A(8 * TC);
   d.store = (uint8_t*)A(w->L.sstride * TS);
@@ -763,13 +796,38 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
     ts.tm2 = (double*)A(8 * T);
   }
   w->emit_list = (uint32_t*)A(8 * TS);
-  if (ok && sort_keys_temp_bytes(max_cells, &w->sort_tmp_bytes) != hipSuccess) ok = false;
-  if (ok) w->sort_tmp = A(w->sort_tmp_bytes);
+  {   // placement buckets: 2^k per world, about four cells each
+    std::vector<uint32_t> pinfo;
+    uint32_t nb = 0;
+    for (uint32_t i = 0; i < n_worlds; ++i) {
+      uint32_t k = 0;
+      while (k < 30 && (4ull << k) < w->wp[i].cells) ++k;
+      pinfo.push_back(nb);
+      pinfo.push_back(32 - k);
+      nb += 1u << k;
+    }
+    pinfo.push_back(nb);
+    pinfo.push_back(32);
+    w->n_buckets = nb;
+    w->place_info = A(4 * pinfo.size());
+    w->place_cnt = (uint32_t*)A(4ull * nb);
+    w->place_start = (uint32_t*)A(4ull * (nb + n_worlds));
+    w->place_info_h = pinfo;
+  }
   if (!ok) {
     free_all(w);
     delete w;
     return fail(ECO_ENOMEM, "device allocation failed");
   }
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&w->n_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      birth_commit_blocks_per_cu(w->L, &w->birth_bpc) != hipSuccess) {
+    (void)hipGetLastError();
+    free_all(w);
+    delete w;
+    return fail(ECO_EDEVICE, "no HIP device");
+  }
+  w->birth_bpc = std::max(1, w->birth_bpc);
   d.n_worlds = n_worlds;
   d.total_slots = w->total_slots;
   d.total_cells = w->total_cells;
@@ -788,6 +846,13 @@ eco_status eco_world_create(const eco_world_desc* descs, uint32_t n_worlds, void
                      hipMemcpyHostToDevice, s), "upload tiles");
   chk(hipMemcpyAsync(w->tile_rng, w->tile_rng_h.data(), 4 * w->tile_rng_h.size(), hipMemcpyHostToDevice, s),
       "upload tile ranges");
+  chk(hipMemcpyAsync(w->place_info, w->place_info_h.data(), 4 * w->place_info_h.size(), hipMemcpyHostToDevice, s),
+      "upload placement table");
+  {
+    static const std::vector<double2> trig = angle_table();
+    chk(hipMemcpyAsync((void*)d.trig, trig.data(), sizeof(double2) * kTrigTable, hipMemcpyHostToDevice, s),
+        "upload angle table");
+  }
   chk(hipMemsetAsync(d.store, 0, w->L.sstride * TS, s), "clear weights");
   if (d.master != d.store) chk(hipMemsetAsync(d.master, 0, w->L.mstride * TS, s), "clear master");
   chk(hipMemsetAsync(d.trait, 0, 8 * TS, s), "clear trait");

@@ -173,40 +173,29 @@ __device__ __forceinline__ float fp8_value(uint32_t q) {
   return (q & 0x80u) ? -v : v;
 }
 
-enum EmitMode { EMIT_INIT = 0, EMIT_MUTATE = 1, EMIT_REQUANT = 2 };
+enum EmitMode { EMIT_INIT = 0, EMIT_REQUANT = 2 };
 
 // Writes the FP32 master of global slot `child` and its storage copy, and the
-// trait |theta|^2.  INIT: N(0, 1/fan_in) weights from (rng_slot, step 0,
-// WINIT), zero biases.  MUTATE: parent master + sigma z, z from (rng_slot =
-// parent local slot, step, MUTATE).  REQUANT: master already written.
+// trait |theta|^2 (init and weight writes; births go through mutate_child).
+// INIT: N(0, 1/fan_in) weights from (rng_slot, step 0, WINIT), zero biases.
+// REQUANT: master already written.
 template <int WDT>
 __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp, uint32_t child, int mode,
-                           uint32_t parent, uint32_t rng_slot, uint32_t step, double std1, double std2,
-                           double std3, uint32_t* s_amax, double* s_red) {
+                           uint32_t rng_slot, double std1, double std2, double std3, const double2* tab,
+                           uint32_t* s_amax, double* s_red) {
   const int tid = threadIdx.x;
   float* mc = reinterpret_cast<float*>(d.master + (uint64_t)child * L.mstride);
-  const float* mp = reinterpret_cast<const float*>(d.master + (uint64_t)parent * L.mstride);
   uint8_t* sc = d.store + (uint64_t)child * L.sstride;
   const uint32_t nrows = L.H1 + L.H2 + L.R3;
   if (WDT == 2) {
     for (uint32_t i = tid; i < nrows; i += blockDim.x) s_amax[i] = 0u;
     __syncthreads();
   }
-  const double sigma = (double)wp.sigma;
-  if (L.colour && tid == 0 && mode != EMIT_REQUANT) {
-    // colour trait: U[0,1) per channel at init, the parent's plus sigma N(0,1) at birth
-    float4 c;
-    if (mode == EMIT_INIT) {
-      const uint4 x = philox10(rng_slot, 0u, ST_COLOUR_INIT, 0u, wp.key0, wp.key1);
-      c = make_float4((float)(x.x >> 8) * 0x1p-24f, (float)(x.y >> 8) * 0x1p-24f, (float)(x.z >> 8) * 0x1p-24f, 0.0f);
-    } else {
-      double z[4];
-      gauss4(wp, rng_slot, step, ST_COLOUR_MUTATE, 0u, z);
-      const float4 pc = d.colour[parent];
-      c = make_float4((float)__builtin_fma(sigma, z[0], (double)pc.x), (float)__builtin_fma(sigma, z[1], (double)pc.y),
-                      (float)__builtin_fma(sigma, z[2], (double)pc.z), 0.0f);
-    }
-    d.colour[child] = c;
+  if (L.colour && tid == 0 && mode == EMIT_INIT) {
+    // colour trait: U[0,1) per channel
+    const uint4 x = philox10(rng_slot, 0u, ST_COLOUR_INIT, 0u, wp.key0, wp.key1);
+    d.colour[child] = make_float4((float)(x.x >> 8) * 0x1p-24f, (float)(x.y >> 8) * 0x1p-24f,
+                                  (float)(x.z >> 8) * 0x1p-24f, 0.0f);
   }
   double tsum = 0.0;
   for (uint32_t u = tid; u < L.u_end; u += blockDim.x) {
@@ -215,23 +204,12 @@ __device__ void emit_agent(const Dev& d, const Layout& L, const WorldParams& wp,
     if (mode == EMIT_REQUANT) {
       const float4 m4 = reinterpret_cast<const float4*>(mc)[u];
       v[0] = m4.x; v[1] = m4.y; v[2] = m4.z; v[3] = m4.w;
-    } else if (ui.nvalid > 0) {
+    } else if (ui.nvalid > 0 && ui.layer < 3) {
       double z[4];
-      if (mode == EMIT_INIT) {
-        if (ui.layer < 3) {
-          gauss4(wp, rng_slot, 0u, ST_WINIT, ui.p >> 2, z);
-          const double sd = ui.layer == 0 ? std1 : (ui.layer == 1 ? std2 : std3);
+      gauss4(wp, rng_slot, 0u, ST_WINIT, ui.p >> 2, tab, z);
+      const double sd = ui.layer == 0 ? std1 : (ui.layer == 1 ? std2 : std3);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = (float)(z[i] * sd);
-        }
-      } else {
-        const float4 p4 = reinterpret_cast<const float4*>(mp)[u];
-        const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
-        gauss4(wp, rng_slot, step, ST_MUTATE, ui.p >> 2, z);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          v[i] = (i < (int)ui.nvalid) ? (float)__builtin_fma(sigma, z[i], (double)pv[i]) : 0.0f;
-      }
+      for (int i = 0; i < 4; ++i) v[i] = (float)(z[i] * sd);
     }
     if (mode != EMIT_REQUANT) reinterpret_cast<float4*>(mc)[u] = make_float4(v[0], v[1], v[2], v[3]);
 #pragma unroll
@@ -652,12 +630,203 @@ __device__ __forceinline__ void birth_offsets(const WorldVar* __restrict__ wv, u
 
 constexpr int kMaxWorlds = 1024;
 
-// One block per birth (persistent over all worlds' births).
+// Unit u of an agent's master (16 bytes, four consecutive logical parameters):
+// its Philox block (= first logical parameter / 4), layer (0..2 weights, 3..5
+// biases), output row (first row for biases), k-block (the column quad in layer
+// 2) and the number of its parameters that exist.  H = H1 = H2 is a power of
+// two, so every index is a shift or a mask.
+struct UnitPos {
+  uint32_t blk, row, kb, nvalid;
+  int layer;
+};
+
+template <int H>
+__device__ __forceinline__ UnitPos unit_pos(const Layout& L, uint32_t u) {
+  constexpr uint32_t LG = H == 32 ? 5 : (H == 64 ? 6 : 7);
+  UnitPos r;
+  r.nvalid = 4;
+  r.kb = 0;
+  if (u < L.u_b1) {                   // W1 [kb][row]: first parameter row D + 4 kb
+    r.layer = 0; r.row = u & (H - 1); r.kb = u >> LG; r.blk = r.row * L.KB1 + r.kb;
+  } else if (u < L.u_w2) {            // b1
+    const uint32_t e = u - L.u_b1;
+    r.layer = 3; r.row = 4 * e; r.blk = (L.p_b1 >> 2) + e;
+  } else if (u < L.u_b2) {            // W2 [kb][row]: p_w2 + row H + 4 kb
+    const uint32_t e = u - L.u_w2;
+    r.layer = 1; r.row = e & (H - 1); r.kb = e >> LG; r.blk = (L.p_w2 >> 2) + r.row * (H / 4) + r.kb;
+  } else if (u < L.u_w3) {            // b2
+    const uint32_t e = u - L.u_b2;
+    r.layer = 4; r.row = 4 * e; r.blk = (L.p_b2 >> 2) + e;
+  } else if (u < L.u_b3) {            // W3 [row][H]: p_w3 + row H + 4 kb (rows >= A are padding)
+    const uint32_t e = u - L.u_w3;
+    r.layer = 2; r.row = e >> (LG - 2); r.kb = e & (H / 4 - 1); r.blk = (L.p_w3 >> 2) + e;
+    r.nvalid = r.row < L.A ? 4u : 0u;
+  } else {                            // b3, then the log temperature in slot A when it evolves
+    const uint32_t e = u - L.u_b3, n3 = L.A + L.temp;
+    r.layer = 5; r.row = 4 * e; r.blk = (L.p_b3 >> 2) + e;
+    r.nvalid = r.row < n3 ? min(4u, n3 - r.row) : 0u;
+  }
+  return r;
+}
+
+// Streaming accesses of the weight blocks a birth reads once and writes once
+// (non-temporal: no cache line is kept for them).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 stream_load4(const float4* p) {
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+// The child's FP32 master; cached when it is read back for FP8 row scales (WDT 2).
 template <int WDT>
-__global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
+__device__ __forceinline__ void stream_store4(float4* p, float a, float b, float c, float d) {
+  if (WDT == 2) *p = make_float4(a, b, c, d);
+  else __builtin_nontemporal_store(f32x4{a, b, c, d}, reinterpret_cast<f32x4*>(p));
+}
+
+// Storage copy of one unit's four master values (BF16 round-to-nearest-even;
+// FP8: biases as FP32 here, weights after the row scales are known).
+template <int WDT, int H>
+__device__ __forceinline__ void store_unit(const Layout& L, uint8_t* sc, int layer, uint32_t row, uint32_t kb,
+                                           const float (&v)[4], uint32_t* s_amax) {
+  if (WDT == 1) {
+    const uint32_t lo = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
+    const uint32_t hi = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
+    uint64_t off;
+    if (layer == 0) off = L.s_w1 + ((uint64_t)(kb >> 1) * H + row) * 16 + (kb & 1) * 8;
+    else if (layer == 1) off = L.s_w2 + ((uint64_t)(kb >> 1) * H + row) * 16 + (kb & 1) * 8;
+    else if (layer == 2) off = L.s_w3 + ((uint64_t)row * H + 4 * kb) * 2;
+    else off = L.s_b1 + (layer >= 4 ? L.s_b2 - L.s_b1 : 0u) + (layer >= 5 ? L.s_b3 - L.s_b2 : 0u) + (uint64_t)row * 2;
+    *reinterpret_cast<uint2*>(sc + off) = make_uint2(lo, hi);   // half of a 16-byte block: cached
+  } else if (WDT == 2) {
+    if (layer < 3) {
+      const uint32_t r = layer == 0 ? row : (layer == 1 ? H + row : 2 * H + row);
+      const float mx = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+      atomicMax(&s_amax[r], __float_as_uint(mx));
+    } else {
+      const uint32_t base = L.s_b1 + (layer >= 4 ? L.s_b2 - L.s_b1 : 0u) + (layer >= 5 ? L.s_b3 - L.s_b2 : 0u);
+      *reinterpret_cast<float4*>(sc + base + (uint64_t)row * 4) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// FP8 storage, after store_unit has gathered each row's amax in s_amax: the row
+// scales, then the weights quantised with them (each thread re-reads the master
+// units it wrote itself).
+template <int H>
+__device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __restrict__ mc, uint8_t* sc,
+                                           const uint32_t* s_amax, uint32_t tid) {
+  const uint32_t nrows = 2 * H + L.R3;
+  for (uint32_t r = tid; r < nrows; r += 256) {
+    const float amax = __uint_as_float(s_amax[r]);
+    const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+    uint64_t off;
+    if (r < H) off = L.s_sc1 + (uint64_t)r * 4;
+    else if (r < 2 * H) off = L.s_sc2 + (uint64_t)(r - H) * 4;
+    else off = L.s_sc3 + (uint64_t)(r - 2 * H) * 4;
+    *reinterpret_cast<float*>(sc + off) = scale;
+  }
+  for (uint32_t u = tid; u < L.u_b3; u += 256) {
+    const UnitPos up = unit_pos<H>(L, u);
+    const int layer = up.layer;
+    const uint32_t row = up.row, kb = up.kb;
+    if (layer >= 3) continue;
+    const uint32_t r = layer == 0 ? row : (layer == 1 ? H + row : 2 * H + row);
+    const float amax = __uint_as_float(s_amax[r]);
+    const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+    const float4 m4 = mc[u];
+    const uint32_t q = fp8_rne_sat(m4.x / scale) | (fp8_rne_sat(m4.y / scale) << 8) |
+                       (fp8_rne_sat(m4.z / scale) << 16) | (fp8_rne_sat(m4.w / scale) << 24);
+    uint64_t off;
+    if (layer == 0) off = L.s_w1 + ((uint64_t)(kb >> 2) * H + row) * 16 + (kb & 3) * 4;
+    else if (layer == 1) off = L.s_w2 + ((uint64_t)(kb >> 2) * H + row) * 16 + (kb & 3) * 4;
+    else off = L.s_w3 + (uint64_t)row * H + 4 * kb;
+    *reinterpret_cast<uint32_t*>(sc + off) = q;
+  }
+}
+
+// Child master = parent master + sigma z (Sec. 3.3 mutation of every parameter),
+// z standard normal from the parent's Philox stream (parent slot, step, MUTATE,
+// block); the storage copy re-quantised from it; the child's |theta|^2.  One
+// block of 256 threads per child.
+template <int WDT, int H>
+__device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& wp, uint32_t child, uint32_t parent,
+                             uint32_t rng_slot, uint32_t step, const double2* tab, uint32_t* s_amax,
+                             double* s_red) {
+  const uint32_t tid = threadIdx.x;
+  const float4* __restrict__ mp = reinterpret_cast<const float4*>(d.master + (uint64_t)parent * L.mstride);
+  float4* __restrict__ mc = reinterpret_cast<float4*>(d.master + (uint64_t)child * L.mstride);
+  uint8_t* sc = d.store + (uint64_t)child * L.sstride;
+  if (WDT == 2) {
+    for (uint32_t i = tid; i < 2 * H + L.R3; i += 256) s_amax[i] = 0u;
+    __syncthreads();
+  }
+  const double sigma = (double)wp.sigma;
+  const uint32_t key0 = wp.key0, key1 = wp.key1;
+  if (L.colour && tid == 0) {
+    // colour trait: the parent's plus sigma N(0,1) per channel
+    double z[4];
+    gauss4(wp, rng_slot, step, ST_COLOUR_MUTATE, 0u, tab, z);
+    const float4 pc = d.colour[parent];
+    d.colour[child] = make_float4((float)__builtin_fma(sigma, z[0], (double)pc.x),
+                                  (float)__builtin_fma(sigma, z[1], (double)pc.y),
+                                  (float)__builtin_fma(sigma, z[2], (double)pc.z), 0.0f);
+  }
+  double tsum = 0.0;
+  auto unit = [&](uint32_t u, const UnitPos& up) {
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (up.nvalid > 0) {
+      const float4 p4 = stream_load4(mp + u);
+      const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+      double z[4];
+      gauss4k(key0, key1, rng_slot, step, ST_MUTATE, up.blk, tab, z);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (i < (int)up.nvalid) ? (float)__builtin_fma(sigma, z[i], (double)pv[i]) : 0.0f;
+    }
+    stream_store4<WDT>(mc + u, v[0], v[1], v[2], v[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tsum += (double)v[i] * (double)v[i];
+    store_unit<WDT, H>(L, sc, up.layer, up.row, up.kb, v, s_amax);
+  };
+  // W1 (most of the units) without the layer decode, then the other layers
+  constexpr uint32_t LG = H == 32 ? 5 : (H == 64 ? 6 : 7);
+  const uint32_t ub1 = L.u_b1;
+  float4 next = tid < ub1 ? stream_load4(mp + tid) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll 1
+  for (uint32_t u = tid; u < ub1; u += 256) {
+    const float4 p4 = next;   // this unit's parent values, loaded one unit ahead
+    if (u + 256 < ub1) next = stream_load4(mp + u + 256);
+    const uint32_t row = u & (H - 1), kb = u >> LG;
+    const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+    double z[4];
+    gauss4k(key0, key1, rng_slot, step, ST_MUTATE, row * L.KB1 + kb, tab, z);
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (float)__builtin_fma(sigma, z[i], (double)pv[i]);
+    stream_store4<WDT>(mc + u, v[0], v[1], v[2], v[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tsum += (double)v[i] * (double)v[i];
+    store_unit<WDT, H>(L, sc, 0, row, kb, v, s_amax);
+  }
+#pragma unroll 1
+  for (uint32_t u = L.u_b1 + tid; u < L.u_end; u += 256) unit(u, unit_pos<H>(L, u));
+  if (WDT == 2) {
+    __syncthreads();
+    fp8_finish<H>(L, mc, sc, s_amax, tid);
+  }
+  const double t = block_sum_f64<256>(tsum, s_red);
+  if (tid == 0) d.trait[child] = t;
+}
+
+// One block per birth (persistent over all worlds' births).  Six waves per SIMD
+// (five with the FP8 copy and its row scales) fit without spilling; the noise
+// arithmetic of the other waves hides each wave's parent reads.
+template <int WDT, int H>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 2 ? 5 : 6))) void k_birth_commit(Dev d, Layout L) {
   __shared__ uint32_t off[kMaxWorlds + 1];
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];
+  __shared__ double2 tab[kTrigTable];
+  load_trig(d.trig, tab);
   birth_offsets(d.wv, d.n_worlds, off);
   const uint32_t total = off[d.n_worlds];
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -688,7 +857,7 @@ __global__ __launch_bounds__(256) void k_birth_commit(Dev d, Layout L) {
         d.hp[cg] = e.hp_child;
       }
     }
-    emit_agent<WDT>(d, L, wp, cg, EMIT_MUTATE, pg, p_local, step, 0.0, 0.0, 0.0, s_amax, s_red);
+    mutate_child<WDT, H>(d, L, wp, cg, pg, p_local, step, tab, s_amax, s_red);
     __syncthreads();
   }
 }
@@ -1146,6 +1315,88 @@ __global__ __launch_bounds__(256) void k_init_cells(Dev d, const Tile* __restric
   }
 }
 
+// Placement (Sec. 3.2: the initial population on distinct cells; slot j takes
+// the cell with the j-th smallest (Philox key, cell) pair).  The keys are 32-bit
+// uniform draws, so a world's cells are bucketed by the top bits of the key into
+// 2^k buckets of about four cells each (counts, a per-world exclusive scan, a
+// scatter), and each cell's rank is its bucket's start plus the number of cells
+// of its bucket with a smaller (key, cell) pair.  Only ranks below n_init are
+// written.  Init only, never on the step path.
+struct PlaceInfo {
+  uint32_t boff;    // first bucket of the world in the bucket arrays
+  uint32_t shift;   // bucket = key >> shift (2^(32 - shift) buckets)
+};
+
+__device__ __forceinline__ uint32_t place_bucket(const PlaceInfo& pi, unsigned long long k64) {
+  return pi.boff + (pi.shift >= 32 ? 0u : (uint32_t)(k64 >> 32) >> pi.shift);
+}
+
+// Bucket counts (cnt zeroed by the caller).
+__global__ __launch_bounds__(256) void k_place_count(Dev d, const Tile* __restrict__ tiles,
+                                                     const PlaceInfo* __restrict__ pinfo, uint32_t* cnt) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  const PlaceInfo pi = pinfo[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x)
+    atomicAdd(&cnt[place_bucket(pi, d.cellkeys[wp.cell_off + tl.start + i])], 1u);
+}
+
+// Per world (one block each): start[b] = exclusive prefix of the counts over the
+// world's buckets (start of world w's buckets at boff + w, one extra entry per
+// world holding its total), and the counts cleared for the scatter's cursors.
+__global__ __launch_bounds__(kScanThreads) void k_place_scan(const PlaceInfo* __restrict__ pinfo, uint32_t* cnt,
+                                                             uint32_t* start) {
+  __shared__ uint32_t red[kScanThreads / 64 + 1];
+  const uint32_t w = blockIdx.x;
+  const PlaceInfo pi = pinfo[w];
+  const uint32_t nb = pinfo[w + 1].boff - pi.boff;
+  const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = pi.boff + threadIdx.x * per, hi = min(lo + per, pi.boff + nb);
+  uint32_t own = 0;
+  for (uint32_t b = lo; b < hi; ++b) own += cnt[b];
+  uint32_t total;
+  uint32_t run = block_exscan<kScanThreads>(own, red, &total);
+  for (uint32_t b = lo; b < hi; ++b) {
+    const uint32_t c = cnt[b];
+    start[b + w] = run;
+    run += c;
+    cnt[b] = 0;
+  }
+  if (threadIdx.x == 0) start[pi.boff + nb + w] = total;
+}
+
+// Each cell into its bucket (unordered within the bucket) of sorted[].
+__global__ __launch_bounds__(256) void k_place_scatter(Dev d, const Tile* __restrict__ tiles,
+                                                       const PlaceInfo* __restrict__ pinfo, uint32_t* cnt,
+                                                       const uint32_t* __restrict__ start) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  const PlaceInfo pi = pinfo[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const unsigned long long k = d.cellkeys[wp.cell_off + tl.start + i];
+    const uint32_t b = place_bucket(pi, k);
+    d.sorted[wp.cell_off + start[b + tl.world] + atomicAdd(&cnt[b], 1u)] = k;
+  }
+}
+
+// Rank of each bucketed cell; ranks below n_init go to cellkeys[cell_off + rank].
+__global__ __launch_bounds__(256) void k_place_rank(Dev d, const Tile* __restrict__ tiles,
+                                                    const PlaceInfo* __restrict__ pinfo,
+                                                    const uint32_t* __restrict__ start) {
+  const Tile tl = tiles[blockIdx.x];
+  const WorldParams wp = d.wp[tl.world];
+  const PlaceInfo pi = pinfo[tl.world];
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const unsigned long long k = d.sorted[wp.cell_off + tl.start + i];
+    const uint32_t b = place_bucket(pi, k) + tl.world;
+    const uint32_t s0 = start[b], s1 = start[b + 1];
+    if (s0 >= wp.n_init) continue;   // the whole bucket ranks past the initial population
+    uint32_t r = s0;
+    for (uint32_t q = s0; q < s1; ++q) r += d.sorted[wp.cell_off + q] < k ? 1u : 0u;
+    if (r < wp.n_init) d.cellkeys[wp.cell_off + r] = k;
+  }
+}
+
 // Slot j < n_init takes the j-th smallest (key, cell); all other slots are free.
 __global__ __launch_bounds__(kSlotTile) void k_init_agents(Dev d, const Tile* __restrict__ tiles) {
   const Tile tl = tiles[blockIdx.x];
@@ -1156,7 +1407,7 @@ __global__ __launch_bounds__(kSlotTile) void k_init_agents(Dev d, const Tile* __
   d.act[g] = 0;
   d.sampled[g] = 255;
   if (j < wp.n_init) {
-    const uint32_t cell = (uint32_t)(d.sorted[wp.cell_off + j] & 0xFFFFFFFFull);
+    const uint32_t cell = (uint32_t)(d.cellkeys[wp.cell_off + j] & 0xFFFFFFFFull);   // ranked by placement
     d.flags[g] = kAlive;
     d.pos[g] = (int)cell;
     d.occ[wp.cell_off + cell] = (int)j;
@@ -1184,11 +1435,13 @@ __global__ __launch_bounds__(256) void k_emit_list(Dev d, Layout L, const uint32
                                                    int mode, double std1, double std2, double std3) {
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];
+  __shared__ double2 tab[kTrigTable];
+  load_trig(d.trig, tab);
   for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
     const uint32_t w = list[2 * e], j = list[2 * e + 1];
     const WorldParams wp = d.wp[w];
     const uint32_t g = wp.slot_off + j;
-    emit_agent<WDT>(d, L, wp, g, mode, g, j, 0u, std1, std2, std3, s_amax, s_red);
+    emit_agent<WDT>(d, L, wp, g, mode, j, std1, std2, std3, tab, s_amax, s_red);
     __syncthreads();
   }
 }
@@ -1250,10 +1503,31 @@ hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts)
   hipLaunchKernelGGL(k_birth_rank_write, dim3(ts.n_slot_tiles), dim3(kSlotTile), 0, s, d, ts);
   ECO_CHECK_LAUNCH();
 }
+// Resident blocks per CU of the birth-commit kernel for this layout (its register
+// and LDS use), so that the persistent grid is exactly one wave of resident blocks.
+template <int WDT>
+const void* birth_commit_fn(uint32_t H) {
+  if (H == 32) return reinterpret_cast<const void*>(&k_birth_commit<WDT, 32>);
+  if (H == 64) return reinterpret_cast<const void*>(&k_birth_commit<WDT, 64>);
+  return reinterpret_cast<const void*>(&k_birth_commit<WDT, 128>);
+}
+hipError_t birth_commit_blocks_per_cu(const Layout& L, int* blocks) {
+  const void* f = L.wdtype == 0 ? birth_commit_fn<0>(L.H1) : (L.wdtype == 1 ? birth_commit_fn<1>(L.H1)
+                                                                              : birth_commit_fn<2>(L.H1));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, 256, 0);
+}
+
+template <int WDT>
+void launch_birth_commit_w(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks) {
+  if (L.H1 == 32) hipLaunchKernelGGL((k_birth_commit<WDT, 32>), dim3(blocks), dim3(256), 0, s, d, L);
+  else if (L.H1 == 64) hipLaunchKernelGGL((k_birth_commit<WDT, 64>), dim3(blocks), dim3(256), 0, s, d, L);
+  else hipLaunchKernelGGL((k_birth_commit<WDT, 128>), dim3(blocks), dim3(256), 0, s, d, L);
+}
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks) {
-  if (L.wdtype == 0) hipLaunchKernelGGL(k_birth_commit<0>, dim3(blocks), dim3(256), 0, s, d, L);
-  else if (L.wdtype == 1) hipLaunchKernelGGL(k_birth_commit<1>, dim3(blocks), dim3(256), 0, s, d, L);
-  else hipLaunchKernelGGL(k_birth_commit<2>, dim3(blocks), dim3(256), 0, s, d, L);
+  if (L.H1 != L.H2 || (L.H1 != 32 && L.H1 != 64 && L.H1 != 128)) return hipErrorInvalidValue;
+  if (L.wdtype == 0) launch_birth_commit_w<0>(s, d, L, blocks);
+  else if (L.wdtype == 1) launch_birth_commit_w<1>(s, d, L, blocks);
+  else launch_birth_commit_w<2>(s, d, L, blocks);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world) {
@@ -1291,6 +1565,20 @@ hipError_t launch_resource_total(hipStream_t s, const Dev& d, int only_world) {
 hipError_t launch_init_cells(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt) {
   if (nt == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_cells, dim3(nt), dim3(256), 0, s, d, tiles);
+  ECO_CHECK_LAUNCH();
+}
+hipError_t launch_placement(hipStream_t s, const Dev& d, const Tile* cell_tiles, uint32_t nt, const void* pinfo,
+                            uint32_t* cnt, uint32_t* start) {
+  if (nt == 0) return hipSuccess;
+  const PlaceInfo* pi = reinterpret_cast<const PlaceInfo*>(pinfo);
+  hipLaunchKernelGGL(k_place_count, dim3(nt), dim3(256), 0, s, d, cell_tiles, pi, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_place_scan, dim3(d.n_worlds), dim3(kScanThreads), 0, s, pi, cnt, start);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_place_scatter, dim3(nt), dim3(256), 0, s, d, cell_tiles, pi, cnt, start);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_place_rank, dim3(nt), dim3(256), 0, s, d, cell_tiles, pi, start);
   ECO_CHECK_LAUNCH();
 }
 hipError_t launch_init_agents(hipStream_t s, const Dev& d, const Tile* tiles, uint32_t nt) {

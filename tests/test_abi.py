@@ -80,3 +80,64 @@ def test_struct_sizes_match_header(tmp_path):
         assert int(out[k]) == ctypes.sizeof(cls), k
         for n in fields[k]:
             assert int(out[f"{k}.{n}"]) == getattr(cls, n).offset, (k, n)
+
+
+def _counting_allocator(eco, fail_at):
+    """An allocator that hands out distinct fake addresses (never dereferenced on
+    these paths) and returns NULL at call number fail_at; it records frees."""
+    state = {"calls": 0, "live": set(), "freed": []}
+
+    def alloc(nbytes, ctx):
+        i = state["calls"]
+        state["calls"] += 1
+        if i == fail_at:
+            return None
+        addr = 0x10000000 + 0x100000 * i
+        state["live"].add(addr)
+        return addr
+
+    def free(ptr, ctx):
+        state["freed"].append(ptr)
+        state["live"].discard(ptr)
+
+    fa, ff = eco.ALLOC_FN(alloc), eco.FREE_FN(free)
+    return eco.Allocator(fa, ff, None), state, (fa, ff)
+
+
+def test_allocator_null_gives_enomem_and_no_leak():
+    """An allocator that returns NULL on its k-th call: eco_world_create reports
+    ECO_ENOMEM, gives every earlier allocation back through the allocator's free,
+    and leaves *out NULL.  The allocations come before any device call when the
+    caller brings the allocator, so this runs without a GPU."""
+    import torch
+    from paper_2510_18221_amd import eco
+    from paper_2510_18221_amd import workloads as wl
+    lib = eco.lib()
+    d = (eco.Desc * 1)(eco.make_desc(wl.desc()))
+    sentinel = 0xDEAD0000
+    n_total = None
+    if not torch.cuda.is_available():
+        # every allocation succeeds: the device query then fails, and all is given back
+        al, st, keep = _counting_allocator(eco, fail_at=-1)
+        out = ctypes.c_void_p(sentinel)
+        assert lib.eco_world_create(d, 1, None, ctypes.byref(al), ctypes.byref(out)) == eco.ECO_EDEVICE
+        assert out.value is None and not st["live"] and len(st["freed"]) == st["calls"] > 10
+        n_total = st["calls"]
+    for k in [0, 1, 7] + ([n_total // 2, n_total - 1] if n_total else []):
+        al, st, keep = _counting_allocator(eco, fail_at=k)
+        out = ctypes.c_void_p(sentinel)
+        assert lib.eco_world_create(d, 1, None, ctypes.byref(al), ctypes.byref(out)) == eco.ECO_ENOMEM, k
+        assert b"allocation" in lib.eco_last_error()
+        assert out.value is None, k
+        assert st["calls"] == k + 1, (k, st["calls"])      # nothing allocated after the failure
+        assert not st["live"] and len(st["freed"]) == k, k  # everything before it given back
+
+
+def test_create_sets_out_to_null_on_error():
+    from paper_2510_18221_amd import eco
+    from paper_2510_18221_amd import workloads as wl
+    lib = eco.lib()
+    out = ctypes.c_void_p(0xDEAD0000)
+    d = (eco.Desc * 1)(eco.make_desc(wl.desc(window=4)))
+    assert lib.eco_world_create(d, 1, None, None, ctypes.byref(out)) == eco.ECO_EINVAL
+    assert out.value is None
