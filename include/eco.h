@@ -266,6 +266,20 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps);
  * A later eco_world_set_flags or eco_world_set_launch drops the built graphs. */
 eco_status eco_world_prepare(eco_world* w, uint32_t n_steps);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same n_steps steps
+ * as eco_world_step, enqueued eagerly on the object's stream with no
+ * allocation, no graph and no allocating library call.  The step's scratch
+ * (tile partials, birth lists, step counters: about 8 bytes per slot plus
+ * 128 bytes per 256-slot tile) lives in one static device array of 16 MiB per
+ * GPU, held until the process ends; an object that needs more gets EINVAL and
+ * nothing runs.  Every call on a GPU shares that GPU's array and nothing in it
+ * has to start cleared; calls that overlap on one GPU (objects stepped on
+ * different streams at once) race and must be serialised by the caller.
+ * Returns like eco_world_step (asynchronous; ECO_RT_TIME_KERNELS and
+ * ECO_RT_USE_GRAPH are ignored, ECO_RT_KEEP_LOGITS applies). */
+eco_status eco_world_step_static(eco_world* w, uint32_t n_steps);
+
 /* Re-initialise every world (the init of Sec. 3.3 and the placement of
  * Sec. 3.2: initial weights, positions, facings and resources, all from the
  * world's seed); seeds = NULL keeps each world's seed, else seeds[n_worlds]

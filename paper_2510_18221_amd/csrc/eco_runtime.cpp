@@ -30,6 +30,7 @@ hipError_t launch_birth_claim_regrow(hipStream_t s, const Dev& d, const TileScra
 hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
 hipError_t birth_commit_blocks_per_cu(const Layout& L, int* blocks);
+hipError_t static_scratch(void** ptr, size_t* bytes);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
 hipError_t launch_prestep_fill(hipStream_t s, const Dev& d);
 hipError_t launch_stream_read(hipStream_t s, const void* p, uint64_t n16, uint32_t* sink, uint32_t blocks,
@@ -428,19 +429,21 @@ const char* group_name(int k) {
     default: return "compaction kernels";
   }
 }
-hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, int k) {
+hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, const TileScratch& ts, int k) {
   switch (k) {
     case ECO_K_FORWARD: return launch_forward(w, s, d, w->launch);
-    case ECO_K_MOVE: return launch_move(s, d, w->ts);
-    case ECO_K_BIRTH_CLAIM: return launch_birth_claim_regrow(s, d, w->ts, w->L.A);
-    case ECO_K_BIRTH_SCAN: return launch_birth_rank(s, d, w->ts);
+    case ECO_K_MOVE: return launch_move(s, d, ts);
+    case ECO_K_BIRTH_CLAIM: return launch_birth_claim_regrow(s, d, ts, w->L.A);
+    case ECO_K_BIRTH_SCAN: return launch_birth_rank(s, d, ts);
     case ECO_K_BIRTH_COMMIT: return launch_birth_commit(s, d, w->L, birth_blocks(w));
-    default: return launch_compact(s, d, w->ts, 0, -1);
+    default: return launch_compact(s, d, ts, 0, -1);
   }
 }
 
 // Enqueue one step's kernels.  timed: bracket each kernel group with events.
-eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
+// ts: the tile partials the step's kernels use (the object's own, or the static
+// array's for eco_world_step_static).
+eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, const TileScratch& ts, bool timed) {
   if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
   for (int k : kStepGroups) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -450,7 +453,7 @@ eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, bool timed) {
       if (!a || !b) return dev_fail(w, hipErrorOutOfMemory, "timing events");
       HIPCHK(w, hipEventRecord(a, s), "event record");
     }
-    HIPCHK(w, launch_group(w, s, d, k), group_name(k));
+    HIPCHK(w, launch_group(w, s, d, ts, k), group_name(k));
     if (timed) {
       HIPCHK(w, hipEventRecord(b, s), "event record");
       w->ev_pending.push_back({k, {a, b}});
@@ -496,7 +499,7 @@ eco_status build_graph(eco_world* w) {
   d.dry = 0;
   d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
   HIPCHK(w, hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  eco_status st = enqueue_step(w, w->cap_stream, d, false);
+  eco_status st = enqueue_step(w, w->cap_stream, d, w->ts, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(w->cap_stream, &g);
   if (st != ECO_OK) {
@@ -530,7 +533,7 @@ eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {
   t.n = n;
   HIPCHK(w, hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   eco_status st = ECO_OK;
-  for (uint32_t i = 0; i < n && st == ECO_OK; ++i) st = enqueue_step(w, w->cap_stream, d, false);
+  for (uint32_t i = 0; i < n && st == ECO_OK; ++i) st = enqueue_step(w, w->cap_stream, d, w->ts, false);
   hipError_t e = hipStreamEndCapture(w->cap_stream, &t.graph);
   if (st != ECO_OK) {
     destroy_timed(t);
@@ -916,10 +919,61 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps) {
     return ECO_OK;
   }
   for (uint32_t i = 0; i < n_steps; ++i) {
-    st = enqueue_step(w, w->stream, d, timed);
+    st = enqueue_step(w, w->stream, d, w->ts, timed);
     if (st != ECO_OK) return st;
   }
   if (timed) return drain_events(w);
+  return ECO_OK;
+}
+
+eco_status eco_world_step_static(eco_world* w, uint32_t n_steps) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (n_steps == 0) return ECO_OK;
+  // the step's scratch, laid out in the static array (each part 256-aligned)
+  const uint64_t T = std::max(1u, w->n_slot_tiles), C = std::max(1u, w->n_cell_tiles);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = round_up(off + bytes, 256);
+    return o;
+  };
+  const uint64_t o_part_slot = take(4ull * kSlotPartH * T), o_part_cell = take(8ull * kCellPartH * C),
+                 o_scan = take(16 * T), o_esum = take(8 * T), o_tmean = take(8 * T), o_tm2 = take(8 * T),
+                 o_ecosum = w->L.ecology ? take(24 * T) : 0, o_bparent = take(4ull * w->total_slots),
+                 o_freel = take(4ull * w->total_slots), o_cnt = take(sizeof(StepCounters) * w->n_worlds);
+  void* base = nullptr;
+  size_t cap = 0;
+  HIPCHK(w, static_scratch(&base, &cap), "static scratch address");
+  if (off > cap) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "eco_world_step_static: the object needs %llu bytes of scratch, above the static "
+             "array's %llu", (unsigned long long)off, (unsigned long long)cap);
+    return fail(ECO_EINVAL, buf);
+  }
+  uint8_t* b = static_cast<uint8_t*>(base);
+  Dev d = w->d;
+  d.inject = 0;
+  d.dry = 0;
+  d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  d.bparent = reinterpret_cast<int32_t*>(b + o_bparent);
+  d.freel = reinterpret_cast<int32_t*>(b + o_freel);
+  d.cnt = reinterpret_cast<StepCounters*>(b + o_cnt);
+  TileScratch ts = w->ts;
+  ts.part_slot = reinterpret_cast<uint32_t*>(b + o_part_slot);
+  ts.part_cell = reinterpret_cast<unsigned long long*>(b + o_part_cell);
+  ts.scan = reinterpret_cast<uint32_t*>(b + o_scan);
+  ts.esum = reinterpret_cast<long long*>(b + o_esum);
+  ts.tmean = reinterpret_cast<double*>(b + o_tmean);
+  ts.tm2 = reinterpret_cast<double*>(b + o_tm2);
+  ts.ecosum = w->L.ecology ? reinterpret_cast<unsigned long long*>(b + o_ecosum) : nullptr;
+  // every part is written by the step before it is read (the tile counters by
+  // the move, claim and compaction passes, the birth lists and counters by the
+  // ranking pass), so nothing needs clearing between calls
+  for (uint32_t i = 0; i < n_steps; ++i) {
+    st = enqueue_step(w, w->stream, d, ts, false);
+    if (st != ECO_OK) return st;
+  }
   return ECO_OK;
 }
 
@@ -958,7 +1012,7 @@ eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions) {
   d.inject = 1;
   d.dry = 0;
   d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
-  st = enqueue_step(w, w->stream, d, false);
+  st = enqueue_step(w, w->stream, d, w->ts, false);
   if (st != ECO_OK) return st;
   return sync(w);
 }

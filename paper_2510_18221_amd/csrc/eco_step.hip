@@ -16,6 +16,8 @@
 //                  statistics (App. E measurement interface)
 // Every contended write is an atomicMin on a claim word; every other write goes
 // to a unique slot or cell, so the integer state is independent of scheduling.
+#include <mutex>
+
 #include "eco_device.h"
 
 namespace eco {
@@ -1478,6 +1480,37 @@ __global__ __launch_bounds__(512) void k_stream_read(const probe_u32x4* __restri
     acc ^= v.x ^ v.y ^ v.z ^ v.w;
   }
   if (acc == 0x9E3779B9u) *sink = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free step (eco_world_step_static): the tile
+// partials, birth lists and step counters of one object live in this array
+// instead of the object's own buffers.  Each GPU the library runs on holds one
+// copy until the process ends; every call on that GPU shares it.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// This GPU's address of the array (the array's name in host code is only a host
+// stand-in): looked up once per device, with that device current, and kept.
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex lock;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

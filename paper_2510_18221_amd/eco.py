@@ -24,7 +24,7 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
            "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps", "eco_world_read_colours",
-           "eco_world_write_colour", "eco_world_read_terrain", "eco_world_write_terrain"]
+           "eco_world_write_colour", "eco_world_read_terrain", "eco_world_write_terrain", "eco_world_step_static"]
 
 
 class EcoError(RuntimeError):
@@ -120,6 +120,7 @@ def lib():
         L.eco_world_destroy.argtypes = [P]
         L.eco_world_destroy.restype = None
         L.eco_world_step.argtypes = [P, U32]
+        L.eco_world_step_static.argtypes = [P, U32]
         L.eco_world_prepare.argtypes = [P, U32]
         L.eco_stream_read_gbps.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
         L.eco_world_reset.argtypes = [P, P]
@@ -241,6 +242,10 @@ class World:
     # -- stepping ---------------------------------------------------------
     def step(self, n=1):
         _err(lib().eco_world_step(self._h, n))
+
+    def step_static(self, n=1):
+        """eco_world_step_static: the same steps with the static scratch array (no allocation)."""
+        _err(lib().eco_world_step_static(self._h, n))
 
     def prepare(self, n=1):
         _err(lib().eco_world_prepare(self._h, n))
