@@ -64,12 +64,15 @@ def run_history(w, steps, s_end):
     return out
 
 
-def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None):
+TUNE_CACHE = os.path.join(ROOT, "paper_2510_18221_amd", "launch_cache.jsonl")
+
+
+def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None, tune_cache=None):
     import torch
     w = eco.World(cfg)
     if launch:
         w.set_launch(*launch)
-    tuned = w.autotune() if autotune else w.get_launch()
+    tuned = w.autotune(cache=tune_cache) if autotune else w.get_launch()
     # timed region: K steps replayed from the one-step hipGraph (the library's default path)
     w.set_flags(eco.RT_USE_GRAPH)
     w.prepare(1)
@@ -111,17 +114,20 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None):
     return res
 
 
-def trajectory(eco, cfg, steps, chunk=1000, out_path=None):
+def trajectory(eco, cfg, steps, chunk=1000, out_path=None, tune_cache=None):
     """Long free-running run: population, throughput and policy-kernel bandwidth per chunk
-    of steps (each chunk replayed from one graph with event nodes around the policy kernel)."""
+    of steps (each chunk replayed from one graph with event nodes around the policy kernel).
+    The launch shape is chosen again before each chunk for the live population of the
+    moment (the tuner's cache is keyed by its power-of-two bucket)."""
     import torch
     w = eco.World(cfg)
-    w.autotune()
     w.set_flags(eco.RT_USE_GRAPH | eco.RT_TIME_KERNELS)
     bytes_per_agent = w.info["weight_bytes_per_agent"] + STATE_BYTES_PER_AGENT
     rows = []
     for c0 in range(0, steps, chunk):
         n = min(chunk, steps - c0)
+        launch = w.autotune(cache=tune_cache)
+        w.set_flags(eco.RT_USE_GRAPH | eco.RT_TIME_KERNELS)
         w.prepare(n)
         w.kernel_times(reset=True)
         torch.cuda.synchronize()
@@ -136,7 +142,8 @@ def trajectory(eco, cfg, steps, chunk=1000, out_path=None):
                "births": sum(h["births"] for h in hist[1:]), "deaths": sum(h["deaths"] for h in hist[1:]),
                "agent_steps_per_s": round(agent_steps / dt, 1), "ms_per_step": round(dt * 1e3 / n, 4),
                "forward_GBps": round(agent_steps * bytes_per_agent / (fwd_ms * 1e-3) / 1e9, 1) if fwd_ms > 0 else 0.0,
-               "pop_min": min(h["population"] for h in hist), "pop_max": max(h["population"] for h in hist)}
+               "pop_min": min(h["population"] for h in hist), "pop_max": max(h["population"] for h in hist),
+               "launch": [launch["waves_per_block"], launch["blocks_per_cu"], launch["unroll"]]}
         rows.append(row)
         log(f"[trajectory] {row}")
     w.close()
@@ -272,7 +279,9 @@ def cpu_baseline(min_seconds=10.0, max_steps=100):
 
 WORKLOADS = {
     "65k": ("single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, 11x11x4 window + 8 "
-            "scalars, per-agent 492->64->64->7 MLP, FP32 weights, full dynamics", "f32"),
+            "scalars, per-agent 492->64->64->7 MLP, FP32 weights; every kernel of the step runs, but with energy "
+            "starting at 10, a cost of 0.1 per step and reproduction at 20 no agent is born or dies in the "
+            "timed steps (births and deaths are timed in the turnover and ecology variants)", "f32"),
     "batch": ("64 independent worlds in one object (one graph per step), sides log-uniform in [128, 1024], 6.25% "
               "occupancy (984,579 agents), capacity 1.125x, 492->64->64->7 BF16 weights + FP32 master", "bf16"),
     "large": ("single world 2048x2048, capacity 262,144 starting half full, density 0.03, regrowth 0.005, "
@@ -311,9 +320,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the launch shapes instead of taking them from the tuner's result cache")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="the tuner's result cache (JSON lines)")
     ap.add_argument("--wdtype", choices=["f32", "bf16", "fp8"], default=None,
                     help="weight storage of the 65k world's main line (default FP32, the metric's form)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 4 GiB device copy (PMC scaling)")
+    ap.add_argument("--agents", type=int, default=0,
+                    help="the 65k world's grid with this many agents instead, held (no cost, no births)")
     ap.add_argument("--launch", default=None, help="fixed policy-kernel launch 'waves_per_block,blocks_per_cu,unroll'")
     ap.add_argument("--trajectory", type=int, default=0, help="instead: free-run this many steps, report per 1000")
     ap.add_argument("--trajectory-out", default=None)
@@ -336,15 +350,19 @@ def main():
         log(f"[bench] device-copy ceiling {COPY_CEILING['gbps']} GB/s (reads + writes)")
 
     cfg = workload_cfg(wl, args.workload, args.wdtype)
+    if args.agents:
+        cfg = dict(wl.world_65k(seed=0, frozen=True, wdtype=cfg["wdtype"]), n_agents_init=args.agents)
     if args.trajectory:
-        rows = trajectory(eco, cfg, args.trajectory, chunk=args.trajectory_chunk, out_path=args.trajectory_out)
+        rows = trajectory(eco, cfg, args.trajectory, chunk=args.trajectory_chunk, out_path=args.trajectory_out,
+                          tune_cache=None if args.retune else args.tune_cache)
         print(json.dumps({"workload": args.workload, "trajectory": rows}), flush=True)
         return
 
     log(f"[bench] {args.workload}: warmup {args.warmup}, timed {args.steps}")
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     autotune = not args.no_autotune and launch is None
-    main_r = timed_run(eco, cfg, args.steps, args.warmup, autotune=autotune, launch=launch)
+    cache = None if args.retune else args.tune_cache
+    main_r = timed_run(eco, cfg, args.steps, args.warmup, autotune=autotune, launch=launch, tune_cache=cache)
     value = main_r["agent_steps"] / main_r["seconds"]
     ms_per_step = main_r["seconds"] * 1e3 / main_r["steps"]
     log(f"[bench] {args.workload}: {value / 1e6:.2f} M agent-steps/s, {ms_per_step:.3f} ms/step, "
@@ -408,7 +426,7 @@ def main():
                            ("fp32_terrain_rcv_a_7x7", ocean_cfg),
                            ("fp32_terrain_rcv_a_7x7_held", ocean_held_cfg)]:
             log(f"[bench] variant {name}")
-            r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch)
+            r = timed_run(eco, vcfg, args.steps, args.warmup, autotune=autotune, launch=launch, tune_cache=cache)
             v = r["agent_steps"] / r["seconds"]
             variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
                               "roofline": roofline(r, {"bf16": "65k_bf16", "fp8": "65k_fp8"}.get(name)),
@@ -416,11 +434,23 @@ def main():
                               "launch": r["launch"]}
             if vcfg.get("flags", 0) & eco.DESC_ECOLOGY or name.endswith("turnover"):
                 variants[name]["births_deaths"] = [r["births"], r["deaths"]]
-                variants[name]["birth_roofline"] = birth_roofline(r)
+                if r["eager"]["births"]:   # the birth kernel's rate, over the eager steps' births
+                    variants[name]["birth_roofline"] = birth_roofline(r)
             if vcfg.get("attack_enabled"):
                 # the predation measures of the paper's Table 3 over the timed steps
                 variants[name]["attacks_per_agent"] = round(r["attacks"] / max(r["agent_steps"], 1), 4)
                 variants[name]["homicides_per_attack"] = round(r["killed"] / max(r["attacks"], 1), 4)
+            log(f"[bench] {name}: {v / 1e6:.2f} M agent-steps/s")
+        # the batching pattern (64 independent worlds of uneven size, one graph per step) and the large world
+        for name, wname in [("batch64_bf16", "batch"), ("large2048_bf16", "large")]:
+            log(f"[bench] variant {name}")
+            r = timed_run(eco, workload_cfg(wl, wname), args.steps, args.warmup, autotune=autotune, launch=launch,
+                          tune_cache=cache)
+            v = r["agent_steps"] / r["seconds"]
+            variants[name] = {"value": round(v, 1), "ms_per_step": round(r["seconds"] * 1e3 / r["steps"], 4),
+                              "workload": WORKLOADS[wname][0],
+                              "roofline": roofline(r), "agents_start": r["pop_start"], "agents_end": r["pop_end"],
+                              "births_deaths": [r["births"], r["deaths"]], "launch": r["launch"]}
             log(f"[bench] {name}: {v / 1e6:.2f} M agent-steps/s")
         out["variants"] = variants
     if args.copy_probe:

@@ -308,6 +308,16 @@ eco_status eco_world_get_launch(const eco_world* w, eco_launch* out);
  * eleven rounds, and keep the shape with the lowest mean of the second pass.
  * Every candidate produces bit-identical actions.  *best may be NULL. */
 eco_status eco_world_autotune(eco_world* w, eco_launch* best);
+/* eco_world_autotune with a persistent result cache: a text file of JSON lines
+ * {"key": ..., "waves_per_block": .., "blocks_per_cu": .., "unroll": .., "ms": ..}.
+ * The key names what the choice depends on: the device architecture and CU
+ * count, the policy shape (D, H, A, window, storage type, window words, ninth
+ * row) and the live population rounded to a power of two.  A line with this
+ * object's key sets the launch without timing anything (*from_cache = 1);
+ * otherwise the shapes are timed as above and a line is appended (*from_cache
+ * = 0; a file that cannot be written is not an error).  path NULL: EINVAL.
+ * best and from_cache may be NULL. */
+eco_status eco_world_autotune_cached(eco_world* w, const char* path, eco_launch* best, int* from_cache);
 /* Accumulated per-kernel-group times of the steps run with ECO_RT_TIME_KERNELS
  * (milliseconds and launch counts); reset != 0 zeroes them after reading. */
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset);

@@ -1194,6 +1194,66 @@ eco_status eco_world_autotune(eco_world* w, eco_launch* best) {
   return ECO_OK;
 }
 
+eco_status eco_world_autotune_cached(eco_world* w, const char* path, eco_launch* best, int* from_cache) {
+  eco_status st = check_world(w);
+  if (st != ECO_OK) return st;
+  if (!path) return fail(ECO_EINVAL, "autotune cache path is NULL");
+  // the key: device, policy shape, live population (power-of-two bucket)
+  int dev = 0;
+  hipDeviceProp_t prop;
+  HIPCHK(w, hipGetDevice(&dev), "hipGetDevice");
+  HIPCHK(w, hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::vector<WorldVar> wv(w->n_worlds);
+  HIPCHK(w, hipMemcpyAsync(wv.data(), w->d.wv, sizeof(WorldVar) * w->n_worlds, hipMemcpyDeviceToHost, w->stream),
+         "read vars");
+  st = sync(w);
+  if (st != ECO_OK) return st;
+  uint64_t live = 0;
+  for (const auto& v : wv) live += v.n_live;
+  uint32_t lg = 0;
+  while ((2ull << lg) <= live) ++lg;   // live in [2^lg, 2^(lg+1)), 0 for none or one
+  const int words = (w->L.colour | w->L.ecology) != 0, nine = w->L.A + w->L.temp > 8;
+  char key[200];
+  snprintf(key, sizeof key, "%s cus=%d D=%u H=%u A=%u S=%u wdtype=%u words=%d nine=%d live=2^%u", arch.c_str(),
+           w->n_cus, w->L.D, w->L.H1, w->L.A, w->L.S, w->L.wdtype, words, nine, lg);
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[512];
+    eco_launch hit{};
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+      char k[200];
+      unsigned a = 0, b = 0, c = 0;
+      if (std::sscanf(line, " {\"key\": \"%199[^\"]\", \"waves_per_block\": %u, \"blocks_per_cu\": %u, \"unroll\": %u",
+                      k, &a, &b, &c) == 4 &&
+          std::strcmp(k, key) == 0) {
+        hit = eco_launch{a, b, c, 0};
+        found = true;   // the last matching line wins
+      }
+    }
+    std::fclose(f);
+    if (found) {
+      st = eco_world_set_launch(w, &hit);
+      if (st != ECO_OK) return st;
+      if (best) *best = hit;
+      if (from_cache) *from_cache = 1;
+      return ECO_OK;
+    }
+  }
+  eco_launch chosen{};
+  st = eco_world_autotune(w, &chosen);
+  if (st != ECO_OK) return st;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "{\"key\": \"%s\", \"waves_per_block\": %u, \"blocks_per_cu\": %u, \"unroll\": %u}\n", key,
+                 chosen.waves_per_block, chosen.blocks_per_cu, chosen.unroll);
+    std::fclose(f);
+  }
+  if (best) *best = chosen;
+  if (from_cache) *from_cache = 0;
+  return ECO_OK;
+}
+
 eco_status eco_world_kernel_times(eco_world* w, eco_kernel_times* out, int reset) {
   if (!w) return fail(ECO_EINVAL, "null world");
   eco_status st = drain_events(w);

@@ -727,7 +727,31 @@ __device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __rest
     else off = L.s_sc3 + (uint64_t)(r - 2 * H) * 4;
     *reinterpret_cast<float*>(sc + off) = scale;
   }
-  for (uint32_t u = tid; u < L.u_b3; u += 256) {
+  // W1: the four k-blocks of one 16-byte storage block of a row (k-blocks 4j .. 4j + 3,
+  // the missing ones of a row's last block zero) in one thread, written whole
+  constexpr uint32_t LG = H == 32 ? 5 : (H == 64 ? 6 : 7);
+  const uint32_t KB1 = L.KB1, nquads = ((KB1 + 3) >> 2) * H;
+#pragma unroll 1
+  for (uint32_t q = tid; q < nquads; q += 256) {
+    const uint32_t row = q & (H - 1), j = q >> LG;
+    const float amax = __uint_as_float(s_amax[row]);
+    const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+    uint32_t wq[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t kb = 4 * j + t;
+      wq[t] = 0u;
+      if (kb < KB1) {
+        const float4 m4 = mc[kb * H + row];
+        wq[t] = fp8_rne_sat(m4.x / scale) | (fp8_rne_sat(m4.y / scale) << 8) | (fp8_rne_sat(m4.z / scale) << 16) |
+                (fp8_rne_sat(m4.w / scale) << 24);
+      }
+    }
+    typedef unsigned int u32x4s __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(u32x4s{wq[0], wq[1], wq[2], wq[3]},
+                                reinterpret_cast<u32x4s*>(sc + L.s_w1 + ((uint64_t)j * H + row) * 16));
+  }
+  for (uint32_t u = L.u_b1 + tid; u < L.u_b3; u += 256) {
     const UnitPos up = unit_pos<H>(L, u);
     const int layer = up.layer;
     const uint32_t row = up.row, kb = up.kb;
@@ -792,9 +816,43 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
   // W1 (most of the units) without the layer decode, then the other layers
   constexpr uint32_t LG = H == 32 ? 5 : (H == 64 ? 6 : 7);
   const uint32_t ub1 = L.u_b1;
-  float4 next = tid < ub1 ? stream_load4(mp + tid) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (WDT == 1) {
+    // BF16: the two units of one 16-byte storage block (k-blocks 2j and 2j + 1 of a
+    // row) in one thread, so that the block is written whole and, like the
+    // master, streamed past the caches (the second half of a row's last block is
+    // padding when the row has an odd number of k-blocks: zero)
+    const uint32_t KB1 = L.KB1, npairs = ((KB1 + 1) >> 1) * H;
 #pragma unroll 1
-  for (uint32_t u = tid; u < ub1; u += 256) {
+    for (uint32_t q = tid; q < npairs; q += 256) {
+      const uint32_t row = q & (H - 1), j = q >> LG, kb0 = 2 * j;
+      const bool two = kb0 + 1 < KB1;
+      const uint32_t u0 = kb0 * H + row, u1 = u0 + H;
+      const float4 a = stream_load4(mp + u0);
+      const float4 b = two ? stream_load4(mp + u1) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const float pa[4] = {a.x, a.y, a.z, a.w}, pb[4] = {b.x, b.y, b.z, b.w};
+      float va[4], vb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      double z[4];
+      gauss4k(key0, key1, rng_slot, step, ST_MUTATE, row * KB1 + kb0, tab, z);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) va[i] = (float)__builtin_fma(sigma, z[i], (double)pa[i]);
+      if (two) {
+        gauss4k(key0, key1, rng_slot, step, ST_MUTATE, row * KB1 + kb0 + 1, tab, z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vb[i] = (float)__builtin_fma(sigma, z[i], (double)pb[i]);
+        stream_store4<WDT>(mc + u1, vb[0], vb[1], vb[2], vb[3]);
+      }
+      stream_store4<WDT>(mc + u0, va[0], va[1], va[2], va[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tsum += (double)va[i] * (double)va[i] + (double)vb[i] * (double)vb[i];
+      typedef unsigned int u32x4s __attribute__((ext_vector_type(4)));
+      const u32x4s blk = {bf16_rne(va[0]) | (bf16_rne(va[1]) << 16), bf16_rne(va[2]) | (bf16_rne(va[3]) << 16),
+                          bf16_rne(vb[0]) | (bf16_rne(vb[1]) << 16), bf16_rne(vb[2]) | (bf16_rne(vb[3]) << 16)};
+      __builtin_nontemporal_store(blk, reinterpret_cast<u32x4s*>(sc + L.s_w1 + ((uint64_t)j * H + row) * 16));
+    }
+  }
+  float4 next = (WDT != 1 && tid < ub1) ? stream_load4(mp + tid) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll 1
+  for (uint32_t u = WDT == 1 ? ub1 : tid; u < ub1; u += 256) {
     const float4 p4 = next;   // this unit's parent values, loaded one unit ahead
     if (u + 256 < ub1) next = stream_load4(mp + u + 256);
     const uint32_t row = u & (H - 1), kb = u >> LG;
@@ -820,10 +878,10 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
 }
 
 // One block per birth (persistent over all worlds' births).  Six waves per SIMD
-// (five with the FP8 copy and its row scales) fit without spilling; the noise
+// (five with a BF16 or FP8 copy to write) fit without spilling; the noise
 // arithmetic of the other waves hides each wave's parent reads.
 template <int WDT, int H>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 2 ? 5 : 6))) void k_birth_commit(Dev d, Layout L) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 0 ? 6 : 5))) void k_birth_commit(Dev d, Layout L) {
   __shared__ uint32_t off[kMaxWorlds + 1];
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];

@@ -24,7 +24,8 @@ EXPORTS = ["eco_world_create", "eco_world_destroy", "eco_last_error", "eco_world
            "eco_world_step_with_actions", "eco_world_state_bytes", "eco_world_read_state",
            "eco_world_write_state", "eco_world_read_logits", "eco_world_read_sampled", "eco_world_read_weights",
            "eco_world_write_weights", "eco_world_prepare", "eco_stream_read_gbps", "eco_world_read_colours",
-           "eco_world_write_colour", "eco_world_read_terrain", "eco_world_write_terrain", "eco_world_step_static"]
+           "eco_world_write_colour", "eco_world_read_terrain", "eco_world_write_terrain", "eco_world_step_static",
+           "eco_world_autotune_cached"]
 
 
 class EcoError(RuntimeError):
@@ -121,6 +122,7 @@ def lib():
         L.eco_world_destroy.restype = None
         L.eco_world_step.argtypes = [P, U32]
         L.eco_world_step_static.argtypes = [P, U32]
+        L.eco_world_autotune_cached.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_int)]
         L.eco_world_prepare.argtypes = [P, U32]
         L.eco_stream_read_gbps.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
         L.eco_world_reset.argtypes = [P, P]
@@ -291,10 +293,19 @@ class World:
         _err(lib().eco_world_get_launch(self._h, ctypes.byref(lc)))
         return dict(waves_per_block=lc.waves_per_block, blocks_per_cu=lc.blocks_per_cu, unroll=lc.unroll)
 
-    def autotune(self):
+    def autotune(self, cache=None):
+        """Tune the policy-kernel launch; cache: path of the result cache (JSON lines),
+        whose entry for this object's key is used instead of timing when present."""
         lc = Launch()
-        _err(lib().eco_world_autotune(self._h, ctypes.byref(lc)))
-        return dict(waves_per_block=lc.waves_per_block, blocks_per_cu=lc.blocks_per_cu, unroll=lc.unroll)
+        if cache is None:
+            _err(lib().eco_world_autotune(self._h, ctypes.byref(lc)))
+            hit = 0
+        else:
+            h = ctypes.c_int(0)
+            _err(lib().eco_world_autotune_cached(self._h, os.fsencode(cache), ctypes.byref(lc), ctypes.byref(h)))
+            hit = h.value
+        return dict(waves_per_block=lc.waves_per_block, blocks_per_cu=lc.blocks_per_cu, unroll=lc.unroll,
+                    **({"from_cache": bool(hit)} if cache is not None else {}))
 
     def kernel_times(self, reset=False):
         kt = KernelTimes()
