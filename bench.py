@@ -109,6 +109,8 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None, tune_cache=No
     res["kernel_times_eager"] = w.kernel_times(reset=True)
     res["eager"] = run_history(w, n_eager, s2 + n_eager)
     res["eager"]["steps"] = n_eager
+    # births of every step of the run, oldest first (the birth kernel's launches, one per step)
+    res["births_per_step"] = [h["births"] for h in w.stats_history(0, 1024)[1:]] if w.n_worlds == 1 else None
     w.close()
     torch.cuda.empty_cache()
     return res
@@ -389,6 +391,7 @@ def main():
     if args.workload == "turnover":
         out["config"]["births_deaths"] = [main_r["births"], main_r["deaths"]]
         out["birth_roofline"] = birth_roofline(main_r)
+        out["births_per_step"] = main_r["births_per_step"]
     if args.workload == "65k" and not args.no_variants:
         variants = {}
         attack_cfg = dict(wl.world_65k(seed=0), attack_enabled=1)

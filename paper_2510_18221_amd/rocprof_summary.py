@@ -1,6 +1,7 @@
 """Summarise rocprofv3 CSV output of this library's kernels into short markdown.
 
     python -m paper_2510_18221_amd.rocprof_summary stats   <kernel_stats.csv>
+    python -m paper_2510_18221_amd.rocprof_summary trace   <kernel_trace.csv> [--pattern k_forward]
     python -m paper_2510_18221_amd.rocprof_summary traffic <fetch counter_collection.csv> <write ...csv>
         [--copy-bytes N] [--kernel k_forward] [--algorithmic-bytes B]
 
@@ -36,6 +37,23 @@ def stats(path):
             name = name[:77] + "..."
         print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
               f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+
+
+def trace(path, pattern):
+    """Per-dispatch durations of the kernels whose name contains `pattern` (kernel
+    trace CSV): all launches, and the warm ones (every launch after the first of
+    each kernel, whose first launch pays for code loading and cold caches)."""
+    rows = [r for r in csv.DictReader(open(path)) if pattern in r["Kernel_Name"]]
+    by = collections.defaultdict(list)
+    for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
+        by[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print("| kernel | launches | mean us | warm launches | warm mean us | warm median us | min us |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for k, d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        warm = sorted(d[1:]) if len(d) > 1 else d
+        name = k if len(k) < 70 else k[:67] + "..."
+        print(f"| `{name}` | {len(d)} | {sum(d) / len(d):.1f} | {len(warm)} | {sum(warm) / len(warm):.1f} | "
+              f"{warm[len(warm) // 2]:.1f} | {min(d):.1f} |")
 
 
 def per_kernel(path, counter):
@@ -79,7 +97,8 @@ def traffic(fetch_csv, write_csv, copy_bytes, kernel, algorithmic):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "traffic"])
+    ap.add_argument("mode", choices=["stats", "traffic", "trace"])
+    ap.add_argument("--pattern", default="k_forward", help="trace: kernels whose name contains this")
     ap.add_argument("files", nargs="+")
     ap.add_argument("--copy-bytes", type=float, default=float(4 << 30))
     ap.add_argument("--kernel", default="k_forward")
@@ -87,6 +106,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.files[0])
+    elif a.mode == "trace":
+        trace(a.files[0], a.pattern)
     else:
         traffic(a.files[0], a.files[1], a.copy_bytes, a.kernel, a.algorithmic_bytes)
 
