@@ -93,40 +93,92 @@ __device__ __forceinline__ float dot_block<2>(u32x4 w, const float* __restrict__
   return acc;
 }
 
-// Streams one layer stored as [KB][ROWS] 16-byte blocks.  Lane l reads block
-// it*64 + l; ROWS = 64: row l, k-block it.  ROWS = 32: row l%32, k-block
-// 2it + l/32 (the two half-waves are summed afterwards).  ROWS = 128: row
-// l + 64 (it%2), k-block it/2 (two accumulators).  Accumulation order per
-// row is fixed by (ROWS, KB) only, never by U.
-template <int WDT, int ROWS, int U>
-__device__ __forceinline__ void stream_layer(const u32x4* __restrict__ blk, int KB, const float* __restrict__ xs,
-                                             int lane, float (&acc)[ROWS == 128 ? 2 : 1]) {
+// One layer of one agent as a stream of 16-byte blocks stored [KB][ROWS]: lane l
+// reads block it*64 + l of iteration it, so each load instruction of the wave
+// reads one contiguous kilobyte.  ROWS = 64: row l, k-block it.  ROWS = 32: row
+// l%32, k-block 2it + l/32 (the two half-waves are summed afterwards).  ROWS =
+// 128: row l + 64 (it%2), k-block it/2 (two accumulators).
+struct Seg {
+  const u32x4* blk;   // the layer's first block
+  int nblk;           // KB * ROWS blocks
+  int nit;            // ceil(nblk / 64) iterations
+};
+
+template <int ROWS>
+__device__ __forceinline__ Seg make_seg(const uint8_t* __restrict__ wbase, uint32_t off, int KB) {
+  Seg s;
+  s.blk = reinterpret_cast<const u32x4*>(wbase + off);
+  s.nblk = KB * ROWS;
+  s.nit = (s.nblk + 63) >> 6;
+  return s;
+}
+
+// The lane's block of iteration it.  With 32 rows an odd KB leaves the upper
+// half-wave of the last iteration past the layer: it re-reads the layer's last
+// block (that value is never used), so every load stays inside the layer.
+template <int ROWS>
+__device__ __forceinline__ u32x4 ld_block(const Seg& s, int it, int lane) {
+  int e = it * 64 + lane;
+  if (ROWS == 32) e = min(e, s.nblk - 1);
+  return __builtin_nontemporal_load(s.blk + e);
+}
+
+// acc += the products of block w of iteration it (u: it modulo the ring length,
+// which is even, so u % 2 == it % 2).  Accumulation order per row is fixed by
+// (ROWS, KB) only, never by the ring length.
+template <int WDT, int ROWS>
+__device__ __forceinline__ void consume_block(const u32x4& w, int it, int u, int KB, const float* __restrict__ xs,
+                                              int lane, float (&acc)[ROWS == 128 ? 2 : 1]) {
   constexpr int VPL = WTraits<WDT>::VPL;
+  if (ROWS == 64) {
+    acc[0] = dot_block<WDT>(w, xs + it * VPL, acc[0]);
+  } else if (ROWS == 32) {
+    const int kb = 2 * it + (lane >> 5);
+    if (kb < KB) acc[0] = dot_block<WDT>(w, xs + kb * VPL, acc[0]);
+  } else {
+    acc[u & 1] = dot_block<WDT>(w, xs + (it >> 1) * VPL, acc[u & 1]);
+  }
+}
+
+// Streams segment `cur` through a ring of U registers holding loads in flight.
+// The segment's iterations are taken in chunks of U (the last chunk padded): on
+// entry w[u] holds (or is loading) iteration u of cur; each block consumed is
+// replaced at once by the load of the iteration U further on, so the wave keeps
+// U loads in flight without draining between chunks, and the last chunk's
+// slots take iterations 0..U-1 of the next segment (the agent's second layer,
+// or the next agent's first layer), so the stream does not drain between layers
+// or agents either.  Padding iterations, and the next segment when there is
+// none, re-read the segment's last block (a cache hit, never used), so that
+// every slot issues exactly one load per chunk and no load sits in a branch.
+template <int WDT, int ROWS, int U>
+__device__ __forceinline__ void stream_seg(u32x4 (&w)[U], const Seg& cur, int KB, const float* __restrict__ xs,
+                                           int lane, float (&acc)[ROWS == 128 ? 2 : 1], const Seg& nxt,
+                                           bool has_nxt) {
   static_assert(U % 2 == 0, "U must be even");
-  const int nblk = KB * ROWS;
-  const int nit = (nblk + 63) >> 6;
-  for (int it0 = 0; it0 < nit; it0 += U) {
-    u32x4 w[U];
+  const int nit = cur.nit;
+  const int last = ((nit - 1) / U) * U;   // first iteration of the last chunk
+  int it0 = 0;
+  for (; it0 < last; it0 += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = ((it0 + u) << 6) + lane;
-      w[u] = (e < nblk) ? __builtin_nontemporal_load(blk + e) : u32x4{0u, 0u, 0u, 0u};
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int it = it0 + u;
-      if (it < nit) {
-        if (ROWS == 64) {
-          acc[0] = dot_block<WDT>(w[u], xs + it * VPL, acc[0]);
-        } else if (ROWS == 32) {
-          const int kb = 2 * it + (lane >> 5);
-          if (kb < KB) acc[0] = dot_block<WDT>(w[u], xs + kb * VPL, acc[0]);
-        } else {
-          acc[u & 1] = dot_block<WDT>(w[u], xs + (it >> 1) * VPL, acc[u & 1]);
-        }
-      }
+      consume_block<WDT, ROWS>(w[u], it0 + u, u, KB, xs, lane, acc);
+      w[u] = ld_block<ROWS>(cur, min(it0 + U + u, nit - 1), lane);
     }
   }
+  const Seg& t = has_nxt ? nxt : cur;
+  const int tl = has_nxt ? 0 : nit - 1;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (it0 + u < nit) consume_block<WDT, ROWS>(w[u], it0 + u, u, KB, xs, lane, acc);
+    w[u] = ld_block<ROWS>(t, has_nxt ? min(u, t.nit - 1) : tl, lane);
+  }
+}
+
+// The first blocks of a segment into an empty ring.
+template <int ROWS, int U>
+__device__ __forceinline__ void ring_start(u32x4 (&w)[U], const Seg& s, int lane) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) w[u] = ld_block<ROWS>(s, min(u, s.nit - 1), lane);
 }
 
 // Biases (BF16 for BF16 storage, FP32 otherwise) and FP8 row scales of one
@@ -167,17 +219,12 @@ __device__ __forceinline__ void load_tail(const uint8_t* __restrict__ wbase, con
   t.s3 = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[lane >> 3] : 0u;
 }
 
-// One hidden layer: streamed dot products, half-wave combine, scale, bias, ReLU,
-// result to LDS hs[0..ROWS).
-template <int WDT, int ROWS, int U>
-__device__ __forceinline__ void hidden_layer(const uint8_t* __restrict__ wbase, uint32_t w_off, int KB,
-                                             const float* __restrict__ xs, float* __restrict__ hs, int lane,
-                                             const uint32_t (&bias)[ROWS == 128 ? 2 : 1],
-                                             const uint32_t (&scale)[ROWS == 128 ? 2 : 1]) {
-  float acc[ROWS == 128 ? 2 : 1];
-#pragma unroll
-  for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) acc[r] = 0.0f;
-  stream_layer<WDT, ROWS, U>(reinterpret_cast<const u32x4*>(wbase + w_off), KB, xs, lane, acc);
+// Epilogue of one hidden layer: half-wave combine, scale, bias, ReLU, result to
+// LDS hs[0..ROWS).
+template <int WDT, int ROWS>
+__device__ __forceinline__ void layer_epilogue(float (&acc)[ROWS == 128 ? 2 : 1], float* __restrict__ hs, int lane,
+                                               const uint32_t (&bias)[ROWS == 128 ? 2 : 1],
+                                               const uint32_t (&scale)[ROWS == 128 ? 2 : 1]) {
   if (ROWS == 32) acc[0] += __shfl_xor(acc[0], 32);
 #pragma unroll
   for (int r = 0; r < (ROWS == 128 ? 2 : 1); ++r) {
@@ -471,12 +518,12 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
   wave_sync();
 }
 
-// At least three waves per SIMD (two for the 16-deep variants of the 128-wide
-// layers and of the word path, whose loads in flight need the registers): the
-// compiler's own register choice moves between these variants from build to
-// build, and a wave fewer costs more than the few registers it frees.
+// At least three waves per SIMD (two for the 16-deep rings, and the 8-deep ring
+// of the word path, whose loads in flight need the registers): the compiler's
+// own register choice moves between these variants from build to build, and a
+// wave fewer costs more than the few registers it frees.
 template <int H, int U, bool WORDS>
-constexpr int kMinWavesPerSimd = (U == 16 && (H == 128 || WORDS)) ? 2 : 3;
+constexpr int kMinWavesPerSimd = (U == 16 || (U == 8 && WORDS)) ? 2 : 3;
 
 // NINE: a ninth output row (the ecology with attack: a ninth action; with the
 // evolving temperature and eight actions: the log temperature), from
@@ -516,6 +563,10 @@ void k_forward(Dev d, Layout L) {
   AgentCtx cur = load_agent(d, woff, g_lo, find_world(woff, d.n_worlds, g_lo));
   uint32_t sv[kMaxWindowCellsPerLane];
   gather_sense<WORDS>(d, L, cur, lane, sv);
+  const int KB2 = (int)L.H1 / VPL;   // layer-2 k-blocks (H1 == H; a run-time value, so the compiler keeps the stream a loop)
+  // the weight stream: layer 1 and layer 2 of each agent in turn, U blocks in flight
+  u32x4 ring[U];
+  ring_start<H, U>(ring, make_seg<H>(d.store + (uint64_t)cur.slot * L.sstride, L.s_w1, (int)L.KBv), lane);
   for (uint32_t g = g_lo; g < g_hi; ++g) {
     const WorldParams& wp = cur.wp;
     // ---- 1. observation into LDS (window bytes fetched one agent ahead) ----
@@ -534,12 +585,18 @@ void k_forward(Dev d, Layout L) {
     const uint8_t* wbase = d.store + (uint64_t)cur.slot * L.sstride;
     Tail<WDT, H> tl;
     load_tail<WDT, H>(wbase, L, lane, tl);
-    hidden_layer<WDT, H, U>(wbase, L.s_w1, (int)L.KBv, xs, h1s, lane, tl.b1, tl.s1);
+    const Seg s1 = make_seg<H>(wbase, L.s_w1, (int)L.KBv), s2 = make_seg<H>(wbase, L.s_w2, KB2);
+    float acc1[H == 128 ? 2 : 1] = {};
+    stream_seg<WDT, H, U>(ring, s1, (int)L.KBv, xs, lane, acc1, s2, true);
+    layer_epilogue<WDT, H>(acc1, h1s, lane, tl.b1, tl.s1);
     W3<WDT, H> w3;
     load_w3<WDT, H>(wbase, L, lane, w3);
     Row9<WDT, H> r9;
     if (NINE) load_row9<WDT, H>(wbase, L, lane, r9);
-    hidden_layer<WDT, H, U>(wbase, L.s_w2, H / VPL, h1s, h2s, lane, tl.b2, tl.s2);
+    const Seg n1 = make_seg<H>(d.store + (uint64_t)nxt.slot * L.sstride, L.s_w1, (int)L.KBv);
+    float acc2[H == 128 ? 2 : 1] = {};
+    stream_seg<WDT, H, U>(ring, s2, KB2, h1s, lane, acc2, n1, has_next);
+    layer_epilogue<WDT, H>(acc2, h2s, lane, tl.b2, tl.s2);
     const float lg = output_layer<WDT, H>(w3, h2s, lane, tl.b3, tl.s3);
     const float l8 = NINE ? ninth_logit<WDT, H>(r9, h2s, lane) : 0.0f;
 
