@@ -163,6 +163,9 @@ __device__ __forceinline__ void stream_seg(u32x4 (&w)[U], const Seg& cur, int KB
     for (int u = 0; u < U; ++u) {
       consume_block<WDT, ROWS>(w[u], it0 + u, u, KB, xs, lane, acc);
       w[u] = ld_block<ROWS>(cur, min(it0 + U + u, nit - 1), lane);
+      // keeps the scheduler from unpacking blocks ahead of their turn, which
+      // doubles the registers a block holds and, at two waves per SIMD, spills
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   const Seg& t = has_nxt ? nxt : cur;
@@ -180,6 +183,26 @@ __device__ __forceinline__ void ring_start(u32x4 (&w)[U], const Seg& s, int lane
 #pragma unroll
   for (int u = 0; u < U; ++u) w[u] = ld_block<ROWS>(s, min(u, s.nit - 1), lane);
 }
+
+// A field of the kernel's by-value Dev argument, read from the kernel's argument
+// segment where it is used.  The argument segment holds the kernel's explicit
+// arguments in order, each at its natural alignment, so Dev (the first) starts
+// at offset 0.  The segment pointer passes through an empty asm statement first,
+// which the compiler cannot see through: each use is one scalar load from the
+// scalar cache, instead of a value hoisted to the kernel's entry and held in a
+// scalar register across the agent loop (the policy kernel reads some thirty
+// such pointers, more than the scalar registers hold, and the excess spilled).
+template <typename T>
+__device__ __forceinline__ T dev_arg(uint32_t offset) {
+  typedef const __attribute__((address_space(4))) uint8_t* seg_ptr;
+  seg_ptr p = (seg_ptr)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const __attribute__((address_space(4))) T*)(p + offset);
+}
+#define DEV_ARG(field) dev_arg<decltype(Dev::field)>(offsetof(Dev, field))
+// The same for the Layout argument, which follows Dev at Layout's alignment.
+constexpr uint32_t kLayoutArg = (sizeof(Dev) + alignof(Layout) - 1) / alignof(Layout) * alignof(Layout);
+#define LAYOUT_ARG(field) dev_arg<decltype(Layout::field)>(kLayoutArg + offsetof(Layout, field))
 
 // Biases (BF16 for BF16 storage, FP32 otherwise) and FP8 row scales of one
 // agent, loaded as raw words when the agent starts and converted where they are
@@ -210,13 +233,13 @@ __device__ __forceinline__ void load_tail(const uint8_t* __restrict__ wbase, con
 #pragma unroll
   for (int r = 0; r < Tail<WDT, H>::RPL; ++r) {
     const int j = (H == 32) ? (lane & 31) : lane + 64 * r;
-    t.b1[r] = load_bias_raw<WDT>(wbase + L.s_b1, j);
-    t.b2[r] = load_bias_raw<WDT>(wbase + L.s_b2, j);
-    t.s1[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc1)[j] : 0u;
-    t.s2[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc2)[j] : 0u;
+    t.b1[r] = load_bias_raw<WDT>(wbase + LAYOUT_ARG(s_b1), j);
+    t.b2[r] = load_bias_raw<WDT>(wbase + LAYOUT_ARG(s_b2), j);
+    t.s1[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + LAYOUT_ARG(s_sc1))[j] : 0u;
+    t.s2[r] = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + LAYOUT_ARG(s_sc2))[j] : 0u;
   }
-  t.b3 = load_bias_raw<WDT>(wbase + L.s_b3, lane >> 3);
-  t.s3 = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[lane >> 3] : 0u;
+  t.b3 = load_bias_raw<WDT>(wbase + LAYOUT_ARG(s_b3), lane >> 3);
+  t.s3 = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + LAYOUT_ARG(s_sc3))[lane >> 3] : 0u;
 }
 
 // Epilogue of one hidden layer: half-wave combine, scale, bias, ReLU, result to
@@ -253,7 +276,7 @@ __device__ __forceinline__ void load_w3(const uint8_t* __restrict__ wbase, const
   constexpr int NV = W3<WDT, H2>::NV, NW = W3<WDT, H2>::NW;
   constexpr int VB = (WDT == 0) ? 4 : (WDT == 1) ? 2 : 1;  // bytes per value
   const int first = (lane >> 3) * H2 + (lane & 7) * NV;
-  const uint8_t* p = wbase + L.s_w3 + (uint64_t)first * VB;  // 4 * NW bytes, aligned to min(16, 4 * NW)
+  const uint8_t* p = wbase + LAYOUT_ARG(s_w3) + (uint64_t)first * VB;  // 4 * NW bytes, aligned to min(16, 4 * NW)
   if (NW >= 4) {
 #pragma unroll
     for (int q = 0; q < NW / 4; ++q) {
@@ -317,13 +340,13 @@ __device__ __forceinline__ void load_row9(const uint8_t* __restrict__ wbase, con
   for (int r = 0; r < (H2 == 128 ? 2 : 1); ++r) {
     const uint32_t e = 8u * H2 + (uint32_t)(lane + 64 * r);   // element of row 8
     if (H2 == 32 && lane >= 32) o.w[r] = 0u;
-    else if (WDT == 0) o.w[r] = reinterpret_cast<const uint32_t*>(wbase + L.s_w3)[e];
-    else if (WDT == 1) o.w[r] = reinterpret_cast<const uint16_t*>(wbase + L.s_w3)[e];
-    else o.w[r] = (wbase + L.s_w3)[e];
+    else if (WDT == 0) o.w[r] = reinterpret_cast<const uint32_t*>(wbase + LAYOUT_ARG(s_w3))[e];
+    else if (WDT == 1) o.w[r] = reinterpret_cast<const uint16_t*>(wbase + LAYOUT_ARG(s_w3))[e];
+    else o.w[r] = (wbase + LAYOUT_ARG(s_w3))[e];
   }
-  o.b = load_bias_raw<WDT>(wbase + L.s_b3, 8);
-  o.s = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + L.s_sc3)[8] : 0u;
-  o.t = (L.temp && L.A > 8) ? load_bias_raw<WDT>(wbase + L.s_b3, 9) : 0u;
+  o.b = load_bias_raw<WDT>(wbase + LAYOUT_ARG(s_b3), 8);
+  o.s = (WDT == 2) ? reinterpret_cast<const uint32_t*>(wbase + LAYOUT_ARG(s_sc3))[8] : 0u;
+  o.t = (LAYOUT_ARG(temp) && LAYOUT_ARG(A) > 8) ? load_bias_raw<WDT>(wbase + LAYOUT_ARG(s_b3), 9) : 0u;
 }
 
 template <int WDT, int H2>
@@ -375,37 +398,39 @@ __device__ __forceinline__ T sload(const T* p) {
   return *(const __attribute__((address_space(4))) T*)(p);
 }
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ WorldParams sload_params(const WorldParams* p) {
-  static_assert(sizeof(WorldParams) % 4 == 0, "word-sized params");
-  WorldParams r;
-  uint32_t* o = reinterpret_cast<uint32_t*>(&r);
-  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(WorldParams) / 4); ++i) o[i] = sload(q + i);
-  return r;
-}
 
-// Uniform description of one agent of the wave's chunk.
+// Uniform description of one agent of the wave's chunk (with its world's grid;
+// the world's other parameters are read where they are used).
 struct AgentCtx {
-  WorldParams wp;
   uint32_t w, local, slot, step;
   int pos, facing, energy, age;
+  uint32_t W, H, cell_off;
 };
+
+// Field of world w's parameters, read from the scalar cache where it is used.
+template <typename T>
+__device__ __forceinline__ T world_param(uint32_t w, uint32_t offset) {
+  return sload(reinterpret_cast<const T*>(reinterpret_cast<const uint8_t*>(DEV_ARG(wp) + w) + offset));
+}
+#define WORLD_PARAM(w, field) world_param<decltype(WorldParams::field)>(w, offsetof(WorldParams, field))
 
 // Agent g of the step's live list (woff in LDS: exclusive world offsets); w is a
 // world index not past g's world.
-__device__ __forceinline__ AgentCtx load_agent(const Dev& d, const uint32_t* woff, uint32_t g, uint32_t w) {
+__device__ __forceinline__ AgentCtx load_agent(const uint32_t* woff, uint32_t g, uint32_t w) {
   while (g >= uni(woff[w + 1])) ++w;
   AgentCtx c;
   c.w = w;
-  c.wp = sload_params(d.wp + w);
-  c.local = (uint32_t)sload(d.live + c.wp.slot_off + (g - uni(woff[w])));
-  c.slot = c.wp.slot_off + c.local;
-  c.step = (uint32_t)sload(&d.wv[w].step);
-  c.pos = sload(d.pos + c.slot);
-  c.energy = sload(d.energy + c.slot);
-  c.age = sload(d.age + c.slot);
-  const uint32_t fw = sload(reinterpret_cast<const uint32_t*>(d.facing + (c.slot & ~3u)));
+  const uint32_t slot_off = WORLD_PARAM(w, slot_off);
+  c.W = WORLD_PARAM(w, W);
+  c.H = WORLD_PARAM(w, H);
+  c.cell_off = WORLD_PARAM(w, cell_off);
+  c.local = (uint32_t)sload(DEV_ARG(live) + slot_off + (g - uni(woff[w])));
+  c.slot = slot_off + c.local;
+  c.step = (uint32_t)sload(&DEV_ARG(wv)[w].step);
+  c.pos = sload(DEV_ARG(pos) + c.slot);
+  c.energy = sload(DEV_ARG(energy) + c.slot);
+  c.age = sload(DEV_ARG(age) + c.slot);
+  const uint32_t fw = sload(reinterpret_cast<const uint32_t*>(DEV_ARG(facing) + (c.slot & ~3u)));
   c.facing = (int)((fw >> (8 * (c.slot & 3u))) & 0xFFu);
   return c;
 }
@@ -423,10 +448,10 @@ constexpr int kEcoLane = 58;               // lanes 58..63 of the last window sl
 // as sense bytes; a compile-time choice, so the byte path carries none of the
 // word path's code.
 template <bool WORDS>
-__device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, const AgentCtx& c, int lane,
+__device__ __forceinline__ void gather_sense(const Layout& L, const AgentCtx& c, int lane,
                                              uint32_t (&sv)[kMaxWindowCellsPerLane]) {
-  const WorldParams& wp = c.wp;
-  const int S = (int)L.S, R = (int)L.R, SS = S * S;
+  const AgentCtx& wp = c;   // the world's grid
+  const int S = (int)LAYOUT_ARG(S), R = (int)LAYOUT_ARG(R), SS = S * S;
   const int ax = c.pos % (int)wp.W, ay = c.pos / (int)wp.W;
   const int dx = dir_dx(c.facing), dy = dir_dy(c.facing), rx = -dy, ry = dx;
 #pragma unroll
@@ -435,19 +460,20 @@ __device__ __forceinline__ void gather_sense(const Dev& d, const Layout& L, cons
     sv[k] = 0;
     if (i < SS) {
       const int r = i / S, col = i - r * S;
-      const int fw = (int)L.ahead0 - r, rt = col - R;
+      const int fw = (int)LAYOUT_ARG(ahead0) - r, rt = col - R;
       int cx = ax + fw * dx + rt * rx, cy = ay + fw * dy + rt * ry;
       if (cx < 0) cx += (int)wp.W; else if (cx >= (int)wp.W) cx -= (int)wp.W;
       if (cy < 0) cy += (int)wp.H; else if (cy >= (int)wp.H) cy -= (int)wp.H;
       const uint32_t cell = wp.cell_off + (uint32_t)cy * wp.W + (uint32_t)cx;
-      if constexpr (WORDS) sv[k] = d.rgb[cell];
-      else sv[k] = d.sense[cell];
-    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
+      if constexpr (WORDS) sv[k] = DEV_ARG(rgb)[cell];
+      else sv[k] = DEV_ARG(sense)[cell];
+    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && LAYOUT_ARG(ecology) && lane >= kEcoLane) {
       // ecology: the own cell's water, energy, biomass and the agent's water,
       // biomass, health ride in window slots no window reaches (S*S <= 225 < 250),
       // fetched with the window
       const int j = lane - kEcoLane;
-      const int32_t* src = j == 0 ? d.cw : j == 1 ? d.ce : j == 2 ? d.cb : j == 3 ? d.water : j == 4 ? d.biomass : d.hp;
+      const int32_t* src = j == 0 ? DEV_ARG(cw) : j == 1 ? DEV_ARG(ce) : j == 2 ? DEV_ARG(cb)
+                           : j == 3 ? DEV_ARG(water) : j == 4 ? DEV_ARG(biomass) : DEV_ARG(hp);
       sv[k] = (uint32_t)src[j < 3 ? wp.cell_off + (uint32_t)c.pos : c.slot];
     }
   }
@@ -468,10 +494,10 @@ __device__ __forceinline__ uint32_t window_word(const uint32_t (&sv)[kMaxWindowC
 template <bool WORDS>
 __device__ __forceinline__ void write_observation(const Layout& L, const AgentCtx& c, int lane,
                                                   const uint32_t (&sv)[kMaxWindowCellsPerLane], float* xs) {
-  const int SS = (int)(L.S * L.S);
-  const int centre = (int)(L.ahead0 * L.S + L.R);  // the agent's own cell
+  const int SS = (int)(LAYOUT_ARG(S) * LAYOUT_ARG(S));
+  const int centre = (int)(LAYOUT_ARG(ahead0) * LAYOUT_ARG(S) + LAYOUT_ARG(R));  // the agent's own cell
   // colour words carry the cell's sense bits and rock height in their top byte
-  const uint32_t here = (WORDS && L.colour) ? window_word(sv, centre) : 0u;
+  const uint32_t here = (WORDS && LAYOUT_ARG(colour)) ? window_word(sv, centre) : 0u;
   const int own_rock = (int)(here >> 27);
 #pragma unroll
   for (int k = 0; k < kMaxWindowCellsPerLane; ++k) {
@@ -481,7 +507,7 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
       float4 o;
       if constexpr (!WORDS) {
         o = make_float4((float)(v & 1u), (float)((v >> 1) & 1u), (float)((v >> 2) & 1u), (float)(v >> 3));
-      } else if (L.colour) {   // rendered colour; the elevation difference from the rock bits (0 without terrain)
+      } else if (LAYOUT_ARG(colour)) {   // rendered colour; the elevation difference from the rock bits (0 without terrain)
         o = make_float4(ldexpf((float)(v & 0xFFu), -8), ldexpf((float)((v >> 8) & 0xFFu), -8),
                         ldexpf((float)((v >> 16) & 0xFFu), -8), ldexpf((float)((int)(v >> 27) - own_rock), -3));
       } else {   // ecology: agent present, then the water, energy, biomass levels
@@ -489,7 +515,7 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
                         ldexpf((float)((v >> 16) & 0xFFu), -4));
       }
       reinterpret_cast<float4*>(xs)[i] = o;
-    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && L.ecology && lane >= kEcoLane) {
+    } else if (WORDS && k == kMaxWindowCellsPerLane - 1 && LAYOUT_ARG(ecology) && lane >= kEcoLane) {
       // fetched into this unused window slot: the own cell's levels (external
       // sensor, min(units, 255) * 2^-4) and the agent's water, biomass, health
       const int j = lane - kEcoLane, u = (int)sv[k];
@@ -500,30 +526,30 @@ __device__ __forceinline__ void write_observation(const Layout& L, const AgentCt
   const float res_here = (float)((here >> 25) & 1u);
 
   wave_sync();
-  if (WORDS && L.ecology) {
+  if (WORDS && LAYOUT_ARG(ecology)) {
     // internal: energy, age (here), water, biomass, health (written above by the
     // lanes that fetched them); external: the own cell's levels (written above);
     // the compass when n_s = 12
     if (lane < 2) xs[4 * SS + lane] = lane == 0 ? ldexpf((float)c.energy, -8) : ldexpf((float)min(c.age, 1024), -10);
-    else if (lane >= 8 && lane < (int)L.ns) xs[4 * SS + lane] = (lane - 8 == c.facing) ? 1.0f : 0.0f;
-  } else if (lane < (int)L.ns) {
+    else if (lane >= 8 && lane < (int)LAYOUT_ARG(ns)) xs[4 * SS + lane] = (lane - 8 == c.facing) ? 1.0f : 0.0f;
+  } else if (lane < (int)LAYOUT_ARG(ns)) {
     float v;
     if (lane == 0) v = ldexpf((float)c.energy, -8);
     else if (lane == 1) v = ldexpf((float)min(c.age, 1024), -10);
-    else if (lane == 2) v = (WORDS && L.colour) ? res_here : xs[4 * centre + 1];  // resource here: the own cell's resource
-    else if (lane == 3) v = (c.energy >= c.wp.e_repro) ? 1.0f : 0.0f;
+    else if (lane == 2) v = (WORDS && LAYOUT_ARG(colour)) ? res_here : xs[4 * centre + 1];  // resource here: the own cell's resource
+    else if (lane == 3) v = (c.energy >= WORLD_PARAM(c.w, e_repro)) ? 1.0f : 0.0f;
     else v = (lane - 4 == c.facing) ? 1.0f : 0.0f;
     xs[4 * SS + lane] = v;
   }
   wave_sync();
 }
 
-// At least three waves per SIMD (two for the 16-deep rings, and the 8-deep ring
-// of the word path, whose loads in flight need the registers): the compiler's
-// own register choice moves between these variants from build to build, and a
-// wave fewer costs more than the few registers it frees.
+// At least three waves per SIMD (two for the 8- and 16-deep rings of the word
+// path, whose loads in flight need the registers): the compiler's own register
+// choice moves between these variants from build to build, and a wave fewer
+// costs more than the few registers it frees.
 template <int H, int U, bool WORDS>
-constexpr int kMinWavesPerSimd = (U == 16 || (U == 8 && WORDS)) ? 2 : 3;
+constexpr int kMinWavesPerSimd = (U == 16 || (WORDS && U == 8)) ? 2 : 3;
 
 // NINE: a ninth output row (the ecology with attack: a ninth action; with the
 // evolving temperature and eight actions: the log temperature), from
@@ -554,21 +580,21 @@ void k_forward(Dev d, Layout L) {
 
   static_assert(WORDS || !NINE, "a ninth action needs the ecology's window words");
   constexpr int NA = NINE ? 9 : 8;   // the most actions this instantiation samples from
-  const int A = (int)L.A;
-  // Window cell ahead of the agent (row ahead0 - 1, column R), when the window has
-  // one: the move claim reads its agent and wall channels from the observation
-  // (with colour vision, from the sense bits of its rendered word).
-  const int front = (L.ahead0 >= 1) ? (int)((L.ahead0 - 1) * L.S + L.R) : -1;
 
-  AgentCtx cur = load_agent(d, woff, g_lo, find_world(woff, d.n_worlds, g_lo));
+  AgentCtx cur = load_agent(woff, g_lo, find_world(woff, d.n_worlds, g_lo));
   uint32_t sv[kMaxWindowCellsPerLane];
-  gather_sense<WORDS>(d, L, cur, lane, sv);
+  gather_sense<WORDS>(L, cur, lane, sv);
   const int KB2 = (int)L.H1 / VPL;   // layer-2 k-blocks (H1 == H; a run-time value, so the compiler keeps the stream a loop)
   // the weight stream: layer 1 and layer 2 of each agent in turn, U blocks in flight
   u32x4 ring[U];
   ring_start<H, U>(ring, make_seg<H>(d.store + (uint64_t)cur.slot * L.sstride, L.s_w1, (int)L.KBv), lane);
   for (uint32_t g = g_lo; g < g_hi; ++g) {
-    const WorldParams& wp = cur.wp;
+    const AgentCtx& wp = cur;   // the world's grid
+    // Window cell ahead of the agent (row ahead0 - 1, column R), when the window has
+    // one: the move claim reads its agent and wall channels from the observation
+    // (with colour vision, from the sense bits of its rendered word).
+    const uint32_t ahead0 = LAYOUT_ARG(ahead0);
+    const int front = (ahead0 >= 1) ? (int)((ahead0 - 1) * LAYOUT_ARG(S) + LAYOUT_ARG(R)) : -1;
     // ---- 1. observation into LDS (window bytes fetched one agent ahead) ----
     write_observation<WORDS>(L, cur, lane, sv, xs);
     const uint32_t front_word = (WORDS && front >= 0) ? window_word(sv, front) : 0u;
@@ -577,15 +603,15 @@ void k_forward(Dev d, Layout L) {
     AgentCtx nxt = cur;
     uint32_t sn[kMaxWindowCellsPerLane];
     if (has_next) {
-      nxt = load_agent(d, woff, g + 1, cur.w);
-      gather_sense<WORDS>(d, L, nxt, lane, sn);
+      nxt = load_agent(woff, g + 1, cur.w);
+      gather_sense<WORDS>(L, nxt, lane, sn);
     }
 
     // ---- 2. the agent's MLP, weights streamed once from HBM ----
-    const uint8_t* wbase = d.store + (uint64_t)cur.slot * L.sstride;
+    const uint8_t* wbase = DEV_ARG(store) + (uint64_t)cur.slot * LAYOUT_ARG(sstride);
     Tail<WDT, H> tl;
     load_tail<WDT, H>(wbase, L, lane, tl);
-    const Seg s1 = make_seg<H>(wbase, L.s_w1, (int)L.KBv), s2 = make_seg<H>(wbase, L.s_w2, KB2);
+    const Seg s1 = make_seg<H>(wbase, LAYOUT_ARG(s_w1), (int)L.KBv), s2 = make_seg<H>(wbase, LAYOUT_ARG(s_w2), KB2);
     float acc1[H == 128 ? 2 : 1] = {};
     stream_seg<WDT, H, U>(ring, s1, (int)L.KBv, xs, lane, acc1, s2, true);
     layer_epilogue<WDT, H>(acc1, h1s, lane, tl.b1, tl.s1);
@@ -593,7 +619,7 @@ void k_forward(Dev d, Layout L) {
     load_w3<WDT, H>(wbase, L, lane, w3);
     Row9<WDT, H> r9;
     if (NINE) load_row9<WDT, H>(wbase, L, lane, r9);
-    const Seg n1 = make_seg<H>(d.store + (uint64_t)nxt.slot * L.sstride, L.s_w1, (int)L.KBv);
+    const Seg n1 = make_seg<H>(DEV_ARG(store) + (uint64_t)nxt.slot * LAYOUT_ARG(sstride), LAYOUT_ARG(s_w1), (int)L.KBv);
     float acc2[H == 128 ? 2 : 1] = {};
     stream_seg<WDT, H, U>(ring, s2, KB2, h1s, lane, acc2, n1, has_next);
     layer_epilogue<WDT, H>(acc2, h2s, lane, tl.b2, tl.s2);
@@ -601,6 +627,7 @@ void k_forward(Dev d, Layout L) {
     const float l8 = NINE ? ninth_logit<WDT, H>(r9, h2s, lane) : 0.0f;
 
     // ---- 3. softmax inverse-CDF sample ----
+    const int A = (int)LAYOUT_ARG(A);
     float l[9];
 #pragma unroll
     for (int a = 0; a < 8; ++a) l[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lg), 8 * a));
@@ -616,7 +643,8 @@ void k_forward(Dev d, Layout L) {
     // ecology's eight actions), or bias slot 9 itself (its nine).  The largest
     // logits weigh exactly 1.
     float e_lane, inv_tau = 1.0f;
-    if (L.temp) {
+    const bool temp = LAYOUT_ARG(temp) != 0;
+    if (temp) {
       float lt = 0.0f;
 #pragma unroll
       for (int a = 0; a < 8; ++a)
@@ -637,10 +665,10 @@ void k_forward(Dev d, Layout L) {
     }
     if (NINE) {   // the ninth action's weight (zero when logit 8 is the log temperature)
       const float x8 = l8 - m;
-      wk[8] = (A > 8) ? (L.temp ? (x8 == 0.0f ? 1.0f : expf(x8 * inv_tau)) : expf(x8)) : 0.0f;
+      wk[8] = (A > 8) ? (temp ? (x8 == 0.0f ? 1.0f : expf(x8 * inv_tau)) : expf(x8)) : 0.0f;
       C[8] = accum + wk[8];
     }
-    const uint32_t x0 = draw32(wp, cur.local, cur.step, ST_ACTION);
+    const uint32_t x0 = philox10(cur.local, cur.step, ST_ACTION, 0u, WORLD_PARAM(cur.w, key0), WORLD_PARAM(cur.w, key1)).x;
     const float u = (float)(x0 >> 8) * 0x1p-24f;
     const float t = u * C[NA - 1];   // = C[A - 1]: the weights of actions >= A are zero
     int as = -1;
@@ -656,17 +684,17 @@ void k_forward(Dev d, Layout L) {
     // ---- 4. bookkeeping, turn, move claim (lane 0) ----
     const uint32_t slot = cur.slot;
     constexpr uint32_t lgs = NINE ? 16u : 8u;   // the logit buffer's stride (Dev::lgs)
-    if (d.keep_logits && (lane & 7) == 0) d.logits[(uint64_t)slot * lgs + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
-    if (NINE && d.keep_logits && lane == 0) d.logits[(uint64_t)slot * lgs + 8] = l8;
-    if (lane == 0 && d.dry) d.sampled[slot] = (uint8_t)as;
-    if (lane == 0 && !d.dry) {
-      const int a = d.inject ? (int)d.act_in[slot] : as;
+    if (DEV_ARG(keep_logits) && (lane & 7) == 0) DEV_ARG(logits)[(uint64_t)slot * lgs + (lane >> 3)] = ((lane >> 3) < A) ? lg : 0.0f;
+    if (NINE && DEV_ARG(keep_logits) && lane == 0) DEV_ARG(logits)[(uint64_t)slot * lgs + 8] = l8;
+    if (lane == 0 && DEV_ARG(dry)) DEV_ARG(sampled)[slot] = (uint8_t)as;
+    if (lane == 0 && !DEV_ARG(dry)) {
+      const int a = DEV_ARG(inject) ? (int)DEV_ARG(act_in)[slot] : as;
       const int f = cur.facing;
-      d.sampled[slot] = (uint8_t)as;
-      d.act[slot] = (uint8_t)a;
+      DEV_ARG(sampled)[slot] = (uint8_t)as;
+      DEV_ARG(act)[slot] = (uint8_t)a;
       int tg = -1;
-      if (a == TURN_L) d.facing[slot] = (uint8_t)((f + 3) & 3);
-      else if (a == TURN_R) d.facing[slot] = (uint8_t)((f + 1) & 3);
+      if (a == TURN_L) DEV_ARG(facing)[slot] = (uint8_t)((f + 3) & 3);
+      else if (a == TURN_R) DEV_ARG(facing)[slot] = (uint8_t)((f + 1) & 3);
       else if (a == FORWARD) {
         const uint32_t tc = neighbour(wp, (uint32_t)cur.pos, f, +1);
         bool free_cell;
@@ -675,14 +703,15 @@ void k_forward(Dev d, Layout L) {
         } else if (front >= 0) {  // the observation holds the cell ahead as seen at step start
           free_cell = xs[4 * front] == 0.0f && xs[4 * front + 2] == 0.0f;
         } else {
-          free_cell = d.occ[wp.cell_off + tc] == -1 && !(wp.has_walls && d.wall[wp.cell_off + tc]);
+          free_cell = DEV_ARG(occ)[wp.cell_off + tc] == -1 &&
+                      !(WORLD_PARAM(cur.w, has_walls) && DEV_ARG(wall)[wp.cell_off + tc]);
         }
         if (free_cell) {
-          atomicMin(&d.claim[wp.cell_off + tc], slot);
+          atomicMin(&DEV_ARG(claim)[wp.cell_off + tc], slot);
           tg = (int)tc;
         }
       }
-      d.tgt[slot] = tg;
+      DEV_ARG(tgt)[slot] = tg;
     }
     // An attacker (it neither turns nor moves) stamps the 3x3 square directly
     // ahead of it, rows 1..3 ahead, one column to either side, with this step;
@@ -694,8 +723,8 @@ void k_forward(Dev d, Layout L) {
     // once: lane (ahead, side) is cell (ahead mod Lf, side mod Lr) of the square,
     // Lf and Lr the torus lengths along and across the facing, so it repeats an
     // earlier lane exactly when side + 1 >= Lr or ahead > Lf (sides below 3).
-    if (wp.attack && !d.dry) {
-      const int a = d.inject ? (int)d.act_in[slot] : as;
+    if (WORLD_PARAM(cur.w, attack) && !DEV_ARG(dry)) {
+      const int a = DEV_ARG(inject) ? (int)DEV_ARG(act_in)[slot] : as;
       if (a == (NINE ? (int)ATTACK_ECO : (int)ATTACK) && lane < 9) {
         const int ahead = 1 + lane / 3, side = lane % 3 - 1;
         const uint32_t c = offset_cell(wp, (uint32_t)cur.pos, cur.facing, ahead, side);
@@ -705,8 +734,8 @@ void k_forward(Dev d, Layout L) {
           skip |= side + 1 >= lr || ahead > lf;
         }
         if (!skip) {
-          if (NINE) atomicAdd(&d.mark[wp.cell_off + c], 1u);
-          else d.mark[wp.cell_off + c] = cur.step + 1u;
+          if (NINE) atomicAdd(&DEV_ARG(mark)[wp.cell_off + c], 1u);
+          else DEV_ARG(mark)[wp.cell_off + c] = cur.step + 1u;
         }
       }
     }
