@@ -58,12 +58,13 @@ def test_validation_errors_without_device():
 
 
 def test_struct_sizes_match_header(tmp_path):
-    """The ctypes mirrors of eco_world_desc and eco_stats have the header's size and
+    """The ctypes mirrors of eco_world_desc, eco_stats and eco_launch have the header's size and
     field offsets (the header compiled by the host C compiler)."""
     import subprocess
     from paper_2510_18221_amd import eco
-    fields = {"Desc": [n for n, _ in eco.Desc._fields_], "Stats": [n for n, _ in eco.Stats._fields_]}
-    cname = {"Desc": "eco_world_desc", "Stats": "eco_stats"}
+    fields = {"Desc": [n for n, _ in eco.Desc._fields_], "Stats": [n for n, _ in eco.Stats._fields_],
+              "Launch": [n for n, _ in eco.Launch._fields_]}
+    cname = {"Desc": "eco_world_desc", "Stats": "eco_stats", "Launch": "eco_launch"}
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "eco.h"', "int main(void) {"]
     for k, names in fields.items():
         src.append(f'printf("{k} %zu\\n", sizeof({cname[k]}));')
