@@ -29,6 +29,7 @@ hipError_t launch_move(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_claim_regrow(hipStream_t s, const Dev& d, const TileScratch& ts, uint32_t A);
 hipError_t launch_birth_rank(hipStream_t s, const Dev& d, const TileScratch& ts);
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks);
+hipError_t launch_step_small(hipStream_t s, const Dev& d, const Layout& L);
 hipError_t birth_commit_blocks_per_cu(const Layout& L, int* blocks);
 hipError_t static_scratch(void** ptr, size_t* bytes);
 hipError_t launch_compact(hipStream_t s, const Dev& d, const TileScratch& ts, int init, int only_world);
@@ -440,11 +441,38 @@ hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, const TileScr
   }
 }
 
+// An object of one small world without the ecology steps with the policy kernel
+// and one fused launch (k_step_small) unless ECO_RT_SPLIT_STEP asks for the
+// separate kernels: its step is bound by launch latency, not by bytes.
+constexpr uint32_t kSmallSlots = 8192, kSmallCells = 16384;
+bool small_step(const eco_world* w) {
+  return w->n_worlds == 1 && !w->L.ecology && w->total_slots <= kSmallSlots && w->total_cells <= kSmallCells &&
+         !(w->rt_flags & ECO_RT_SPLIT_STEP);
+}
+
 // Enqueue one step's kernels.  timed: bracket each kernel group with events.
 // ts: the tile partials the step's kernels use (the object's own, or the static
 // array's for eco_world_step_static).
 eco_status enqueue_step(eco_world* w, hipStream_t s, const Dev& d, const TileScratch& ts, bool timed) {
   if (d.keep_logits) HIPCHK(w, launch_prestep_fill(s, d), "prestep fill");
+  if (small_step(w)) {   // the policy kernel, then the rest of the step in one launch (timed as MOVE)
+    for (int k : {ECO_K_FORWARD, ECO_K_MOVE}) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (timed) {
+        a = take_event(w);
+        b = take_event(w);
+        if (!a || !b) return dev_fail(w, hipErrorOutOfMemory, "timing events");
+        HIPCHK(w, hipEventRecord(a, s), "event record");
+      }
+      if (k == ECO_K_FORWARD) HIPCHK(w, launch_forward(w, s, d, w->launch), "forward kernel");
+      else HIPCHK(w, launch_step_small(s, d, w->L), "small-world step kernel");
+      if (timed) {
+        HIPCHK(w, hipEventRecord(b, s), "event record");
+        w->ev_pending.push_back({k, {a, b}});
+      }
+    }
+    return ECO_OK;
+  }
   for (int k : kStepGroups) {
     hipEvent_t a = nullptr, b = nullptr;
     if (timed) {
@@ -1090,7 +1118,8 @@ eco_status eco_world_info(const eco_world* w, eco_info* out) {
 
 eco_status eco_world_set_flags(eco_world* w, uint32_t flags) {
   if (!w) return fail(ECO_EINVAL, "null world");
-  if (flags & ~(ECO_RT_KEEP_LOGITS | ECO_RT_USE_GRAPH | ECO_RT_TIME_KERNELS)) return fail(ECO_EINVAL, "unknown flag");
+  if (flags & ~(ECO_RT_KEEP_LOGITS | ECO_RT_USE_GRAPH | ECO_RT_TIME_KERNELS | ECO_RT_SPLIT_STEP))
+    return fail(ECO_EINVAL, "unknown flag");
   if (flags != w->rt_flags) drop_graph(w);
   w->rt_flags = flags;
   return ECO_OK;

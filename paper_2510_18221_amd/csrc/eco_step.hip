@@ -332,6 +332,58 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
   return E;
 }
 
+// One live agent's move (a FORWARD winner takes its claimed cell), then EAT, the
+// step cost and death (Sec. 3.2), or with the ecology ecology_agent; counts into
+// the LDS counters cnt.  stamp: the attack stamp of this step (step + 1).
+__device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
+                                           uint32_t local, uint32_t stamp, uint32_t* cnt) {
+  const int a = d.act[slot];
+  atomicAdd(&cnt[PC_HIST + a], 1u);
+  int cell = d.pos[slot];
+  if (a == FORWARD) {
+    const int t = d.tgt[slot];
+    if (t >= 0 && d.claim[wp.cell_off + t] == slot) {
+      d.claim[wp.cell_off + t] = 0xFFFFFFFFu;
+      d.occ[wp.cell_off + cell] = -1;
+      d.occ[wp.cell_off + t] = (int)local;
+      cell = t;
+      d.pos[slot] = cell;
+      atomicAdd(&cnt[PC_MOVES_OK], 1u);
+    } else {
+      atomicAdd(&cnt[PC_MOVES_BLOCKED], 1u);
+    }
+  }
+  int E = d.energy[slot];
+  if (d.ep) {
+    const uint32_t g = wp.cell_off + (uint32_t)cell;
+    E = ecology_agent(d, d.ep[w], wp, slot, g, a, wp.attack ? d.mark[g] : 0u, cnt);
+  } else if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
+    // struck after the moves: dies where it stands; its carried energy goes
+    // back to the cell as one resource unit (cells hold 0 or 1 unit)
+    d.flags[slot] = 0;
+    d.occ[wp.cell_off + cell] = -1;
+    d.res[wp.cell_off + cell] = 1;
+    E = 0;
+    atomicAdd(&cnt[PC_DEATHS], 1u);
+    atomicAdd(&cnt[PC_KILLED], 1u);
+  } else {
+    if (a == EAT && d.res[wp.cell_off + cell] > 0) {
+      d.res[wp.cell_off + cell] -= 1;
+      E += wp.e_eat;
+      atomicAdd(&cnt[PC_EATEN], 1u);
+    }
+    E -= wp.e_cost;
+    if (E <= 0) {
+      d.flags[slot] = 0;
+      d.occ[wp.cell_off + cell] = -1;
+      atomicAdd(&cnt[PC_DEATHS], 1u);
+    } else {
+      d.age[slot] += 1;
+    }
+  }
+  d.energy[slot] = E;
+}
+
 __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restrict__ tiles, uint32_t* __restrict__ part) {
   __shared__ uint32_t cnt[kSlotPart];
   if (threadIdx.x < kSlotPart) cnt[threadIdx.x] = 0;
@@ -342,53 +394,7 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
   if (threadIdx.x < tl.count) {
     const uint32_t local = tl.start + threadIdx.x;
     const uint32_t slot = wp.slot_off + local;
-    if (d.flags[slot] & kAlive) {
-      const int a = d.act[slot];
-      atomicAdd(&cnt[PC_HIST + a], 1u);
-      int cell = d.pos[slot];
-      if (a == FORWARD) {
-        const int t = d.tgt[slot];
-        if (t >= 0 && d.claim[wp.cell_off + t] == slot) {
-          d.claim[wp.cell_off + t] = 0xFFFFFFFFu;
-          d.occ[wp.cell_off + cell] = -1;
-          d.occ[wp.cell_off + t] = (int)local;
-          cell = t;
-          d.pos[slot] = cell;
-          atomicAdd(&cnt[PC_MOVES_OK], 1u);
-        } else {
-          atomicAdd(&cnt[PC_MOVES_BLOCKED], 1u);
-        }
-      }
-      int E = d.energy[slot];
-      if (d.ep) {
-        const uint32_t g = wp.cell_off + (uint32_t)cell;
-        E = ecology_agent(d, d.ep[tl.world], wp, slot, g, a, wp.attack ? d.mark[g] : 0u, cnt);
-      } else if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
-        // struck after the moves: dies where it stands; its carried energy goes
-        // back to the cell as one resource unit (cells hold 0 or 1 unit)
-        d.flags[slot] = 0;
-        d.occ[wp.cell_off + cell] = -1;
-        d.res[wp.cell_off + cell] = 1;
-        E = 0;
-        atomicAdd(&cnt[PC_DEATHS], 1u);
-        atomicAdd(&cnt[PC_KILLED], 1u);
-      } else {
-        if (a == EAT && d.res[wp.cell_off + cell] > 0) {
-          d.res[wp.cell_off + cell] -= 1;
-          E += wp.e_eat;
-          atomicAdd(&cnt[PC_EATEN], 1u);
-        }
-        E -= wp.e_cost;
-        if (E <= 0) {
-          d.flags[slot] = 0;
-          d.occ[wp.cell_off + cell] = -1;
-          atomicAdd(&cnt[PC_DEATHS], 1u);
-        } else {
-          d.age[slot] += 1;
-        }
-      }
-      d.energy[slot] = E;
-    }
+    if (d.flags[slot] & kAlive) move_agent(d, wp, tl.world, slot, local, stamp, cnt);
   }
   __syncthreads();
   if (threadIdx.x < kSlotPart && threadIdx.x != PC_BB_CELL)   // the birth claims write PC_BB_CELL
@@ -398,34 +404,37 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
 // Eligible parents claim the empty cell directly behind them (slot tiles), and
 // in the same launch each cell tile regrows its empty cells (independent work:
 // regrowth reads and writes only the resource layer).
+// One slot's birth claim: an eligible live parent claims the empty cell directly
+// behind it (lowest slot wins, atomicMin); a parent whose cell behind is taken or
+// walled counts as blocked.
+__device__ __forceinline__ void birth_claim_slot(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
+                                                 uint32_t n_actions, uint32_t* blocked) {
+  const uint8_t fl = d.flags[slot];
+  if (!(fl & kAlive)) return;
+  bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
+  if (d.ep) {   // ecology: the eighth action, and spare biomass and water to give the child
+    const eco_ecology& e = d.ep[w];
+    eligible = d.act[slot] == REPRODUCE_ECO && d.energy[slot] >= wp.e_repro && d.water[slot] >= e.w_child &&
+               d.biomass[slot] >= e.b_repro;
+  }
+  if (eligible) {
+    const uint32_t t = neighbour(wp, (uint32_t)d.pos[slot], d.facing[slot], -1);
+    const bool walled = wp.has_walls && d.wall[wp.cell_off + t];
+    if (d.occ[wp.cell_off + t] == -1 && !walled) {
+      atomicMin(&d.claim[wp.cell_off + t], slot);
+      d.tgt[slot] = (int)t;
+      d.flags[slot] = fl | kBirthClaim;
+    } else {
+      atomicAdd(blocked, 1u);
+    }
+  }
+}
+
 __device__ __forceinline__ void birth_claim_tile(const Dev& d, const TileScratch& ts, uint32_t tile, uint32_t n_actions,
                                                  uint32_t* blocked) {
   const Tile tl = ts.slot_tiles[tile];
   const WorldParams wp = d.wp[tl.world];
-  if (threadIdx.x < tl.count) {
-    const uint32_t local = tl.start + threadIdx.x;
-    const uint32_t slot = wp.slot_off + local;
-    const uint8_t fl = d.flags[slot];
-    if (fl & kAlive) {
-      bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
-      if (d.ep) {   // ecology: the eighth action, and spare biomass and water to give the child
-        const eco_ecology& e = d.ep[tl.world];
-        eligible = d.act[slot] == REPRODUCE_ECO && d.energy[slot] >= wp.e_repro && d.water[slot] >= e.w_child &&
-                   d.biomass[slot] >= e.b_repro;
-      }
-      if (eligible) {
-        const uint32_t t = neighbour(wp, (uint32_t)d.pos[slot], d.facing[slot], -1);
-        const bool walled = wp.has_walls && d.wall[wp.cell_off + t];
-        if (d.occ[wp.cell_off + t] == -1 && !walled) {
-          atomicMin(&d.claim[wp.cell_off + t], slot);
-          d.tgt[slot] = (int)t;
-          d.flags[slot] = fl | kBirthClaim;
-        } else {
-          atomicAdd(blocked, 1u);
-        }
-      }
-    }
-  }
+  if (threadIdx.x < tl.count) birth_claim_slot(d, wp, tl.world, wp.slot_off + tl.start + threadIdx.x, n_actions, blocked);
   __syncthreads();
   if (threadIdx.x == 0) ts.part_slot[tile * kSlotPart + PC_BB_CELL] = *blocked;
 }
@@ -445,6 +454,30 @@ __device__ __forceinline__ uint64_t photo_threshold(float rate, int b) {
   if (k <= -64) return 0;
   const uint64_t v = mb >> (-k);
   return v > one ? one : v;
+}
+
+// Regrowth of the cells of tile tl (one resource layer): each empty cell regrows
+// one unit with probability p (a Philox draw against floor(p 2^32)); the regrown
+// count and the resource total go to cnt[0], cnt[1] (LDS).
+__device__ __forceinline__ bool regrows(const WorldParams& wp, uint32_t c, uint32_t step) {
+  return (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr;
+}
+
+__device__ __forceinline__ void regrow_cells(const Dev& d, const WorldParams& wp, const Tile tl, uint32_t step,
+                                             unsigned long long* cnt) {
+  unsigned long long grown = 0, total = 0;
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i;
+    uint8_t r = d.res[wp.cell_off + c];
+    if (r == 0 && regrows(wp, c, step)) {
+      r = 1;
+      d.res[wp.cell_off + c] = 1;
+      ++grown;
+    }
+    total += r;
+  }
+  if (grown) atomicAdd(&cnt[0], grown);
+  atomicAdd(&cnt[1], total);
 }
 
 __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile,
@@ -498,18 +531,7 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
     if (threadIdx.x < kCellPart) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
     return;
   }
-  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-    const uint32_t c = tl.start + i;
-    uint8_t r = d.res[wp.cell_off + c];
-    if (r == 0 && (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr) {
-      r = 1;
-      d.res[wp.cell_off + c] = 1;
-      ++grown;
-    }
-    total += r;
-  }
-  if (grown) atomicAdd(&cnt[0], grown);
-  atomicAdd(&cnt[1], total);
+  regrow_cells(d, wp, tl, step, cnt);
   __syncthreads();
   if (threadIdx.x < kCellPart) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
 }
@@ -877,6 +899,39 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
   if (tid == 0) d.trait[child] = t;
 }
 
+// Birth k of world w (the block's 256 threads): the parent bparent[k] places
+// its child in the free slot freel[k] (Sec. 3.2 reproduce, Sec. 3.3 mutation).
+template <int WDT, int H>
+__device__ __forceinline__ void commit_birth(const Dev& d, const Layout& L, uint32_t w, const WorldParams& wp,
+                                             uint32_t k, uint32_t step, const double2* tab, uint32_t* s_amax,
+                                             double* s_red) {
+  const uint32_t p_local = (uint32_t)d.bparent[wp.slot_off + k];
+  const uint32_t c_local = (uint32_t)d.freel[wp.slot_off + k];
+  const uint32_t pg = wp.slot_off + p_local, cg = wp.slot_off + c_local;
+  if (threadIdx.x == 0) {
+    const int t = d.tgt[pg];
+    d.energy[pg] -= wp.e_child;
+    d.flags[cg] = kAlive;
+    d.pos[cg] = t;
+    d.occ[wp.cell_off + t] = (int)c_local;
+    d.facing[cg] = d.facing[pg];
+    d.energy[cg] = wp.e_child;
+    d.age[cg] = 0;
+    d.uid[cg] = d.wv[w].uid_next + k;
+    d.puid[cg] = d.uid[pg];
+    if (d.ep) {   // ecology: the parent gives water and biomass; the child starts at hp_child
+      const eco_ecology& e = d.ep[w];
+      d.water[pg] -= e.w_child;
+      d.biomass[pg] -= e.b_child;
+      d.water[cg] = e.w_child;
+      d.biomass[cg] = e.b_child;
+      d.hp[cg] = e.hp_child;
+    }
+  }
+  mutate_child<WDT, H>(d, L, wp, cg, pg, p_local, step, tab, s_amax, s_red);
+  __syncthreads();
+}
+
 // One block per birth (persistent over all worlds' births).  Six waves per SIMD
 // (five with a BF16 or FP8 copy to write) fit without spilling; the noise
 // arithmetic of the other waves hides each wave's parent reads.
@@ -892,33 +947,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 0 ? 
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     const uint32_t w = find_world(off, d.n_worlds, g);
     const WorldParams wp = d.wp[w];
-    const uint32_t k = g - off[w];
-    const uint32_t p_local = (uint32_t)d.bparent[wp.slot_off + k];
-    const uint32_t c_local = (uint32_t)d.freel[wp.slot_off + k];
-    const uint32_t pg = wp.slot_off + p_local, cg = wp.slot_off + c_local;
-    const uint32_t step = (uint32_t)d.wv[w].step;
-    if (threadIdx.x == 0) {
-      const int t = d.tgt[pg];
-      d.energy[pg] -= wp.e_child;
-      d.flags[cg] = kAlive;
-      d.pos[cg] = t;
-      d.occ[wp.cell_off + t] = (int)c_local;
-      d.facing[cg] = d.facing[pg];
-      d.energy[cg] = wp.e_child;
-      d.age[cg] = 0;
-      d.uid[cg] = d.wv[w].uid_next + k;
-      d.puid[cg] = d.uid[pg];
-      if (d.ep) {   // ecology: the parent gives water and biomass; the child starts at hp_child
-        const eco_ecology& e = d.ep[w];
-        d.water[pg] -= e.w_child;
-        d.biomass[pg] -= e.b_child;
-        d.water[cg] = e.w_child;
-        d.biomass[cg] = e.b_child;
-        d.hp[cg] = e.hp_child;
-      }
-    }
-    mutate_child<WDT, H>(d, L, wp, cg, pg, p_local, step, tab, s_amax, s_red);
-    __syncthreads();
+    commit_birth<WDT, H>(d, L, w, wp, g - off[w], (uint32_t)d.wv[w].step, tab, s_amax, s_red);
   }
 }
 
@@ -1254,6 +1283,226 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   const uint32_t r = ol + block_exscan<kSlotTile>(alive ? 1u : 0u, red, &tot);
   if (alive) d.live[wp.slot_off + r] = (int)local;
   if (blockIdx.x + 1 == t1) world_finalize<kSlotTile>(d, ts, w, init);
+}
+
+// ---------------------------------------------------------------------------
+// The step after the policy kernel for an object of one small world, in one
+// block: moves, eating, costs and deaths, birth claims and regrowth, the birth
+// ranking, the births, the next live list with the statistics record, and the
+// next step's window channels (the same per-agent and per-cell rules as the
+// kernels above, with the world's scans done inside the block).  A small world's
+// step is bound by the latency of its launches, and this replaces seven
+// dependent launches by one.  Worlds with the ecology or terrain take the
+// separate kernels.  A thread scans a contiguous range of slots, so every scan
+// is one block-wide exclusive sum.
+// ---------------------------------------------------------------------------
+template <int WDT, int H>
+__global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
+  constexpr int NT = 256, CH = 16;   // threads; slots or cells per thread in one pass (one 16-byte load of bytes)
+  __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
+  __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
+  __shared__ uint32_t blocked, claims;
+  __shared__ uint32_t red[NT / 64 + 1];
+  __shared__ unsigned long long red64[NT / 64];
+  __shared__ double redm[NT / 64][3];
+  __shared__ uint32_t s_amax[128 + 128 + 16];
+  __shared__ double s_red[4];
+  __shared__ double2 tab[kTrigTable];
+  const uint32_t tid = threadIdx.x;
+  if (tid < kSlotPart) cnt[tid] = 0;
+  if (tid < kCellPart) ccnt[tid] = 0;
+  if (tid == 0) blocked = claims = 0;
+  __syncthreads();
+  constexpr uint32_t w = 0;
+  const WorldParams wp = d.wp[w];
+  const uint32_t step = (uint32_t)d.wv[w].step, n_live = d.wv[w].n_live, cap = wp.cap, cells = wp.cells;
+  const int32_t* live = d.live + wp.slot_off;
+  // each thread's contiguous range of the live list
+  const uint32_t per_l = (n_live + NT - 1) / NT;
+  const uint32_t l0 = min(tid * per_l, n_live), l1 = min(l0 + per_l, n_live);
+  // the 16 flag bytes of slots b0 .. b0 + 15 (slot and cell ranges start at multiples
+  // of 64 and their allocations end at one, so the 16-byte loads stay inside)
+  auto flags16 = [&](uint32_t b0) {
+    const uint4 v = *reinterpret_cast<const uint4*>(d.flags + wp.slot_off + b0);
+    return v;
+  };
+  auto byte_of = [](const uint4& v, int j) -> uint32_t {
+    const uint32_t wd = j < 4 ? v.x : (j < 8 ? v.y : (j < 12 ? v.z : v.w));
+    return (wd >> (8 * (j & 3))) & 0xFFu;
+  };
+
+  // 1. moves, eating, costs and deaths of the step's live agents
+  for (uint32_t i = l0; i < l1; ++i) {
+    const uint32_t local = (uint32_t)live[i];
+    move_agent(d, wp, w, wp.slot_off + local, local, step + 1u, cnt);
+  }
+  __syncthreads();
+  // 2. birth claims of the agents still alive; regrowth of every cell (16 per thread)
+  for (uint32_t i = l0; i < l1; ++i) birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
+  {
+    unsigned long long grown = 0, total = 0;
+    for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
+      uint4* rp = reinterpret_cast<uint4*>(d.res + wp.cell_off + c0);
+      const uint4 v = *rp;
+      uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+      bool changed = false;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const uint32_t c = c0 + j;
+        uint32_t r = (wd[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        if (c < cells && r == 0 && regrows(wp, c, step)) {
+          r = 1;
+          wd[j >> 2] |= 1u << (8 * (j & 3));
+          ++grown;
+          changed = true;
+        }
+        if (c < cells) total += r;
+      }
+      if (changed) *rp = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
+    if (grown) atomicAdd(&ccnt[0], grown);
+    atomicAdd(&ccnt[1], total);
+  }
+  __syncthreads();
+  // 3. birth ranking: the claim winners in slot order (the live list's order) ...
+  uint32_t nw = 0, nc = 0;
+  for (uint32_t i = l0; i < l1; ++i) {
+    const uint32_t slot = wp.slot_off + (uint32_t)live[i];
+    if (d.flags[slot] & kBirthClaim) {
+      ++nc;
+      if (d.claim[wp.cell_off + d.tgt[slot]] == slot) ++nw;
+    }
+  }
+  if (nc) atomicAdd(&claims, nc);
+  uint32_t Wn;
+  uint32_t k = block_exscan<NT>(nw, red, &Wn);
+  for (uint32_t i = l0; i < l1 && nw; ++i) {
+    const uint32_t local = (uint32_t)live[i], slot = wp.slot_off + local;
+    if ((d.flags[slot] & kBirthClaim) && d.claim[wp.cell_off + d.tgt[slot]] == slot) d.bparent[wp.slot_off + k++] = (int)local;
+  }
+  // ... and the free slots in ascending order (the recycled-slot free list; only
+  // its first Wn entries are used).  The claim flags and the claimed cells are
+  // cleared at the end of the step, by the last pass over the slots and the cells.
+  uint32_t F = 0;
+  for (uint32_t p0 = 0; p0 < cap; p0 += NT * CH) {
+    const uint32_t b0 = p0 + tid * CH;
+    uint32_t fm = 0;
+    if (b0 < cap) {
+      const uint4 v = flags16(b0);
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (b0 + j < cap && !(byte_of(v, j) & kAlive)) fm |= 1u << j;
+    }
+    uint32_t tot;
+    uint32_t f = F + block_exscan<NT>((uint32_t)__builtin_popcount(fm), red, &tot);
+    for (; fm && f < Wn; fm &= fm - 1) d.freel[wp.slot_off + f++] = (int)(b0 + __builtin_ctz(fm));
+    F += tot;
+  }
+  const uint32_t nb = min(Wn, F);
+  __syncthreads();
+  // 4. the births, one at a time (the angle table of the mutation noise only when there are any)
+  if (nb) load_trig(d.trig, tab);
+  for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H>(d, L, w, wp, b, step, tab, s_amax, s_red);
+  // 5. the next step's live list and the statistics record
+  uint32_t N = 0;
+  long long es = 0;
+  Moments tm{0.0, 0.0, 0.0};
+  for (uint32_t p0 = 0; p0 < cap; p0 += NT * CH) {
+    const uint32_t b0 = p0 + tid * CH;
+    uint32_t am = 0;
+    if (b0 < cap) {
+      const uint4 v = flags16(b0);
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (b0 + j < cap && (byte_of(v, j) & kAlive)) am |= 1u << j;
+      // the step's birth-claim flags cleared (a flag byte is 0 or alive, after the step)
+      constexpr uint32_t claim_bits = 0x01010101u * (kBirthClaim | kBirthWon);
+      if ((v.x | v.y | v.z | v.w) & claim_bits)
+        *reinterpret_cast<uint4*>(d.flags + wp.slot_off + b0) =
+            make_uint4(v.x & ~claim_bits, v.y & ~claim_bits, v.z & ~claim_bits, v.w & ~claim_bits);
+      int32_t e[CH];
+      double t[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        e[j] = (am >> j) & 1u ? d.energy[wp.slot_off + b0 + j] : 0;
+        t[j] = (am >> j) & 1u ? d.trait[wp.slot_off + b0 + j] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if ((am >> j) & 1u) {
+          es += e[j];
+          tm = merge_moments(tm, Moments{1.0, t[j], 0.0});
+        }
+    }
+    uint32_t tot;
+    uint32_t r = N + block_exscan<NT>((uint32_t)__builtin_popcount(am), red, &tot);
+    for (; am; am &= am - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(am));
+    N += tot;
+  }
+  const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
+  const Moments TM = block_merge_moments<NT>(tm, redm);
+  if (tid == 0) {
+    WorldVar& v = d.wv[w];
+    v.n_births = nb;
+    v.n_win = Wn;
+    v.step += 1;
+    v.uid_next += nb;
+    v.n_live = N;
+    d.cnt[w].births = nb;
+    d.cnt[w].births_blocked_cell = claims - Wn;
+    d.cnt[w].births_blocked_capacity = Wn - nb;
+    eco_stats st = {};
+    st.step = v.step;
+    st.population = N;
+    st.births = nb;
+    st.births_blocked_cell = claims - Wn + blocked;
+    st.births_blocked_capacity = Wn - nb;
+    st.deaths = cnt[PC_DEATHS];
+    st.killed = cnt[PC_KILLED];
+    st.eaten = cnt[PC_EATEN];
+    st.moves_ok = cnt[PC_MOVES_OK];
+    st.moves_blocked = cnt[PC_MOVES_BLOCKED];
+    for (int a = 0; a < 9; ++a) st.action_hist[a] = cnt[PC_HIST + a];
+    st.regrown = ccnt[0];
+    st.resource_total = ccnt[1];
+    st.energy_total = (double)(long long)E;
+    st.trait_mean = N ? TM.mean : 0.0;
+    st.trait_var = N ? TM.m2 / (double)N : 0.0;
+    d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
+  }
+  // the step's claimed cells released (every claim word back to "none": the
+  // movers' winners released theirs in the move phase, the births' here)
+  for (uint32_t c0 = tid * 4; c0 < cells; c0 += NT * 4)
+    *reinterpret_cast<uint4*>(d.claim + wp.cell_off + c0) = make_uint4(~0u, ~0u, ~0u, ~0u);
+  // the window channels of every cell for the next step (the grid is final): 16
+  // cells per thread, their occupancy, resource and wall bytes in four loads
+  if (d.rgb) {
+    cell_render_tile(d, Tile{w, 0u, cells, 0u});
+  } else {
+    for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
+      const uint32_t g = wp.cell_off + c0;
+      int o[CH];
+#pragma unroll
+      for (int q = 0; q < CH / 4; ++q) {
+        const int4 v = *reinterpret_cast<const int4*>(d.occ + g + 4 * q);
+        o[4 * q] = v.x;
+        o[4 * q + 1] = v.y;
+        o[4 * q + 2] = v.z;
+        o[4 * q + 3] = v.w;
+      }
+      const uint4 rv = *reinterpret_cast<const uint4*>(d.res + g);
+      const uint4 wv4 = *reinterpret_cast<const uint4*>(d.wall + g);
+      uint32_t sw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (c0 + j < cells) sw[j >> 2] |= sense_of(wp, d, o[j], byte_of(rv, j), byte_of(wv4, j)) << (8 * (j & 3));
+      if (c0 + CH <= cells) {
+        *reinterpret_cast<uint4*>(d.sense + g) = make_uint4(sw[0], sw[1], sw[2], sw[3]);
+      } else {
+        for (uint32_t j = 0; c0 + j < cells; ++j) d.sense[g + j] = (uint8_t)(sw[j >> 2] >> (8 * (j & 3)));
+      }
+    }
+  }
 }
 
 // Rendered window words of one world's cells (after a colour write).
@@ -1613,6 +1862,18 @@ void launch_birth_commit_w(hipStream_t s, const Dev& d, const Layout& L, uint32_
   if (L.H1 == 32) hipLaunchKernelGGL((k_birth_commit<WDT, 32>), dim3(blocks), dim3(256), 0, s, d, L);
   else if (L.H1 == 64) hipLaunchKernelGGL((k_birth_commit<WDT, 64>), dim3(blocks), dim3(256), 0, s, d, L);
   else hipLaunchKernelGGL((k_birth_commit<WDT, 128>), dim3(blocks), dim3(256), 0, s, d, L);
+}
+hipError_t launch_step_small(hipStream_t s, const Dev& d, const Layout& L) {
+  if (L.H1 != L.H2 || (L.H1 != 32 && L.H1 != 64 && L.H1 != 128)) return hipErrorInvalidValue;
+#define ECO_SMALL(WW)                                                                                             \
+  if (L.H1 == 32) hipLaunchKernelGGL((k_step_small<WW, 32>), dim3(1), dim3(256), 0, s, d, L, L.A);               \
+  else if (L.H1 == 64) hipLaunchKernelGGL((k_step_small<WW, 64>), dim3(1), dim3(256), 0, s, d, L, L.A);          \
+  else hipLaunchKernelGGL((k_step_small<WW, 128>), dim3(1), dim3(256), 0, s, d, L, L.A);
+  if (L.wdtype == 0) { ECO_SMALL(0) }
+  else if (L.wdtype == 1) { ECO_SMALL(1) }
+  else { ECO_SMALL(2) }
+#undef ECO_SMALL
+  ECO_CHECK_LAUNCH();
 }
 hipError_t launch_birth_commit(hipStream_t s, const Dev& d, const Layout& L, uint32_t blocks) {
   if (L.H1 != L.H2 || (L.H1 != 32 && L.H1 != 64 && L.H1 != 128)) return hipErrorInvalidValue;

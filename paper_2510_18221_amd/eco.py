@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeco.so")
 
 ECO_OK, ECO_EINVAL, ECO_ENOMEM, ECO_EDEVICE, ECO_ESTATE, ECO_ENOTSUP = 0, -1, -2, -3, -4, -5
-RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS = 1, 2, 4
+RT_KEEP_LOGITS, RT_USE_GRAPH, RT_TIME_KERNELS, RT_SPLIT_STEP = 1, 2, 4, 8
 DESC_FRONT_VISION, DESC_EVOLVE_TEMPERATURE, DESC_COLOUR_VISION, DESC_ECOLOGY, DESC_TERRAIN = 1, 2, 4, 8, 16
 KERNELS = ["forward", "move", "birth_claim", "birth_scan", "birth_commit", "regrow", "compact", "sense"]
 

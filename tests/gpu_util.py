@@ -72,16 +72,18 @@ def compare_world(gw, ow, what, world=0, weights_slots=8):
     return gs
 
 
-def run_pair(eco, cfg, steps, actions_fn=None, check_logits=True, what="", every=1, launch=None):
+def run_pair(eco, cfg, steps, actions_fn=None, check_logits=True, what="", every=1, launch=None, flags=0):
     """Step GPU and oracle together.  actions_fn(step) -> actions, or None for the
     oracle's own sampled actions, which are injected into the GPU world.
-    launch: optional policy-kernel shape (waves per block, blocks per CU, unroll)."""
+    launch: optional policy-kernel shape (waves per block, blocks per CU, unroll).
+    flags: runtime flags added to RT_KEEP_LOGITS (RT_SPLIT_STEP: a small world's
+    step as separate kernels instead of the fused launch)."""
     from oracle import oracle as orc
     ow = orc.OracleWorld(cfg)
     gw = eco.World(cfg)
     if launch:
         gw.set_launch(*launch)
-    gw.set_flags(eco.RT_KEEP_LOGITS)
+    gw.set_flags(eco.RT_KEEP_LOGITS | flags)
     compare_world(gw, ow, f"{what} init")
     assert_stats_match(gw.stats()[0], ow.stats(), f"{what} init")
     worst = 0.0

@@ -1,0 +1,128 @@
+"""The fused small-world step (k_step_small: one launch after the policy kernel for
+an object of one world without the ecology, at most 8,192 slots and 16,384 cells)
+against the separate kernels (ECO_RT_SPLIT_STEP) and against the oracle.
+
+The fused launch applies the same per-agent and per-cell rules and does the
+world's scans inside one block, so the integer state, the weights, the logits and
+every integer statistic are identical to the separate kernels' step for step;
+only the trait moments, merged in another order, may differ in the last bits.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_18221_amd import eco as eco_mod
+from paper_2510_18221_amd import workloads as wl
+
+from gpu_util import need_gpu, run_pair, say
+from worldstate import assert_same_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eco():
+    need_gpu()
+    from paper_2510_18221_amd import eco as m
+    m.lib()
+    return m
+
+
+def busy(**kw):
+    """A small world with births every step: agents start at the reproduction
+    threshold and the step costs nothing, so parents reproduce whenever the cell
+    behind is free and newborns (born with no energy) die at their first step."""
+    base = dict(width=24, height=20, n_agents_init=120, capacity=300, resource_density=0.3, regrow_prob=0.05,
+                mutation_sigma=0.05, window=5, n_scalars=8, hidden1=32, hidden2=32, n_actions=7, e_init=200,
+                e_cost=0, e_child=0, seed=11)
+    base.update(kw)
+    return wl.desc(**base)
+
+
+CASES = {
+    "config1": wl.world_small(seed=3),
+    "busy_fp32": busy(),
+    "busy_bf16": busy(wdtype=wl.BF16, seed=12),
+    "busy_fp8_h64": busy(wdtype=wl.FP8, hidden1=64, hidden2=64, seed=13),
+    "busy_h128_a5": busy(hidden1=128, hidden2=128, n_actions=5, window=3, n_scalars=4, seed=14),
+    "attack": busy(attack_enabled=1, e_init=150, e_cost=1, e_child=40, seed=15),
+    "colour_temp": busy(flags=eco_mod.DESC_COLOUR_VISION | eco_mod.DESC_EVOLVE_TEMPERATURE, seed=16),
+    "full_capacity": busy(n_agents_init=200, capacity=200, seed=17),
+}
+
+
+def trait_close(a, b):
+    return abs(a - b) <= 1e-12 * max(abs(a), abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fused_equals_split(eco, name):
+    cfg = CASES[name]
+    steps = 25
+    fused, split = eco.World(cfg), eco.World(cfg)
+    fused.set_flags(eco.RT_KEEP_LOGITS | eco.RT_USE_GRAPH)
+    split.set_flags(eco.RT_KEEP_LOGITS | eco.RT_USE_GRAPH | eco.RT_SPLIT_STEP)
+    births = 0
+    for t in range(steps):
+        fused.step(1)
+        split.step(1)
+        a, b = fused.read_state(), split.read_state()
+        assert_same_state(a, b, f"{name} step {t}")
+        np.testing.assert_array_equal(fused.read_logits(), split.read_logits())
+        sa, sb = fused.stats()[0], split.stats()[0]
+        for k, v in sa.items():
+            if k in ("trait_mean", "trait_var"):
+                assert trait_close(v, sb[k]), (name, t, k, v, sb[k])
+            else:
+                assert v == sb[k], (name, t, k, v, sb[k])
+        births += sa["births"]
+    live = np.nonzero(a["alive"])[0]
+    for s in live[:: max(1, len(live) // 6)]:
+        for master in (True, False):
+            np.testing.assert_array_equal(fused.read_weights(int(s), master=master),
+                                          split.read_weights(int(s), master=master))
+    fused.close()
+    split.close()
+    say(f"{name}: {steps} steps, {births} births, fused == split")
+    if name.startswith("busy"):
+        assert births > 0
+
+
+def test_fused_path_is_the_one_that_runs(eco):
+    """Kernel-group timers: the fused launch is timed as MOVE, with no separate
+    birth-claim, ranking, commit or compaction launches; RT_SPLIT_STEP runs them."""
+    cfg = CASES["busy_fp32"]
+    for flags, fused in ((eco.RT_TIME_KERNELS, True), (eco.RT_TIME_KERNELS | eco.RT_SPLIT_STEP, False)):
+        w = eco.World(cfg)
+        w.set_flags(flags)
+        w.step(3)
+        kt = w.kernel_times(reset=True)
+        w.close()
+        assert kt["forward"][1] == 3 and kt["move"][1] == 3
+        for k in ("birth_claim", "birth_scan", "birth_commit", "compact"):
+            assert (kt[k][1] == 0) == fused, (flags, k, kt[k])
+
+
+def test_large_object_takes_the_split_kernels(eco):
+    cfg = busy(width=160, height=128, n_agents_init=2000, capacity=4000, seed=18)   # 20,480 cells: above the limit
+    w = eco.World(cfg)
+    w.set_flags(eco.RT_TIME_KERNELS)
+    w.step(2)
+    kt = w.kernel_times(reset=True)
+    w.close()
+    assert kt["compact"][1] == 2
+
+
+@pytest.mark.parametrize("name", ["config1", "busy_bf16"])
+def test_split_kernels_match_oracle_on_small_worlds(eco, name):
+    """The separate kernels keep their oracle parity on small worlds too."""
+    cfg = CASES[name]
+    acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 7, t, p_forward=0.35, p_eat=0.3)
+    run_pair(eco, cfg, 8, actions_fn=acts, what=f"split {name}", flags=eco.RT_SPLIT_STEP)
+
+
+@pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64"])
+def test_fused_matches_oracle(eco, name):
+    cfg = CASES[name]
+    acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 5, t, p_forward=0.3, p_eat=0.3,
+                                       **({"p_attack": 0.1} if cfg.get("attack_enabled") else {}))
+    run_pair(eco, cfg, 10, actions_fn=acts, what=f"fused {name}")
