@@ -736,11 +736,11 @@ __device__ __forceinline__ void store_unit(const Layout& L, uint8_t* sc, int lay
 // FP8 storage, after store_unit has gathered each row's amax in s_amax: the row
 // scales, then the weights quantised with them (each thread re-reads the master
 // units it wrote itself).
-template <int H>
+template <int H, int NT>
 __device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __restrict__ mc, uint8_t* sc,
                                            const uint32_t* s_amax, uint32_t tid) {
   const uint32_t nrows = 2 * H + L.R3;
-  for (uint32_t r = tid; r < nrows; r += 256) {
+  for (uint32_t r = tid; r < nrows; r += NT) {
     const float amax = __uint_as_float(s_amax[r]);
     const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
     uint64_t off;
@@ -754,7 +754,7 @@ __device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __rest
   constexpr uint32_t LG = H == 32 ? 5 : (H == 64 ? 6 : 7);
   const uint32_t KB1 = L.KB1, nquads = ((KB1 + 3) >> 2) * H;
 #pragma unroll 1
-  for (uint32_t q = tid; q < nquads; q += 256) {
+  for (uint32_t q = tid; q < nquads; q += NT) {
     const uint32_t row = q & (H - 1), j = q >> LG;
     const float amax = __uint_as_float(s_amax[row]);
     const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
@@ -773,7 +773,7 @@ __device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __rest
     __builtin_nontemporal_store(u32x4s{wq[0], wq[1], wq[2], wq[3]},
                                 reinterpret_cast<u32x4s*>(sc + L.s_w1 + ((uint64_t)j * H + row) * 16));
   }
-  for (uint32_t u = L.u_b1 + tid; u < L.u_b3; u += 256) {
+  for (uint32_t u = L.u_b1 + tid; u < L.u_b3; u += NT) {
     const UnitPos up = unit_pos<H>(L, u);
     const int layer = up.layer;
     const uint32_t row = up.row, kb = up.kb;
@@ -796,7 +796,7 @@ __device__ __forceinline__ void fp8_finish(const Layout& L, const float4* __rest
 // z standard normal from the parent's Philox stream (parent slot, step, MUTATE,
 // block); the storage copy re-quantised from it; the child's |theta|^2.  One
 // block of 256 threads per child.
-template <int WDT, int H>
+template <int WDT, int H, int NT>
 __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& wp, uint32_t child, uint32_t parent,
                              uint32_t rng_slot, uint32_t step, const double2* tab, uint32_t* s_amax,
                              double* s_red) {
@@ -805,7 +805,7 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
   float4* __restrict__ mc = reinterpret_cast<float4*>(d.master + (uint64_t)child * L.mstride);
   uint8_t* sc = d.store + (uint64_t)child * L.sstride;
   if (WDT == 2) {
-    for (uint32_t i = tid; i < 2 * H + L.R3; i += 256) s_amax[i] = 0u;
+    for (uint32_t i = tid; i < 2 * H + L.R3; i += NT) s_amax[i] = 0u;
     __syncthreads();
   }
   const double sigma = (double)wp.sigma;
@@ -845,7 +845,7 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
     // padding when the row has an odd number of k-blocks: zero)
     const uint32_t KB1 = L.KB1, npairs = ((KB1 + 1) >> 1) * H;
 #pragma unroll 1
-    for (uint32_t q = tid; q < npairs; q += 256) {
+    for (uint32_t q = tid; q < npairs; q += NT) {
       const uint32_t row = q & (H - 1), j = q >> LG, kb0 = 2 * j;
       const bool two = kb0 + 1 < KB1;
       const uint32_t u0 = kb0 * H + row, u1 = u0 + H;
@@ -874,9 +874,9 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
   }
   float4 next = (WDT != 1 && tid < ub1) ? stream_load4(mp + tid) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll 1
-  for (uint32_t u = WDT == 1 ? ub1 : tid; u < ub1; u += 256) {
+  for (uint32_t u = WDT == 1 ? ub1 : tid; u < ub1; u += NT) {
     const float4 p4 = next;   // this unit's parent values, loaded one unit ahead
-    if (u + 256 < ub1) next = stream_load4(mp + u + 256);
+    if (u + NT < ub1) next = stream_load4(mp + u + NT);
     const uint32_t row = u & (H - 1), kb = u >> LG;
     const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
     double z[4];
@@ -890,18 +890,18 @@ __device__ void mutate_child(const Dev& d, const Layout& L, const WorldParams& w
     store_unit<WDT, H>(L, sc, 0, row, kb, v, s_amax);
   }
 #pragma unroll 1
-  for (uint32_t u = L.u_b1 + tid; u < L.u_end; u += 256) unit(u, unit_pos<H>(L, u));
+  for (uint32_t u = L.u_b1 + tid; u < L.u_end; u += NT) unit(u, unit_pos<H>(L, u));
   if (WDT == 2) {
     __syncthreads();
-    fp8_finish<H>(L, mc, sc, s_amax, tid);
+    fp8_finish<H, NT>(L, mc, sc, s_amax, tid);
   }
-  const double t = block_sum_f64<256>(tsum, s_red);
+  const double t = block_sum_f64<NT>(tsum, s_red);
   if (tid == 0) d.trait[child] = t;
 }
 
-// Birth k of world w (the block's 256 threads): the parent bparent[k] places
+// Birth k of world w (the block's NT threads): the parent bparent[k] places
 // its child in the free slot freel[k] (Sec. 3.2 reproduce, Sec. 3.3 mutation).
-template <int WDT, int H>
+template <int WDT, int H, int NT>
 __device__ __forceinline__ void commit_birth(const Dev& d, const Layout& L, uint32_t w, const WorldParams& wp,
                                              uint32_t k, uint32_t step, const double2* tab, uint32_t* s_amax,
                                              double* s_red) {
@@ -928,7 +928,7 @@ __device__ __forceinline__ void commit_birth(const Dev& d, const Layout& L, uint
       d.hp[cg] = e.hp_child;
     }
   }
-  mutate_child<WDT, H>(d, L, wp, cg, pg, p_local, step, tab, s_amax, s_red);
+  mutate_child<WDT, H, NT>(d, L, wp, cg, pg, p_local, step, tab, s_amax, s_red);
   __syncthreads();
 }
 
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 0 ? 
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     const uint32_t w = find_world(off, d.n_worlds, g);
     const WorldParams wp = d.wp[w];
-    commit_birth<WDT, H>(d, L, w, wp, g - off[w], (uint32_t)d.wv[w].step, tab, s_amax, s_red);
+    commit_birth<WDT, H, 256>(d, L, w, wp, g - off[w], (uint32_t)d.wv[w].step, tab, s_amax, s_red);
   }
 }
 
@@ -1297,16 +1297,17 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
 // is one block-wide exclusive sum.
 // ---------------------------------------------------------------------------
 template <int WDT, int H>
-__global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
-  constexpr int NT = 256, CH = 16;   // threads; slots or cells per thread in one pass (one 16-byte load of bytes)
+__global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
+  // threads; slots or cells per thread in one pass (one 4-byte load of bytes); passes over
+  // the slots (the capacity is at most NT CH NP)
+  constexpr int NT = 1024, CH = 4, NP = 2;
   __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
   __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
   __shared__ uint32_t blocked, claims;
   __shared__ uint32_t red[NT / 64 + 1];
   __shared__ unsigned long long red64[NT / 64];
-  __shared__ double redm[NT / 64][3];
   __shared__ uint32_t s_amax[128 + 128 + 16];
-  __shared__ double s_red[4];
+  __shared__ double s_red[NT / 64];
   __shared__ double2 tab[kTrigTable];
   const uint32_t tid = threadIdx.x;
   if (tid < kSlotPart) cnt[tid] = 0;
@@ -1320,16 +1321,9 @@ __global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_
   // each thread's contiguous range of the live list
   const uint32_t per_l = (n_live + NT - 1) / NT;
   const uint32_t l0 = min(tid * per_l, n_live), l1 = min(l0 + per_l, n_live);
-  // the 16 flag bytes of slots b0 .. b0 + 15 (slot and cell ranges start at multiples
-  // of 64 and their allocations end at one, so the 16-byte loads stay inside)
-  auto flags16 = [&](uint32_t b0) {
-    const uint4 v = *reinterpret_cast<const uint4*>(d.flags + wp.slot_off + b0);
-    return v;
-  };
-  auto byte_of = [](const uint4& v, int j) -> uint32_t {
-    const uint32_t wd = j < 4 ? v.x : (j < 8 ? v.y : (j < 12 ? v.z : v.w));
-    return (wd >> (8 * (j & 3))) & 0xFFu;
-  };
+  // the flag bytes of slots b0 .. b0 + 3 (slot and cell ranges start at multiples of
+  // 64 and their allocations end at one, so these 4-byte loads stay inside)
+  auto flags4 = [&](uint32_t b0) { return *reinterpret_cast<const uint32_t*>(d.flags + wp.slot_off + b0); };
 
   // 1. moves, eating, costs and deaths of the step's live agents
   for (uint32_t i = l0; i < l1; ++i) {
@@ -1337,28 +1331,26 @@ __global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_
     move_agent(d, wp, w, wp.slot_off + local, local, step + 1u, cnt);
   }
   __syncthreads();
-  // 2. birth claims of the agents still alive; regrowth of every cell (16 per thread)
+  // 2. birth claims of the agents still alive; regrowth of every cell (4 per thread and pass)
   for (uint32_t i = l0; i < l1; ++i) birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
   {
     unsigned long long grown = 0, total = 0;
     for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
-      uint4* rp = reinterpret_cast<uint4*>(d.res + wp.cell_off + c0);
-      const uint4 v = *rp;
-      uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-      bool changed = false;
+      uint32_t* rp = reinterpret_cast<uint32_t*>(d.res + wp.cell_off + c0);
+      const uint32_t v = *rp;
+      uint32_t nv = v;
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         const uint32_t c = c0 + j;
-        uint32_t r = (wd[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        uint32_t r = (v >> (8 * j)) & 0xFFu;
         if (c < cells && r == 0 && regrows(wp, c, step)) {
           r = 1;
-          wd[j >> 2] |= 1u << (8 * (j & 3));
+          nv |= 1u << (8 * j);
           ++grown;
-          changed = true;
         }
         if (c < cells) total += r;
       }
-      if (changed) *rp = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+      if (nv != v) *rp = nv;
     }
     if (grown) atomicAdd(&ccnt[0], grown);
     atomicAdd(&ccnt[1], total);
@@ -1384,14 +1376,15 @@ __global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_
   // its first Wn entries are used).  The claim flags and the claimed cells are
   // cleared at the end of the step, by the last pass over the slots and the cells.
   uint32_t F = 0;
-  for (uint32_t p0 = 0; p0 < cap; p0 += NT * CH) {
-    const uint32_t b0 = p0 + tid * CH;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t b0 = (p * NT + tid) * CH;
     uint32_t fm = 0;
     if (b0 < cap) {
-      const uint4 v = flags16(b0);
+      const uint32_t v = flags4(b0);
 #pragma unroll
       for (int j = 0; j < CH; ++j)
-        if (b0 + j < cap && !(byte_of(v, j) & kAlive)) fm |= 1u << j;
+        if (b0 + j < cap && !((v >> (8 * j)) & kAlive)) fm |= 1u << j;
     }
     uint32_t tot;
     uint32_t f = F + block_exscan<NT>((uint32_t)__builtin_popcount(fm), red, &tot);
@@ -1402,45 +1395,52 @@ __global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_
   __syncthreads();
   // 4. the births, one at a time (the angle table of the mutation noise only when there are any)
   if (nb) load_trig(d.trig, tab);
-  for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H>(d, L, w, wp, b, step, tab, s_amax, s_red);
-  // 5. the next step's live list and the statistics record
+  for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H, NT>(d, L, w, wp, b, step, tab, s_amax, s_red);
+  // 5. the next step's live list and the statistics record: energy exact in
+  // integers, the trait moments in two passes over the values held in registers
   uint32_t N = 0;
   long long es = 0;
-  Moments tm{0.0, 0.0, 0.0};
-  for (uint32_t p0 = 0; p0 < cap; p0 += NT * CH) {
-    const uint32_t b0 = p0 + tid * CH;
-    uint32_t am = 0;
+  double t[NP][CH], s1 = 0.0;
+  uint32_t am[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t b0 = (p * NT + tid) * CH;
+    am[p] = 0;
     if (b0 < cap) {
-      const uint4 v = flags16(b0);
+      const uint32_t v = flags4(b0);
 #pragma unroll
       for (int j = 0; j < CH; ++j)
-        if (b0 + j < cap && (byte_of(v, j) & kAlive)) am |= 1u << j;
+        if (b0 + j < cap && ((v >> (8 * j)) & kAlive)) am[p] |= 1u << j;
       // the step's birth-claim flags cleared (a flag byte is 0 or alive, after the step)
       constexpr uint32_t claim_bits = 0x01010101u * (kBirthClaim | kBirthWon);
-      if ((v.x | v.y | v.z | v.w) & claim_bits)
-        *reinterpret_cast<uint4*>(d.flags + wp.slot_off + b0) =
-            make_uint4(v.x & ~claim_bits, v.y & ~claim_bits, v.z & ~claim_bits, v.w & ~claim_bits);
-      int32_t e[CH];
-      double t[CH];
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        e[j] = (am >> j) & 1u ? d.energy[wp.slot_off + b0 + j] : 0;
-        t[j] = (am >> j) & 1u ? d.trait[wp.slot_off + b0 + j] : 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if ((am >> j) & 1u) {
-          es += e[j];
-          tm = merge_moments(tm, Moments{1.0, t[j], 0.0});
-        }
+      if (v & claim_bits) *reinterpret_cast<uint32_t*>(d.flags + wp.slot_off + b0) = v & ~claim_bits;
     }
-    uint32_t tot;
-    uint32_t r = N + block_exscan<NT>((uint32_t)__builtin_popcount(am), red, &tot);
-    for (; am; am &= am - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(am));
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const bool on = (am[p] >> j) & 1u;
+      t[p][j] = on ? d.trait[wp.slot_off + b0 + j] : 0.0;
+      es += on ? d.energy[wp.slot_off + b0 + j] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) s1 += t[p][j];
+    uint32_t tot, a = am[p];
+    uint32_t r = N + block_exscan<NT>((uint32_t)__builtin_popcount(a), red, &tot);
+    for (; a; a &= a - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(a));
     N += tot;
   }
   const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
-  const Moments TM = block_merge_moments<NT>(tm, redm);
+  const double S1 = block_sum_f64<NT>(s1, s_red);   // valid in thread 0
+  if (tid == 0) s_red[0] = N ? S1 / (double)N : 0.0;
+  __syncthreads();
+  const double mean = s_red[0];
+  __syncthreads();
+  double m2 = 0.0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean) * (t[p][j] - mean);
+  const double M2 = block_sum_f64<NT>(m2, s_red);
   if (tid == 0) {
     WorldVar& v = d.wv[w];
     v.n_births = nb;
@@ -1466,43 +1466,18 @@ __global__ __launch_bounds__(256) void k_step_small(Dev d, Layout L, uint32_t n_
     st.regrown = ccnt[0];
     st.resource_total = ccnt[1];
     st.energy_total = (double)(long long)E;
-    st.trait_mean = N ? TM.mean : 0.0;
-    st.trait_var = N ? TM.m2 / (double)N : 0.0;
+    st.trait_mean = mean;
+    st.trait_var = N ? M2 / (double)N : 0.0;
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
   // the step's claimed cells released (every claim word back to "none": the
-  // movers' winners released theirs in the move phase, the births' here)
+  // movers' winners released theirs in the move phase, the births' here), and the
+  // window channels of every cell for the next step (the grid is final)
   for (uint32_t c0 = tid * 4; c0 < cells; c0 += NT * 4)
     *reinterpret_cast<uint4*>(d.claim + wp.cell_off + c0) = make_uint4(~0u, ~0u, ~0u, ~0u);
-  // the window channels of every cell for the next step (the grid is final): 16
-  // cells per thread, their occupancy, resource and wall bytes in four loads
-  if (d.rgb) {
-    cell_render_tile(d, Tile{w, 0u, cells, 0u});
-  } else {
-    for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
-      const uint32_t g = wp.cell_off + c0;
-      int o[CH];
-#pragma unroll
-      for (int q = 0; q < CH / 4; ++q) {
-        const int4 v = *reinterpret_cast<const int4*>(d.occ + g + 4 * q);
-        o[4 * q] = v.x;
-        o[4 * q + 1] = v.y;
-        o[4 * q + 2] = v.z;
-        o[4 * q + 3] = v.w;
-      }
-      const uint4 rv = *reinterpret_cast<const uint4*>(d.res + g);
-      const uint4 wv4 = *reinterpret_cast<const uint4*>(d.wall + g);
-      uint32_t sw[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (c0 + j < cells) sw[j >> 2] |= sense_of(wp, d, o[j], byte_of(rv, j), byte_of(wv4, j)) << (8 * (j & 3));
-      if (c0 + CH <= cells) {
-        *reinterpret_cast<uint4*>(d.sense + g) = make_uint4(sw[0], sw[1], sw[2], sw[3]);
-      } else {
-        for (uint32_t j = 0; c0 + j < cells; ++j) d.sense[g + j] = (uint8_t)(sw[j >> 2] >> (8 * (j & 3)));
-      }
-    }
-  }
+  const Tile all{w, 0u, cells, 0u};
+  if (d.rgb) cell_render_tile(d, all);
+  else cell_sense_tile(d, all);
 }
 
 // Rendered window words of one world's cells (after a colour write).
@@ -1866,9 +1841,9 @@ void launch_birth_commit_w(hipStream_t s, const Dev& d, const Layout& L, uint32_
 hipError_t launch_step_small(hipStream_t s, const Dev& d, const Layout& L) {
   if (L.H1 != L.H2 || (L.H1 != 32 && L.H1 != 64 && L.H1 != 128)) return hipErrorInvalidValue;
 #define ECO_SMALL(WW)                                                                                             \
-  if (L.H1 == 32) hipLaunchKernelGGL((k_step_small<WW, 32>), dim3(1), dim3(256), 0, s, d, L, L.A);               \
-  else if (L.H1 == 64) hipLaunchKernelGGL((k_step_small<WW, 64>), dim3(1), dim3(256), 0, s, d, L, L.A);          \
-  else hipLaunchKernelGGL((k_step_small<WW, 128>), dim3(1), dim3(256), 0, s, d, L, L.A);
+  if (L.H1 == 32) hipLaunchKernelGGL((k_step_small<WW, 32>), dim3(1), dim3(1024), 0, s, d, L, L.A);              \
+  else if (L.H1 == 64) hipLaunchKernelGGL((k_step_small<WW, 64>), dim3(1), dim3(1024), 0, s, d, L, L.A);         \
+  else hipLaunchKernelGGL((k_step_small<WW, 128>), dim3(1), dim3(1024), 0, s, d, L, L.A);
   if (L.wdtype == 0) { ECO_SMALL(0) }
   else if (L.wdtype == 1) { ECO_SMALL(1) }
   else { ECO_SMALL(2) }
