@@ -10,8 +10,9 @@ eating, births/deaths, regrowth, compaction/statistics) over all live agents.
 
 value = live agent-steps per second (sum over the timed steps of the agents
 alive at each step's start, divided by the wall time of the timed region,
-inputs resident in HBM); the timed region replays the one-step hipGraph K
-times, the library's default path.  The roofline object reports the policy
+inputs resident in HBM); the timed region replays hipGraphs of whole steps
+(K steps as 32-step graphs and one of the remainder), the library's default
+path.  The roofline object reports the policy
 kernel (the dominant kernel): algorithmic bytes (live agents x per-agent
 weight and state bytes) over its average launch duration, measured with HIP
 events on the library's stream over the next K steps, replayed from one graph
@@ -73,9 +74,9 @@ def timed_run(eco, cfg, steps, warmup, autotune=True, launch=None, tune_cache=No
     if launch:
         w.set_launch(*launch)
     tuned = w.autotune(cache=tune_cache) if autotune else w.get_launch()
-    # timed region: K steps replayed from the one-step hipGraph (the library's default path)
+    # timed region: K steps replayed from hipGraphs of whole steps (the library's default path)
     w.set_flags(eco.RT_USE_GRAPH)
-    w.prepare(1)
+    w.prepare(steps)
     if warmup:
         w.step(warmup)
     torch.cuda.synchronize()

@@ -230,7 +230,10 @@ typedef struct {
 
 /* Runtime flags (eco_world_set_flags). */
 #define ECO_RT_KEEP_LOGITS 1u   /* forward writes FP32 logits for read_logits */
-#define ECO_RT_USE_GRAPH 2u     /* eco_world_step replays a captured hipGraph (default on) */
+#define ECO_RT_USE_GRAPH 2u     /* eco_world_step replays captured hipGraphs of whole steps
+                                   (default on): n steps as n / 32 replays of a 32-step graph
+                                   and one graph of the remaining n mod 32 (each built on first
+                                   use; the last four step counts are kept) */
 #define ECO_RT_TIME_KERNELS 4u  /* hipEvents around every kernel group of eager launches; with
                                    ECO_RT_USE_GRAPH, event-record nodes around the policy kernel
                                    only, in a graph of the n steps of each eco_world_step call (one
@@ -265,10 +268,12 @@ const char* eco_last_error(void);
 /* Advance every world by n_steps whole steps (asynchronous, except that
  * ECO_RT_TIME_KERNELS synchronises at the end to read its timers). */
 eco_status eco_world_step(eco_world* w, uint32_t n_steps);
-/* Build, without running it, the graph eco_world_step(w, n_steps) replays under
- * the current flags (the one-step graph, or the timed graph of n_steps), so the
- * capture stays out of a caller's timed region.  No-op without ECO_RT_USE_GRAPH.
- * A later eco_world_set_flags or eco_world_set_launch drops the built graphs. */
+/* Build, without running them, the graphs eco_world_step(w, n_steps) replays
+ * under the current flags (the 32-step graph and the remainder's, or the timed
+ * graph of n_steps), so the capture stays out of a caller's timed region.  No-op
+ * without ECO_RT_USE_GRAPH or with n_steps = 0.  A later eco_world_set_flags,
+ * eco_world_set_launch or eco_world_autotune drops the built graphs (after
+ * waiting for the object's stream). */
 eco_status eco_world_prepare(eco_world* w, uint32_t n_steps);
 
 /* For callers that cannot allocate device memory (code under graph capture,

@@ -110,8 +110,17 @@ struct eco_world {
   int birth_bpc = 4;        // resident birth-commit blocks per CU
   eco_launch launch{4, 4, 8, 0};
   uint32_t rt_flags = ECO_RT_USE_GRAPH;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // Graphs of m whole steps (1 <= m <= kGraphSteps) replayed by eco_world_step
+  // under ECO_RT_USE_GRAPH, kept per m (at most kGraphKeep of them): n steps run
+  // as n / kGraphSteps replays of the kGraphSteps-step graph and one of the
+  // remainder's, so consecutive steps are separated by a kernel boundary inside
+  // a graph, not by a graph launch.
+  struct StepGraph {
+    uint32_t n = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<StepGraph> sgraphs;
   bool broken = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
@@ -511,33 +520,67 @@ void destroy_timed(eco_world::TimedGraph& t) {
   t = eco_world::TimedGraph{};
 }
 
+void destroy_step_graph(eco_world::StepGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = eco_world::StepGraph{};
+}
+
+// Drops every built graph (after the stream has drained: a replay may still run).
 void drop_graph(eco_world* w) {
-  if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
-  if (w->graph) (void)hipGraphDestroy(w->graph);
-  w->gexec = nullptr;
-  w->graph = nullptr;
+  if (w->sgraphs.empty() && w->tgraphs.empty()) return;
+  (void)hipStreamSynchronize(w->stream);
+  for (auto& g : w->sgraphs) destroy_step_graph(g);
+  w->sgraphs.clear();
   for (auto& t : w->tgraphs) destroy_timed(t);
   w->tgraphs.clear();
 }
 
-eco_status build_graph(eco_world* w) {
-  drop_graph(w);
+constexpr uint32_t kGraphSteps = 32, kGraphKeep = 4;
+
+// The graph of m whole steps (built and kept on first use).
+eco_status step_graph(eco_world* w, uint32_t m, hipGraphExec_t* out) {
+  for (auto& g : w->sgraphs)
+    if (g.n == m) {
+      *out = g.exec;
+      return ECO_OK;
+    }
+  if (w->sgraphs.size() >= kGraphKeep) {
+    (void)hipStreamSynchronize(w->stream);   // the oldest may still be replaying
+    destroy_step_graph(w->sgraphs.front());
+    w->sgraphs.erase(w->sgraphs.begin());
+  }
   Dev d = w->d;
   d.inject = 0;
   d.dry = 0;
   d.keep_logits = (w->rt_flags & ECO_RT_KEEP_LOGITS) ? 1u : 0u;
+  eco_world::StepGraph g;
+  g.n = m;
   HIPCHK(w, hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  eco_status st = enqueue_step(w, w->cap_stream, d, w->ts, false);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(w->cap_stream, &g);
-  if (st != ECO_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return st;
+  eco_status st = ECO_OK;
+  for (uint32_t i = 0; i < m && st == ECO_OK; ++i) st = enqueue_step(w, w->cap_stream, d, w->ts, false);
+  const hipError_t e = hipStreamEndCapture(w->cap_stream, &g.graph);
+  if (st != ECO_OK || e != hipSuccess) {
+    destroy_step_graph(g);
+    return st != ECO_OK ? st : dev_fail(w, e, "end capture");
   }
-  if (e != hipSuccess) return dev_fail(w, e, "end capture");
-  w->graph = g;
-  HIPCHK(w, hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+  const hipError_t ei = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    destroy_step_graph(g);
+    return dev_fail(w, ei, "graph instantiate");
+  }
+  w->sgraphs.push_back(g);
+  *out = g.exec;
   return ECO_OK;
+}
+
+// The untimed graphs that n steps replay: the kGraphSteps-step one and the remainder's.
+eco_status prepare_step_graphs(eco_world* w, uint32_t n) {
+  hipGraphExec_t ex = nullptr;
+  eco_status st = ECO_OK;
+  if (n >= kGraphSteps) st = step_graph(w, kGraphSteps, &ex);
+  if (st == ECO_OK && n % kGraphSteps) st = step_graph(w, n % kGraphSteps, &ex);
+  return st;
 }
 
 // Graph of n steps (captured like the one-step graph) with an event-record node
@@ -939,11 +982,14 @@ eco_status eco_world_step(eco_world* w, uint32_t n_steps) {
     return drain_events(w);
   }
   if (graph) {
-    if (!w->gexec) {
-      st = build_graph(w);
+    for (uint32_t left = n_steps; left > 0;) {
+      const uint32_t m = std::min(left, kGraphSteps);
+      hipGraphExec_t ex = nullptr;
+      st = step_graph(w, m, &ex);
       if (st != ECO_OK) return st;
+      HIPCHK(w, hipGraphLaunch(ex, w->stream), "graph launch");
+      left -= m;
     }
-    for (uint32_t i = 0; i < n_steps; ++i) HIPCHK(w, hipGraphLaunch(w->gexec, w->stream), "graph launch");
     return ECO_OK;
   }
   for (uint32_t i = 0; i < n_steps; ++i) {
@@ -1014,7 +1060,7 @@ eco_status eco_world_prepare(eco_world* w, uint32_t n_steps) {
     eco_world::TimedGraph* t = nullptr;
     return timed_graph(w, n_steps, &t);
   }
-  return w->gexec ? ECO_OK : build_graph(w);
+  return prepare_step_graphs(w, n_steps);
 }
 
 eco_status eco_world_step_with_actions(eco_world* w, const uint8_t* actions) {

@@ -93,6 +93,69 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* red, uint
   return ex;
 }
 
+// Sum of the per-wave values r_i (lane i of every wave holding r_i, i < NW,
+// zero in the other lanes) over the waves before the calling one; *all gets the
+// sum over all NW waves.  Every wave computes both the same way.
+template <int NW, typename T>
+__device__ __forceinline__ T waves_before(T r, T* all) {
+  static_assert(NW <= 64 && (NW & (NW - 1)) == 0, "a power of two of waves, at most 64");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < NW; d <<= 1) {
+    const T t = __shfl_up(r, d);
+    if ((lane & (NW - 1)) >= d) r += t;
+  }
+  *all = __shfl(r, NW - 1);
+  const T b = __shfl(r, wave > 0 ? wave - 1 : 0);
+  return wave > 0 ? b : T(0);
+}
+
+// Exclusive scan of one u64 per thread over the block with one barrier: each
+// wave reads the waves' totals from red itself.  red[NT / 64] must not be
+// written again before every thread has returned (the caller's next barrier).
+template <int NT>
+__device__ __forceinline__ unsigned long long block_exscan_u64(unsigned long long v, unsigned long long* red,
+                                                             unsigned long long* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) red[wave] = inc;
+  __syncthreads();
+  const unsigned long long before = waves_before<NT / 64>(lane < NT / 64 ? red[lane] : 0ull, total);
+  return before + inc - v;
+}
+
+// Block counters in LDS with one atomic per wave instead of one per lane (the
+// atomics of a wave's lanes on one LDS address run one after another, several
+// cycles each).  count_lanes: adds the number of the wave's active lanes to *c
+// (called in the branch whose lanes are counted).  count_lanes_by<N>: adds, for
+// each k < N, the number of active lanes whose v is k to c[k].  wave_add_u64:
+// adds the sum of v over the wave to *c (every lane of the wave active).
+__device__ __forceinline__ void count_lanes(uint32_t* c) {
+  const uint64_t m = __ballot(1);
+  if ((threadIdx.x & 63u) == (uint32_t)__builtin_ctzll(m)) atomicAdd(c, (uint32_t)__builtin_popcountll(m));
+}
+
+template <int N>
+__device__ __forceinline__ void count_lanes_by(uint32_t* c, int v) {
+  const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(1));
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const uint64_t m = __ballot(v == k);
+    if (m && (threadIdx.x & 63u) == first) atomicAdd(&c[k], (uint32_t)__builtin_popcountll(m));
+  }
+}
+
+__device__ __forceinline__ void wave_add_u64(unsigned long long v, unsigned long long* c) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  if ((threadIdx.x & 63u) == 0 && v) atomicAdd(c, v);
+}
+
 // ---------------------------------------------------------------------------
 // Weight emission (init, mutation, re-quantisation) for one agent, one block.
 // A "unit" is 4 consecutive logical parameters = one 16-byte FP32 master block.
@@ -299,7 +362,7 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
     t = min(min(e.eat_biomass, d.cb[c]), e.cap_biomass - B);
     if (t > 0) { d.cb[c] -= t; B += t; }
   }
-  if (t > 0) atomicAdd(&cnt[PC_EATEN], 1u);
+  if (t > 0) count_lanes(&cnt[PC_EATEN]);
   int over = 0;
   E -= (a == REST) ? wp.e_cost : e.e_cost_move;
   if (E < 0) { E = 0; ++over; }
@@ -316,8 +379,8 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
     E = Wt = B = hp = 0;
     d.flags[slot] = 0;
     d.occ[c] = -1;
-    atomicAdd(&cnt[PC_DEATHS], 1u);
-    if (hits) atomicAdd(&cnt[PC_KILLED], 1u);
+    count_lanes(&cnt[PC_DEATHS]);
+    if (hits) count_lanes(&cnt[PC_KILLED]);
   } else {
     hp -= (int)damage;
     if (hp < e.hp_max && E >= e.heal_energy) {
@@ -338,7 +401,7 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
 __device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
                                            uint32_t local, uint32_t stamp, uint32_t* cnt) {
   const int a = d.act[slot];
-  atomicAdd(&cnt[PC_HIST + a], 1u);
+  count_lanes_by<9>(&cnt[PC_HIST], a);
   int cell = d.pos[slot];
   if (a == FORWARD) {
     const int t = d.tgt[slot];
@@ -348,9 +411,9 @@ __device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, 
       d.occ[wp.cell_off + t] = (int)local;
       cell = t;
       d.pos[slot] = cell;
-      atomicAdd(&cnt[PC_MOVES_OK], 1u);
+      count_lanes(&cnt[PC_MOVES_OK]);
     } else {
-      atomicAdd(&cnt[PC_MOVES_BLOCKED], 1u);
+      count_lanes(&cnt[PC_MOVES_BLOCKED]);
     }
   }
   int E = d.energy[slot];
@@ -364,19 +427,19 @@ __device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, 
     d.occ[wp.cell_off + cell] = -1;
     d.res[wp.cell_off + cell] = 1;
     E = 0;
-    atomicAdd(&cnt[PC_DEATHS], 1u);
-    atomicAdd(&cnt[PC_KILLED], 1u);
+    count_lanes(&cnt[PC_DEATHS]);
+    count_lanes(&cnt[PC_KILLED]);
   } else {
     if (a == EAT && d.res[wp.cell_off + cell] > 0) {
       d.res[wp.cell_off + cell] -= 1;
       E += wp.e_eat;
-      atomicAdd(&cnt[PC_EATEN], 1u);
+      count_lanes(&cnt[PC_EATEN]);
     }
     E -= wp.e_cost;
     if (E <= 0) {
       d.flags[slot] = 0;
       d.occ[wp.cell_off + cell] = -1;
-      atomicAdd(&cnt[PC_DEATHS], 1u);
+      count_lanes(&cnt[PC_DEATHS]);
     } else {
       d.age[slot] += 1;
     }
@@ -425,7 +488,7 @@ __device__ __forceinline__ void birth_claim_slot(const Dev& d, const WorldParams
       d.tgt[slot] = (int)t;
       d.flags[slot] = fl | kBirthClaim;
     } else {
-      atomicAdd(blocked, 1u);
+      count_lanes(blocked);
     }
   }
 }
@@ -476,8 +539,8 @@ __device__ __forceinline__ void regrow_cells(const Dev& d, const WorldParams& wp
     }
     total += r;
   }
-  if (grown) atomicAdd(&cnt[0], grown);
-  atomicAdd(&cnt[1], total);
+  wave_add_u64(grown, &cnt[0]);
+  wave_add_u64(total, &cnt[1]);
 }
 
 __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile,
@@ -523,10 +586,10 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
         d.cw_next[g] = acc;
       }
     }
-    if (grown) atomicAdd(&cnt[0], grown);
-    atomicAdd(&cnt[1], total);
-    atomicAdd(&cnt[2], wsum);
-    atomicAdd(&cnt[3], bsum);
+    wave_add_u64(grown, &cnt[0]);
+    wave_add_u64(total, &cnt[1]);
+    wave_add_u64(wsum, &cnt[2]);
+    wave_add_u64(bsum, &cnt[3]);
     __syncthreads();
     if (threadIdx.x < kCellPart) ts.part_cell[tile * kCellPart + threadIdx.x] = cnt[threadIdx.x];
     return;
@@ -558,13 +621,13 @@ __global__ __launch_bounds__(kSlotTile) void k_birth_rank_count(Dev d, TileScrat
     const uint32_t slot = wp.slot_off + tl.start + threadIdx.x;
     const uint8_t fl = d.flags[slot];
     if (fl & kBirthClaim) {
-      atomicAdd(&cnt[0], 1u);
+      count_lanes(&cnt[0]);
       if (d.claim[wp.cell_off + d.tgt[slot]] == slot) {
         d.flags[slot] = fl | kBirthWon;
-        atomicAdd(&cnt[1], 1u);
+        count_lanes(&cnt[1]);
       }
     }
-    if (!(fl & kAlive)) atomicAdd(&cnt[2], 1u);
+    if (!(fl & kAlive)) count_lanes(&cnt[2]);
   }
   __syncthreads();
   if (threadIdx.x < 3) ts.scan[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
@@ -1303,16 +1366,18 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   constexpr int NT = 1024, CH = 4, NP = 2;
   __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
   __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
-  __shared__ uint32_t blocked, claims;
-  __shared__ uint32_t red[NT / 64 + 1];
-  __shared__ unsigned long long red64[NT / 64];
+  __shared__ uint32_t blocked;
+  __shared__ unsigned long long rank_red[NT / 64];   // the ranking scan's wave totals
+  __shared__ uint32_t live_red[NT / 64];             // the live list's wave counts
+  __shared__ unsigned long long red64[NT / 64];      // the waves' energy sums
+  __shared__ double m2_red[NT / 64];                 // the waves' sums of squared deviations
   __shared__ uint32_t s_amax[128 + 128 + 16];
-  __shared__ double s_red[NT / 64];
+  __shared__ double s_red[NT / 64];                  // the births' reductions, then the waves' trait sums
   __shared__ double2 tab[kTrigTable];
   const uint32_t tid = threadIdx.x;
   if (tid < kSlotPart) cnt[tid] = 0;
   if (tid < kCellPart) ccnt[tid] = 0;
-  if (tid == 0) blocked = claims = 0;
+  if (tid == 0) blocked = 0;
   __syncthreads();
   constexpr uint32_t w = 0;
   const WorldParams wp = d.wp[w];
@@ -1352,11 +1417,17 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       }
       if (nv != v) *rp = nv;
     }
-    if (grown) atomicAdd(&ccnt[0], grown);
-    atomicAdd(&ccnt[1], total);
+    wave_add_u64(grown, &ccnt[0]);
+    wave_add_u64(total, &ccnt[1]);
   }
   __syncthreads();
-  // 3. birth ranking: the claim winners in slot order (the live list's order) ...
+  // 3. birth ranking: the claim winners in slot order (the live list's order)
+  // and the free slots in ascending order (the recycled-slot free list; only its
+  // first Wn entries are used), both ranked by one block scan of 16-bit counts
+  // packed in a u64 (winners, free slots of each pass, claims; no field carries
+  // into the next: every total is at most 8,192).  The claim flags and the
+  // claimed cells are cleared at the end of the step, by the last pass over the
+  // slots and the cells.
   uint32_t nw = 0, nc = 0;
   for (uint32_t i = l0; i < l1; ++i) {
     const uint32_t slot = wp.slot_off + (uint32_t)live[i];
@@ -1365,31 +1436,37 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       if (d.claim[wp.cell_off + d.tgt[slot]] == slot) ++nw;
     }
   }
-  if (nc) atomicAdd(&claims, nc);
-  uint32_t Wn;
-  uint32_t k = block_exscan<NT>(nw, red, &Wn);
-  for (uint32_t i = l0; i < l1 && nw; ++i) {
-    const uint32_t local = (uint32_t)live[i], slot = wp.slot_off + local;
-    if ((d.flags[slot] & kBirthClaim) && d.claim[wp.cell_off + d.tgt[slot]] == slot) d.bparent[wp.slot_off + k++] = (int)local;
-  }
-  // ... and the free slots in ascending order (the recycled-slot free list; only
-  // its first Wn entries are used).  The claim flags and the claimed cells are
-  // cleared at the end of the step, by the last pass over the slots and the cells.
-  uint32_t F = 0;
+  uint32_t fm[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const uint32_t b0 = (p * NT + tid) * CH;
-    uint32_t fm = 0;
+    fm[p] = 0;
     if (b0 < cap) {
       const uint32_t v = flags4(b0);
 #pragma unroll
       for (int j = 0; j < CH; ++j)
-        if (b0 + j < cap && !((v >> (8 * j)) & kAlive)) fm |= 1u << j;
+        if (b0 + j < cap && !((v >> (8 * j)) & kAlive)) fm[p] |= 1u << j;
     }
-    uint32_t tot;
-    uint32_t f = F + block_exscan<NT>((uint32_t)__builtin_popcount(fm), red, &tot);
-    for (; fm && f < Wn; fm &= fm - 1) d.freel[wp.slot_off + f++] = (int)(b0 + __builtin_ctz(fm));
-    F += tot;
+  }
+  static_assert(NP == 2, "the packed ranking scan holds two passes of free slots");
+  unsigned long long rtot;
+  const unsigned long long rex =
+      block_exscan_u64<NT>((unsigned long long)nw | (unsigned long long)__builtin_popcount(fm[0]) << 16 |
+                               (unsigned long long)__builtin_popcount(fm[1]) << 32 | (unsigned long long)nc << 48,
+                           rank_red, &rtot);
+  const uint32_t Wn = (uint32_t)(rtot & 0xFFFFu), claims = (uint32_t)(rtot >> 48);
+  uint32_t k = (uint32_t)(rex & 0xFFFFu);
+  for (uint32_t i = l0; i < l1 && nw; ++i) {
+    const uint32_t local = (uint32_t)live[i], slot = wp.slot_off + local;
+    if ((d.flags[slot] & kBirthClaim) && d.claim[wp.cell_off + d.tgt[slot]] == slot) d.bparent[wp.slot_off + k++] = (int)local;
+  }
+  uint32_t F = 0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t b0 = (p * NT + tid) * CH;
+    uint32_t f = F + (uint32_t)((rex >> (16 * (p + 1))) & 0xFFFFu);
+    for (uint32_t m = fm[p]; m && f < Wn; m &= m - 1) d.freel[wp.slot_off + f++] = (int)(b0 + __builtin_ctz(m));
+    F += (uint32_t)((rtot >> (16 * (p + 1))) & 0xFFFFu);
   }
   const uint32_t nb = min(Wn, F);
   __syncthreads();
@@ -1397,8 +1474,10 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   if (nb) load_trig(d.trig, tab);
   for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H, NT>(d, L, w, wp, b, step, tab, s_amax, s_red);
   // 5. the next step's live list and the statistics record: energy exact in
-  // integers, the trait moments in two passes over the values held in registers
-  uint32_t N = 0;
+  // integers, the trait moments in two passes over the values held in registers.
+  // One barrier gives every thread its wave's offsets in the live list (both
+  // passes' counts packed in a u32), the energy total and the trait sum (the
+  // waves' sums added in wave order); a second one the sum of squared deviations.
   long long es = 0;
   double t[NP][CH], s1 = 0.0;
   uint32_t am[NP];
@@ -1423,25 +1502,58 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     }
 #pragma unroll
     for (int j = 0; j < CH; ++j) s1 += t[p][j];
-    uint32_t tot, a = am[p];
-    uint32_t r = N + block_exscan<NT>((uint32_t)__builtin_popcount(a), red, &tot);
-    for (; a; a &= a - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(a));
-    N += tot;
   }
-  const unsigned long long E = block_sum_u64<NT>((unsigned long long)es, red64);
-  const double S1 = block_sum_f64<NT>(s1, s_red);   // valid in thread 0
-  if (tid == 0) s_red[0] = N ? S1 / (double)N : 0.0;
+  const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
+  uint32_t inc = (uint32_t)__builtin_popcount(am[0]) | (uint32_t)__builtin_popcount(am[1]) << 16;
+  const uint32_t own = inc;
+  unsigned long long ew = (unsigned long long)es;
+  double sw = s1;
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) {
+    const uint32_t u = __shfl_up(inc, dd);
+    if (lane >= dd) inc += u;
+  }
+#pragma unroll
+  for (int dd = 32; dd >= 1; dd >>= 1) {
+    ew += __shfl_xor(ew, dd);
+    sw += __shfl_xor(sw, dd);
+  }
+  if (lane == 63) live_red[wave] = inc;
+  if (lane == 0) {
+    red64[wave] = ew;
+    s_red[wave] = sw;
+  }
   __syncthreads();
-  const double mean = s_red[0];
-  __syncthreads();
+  // the waves' sums added in wave order in every thread (lane i reads wave i's)
+  uint32_t ntot;
+  const uint32_t before = waves_before<NT / 64>(lane < NT / 64 ? live_red[lane] : 0u, &ntot);
+  unsigned long long E;
+  (void)waves_before<NT / 64>(lane < NT / 64 ? red64[lane] : 0ull, &E);
+  double S1;
+  (void)waves_before<NT / 64>(lane < NT / 64 ? s_red[lane] : 0.0, &S1);
+  const uint32_t N0 = ntot & 0xFFFFu, N = N0 + (ntot >> 16);
+  const uint32_t ex = before + inc - own;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t b0 = (p * NT + tid) * CH;
+    uint32_t r = (p == 0 ? 0u : N0) + ((ex >> (16 * p)) & 0xFFFFu);
+    for (uint32_t a = am[p]; a; a &= a - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(a));
+  }
+  const double mean = N ? S1 / (double)N : 0.0;
   double m2 = 0.0;
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int j = 0; j < CH; ++j)
       if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean) * (t[p][j] - mean);
-  const double M2 = block_sum_f64<NT>(m2, s_red);
+#pragma unroll
+  for (int dd = 32; dd >= 1; dd >>= 1) m2 += __shfl_xor(m2, dd);
+  if (lane == 0) m2_red[wave] = m2;
+  __syncthreads();
   if (tid == 0) {
+    double M2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) M2 += m2_red[i];
     WorldVar& v = d.wv[w];
     v.n_births = nb;
     v.n_win = Wn;

@@ -191,7 +191,10 @@ class _TorchAllocator:
             return None
 
     def free(self, ptr, ctx):
-        self.torch.cuda.caching_allocator_delete(ptr)
+        cuda = getattr(self.torch, "cuda", None)
+        if cuda is None:   # interpreter shutdown: torch's modules are already torn down
+            return
+        cuda.caching_allocator_delete(ptr)
 
 
 class World:

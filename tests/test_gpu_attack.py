@@ -125,7 +125,7 @@ def test_attack_world_policy_actions(eco):
 
 def test_attack_graph_and_eager_agree(eco):
     """Free-running GPU worlds with attacks (the policy kernel's own samples decide
-    who attacks): one-step graph, eager launches and the timed graph give the same
+    who attacks): step graphs, eager launches and the timed graph give the same
     state and statistics."""
     cfg = _attack_world(seed=31, e_init=150)
     a, b, c = eco.World(cfg), eco.World(cfg), eco.World(cfg)

@@ -126,6 +126,35 @@ def test_graph_and_eager_paths_agree(eco):
         w.close()
 
 
+@pytest.mark.parametrize("split", [False, True], ids=["fused", "split"])
+def test_step_graph_chunks_agree_with_eager(eco, split):
+    """eco_world_step under ECO_RT_USE_GRAPH runs n steps as 32-step graphs and one
+    of the remainder: step counts across the chunk boundary, more distinct counts
+    than the graphs kept (the oldest is dropped and rebuilt), and a flag change
+    between calls all give the eager path's state and statistics (the small
+    world's fused step, and its separate kernels)."""
+    cfg = mid_world(seed=8, e_init=150)
+    extra = eco.RT_SPLIT_STEP if split else 0
+    a = eco.World(cfg)
+    b = eco.World(cfg)
+    a.set_flags(eco.RT_USE_GRAPH | extra)
+    b.set_flags(extra)
+    counts = (70, 1, 33, 5, 2, 3, 32, 4)
+    for i, n in enumerate(counts):
+        if i == 4:   # a flag change drops the built graphs
+            a.set_flags(eco.RT_USE_GRAPH | eco.RT_KEEP_LOGITS | extra)
+            b.set_flags(eco.RT_KEEP_LOGITS | extra)
+        a.step(n)
+        b.step(n)
+    assert_same_state(a.read_state(), b.read_state(), "step graphs vs eager")
+    assert a.stats() == b.stats()
+    h = a.stats_history(0, 150)
+    assert h == b.stats_history(0, 150) and h[-1]["step"] == sum(counts)
+    assert np.array_equal(a.read_logits(), b.read_logits(), equal_nan=True)
+    for w in (a, b):
+        w.close()
+
+
 def test_resume_from_state_and_weights(eco):
     cfg = mid_world(seed=7, e_init=150)
     a = eco.World(cfg)
