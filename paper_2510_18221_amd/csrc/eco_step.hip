@@ -35,12 +35,55 @@ enum { PC_HIST = 0, PC_MOVES_OK = 9, PC_MOVES_BLOCKED = 10, PC_EATEN = 11, PC_DE
 // ---------------------------------------------------------------------------
 // Small block helpers
 // ---------------------------------------------------------------------------
+// Wave-wide sums by DPP, the data-parallel lane moves of the VALU: lane i of
+// each row of 16 lanes adds row lanes i - 1, i - 2, i - 4, i - 8 (taking 0 past
+// the row's start), then rows 1 and 3 add the last lane of rows 0 and 2, and
+// rows 2 and 3 the last lane of row 1.  Each step is a few VALU cycles where a
+// lane shuffle goes through the LDS crossbar.  Every lane of the wave must be
+// active.  64-bit values move as two 32-bit halves.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_move(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)__builtin_bit_cast(uint32_t, x), CTRL, ROWS, 0xf, false));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// Inclusive sum over lanes 0..lane of the wave (a fixed order for FP64).
+template <typename T>
+__device__ __forceinline__ T wave_scan(T x) {
+  x += dpp_move<0x111, 0xf>(x);   // row_shr:1
+  x += dpp_move<0x112, 0xf>(x);   // row_shr:2
+  x += dpp_move<0x114, 0xf>(x);   // row_shr:4
+  x += dpp_move<0x118, 0xf>(x);   // row_shr:8
+  x += dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// x of lane l (the same l in every lane).
+template <typename T>
+__device__ __forceinline__ T lane_value(T x, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint32_t, x), l));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  if (lane == 0) red[wave] = v;
+  v = wave_scan(v);
+  if (lane == 63) red[wave] = v;
   __syncthreads();
   unsigned long long t = 0;
   if (threadIdx.x == 0)
@@ -49,13 +92,12 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
   return t;  // valid in thread 0
 }
 
-// Deterministic FP64 block sum: fixed butterfly per wave, then waves in order.
+// Deterministic FP64 block sum: a fixed order within each wave, then waves in order.
 template <int NT>
 __device__ __forceinline__ double block_sum_f64(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  if (lane == 0) red[wave] = v;
+  v = wave_scan(v);
+  if (lane == 63) red[wave] = v;
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0)
@@ -69,12 +111,7 @@ __device__ __forceinline__ double block_sum_f64(double v, double* red) {
 template <int NT>
 __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* red, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(inc, d);
-    if (lane >= d) inc += t;
-  }
+  const uint32_t inc = wave_scan(v);
   if (lane == 63) red[wave] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -98,15 +135,11 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* red, uint
 // sum over all NW waves.  Every wave computes both the same way.
 template <int NW, typename T>
 __device__ __forceinline__ T waves_before(T r, T* all) {
-  static_assert(NW <= 64 && (NW & (NW - 1)) == 0, "a power of two of waves, at most 64");
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 1; d < NW; d <<= 1) {
-    const T t = __shfl_up(r, d);
-    if ((lane & (NW - 1)) >= d) r += t;
-  }
-  *all = __shfl(r, NW - 1);
-  const T b = __shfl(r, wave > 0 ? wave - 1 : 0);
+  static_assert(NW >= 1 && NW <= 64, "at most 64 waves");
+  const int wave = threadIdx.x >> 6;
+  r = wave_scan(r);
+  *all = lane_value(r, NW - 1);
+  const T b = lane_value(r, wave > 0 ? wave - 1 : 0);
   return wave > 0 ? b : T(0);
 }
 
@@ -117,12 +150,7 @@ template <int NT>
 __device__ __forceinline__ unsigned long long block_exscan_u64(unsigned long long v, unsigned long long* red,
                                                              unsigned long long* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  unsigned long long inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const unsigned long long t = __shfl_up(inc, d);
-    if (lane >= d) inc += t;
-  }
+  const unsigned long long inc = wave_scan(v);
   if (lane == 63) red[wave] = inc;
   __syncthreads();
   const unsigned long long before = waves_before<NT / 64>(lane < NT / 64 ? red[lane] : 0ull, total);
@@ -151,9 +179,8 @@ __device__ __forceinline__ void count_lanes_by(uint32_t* c, int v) {
 }
 
 __device__ __forceinline__ void wave_add_u64(unsigned long long v, unsigned long long* c) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  if ((threadIdx.x & 63u) == 0 && v) atomicAdd(c, v);
+  v = wave_scan(v);
+  if ((threadIdx.x & 63u) == 63 && v) atomicAdd(c, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,27 +427,36 @@ __device__ __forceinline__ int ecology_agent(const Dev& d, const eco_ecology& e,
 // the LDS counters cnt.  stamp: the attack stamp of this step (step + 1).
 __device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
                                            uint32_t local, uint32_t stamp, uint32_t* cnt) {
+  // every load the non-ecology rules can need, issued before any store: the
+  // agent's fields, then the cells it stands on or claimed (no other agent
+  // writes these cells in this pass: a claim targets a cell free at step start)
   const int a = d.act[slot];
-  count_lanes_by<9>(&cnt[PC_HIST], a);
   int cell = d.pos[slot];
+  const int t = d.tgt[slot];
+  int E = d.energy[slot];
+  const uint32_t won = (a == FORWARD && t >= 0) ? d.claim[wp.cell_off + t] : ~0u;
+  const uint8_t r0 = d.ep ? 0 : d.res[wp.cell_off + cell];
+  const uint32_t m0 = (!d.ep && wp.attack) ? d.mark[wp.cell_off + cell] : 0u;
+  const uint32_t m1 = (!d.ep && wp.attack && a == FORWARD && t >= 0) ? d.mark[wp.cell_off + t] : 0u;
+  count_lanes_by<9>(&cnt[PC_HIST], a);
+  bool moved = false;
   if (a == FORWARD) {
-    const int t = d.tgt[slot];
-    if (t >= 0 && d.claim[wp.cell_off + t] == slot) {
+    if (t >= 0 && won == slot) {
       d.claim[wp.cell_off + t] = 0xFFFFFFFFu;
       d.occ[wp.cell_off + cell] = -1;
       d.occ[wp.cell_off + t] = (int)local;
       cell = t;
+      moved = true;
       d.pos[slot] = cell;
       count_lanes(&cnt[PC_MOVES_OK]);
     } else {
       count_lanes(&cnt[PC_MOVES_BLOCKED]);
     }
   }
-  int E = d.energy[slot];
   if (d.ep) {
     const uint32_t g = wp.cell_off + (uint32_t)cell;
     E = ecology_agent(d, d.ep[w], wp, slot, g, a, wp.attack ? d.mark[g] : 0u, cnt);
-  } else if (wp.attack && d.mark[wp.cell_off + cell] == stamp) {
+  } else if (wp.attack && (moved ? m1 : m0) == stamp) {
     // struck after the moves: dies where it stands; its carried energy goes
     // back to the cell as one resource unit (cells hold 0 or 1 unit)
     d.flags[slot] = 0;
@@ -430,8 +466,8 @@ __device__ __forceinline__ void move_agent(const Dev& d, const WorldParams& wp, 
     count_lanes(&cnt[PC_DEATHS]);
     count_lanes(&cnt[PC_KILLED]);
   } else {
-    if (a == EAT && d.res[wp.cell_off + cell] > 0) {
-      d.res[wp.cell_off + cell] -= 1;
+    if (a == EAT && r0 > 0) {   // an eater did not move: cell is its own
+      d.res[wp.cell_off + cell] = (uint8_t)(r0 - 1);
       E += wp.e_eat;
       count_lanes(&cnt[PC_EATEN]);
     }
@@ -699,12 +735,7 @@ __device__ __forceinline__ void birth_offsets(const WorldVar* __restrict__ wv, u
     const uint32_t lo = tid * per, hi = min(lo + per, n);
     uint32_t s = 0;
     for (uint32_t i = lo; i < hi; ++i) s += wv[i].n_births;
-    uint32_t inc = s;
-#pragma unroll
-    for (int dd = 1; dd < 64; dd <<= 1) {
-      const uint32_t v = __shfl_up(inc, dd);
-      if (tid >= dd) inc += v;
-    }
+    const uint32_t inc = wave_scan(s);
     uint32_t run = inc - s;
     for (uint32_t i = lo; i < hi; ++i) {
       off[i] = run;
@@ -1265,16 +1296,10 @@ __device__ void world_finalize(const Dev& d, const TileScratch& ts, uint32_t w, 
 #pragma unroll
       for (int k = 0; k < kCellPart; ++k) cc[k] += ts.part_cell[t * kCellPart + k];
 #pragma unroll
-    for (int k = 0; k < kSlotPart; ++k) {
+    for (int k = 0; k < kSlotPart; ++k) c[k] = wave_scan(c[k]);
 #pragma unroll
-      for (int dd = 32; dd >= 1; dd >>= 1) c[k] += __shfl_xor(c[k], dd);
-    }
-#pragma unroll
-    for (int k = 0; k < kCellPart; ++k) {
-#pragma unroll
-      for (int dd = 32; dd >= 1; dd >>= 1) cc[k] += __shfl_xor(cc[k], dd);
-    }
-    if ((threadIdx.x & 63) == 0) {
+    for (int k = 0; k < kCellPart; ++k) cc[k] = wave_scan(cc[k]);
+    if ((threadIdx.x & 63) == 63) {
 #pragma unroll
       for (int k = 0; k < kSlotPart; ++k) atomicAdd(&s_cnt[k], (unsigned long long)c[k]);
 #pragma unroll
@@ -1375,6 +1400,10 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   __shared__ double s_red[NT / 64];                  // the births' reductions, then the waves' trait sums
   __shared__ double2 tab[kTrigTable];
   const uint32_t tid = threadIdx.x;
+  // live-list entry tid, loaded together with the world's live count: the
+  // thread's only agent when there are at most NT (the object's one world
+  // starts at slot 0; the list's allocation holds total_slots entries)
+  const int32_t live_tid = d.live[min(tid, d.total_slots - 1u)];
   if (tid < kSlotPart) cnt[tid] = 0;
   if (tid < kCellPart) ccnt[tid] = 0;
   if (tid == 0) blocked = 0;
@@ -1392,7 +1421,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
 
   // 1. moves, eating, costs and deaths of the step's live agents
   for (uint32_t i = l0; i < l1; ++i) {
-    const uint32_t local = (uint32_t)live[i];
+    const uint32_t local = (uint32_t)(i == tid ? live_tid : live[i]);
     move_agent(d, wp, w, wp.slot_off + local, local, step + 1u, cnt);
   }
   __syncthreads();
@@ -1494,32 +1523,34 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       constexpr uint32_t claim_bits = 0x01010101u * (kBirthClaim | kBirthWon);
       if (v & claim_bits) *reinterpret_cast<uint32_t*>(d.flags + wp.slot_off + b0) = v & ~claim_bits;
     }
+    // the four slots' traits and energies in 16-byte loads, whether alive or not
+    // (they lie inside the allocations, which end at a multiple of 64 slots)
+    static_assert(CH == 4, "one 16-byte load of energies per pass");
+    double2 tv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    int4 ev = make_int4(0, 0, 0, 0);
+    if (b0 < cap) {
+      tv[0] = *reinterpret_cast<const double2*>(d.trait + wp.slot_off + b0);
+      tv[1] = *reinterpret_cast<const double2*>(d.trait + wp.slot_off + b0 + 2);
+      ev = *reinterpret_cast<const int4*>(d.energy + wp.slot_off + b0);
+    }
+    const double tj[4] = {tv[0].x, tv[0].y, tv[1].x, tv[1].y};
+    const int ej[4] = {ev.x, ev.y, ev.z, ev.w};
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const bool on = (am[p] >> j) & 1u;
-      t[p][j] = on ? d.trait[wp.slot_off + b0 + j] : 0.0;
-      es += on ? d.energy[wp.slot_off + b0 + j] : 0;
+      t[p][j] = on ? tj[j] : 0.0;
+      es += on ? ej[j] : 0;
     }
 #pragma unroll
     for (int j = 0; j < CH; ++j) s1 += t[p][j];
   }
   const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
-  uint32_t inc = (uint32_t)__builtin_popcount(am[0]) | (uint32_t)__builtin_popcount(am[1]) << 16;
-  const uint32_t own = inc;
-  unsigned long long ew = (unsigned long long)es;
-  double sw = s1;
-#pragma unroll
-  for (int dd = 1; dd < 64; dd <<= 1) {
-    const uint32_t u = __shfl_up(inc, dd);
-    if (lane >= dd) inc += u;
-  }
-#pragma unroll
-  for (int dd = 32; dd >= 1; dd >>= 1) {
-    ew += __shfl_xor(ew, dd);
-    sw += __shfl_xor(sw, dd);
-  }
-  if (lane == 63) live_red[wave] = inc;
-  if (lane == 0) {
+  const uint32_t own = (uint32_t)__builtin_popcount(am[0]) | (uint32_t)__builtin_popcount(am[1]) << 16;
+  const uint32_t inc = wave_scan(own);
+  const unsigned long long ew = wave_scan((unsigned long long)es);
+  const double sw = wave_scan(s1);
+  if (lane == 63) {
+    live_red[wave] = inc;
     red64[wave] = ew;
     s_red[wave] = sw;
   }
@@ -1546,9 +1577,8 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
 #pragma unroll
     for (int j = 0; j < CH; ++j)
       if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean) * (t[p][j] - mean);
-#pragma unroll
-  for (int dd = 32; dd >= 1; dd >>= 1) m2 += __shfl_xor(m2, dd);
-  if (lane == 0) m2_red[wave] = m2;
+  m2 = wave_scan(m2);
+  if (lane == 63) m2_red[wave] = m2;
   __syncthreads();
   if (tid == 0) {
     double M2 = 0.0;
