@@ -1035,9 +1035,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WDT == 0 ? 
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[4];
   __shared__ double2 tab[kTrigTable];
-  load_trig(d.trig, tab);
   birth_offsets(d.wv, d.n_worlds, off);
   const uint32_t total = off[d.n_worlds];
+  if (blockIdx.x >= total) return;   // no birth for this block (the whole launch, in a step without births)
+  load_trig(d.trig, tab);
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     const uint32_t w = find_world(off, d.n_worlds, g);
     const WorldParams wp = d.wp[w];
