@@ -583,7 +583,7 @@ eco_status prepare_step_graphs(eco_world* w, uint32_t n) {
   return st;
 }
 
-// Graph of n steps (captured like the one-step graph) with an event-record node
+// Graph of n steps (captured like the step graphs) with an event-record node
 // before and after every policy-kernel node, kept per n.  Only the dominant
 // kernel is bracketed: each event node costs the replay several microseconds.
 eco_status timed_graph(eco_world* w, uint32_t n, eco_world::TimedGraph** out) {

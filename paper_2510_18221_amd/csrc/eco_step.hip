@@ -1507,7 +1507,8 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // integers, the trait moments in two passes over the values held in registers.
   // One barrier gives every thread its wave's offsets in the live list (both
   // passes' counts packed in a u32), the energy total and the trait sum (the
-  // waves' sums added in wave order); a second one the sum of squared deviations.
+  // waves' sums, added the same way in every wave); a second one the sum of
+  // squared deviations.
   long long es = 0;
   double t[NP][CH], s1 = 0.0;
   uint32_t am[NP];
@@ -1556,7 +1557,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     s_red[wave] = sw;
   }
   __syncthreads();
-  // the waves' sums added in wave order in every thread (lane i reads wave i's)
+  // the waves' sums, added the same way in every wave (lane i reads wave i's)
   uint32_t ntot;
   const uint32_t before = waves_before<NT / 64>(lane < NT / 64 ? live_red[lane] : 0u, &ntot);
   unsigned long long E;
