@@ -266,7 +266,9 @@ void eco_world_destroy(eco_world* w);
 const char* eco_last_error(void);
 
 /* Advance every world by n_steps whole steps (asynchronous, except that
- * ECO_RT_TIME_KERNELS synchronises at the end to read its timers). */
+ * ECO_RT_TIME_KERNELS synchronises at the end to read its timers).  Under
+ * ECO_RT_USE_GRAPH the first call with a step count captures the graphs it
+ * replays (eco_world_prepare does that ahead of time). */
 eco_status eco_world_step(eco_world* w, uint32_t n_steps);
 /* Build, without running them, the graphs eco_world_step(w, n_steps) replays
  * under the current flags (the 32-step graph and the remainder's, or the timed
