@@ -47,6 +47,15 @@ CASES = {
     "attack": busy(attack_enabled=1, e_init=150, e_cost=1, e_child=40, seed=15),
     "colour_temp": busy(flags=eco_mod.DESC_COLOUR_VISION | eco_mod.DESC_EVOLVE_TEMPERATURE, seed=16),
     "full_capacity": busy(n_agents_init=200, capacity=200, seed=17),
+    # every (storage type, hidden width) instantiation of the fused kernel
+    "busy_fp32_h64": busy(hidden1=64, hidden2=64, seed=19),
+    "busy_bf16_h64": busy(wdtype=wl.BF16, hidden1=64, hidden2=64, seed=20),
+    "busy_bf16_h128": busy(wdtype=wl.BF16, hidden1=128, hidden2=128, window=3, seed=21),
+    "busy_fp8_h32": busy(wdtype=wl.FP8, seed=22),
+    "busy_fp8_h128": busy(wdtype=wl.FP8, hidden1=128, hidden2=128, window=3, n_actions=5, n_scalars=4, seed=23),
+    # the largest object the fused launch takes: 8,192 slots (both passes of four
+    # slots per thread full) and 16,384 cells (four passes of the cell loops)
+    "limits": busy(width=128, height=128, n_agents_init=5000, capacity=8192, seed=24),
 }
 
 
@@ -83,7 +92,7 @@ def test_fused_equals_split(eco, name):
     fused.close()
     split.close()
     say(f"{name}: {steps} steps, {births} births, fused == split")
-    if name.startswith("busy"):
+    if name.startswith("busy") or name == "limits":
         assert births > 0
 
 
@@ -120,7 +129,7 @@ def test_split_kernels_match_oracle_on_small_worlds(eco, name):
     run_pair(eco, cfg, 8, actions_fn=acts, what=f"split {name}", flags=eco.RT_SPLIT_STEP)
 
 
-@pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64"])
+@pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64", "busy_bf16_h128", "limits"])
 def test_fused_matches_oracle(eco, name):
     cfg = CASES[name]
     acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 5, t, p_forward=0.3, p_eat=0.3,
