@@ -243,6 +243,10 @@ typedef struct {
                                    as one fused launch (timed as ECO_K_MOVE); this flag runs the
                                    separate kernels instead.  Same integer state and statistics
                                    either way (the trait moments to rounding). */
+/* The fused launch's limits: total slots and total cells of the object (each
+ * world's ranges rounded up to 64). */
+#define ECO_SMALL_STEP_MAX_SLOTS 8192u
+#define ECO_SMALL_STEP_MAX_CELLS 16384u
 
 /* Create n_worlds worlds (all with the same window, n_scalars, hidden sizes,
  * n_actions and wdtype) and run the deterministic init of Sec. 3.3 / placement.

@@ -1142,16 +1142,24 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_count(Dev d, TileScratch 
 // byte per cell instead of the occupancy, resource and wall arrays plus a
 // dependent read of each occupant's energy.  Threads take 4 consecutive cells
 // (cell_off and tile starts are multiples of 4); a ragged tail goes cell by cell.
-__device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d, int o, uint32_t r, uint32_t wl) {
-  uint32_t v = (r != 0 ? 2u : 0u) | (wp.has_walls && wl != 0 ? 4u : 0u);
-  if (o >= 0) {
-    const long long e8 = (long long)d.energy[wp.slot_off + (uint32_t)o] * 8;
-    uint32_t eb = 0;
+// The cell's resource and wall bits of its sense byte.
+__device__ __forceinline__ uint32_t cell_sense(const WorldParams& wp, uint32_t r, uint32_t wl) {
+  return (r != 0 ? 2u : 0u) | (wp.has_walls && wl != 0 ? 4u : 0u);
+}
+
+// An occupant's bits of the sense byte: the agent bit and its energy bin
+// (the number of b in 1..7 with 8 E >= b e_repro).
+__device__ __forceinline__ uint32_t agent_sense(const WorldParams& wp, int energy) {
+  const long long e8 = (long long)energy * 8;
+  uint32_t eb = 0;
 #pragma unroll
-    for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1u : 0u;
-    v |= 1u | (eb << 3);
-  }
-  return v;
+  for (int b = 1; b < 8; ++b) eb += (e8 >= (long long)b * wp.e_repro) ? 1u : 0u;
+  return 1u | (eb << 3);
+}
+
+__device__ __forceinline__ uint32_t sense_of(const WorldParams& wp, const Dev& d, int o, uint32_t r, uint32_t wl) {
+  const uint32_t v = cell_sense(wp, r, wl);
+  return o >= 0 ? v | agent_sense(wp, d.energy[wp.slot_off + (uint32_t)o]) : v;
 }
 
 // Colour vision: the cell as others see it (occupant's colour, else a resource
@@ -1390,6 +1398,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // threads; slots or cells per thread in one pass (one 4-byte load of bytes); passes over
   // the slots (the capacity is at most NT CH NP)
   constexpr int NT = 1024, CH = 4, NP = 2;
+  static_assert(NT * CH * NP == ECO_SMALL_STEP_MAX_SLOTS, "the slot passes cover the largest object taken");
   __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
   __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
   __shared__ uint32_t blocked;
@@ -1400,6 +1409,9 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[NT / 64];                  // the births' reductions, then the waves' trait sums
   __shared__ double2 tab[kTrigTable];
+  // per cell: the agent bit and energy bin of its occupant after the step (0: none),
+  // written from the live slots, read by the window-channel pass
+  __shared__ __align__(16) uint8_t s_agent[ECO_SMALL_STEP_MAX_CELLS];
   const uint32_t tid = threadIdx.x;
   // live-list entry tid, loaded together with the world's live count: the
   // thread's only agent when there are at most NT (the object's one world
@@ -1419,6 +1431,9 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // the flag bytes of slots b0 .. b0 + 3 (slot and cell ranges start at multiples of
   // 64 and their allocations end at one, so these 4-byte loads stay inside)
   auto flags4 = [&](uint32_t b0) { return *reinterpret_cast<const uint32_t*>(d.flags + wp.slot_off + b0); };
+  const bool sense_bytes = d.rgb == nullptr;   // window channels as sense bytes (else rendered words)
+  if (sense_bytes)
+    for (uint32_t c0 = tid * 16; c0 < cells; c0 += NT * 16) *reinterpret_cast<uint4*>(s_agent + c0) = make_uint4(0, 0, 0, 0);
 
   // 1. moves, eating, costs and deaths of the step's live agents
   for (uint32_t i = l0; i < l1; ++i) {
@@ -1529,19 +1544,21 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     // (they lie inside the allocations, which end at a multiple of 64 slots)
     static_assert(CH == 4, "one 16-byte load of energies per pass");
     double2 tv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-    int4 ev = make_int4(0, 0, 0, 0);
+    int4 ev = make_int4(0, 0, 0, 0), pv = make_int4(0, 0, 0, 0);
     if (b0 < cap) {
       tv[0] = *reinterpret_cast<const double2*>(d.trait + wp.slot_off + b0);
       tv[1] = *reinterpret_cast<const double2*>(d.trait + wp.slot_off + b0 + 2);
       ev = *reinterpret_cast<const int4*>(d.energy + wp.slot_off + b0);
+      if (sense_bytes) pv = *reinterpret_cast<const int4*>(d.pos + wp.slot_off + b0);
     }
     const double tj[4] = {tv[0].x, tv[0].y, tv[1].x, tv[1].y};
-    const int ej[4] = {ev.x, ev.y, ev.z, ev.w};
+    const int ej[4] = {ev.x, ev.y, ev.z, ev.w}, pj[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const bool on = (am[p] >> j) & 1u;
       t[p][j] = on ? tj[j] : 0.0;
       es += on ? ej[j] : 0;
+      if (sense_bytes && on) s_agent[pj[j]] = (uint8_t)agent_sense(wp, ej[j]);   // one agent per cell
     }
 #pragma unroll
     for (int j = 0; j < CH; ++j) s1 += t[p][j];
@@ -1619,9 +1636,27 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // window channels of every cell for the next step (the grid is final)
   for (uint32_t c0 = tid * 4; c0 < cells; c0 += NT * 4)
     *reinterpret_cast<uint4*>(d.claim + wp.cell_off + c0) = make_uint4(~0u, ~0u, ~0u, ~0u);
-  const Tile all{w, 0u, cells, 0u};
-  if (d.rgb) cell_render_tile(d, all);
-  else cell_sense_tile(d, all);
+  if (sense_bytes) {
+    // the sense bytes: resource and wall bits of each cell, with its occupant's
+    // agent bit and energy bin from s_agent (complete since the barrier above)
+    for (uint32_t c0 = tid * 4; c0 < cells; c0 += NT * 4) {
+      const uint32_t g = wp.cell_off + c0;
+      const uint32_t r = *reinterpret_cast<const uint32_t*>(d.res + g);
+      const uint32_t wl = *reinterpret_cast<const uint32_t*>(d.wall + g);
+      const uint32_t ag = *reinterpret_cast<const uint32_t*>(s_agent + c0);
+      uint32_t v = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v |= (((ag >> (8 * j)) & 0xFFu) | cell_sense(wp, (r >> (8 * j)) & 0xFFu, (wl >> (8 * j)) & 0xFFu)) << (8 * j);
+      if (c0 + 4 <= cells) {
+        *reinterpret_cast<uint32_t*>(d.sense + g) = v;
+      } else {
+        for (uint32_t j = 0; c0 + j < cells; ++j) d.sense[g + j] = (uint8_t)(v >> (8 * j));
+      }
+    }
+  } else {
+    cell_render_tile(d, Tile{w, 0u, cells, 0u});
+  }
 }
 
 // Rendered window words of one world's cells (after a colour write).
