@@ -92,6 +92,15 @@ static uint32_t draw_x0(const uint32_t key[2], uint32_t a, uint32_t step, uint32
     return out[0];
 }
 
+/* The regrowth (or photosynthesis) draw of cell c at step t: output c mod 4 of
+ * the block with counter (c / 4, t, REGROW, 0), one block for four neighbouring
+ * cells, as a parameter takes output p mod 4 of its mutation block. */
+static uint32_t draw_cell(const uint32_t key[2], uint32_t c, uint32_t step) {
+    uint32_t ctr[4] = {c >> 2, step, ST_REGROW, 0}, out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[c & 3];
+}
+
 /* cos and sin of 2 pi j 2^-24 for 0 <= j < 2^24.  The whole quarter turns
  * q = j >> 22 come off exactly; of the rest r (a fraction r 2^-22 of a quarter
  * turn) libm gets the angle from the nearer end of the quarter, 2 pi r 2^-24 or
@@ -1106,19 +1115,20 @@ int orc_step(orc_world* w, const uint8_t* actions, double* logits_out, uint8_t* 
     /* 7. Regrowth: an empty cell gets one unit with probability regrow_prob.
      *    Ecology: photosynthesis instead, one energy unit with probability
      *    min(1, photo_rate * biomass) on every cell holding biomass, up to
-     *    cell_energy_max (photo_rate * biomass is exact in FP64). */
+     *    cell_energy_max (photo_rate * biomass is exact in FP64).  The draw of
+     *    cell c is draw_cell (four cells per Philox block). */
     if (!w->eco) {
         uint64_t thr = bern_threshold(w->d.regrow_prob);
         for (uint32_t c = 0; c < w->cells; ++c) {
             if (w->res[c] != 0) continue;
-            if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->res[c] = 1; st->regrown++; }
+            if ((uint64_t)draw_cell(w->key, c, step32) < thr) { w->res[c] = 1; st->regrown++; }
         }
     } else {
         for (uint32_t c = 0; c < w->cells; ++c) {
             if (w->cb[c] <= 0 || w->ce[c] >= w->d.eco.cell_energy_max) continue;
             double p = (double)w->d.eco.photo_rate * (double)w->cb[c];
             uint64_t thr = p >= 1.0 ? (1ull << 32) : (uint64_t)floor(p * 4294967296.0);
-            if ((uint64_t)draw_x0(w->key, c, step32, ST_REGROW, 0) < thr) { w->ce[c] += 1; st->regrown++; }
+            if ((uint64_t)draw_cell(w->key, c, step32) < thr) { w->ce[c] += 1; st->regrown++; }
         }
         /* 7b. Terrain: all water on a cell with a flow direction moves one cell
          *     downhill, every cell at once (water is conserved). */

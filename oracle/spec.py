@@ -423,7 +423,8 @@ class SpecWorld:
             nb += 1
         st["births"] = nb
         self.uid_next += nb
-        # regrowth (ecology: photosynthesis on biomass)
+        # regrowth (ecology: photosynthesis on biomass); cell i draws output i mod 4 of
+        # the block (i // 4, step, 6, 0)
         thr = math.floor(f32(c["regrow_prob"]) * 4294967296.0)
         for i in range(self.W * self.H):
             if self.eco is not None:
@@ -432,10 +433,10 @@ class SpecWorld:
                     continue
                 p = Fraction(f32(self.eco["photo_rate"])) * b
                 t = 2 ** 32 if p >= 1 else math.floor(p * 2 ** 32)
-                if philox4x32_10([i, n, 6, 0], self.key)[0] < t:
+                if philox4x32_10([i >> 2, n, 6, 0], self.key)[i & 3] < t:
                     self.ce[i] += 1
                     st["regrown"] += 1
-            elif self.res[i] == 0 and philox4x32_10([i, n, 6, 0], self.key)[0] < thr:
+            elif self.res[i] == 0 and philox4x32_10([i >> 2, n, 6, 0], self.key)[i & 3] < thr:
                 self.res[i] = 1
                 st["regrown"] += 1
         if self.flags & TERRAIN:   # all water one cell downhill, every cell at once

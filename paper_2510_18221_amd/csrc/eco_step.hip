@@ -555,25 +555,60 @@ __device__ __forceinline__ uint64_t photo_threshold(float rate, int b) {
   return v > one ? one : v;
 }
 
-// Regrowth of the cells of tile tl (one resource layer): each empty cell regrows
-// one unit with probability p (a Philox draw against floor(p 2^32)); the regrown
-// count and the resource total go to cnt[0], cnt[1] (LDS).
-__device__ __forceinline__ bool regrows(const WorldParams& wp, uint32_t c, uint32_t step) {
-  return (uint64_t)draw32(wp, c, step, ST_REGROW) < wp.regrow_thr;
+// The regrowth (and photosynthesis) draws of local cells 4 q .. 4 q + 3 at `step`:
+// one Philox block, output j for cell 4 q + j.
+__device__ __forceinline__ uint4 regrow_draws(const WorldParams& wp, uint32_t q, uint32_t step) {
+  return philox10(q, step, ST_REGROW, 0u, wp.key0, wp.key1);
 }
 
+__device__ __forceinline__ uint32_t word_of(const uint4& x, int j) {
+  return j == 0 ? x.x : (j == 1 ? x.y : (j == 2 ? x.z : x.w));
+}
+
+// One regrowth pass over the resource bytes of local cells c0 .. c0 + n - 1 (c0 a
+// multiple of 4, n <= 4) held in the word v: each empty cell regrows one unit
+// with probability p (its draw against floor(p 2^32)).  Returns the new word;
+// adds the regrown cells and the resource total to grown and total.
+__device__ __forceinline__ uint32_t regrow_word(const WorldParams& wp, uint32_t c0, uint32_t n, uint32_t v,
+                                                uint32_t step, unsigned long long& grown, unsigned long long& total) {
+  bool any = false;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) any |= j < n && ((v >> (8 * j)) & 0xFFu) == 0;
+  uint32_t nv = v;
+  if (any) {
+    const uint4 x = regrow_draws(wp, c0 >> 2, step);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < n && ((v >> (8 * j)) & 0xFFu) == 0 && (uint64_t)word_of(x, (int)j) < wp.regrow_thr) {
+        nv |= 1u << (8 * j);
+        ++grown;
+      }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j)
+    if (j < n) total += (nv >> (8 * j)) & 0xFFu;
+  return nv;
+}
+
+// Regrowth of the cells of tile tl (one resource layer), four cells per thread
+// and pass (tiles start at multiples of 1024 cells; the cell allocation ends at a
+// multiple of 64, so the last word of a tile stays inside it); the regrown count
+// and the resource total go to cnt[0], cnt[1] (LDS).
 __device__ __forceinline__ void regrow_cells(const Dev& d, const WorldParams& wp, const Tile tl, uint32_t step,
                                              unsigned long long* cnt) {
   unsigned long long grown = 0, total = 0;
-  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-    const uint32_t c = tl.start + i;
-    uint8_t r = d.res[wp.cell_off + c];
-    if (r == 0 && regrows(wp, c, step)) {
-      r = 1;
-      d.res[wp.cell_off + c] = 1;
-      ++grown;
+  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
+    const uint32_t c0 = tl.start + i, n = min(4u, tl.count - i);
+    uint8_t* rp = d.res + wp.cell_off + c0;
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(rp);
+    const uint32_t nv = regrow_word(wp, c0, n, v, step, grown, total);
+    if (nv != v) {
+      if (n == 4) {
+        *reinterpret_cast<uint32_t*>(rp) = nv;
+      } else {
+        for (uint32_t j = 0; j < n; ++j) rp[j] = (uint8_t)(nv >> (8 * j));
+      }
     }
-    total += r;
   }
   wave_add_u64(grown, &cnt[0]);
   wave_add_u64(total, &cnt[1]);
@@ -596,7 +631,7 @@ __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts,
       const int b = d.cb[g];
       int en = d.ce[g];
       if (b > 0 && en < e.cell_energy_max) {
-        if ((uint64_t)draw32(wp, c, step, ST_REGROW) < photo_threshold(e.photo_rate, b)) {
+        if ((uint64_t)word_of(regrow_draws(wp, c >> 2, step), (int)(c & 3u)) < photo_threshold(e.photo_rate, b)) {
           d.ce[g] = ++en;
           ++grown;
         }
@@ -1448,18 +1483,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
       uint32_t* rp = reinterpret_cast<uint32_t*>(d.res + wp.cell_off + c0);
       const uint32_t v = *rp;
-      uint32_t nv = v;
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        const uint32_t c = c0 + j;
-        uint32_t r = (v >> (8 * j)) & 0xFFu;
-        if (c < cells && r == 0 && regrows(wp, c, step)) {
-          r = 1;
-          nv |= 1u << (8 * j);
-          ++grown;
-        }
-        if (c < cells) total += r;
-      }
+      const uint32_t nv = regrow_word(wp, c0, min((uint32_t)CH, cells - c0), v, step, grown, total);
       if (nv != v) *rp = nv;
     }
     wave_add_u64(grown, &ccnt[0]);

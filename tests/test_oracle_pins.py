@@ -600,6 +600,22 @@ def test_T10_regrowth_extremes():
     assert s["regrown"] == 0 and out["res"].sum() == 1
 
 
+def test_T10b_regrowth_draw_mapping():
+    """The regrowth draw of cell c at step t is output c mod 4 of the Philox block
+    with counter (c // 4, t, 6, 0) (reading 22): with p = 1/2 exactly the empty
+    cells whose draw is below 2^31 regrow.  The block is computed here from the
+    published round function (pinned by the known-answer vectors above)."""
+    cfg = tiny_cfg(width=8, height=8, regrow_prob=0.5, seed=0x1234_5678_9ABC)
+    st = empty_state(8, 8, 4, step=5)
+    st["res"][[3, 17, 40]] = 1
+    out, s = run_both(cfg, st, [0, 0, 0, 0])
+    key = [cfg["seed"] & 0xFFFFFFFF, cfg["seed"] >> 32]
+    want = [1 if st["res"][c] else int(spec.philox4x32_10([c >> 2, 5, 6, 0], key)[c & 3] < 2 ** 31)
+            for c in range(64)]
+    assert list(out["res"]) == want
+    assert s["regrown"] == sum(want) - 3 and 0 < s["regrown"] < 61
+
+
 def test_T11_window_orientation():
     cfg = tiny_cfg(width=5, height=5, window=3, capacity=4)
     for facing, idx in [(E, 4 * (0 * 3 + 1) + 1), (N, 4 * (1 * 3 + 2) + 1), (S, 4 * (1 * 3 + 0) + 1),
