@@ -1543,11 +1543,10 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   if (nb) load_trig(d.trig, tab);
   for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H, NT>(d, L, w, wp, b, step, tab, s_amax, s_red);
   // 5. the next step's live list and the statistics record: energy exact in
-  // integers, the trait moments in two passes over the values held in registers.
-  // One barrier gives every thread its wave's offsets in the live list (both
-  // passes' counts packed in a u32), the energy total and the trait sum (the
-  // waves' sums, added the same way in every wave); a second one the sum of
-  // squared deviations.
+  // integers, the trait moments of each wave in two passes over the values held
+  // in registers, merged across waves.  One barrier gives every wave its offsets
+  // in the live list (both passes' counts packed in a u32) and thread 0 the
+  // waves' energy sums and trait moments.
   long long es = 0;
   double t[NP][CH], s1 = 0.0;
   uint32_t am[NP];
@@ -1591,20 +1590,29 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   const uint32_t own = (uint32_t)__builtin_popcount(am[0]) | (uint32_t)__builtin_popcount(am[1]) << 16;
   const uint32_t inc = wave_scan(own);
   const unsigned long long ew = wave_scan((unsigned long long)es);
-  const double sw = wave_scan(s1);
+  // the wave's trait moments in two passes over its values: count, mean, and the
+  // sum of squared deviations from that mean (merged across waves by thread 0)
+  const uint32_t wc = lane_value(inc, 63);
+  const double n_w = (double)((wc & 0xFFFFu) + (wc >> 16));
+  const double mean_w = n_w > 0.0 ? lane_value(wave_scan(s1), 63) / n_w : 0.0;
+  double m2 = 0.0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean_w) * (t[p][j] - mean_w);
+  m2 = wave_scan(m2);
   if (lane == 63) {
     live_red[wave] = inc;
     red64[wave] = ew;
-    s_red[wave] = sw;
+    s_red[wave] = mean_w;
+    m2_red[wave] = m2;
   }
   __syncthreads();
-  // the waves' sums, added the same way in every wave (lane i reads wave i's)
+  // each wave's offsets in the live list (the waves' counts added the same way in
+  // every wave, lane i reading wave i's)
   uint32_t ntot;
   const uint32_t before = waves_before<NT / 64>(lane < NT / 64 ? live_red[lane] : 0u, &ntot);
-  unsigned long long E;
-  (void)waves_before<NT / 64>(lane < NT / 64 ? red64[lane] : 0ull, &E);
-  double S1;
-  (void)waves_before<NT / 64>(lane < NT / 64 ? s_red[lane] : 0.0, &S1);
   const uint32_t N0 = ntot & 0xFFFFu, N = N0 + (ntot >> 16);
   const uint32_t ex = before + inc - own;
 #pragma unroll
@@ -1613,20 +1621,17 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     uint32_t r = (p == 0 ? 0u : N0) + ((ex >> (16 * p)) & 0xFFFFu);
     for (uint32_t a = am[p]; a; a &= a - 1) d.live[wp.slot_off + r++] = (int)(b0 + __builtin_ctz(a));
   }
-  const double mean = N ? S1 / (double)N : 0.0;
-  double m2 = 0.0;
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int j = 0; j < CH; ++j)
-      if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean) * (t[p][j] - mean);
-  m2 = wave_scan(m2);
-  if (lane == 63) m2_red[wave] = m2;
-  __syncthreads();
   if (tid == 0) {
-    double M2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) M2 += m2_red[i];
+    // the energy total exactly, the trait moments by the pairwise (Chan-Golub-LeVeque)
+    // merge of the waves' in wave order
+    unsigned long long E = 0;
+    Moments tm{0.0, 0.0, 0.0};
+    for (int i = 0; i < NT / 64; ++i) {
+      E += red64[i];
+      const uint32_t c = live_red[i];
+      tm = merge_moments(tm, Moments{(double)((c & 0xFFFFu) + (c >> 16)), s_red[i], m2_red[i]});
+    }
+    const double mean = N ? tm.mean : 0.0, M2 = tm.m2;
     WorldVar& v = d.wv[w];
     v.n_births = nb;
     v.n_win = Wn;
