@@ -506,10 +506,11 @@ __global__ __launch_bounds__(kSlotTile) void k_move(Dev d, const Tile* __restric
 // One slot's birth claim: an eligible live parent claims the empty cell directly
 // behind it (lowest slot wins, atomicMin); a parent whose cell behind is taken or
 // walled counts as blocked.
-__device__ __forceinline__ void birth_claim_slot(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
+// Returns whether the slot claimed a cell.
+__device__ __forceinline__ bool birth_claim_slot(const Dev& d, const WorldParams& wp, uint32_t w, uint32_t slot,
                                                  uint32_t n_actions, uint32_t* blocked) {
   const uint8_t fl = d.flags[slot];
-  if (!(fl & kAlive)) return;
+  if (!(fl & kAlive)) return false;
   bool eligible = d.energy[slot] >= wp.e_repro && (n_actions == 5 || d.act[slot] == REPRODUCE);
   if (d.ep) {   // ecology: the eighth action, and spare biomass and water to give the child
     const eco_ecology& e = d.ep[w];
@@ -523,10 +524,11 @@ __device__ __forceinline__ void birth_claim_slot(const Dev& d, const WorldParams
       atomicMin(&d.claim[wp.cell_off + t], slot);
       d.tgt[slot] = (int)t;
       d.flags[slot] = fl | kBirthClaim;
-    } else {
-      count_lanes(blocked);
+      return true;
     }
+    count_lanes(blocked);
   }
+  return false;
 }
 
 __device__ __forceinline__ void birth_claim_tile(const Dev& d, const TileScratch& ts, uint32_t tile, uint32_t n_actions,
@@ -1436,7 +1438,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   static_assert(NT * CH * NP == ECO_SMALL_STEP_MAX_SLOTS, "the slot passes cover the largest object taken");
   __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
   __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
-  __shared__ uint32_t blocked;
+  __shared__ uint32_t blocked, any_claim;
   __shared__ unsigned long long rank_red[NT / 64];   // the ranking scan's wave totals
   __shared__ uint32_t live_red[NT / 64];             // the live list's wave counts
   __shared__ unsigned long long red64[NT / 64];      // the waves' energy sums
@@ -1454,7 +1456,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   const int32_t live_tid = d.live[min(tid, d.total_slots - 1u)];
   if (tid < kSlotPart) cnt[tid] = 0;
   if (tid < kCellPart) ccnt[tid] = 0;
-  if (tid == 0) blocked = 0;
+  if (tid == 0) blocked = any_claim = 0;
   __syncthreads();
   constexpr uint32_t w = 0;
   const WorldParams wp = d.wp[w];
@@ -1477,7 +1479,9 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   }
   __syncthreads();
   // 2. birth claims of the agents still alive; regrowth of every cell (4 per thread and pass)
-  for (uint32_t i = l0; i < l1; ++i) birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
+  bool claimed = false;
+  for (uint32_t i = l0; i < l1; ++i) claimed |= birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
+  if (claimed) any_claim = 1u;   // the same value from every claimant
   {
     unsigned long long grown = 0, total = 0;
     for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
@@ -1490,55 +1494,59 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     wave_add_u64(total, &ccnt[1]);
   }
   __syncthreads();
-  // 3. birth ranking: the claim winners in slot order (the live list's order)
-  // and the free slots in ascending order (the recycled-slot free list; only its
-  // first Wn entries are used), both ranked by one block scan of 16-bit counts
-  // packed in a u64 (winners, free slots of each pass, claims; no field carries
-  // into the next: every total is at most 8,192).  The claim flags and the
-  // claimed cells are cleared at the end of the step, by the last pass over the
-  // slots and the cells.
-  uint32_t nw = 0, nc = 0;
-  for (uint32_t i = l0; i < l1; ++i) {
-    const uint32_t slot = wp.slot_off + (uint32_t)live[i];
-    if (d.flags[slot] & kBirthClaim) {
-      ++nc;
-      if (d.claim[wp.cell_off + d.tgt[slot]] == slot) ++nw;
+  // 3. birth ranking, when any parent claimed a cell: the claim winners in slot
+  // order (the live list's order) and the free slots in ascending order (the
+  // recycled-slot free list; only its first Wn entries are used), both ranked by
+  // one block scan of 16-bit counts packed in a u64 (winners, free slots of each
+  // pass, claims; no field carries into the next: every total is at most 8,192).
+  // The claim flags and the claimed cells are cleared at the end of the step, by
+  // the last pass over the slots and the cells.
+  uint32_t Wn = 0, claims = 0, nb = 0;
+  if (any_claim) {   // the same in every thread (written before the barrier above)
+    uint32_t nw = 0, nc = 0;
+    for (uint32_t i = l0; i < l1; ++i) {
+      const uint32_t slot = wp.slot_off + (uint32_t)live[i];
+      if (d.flags[slot] & kBirthClaim) {
+        ++nc;
+        if (d.claim[wp.cell_off + d.tgt[slot]] == slot) ++nw;
+      }
     }
-  }
-  uint32_t fm[NP];
+    uint32_t fm[NP];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const uint32_t b0 = (p * NT + tid) * CH;
-    fm[p] = 0;
-    if (b0 < cap) {
-      const uint32_t v = flags4(b0);
+    for (int p = 0; p < NP; ++p) {
+      const uint32_t b0 = (p * NT + tid) * CH;
+      fm[p] = 0;
+      if (b0 < cap) {
+        const uint32_t v = flags4(b0);
 #pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (b0 + j < cap && !((v >> (8 * j)) & kAlive)) fm[p] |= 1u << j;
+        for (int j = 0; j < CH; ++j)
+          if (b0 + j < cap && !((v >> (8 * j)) & kAlive)) fm[p] |= 1u << j;
+      }
     }
-  }
-  static_assert(NP == 2, "the packed ranking scan holds two passes of free slots");
-  unsigned long long rtot;
-  const unsigned long long rex =
-      block_exscan_u64<NT>((unsigned long long)nw | (unsigned long long)__builtin_popcount(fm[0]) << 16 |
-                               (unsigned long long)__builtin_popcount(fm[1]) << 32 | (unsigned long long)nc << 48,
-                           rank_red, &rtot);
-  const uint32_t Wn = (uint32_t)(rtot & 0xFFFFu), claims = (uint32_t)(rtot >> 48);
-  uint32_t k = (uint32_t)(rex & 0xFFFFu);
-  for (uint32_t i = l0; i < l1 && nw; ++i) {
-    const uint32_t local = (uint32_t)live[i], slot = wp.slot_off + local;
-    if ((d.flags[slot] & kBirthClaim) && d.claim[wp.cell_off + d.tgt[slot]] == slot) d.bparent[wp.slot_off + k++] = (int)local;
-  }
-  uint32_t F = 0;
+    static_assert(NP == 2, "the packed ranking scan holds two passes of free slots");
+    unsigned long long rtot;
+    const unsigned long long rex =
+        block_exscan_u64<NT>((unsigned long long)nw | (unsigned long long)__builtin_popcount(fm[0]) << 16 |
+                                 (unsigned long long)__builtin_popcount(fm[1]) << 32 | (unsigned long long)nc << 48,
+                             rank_red, &rtot);
+    Wn = (uint32_t)(rtot & 0xFFFFu);
+    claims = (uint32_t)(rtot >> 48);
+    uint32_t k = (uint32_t)(rex & 0xFFFFu);
+    for (uint32_t i = l0; i < l1 && nw; ++i) {
+      const uint32_t local = (uint32_t)live[i], slot = wp.slot_off + local;
+      if ((d.flags[slot] & kBirthClaim) && d.claim[wp.cell_off + d.tgt[slot]] == slot) d.bparent[wp.slot_off + k++] = (int)local;
+    }
+    uint32_t F = 0;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const uint32_t b0 = (p * NT + tid) * CH;
-    uint32_t f = F + (uint32_t)((rex >> (16 * (p + 1))) & 0xFFFFu);
-    for (uint32_t m = fm[p]; m && f < Wn; m &= m - 1) d.freel[wp.slot_off + f++] = (int)(b0 + __builtin_ctz(m));
-    F += (uint32_t)((rtot >> (16 * (p + 1))) & 0xFFFFu);
+    for (int p = 0; p < NP; ++p) {
+      const uint32_t b0 = (p * NT + tid) * CH;
+      uint32_t f = F + (uint32_t)((rex >> (16 * (p + 1))) & 0xFFFFu);
+      for (uint32_t m = fm[p]; m && f < Wn; m &= m - 1) d.freel[wp.slot_off + f++] = (int)(b0 + __builtin_ctz(m));
+      F += (uint32_t)((rtot >> (16 * (p + 1))) & 0xFFFFu);
+    }
+    nb = min(Wn, F);
+    __syncthreads();
   }
-  const uint32_t nb = min(Wn, F);
-  __syncthreads();
   // 4. the births, one at a time (the angle table of the mutation noise only when there are any)
   if (nb) load_trig(d.trig, tab);
   for (uint32_t b = 0; b < nb; ++b) commit_birth<WDT, H, NT>(d, L, w, wp, b, step, tab, s_amax, s_red);
