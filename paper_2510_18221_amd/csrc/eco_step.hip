@@ -1499,8 +1499,8 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // recycled-slot free list; only its first Wn entries are used), both ranked by
   // one block scan of 16-bit counts packed in a u64 (winners, free slots of each
   // pass, claims; no field carries into the next: every total is at most 8,192).
-  // The claim flags and the claimed cells are cleared at the end of the step, by
-  // the last pass over the slots and the cells.
+  // The claimed cells are released right after the ranking, the claim flags by the
+  // last pass over the slots.
   uint32_t Wn = 0, claims = 0, nb = 0;
   if (any_claim) {   // the same in every thread (written before the barrier above)
     uint32_t nw = 0, nc = 0;
@@ -1546,6 +1546,12 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     }
     nb = min(Wn, F);
     __syncthreads();
+    // the claimed cells released (every claimant has read its cell's claim word;
+    // the movers' winners released theirs in the move phase)
+    for (uint32_t i = l0; i < l1; ++i) {
+      const uint32_t slot = wp.slot_off + (uint32_t)live[i];
+      if (d.flags[slot] & kBirthClaim) d.claim[wp.cell_off + d.tgt[slot]] = 0xFFFFFFFFu;
+    }
   }
   // 4. the births, one at a time (the angle table of the mutation noise only when there are any)
   if (nb) load_trig(d.trig, tab);
@@ -1668,11 +1674,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     st.trait_var = N ? M2 / (double)N : 0.0;
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
-  // the step's claimed cells released (every claim word back to "none": the
-  // movers' winners released theirs in the move phase, the births' here), and the
-  // window channels of every cell for the next step (the grid is final)
-  for (uint32_t c0 = tid * 4; c0 < cells; c0 += NT * 4)
-    *reinterpret_cast<uint4*>(d.claim + wp.cell_off + c0) = make_uint4(~0u, ~0u, ~0u, ~0u);
+  // the window channels of every cell for the next step (the grid is final)
   if (sense_bytes) {
     // the sense bytes: resource and wall bits of each cell, with its occupant's
     // agent bit and energy bin from s_agent (complete since the barrier above)
