@@ -238,7 +238,7 @@ typedef struct {
                                    ECO_RT_USE_GRAPH, event-record nodes around the policy kernel
                                    only, in a graph of the n steps of each eco_world_step call (one
                                    graph kept per n).  The call synchronises to read the times. */
-#define ECO_RT_SPLIT_STEP 8u    /* an object of one world without the ecology, with at most 8,192
+#define ECO_RT_SPLIT_STEP 8u    /* an object of one world with at most 8,192
                                    slots and 16,384 cells, runs the step after the policy kernel
                                    as one fused launch (timed as ECO_K_MOVE); this flag runs the
                                    separate kernels instead.  Same integer state and statistics

@@ -450,12 +450,12 @@ hipError_t launch_group(eco_world* w, hipStream_t s, const Dev& d, const TileScr
   }
 }
 
-// An object of one small world without the ecology steps with the policy kernel
+// An object of one small world steps with the policy kernel
 // and one fused launch (k_step_small) unless ECO_RT_SPLIT_STEP asks for the
 // separate kernels: its step is bound by launch latency, not by bytes.
 constexpr uint32_t kSmallSlots = ECO_SMALL_STEP_MAX_SLOTS, kSmallCells = ECO_SMALL_STEP_MAX_CELLS;
 bool small_step(const eco_world* w) {
-  return w->n_worlds == 1 && !w->L.ecology && w->total_slots <= kSmallSlots && w->total_cells <= kSmallCells &&
+  return w->n_worlds == 1 && w->total_slots <= kSmallSlots && w->total_cells <= kSmallCells &&
          !(w->rt_flags & ECO_RT_SPLIT_STEP);
 }
 

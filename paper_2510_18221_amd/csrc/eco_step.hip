@@ -616,49 +616,55 @@ __device__ __forceinline__ void regrow_cells(const Dev& d, const WorldParams& wp
   wave_add_u64(total, &cnt[1]);
 }
 
+// The ecology's cell pass over tile tl (the block's threads in turn): photosynthesis,
+// one energy unit with probability min(1, rate * biomass) on cells holding biomass
+// below the energy ceiling (the threshold in exact integers); the strikes of this
+// step cleared (they have been counted); with terrain, all water of a cell moves one
+// cell downhill, every cell at once, as a gather into cw_next (a cell keeps its water
+// if it has no way down, and takes that of each neighbour whose way down leads
+// here; the window-word pass copies it back once every cell has read the old
+// layer).  Adds the photosynthesised units to grown and the grid totals of energy,
+// water and biomass to total, wsum, bsum.
+__device__ __forceinline__ void ecology_cells(const Dev& d, const WorldParams& wp, const eco_ecology& e, const Tile tl,
+                                              uint32_t step, unsigned long long& grown, unsigned long long& total,
+                                              unsigned long long& wsum, unsigned long long& bsum) {
+  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+    const uint32_t c = tl.start + i, g = wp.cell_off + c;
+    const int b = d.cb[g];
+    int en = d.ce[g];
+    if (b > 0 && en < e.cell_energy_max) {
+      if ((uint64_t)word_of(regrow_draws(wp, c >> 2, step), (int)(c & 3u)) < photo_threshold(e.photo_rate, b)) {
+        d.ce[g] = ++en;
+        ++grown;
+      }
+    }
+    total += (unsigned long long)(uint32_t)en;
+    wsum += (unsigned long long)(uint32_t)d.cw[g];
+    bsum += (unsigned long long)(uint32_t)b;
+    if (wp.attack) d.mark[g] = 0;
+  }
+  if (d.rock) {
+    for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
+      const uint32_t c = tl.start + i, g = wp.cell_off + c;
+      int acc = d.flowdir[g] < 0 ? d.cw[g] : 0;
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const uint32_t n = wp.cell_off + neighbour(wp, c, dd, +1);
+        if (d.flowdir[n] == ((dd + 2) & 3)) acc += d.cw[n];
+      }
+      d.cw_next[g] = acc;
+    }
+  }
+}
+
 __device__ __forceinline__ void regrow_tile(const Dev& d, const TileScratch& ts, uint32_t tile,
                                             unsigned long long* cnt) {
   const Tile tl = ts.cell_tiles[tile];
   const WorldParams wp = d.wp[tl.world];
   const uint32_t step = (uint32_t)d.wv[tl.world].step;
-  unsigned long long grown = 0, total = 0;
-  if (d.ep) {
-    // ecology: photosynthesis, one energy unit with probability min(1, rate * biomass)
-    // on cells holding biomass below the energy ceiling (the threshold in exact
-    // integers); the tile's grid totals of energy, water and biomass for the statistics
-    const eco_ecology& e = d.ep[tl.world];
-    unsigned long long wsum = 0, bsum = 0;
-    for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-      const uint32_t c = tl.start + i, g = wp.cell_off + c;
-      const int b = d.cb[g];
-      int en = d.ce[g];
-      if (b > 0 && en < e.cell_energy_max) {
-        if ((uint64_t)word_of(regrow_draws(wp, c >> 2, step), (int)(c & 3u)) < photo_threshold(e.photo_rate, b)) {
-          d.ce[g] = ++en;
-          ++grown;
-        }
-      }
-      total += (unsigned long long)(uint32_t)en;
-      wsum += (unsigned long long)(uint32_t)d.cw[g];
-      bsum += (unsigned long long)(uint32_t)b;
-      if (wp.attack) d.mark[g] = 0;   // the strikes of this step have been counted
-    }
-    if (d.rock) {
-      // terrain: all water of a cell moves one cell downhill, every cell at once,
-      // as a gather (a cell keeps its water if it has no way down, and takes that
-      // of each neighbour whose way down leads here); the compaction's cell pass
-      // copies it back, after this launch has read the old layer everywhere
-      for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-        const uint32_t c = tl.start + i, g = wp.cell_off + c;
-        int acc = d.flowdir[g] < 0 ? d.cw[g] : 0;
-#pragma unroll
-        for (int dd = 0; dd < 4; ++dd) {
-          const uint32_t n = wp.cell_off + neighbour(wp, c, dd, +1);
-          if (d.flowdir[n] == ((dd + 2) & 3)) acc += d.cw[n];
-        }
-        d.cw_next[g] = acc;
-      }
-    }
+  if (d.ep) {   // ecology: photosynthesis, strikes, flow; the tile's grid totals for the statistics
+    unsigned long long grown = 0, total = 0, wsum = 0, bsum = 0;
+    ecology_cells(d, wp, d.ep[tl.world], tl, step, grown, total, wsum, bsum);
     wave_add_u64(grown, &cnt[0]);
     wave_add_u64(total, &cnt[1]);
     wave_add_u64(wsum, &cnt[2]);
@@ -1242,8 +1248,7 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
 // first take the water the step's flow left on the cell.
 __device__ __forceinline__ uint32_t sat255(int v) { return (uint32_t)min(max(v, 0), 255); }
 
-__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const Tile tl, int flowed) {
-  const WorldParams wp = d.wp[tl.world];
+__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParams& wp, const Tile tl, int flowed) {
   for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
     const uint32_t cell = wp.cell_off + tl.start + i;
     if (flowed && d.rock) d.cw[cell] = d.cw_next[cell];
@@ -1398,7 +1403,7 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
   if (blockIdx.x >= ts.n_slot_tiles) {
     const Tile ct = ts.cell_tiles[blockIdx.x - ts.n_slot_tiles];
     if (only_world < 0 || (int)ct.world == only_world) {
-      if (d.ep) cell_ecology_tile(d, ct, !init);
+      if (d.ep) cell_ecology_tile(d, d.wp[ct.world], ct, !init);
       else if (d.rgb) cell_render_tile(d, ct);
       else cell_sense_tile(d, ct);
     }
@@ -1421,14 +1426,14 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
 
 // ---------------------------------------------------------------------------
 // The step after the policy kernel for an object of one small world, in one
-// block: moves, eating, costs and deaths, birth claims and regrowth, the birth
+// block: moves, eating, costs and deaths, birth claims and regrowth (the
+// ecology: photosynthesis, and with terrain the water's flow), the birth
 // ranking, the births, the next live list with the statistics record, and the
 // next step's window channels (the same per-agent and per-cell rules as the
 // kernels above, with the world's scans done inside the block).  A small world's
 // step is bound by the latency of its launches, and this replaces seven
-// dependent launches by one.  Worlds with the ecology or terrain take the
-// separate kernels.  A thread scans a contiguous range of slots, so every scan
-// is one block-wide exclusive sum.
+// dependent launches by one.  A thread scans a contiguous range of slots, so
+// every scan is one block-wide exclusive sum.
 // ---------------------------------------------------------------------------
 template <int WDT, int H>
 __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
@@ -1437,12 +1442,13 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   constexpr int NT = 1024, CH = 4, NP = 2;
   static_assert(NT * CH * NP == ECO_SMALL_STEP_MAX_SLOTS, "the slot passes cover the largest object taken");
   __shared__ uint32_t cnt[kSlotPart];              // step counters (PC_*)
-  __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total
+  __shared__ unsigned long long ccnt[kCellPart];   // regrown units, resource total (the ecology: grid energy), grid water, biomass
   __shared__ uint32_t blocked, any_claim;
   __shared__ unsigned long long rank_red[NT / 64];   // the ranking scan's wave totals
   __shared__ uint32_t live_red[NT / 64];             // the live list's wave counts
   __shared__ unsigned long long red64[NT / 64];      // the waves' energy sums
   __shared__ double m2_red[NT / 64];                 // the waves' sums of squared deviations
+  __shared__ unsigned long long eco_red[3][NT / 64];  // the ecology: the waves' carried water, biomass, health
   __shared__ uint32_t s_amax[128 + 128 + 16];
   __shared__ double s_red[NT / 64];                  // the births' reductions, then the waves' trait sums
   __shared__ double2 tab[kTrigTable];
@@ -1482,7 +1488,14 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   bool claimed = false;
   for (uint32_t i = l0; i < l1; ++i) claimed |= birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
   if (claimed) any_claim = 1u;   // the same value from every claimant
-  {
+  if (d.ep) {   // the ecology: photosynthesis, strikes cleared, the flow gather; the grid totals
+    unsigned long long grown = 0, total = 0, wsum = 0, bsum = 0;
+    ecology_cells(d, wp, d.ep[w], Tile{w, 0u, cells, 0u}, step, grown, total, wsum, bsum);
+    wave_add_u64(grown, &ccnt[0]);
+    wave_add_u64(total, &ccnt[1]);
+    wave_add_u64(wsum, &ccnt[2]);
+    wave_add_u64(bsum, &ccnt[3]);
+  } else {
     unsigned long long grown = 0, total = 0;
     for (uint32_t c0 = tid * CH; c0 < cells; c0 += NT * CH) {
       uint32_t* rp = reinterpret_cast<uint32_t*>(d.res + wp.cell_off + c0);
@@ -1597,6 +1610,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       es += on ? ej[j] : 0;
       if (sense_bytes && on) s_agent[pj[j]] = (uint8_t)agent_sense(wp, ej[j]);   // one agent per cell
     }
+
 #pragma unroll
     for (int j = 0; j < CH; ++j) s1 += t[p][j];
   }
@@ -1616,11 +1630,38 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     for (int j = 0; j < CH; ++j)
       if ((am[p] >> j) & 1u) m2 += (t[p][j] - mean_w) * (t[p][j] - mean_w);
   m2 = wave_scan(m2);
+  // the ecology: water, biomass and health carried by the live agents (after the
+  // trait values are no longer needed)
+  unsigned long long eco_w[3] = {0, 0, 0};
+  if (d.ep) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const uint32_t b0 = (p * NT + tid) * CH;
+      if (b0 < cap) {
+        const int4 wv4 = *reinterpret_cast<const int4*>(d.water + wp.slot_off + b0);
+        const int4 bv4 = *reinterpret_cast<const int4*>(d.biomass + wp.slot_off + b0);
+        const int4 hv4 = *reinterpret_cast<const int4*>(d.hp + wp.slot_off + b0);
+        const int wj[4] = {wv4.x, wv4.y, wv4.z, wv4.w}, bj[4] = {bv4.x, bv4.y, bv4.z, bv4.w},
+                  hj[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if ((am[p] >> j) & 1u) {
+            eco_w[0] += (unsigned long long)wj[j];
+            eco_w[1] += (unsigned long long)bj[j];
+            eco_w[2] += (unsigned long long)hj[j];
+          }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) eco_w[k] = wave_scan(eco_w[k]);
+  }
   if (lane == 63) {
     live_red[wave] = inc;
     red64[wave] = ew;
     s_red[wave] = mean_w;
     m2_red[wave] = m2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) eco_red[k][wave] = eco_w[k];
   }
   __syncthreads();
   // each wave's offsets in the live list (the waves' counts added the same way in
@@ -1672,6 +1713,15 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     st.energy_total = (double)(long long)E;
     st.trait_mean = mean;
     st.trait_var = N ? M2 / (double)N : 0.0;
+    if (d.ep) {   // grid (the cell pass) plus carried (the live slots)
+      unsigned long long ecot[3] = {0, 0, 0};
+#pragma unroll 1
+      for (int i = 0; i < NT / 64; ++i)
+        for (int k = 0; k < 3; ++k) ecot[k] += eco_red[k][i];
+      st.water_total = ecot[0] + ccnt[2];
+      st.biomass_total = ecot[1] + ccnt[3];
+      st.hp_total = ecot[2];
+    }
     d.ring[(uint64_t)w * kStatsRing + (v.step % kStatsRing)] = st;
   }
   // the window channels of every cell for the next step (the grid is final)
@@ -1693,6 +1743,8 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
         for (uint32_t j = 0; c0 + j < cells; ++j) d.sense[g + j] = (uint8_t)(v >> (8 * j));
       }
     }
+  } else if (d.ep) {
+    cell_ecology_tile(d, wp, Tile{w, 0u, cells, 0u}, 1);   // with terrain, the flowed water copied back first
   } else {
     cell_render_tile(d, Tile{w, 0u, cells, 0u});
   }
@@ -1702,7 +1754,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
 __global__ __launch_bounds__(256) void k_render(Dev d, const Tile* __restrict__ tiles, int only_world) {
   const Tile ct = tiles[blockIdx.x];
   if ((int)ct.world != only_world) return;
-  if (d.ep) cell_ecology_tile(d, ct, 0);
+  if (d.ep) cell_ecology_tile(d, d.wp[ct.world], ct, 0);
   else cell_render_tile(d, ct);
 }
 

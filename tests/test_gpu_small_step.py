@@ -1,5 +1,5 @@
 """The fused small-world step (k_step_small: one launch after the policy kernel for
-an object of one world without the ecology, at most 8,192 slots and 16,384 cells)
+an object of one world of at most 8,192 slots and 16,384 cells)
 against the separate kernels (ECO_RT_SPLIT_STEP) and against the oracle.
 
 The fused launch applies the same per-agent and per-cell rules and does the
@@ -59,6 +59,35 @@ CASES = {
 }
 
 
+def eco_world(**kw):
+    """A small world of the three-resource ecology with births: agents start with
+    the biomass and energy to reproduce, and meals are cheap."""
+    base = dict(width=24, height=20, n_agents_init=120, capacity=300, window=5, hidden1=32, hidden2=32,
+                mutation_sigma=0.05, e_init=250, seed=31)
+    e = kw.pop("eco", {})
+    base.update(kw)
+    return wl.ecology_desc(eco=dict(w_cost=1, age_shift=6, b_init=4, **e), **base)
+
+
+ECO = eco_mod.DESC_ECOLOGY
+CASES.update({
+    # the ecology: photosynthesis and the three totals in the record
+    "eco": eco_world(),
+    "eco_bf16_h64": eco_world(wdtype=wl.BF16, hidden1=64, hidden2=64, seed=32),
+    # strikes as the ninth action (health damage, marks cleared by the cell pass)
+    "eco_attack": eco_world(attack_enabled=1, eco=dict(attack_damage=50), seed=33),
+    # terrain (the flow gather and its copy-back) with the rendered colour window
+    "eco_terrain_colour": eco_world(window=7, flags=ECO | eco_mod.DESC_TERRAIN | eco_mod.DESC_COLOUR_VISION,
+                                    eco=dict(terrain_scale=12, sea_level=12, water_per_depth=3), seed=34),
+    # the paper's Ocean agent in a small world: the same with full-strength strikes
+    # and the evolving temperature, FP8 weights
+    "eco_ocean_fp8": eco_world(window=7, n_actions=9, attack_enabled=1, wdtype=wl.FP8,
+                               flags=ECO | eco_mod.DESC_TERRAIN | eco_mod.DESC_COLOUR_VISION
+                               | eco_mod.DESC_EVOLVE_TEMPERATURE,
+                               eco=dict(terrain_scale=12, sea_level=12, water_per_depth=3), seed=35),
+})
+
+
 def trait_close(a, b):
     return abs(a - b) <= 1e-12 * max(abs(a), abs(b), 1e-300)
 
@@ -92,7 +121,7 @@ def test_fused_equals_split(eco, name):
     fused.close()
     split.close()
     say(f"{name}: {steps} steps, {births} births, fused == split")
-    if name.startswith("busy") or name == "limits":
+    if name.startswith(("busy", "eco")) or name == "limits":
         assert births > 0
 
 
@@ -129,7 +158,8 @@ def test_split_kernels_match_oracle_on_small_worlds(eco, name):
     run_pair(eco, cfg, 8, actions_fn=acts, what=f"split {name}", flags=eco.RT_SPLIT_STEP)
 
 
-@pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64", "busy_bf16_h128", "limits"])
+@pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64", "busy_bf16_h128", "limits", "eco",
+                                  "eco_attack", "eco_terrain_colour", "eco_ocean_fp8"])
 def test_fused_matches_oracle(eco, name):
     cfg = CASES[name]
     acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 5, t, p_forward=0.3, p_eat=0.3,
