@@ -616,43 +616,122 @@ __device__ __forceinline__ void regrow_cells(const Dev& d, const WorldParams& wp
   wave_add_u64(total, &cnt[1]);
 }
 
-// The ecology's cell pass over tile tl (the block's threads in turn): photosynthesis,
-// one energy unit with probability min(1, rate * biomass) on cells holding biomass
-// below the energy ceiling (the threshold in exact integers); the strikes of this
-// step cleared (they have been counted); with terrain, all water of a cell moves one
-// cell downhill, every cell at once, as a gather into cw_next (a cell keeps its water
-// if it has no way down, and takes that of each neighbour whose way down leads
-// here; the window-word pass copies it back once every cell has read the old
-// layer).  Adds the photosynthesised units to grown and the grid totals of energy,
-// water and biomass to total, wsum, bsum.
+// Four consecutive int32 cells from g (g a multiple of 4; the cell allocation ends
+// at a multiple of 64, so the vector stays inside it even for a ragged tail) and
+// their store, whole for n = 4, else cell by cell.
+__device__ __forceinline__ void load_cells4(const int32_t* p, int v[4]) {
+  const int4 x = *reinterpret_cast<const int4*>(p);
+  v[0] = x.x;
+  v[1] = x.y;
+  v[2] = x.z;
+  v[3] = x.w;
+}
+
+__device__ __forceinline__ void store_cells4(int32_t* p, uint32_t n, const int v[4]) {
+  if (n == 4) {
+    *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]);
+  } else {
+    for (uint32_t j = 0; j < n; ++j) p[j] = v[j];
+  }
+}
+
+__device__ __forceinline__ int byte_of(uint32_t v, int j) { return (int)(int8_t)(uint8_t)(v >> (8 * j)); }
+
+// Terrain: the water on local cells c0 .. c0 + n - 1 after the flow (each cell's
+// water moves one cell downhill, every cell at once): a cell keeps its own water if
+// it has no way down, and takes that of each neighbour whose way down leads to it.
+// own[] holds the cells' water before the flow, fd their four direction bytes.
+// With W a multiple of 4 a whole group lies in one row, and the neighbours above
+// and below are whole aligned groups.
+__device__ __forceinline__ void flow_gather4(const Dev& d, const WorldParams& wp, uint32_t c0, uint32_t n,
+                                             const int own[4], uint32_t fd, int out[4]) {
+  const uint32_t off = wp.cell_off;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = byte_of(fd, j) < 0 ? own[j] : 0;
+  if ((wp.W & 3u) == 0 && n == 4) {
+    const uint32_t W = wp.W, y0 = c0 / W, x0 = c0 - y0 * W, row = y0 * W;
+    const uint32_t up = (y0 == 0 ? wp.H - 1 : y0 - 1) * W + x0, dn = (y0 + 1 == wp.H ? 0u : y0 + 1) * W + x0;
+    const uint32_t lf = row + (x0 == 0 ? W - 1 : x0 - 1), rt = row + (x0 + 4 == W ? 0u : x0 + 4);
+    int wu[4], wd[4];
+    load_cells4(d.cw + off + up, wu);
+    load_cells4(d.cw + off + dn, wd);
+    const uint32_t fu = *reinterpret_cast<const uint32_t*>(d.flowdir + off + up);
+    const uint32_t fdn = *reinterpret_cast<const uint32_t*>(d.flowdir + off + dn);
+    const int wl = d.cw[off + lf], wr = d.cw[off + rt];
+    const int fl = d.flowdir[off + lf], fr = d.flowdir[off + rt];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // the neighbour above (facing 0) leads here if it flows down (2), the one to
+      // the right (1) if it flows left (3), below (2) if up (0), left (3) if right (1)
+      if (byte_of(fu, j) == 2) out[j] += wu[j];
+      if ((j < 3 ? byte_of(fd, j + 1) : fr) == 3) out[j] += j < 3 ? own[j + 1] : wr;
+      if (byte_of(fdn, j) == 0) out[j] += wd[j];
+      if ((j > 0 ? byte_of(fd, j - 1) : fl) == 1) out[j] += j > 0 ? own[j - 1] : wl;
+    }
+  } else {
+    for (uint32_t j = 0; j < n; ++j) {
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const uint32_t nb = off + neighbour(wp, c0 + j, dd, +1);
+        if (d.flowdir[nb] == ((dd + 2) & 3)) out[j] += d.cw[nb];
+      }
+    }
+  }
+}
+
+// The ecology's cell pass over tile tl, four consecutive cells per thread and pass
+// (tile starts are multiples of 4): photosynthesis, one energy unit with
+// probability min(1, rate * biomass) on cells holding biomass below the energy
+// ceiling (the threshold in exact integers; the four cells' draws are the four
+// outputs of one Philox block); the strikes of this step cleared (they have been
+// counted); with terrain, the water's flow gathered into cw_next (the window-word
+// pass copies it back once every cell has read the old layer).  Adds the
+// photosynthesised units to grown and the grid totals of energy, water and biomass
+// to total, wsum, bsum.
 __device__ __forceinline__ void ecology_cells(const Dev& d, const WorldParams& wp, const eco_ecology& e, const Tile tl,
                                               uint32_t step, unsigned long long& grown, unsigned long long& total,
                                               unsigned long long& wsum, unsigned long long& bsum) {
-  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-    const uint32_t c = tl.start + i, g = wp.cell_off + c;
-    const int b = d.cb[g];
-    int en = d.ce[g];
-    if (b > 0 && en < e.cell_energy_max) {
-      if ((uint64_t)word_of(regrow_draws(wp, c >> 2, step), (int)(c & 3u)) < photo_threshold(e.photo_rate, b)) {
-        d.ce[g] = ++en;
-        ++grown;
+  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
+    const uint32_t c0 = tl.start + i, n = min(4u, tl.count - i), g = wp.cell_off + c0;
+    int b[4], en[4], wv[4];
+    load_cells4(d.cb + g, b);
+    load_cells4(d.ce + g, en);
+    load_cells4(d.cw + g, wv);
+    const uint32_t fd = d.rock ? *reinterpret_cast<const uint32_t*>(d.flowdir + g) : 0u;
+    bool any = false;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) any |= j < n && b[j] > 0 && en[j] < e.cell_energy_max;
+    if (any) {
+      const uint4 x = regrow_draws(wp, c0 >> 2, step);
+      bool grew = false;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if (j < n && b[j] > 0 && en[j] < e.cell_energy_max &&
+            (uint64_t)word_of(x, (int)j) < photo_threshold(e.photo_rate, b[j])) {
+          ++en[j];
+          ++grown;
+          grew = true;
+        }
+      if (grew) store_cells4(d.ce + g, n, en);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < n) {
+        total += (unsigned long long)(uint32_t)en[j];
+        wsum += (unsigned long long)(uint32_t)wv[j];
+        bsum += (unsigned long long)(uint32_t)b[j];
+      }
+    if (wp.attack) {
+      if (n == 4) {
+        *reinterpret_cast<uint4*>(d.mark + g) = make_uint4(0u, 0u, 0u, 0u);
+      } else {
+        for (uint32_t j = 0; j < n; ++j) d.mark[g + j] = 0u;
       }
     }
-    total += (unsigned long long)(uint32_t)en;
-    wsum += (unsigned long long)(uint32_t)d.cw[g];
-    bsum += (unsigned long long)(uint32_t)b;
-    if (wp.attack) d.mark[g] = 0;
-  }
-  if (d.rock) {
-    for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-      const uint32_t c = tl.start + i, g = wp.cell_off + c;
-      int acc = d.flowdir[g] < 0 ? d.cw[g] : 0;
-#pragma unroll
-      for (int dd = 0; dd < 4; ++dd) {
-        const uint32_t n = wp.cell_off + neighbour(wp, c, dd, +1);
-        if (d.flowdir[n] == ((dd + 2) & 3)) acc += d.cw[n];
-      }
-      d.cw_next[g] = acc;
+    if (d.rock) {
+      int nw[4];
+      flow_gather4(d, wp, c0, n, wv, fd, nw);
+      store_cells4(d.cw_next + g, n, nw);
     }
   }
 }
@@ -1245,29 +1324,46 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
 // colour vision the cell as others see it (occupant's colour, wall grey, else
 // energy / biomass / water as red / green / blue); the agent / wall bits and the
 // rock height in the top byte.  flowed != 0 (the end of a step with terrain):
-// first take the water the step's flow left on the cell.
+// first take the water the step's flow left on the cell.  Four consecutive cells
+// per thread and pass, their loads issued together.
 __device__ __forceinline__ uint32_t sat255(int v) { return (uint32_t)min(max(v, 0), 255); }
 
 __device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParams& wp, const Tile tl, int flowed) {
-  for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
-    const uint32_t cell = wp.cell_off + tl.start + i;
-    if (flowed && d.rock) d.cw[cell] = d.cw_next[cell];
-    const int o = d.occ[cell];
-    const bool wl = wp.has_walls && d.wall[cell] != 0;
-    uint32_t q;
-    if (!d.colour) {
-      q = sat255(d.cw[cell]) | (sat255(d.ce[cell]) << 8) | (sat255(d.cb[cell]) << 16);
-    } else if (o >= 0) {
-      const float4 c = d.colour[wp.slot_off + (uint32_t)o];
-      q = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
-    } else if (wl) {
-      q = 0x808080u;
+  for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
+    const uint32_t n = min(4u, tl.count - i), g = wp.cell_off + tl.start + i;
+    int wv[4], o[4], ce[4], cb[4], rk[4] = {0, 0, 0, 0};
+    if (flowed && d.rock) {
+      load_cells4(d.cw_next + g, wv);
+      store_cells4(d.cw + g, n, wv);
     } else {
-      q = sat255(16 * min(d.ce[cell], 1 << 20)) | (sat255(64 * min(d.cb[cell], 1 << 20)) << 8) |
-          (sat255(16 * min(d.cw[cell], 1 << 20)) << 16);
+      load_cells4(d.cw + g, wv);
     }
-    const uint32_t rk = d.rock ? (uint32_t)d.rock[cell] : 0u;
-    d.rgb[cell] = q | (((o >= 0 ? 1u : 0u) | (wl ? 4u : 0u) | (rk << 3)) << 24);
+    load_cells4(d.occ + g, o);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j >= n) o[j] = -1;   // past a ragged tail: no occupant read
+    load_cells4(d.ce + g, ce);
+    load_cells4(d.cb + g, cb);
+    if (d.rock) load_cells4(d.rock + g, rk);
+    const uint32_t wl4 = wp.has_walls ? *reinterpret_cast<const uint32_t*>(d.wall + g) : 0u;
+    uint32_t q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool wl = ((wl4 >> (8 * j)) & 0xFFu) != 0;
+      if (!d.colour) {
+        q[j] = sat255(wv[j]) | (sat255(ce[j]) << 8) | (sat255(cb[j]) << 16);
+      } else if (o[j] >= 0) {
+        const float4 c = d.colour[wp.slot_off + (uint32_t)o[j]];
+        q[j] = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+      } else if (wl) {
+        q[j] = 0x808080u;
+      } else {
+        q[j] = sat255(16 * min(ce[j], 1 << 20)) | (sat255(64 * min(cb[j], 1 << 20)) << 8) |
+               (sat255(16 * min(wv[j], 1 << 20)) << 16);
+      }
+      q[j] |= ((o[j] >= 0 ? 1u : 0u) | (wl ? 4u : 0u) | ((uint32_t)rk[j] << 3)) << 24;
+    }
+    store_cells4(reinterpret_cast<int32_t*>(d.rgb + g), n, reinterpret_cast<const int*>(q));
   }
 }
 
