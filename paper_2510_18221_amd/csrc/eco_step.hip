@@ -1529,9 +1529,11 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
 // kernels above, with the world's scans done inside the block).  A small world's
 // step is bound by the latency of its launches, and this replaces seven
 // dependent launches by one.  A thread scans a contiguous range of slots, so
-// every scan is one block-wide exclusive sum.
+// every scan is one block-wide exclusive sum.  ECO: the world has the ecology
+// (d.ep set); each instantiation carries only its own rules' code, which a
+// single-block launch fetches into the instruction cache afresh every step.
 // ---------------------------------------------------------------------------
-template <int WDT, int H>
+template <int WDT, int H, bool ECO>
 __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
   // threads; slots or cells per thread in one pass (one 4-byte load of bytes); passes over
   // the slots (the capacity is at most NT CH NP)
@@ -1584,7 +1586,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   bool claimed = false;
   for (uint32_t i = l0; i < l1; ++i) claimed |= birth_claim_slot(d, wp, w, wp.slot_off + (uint32_t)live[i], n_actions, &blocked);
   if (claimed) any_claim = 1u;   // the same value from every claimant
-  if (d.ep) {   // the ecology: photosynthesis, strikes cleared, the flow gather; the grid totals
+  if constexpr (ECO) {   // the ecology: photosynthesis, strikes cleared, the flow gather; the grid totals
     unsigned long long grown = 0, total = 0, wsum = 0, bsum = 0;
     ecology_cells(d, wp, d.ep[w], Tile{w, 0u, cells, 0u}, step, grown, total, wsum, bsum);
     wave_add_u64(grown, &ccnt[0]);
@@ -1729,7 +1731,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // the ecology: water, biomass and health carried by the live agents (after the
   // trait values are no longer needed)
   unsigned long long eco_w[3] = {0, 0, 0};
-  if (d.ep) {
+  if constexpr (ECO) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const uint32_t b0 = (p * NT + tid) * CH;
@@ -1756,8 +1758,10 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     red64[wave] = ew;
     s_red[wave] = mean_w;
     m2_red[wave] = m2;
+    if constexpr (ECO) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) eco_red[k][wave] = eco_w[k];
+      for (int k = 0; k < 3; ++k) eco_red[k][wave] = eco_w[k];
+    }
   }
   __syncthreads();
   // each wave's offsets in the live list (the waves' counts added the same way in
@@ -1809,7 +1813,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
     st.energy_total = (double)(long long)E;
     st.trait_mean = mean;
     st.trait_var = N ? M2 / (double)N : 0.0;
-    if (d.ep) {   // grid (the cell pass) plus carried (the live slots)
+    if constexpr (ECO) {   // grid (the cell pass) plus carried (the live slots)
       unsigned long long ecot[3] = {0, 0, 0};
 #pragma unroll 1
       for (int i = 0; i < NT / 64; ++i)
@@ -1839,7 +1843,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
         for (uint32_t j = 0; c0 + j < cells; ++j) d.sense[g + j] = (uint8_t)(v >> (8 * j));
       }
     }
-  } else if (d.ep) {
+  } else if (ECO) {
     cell_ecology_tile(d, wp, Tile{w, 0u, cells, 0u}, 1);   // with terrain, the flowed water copied back first
   } else {
     cell_render_tile(d, Tile{w, 0u, cells, 0u});
@@ -2206,13 +2210,19 @@ void launch_birth_commit_w(hipStream_t s, const Dev& d, const Layout& L, uint32_
 }
 hipError_t launch_step_small(hipStream_t s, const Dev& d, const Layout& L) {
   if (L.H1 != L.H2 || (L.H1 != 32 && L.H1 != 64 && L.H1 != 128)) return hipErrorInvalidValue;
-#define ECO_SMALL(WW)                                                                                             \
-  if (L.H1 == 32) hipLaunchKernelGGL((k_step_small<WW, 32>), dim3(1), dim3(1024), 0, s, d, L, L.A);              \
-  else if (L.H1 == 64) hipLaunchKernelGGL((k_step_small<WW, 64>), dim3(1), dim3(1024), 0, s, d, L, L.A);         \
-  else hipLaunchKernelGGL((k_step_small<WW, 128>), dim3(1), dim3(1024), 0, s, d, L, L.A);
-  if (L.wdtype == 0) { ECO_SMALL(0) }
-  else if (L.wdtype == 1) { ECO_SMALL(1) }
-  else { ECO_SMALL(2) }
+#define ECO_SMALL(WW, E)                                                                                          \
+  if (L.H1 == 32) hipLaunchKernelGGL((k_step_small<WW, 32, E>), dim3(1), dim3(1024), 0, s, d, L, L.A);           \
+  else if (L.H1 == 64) hipLaunchKernelGGL((k_step_small<WW, 64, E>), dim3(1), dim3(1024), 0, s, d, L, L.A);      \
+  else hipLaunchKernelGGL((k_step_small<WW, 128, E>), dim3(1), dim3(1024), 0, s, d, L, L.A);
+  if (d.ep) {
+    if (L.wdtype == 0) { ECO_SMALL(0, true) }
+    else if (L.wdtype == 1) { ECO_SMALL(1, true) }
+    else { ECO_SMALL(2, true) }
+  } else {
+    if (L.wdtype == 0) { ECO_SMALL(0, false) }
+    else if (L.wdtype == 1) { ECO_SMALL(1, false) }
+    else { ECO_SMALL(2, false) }
+  }
 #undef ECO_SMALL
   ECO_CHECK_LAUNCH();
 }
