@@ -85,6 +85,16 @@ CASES.update({
                                flags=ECO | eco_mod.DESC_TERRAIN | eco_mod.DESC_COLOUR_VISION
                                | eco_mod.DESC_EVOLVE_TEMPERATURE,
                                eco=dict(terrain_scale=12, sea_level=12, water_per_depth=3), seed=35),
+    # the largest ecology object the fused launch takes (four passes of the cell loops),
+    # with terrain, colour and strikes
+    "eco_limits": eco_world(width=128, height=128, n_agents_init=3000, capacity=8192, window=7, n_actions=9,
+                            attack_enabled=1, flags=ECO | eco_mod.DESC_TERRAIN | eco_mod.DESC_COLOUR_VISION,
+                            eco=dict(terrain_scale=12, sea_level=12, water_per_depth=3, attack_damage=50), seed=36),
+    # a width that is not a multiple of 4 (the flow's per-cell neighbour path) and a
+    # ragged last group of cells (127 x 129 = 16,383 cells)
+    "eco_odd": eco_world(width=127, height=129, n_agents_init=1500, capacity=4000, window=7,
+                         flags=ECO | eco_mod.DESC_TERRAIN, eco=dict(terrain_scale=12, sea_level=12, water_per_depth=3),
+                         seed=37),
 })
 
 
@@ -159,7 +169,7 @@ def test_split_kernels_match_oracle_on_small_worlds(eco, name):
 
 
 @pytest.mark.parametrize("name", ["busy_fp32", "attack", "busy_fp8_h64", "busy_bf16_h128", "limits", "eco",
-                                  "eco_attack", "eco_terrain_colour", "eco_ocean_fp8"])
+                                  "eco_attack", "eco_terrain_colour", "eco_ocean_fp8", "eco_limits", "eco_odd"])
 def test_fused_matches_oracle(eco, name):
     cfg = CASES[name]
     acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 5, t, p_forward=0.3, p_eat=0.3,
