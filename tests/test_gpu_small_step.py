@@ -160,9 +160,10 @@ def test_large_object_takes_the_split_kernels(eco):
     assert kt["compact"][1] == 2
 
 
-@pytest.mark.parametrize("name", ["config1", "busy_bf16"])
+@pytest.mark.parametrize("name", ["config1", "busy_bf16", "eco_terrain_colour", "eco_odd"])
 def test_split_kernels_match_oracle_on_small_worlds(eco, name):
-    """The separate kernels keep their oracle parity on small worlds too."""
+    """The separate kernels keep their oracle parity on small worlds too (the
+    ecology's cell passes in cell tiles, with a ragged last tile and group)."""
     cfg = CASES[name]
     acts = lambda t: wl.biased_actions(cfg["capacity"], cfg["n_actions"], 7, t, p_forward=0.35, p_eat=0.3)
     run_pair(eco, cfg, 8, actions_fn=acts, what=f"split {name}", flags=eco.RT_SPLIT_STEP)
