@@ -291,6 +291,9 @@ WORKLOADS = {
               "15x15x4 window + 8 scalars, 908->128->128->7 BF16 weights + FP32 master", "bf16"),
     "small": ("single world 64x64 torus, 256 agents at start, capacity 4,096, density 0.1, regrowth 0.01, "
               "5x5x4 window + 4 scalars, 104->32->32->5 FP32 weights (cache-resident: a latency test)", "f32"),
+    "small_ecology": ("single world 64x64 torus with the three-resource ecology, terrain (water flowing downhill) "
+                      "and the 7x7 rendered colour + elevation window, 256 agents held (no costs, no births, no "
+                      "health damage), 208->32->32->8 FP32 weights (cache-resident: a latency test)", "f32"),
     "turnover": ("single world 1024x1024 torus, 65,536 agents at start, capacity 131,072, 11x11x4 window + 8 "
                  "scalars, per-agent 492->64->64->7 MLP, FP32 weights; no step cost and no transfer to the "
                  "child (every agent at the reproduction threshold, children born with zero energy die at "
@@ -311,6 +314,10 @@ def workload_cfg(wl, name, wdtype=None):
         return wl.world_batch(64)
     if name == "small":
         return wl.world_small(seed=0)
+    if name == "small_ecology":
+        held = dict(wl.ECOLOGY, e_cost_move=0, w_cost=0, hp_overspend=0, age_shift=31, attack_damage=0)
+        return wl.ecology_desc(eco=held, window=7, n_scalars=12, e_cost=0, e_repro=1 << 30, seed=0,
+                               flags=wl.ECOLOGY_FLAG | 16 | 4)   # with terrain and colour vision
     return wl.world_large(seed=0)
 
 
