@@ -642,37 +642,52 @@ __device__ __forceinline__ int byte_of(uint32_t v, int j) { return (int)(int8_t)
 // it has no way down, and takes that of each neighbour whose way down leads to it.
 // own[] holds the cells' water before the flow, fd their four direction bytes.
 // With W a multiple of 4 a whole group lies in one row, and the neighbours above
-// and below are whole aligned groups.
+// and below are whole aligned groups: flow_rows_load reads them (and the cells
+// left and right of the group) so that the caller can issue these loads with its
+// own, and returns false where the group takes the per-cell path instead.
+struct FlowRows {
+  int wu[4], wd[4];   // water of the cells above and below
+  uint32_t fu, fdn;   // their direction bytes
+  int wl, wr, fl, fr;   // water and direction of the cells left and right of the group
+};
+
+__device__ __forceinline__ bool flow_rows_load(const Dev& d, const WorldParams& wp, uint32_t c0, uint32_t n,
+                                               FlowRows& r) {
+  if ((wp.W & 3u) != 0 || n != 4) return false;
+  const uint32_t off = wp.cell_off, W = wp.W, y0 = c0 / W, x0 = c0 - y0 * W, row = y0 * W;
+  const uint32_t up = (y0 == 0 ? wp.H - 1 : y0 - 1) * W + x0, dn = (y0 + 1 == wp.H ? 0u : y0 + 1) * W + x0;
+  const uint32_t lf = row + (x0 == 0 ? W - 1 : x0 - 1), rt = row + (x0 + 4 == W ? 0u : x0 + 4);
+  load_cells4(d.cw + off + up, r.wu);
+  load_cells4(d.cw + off + dn, r.wd);
+  r.fu = *reinterpret_cast<const uint32_t*>(d.flowdir + off + up);
+  r.fdn = *reinterpret_cast<const uint32_t*>(d.flowdir + off + dn);
+  r.wl = d.cw[off + lf];
+  r.wr = d.cw[off + rt];
+  r.fl = d.flowdir[off + lf];
+  r.fr = d.flowdir[off + rt];
+  return true;
+}
+
 __device__ __forceinline__ void flow_gather4(const Dev& d, const WorldParams& wp, uint32_t c0, uint32_t n,
-                                             const int own[4], uint32_t fd, int out[4]) {
-  const uint32_t off = wp.cell_off;
+                                             const int own[4], uint32_t fd, bool rows, const FlowRows& r,
+                                             int out[4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) out[j] = byte_of(fd, j) < 0 ? own[j] : 0;
-  if ((wp.W & 3u) == 0 && n == 4) {
-    const uint32_t W = wp.W, y0 = c0 / W, x0 = c0 - y0 * W, row = y0 * W;
-    const uint32_t up = (y0 == 0 ? wp.H - 1 : y0 - 1) * W + x0, dn = (y0 + 1 == wp.H ? 0u : y0 + 1) * W + x0;
-    const uint32_t lf = row + (x0 == 0 ? W - 1 : x0 - 1), rt = row + (x0 + 4 == W ? 0u : x0 + 4);
-    int wu[4], wd[4];
-    load_cells4(d.cw + off + up, wu);
-    load_cells4(d.cw + off + dn, wd);
-    const uint32_t fu = *reinterpret_cast<const uint32_t*>(d.flowdir + off + up);
-    const uint32_t fdn = *reinterpret_cast<const uint32_t*>(d.flowdir + off + dn);
-    const int wl = d.cw[off + lf], wr = d.cw[off + rt];
-    const int fl = d.flowdir[off + lf], fr = d.flowdir[off + rt];
+  if (rows) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       // the neighbour above (facing 0) leads here if it flows down (2), the one to
       // the right (1) if it flows left (3), below (2) if up (0), left (3) if right (1)
-      if (byte_of(fu, j) == 2) out[j] += wu[j];
-      if ((j < 3 ? byte_of(fd, j + 1) : fr) == 3) out[j] += j < 3 ? own[j + 1] : wr;
-      if (byte_of(fdn, j) == 0) out[j] += wd[j];
-      if ((j > 0 ? byte_of(fd, j - 1) : fl) == 1) out[j] += j > 0 ? own[j - 1] : wl;
+      if (byte_of(r.fu, j) == 2) out[j] += r.wu[j];
+      if ((j < 3 ? byte_of(fd, j + 1) : r.fr) == 3) out[j] += j < 3 ? own[j + 1] : r.wr;
+      if (byte_of(r.fdn, j) == 0) out[j] += r.wd[j];
+      if ((j > 0 ? byte_of(fd, j - 1) : r.fl) == 1) out[j] += j > 0 ? own[j - 1] : r.wl;
     }
   } else {
     for (uint32_t j = 0; j < n; ++j) {
 #pragma unroll
       for (int dd = 0; dd < 4; ++dd) {
-        const uint32_t nb = off + neighbour(wp, c0 + j, dd, +1);
+        const uint32_t nb = wp.cell_off + neighbour(wp, c0 + j, dd, +1);
         if (d.flowdir[nb] == ((dd + 2) & 3)) out[j] += d.cw[nb];
       }
     }
@@ -698,6 +713,8 @@ __device__ __forceinline__ void ecology_cells(const Dev& d, const WorldParams& w
     load_cells4(d.ce + g, en);
     load_cells4(d.cw + g, wv);
     const uint32_t fd = d.rock ? *reinterpret_cast<const uint32_t*>(d.flowdir + g) : 0u;
+    FlowRows fr{};   // the flow's neighbour rows, loaded with the cells' own values
+    const bool rows = d.rock && flow_rows_load(d, wp, c0, n, fr);
     bool any = false;
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) any |= j < n && b[j] > 0 && en[j] < e.cell_energy_max;
@@ -730,7 +747,7 @@ __device__ __forceinline__ void ecology_cells(const Dev& d, const WorldParams& w
     }
     if (d.rock) {
       int nw[4];
-      flow_gather4(d, wp, c0, n, wv, fd, nw);
+      flow_gather4(d, wp, c0, n, wv, fd, rows, fr, nw);
       store_cells4(d.cw_next + g, n, nw);
     }
   }
@@ -1332,12 +1349,8 @@ __device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParam
   for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
     const uint32_t n = min(4u, tl.count - i), g = wp.cell_off + tl.start + i;
     int wv[4], o[4], ce[4], cb[4], rk[4] = {0, 0, 0, 0};
-    if (flowed && d.rock) {
-      load_cells4(d.cw_next + g, wv);
-      store_cells4(d.cw + g, n, wv);
-    } else {
-      load_cells4(d.cw + g, wv);
-    }
+    const bool copy_back = flowed && d.rock;
+    load_cells4((copy_back ? d.cw_next : d.cw) + g, wv);
     load_cells4(d.occ + g, o);
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j)
@@ -1346,6 +1359,7 @@ __device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParam
     load_cells4(d.cb + g, cb);
     if (d.rock) load_cells4(d.rock + g, rk);
     const uint32_t wl4 = wp.has_walls ? *reinterpret_cast<const uint32_t*>(d.wall + g) : 0u;
+    if (copy_back) store_cells4(d.cw + g, n, wv);   // after every load of the group is issued
     uint32_t q[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
