@@ -1544,8 +1544,8 @@ __global__ __launch_bounds__(kSlotTile) void k_compact_write(Dev d, TileScratch 
 // step is bound by the latency of its launches, and this replaces seven
 // dependent launches by one.  A thread scans a contiguous range of slots, so
 // every scan is one block-wide exclusive sum.  ECO: the world has the ecology
-// (d.ep set); each instantiation carries only its own rules' code, which a
-// single-block launch fetches into the instruction cache afresh every step.
+// (d.ep set); the single-resource instantiation carries none of the ecology's
+// phases (behind a run-time test they made its step measurably slower).
 // ---------------------------------------------------------------------------
 template <int WDT, int H, bool ECO>
 __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n_actions) {
