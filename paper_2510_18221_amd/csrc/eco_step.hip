@@ -1318,7 +1318,13 @@ __device__ __forceinline__ uint32_t colour_byte(float c) {
   return (uint32_t)((255ull * M + (1ull << (s - 1))) >> s);
 }
 
-__device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
+// col: the live agents' colour words by local slot, if the caller has them in LDS
+// (else read from the colour trait).
+__device__ __forceinline__ uint32_t colour_word(const float4 c) {
+  return colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+}
+
+__device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl, const uint32_t* col = nullptr) {
   const WorldParams wp = d.wp[tl.world];
   for (uint32_t i = threadIdx.x; i < tl.count; i += blockDim.x) {
     const uint32_t cell = wp.cell_off + tl.start + i;
@@ -1326,8 +1332,7 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
     const bool r = d.res[cell] != 0, wl = wp.has_walls && d.wall[cell] != 0;
     uint32_t q = 0u;
     if (o >= 0) {
-      const float4 c = d.colour[wp.slot_off + (uint32_t)o];
-      q = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+      q = col ? col[o] : colour_word(d.colour[wp.slot_off + (uint32_t)o]);
     } else if (r) {
       q = 255u << 8;
     } else if (wl) {
@@ -1345,7 +1350,8 @@ __device__ __forceinline__ void cell_render_tile(const Dev& d, const Tile tl) {
 // per thread and pass, their loads issued together.
 __device__ __forceinline__ uint32_t sat255(int v) { return (uint32_t)min(max(v, 0), 255); }
 
-__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParams& wp, const Tile tl, int flowed) {
+__device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParams& wp, const Tile tl, int flowed,
+                                                  const uint32_t* col = nullptr) {
   for (uint32_t i = 4 * threadIdx.x; i < tl.count; i += 4 * blockDim.x) {
     const uint32_t n = min(4u, tl.count - i), g = wp.cell_off + tl.start + i;
     int wv[4], o[4], ce[4], cb[4], rk[4] = {0, 0, 0, 0};
@@ -1367,8 +1373,7 @@ __device__ __forceinline__ void cell_ecology_tile(const Dev& d, const WorldParam
       if (!d.colour) {
         q[j] = sat255(wv[j]) | (sat255(ce[j]) << 8) | (sat255(cb[j]) << 16);
       } else if (o[j] >= 0) {
-        const float4 c = d.colour[wp.slot_off + (uint32_t)o[j]];
-        q[j] = colour_byte(c.x) | (colour_byte(c.y) << 8) | (colour_byte(c.z) << 16);
+        q[j] = col ? col[o[j]] : colour_word(d.colour[wp.slot_off + (uint32_t)o[j]]);
       } else if (wl) {
         q[j] = 0x808080u;
       } else {
@@ -1567,6 +1572,9 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
   // per cell: the agent bit and energy bin of its occupant after the step (0: none),
   // written from the live slots, read by the window-channel pass
   __shared__ __align__(16) uint8_t s_agent[ECO_SMALL_STEP_MAX_CELLS];
+  // colour vision: the live agents' colour words by slot, written from the live
+  // slots, read by the window-word pass (no occupant-then-colour lookup chain)
+  __shared__ uint32_t s_col[ECO_SMALL_STEP_MAX_SLOTS];
   const uint32_t tid = threadIdx.x;
   // live-list entry tid, loaded together with the world's live count: the
   // thread's only agent when there are at most NT (the object's one world
@@ -1713,6 +1721,11 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       ev = *reinterpret_cast<const int4*>(d.energy + wp.slot_off + b0);
       if (sense_bytes) pv = *reinterpret_cast<const int4*>(d.pos + wp.slot_off + b0);
     }
+    float4 cv[4];
+    if (d.colour && b0 < cap) {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) cv[j] = d.colour[wp.slot_off + b0 + j];
+    }
     const double tj[4] = {tv[0].x, tv[0].y, tv[1].x, tv[1].y};
     const int ej[4] = {ev.x, ev.y, ev.z, ev.w}, pj[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
@@ -1721,6 +1734,7 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       t[p][j] = on ? tj[j] : 0.0;
       es += on ? ej[j] : 0;
       if (sense_bytes && on) s_agent[pj[j]] = (uint8_t)agent_sense(wp, ej[j]);   // one agent per cell
+      if (d.colour && on) s_col[b0 + j] = colour_word(cv[j]);
     }
 
 #pragma unroll
@@ -1858,9 +1872,9 @@ __global__ __launch_bounds__(1024) void k_step_small(Dev d, Layout L, uint32_t n
       }
     }
   } else if (ECO) {
-    cell_ecology_tile(d, wp, Tile{w, 0u, cells, 0u}, 1);   // with terrain, the flowed water copied back first
+    cell_ecology_tile(d, wp, Tile{w, 0u, cells, 0u}, 1, s_col);   // with terrain, the flowed water copied back first
   } else {
-    cell_render_tile(d, Tile{w, 0u, cells, 0u});
+    cell_render_tile(d, Tile{w, 0u, cells, 0u}, s_col);
   }
 }
 
